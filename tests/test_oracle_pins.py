@@ -1,0 +1,449 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test names what fixes the expected value: an independent library
+implementation, a closed form, an invariant of the model, a quadrature of
+the model's density, or numbers printed in the paper.
+"""
+import json
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.stats
+
+import oracle
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TWO_PI = 2.0 * math.pi
+Q = 0.5
+
+
+def mpr_energy_numpy(phi, q=Q):
+    """Equation (Hamiltonian_mod), written directly on numpy arrays."""
+    h = -np.cos(q * (phi[:, 1:] - phi[:, :-1])).sum()
+    v = -np.cos(q * (phi[1:, :] - phi[:-1, :])).sum()
+    return h + v
+
+
+# ------------------------------------------------------------------ Philox
+@pytest.fixture(scope="module")
+def rocrand_helper(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if gxx is None or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("rocRAND headers or g++ not available")
+    exe = tmp_path_factory.mktemp("rr") / "rocrand_philox"
+    subprocess.check_call([gxx, "-std=c++17", "-O1", "-D__HIP_PLATFORM_AMD__",
+                           "-I/opt/rocm/include", os.path.join(HERE, "helpers", "rocrand_philox.cpp"),
+                           "-o", str(exe)])
+    return str(exe)
+
+
+def test_philox_matches_rocrand(rocrand_helper):
+    """Philox4x32-10 equals rocRAND's independent implementation bit for bit."""
+    rng = np.random.default_rng(7)
+    rows = rng.integers(0, 2**32, size=(3000, 6), dtype=np.uint64).astype(np.uint32)
+    rows[0] = 0
+    rows[1] = 0xFFFFFFFF
+    text = "\n".join(" ".join(f"{v:08x}" for v in r) for r in rows) + "\n"
+    out = subprocess.run([rocrand_helper], input=text, capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    for r, line in zip(rows, out):
+        want = [int(w, 16) for w in line.split()]
+        got = oracle.philox4x32_10(r[:4], r[4:]).tolist()
+        assert got == want, (r, got, want)
+
+
+def test_site_uniforms_layout_and_range():
+    """Sites x and x+2 (x mod 4 in {0,1}) share one call: word pairs (0,1) and (2,3)."""
+    seed, nx = 0x1234_5678_9ABC_DEF0, 37
+    for (x, y) in [(0, 0), (1, 3), (4, 5), (13, 36), (36, 2)]:
+        base = y * nx + (x & ~2)
+        w = oracle.philox4x32_10([base, 9, 4, 2], [seed & 0xFFFFFFFF, seed >> 32])
+        u, r = oracle.site_uniforms(seed, nx, x, y, 9, 4, 2)
+        sel = (x >> 1) & 1
+        assert u == (int(w[2 * sel]) >> 8) / 2**24
+        assert r == (int(w[2 * sel + 1]) >> 8) / 2**24
+        assert 0.0 <= u < 1.0 and 0.0 <= r < 1.0
+
+
+def test_site_uniforms_are_uniform_and_uncorrelated():
+    """The per-site uniforms pass chi-square and lag correlation checks."""
+    us, rs = [], []
+    for y in range(40):
+        for x in range(50):
+            u, r = oracle.site_uniforms(99, 50, x, y, 3, 1, 0)
+            us.append(u)
+            rs.append(r)
+    us, rs = np.array(us), np.array(rs)
+    for v in (us, rs):
+        counts, _ = np.histogram(v, bins=20, range=(0, 1))
+        assert scipy.stats.chisquare(counts).pvalue > 1e-3
+    assert abs(np.corrcoef(us, rs)[0, 1]) < 0.08
+    assert abs(np.corrcoef(us[:-1], us[1:])[0, 1]) < 0.08
+
+
+# ----------------------------------------------------------------- data map
+def test_map_endpoints_and_round_trip():
+    """Equation (map): z_min -> 0, z_max -> 2 pi exactly; G^{-1}(G(z)) = z to 2 ulp."""
+    rng = np.random.default_rng(1)
+    z = rng.normal(50, 10, size=(17, 23))
+    m = (rng.random(z.shape) < 0.6).astype(np.uint8)
+    phi, zz = oracle.map_to_angles(z, m)
+    s = m == 1
+    assert zz[0] == z[s].min() and zz[1] == z[s].max()
+    assert phi[s].min() == 0.0 and phi[s].max() == TWO_PI
+    assert np.all(phi[~s] == 0.0)
+    # Round trip through the prediction's back-map with phi_sum = phi and M = 1:
+    back = oracle.predict(np.zeros_like(z), np.zeros_like(m), phi * s, 1, zz)
+    err = np.abs(back[s] - z[s]) / np.spacing(np.abs(z[s]))
+    assert err.max() <= 2.0
+    # Samples are copied bit-exactly by the prediction.
+    out = oracle.predict(z, m, np.zeros_like(z), 1, zz)
+    assert np.array_equal(out[s], z[s])
+
+
+def test_map_affine_invariance_and_degenerate_inputs():
+    """G(c z + b) = G(z) for c > 0; constant or single-sample data are degenerate."""
+    rng = np.random.default_rng(2)
+    z = rng.normal(0, 1, size=(9, 11))
+    m = np.ones_like(z, dtype=np.uint8)
+    p1, _ = oracle.map_to_angles(z, m)
+    p2, _ = oracle.map_to_angles(3.5 * z + 17.0, m)
+    assert np.max(np.abs(p1 - p2)) < 1e-13
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.map_to_angles(np.full((4, 4), 2.0), np.ones((4, 4), np.uint8))
+    assert e.value.code == oracle.ERR_DEGENERATE
+    one = np.zeros((4, 4), np.uint8)
+    one[1, 1] = 1
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.map_to_angles(z[:4, :4], one)
+    assert e.value.code == oracle.ERR_DEGENERATE
+    bad = z.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.map_to_angles(bad, m)
+    assert e.value.code == oracle.ERR_ARG
+
+
+# ------------------------------------------------------------- energies
+def test_energy_and_sample_energy_against_direct_sums():
+    """Equations (Hamiltonian_mod) and (mpr-sse) on small grids, summed directly."""
+    rng = np.random.default_rng(3)
+    phi = rng.uniform(0, TWO_PI, size=(7, 9))
+    assert abs(oracle.energy(phi) - mpr_energy_numpy(phi)) < 1e-12
+    assert oracle.bond_count(9, 7) == 9 * 6 + 7 * 8
+    m = (rng.random(phi.shape) < 0.5).astype(np.uint8)
+    s, n = 0.0, 0
+    for y in range(7):
+        for x in range(9):
+            for dy, dx in ((0, 1), (1, 0)):
+                yy, xx = y + dy, x + dx
+                if yy < 7 and xx < 9 and m[y, x] and m[yy, xx]:
+                    s -= math.cos(Q * (phi[y, x] - phi[yy, xx]))
+                    n += 1
+    e_s, n_sp = oracle.sample_energy(phi, m)
+    assert n_sp == n and abs(e_s - s / n) < 1e-14
+    # Mirror symmetry z -> z_min + z_max - z maps phi -> 2 pi - phi and keeps H.
+    assert abs(oracle.energy(TWO_PI - phi) - oracle.energy(phi)) < 1e-12
+    # Bounds: for angles in [0, 2 pi], q = 1/2 gives e_s in [-1, 1].
+    assert -1.0 <= e_s <= 1.0
+
+
+def test_sample_energy_degenerate_without_pairs():
+    m = np.zeros((4, 4), np.uint8)
+    m[0, 0] = m[2, 2] = 1
+    with pytest.raises(oracle.OracleError):
+        oracle.sample_energy(np.zeros((4, 4)), m)
+
+
+# ------------------------------------------------------- over-relaxation
+def test_over_relaxation_conserves_energy():
+    """The over-relaxation step keeps the energy (Section 2.4 and 3.3): to 1e-12."""
+    rng = np.random.default_rng(4)
+    for smooth in (False, True):
+        if smooth:
+            z = synth.matern_field(32, 24, 1.5, 0.1, 0.0, 1.0, 11)
+            phi = TWO_PI * (z - z.min()) / (z.max() - z.min())
+        else:
+            phi = rng.uniform(0, TWO_PI, size=(24, 32))
+        m = (rng.random(phi.shape) < 0.3).astype(np.uint8)
+        e0 = mpr_energy_numpy(phi)
+        p = phi
+        for sweep in range(4):
+            for colour in (0, 1):
+                p, acc, flags = oracle.half_sweep(p, m, colour, 0.1, 1.0, sweep,
+                                                  mode=oracle.MODE_OR_ONLY, with_flags=True)
+                assert acc == 0
+        assert abs(mpr_energy_numpy(p) - e0) < 1e-12
+        assert np.all(p[m == 1] == phi[m == 1])
+        assert np.all((p >= 0) & (p < TWO_PI + 1e-12))
+        assert np.max(np.abs(p - phi)) > 0.1  # it did move spins
+
+
+def test_printed_q1_reflection_does_not_conserve_q_half_energy():
+    """Why the q-aware reading: the q = 1 reflection changes the q = 1/2 energy."""
+    rng = np.random.default_rng(5)
+    nb = rng.uniform(0, TWO_PI, size=(2000, 4))
+    phi = rng.uniform(0, TWO_PI, size=2000)
+    lit = np.mod(2 * np.arctan2(np.sin(nb).sum(1), np.cos(nb).sum(1)) - phi, TWO_PI)
+    e_old = -np.cos(Q * (phi[:, None] - nb)).sum(1)
+    e_new = -np.cos(Q * (lit[:, None] - nb)).sum(1)
+    assert np.mean(np.abs(e_new - e_old)) > 0.3
+
+
+def test_over_relaxation_is_an_involution():
+    """Applying the reflection twice (same neighbours) restores every angle."""
+    rng = np.random.default_rng(6)
+    phi = rng.uniform(0, TWO_PI, size=(16, 16))
+    m = np.zeros(phi.shape, np.uint8)
+    p1, _, f = oracle.half_sweep(phi, m, 0, 0.1, 1.0, 0, mode=oracle.MODE_OR_ONLY, with_flags=True)
+    p2, _, _ = oracle.half_sweep(p1, m, 0, 0.1, 1.0, 0, mode=oracle.MODE_OR_ONLY)
+    assert np.max(np.abs(p2 - phi)) < 1e-12
+    kept = (f & oracle.FLAG_KEPT) != 0
+    colour0 = (np.add.outer(np.arange(16), np.arange(16)) % 2) == 0
+    assert 0 < kept[colour0].sum() < colour0.sum()
+
+
+# --------------------------------------------- single-site stationarity
+def _conditional_cdf(nbrs, T):
+    """CDF of p(phi) ~ exp(sum_j cos(q(phi - phi_j)) / T) on [0, 2 pi) by quadrature."""
+    g = np.linspace(0.0, TWO_PI, 20001)
+    logp = np.cos(Q * (g[:, None] - np.asarray(nbrs)[None, :])).sum(1) / T
+    p = np.exp(logp - logp.max())
+    c = scipy.integrate.cumulative_trapezoid(p, g, initial=0.0)
+    c /= c[-1]
+    return lambda v: np.interp(v, g, c)
+
+
+@pytest.mark.parametrize("shape,site,T,a,thin", [
+    ((3, 3), (1, 1), 0.5, 1.0, 10),     # 4 neighbours
+    ((3, 3), (1, 1), 0.05, 6.0, 20),
+    ((2, 3), (1, 0), 0.2, 2.0, 10),     # 3 neighbours (edge)
+    ((2, 2), (0, 0), 0.1, 3.0, 20),     # 2 neighbours (corner)
+])
+def test_single_site_chain_matches_conditional_density(shape, site, T, a, thin):
+    """Algorithm 1 at one gap site with fixed neighbours samples exp(-H/T) (KS test)."""
+    ny, nx = shape
+    x0, y0 = site
+    rng = np.random.default_rng(8)
+    phi = rng.uniform(0.3, TWO_PI - 0.3, size=shape)
+    m = np.ones(shape, np.uint8)
+    m[y0, x0] = 0
+    colour = (x0 + y0) & 1
+    nbrs = [phi[y0 + dy, x0 + dx] for dx, dy in ((-1, 0), (1, 0), (0, -1), (0, 1))
+            if 0 <= x0 + dx < nx and 0 <= y0 + dy < ny]
+    p = phi.copy()
+    samples = []
+    n_samples = 4000
+    for t in range(n_samples * thin):
+        p, _, _ = oracle.half_sweep(p, m, colour, T, a, t, seed=1234)
+        if t % thin == thin - 1:
+            samples.append(p[y0, x0])
+    res = scipy.stats.kstest(np.array(samples), _conditional_cdf(nbrs, T))
+    assert res.pvalue > 1e-3, res
+
+
+# -------------------------------------------------- tiny-grid brute force
+@pytest.mark.parametrize("T", [0.2, 1.0, 5.0])
+def test_two_site_unconditional_energy_by_quadrature(T):
+    """1x2 grid, both free: e(T) = -<cos(D/2)>, D = phi1 - phi2 with weight (2pi - |D|)."""
+    g = np.linspace(-TWO_PI, TWO_PI, 40001)
+    w = (TWO_PI - np.abs(g)) * np.exp(np.cos(Q * g) / T)
+    exact = -np.trapezoid(np.cos(Q * g) * w, g) / np.trapezoid(w, g)
+    # fixed a = 1 (full-circle proposals) so that the tiny chain mixes
+    st = np.full((1, 2), math.pi)
+    free = np.zeros((1, 2), np.uint8)
+    es = []
+    for t in range(40000):
+        st, _, _ = oracle.half_sweep(st, free, 0, T, 1.0, t, seed=77)
+        st, _, _ = oracle.half_sweep(st, free, 1, T, 1.0, t, seed=77)
+        if t >= 200:
+            es.append(oracle.energy(st))
+    assert abs(np.mean(es) - exact) < 0.01, (np.mean(es), exact)
+
+
+def test_two_free_sites_joint_density_by_quadrature():
+    """2x2 grid, two adjacent free sites: <phi_a>, <phi_b> and <H> by 2-D quadrature."""
+    T = 0.3
+    fixed = {(0, 1): 1.0, (1, 1): 4.0}  # (y, x) -> angle
+    phi = np.zeros((2, 2))
+    m = np.zeros((2, 2), np.uint8)
+    for k, v in fixed.items():
+        phi[k] = v
+        m[k] = 1
+    # free: a = (0,0) [nbrs (0,1) fixed, (1,0) free]; b = (1,0) [nbrs (0,0) free, (1,1) fixed]
+    g = (np.arange(600) + 0.5) * TWO_PI / 600
+    A, B = np.meshgrid(g, g, indexing="ij")
+    H = -(np.cos(Q * (A - 1.0)) + np.cos(Q * (A - B)) + np.cos(Q * (B - 4.0))
+          + np.cos(Q * (1.0 - 4.0)))
+    w = np.exp(-(H - H.min()) / T)
+    Z = w.sum()
+    ea, eb, eH = (A * w).sum() / Z, (B * w).sum() / Z, (H * w).sum() / Z
+    p = oracle.default_params(R=4, K=20000, fixed_relax=200, seed=91)
+    ps, _, _, _ = oracle.simulate(phi, m, T, p)
+    M = p.R * p.K
+    assert abs(ps[0, 0] / M - ea) < 0.05, (ps[0, 0] / M, ea)
+    assert abs(ps[1, 0] / M - eb) < 0.05, (ps[1, 0] / M, eb)
+    # <H> via an unconditional-energy-free route: energy of the mean is not <H>,
+    # so check <H> with a direct chain average.
+    hs = []
+    st = phi.copy()
+    for t in range(30000):
+        st, _, _ = oracle.half_sweep(st, m, 0, T, 1.0, t, seed=5)
+        st, _, _ = oracle.half_sweep(st, m, 1, T, 1.0, t, seed=5)
+        if t >= 500:
+            hs.append(oracle.energy(st))
+    assert abs(np.mean(hs) - eH) < 0.02, (np.mean(hs), eH)
+
+
+# ---------------------------------------------------------- e(T) limits
+def test_energy_table_high_temperature_limit():
+    """T -> infinity: e -> -E[cos((u1 - u2)/2)] = -4/pi^2 for independent uniforms."""
+    e = oracle.energy_table(8, 8, [1.0e4], 50, 2000, seed=5)[0]
+    assert abs(e - (-4.0 / math.pi ** 2)) < 3e-3, e
+
+
+@pytest.mark.parametrize("T", [2e-4, 1e-3])
+def test_energy_table_low_temperature_equipartition(T):
+    """T -> 0: e = -1 + T (L+1) / (4 L) on an L x L grid (L^2 - 1 harmonic modes)."""
+    L = 16
+    e = oracle.energy_table(L, L, [T], 400, 2000, seed=6)[0]
+    want = T * (L + 1) / (4.0 * L)
+    assert abs((1.0 + e) / want - 1.0) < 0.05, (1 + e, want)
+
+
+def test_conditional_low_temperature_equipartition():
+    """Gaps at low T: <H> - H_min = P T / 2 (one quadratic mode per free site)."""
+    z = synth.matern_field(24, 24, 2.5, 0.1, 0.0, 1.0, 3)
+    m = synth.random_mask(24, 24, 0.5, 4)
+    phi, _ = oracle.map_to_angles(z, m)
+    P = int((m == 0).sum())
+    res = []
+    for T in (1e-4, 2e-4):
+        p = oracle.default_params(R=1, K=1, fixed_relax=600, seed=9)
+        st = phi.copy()
+        # relax, then average H over many equilibrium sweeps at fixed a
+        a, hs = 1.0, []
+        for t in range(3000):
+            st, acc, _ = oracle.half_sweep(st, m, 0, T, a, t, seed=9)
+            st, acc2, _ = oracle.half_sweep(st, m, 1, T, a, t, seed=9)
+            if (acc + acc2) / P < 0.3:
+                a = 1.0 + (t + 1) / 3.0
+            if t >= 1500:
+                hs.append(oracle.energy(st))
+        res.append(np.mean(hs))
+    slope = (res[1] - res[0]) / 1e-4
+    assert abs(slope / (P / 2.0) - 1.0) < 0.1, (slope, P / 2)
+
+
+# ----------------------------------------------------------- SG slope
+@pytest.mark.parametrize("degree", [1, 2, 3])
+def test_sg_slope_matches_polyfit(degree):
+    """Derivative at the newest point of the least-squares fit equals numpy.polyfit's."""
+    rng = np.random.default_rng(degree)
+    for _ in range(20):
+        n = int(rng.integers(degree + 2, 40))
+        e = rng.normal(size=n) * 1e-3 - 0.98
+        c = np.polyfit(np.arange(n), e, degree)
+        want = np.polyval(np.polyder(c), n - 1)
+        assert abs(oracle.sg_slope(e, degree) - want) < 1e-9 * max(1.0, abs(want)) + 1e-12
+
+
+def test_sg_slope_exact_on_polynomials():
+    j = np.arange(20.0)
+    assert abs(oracle.sg_slope(3.0 - 0.25 * j, 1) + 0.25) < 1e-12
+    assert abs(oracle.sg_slope(1.0 + 0.5 * j - 0.01 * j ** 2, 2) - (0.5 - 0.02 * 19)) < 1e-10
+
+
+# ------------------------------------------------- temperature inversion
+def test_invert_temperature_on_exact_power_law():
+    """A table with 1 + e = c T^b is inverted exactly (log-log interpolation)."""
+    Tg = oracle.temperature_grid(12, 1e-4, 1.0)
+    e = -1.0 + 0.3 * Tg ** 0.9
+    for T in (2e-4, 3.3e-3, 0.5):
+        got, cl = oracle.invert_temperature(Tg, e, -1.0 + 0.3 * T ** 0.9)
+        assert not cl and abs(got / T - 1.0) < 1e-12
+    got, cl = oracle.invert_temperature(Tg, e, -1.0 + 0.3 * 2.0 ** 0.9)
+    assert cl and got == Tg[-1]
+    got, cl = oracle.invert_temperature(Tg, e, -1.0)
+    assert cl and got == Tg[0]
+
+
+def test_invert_temperature_pools_non_monotone_noise():
+    """A non-monotone (noisy) table is made monotone before inversion."""
+    Tg = oracle.temperature_grid(6, 0.01, 1.0)
+    e = np.array([-0.99, -0.97, -0.975, -0.9, -0.8, -0.6])
+    # points 1 and 2 pool to log(1 + e) = log(sqrt(0.03 * 0.025))
+    pooled = -1.0 + math.sqrt(0.03 * 0.025)
+    T, cl = oracle.invert_temperature(Tg, e, pooled - 1e-4)
+    assert not cl and Tg[0] < T < Tg[1]
+    T, cl = oracle.invert_temperature(Tg, e, pooled + 1e-4)
+    assert not cl and Tg[2] < T < Tg[3]
+    ts = [oracle.invert_temperature(Tg, e, v)[0] for v in np.linspace(-0.989, -0.61, 200)]
+    assert np.all(np.diff(ts) >= 0)
+
+
+# ---------------------------------------------------- stopping behaviour
+def test_stopping_rule_and_imax():
+    """The relaxation stops at a check point (t >= n_fit, t = 0 mod n_f) or at i_max."""
+    im = synth.workload_l64()
+    phi, _ = oracle.map_to_angles(im.z, im.mask)
+    p = oracle.default_params(R=2, K=1, seed=3000)
+    _, st, tr, _ = oracle.simulate(phi, im.mask, 0.18, p, trace_len=400)
+    for c, row in zip(st, tr):
+        t_stop = c["relax_sweeps"] - 1
+        assert t_stop >= p.n_fit and t_stop % p.n_f == 0
+        assert c["k_last"] >= 0 and not c["not_converged"]
+        # the slope at the stop equals the fit through the last n_fit energies
+        seg = row[t_stop + 1 - p.n_fit: t_stop + 1]
+        assert abs(oracle.sg_slope(seg, 1) - c["k_last"]) < 1e-15
+        assert abs(np.polyfit(np.arange(p.n_fit), seg, 1)[0] - c["k_last"]) < 1e-9
+    p = oracle.default_params(R=1, K=1, i_max=7, seed=3000)
+    _, st, _, _ = oracle.simulate(phi, im.mask, 0.18, p)
+    assert st[0]["relax_sweeps"] == 8 and st[0]["not_converged"] == 1
+
+
+def test_no_gaps_is_a_no_op():
+    z = synth.matern_field(8, 8, 0.5, 0.2, 50, 10, 1)
+    m = np.ones((8, 8), np.uint8)
+    phi, zz = oracle.map_to_angles(z, m)
+    ps, st, _, _ = oracle.simulate(phi, m, 0.1, oracle.default_params(K=3))
+    assert np.all(ps == 0) and st[0]["relax_sweeps"] == 0
+    assert np.array_equal(oracle.predict(z, m, ps, 3, zz), z)
+
+
+# --------------------------------------- the paper's printed validation
+@pytest.mark.slow
+def test_reproduces_paper_table2_validation_measures():
+    """Tables 2 and 3 (Section 4): WM nu=0.5 kappa=0.2, N(50,10), p=33%, 66%.
+
+    The paper's measures come from L = 1024 averaged over 100 masks; here two
+    fields at L = 256 with M = 100 (one chain) and T estimated from an e(T)
+    table on a 64 x 64 grid.  Tolerances cover the smaller sample.
+    """
+    with open(os.path.join(HERE, "golden", "paper_table2_validation.json")) as f:
+        gold = json.load(f)
+    Tg = oracle.temperature_grid(10, 0.02, 1.0)
+    etab = oracle.energy_table(64, 64, Tg, 100, 200, seed=12)
+    for key, p_removed in (("p33", 0.33), ("p66", 0.66)):
+        acc = {k: [] for k in ("MAAE", "MARE", "MAARE", "MRASE")}
+        for rep in range(2):
+            im = synth.workload_table2(256, p_removed, rep)
+            phi, zz = oracle.map_to_angles(im.z, im.mask)
+            e_s, _ = oracle.sample_energy(phi, im.mask)
+            T, cl = oracle.invert_temperature(Tg, etab, e_s)
+            assert not cl
+            prm = oracle.default_params(R=1, K=100, seed=3000 + rep)
+            ps, _, _, _ = oracle.simulate(phi, im.mask, T, prm)
+            zh = oracle.predict(im.z, im.mask, ps, 100, zz)
+            for k, v in synth.validation_measures(im.z, zh, im.mask).items():
+                acc[k].append(v)
+        g = gold[key]
+        for k in ("MAAE", "MAARE", "MRASE"):
+            assert abs(np.mean(acc[k]) / g[k] - 1.0) < 0.04, (key, k, np.mean(acc[k]), g[k])
+        assert abs(np.mean(acc["MARE"]) - g["MARE"]) < 0.3, (key, np.mean(acc["MARE"]), g["MARE"])
