@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput of MPR gap filling on one MI355X.
+
+A step is one whole gap fill of the L=4096 workload: angle map, sample
+energy and temperature (e(T, L) table cached per grid size, built during the
+warmup), R=100 independent chains relaxed with the energy stopping rule plus
+K=1 equilibrium state each (M=100 realizations), and the back-transform.
+Inputs are synthetic (lognormal Matern field, 66% of sites removed at
+random) and resident on the GPU before timing starts.
+
+Prints one JSON line: site-updates/s (gap-site updates summed over chains and
+sweeps, divided by wall time), the roofline of the half-sweep kernel (useful
+bytes per launch over its event-timed duration, against 8 TB/s HBM), and the
+FP64 oracle's rate on a bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "site-updates/s at L=4096; time-to-fill at equal MAE, plain vs CNN warm start"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    import synth
+    if name == "l4096-random":
+        return synth.workload_l4096("random"), "lognormal exp(G), G Matern nu=1.5 kappa=0.02 std 0.5; 4096x4096; 66% uniform random gaps"
+    if name == "l4096-cloud":
+        return synth.workload_l4096("cloud"), "lognormal exp(G), G Matern nu=1.5 kappa=0.02 std 0.5; 4096x4096; 40% cloud gaps (Matern threshold)"
+    if name == "l1024":
+        return synth.workload_l1024(), "Gaussian Matern nu=2.5 kappa=0.05 N(50,10); 1024x1024; 50% uniform random gaps"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(im, T: float, sweeps: int, seed: int) -> dict:
+    """The oracle's sweep on one chain of the same workload (bounded sample)."""
+    import numpy as np
+    import oracle
+    z = im.z.astype(np.float32).astype(np.float64)
+    phi, _ = oracle.map_to_angles(z, im.mask)
+    g = im.mask == 0
+    phi[g] = np.random.default_rng(seed).uniform(0.0, 2.0 * np.pi, size=int(g.sum()))
+    P = int(g.sum())
+    t0 = time.perf_counter()
+    for t in range(sweeps):
+        for colour in (0, 1):
+            phi, _, _ = oracle.half_sweep(phi, im.mask, colour, T, 1.0 + t / 3.0, t, seed=seed)
+    dt = time.perf_counter() - t0
+    return {"value": sweeps * P / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} sweeps of 1 chain ({P} gap sites) of the same workload, FP64 oracle, "
+                      f"single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="l4096-random")
+    ap.add_argument("--chains", type=int, default=100)
+    ap.add_argument("--K", type=int, default=1)
+    ap.add_argument("--fixed-sweeps", type=int, default=-1,
+                    help="relax exactly this many sweeps instead of the stopping rule")
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sweep has no multi-GPU path "
+              f"in this library.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1811_01604_amd as mpr
+
+    log(f"workload {args.workload}: generating")
+    im, desc = make_workload(args.workload)
+    log(f"  {im.nx}x{im.ny}, {int((im.mask == 0).sum())} gaps")
+    ctx = mpr.Context(0)
+    shapes = [(im.ny, im.nx)]
+    imgs = mpr.images(shapes)
+    z = torch.from_numpy(im.z.astype(np.float32)).cuda()
+    mk = torch.from_numpy(im.mask).cuda()
+    phi = torch.zeros_like(z)
+    ps = torch.zeros_like(z)
+    zh = torch.zeros_like(z)
+    prm = mpr.default_params(R=args.chains, K=args.K, fixed_relax=args.fixed_sweeps)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    P = int((im.mask == 0).sum())
+    M = prm.R * prm.K
+
+    def step():
+        zz = ctx.map_to_angles(imgs, z, mk, phi)
+        e_s, T, _ = ctx.estimate_temperature(imgs, phi, mk, prm, ws)
+        st = ctx.simulate(imgs, phi, mk, T, prm, ws, ps)
+        ctx.predict(imgs, z, mk, ps, zz, M, zh)
+        return st, float(T[0])
+
+    t0 = time.perf_counter()
+    for i in range(args.warmup):
+        st, T = step()
+        log(f"warmup {i}: T_hat={T:.3e}, relax sweeps mean {np.mean([s['relax_sweeps'] for s in st]):.1f}, "
+            f"{time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    updates = 0
+    sweeps = []
+    for i in range(args.steps):
+        st, T = step()
+        s = [x["relax_sweeps"] + prm.K for x in st]
+        sweeps.extend(s)
+        updates += sum(s) * P
+        log(f"step {i}: mean sweeps/chain {np.mean(s):.1f}, {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    zt = im.z.astype(np.float32)
+    g = im.mask == 0
+    mae = float(np.mean(np.abs(zh.cpu().numpy()[g] - zt[g])))
+    assert prof["site_updates"] == updates, (prof["site_updates"], updates)
+    launch_ms = prof["sweep_kernel_ms"] / max(prof["sweep_launches"], 1)
+    bytes_per_launch = prof["useful_bytes"] / max(prof["sweep_launches"], 1)
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": updates / dt,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "chains_R": prm.R, "states_per_chain_K": prm.K, "gap_sites": P,
+            "relaxation": "stopping rule" if args.fixed_sweeps < 0 else f"fixed {args.fixed_sweeps} sweeps",
+            "mean_sweeps_per_chain": float(np.mean(sweeps)),
+            "T_hat": T, "MAE": mae,
+            "e_T_table": "cached per grid size, built during warmup",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "half_sweep_kernel",
+            "launch_ms": launch_ms, "useful_bytes_per_launch": bytes_per_launch,
+            "sweep_kernel_time_share": prof["sweep_kernel_ms"] * 1e-3 / dt,
+        },
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(im, T, args.cpu_sweeps, 3002)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

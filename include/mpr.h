@@ -1,0 +1,228 @@
+/*
+ * mpr.h - C ABI of the MI355X (gfx950) library for gap filling with the
+ * modified planar rotator (MPR) model: Zukovic, Borovsky, Lach and
+ * Hristopulos, "GPU-accelerated simulation of massive spatial data based on
+ * the modified planar rotator model", arXiv:1811.01604.
+ *
+ * Problem (Section 2.1): an nx x ny grid of which some sites are sampled
+ * (values z known) and the rest are gaps; the library predicts the gaps.
+ * The calls follow the steps of Algorithm 2:
+ *   mpr_map_to_angles        step 3   (equation "map")
+ *   mpr_estimate_temperature step 4   (equations "mpr-sse" and "ene")
+ *   mpr_simulate             steps 2, 5, 6 (Algorithm 1 sweeps, the stopping
+ *                            rule, the equilibrium states)
+ *   mpr_predict              steps 6.3 and 7 (back-transform of the mean)
+ *
+ * Conventions
+ *  - Grids are row-major with x fastest: element (x, y) of image b is at
+ *    index imgs[b].offset + y * imgs[b].nx + x of every per-site buffer.
+ *  - (dev) pointers are device pointers on the context's device; (host)
+ *    pointers are host memory.  The caller owns every buffer, including the
+ *    device workspace sized by mpr_workspace_size.  The library does not
+ *    allocate device memory in these calls (the mpr_diag_* calls excepted).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *    enqueued on it and every call synchronises the stream before it
+ *    returns.
+ *  - Sampled flags are uint8: nonzero = sampled (fixed), 0 = gap.
+ *  - Every call returns MPR_OK (0) or an error code; mpr_last_error gives a
+ *    text for the most recent failure on the context.  No C++ exception
+ *    crosses the boundary.  A context is used by one host thread at a time.
+ */
+#ifndef MPR_H
+#define MPR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MPR_OK = 0,
+    MPR_ERR_ARG = 1,         /* invalid argument (null pointer, bad size, non-finite sample) */
+    MPR_ERR_DEGENERATE = 2,  /* data the method cannot handle, see each call */
+    MPR_ERR_WORKSPACE = 3,   /* workspace smaller than mpr_workspace_size */
+    MPR_ERR_HIP = 4          /* a HIP runtime call failed */
+};
+
+typedef struct mpr_ctx mpr_ctx;
+
+/* One image of a (possibly ragged) batch. */
+typedef struct {
+    int32_t nx, ny;   /* grid size; nx * ny >= 2 */
+    int64_t offset;   /* element offset of the image in per-site buffers */
+    uint32_t id;      /* random-stream id of the image (Philox counter word 3,
+                         must be < 2^31); results depend on it, not on the
+                         image's position in the batch */
+    uint32_t reserved;
+} mpr_image;
+
+/* Simulation parameters (Algorithm 2 step 1.1, Section 2.3).  The paper
+ * leaves the defaults to earlier work; mpr_default_params fills the values
+ * this library uses. */
+typedef struct {
+    double q;             /* coupling exponent, 1/2 (Section 2.2) */
+    int32_t R;            /* independent chains per image */
+    int32_t K;            /* equilibrium states per chain; M = R * K realizations */
+    int32_t n_f;          /* slope checked every n_f sweeps ... */
+    int32_t n_fit;        /* ... from the last n_fit energies (2..64) */
+    int32_t sg_degree;    /* degree of the Savitzky-Golay fit (1..4) */
+    int32_t i_max;        /* cap on relaxation sweeps (relaxation runs while t <= i_max) */
+    double a_targ;        /* target acceptance ratio */
+    double k_a;           /* a(i+1) = 1 + (i+1)/k_a when the acceptance ratio < a_targ */
+    int32_t fixed_relax;  /* -1: stopping rule; >= 0: exactly this many relaxation sweeps */
+    int32_t eq_a_mode;    /* 0: a = 1 in the equilibrium states (Algorithm 2 step 6.2);
+                             1: keep the final relaxation a */
+    /* e(T, L) table for the temperature (equation "ene"): table_nT
+     * temperatures log-spaced over [table_T_lo, table_T_hi], unconditional
+     * runs from phi = pi with table_burn + table_meas sweeps each. */
+    int32_t table_nT;
+    int32_t table_burn;
+    int32_t table_meas;
+    int32_t reserved;
+    double table_T_lo, table_T_hi;
+    uint64_t seed;        /* Philox key */
+} mpr_params;
+
+/* Per chain results of mpr_simulate (R per image, image-major). */
+typedef struct {
+    int32_t relax_sweeps;   /* relaxation sweeps performed */
+    int32_t not_converged;  /* 1 if i_max stopped the relaxation */
+    double a_final;         /* a at the end of the relaxation */
+    double A_last;          /* acceptance ratio of the last relaxation sweep */
+    double k_last;          /* last energy slope */
+} mpr_chain_stats;
+
+/* Context on HIP device `device`.  Returns MPR_ERR_HIP if the device cannot
+ * be used.  The context caches e(T, L) tables by grid size and parameters. */
+int32_t mpr_create(mpr_ctx **ctx, int32_t device);
+void mpr_destroy(mpr_ctx *ctx);
+/* Text of the last error on ctx (valid until the next call on ctx). */
+const char *mpr_last_error(const mpr_ctx *ctx);
+/* Defaults: q=0.5, R=1, K=100, n_f=5, n_fit=20, sg_degree=1, i_max=20000,
+ * a_targ=0.3, k_a=3, fixed_relax=-1, eq_a_mode=0, table 32 points over
+ * [1e-5, 10], 200 + 400 sweeps, seed 3000. */
+void mpr_default_params(mpr_params *p);
+
+/* Device workspace bytes needed by mpr_estimate_temperature and
+ * mpr_simulate for this batch; < 0 on invalid arguments. */
+int64_t mpr_workspace_size(const mpr_image *imgs, int32_t n_images, const mpr_params *p);
+
+/* Equation (map): phi = 2 pi (z - z_min) / (z_max - z_min) at the sampled
+ * sites, with z_min, z_max over the image's samples; gaps get 0.
+ *   z        (dev, float)  data; gap values are ignored
+ *   sampled  (dev, uint8)
+ *   phi      (dev, float, out)
+ *   zmin_zmax (host, double[2 * n_images], out)
+ * The map is evaluated in double precision and rounded once, so sampled
+ * angles are exactly 0 at z_min and the float nearest 2 pi at z_max.
+ * Errors: MPR_ERR_ARG for a non-finite sampled z; MPR_ERR_DEGENERATE if an
+ * image has fewer than 2 samples or z_max == z_min. */
+int32_t mpr_map_to_angles(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
+                          const float *z, const uint8_t *sampled, float *phi,
+                          double *zmin_zmax, void *stream);
+
+/* Section 2.3, Algorithm 2 step 4: the sample specific energy e_s (equation
+ * "mpr-sse", each unordered sample-sample nearest-neighbour pair once) and
+ * T_hat with e(T_hat, L) = e_s.  e(T, L) (equation "ene") comes from
+ * unconditional simulations on the image's grid size with this library's
+ * own sweep, tabulated per mpr_params table_* fields, made monotone and
+ * interpolated in (log T, log(1 + e)).  Tables are cached in ctx.
+ *   phi, sampled (dev)  angles from mpr_map_to_angles
+ *   workspace (dev)     ws_bytes >= mpr_workspace_size
+ *   e_s, T_hat (host, double[n_images], out)
+ *   t_clamped (host, int32[n_images], out, nullable): 1 when e_s lies
+ *             outside the table and T_hat is the end temperature.
+ * Errors: MPR_ERR_DEGENERATE when an image has no sample-sample pair. */
+int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
+                                 const float *phi, const uint8_t *sampled,
+                                 const mpr_params *p, void *workspace, int64_t ws_bytes,
+                                 double *e_s, double *T_hat, int32_t *t_clamped,
+                                 void *stream);
+
+/* Algorithm 2 steps 2, 5 and 6 with Algorithm 1 sweeps on the GPU, for all
+ * images and R chains per image at once.  Each chain starts from U(0, 2 pi)
+ * gap angles (or phi_init), relaxes with the hybrid update until the energy
+ * slope is >= 0 or i_max (or fixed_relax sweeps), then runs K equilibrium
+ * sweeps.  Random numbers are Philox4x32-10 keyed by (seed; site, sweep,
+ * chain, image id), so results do not depend on launch shapes or batch
+ * composition.
+ *   phi, sampled (dev)  sample angles (gap entries ignored)
+ *   T_hat (host, double[n_images])
+ *   phi_init (dev, float, nullable)  starting gap angles in [0, 2 pi)
+ *   phi_sum (dev, float, out)  sum of the M = R*K states at gap sites, 0 at samples
+ *   stats (host, mpr_chain_stats[n_images * R], out, nullable)
+ * An image without gaps is left unchanged (phi_sum 0).
+ * Errors: MPR_ERR_WORKSPACE if ws_bytes is too small. */
+int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
+                     const float *phi, const uint8_t *sampled, const double *T_hat,
+                     const mpr_params *p, const float *phi_init, void *workspace,
+                     int64_t ws_bytes, float *phi_sum, mpr_chain_stats *stats,
+                     void *stream);
+
+/* Algorithm 2 steps 6.3 and 7 with the mean as the statistic:
+ * z_hat = z_min (1 - t) + z_max t with t = (phi_sum / M) / (2 pi) at gaps
+ * (double precision, rounded once); sampled sites are copied bit-exactly.
+ * All buffers (dev) except zmin_zmax (host). */
+int32_t mpr_predict(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
+                    const float *z, const uint8_t *sampled, const float *phi_sum,
+                    const double *zmin_zmax, int32_t M, float *z_hat, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Profiling.  While enabled, mpr_simulate and mpr_estimate_temperature
+ * bracket every sweep's two half-sweep launches with HIP events on the
+ * caller's stream, and count the work done: chain-sweeps, gap-site updates
+ * and the method's useful HBM bytes (4 bytes per site read + 4 per gap site
+ * written, per chain-sweep).  mpr_profile_read returns the totals since the
+ * last mpr_profile_enable(ctx, 1). */
+typedef struct {
+    double sweep_kernel_ms;   /* summed event time of the half-sweep launches */
+    int64_t sweep_launches;   /* half-sweep launches timed */
+    int64_t chain_sweeps;     /* sweeps summed over chains that were active */
+    int64_t site_updates;     /* gap-site updates summed over those sweeps */
+    double useful_bytes;      /* sum of (4 nx ny + 4 P) over those sweeps */
+} mpr_profile;
+
+int32_t mpr_profile_enable(mpr_ctx *ctx, int32_t on);
+int32_t mpr_profile_read(mpr_ctx *ctx, mpr_profile *out);
+
+/* ------------------------------------------------------------------ */
+/* Diagnostics: the production kernels on one grid, for parity testing.
+ * These calls allocate scratch device memory and synchronise. */
+
+/* Philox4x32-10 of n counters (dev, uint32[4n]) with key `seed`, into out
+ * (dev, uint32[4n]). */
+int32_t mpr_diag_philox(mpr_ctx *ctx, const uint32_t *ctr, uint64_t seed, int64_t n,
+                        uint32_t *out, void *stream);
+
+/* One half-sweep (Algorithm 1 on the gap sites of one checkerboard colour,
+ * colour = (x + y) & 1) of an nx x ny grid in place.
+ *   phi (dev, float, in/out), sampled (dev, uint8)
+ *   mode 0: full hybrid update; 1: over-relaxation only
+ *   flags (dev, uint8, out, nullable): per site bit 0 = reflection kept the
+ *         spin, bit 1 = proposal accepted, bit 2 = proposal wrapped,
+ *         bit 3 = site updated, bit 4 = decided by the double-precision path
+ *   accepted (host, int64, out, nullable)
+ * (sweep, chain, stream_id) select the random numbers as in mpr_simulate. */
+int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi,
+                            const uint8_t *sampled, int32_t colour, double T, double a,
+                            double q, uint64_t seed, uint32_t sweep, uint32_t chain,
+                            uint32_t stream_id, int32_t mode, uint8_t *flags,
+                            int64_t *accepted, void *stream);
+
+/* H + N_GP of an nx x ny grid of angles (dev, float) as the simulation
+ * accumulates it: sum over bonds of (1 - cos(q (phi_i - phi_j))) in fixed
+ * point; returned in double (host). */
+int32_t mpr_diag_energy(mpr_ctx *ctx, int32_t nx, int32_t ny, const float *phi, double q,
+                        double *h_plus_ngp, void *stream);
+
+/* The device stopping-rule slope: derivative at the newest point of the
+ * degree-`degree` least-squares polynomial through e[0..n-1] (host). */
+int32_t mpr_diag_sg_slope(mpr_ctx *ctx, const double *e, int32_t n, int32_t degree,
+                          double *slope);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPR_H */

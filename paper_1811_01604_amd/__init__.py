@@ -1,0 +1,247 @@
+"""Python binding of the MPR gap-filling library (include/mpr.h).
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libmpr.so``.  Device buffers are torch tensors on a ROCm device (torch is
+used for memory and streams); host outputs come back as numpy arrays.  If the
+shared library is missing or cannot be loaded, importing works but every call
+raises ``MprLibraryError``: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpr.so")
+
+MPR_OK, MPR_ERR_ARG, MPR_ERR_DEGENERATE, MPR_ERR_WORKSPACE, MPR_ERR_HIP = range(5)
+FLAG_KEPT, FLAG_ACCEPTED, FLAG_WRAPPED, FLAG_UPDATED, FLAG_FP64 = 1, 2, 4, 8, 16
+
+# Every symbol include/mpr.h declares.
+EXPORTS = [
+    "mpr_create", "mpr_destroy", "mpr_last_error", "mpr_default_params", "mpr_workspace_size",
+    "mpr_map_to_angles", "mpr_estimate_temperature", "mpr_simulate", "mpr_predict",
+    "mpr_profile_enable", "mpr_profile_read",
+    "mpr_diag_philox", "mpr_diag_half_sweep", "mpr_diag_energy", "mpr_diag_sg_slope",
+]
+
+
+class MprLibraryError(RuntimeError):
+    pass
+
+
+class MprError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mpr error {code}: {msg}")
+        self.code = code
+
+
+class Image(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("offset", C.c_int64),
+                ("id", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("q", C.c_double), ("R", C.c_int32), ("K", C.c_int32), ("n_f", C.c_int32),
+        ("n_fit", C.c_int32), ("sg_degree", C.c_int32), ("i_max", C.c_int32),
+        ("a_targ", C.c_double), ("k_a", C.c_double), ("fixed_relax", C.c_int32),
+        ("eq_a_mode", C.c_int32), ("table_nT", C.c_int32), ("table_burn", C.c_int32),
+        ("table_meas", C.c_int32), ("reserved", C.c_int32), ("table_T_lo", C.c_double),
+        ("table_T_hi", C.c_double), ("seed", C.c_uint64),
+    ]
+
+
+class Profile(C.Structure):
+    _fields_ = [("sweep_kernel_ms", C.c_double), ("sweep_launches", C.c_int64),
+                ("chain_sweeps", C.c_int64), ("site_updates", C.c_int64), ("useful_bytes", C.c_double)]
+
+
+class ChainStats(C.Structure):
+    _fields_ = [("relax_sweeps", C.c_int32), ("not_converged", C.c_int32),
+                ("a_final", C.c_double), ("A_last", C.c_double), ("k_last", C.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmpr.so (building it first only when it does not exist)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        from . import build as _build
+        try:
+            _build.build()
+        except Exception as e:  # no compiler: no library, no fallback
+            raise MprLibraryError(f"{path} is missing and could not be built: {e}") from e
+    try:
+        lib = C.CDLL(path)
+    except OSError as e:
+        raise MprLibraryError(f"cannot load {path}: {e}") from e
+    _declare(lib)
+    _lib = lib
+    return lib
+
+
+def _declare(L):
+    P, i32, i64, u32, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+    IMG, PRM = C.POINTER(Image), C.POINTER(Params)
+    sig = {
+        "mpr_create": (i32, [C.POINTER(C.c_void_p), i32]),
+        "mpr_destroy": (None, [P]),
+        "mpr_last_error": (C.c_char_p, [P]),
+        "mpr_default_params": (None, [PRM]),
+        "mpr_workspace_size": (i64, [IMG, i32, PRM]),
+        "mpr_map_to_angles": (i32, [P, IMG, i32, P, P, P, P, P]),
+        "mpr_estimate_temperature": (i32, [P, IMG, i32, P, P, PRM, P, i64, P, P, P, P]),
+        "mpr_simulate": (i32, [P, IMG, i32, P, P, P, PRM, P, P, i64, P, C.POINTER(ChainStats), P]),
+        "mpr_predict": (i32, [P, IMG, i32, P, P, P, P, i32, P, P]),
+        "mpr_profile_enable": (i32, [P, i32]),
+        "mpr_profile_read": (i32, [P, C.POINTER(Profile)]),
+        "mpr_diag_philox": (i32, [P, P, u64, i64, P, P]),
+        "mpr_diag_half_sweep": (i32, [P, i32, i32, P, P, i32, d, d, d, u64, u32, u32, u32, i32, P, P, P]),
+        "mpr_diag_energy": (i32, [P, i32, i32, P, d, P, P]),
+        "mpr_diag_sg_slope": (i32, [P, P, i32, i32, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    load().mpr_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def images(shapes, ids=None):
+    """ctypes array of mpr_image for a packed batch of (ny, nx) shapes."""
+    arr = (Image * len(shapes))()
+    off = 0
+    for b, (ny, nx) in enumerate(shapes):
+        arr[b].nx, arr[b].ny, arr[b].offset = nx, ny, off
+        arr[b].id = b if ids is None else ids[b]
+        off += nx * ny
+    return arr
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """An mpr_ctx on one device; methods mirror the C calls."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self._h = C.c_void_p()
+        rc = self.lib.mpr_create(C.byref(self._h), device)
+        if rc != MPR_OK:
+            raise MprError(rc, f"mpr_create(device={device}) failed")
+        self.device = device
+
+    def close(self):
+        if self._h:
+            self.lib.mpr_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != MPR_OK:
+            raise MprError(rc, self.lib.mpr_last_error(self._h).decode())
+
+    # -------------------------------------------------------------- calls
+    def workspace_size(self, imgs, params) -> int:
+        return int(self.lib.mpr_workspace_size(imgs, len(imgs), C.byref(params)))
+
+    def map_to_angles(self, imgs, z, sampled, phi, stream=None) -> np.ndarray:
+        zz = np.zeros(2 * len(imgs))
+        self._check(self.lib.mpr_map_to_angles(self._h, imgs, len(imgs), _ptr(z), _ptr(sampled), _ptr(phi),
+                                               zz.ctypes.data_as(C.c_void_p), _stream(stream)))
+        return zz
+
+    def estimate_temperature(self, imgs, phi, sampled, params, ws, stream=None):
+        n = len(imgs)
+        e_s, T = np.zeros(n), np.zeros(n)
+        cl = np.zeros(n, dtype=np.int32)
+        self._check(self.lib.mpr_estimate_temperature(
+            self._h, imgs, n, _ptr(phi), _ptr(sampled), C.byref(params), _ptr(ws), ws.numel() * ws.element_size(),
+            e_s.ctypes.data_as(C.c_void_p), T.ctypes.data_as(C.c_void_p), cl.ctypes.data_as(C.c_void_p),
+            _stream(stream)))
+        return e_s, T, cl
+
+    def simulate(self, imgs, phi, sampled, T_hat, params, ws, phi_sum, phi_init=None, stream=None):
+        n = len(imgs)
+        T = np.ascontiguousarray(T_hat, dtype=np.float64)
+        st = (ChainStats * (n * params.R))()
+        self._check(self.lib.mpr_simulate(
+            self._h, imgs, n, _ptr(phi), _ptr(sampled), T.ctypes.data_as(C.c_void_p), C.byref(params),
+            _ptr(phi_init), _ptr(ws), ws.numel() * ws.element_size(), _ptr(phi_sum), st, _stream(stream)))
+        return [dict(relax_sweeps=s.relax_sweeps, not_converged=s.not_converged, a_final=s.a_final,
+                     A_last=s.A_last, k_last=s.k_last) for s in st]
+
+    def predict(self, imgs, z, sampled, phi_sum, zmin_zmax, M, z_hat, stream=None):
+        zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)
+        self._check(self.lib.mpr_predict(self._h, imgs, len(imgs), _ptr(z), _ptr(sampled), _ptr(phi_sum),
+                                         zz.ctypes.data_as(C.c_void_p), M, _ptr(z_hat), _stream(stream)))
+
+    # ---------------------------------------------------------- profiling
+    def profile_enable(self, on=True):
+        self._check(self.lib.mpr_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        p = Profile()
+        self._check(self.lib.mpr_profile_read(self._h, C.byref(p)))
+        return {k: getattr(p, k) for k, _ in Profile._fields_}
+
+    # -------------------------------------------------------- diagnostics
+    def diag_philox(self, ctr, seed, out, stream=None):
+        self._check(self.lib.mpr_diag_philox(self._h, _ptr(ctr), seed, ctr.numel() // 4, _ptr(out),
+                                             _stream(stream)))
+
+    def diag_half_sweep(self, phi, sampled, colour, T, a, sweep, chain=0, stream_id=0, seed=3000, q=0.5,
+                        mode=0, flags=None, stream=None) -> int:
+        ny, nx = phi.shape
+        acc = C.c_int64()
+        self._check(self.lib.mpr_diag_half_sweep(self._h, nx, ny, _ptr(phi), _ptr(sampled), colour, T, a, q, seed,
+                                                 sweep, chain, stream_id, mode, _ptr(flags), C.byref(acc),
+                                                 _stream(stream)))
+        return acc.value
+
+    def diag_energy(self, phi, q=0.5, stream=None) -> float:
+        ny, nx = phi.shape
+        out = C.c_double()
+        self._check(self.lib.mpr_diag_energy(self._h, nx, ny, _ptr(phi), q, C.byref(out), _stream(stream)))
+        return out.value
+
+    def diag_sg_slope(self, e, degree=1) -> float:
+        e = np.ascontiguousarray(e, dtype=np.float64)
+        out = C.c_double()
+        self._check(self.lib.mpr_diag_sg_slope(self._h, e.ctypes.data_as(C.c_void_p), e.size, degree,
+                                               C.byref(out)))
+        return out.value

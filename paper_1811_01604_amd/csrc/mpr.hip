@@ -1,0 +1,1357 @@
+// MI355X (gfx950) implementation of the C ABI in include/mpr.h: MPR gap
+// filling with the checkerboard hybrid Monte Carlo sweep (arXiv:1811.01604,
+// Algorithms 1 and 2, Section 3.3).
+//
+// Kernels
+//   init_chains       gap angles U(0, 2 pi) from Philox (Algorithm 2 step 2.2)
+//                     or a warm start; samples stored with the sign bit set
+//   half_sweep        Algorithm 1 on the gap sites of one colour for every
+//                     chain; the colour-1 pass also sums all bond energies
+//                     (every bond has exactly one colour-1 end) and both
+//                     passes count accepted proposals
+//   control           Algorithm 2 steps 5.2-5.5 and 6 per chain: a-rule,
+//                     e(i+1), Savitzky-Golay slope, phase changes
+//   finalize          sum of the M states per gap site
+//   map_*, predict    equation (map) and its inverse
+//   sample_energy     equation (mpr-sse)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mpr.h"
+#include "mpr_device.h"
+
+using namespace mpr;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMapBlocks = 64;           // partial-result blocks per image (map, e_s)
+constexpr size_t kScratchBytes = 8u << 20;
+constexpr uint32_t kTableStream = 0x80000000u;
+constexpr uint32_t kInitSweep = 0xFFFFFFFFu;
+// Layout of the context's device scratch: fixed slots, then a region for
+// per-call partial results.
+constexpr int64_t kDoneOffset = 0;       // done-chain counter
+constexpr int64_t kWorkOffset = 1024;    // three work counters (profiling)
+constexpr int64_t kEnergyOffset = 2048;  // diag energy accumulator
+constexpr int64_t kSlopeOffset = 4096;   // diag slope input / output
+constexpr int64_t kVarOffset = 65536;    // per-call partials
+
+// Parameters of the control kernel.
+struct CtlParams {
+    double a_targ, k_a, q;
+    int32_t n_f, n_fit, i_max, fixed_relax, eq_a_mode, K, burn, meas;
+    double w[kMaxFit];  // Savitzky-Golay derivative weights, oldest first
+};
+
+struct ImgDev {
+    int64_t offset;
+    int32_t nx, ny;
+};
+
+}  // namespace
+
+// ====================================================================== kernels
+
+// Slope of the energy series from the ring buffer: sum_j w_j e(t+1-n_fit+j).
+__device__ double ring_slope(const double *ring, uint32_t t, int n_fit, const double *w)
+{
+    double s = 0.0;
+    for (int j = 0; j < n_fit; ++j) {
+        // e(t + 1 - n_fit + j) was stored at slot (t + 1 - n_fit + j) mod n_fit
+        const uint32_t idx = (t + 1u + (uint32_t)j) % (uint32_t)n_fit;
+        s += w[j] * ring[idx];
+    }
+    return s;
+}
+
+__global__ void init_chains_kernel(const ChainDesc *__restrict__ descs, const int64_t *__restrict__ offsets,
+                                   const float *__restrict__ phi, const uint8_t *__restrict__ sampled,
+                                   const float *__restrict__ phi_init, uint32_t seed_lo, uint32_t seed_hi,
+                                   int table_mode)
+{
+    const ChainDesc d = descs[blockIdx.y];
+    const int64_t n = (int64_t)d.nx * d.ny;
+    const int64_t off = offsets[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / d.nx);
+        const int x = (int)(i - (int64_t)y * d.nx);
+        const int c = (x + y) & 1;
+        const int h = x >> 1;
+        float v;
+        if (table_mode) {
+            v = (float)kPi;
+        } else if (sampled[off + i]) {
+            v = mark_fixed(fabsf(phi[off + i]));
+        } else if (phi_init) {
+            v = phi_init[off + i];
+        } else {
+            U4 ctr = {(uint32_t)y * (uint32_t)d.nx + ((uint32_t)x & ~2u), kInitSweep, d.chain, d.image_id};
+            const U4 w = philox4x32_10(ctr, seed_lo, seed_hi);
+            const uint32_t word = ((x >> 1) & 1) ? w.z : w.x;
+            v = (float)(kTwoPi * (double)unit24(word));
+        }
+        d.h[c][(int64_t)y * d.S + h] = v;
+        if (d.acc[c]) d.acc[c][(int64_t)y * d.S + h] = 0.0f;
+    }
+}
+
+// Half-sweep of colour `colour` for every chain (blockIdx.y = chain).  Each
+// thread takes two neighbouring sites h0 = 2k and h0 + 1 of one half-row;
+// they share one Philox call.
+template <bool DIAG>
+__global__ __launch_bounds__(kBlock) void half_sweep_kernel(const ChainDesc *__restrict__ descs,
+                                                            ChainState *__restrict__ states, int colour,
+                                                            SweepConsts sc, int or_only,
+                                                            uint8_t *__restrict__ flags)
+{
+    ChainState *stp = states + blockIdx.y;
+    const int phase = stp->phase;
+    if (phase == PH_DONE) return;
+    const ChainDesc d = descs[blockIdx.y];
+    const int half = d.S >> 1;
+    const int64_t total = (int64_t)d.ny * half;
+    if ((int64_t)blockIdx.x * blockDim.x >= total) return;
+    ChainState st;
+    st.sweep = stp->sweep;
+    st.inv_T = stp->inv_T;
+    st.dscale = stp->dscale;
+    st.T = stp->T;
+    st.a_cur = stp->a_cur;
+    const bool want_energy = (colour == 1) && (phase != PH_EQ);
+    const bool want_acc = phase != PH_EQ;
+    unsigned long long efx = 0ull, nacc = 0ull;
+
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < total) {
+        const int y = (int)(p / half);
+        const int h0 = 2 * (int)(p - (int64_t)y * half);
+        const int s = (y + colour) & 1;
+        const int W = (d.nx - s + 1) >> 1;
+        const int Wo = (d.nx + s) >> 1;
+        if (h0 < W) {
+            const bool two = (h0 + 1) < W;
+            float *mine = d.h[colour] + (int64_t)y * d.S;
+            const float *oth = d.h[colour ^ 1] + (int64_t)y * d.S;
+            const float2 v = *reinterpret_cast<const float2 *>(mine + h0);
+            float oL = 0.0f, oM = 0.0f, oR = 0.0f;
+            const bool vL = h0 + s - 1 >= 0, vM = h0 + s < Wo, vR = h0 + s + 1 < Wo;
+            if (vL) oL = oth[h0 + s - 1];
+            if (vM) oM = oth[h0 + s];
+            if (vR) oR = oth[h0 + s + 1];
+            float2 up = make_float2(0.0f, 0.0f), dn = make_float2(0.0f, 0.0f);
+            const bool vU = y > 0, vD = y + 1 < d.ny;
+            if (vU) up = *reinterpret_cast<const float2 *>(oth - d.S + h0);
+            if (vD) dn = *reinterpret_cast<const float2 *>(oth + d.S + h0);
+            // neighbour unit vectors (cos, sin of q*phi); missing ones are 0
+            float cL = 0.f, sL = 0.f, cM = 0.f, sM = 0.f, cR = 0.f, sR = 0.f;
+            float cU0 = 0.f, sU0 = 0.f, cU1 = 0.f, sU1 = 0.f, cD0 = 0.f, sD0 = 0.f, cD1 = 0.f, sD1 = 0.f;
+            oL = angle_of(oL);
+            oM = angle_of(oM);
+            oR = angle_of(oR);
+            up.x = angle_of(up.x);
+            up.y = angle_of(up.y);
+            dn.x = angle_of(dn.x);
+            dn.y = angle_of(dn.y);
+            if (vL) sincosf(sc.q * oL, &sL, &cL);
+            if (vM) sincosf(sc.q * oM, &sM, &cM);
+            if (vR && two) sincosf(sc.q * oR, &sR, &cR);
+            if (vU) {
+                sincosf(sc.q * up.x, &sU0, &cU0);
+                if (two) sincosf(sc.q * up.y, &sU1, &cU1);
+            }
+            if (vD) {
+                sincosf(sc.q * dn.x, &sD0, &cD0);
+                if (two) sincosf(sc.q * dn.y, &sD1, &cD1);
+            }
+            const bool fixed0 = is_fixed(v.x), fixed1 = !two || is_fixed(v.y);
+            float u0 = 0.f, r0 = 0.f, u1 = 0.f, r1 = 0.f;
+            if (!or_only && (!fixed0 || !fixed1)) {
+                const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * h0 + s), st.sweep, d.chain,
+                                d.image_id};
+                const U4 w = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
+                u0 = unit24(w.x);
+                r0 = unit24(w.y);
+                u1 = unit24(w.z);
+                r1 = unit24(w.w);
+            }
+            float out0 = v.x, out1 = v.y;
+            uint32_t f0 = 0u, f1 = 0u;
+            // site h0: left oL, right oM, up up.x, down dn.x
+            const float nb0[4] = {oL, oM, up.x, dn.x};
+            const float nc0[4] = {cL, cM, cU0, cD0};
+            const float ns0[4] = {sL, sM, sU0, sD0};
+            const uint32_t val0 = (vL ? 1u : 0u) | (vM ? 2u : 0u) | (vU ? 4u : 0u) | (vD ? 8u : 0u);
+            // site h0+1: left oM, right oR, up up.y, down dn.y
+            const float nb1[4] = {oM, oR, up.y, dn.y};
+            const float nc1[4] = {cM, cR, cU1, cD1};
+            const float ns1[4] = {sM, sR, sU1, sD1};
+            const uint32_t val1 = 1u | (vR ? 2u : 0u) | (vU ? 4u : 0u) | (vD ? 8u : 0u);
+            if (!fixed0) {
+                const SiteOut o = update_site(v.x, nb0, val0, nc0, ns0, u0, r0, st, sc, or_only != 0);
+                out0 = o.phi;
+                f0 = o.flags;
+            }
+            if (!fixed1) {
+                const SiteOut o = update_site(v.y, nb1, val1, nc1, ns1, u1, r1, st, sc, or_only != 0);
+                out1 = o.phi;
+                f1 = o.flags;
+            }
+            if (two) {
+                *reinterpret_cast<float2 *>(mine + h0) = make_float2(out0, out1);
+            } else if (!fixed0) {
+                mine[h0] = out0;
+            }
+            if (phase == PH_EQ && d.acc[colour]) {
+                float *acc = d.acc[colour] + (int64_t)y * d.S;
+                if (!fixed0) acc[h0] += out0;
+                if (two && !fixed1) acc[h0 + 1] += out1;
+            }
+            if (want_acc) nacc = ((f0 & F_ACCEPTED) ? 1ull : 0ull) + ((f1 & F_ACCEPTED) ? 1ull : 0ull);
+            if (want_energy) {
+                float c0, s0;
+                sincosf(sc.q * angle_of(out0), &s0, &c0);
+                efx = site_energy_fx(c0, s0, nc0, ns0, val0);
+                if (two) {
+                    float c1, s1;
+                    sincosf(sc.q * angle_of(out1), &s1, &c1);
+                    efx += site_energy_fx(c1, s1, nc1, ns1, val1);
+                }
+            }
+            if (DIAG && flags) {
+                const int64_t x0 = 2 * h0 + s;
+                flags[(int64_t)y * d.nx + x0] = (uint8_t)f0;
+                if (two) flags[(int64_t)y * d.nx + x0 + 2] = (uint8_t)f1;
+            }
+        }
+    }
+    if (!want_acc) return;
+    // block reduction of the two counters
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        efx += __shfl_xor(efx, off);
+        nacc += __shfl_xor(nacc, off);
+    }
+    __shared__ unsigned long long red[2][kBlock / 64];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        red[0][wid] = efx;
+        red[1][wid] = nacc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long e = 0ull, a = 0ull;
+        for (int i = 0; i < kBlock / 64; ++i) {
+            e += red[0][i];
+            a += red[1][i];
+        }
+        if (e) atomicAdd(&stp->e_fx, e);
+        if (a) atomicAdd(&stp->acc, a);
+    }
+}
+
+__device__ void set_derived(ChainState &st, double q)
+{
+    st.inv_T = (float)(1.0 / st.T);
+    st.dscale = (float)(kTwoPi * q / st.a_cur);
+}
+
+// Algorithm 2 steps 5.2-5.5 (relaxation), 6 (equilibrium states) and the
+// e(T, L) runs, one thread per chain, after both half-sweeps of a sweep.
+__global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *__restrict__ states, int n,
+                               CtlParams cp, unsigned int *done_count, unsigned long long *work)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    ChainState st = states[c];
+    if (st.phase == PH_DONE) return;
+    const ChainDesc d = descs[c];
+    // work counters: chain-sweeps, gap-site updates, useful bytes
+    atomicAdd(&work[0], 1ull);
+    atomicAdd(&work[1], (unsigned long long)d.P);
+    atomicAdd(&work[2], (unsigned long long)(4 * (int64_t)d.nx * d.ny + 4 * d.P));
+    const uint32_t t = st.sweep;
+    const unsigned long long acc = st.acc, efx = st.e_fx;
+    st.acc = 0ull;
+    st.e_fx = 0ull;
+    // 1 + e = (H + N_GP) / N_GP, H + N_GP = sum (1 - cos) = efx * 2^-32
+    const double ope = (double)efx * (1.0 / 4294967296.0) / (double)d.ngp;
+    if (st.phase == PH_RELAX) {
+        const double A = (double)acc / (double)d.P;
+        if (A < cp.a_targ) st.a_relax = 1.0 + (double)(t + 1u) / cp.k_a;
+        st.ring[t % (uint32_t)cp.n_fit] = ope;
+        if (t >= (uint32_t)cp.n_fit && t % (uint32_t)cp.n_f == 0u) st.k = ring_slope(st.ring, t, cp.n_fit, cp.w);
+        st.A_last = A;
+        const uint32_t tn = t + 1u;
+        st.sweep = tn;
+        bool stop;
+        if (cp.fixed_relax >= 0) stop = tn >= (uint32_t)cp.fixed_relax;
+        else stop = !(st.k < 0.0 && (int64_t)tn <= (int64_t)cp.i_max);
+        st.a_cur = st.a_relax;
+        if (stop) {
+            st.relax_sweeps = (int32_t)tn;
+            st.not_converged = (cp.fixed_relax < 0 && st.k < 0.0) ? 1 : 0;
+            st.eq_left = cp.K;
+            st.phase = cp.K > 0 ? PH_EQ : PH_DONE;
+            st.a_cur = cp.eq_a_mode ? st.a_relax : 1.0;
+        }
+    } else if (st.phase == PH_EQ) {
+        st.sweep = t + 1u;
+        if (--st.eq_left <= 0) st.phase = PH_DONE;
+    } else {  // PH_TABLE
+        const double A = (double)acc / (double)d.P;
+        if (A < cp.a_targ) st.a_relax = 1.0 + (double)(t + 1u) / cp.k_a;
+        st.a_cur = st.a_relax;
+        if ((int64_t)t >= (int64_t)cp.burn) st.e_sum += ope;
+        st.sweep = t + 1u;
+        if ((int64_t)t + 1 >= (int64_t)cp.burn + cp.meas) st.phase = PH_DONE;
+    }
+    set_derived(st, cp.q);
+    states[c] = st;
+    if (st.phase == PH_DONE) atomicAdd(done_count, 1u);
+}
+
+// phi_sum at every site of image blockIdx.y: sum over its R chains of the
+// equilibrium sums (K > 1) or the final states (K == 1).
+__global__ void finalize_kernel(const ChainDesc *__restrict__ descs, const ImgDev *__restrict__ imgs, int R,
+                                int K, const uint8_t *__restrict__ sampled, float *__restrict__ phi_sum)
+{
+    const ImgDev im = imgs[blockIdx.y];
+    const int64_t n = (int64_t)im.nx * im.ny;
+    const ChainDesc *dc = descs + (int64_t)blockIdx.y * R;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        if (!sampled[im.offset + i] && K > 0) {
+            const int y = (int)(i / im.nx);
+            const int x = (int)(i - (int64_t)y * im.nx);
+            const int c = (x + y) & 1;
+            const int64_t j = (int64_t)y * dc[0].S + (x >> 1);
+            for (int r = 0; r < R; ++r) s += (K > 1) ? dc[r].acc[c][j] : angle_of(dc[r].h[c][j]);
+        }
+        phi_sum[im.offset + i] = s;
+    }
+}
+
+// Half-grids of one chain back to a full row-major grid of angles.
+__global__ void unsplit_kernel(const ChainDesc *__restrict__ descs, float *__restrict__ phi)
+{
+    const ChainDesc d = descs[0];
+    const int64_t n = (int64_t)d.nx * d.ny;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / d.nx);
+        const int x = (int)(i - (int64_t)y * d.nx);
+        phi[i] = angle_of(d.h[(x + y) & 1][(int64_t)y * d.S + (x >> 1)]);
+    }
+}
+
+// Energy of a full grid of angles as the sweep accumulates it.
+__global__ void grid_energy_kernel(const float *__restrict__ phi, int nx, int ny, float q,
+                                   unsigned long long *out)
+{
+    unsigned long long e = 0ull;
+    const int64_t n = (int64_t)nx * ny;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / nx);
+        const int x = (int)(i - (int64_t)y * nx);
+        if (((x + y) & 1) != 1) continue;
+        float nc[4] = {0.f, 0.f, 0.f, 0.f}, ns[4] = {0.f, 0.f, 0.f, 0.f};
+        uint32_t valid = 0u;
+        if (x > 0) { sincosf(q * phi[i - 1], &ns[0], &nc[0]); valid |= 1u; }
+        if (x + 1 < nx) { sincosf(q * phi[i + 1], &ns[1], &nc[1]); valid |= 2u; }
+        if (y > 0) { sincosf(q * phi[i - nx], &ns[2], &nc[2]); valid |= 4u; }
+        if (y + 1 < ny) { sincosf(q * phi[i + nx], &ns[3], &nc[3]); valid |= 8u; }
+        float ci, si;
+        sincosf(q * phi[i], &si, &ci);
+        e += site_energy_fx(ci, si, nc, ns, valid);
+    }
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    if ((threadIdx.x & 63) == 0 && e) atomicAdd(out, e);
+}
+
+// Per-block min / max / count of the sampled values of image blockIdx.y.
+__global__ void map_minmax_kernel(const ImgDev *__restrict__ imgs, const float *__restrict__ z,
+                                  const uint8_t *__restrict__ sampled, float *__restrict__ pmin,
+                                  float *__restrict__ pmax, unsigned long long *__restrict__ pcount,
+                                  unsigned int *__restrict__ pbad)
+{
+    const ImgDev im = imgs[blockIdx.y];
+    const int64_t n = (int64_t)im.nx * im.ny;
+    float lo = INFINITY, hi = -INFINITY;
+    unsigned long long cnt = 0ull;
+    unsigned int bad = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!sampled[im.offset + i]) continue;
+        const float v = z[im.offset + i];
+        if (!isfinite(v)) {
+            bad = 1u;
+            continue;
+        }
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+        ++cnt;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, off));
+        hi = fmaxf(hi, __shfl_xor(hi, off));
+        cnt += __shfl_xor(cnt, off);
+        bad |= __shfl_xor(bad, off);
+    }
+    __shared__ float slo[kBlock / 64], shi[kBlock / 64];
+    __shared__ unsigned long long scnt[kBlock / 64];
+    __shared__ unsigned int sbad[kBlock / 64];
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        slo[wid] = lo;
+        shi[wid] = hi;
+        scnt[wid] = cnt;
+        sbad[wid] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; ++i) {
+            slo[0] = fminf(slo[0], slo[i]);
+            shi[0] = fmaxf(shi[0], shi[i]);
+            scnt[0] += scnt[i];
+            sbad[0] |= sbad[i];
+        }
+        const int64_t k = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        pmin[k] = slo[0];
+        pmax[k] = shi[0];
+        pcount[k] = scnt[0];
+        pbad[k] = sbad[0];
+    }
+}
+
+__global__ void map_apply_kernel(const ImgDev *__restrict__ imgs, const double *__restrict__ zmm,
+                                 const float *__restrict__ z, const uint8_t *__restrict__ sampled,
+                                 float *__restrict__ phi)
+{
+#pragma clang fp contract(off)
+    const ImgDev im = imgs[blockIdx.y];
+    const double zmin = zmm[2 * blockIdx.y], zmax = zmm[2 * blockIdx.y + 1];
+    const int64_t n = (int64_t)im.nx * im.ny;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = im.offset + i;
+        phi[j] = sampled[j] ? (float)(kTwoPi * (((double)z[j] - zmin) / (zmax - zmin))) : 0.0f;
+    }
+}
+
+__global__ void predict_kernel(const ImgDev *__restrict__ imgs, const double *__restrict__ zmm, int M,
+                               const float *__restrict__ z, const uint8_t *__restrict__ sampled,
+                               const float *__restrict__ phi_sum, float *__restrict__ z_hat)
+{
+#pragma clang fp contract(off)
+    const ImgDev im = imgs[blockIdx.y];
+    const double zmin = zmm[2 * blockIdx.y], zmax = zmm[2 * blockIdx.y + 1];
+    const int64_t n = (int64_t)im.nx * im.ny;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = im.offset + i;
+        if (sampled[j]) {
+            z_hat[j] = z[j];
+        } else {
+            const double t = ((double)phi_sum[j] / (double)M) / kTwoPi;
+            z_hat[j] = (float)(zmin * (1.0 - t) + zmax * t);
+        }
+    }
+}
+
+// Per-block sums of -cos(q (phi_i - phi_j)) over sample-sample bonds.
+__global__ void sample_energy_kernel(const ImgDev *__restrict__ imgs, const float *__restrict__ phi,
+                                     const uint8_t *__restrict__ sampled, double q, double *__restrict__ psum,
+                                     unsigned long long *__restrict__ pcount)
+{
+    const ImgDev im = imgs[blockIdx.y];
+    const int64_t n = (int64_t)im.nx * im.ny;
+    double s = 0.0;
+    unsigned long long cnt = 0ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = im.offset + i;
+        if (!sampled[j]) continue;
+        const int y = (int)(i / im.nx);
+        const int x = (int)(i - (int64_t)y * im.nx);
+        const double a = (double)phi[j];
+        if (x + 1 < im.nx && sampled[j + 1]) {
+            s -= cos(q * (a - (double)phi[j + 1]));
+            ++cnt;
+        }
+        if (y + 1 < im.ny && sampled[j + im.nx]) {
+            s -= cos(q * (a - (double)phi[j + im.nx]));
+            ++cnt;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off);
+        cnt += __shfl_xor(cnt, off);
+    }
+    __shared__ double ss[kBlock / 64];
+    __shared__ unsigned long long sc[kBlock / 64];
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        ss[wid] = s;
+        sc[wid] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; ++i) {
+            ss[0] += ss[i];
+            sc[0] += sc[i];
+        }
+        const int64_t k = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        psum[k] = ss[0];
+        pcount[k] = sc[0];
+    }
+}
+
+__global__ void philox_kernel(const uint32_t *__restrict__ ctr, uint32_t k0, uint32_t k1, int64_t n,
+                              uint32_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    U4 c = {ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
+    const U4 w = philox4x32_10(c, k0, k1);
+    out[4 * i] = w.x;
+    out[4 * i + 1] = w.y;
+    out[4 * i + 2] = w.z;
+    out[4 * i + 3] = w.w;
+}
+
+__global__ void ring_slope_kernel(const double *e, int n, CtlParams cp, double *out)
+{
+    double ring[kMaxFit];
+    for (int j = 0; j < n; ++j) ring[j] = e[j];
+    // values e[0..n-1] sit in ring slots 0..n-1, i.e. the newest is at t = n-1
+    *out = ring_slope(ring, (uint32_t)(n - 1), n, cp.w);
+}
+
+// ====================================================================== host
+
+struct mpr_ctx {
+    int device = 0;
+    std::string err;
+    void *scratch = nullptr;          // small device scratch (partials, counters)
+    unsigned int *done_host = nullptr;  // pinned
+    // profiling
+    bool profile = false;
+    std::vector<hipEvent_t> events;
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0;
+    // e(T, L) tables: key -> (1 + e) per temperature
+    std::map<std::tuple<int, int, double, int, double, double, int, int, double, double, uint64_t>,
+             std::vector<double>>
+        tables;
+};
+
+namespace {
+
+int fail(mpr_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                              \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail((ctx), MPR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int half_stride(int nx) { return (int)round_up((nx + 1) / 2, 64); }
+
+int64_t half_grid_bytes(int nx, int ny) { return (int64_t)ny * half_stride(nx) * 4; }
+
+// Simple bump allocator over the caller's workspace.
+struct Carver {
+    char *base;
+    int64_t cap, used = 0;
+    void *take(int64_t bytes)
+    {
+        used = round_up(used, 256);
+        if (used + bytes > cap) return nullptr;
+        void *p = base + used;
+        used += bytes;
+        return p;
+    }
+};
+
+bool valid_params(const mpr_params *p)
+{
+    return p && p->q > 0.0 && p->q <= 0.5 && p->R >= 1 && p->K >= 0 && p->n_f >= 1 && p->n_fit >= 2 &&
+           p->n_fit <= kMaxFit && p->sg_degree >= 1 && p->sg_degree <= 4 && p->sg_degree < p->n_fit &&
+           p->k_a > 0.0 && p->a_targ >= 0.0 && p->table_nT >= 2 && p->table_meas >= 1 && p->table_burn >= 0 &&
+           p->table_T_lo > 0.0 && p->table_T_hi > p->table_T_lo;
+}
+
+bool valid_images(const mpr_image *imgs, int n)
+{
+    if (!imgs || n < 1) return false;
+    for (int b = 0; b < n; ++b) {
+        if (imgs[b].nx < 1 || imgs[b].ny < 1 || imgs[b].offset < 0) return false;
+        if ((int64_t)imgs[b].nx * imgs[b].ny > (int64_t)1 << 31) return false;
+        if (imgs[b].id >= 0x80000000u) return false;
+    }
+    return true;
+}
+
+int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
+{
+    int64_t b = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t hg = round_up(half_grid_bytes(imgs[i].nx, imgs[i].ny), 256);
+        b += (int64_t)p->R * 2 * hg * (p->K > 1 ? 2 : 1);
+    }
+    const int64_t chains = (int64_t)n * p->R;
+    b += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
+    b += round_up(chains * 8, 256) + round_up((int64_t)n * sizeof(ImgDev), 256) + 4096;
+    return b;
+}
+
+int64_t table_bytes(const mpr_image *imgs, int n, const mpr_params *p)
+{
+    int64_t best = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t hg = round_up(half_grid_bytes(imgs[i].nx, imgs[i].ny), 256);
+        best = std::max(best, (int64_t)p->table_nT * 2 * hg);
+    }
+    const int64_t chains = p->table_nT;
+    best += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
+    best += round_up(chains * 8, 256) + round_up((int64_t)n * sizeof(ImgDev), 256) + 4096;
+    best += round_up((int64_t)n * kMapBlocks * 16, 256);
+    return best;
+}
+
+// Derivative at the newest point of the degree-d least-squares polynomial
+// through n equally spaced points, as weights on the values (oldest first):
+// w = V (V^T V)^{-1} g with V_jk = s_j^k, s_j = j - (n-1)/2, g_k = k s_end^(k-1).
+void sg_weights(int n, int degree, double *w)
+{
+    const int m = degree + 1;
+    std::vector<double> A(m * m, 0.0), G(m, 0.0);
+    const double c = 0.5 * (n - 1);
+    for (int k = 0; k < m; ++k)
+        for (int l = 0; l < m; ++l) {
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += std::pow(j - c, k + l);
+            A[k * m + l] = s;
+        }
+    const double send = (n - 1) - c;
+    for (int k = 1; k < m; ++k) G[k] = k * std::pow(send, k - 1);
+    // solve A x = G (A symmetric positive definite) by Gaussian elimination
+    std::vector<double> M(A), x(G);
+    for (int col = 0; col < m; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < m; ++r)
+            if (std::fabs(M[r * m + col]) > std::fabs(M[piv * m + col])) piv = r;
+        if (piv != col) {
+            for (int l = 0; l < m; ++l) std::swap(M[col * m + l], M[piv * m + l]);
+            std::swap(x[col], x[piv]);
+        }
+        for (int r = col + 1; r < m; ++r) {
+            const double f = M[r * m + col] / M[col * m + col];
+            for (int l = col; l < m; ++l) M[r * m + l] -= f * M[col * m + l];
+            x[r] -= f * x[col];
+        }
+    }
+    for (int r = m - 1; r >= 0; --r) {
+        double s = x[r];
+        for (int l = r + 1; l < m; ++l) s -= M[r * m + l] * x[l];
+        x[r] = s / M[r * m + r];
+    }
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += std::pow(j - c, k) * x[k];
+        w[j] = s;
+    }
+}
+
+CtlParams make_ctl(const mpr_params *p)
+{
+    CtlParams cp;
+    std::memset(&cp, 0, sizeof cp);
+    cp.a_targ = p->a_targ;
+    cp.k_a = p->k_a;
+    cp.q = p->q;
+    cp.n_f = p->n_f;
+    cp.n_fit = p->n_fit;
+    cp.i_max = p->i_max;
+    cp.fixed_relax = p->fixed_relax;
+    cp.eq_a_mode = p->eq_a_mode;
+    cp.K = p->K;
+    cp.burn = p->table_burn;
+    cp.meas = p->table_meas;
+    sg_weights(p->n_fit, p->sg_degree, cp.w);
+    return cp;
+}
+
+SweepConsts make_sc(double q, uint64_t seed)
+{
+    SweepConsts sc;
+    sc.q = (float)q;
+    sc.two_pi_q = (float)(kTwoPi * q);
+    sc.q64 = q;
+    sc.seed_lo = (uint32_t)seed;
+    sc.seed_hi = (uint32_t)(seed >> 32);
+    return sc;
+}
+
+int blocks_for(int64_t n, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, cap)); }
+
+// A set of chains resident in the workspace.
+struct ChainSet {
+    std::vector<ChainDesc> desc;
+    std::vector<ChainState> state;
+    std::vector<int64_t> offset;  // image offset per chain (init)
+    ChainDesc *d_desc = nullptr;
+    ChainState *d_state = nullptr;
+    int64_t *d_offset = nullptr;
+    int max_half_total = 0;       // max over chains of ny * S / 2 (pairs)
+};
+
+// Runs sweeps until every chain is done.  Returns 0 or an error code.
+int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stream, int64_t max_sweeps,
+               int poll_every)
+{
+    const int n = (int)cs.desc.size();
+    unsigned int *d_done = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kDoneOffset);
+    HIP_TRY(ctx, hipMemsetAsync(d_done, 0, sizeof(unsigned int), stream));
+    unsigned int already = 0;
+    for (const auto &s : cs.state)
+        if (s.phase == PH_DONE) ++already;
+    if (already == (unsigned int)n) return MPR_OK;
+    const CtlParams cp = make_ctl(p);
+    const SweepConsts sc = make_sc(p->q, p->seed);
+    const dim3 grid((unsigned)((cs.max_half_total + kBlock - 1) / kBlock), (unsigned)n);
+    const int cblocks = (n + 63) / 64;
+    unsigned long long *d_work = reinterpret_cast<unsigned long long *>((char *)ctx->scratch + kWorkOffset);
+    if (ctx->profile) {
+        while ((int)ctx->events.size() < 2 * poll_every) {
+            hipEvent_t ev;
+            HIP_TRY(ctx, hipEventCreate(&ev));
+            ctx->events.push_back(ev);
+        }
+    }
+    for (int64_t done_sweeps = 0; done_sweeps < max_sweeps;) {
+        int j = 0;
+        for (; j < poll_every && done_sweeps < max_sweeps; ++j, ++done_sweeps) {
+            if (ctx->profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * j], stream));
+            hipLaunchKernelGGL(half_sweep_kernel<false>, grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state, 0, sc,
+                               0, nullptr);
+            hipLaunchKernelGGL(half_sweep_kernel<false>, grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state, 1, sc,
+                               0, nullptr);
+            if (ctx->profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * j + 1], stream));
+            hipLaunchKernelGGL(control_kernel, dim3(cblocks), dim3(64), 0, stream, cs.d_desc, cs.d_state, n, cp,
+                               d_done, d_work);
+        }
+        HIP_TRY(ctx, hipGetLastError());
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->done_host, d_done, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        if (ctx->profile) {
+            for (int k = 0; k < j; ++k) {
+                float ms = 0.0f;
+                HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
+                ctx->prof_ms += ms;
+                ctx->prof_launches += 2;
+            }
+        }
+        if (*ctx->done_host + already >= (unsigned int)n) return MPR_OK;
+    }
+    return fail(ctx, MPR_ERR_HIP, "chains did not finish within %lld sweeps", (long long)max_sweeps);
+}
+
+ChainState fresh_state(double T, int phase)
+{
+    ChainState s;
+    std::memset(&s, 0, sizeof s);
+    s.phase = phase;
+    s.sweep = 0;
+    s.T = T;
+    s.a_cur = 1.0;
+    s.a_relax = 1.0;
+    s.k = -1.0;
+    return s;
+}
+
+int upload_chains(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream, double q)
+{
+    const int n = (int)cs.desc.size();
+    cs.d_desc = (ChainDesc *)cv.take(n * (int64_t)sizeof(ChainDesc));
+    cs.d_state = (ChainState *)cv.take(n * (int64_t)sizeof(ChainState));
+    cs.d_offset = (int64_t *)cv.take(n * 8);
+    if (!cs.d_desc || !cs.d_state || !cs.d_offset) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+    for (auto &s : cs.state) {
+        s.inv_T = (float)(1.0 / s.T);
+        s.dscale = (float)(kTwoPi * q / s.a_cur);
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(cs.d_desc, cs.desc.data(), n * sizeof(ChainDesc), hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipMemcpyAsync(cs.d_state, cs.state.data(), n * sizeof(ChainState), hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipMemcpyAsync(cs.d_offset, cs.offset.data(), n * 8, hipMemcpyHostToDevice, stream));
+    return MPR_OK;
+}
+
+// Allocates both half-grids (and accumulators) of a chain from the workspace.
+bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc)
+{
+    const int64_t hg = half_grid_bytes(nx, ny);
+    d.nx = nx;
+    d.ny = ny;
+    d.S = half_stride(nx);
+    for (int c = 0; c < 2; ++c) {
+        d.h[c] = (float *)cv.take(hg);
+        d.acc[c] = with_acc ? (float *)cv.take(hg) : nullptr;
+        if (!d.h[c] || (with_acc && !d.acc[c])) return false;
+    }
+    return true;
+}
+
+// Monotone (pool-adjacent-violators) fit of y, then log T interpolated
+// linearly in y; y = log(1 + e).
+double invert_table(const std::vector<double> &Tg, const std::vector<double> &ope, double e_s, int *clamped)
+{
+    const int n = (int)Tg.size();
+    std::vector<double> val, wt;
+    std::vector<int> len;
+    for (int k = 0; k < n; ++k) {
+        val.push_back(std::log(std::max(ope[k], 1e-300)));
+        wt.push_back(1.0);
+        len.push_back(1);
+        while (val.size() > 1 && val[val.size() - 2] > val.back()) {
+            const double w2 = wt[wt.size() - 2] + wt.back();
+            const double v2 = (wt[wt.size() - 2] * val[val.size() - 2] + wt.back() * val.back()) / w2;
+            const int l2 = len[len.size() - 2] + len.back();
+            val.pop_back();
+            wt.pop_back();
+            len.pop_back();
+            val.back() = v2;
+            wt.back() = w2;
+            len.back() = l2;
+        }
+    }
+    std::vector<double> y;
+    for (size_t b = 0; b < val.size(); ++b)
+        for (int j = 0; j < len[b]; ++j) y.push_back(val[b]);
+    const double ys = std::log(std::max(1.0 + e_s, 1e-300));
+    *clamped = 0;
+    if (ys <= y[0]) {
+        *clamped = 1;
+        return Tg[0];
+    }
+    if (ys >= y[n - 1]) {
+        *clamped = 1;
+        return Tg[n - 1];
+    }
+    int k = 0;
+    while (!(y[k + 1] >= ys && y[k + 1] > y[k])) ++k;
+    const double x0 = std::log(Tg[k]), x1 = std::log(Tg[k + 1]);
+    return std::exp(x0 + (ys - y[k]) * (x1 - x0) / (y[k + 1] - y[k]));
+}
+
+std::vector<double> temperature_grid(const mpr_params *p)
+{
+    std::vector<double> Tg(p->table_nT);
+    for (int k = 0; k < p->table_nT; ++k)
+        Tg[k] = std::exp(std::log(p->table_T_lo) +
+                         (std::log(p->table_T_hi) - std::log(p->table_T_lo)) * (double)k / (double)(p->table_nT - 1));
+    return Tg;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+int32_t mpr_create(mpr_ctx **out, int32_t device)
+{
+    if (!out) return MPR_ERR_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return MPR_ERR_HIP;
+    if (hipSetDevice(device) != hipSuccess) return MPR_ERR_HIP;
+    mpr_ctx *ctx = new mpr_ctx();
+    ctx->device = device;
+    if (hipMalloc(&ctx->scratch, kScratchBytes) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->done_host, sizeof(unsigned int), hipHostMallocDefault) != hipSuccess) {
+        if (ctx->scratch) (void)hipFree(ctx->scratch);
+        delete ctx;
+        return MPR_ERR_HIP;
+    }
+    *out = ctx;
+    return MPR_OK;
+}
+
+void mpr_destroy(mpr_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->done_host) (void)hipHostFree(ctx->done_host);
+    delete ctx;
+}
+
+const char *mpr_last_error(const mpr_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void mpr_default_params(mpr_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->q = 0.5;
+    p->R = 1;
+    p->K = 100;
+    p->n_f = 5;
+    p->n_fit = 20;
+    p->sg_degree = 1;
+    p->i_max = 20000;
+    p->a_targ = 0.3;
+    p->k_a = 3.0;
+    p->fixed_relax = -1;
+    p->eq_a_mode = 0;
+    p->table_nT = 32;
+    p->table_burn = 200;
+    p->table_meas = 400;
+    p->table_T_lo = 1e-5;
+    p->table_T_hi = 10.0;
+    p->seed = 3000;
+}
+
+int64_t mpr_workspace_size(const mpr_image *imgs, int32_t n, const mpr_params *p)
+{
+    if (!valid_images(imgs, n) || !valid_params(p)) return -1;
+    return std::max(sim_bytes(imgs, n, p), table_bytes(imgs, n, p));
+}
+
+int32_t mpr_map_to_angles(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *z, const uint8_t *sampled,
+                          float *phi, double *zmin_zmax, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!valid_images(imgs, n) || !z || !sampled || !phi || !zmin_zmax)
+        return fail(ctx, MPR_ERR_ARG, "map_to_angles: invalid argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    const int chunk = (int)((kScratchBytes - kVarOffset - 4096) / (kMapBlocks * 24 + 64));
+    for (int b0 = 0; b0 < n; b0 += chunk) {
+        const int nb = std::min(chunk, n - b0);
+        char *sp = (char *)ctx->scratch + kVarOffset;
+        ImgDev *d_img = (ImgDev *)sp;
+        float *pmin = (float *)(sp + round_up((int64_t)nb * sizeof(ImgDev), 256));
+        float *pmax = pmin + (int64_t)nb * kMapBlocks;
+        unsigned long long *pcnt = (unsigned long long *)(pmax + (int64_t)nb * kMapBlocks);
+        unsigned int *pbad = (unsigned int *)(pcnt + (int64_t)nb * kMapBlocks);
+        double *d_zmm = (double *)(pbad + (int64_t)nb * kMapBlocks + 64);
+        d_zmm = (double *)round_up((int64_t)d_zmm, 256);
+        std::vector<ImgDev> hi(nb);
+        for (int b = 0; b < nb; ++b) hi[b] = {imgs[b0 + b].offset, imgs[b0 + b].nx, imgs[b0 + b].ny};
+        HIP_TRY(ctx, hipMemcpyAsync(d_img, hi.data(), nb * sizeof(ImgDev), hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(map_minmax_kernel, dim3(kMapBlocks, nb), dim3(kBlock), 0, stream, d_img, z, sampled, pmin,
+                           pmax, pcnt, pbad);
+        HIP_TRY(ctx, hipGetLastError());
+        std::vector<float> hmin(nb * kMapBlocks), hmax(nb * kMapBlocks);
+        std::vector<unsigned long long> hcnt(nb * kMapBlocks);
+        std::vector<unsigned int> hbad(nb * kMapBlocks);
+        HIP_TRY(ctx, hipMemcpyAsync(hmin.data(), pmin, hmin.size() * 4, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipMemcpyAsync(hmax.data(), pmax, hmax.size() * 4, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipMemcpyAsync(hcnt.data(), pcnt, hcnt.size() * 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipMemcpyAsync(hbad.data(), pbad, hbad.size() * 4, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        std::vector<double> zmm(2 * nb);
+        for (int b = 0; b < nb; ++b) {
+            float lo = INFINITY, hi2 = -INFINITY;
+            unsigned long long cnt = 0;
+            unsigned int bad = 0;
+            for (int k = 0; k < kMapBlocks; ++k) {
+                lo = std::min(lo, hmin[b * kMapBlocks + k]);
+                hi2 = std::max(hi2, hmax[b * kMapBlocks + k]);
+                cnt += hcnt[b * kMapBlocks + k];
+                bad |= hbad[b * kMapBlocks + k];
+            }
+            if (bad) return fail(ctx, MPR_ERR_ARG, "image %d: non-finite sampled value", b0 + b);
+            if (cnt < 2 || !(hi2 > lo))
+                return fail(ctx, MPR_ERR_DEGENERATE, "image %d: fewer than 2 samples or z_max == z_min", b0 + b);
+            zmm[2 * b] = lo;
+            zmm[2 * b + 1] = hi2;
+            zmin_zmax[2 * (b0 + b)] = lo;
+            zmin_zmax[2 * (b0 + b) + 1] = hi2;
+        }
+        HIP_TRY(ctx, hipMemcpyAsync(d_zmm, zmm.data(), zmm.size() * 8, hipMemcpyHostToDevice, stream));
+        int64_t maxn = 0;
+        for (int b = 0; b < nb; ++b) maxn = std::max(maxn, (int64_t)hi[b].nx * hi[b].ny);
+        hipLaunchKernelGGL(map_apply_kernel, dim3(blocks_for(maxn, 4096), nb), dim3(kBlock), 0, stream, d_img, d_zmm,
+                           z, sampled, phi);
+        HIP_TRY(ctx, hipGetLastError());
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+    }
+    return MPR_OK;
+}
+
+int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *phi,
+                                 const uint8_t *sampled, const mpr_params *p, void *ws, int64_t ws_bytes,
+                                 double *e_s, double *T_hat, int32_t *t_clamped, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!valid_images(imgs, n) || !valid_params(p) || !phi || !sampled || !e_s || !T_hat)
+        return fail(ctx, MPR_ERR_ARG, "estimate_temperature: invalid argument");
+    if (!ws || ws_bytes < table_bytes(imgs, n, p)) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    // e_s per image (equation mpr-sse)
+    {
+        Carver cv{(char *)ws, ws_bytes};
+        ImgDev *d_img = (ImgDev *)cv.take(n * (int64_t)sizeof(ImgDev));
+        double *psum = (double *)cv.take((int64_t)n * kMapBlocks * 8);
+        unsigned long long *pcnt = (unsigned long long *)cv.take((int64_t)n * kMapBlocks * 8);
+        if (!d_img || !psum || !pcnt) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+        std::vector<ImgDev> hi(n);
+        for (int b = 0; b < n; ++b) hi[b] = {imgs[b].offset, imgs[b].nx, imgs[b].ny};
+        HIP_TRY(ctx, hipMemcpyAsync(d_img, hi.data(), n * sizeof(ImgDev), hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(sample_energy_kernel, dim3(kMapBlocks, n), dim3(kBlock), 0, stream, d_img, phi, sampled,
+                           p->q, psum, pcnt);
+        HIP_TRY(ctx, hipGetLastError());
+        std::vector<double> hs((size_t)n * kMapBlocks);
+        std::vector<unsigned long long> hc((size_t)n * kMapBlocks);
+        HIP_TRY(ctx, hipMemcpyAsync(hs.data(), psum, hs.size() * 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipMemcpyAsync(hc.data(), pcnt, hc.size() * 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        for (int b = 0; b < n; ++b) {
+            double s = 0.0;
+            unsigned long long c = 0;
+            for (int k = 0; k < kMapBlocks; ++k) {
+                s += hs[(size_t)b * kMapBlocks + k];
+                c += hc[(size_t)b * kMapBlocks + k];
+            }
+            if (c == 0) return fail(ctx, MPR_ERR_DEGENERATE, "image %d: no sample-sample pair", b);
+            e_s[b] = s / (double)c;
+        }
+    }
+    // e(T, L) tables per grid size (equation ene), cached
+    const std::vector<double> Tg = temperature_grid(p);
+    for (int b = 0; b < n; ++b) {
+        const auto key = std::make_tuple(imgs[b].nx, imgs[b].ny, p->q, p->table_nT, p->table_T_lo, p->table_T_hi,
+                                         p->table_burn, p->table_meas, p->a_targ, p->k_a, p->seed);
+        auto it = ctx->tables.find(key);
+        if (it == ctx->tables.end()) {
+            if ((int64_t)imgs[b].nx * imgs[b].ny < 2) return fail(ctx, MPR_ERR_DEGENERATE, "image %d: one site", b);
+            Carver cv{(char *)ws, ws_bytes};
+            ChainSet cs;
+            for (int k = 0; k < p->table_nT; ++k) {
+                ChainDesc d;
+                std::memset(&d, 0, sizeof d);
+                if (!carve_chain(cv, d, imgs[b].nx, imgs[b].ny, false))
+                    return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+                d.image_id = kTableStream;
+                d.chain = (uint32_t)k;
+                d.P = (int64_t)imgs[b].nx * imgs[b].ny;
+                d.ngp = (int64_t)imgs[b].nx * (imgs[b].ny - 1) + (int64_t)imgs[b].ny * (imgs[b].nx - 1);
+                cs.desc.push_back(d);
+                cs.state.push_back(fresh_state(Tg[k], PH_TABLE));
+                cs.offset.push_back(0);
+                cs.max_half_total = std::max<int64_t>(cs.max_half_total, (int64_t)d.ny * d.S / 2);
+            }
+            int rc = upload_chains(ctx, cs, cv, stream, p->q);
+            if (rc) return rc;
+            const int64_t maxn = (int64_t)imgs[b].nx * imgs[b].ny;
+            hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), p->table_nT), dim3(kBlock), 0, stream,
+                               cs.d_desc, cs.d_offset, nullptr, nullptr, nullptr, 0u, 0u, 1);
+            HIP_TRY(ctx, hipGetLastError());
+            rc = run_chains(ctx, cs, p, stream, (int64_t)p->table_burn + p->table_meas, p->table_burn + p->table_meas);
+            if (rc) return rc;
+            HIP_TRY(ctx, hipMemcpyAsync(cs.state.data(), cs.d_state, cs.state.size() * sizeof(ChainState),
+                                        hipMemcpyDeviceToHost, stream));
+            HIP_TRY(ctx, hipStreamSynchronize(stream));
+            std::vector<double> ope(p->table_nT);
+            for (int k = 0; k < p->table_nT; ++k) ope[k] = cs.state[k].e_sum / (double)p->table_meas;
+            it = ctx->tables.emplace(key, ope).first;
+        }
+        int cl = 0;
+        T_hat[b] = invert_table(Tg, it->second, e_s[b], &cl);
+        if (t_clamped) t_clamped[b] = cl;
+    }
+    return MPR_OK;
+}
+
+int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *phi, const uint8_t *sampled,
+                     const double *T_hat, const mpr_params *p, const float *phi_init, void *ws, int64_t ws_bytes,
+                     float *phi_sum, mpr_chain_stats *stats, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!valid_images(imgs, n) || !valid_params(p) || !phi || !sampled || !T_hat || !phi_sum)
+        return fail(ctx, MPR_ERR_ARG, "simulate: invalid argument");
+    for (int b = 0; b < n; ++b)
+        if (!(T_hat[b] > 0.0) || !std::isfinite(T_hat[b])) return fail(ctx, MPR_ERR_ARG, "image %d: bad T_hat", b);
+    if (!ws || ws_bytes < sim_bytes(imgs, n, p)) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    // gap counts (host needs them for the acceptance ratio): from the mask
+    // via a device reduction would need scratch; count with the e_s-style
+    // partials instead, reusing the map kernel's layout.
+    Carver cv{(char *)ws, ws_bytes};
+    ImgDev *d_img = (ImgDev *)cv.take(n * (int64_t)sizeof(ImgDev));
+    std::vector<ImgDev> hi(n);
+    for (int b = 0; b < n; ++b) hi[b] = {imgs[b].offset, imgs[b].nx, imgs[b].ny};
+    HIP_TRY(ctx, hipMemcpyAsync(d_img, hi.data(), n * sizeof(ImgDev), hipMemcpyHostToDevice, stream));
+    std::vector<int64_t> gaps(n, 0);
+    {
+        // count gaps with the map reduction on a constant z
+        char *sp = (char *)ctx->scratch + kVarOffset;
+        float *pmin = (float *)sp;
+        float *pmax = pmin + (int64_t)n * kMapBlocks;
+        unsigned long long *pcnt = (unsigned long long *)(pmax + (int64_t)n * kMapBlocks);
+        unsigned int *pbad = (unsigned int *)(pcnt + (int64_t)n * kMapBlocks);
+        if ((int64_t)n * kMapBlocks * 24 + 512 > (int64_t)kScratchBytes - kVarOffset)
+            return fail(ctx, MPR_ERR_ARG, "too many images in one call");
+        // map_minmax counts sampled sites of finite value; phi is finite
+        hipLaunchKernelGGL(map_minmax_kernel, dim3(kMapBlocks, n), dim3(kBlock), 0, stream, d_img, phi, sampled, pmin,
+                           pmax, pcnt, pbad);
+        HIP_TRY(ctx, hipGetLastError());
+        std::vector<unsigned long long> hc((size_t)n * kMapBlocks);
+        HIP_TRY(ctx, hipMemcpyAsync(hc.data(), pcnt, hc.size() * 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        for (int b = 0; b < n; ++b) {
+            unsigned long long c = 0;
+            for (int k = 0; k < kMapBlocks; ++k) c += hc[(size_t)b * kMapBlocks + k];
+            gaps[b] = (int64_t)imgs[b].nx * imgs[b].ny - (int64_t)c;
+        }
+    }
+    ChainSet cs;
+    for (int b = 0; b < n; ++b) {
+        const int nx = imgs[b].nx, ny = imgs[b].ny;
+        if ((int64_t)nx * ny < 2) return fail(ctx, MPR_ERR_DEGENERATE, "image %d: one site", b);
+        for (int r = 0; r < p->R; ++r) {
+            ChainDesc d;
+            std::memset(&d, 0, sizeof d);
+            if (!carve_chain(cv, d, nx, ny, p->K > 1)) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+            d.image_id = imgs[b].id;
+            d.chain = (uint32_t)r;
+            d.P = gaps[b];
+            d.ngp = (int64_t)nx * (ny - 1) + (int64_t)ny * (nx - 1);
+            cs.desc.push_back(d);
+            int phase = PH_RELAX;
+            if (d.P == 0) phase = PH_DONE;
+            else if (p->fixed_relax == 0) phase = p->K > 0 ? PH_EQ : PH_DONE;
+            ChainState st = fresh_state(T_hat[b], phase);
+            st.eq_left = p->K;
+            if (phase == PH_EQ && !p->eq_a_mode) st.a_cur = 1.0;
+            cs.state.push_back(st);
+            cs.offset.push_back(imgs[b].offset);
+            cs.max_half_total = std::max<int64_t>(cs.max_half_total, (int64_t)ny * d.S / 2);
+        }
+    }
+    int rc = upload_chains(ctx, cs, cv, stream, p->q);
+    if (rc) return rc;
+    int64_t maxn = 0;
+    for (int b = 0; b < n; ++b) maxn = std::max(maxn, (int64_t)imgs[b].nx * imgs[b].ny);
+    for (auto &d : cs.desc) {
+        HIP_TRY(ctx, hipMemsetAsync(d.h[0], 0, half_grid_bytes(d.nx, d.ny), stream));
+        HIP_TRY(ctx, hipMemsetAsync(d.h[1], 0, half_grid_bytes(d.nx, d.ny), stream));
+    }
+    hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), (unsigned)cs.desc.size()), dim3(kBlock), 0,
+                       stream, cs.d_desc, cs.d_offset, phi, sampled, phi_init, (uint32_t)p->seed,
+                       (uint32_t)(p->seed >> 32), 0);
+    HIP_TRY(ctx, hipGetLastError());
+    const int64_t relax_cap = p->fixed_relax >= 0 ? p->fixed_relax : (int64_t)p->i_max + 1;
+    rc = run_chains(ctx, cs, p, stream, relax_cap + p->K + 1, p->n_f);
+    if (rc) return rc;
+    hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, cs.d_desc, d_img,
+                       p->R, p->K, sampled, phi_sum);
+    HIP_TRY(ctx, hipGetLastError());
+    if (stats) {
+        HIP_TRY(ctx, hipMemcpyAsync(cs.state.data(), cs.d_state, cs.state.size() * sizeof(ChainState),
+                                    hipMemcpyDeviceToHost, stream));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    if (stats) {
+        for (size_t c = 0; c < cs.state.size(); ++c) {
+            const ChainState &s = cs.state[c];
+            stats[c].relax_sweeps = s.relax_sweeps;
+            stats[c].not_converged = s.not_converged;
+            stats[c].a_final = s.a_relax;
+            stats[c].A_last = s.A_last;
+            stats[c].k_last = s.k;
+        }
+    }
+    return MPR_OK;
+}
+
+int32_t mpr_predict(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *z, const uint8_t *sampled,
+                    const float *phi_sum, const double *zmin_zmax, int32_t M, float *z_hat, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!valid_images(imgs, n) || !z || !sampled || !phi_sum || !zmin_zmax || !z_hat || M < 1)
+        return fail(ctx, MPR_ERR_ARG, "predict: invalid argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    const int64_t need = round_up((int64_t)n * sizeof(ImgDev), 256) + (int64_t)n * 16;
+    if (need > (int64_t)kScratchBytes - kVarOffset) return fail(ctx, MPR_ERR_ARG, "too many images in one call");
+    char *sp = (char *)ctx->scratch + kVarOffset;
+    ImgDev *d_img = (ImgDev *)sp;
+    double *d_zmm = (double *)(sp + round_up((int64_t)n * sizeof(ImgDev), 256));
+    std::vector<ImgDev> hi(n);
+    int64_t maxn = 0;
+    for (int b = 0; b < n; ++b) {
+        hi[b] = {imgs[b].offset, imgs[b].nx, imgs[b].ny};
+        maxn = std::max(maxn, (int64_t)imgs[b].nx * imgs[b].ny);
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(d_img, hi.data(), n * sizeof(ImgDev), hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_zmm, zmin_zmax, n * 16, hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(predict_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, d_img, d_zmm, M, z,
+                       sampled, phi_sum, z_hat);
+    HIP_TRY(ctx, hipGetLastError());
+    // the host arrays above must outlive the copies
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    return MPR_OK;
+}
+
+int32_t mpr_profile_enable(mpr_ctx *ctx, int32_t on)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    ctx->profile = on != 0;
+    ctx->prof_ms = 0.0;
+    ctx->prof_launches = 0;
+    HIP_TRY(ctx, hipMemset((char *)ctx->scratch + kWorkOffset, 0, 3 * sizeof(unsigned long long)));
+    return MPR_OK;
+}
+
+int32_t mpr_profile_read(mpr_ctx *ctx, mpr_profile *out)
+{
+    if (!ctx || !out) return MPR_ERR_ARG;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    unsigned long long w[3] = {0, 0, 0};
+    HIP_TRY(ctx, hipMemcpy(w, (char *)ctx->scratch + kWorkOffset, sizeof w, hipMemcpyDeviceToHost));
+    out->sweep_kernel_ms = ctx->prof_ms;
+    out->sweep_launches = ctx->prof_launches;
+    out->chain_sweeps = (int64_t)w[0];
+    out->site_updates = (int64_t)w[1];
+    out->useful_bytes = (double)w[2];
+    return MPR_OK;
+}
+
+// ------------------------------------------------------------ diagnostics
+
+int32_t mpr_diag_philox(mpr_ctx *ctx, const uint32_t *ctr, uint64_t seed, int64_t n, uint32_t *out, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!ctr || !out || n < 0) return fail(ctx, MPR_ERR_ARG, "diag_philox: invalid argument");
+    if (n == 0) return MPR_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    hipLaunchKernelGGL(philox_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, ctr,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), n, out);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    return MPR_OK;
+}
+
+int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, const uint8_t *sampled, int32_t colour,
+                            double T, double a, double q, uint64_t seed, uint32_t sweep, uint32_t chain,
+                            uint32_t stream_id, int32_t mode, uint8_t *flags, int64_t *accepted, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (nx < 1 || ny < 1 || (int64_t)nx * ny < 2 || !phi || !sampled || (colour != 0 && colour != 1) || !(T > 0) ||
+        !(a > 0) || !(q > 0 && q <= 0.5) || (mode != 0 && mode != 1))
+        return fail(ctx, MPR_ERR_ARG, "diag_half_sweep: invalid argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    const int64_t hg = half_grid_bytes(nx, ny);
+    const int64_t bytes = 2 * round_up(hg, 256) + 4096;
+    void *buf = nullptr;
+    HIP_TRY(ctx, hipMalloc(&buf, bytes));
+    Carver cv{(char *)buf, bytes};
+    ChainSet cs;
+    ChainDesc d;
+    std::memset(&d, 0, sizeof d);
+    carve_chain(cv, d, nx, ny, false);
+    d.image_id = stream_id;
+    d.chain = chain;
+    d.P = 1;
+    d.ngp = (int64_t)nx * (ny - 1) + (int64_t)ny * (nx - 1);
+    cs.desc.push_back(d);
+    ChainState st = fresh_state(T, PH_RELAX);
+    st.sweep = sweep;
+    st.a_cur = a;
+    cs.state.push_back(st);
+    cs.offset.push_back(0);
+    int rc = upload_chains(ctx, cs, cv, stream, q);
+    if (rc) {
+        (void)hipFree(buf);
+        return rc;
+    }
+    (void)hipMemsetAsync(d.h[0], 0, hg, stream);
+    (void)hipMemsetAsync(d.h[1], 0, hg, stream);
+    const int64_t nsite = (int64_t)nx * ny;
+    // the gap values of phi are the starting state
+    hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(nsite, 2048), 1), dim3(kBlock), 0, stream, cs.d_desc,
+                       cs.d_offset, phi, sampled, phi, 0u, 0u, 0);
+    if (flags) (void)hipMemsetAsync(flags, 0, nsite, stream);
+    const SweepConsts sc = make_sc(q, seed);
+    const int64_t pairs = (int64_t)ny * d.S / 2;
+    hipLaunchKernelGGL(half_sweep_kernel<true>, dim3((unsigned)((pairs + kBlock - 1) / kBlock), 1), dim3(kBlock), 0,
+                       stream, cs.d_desc, cs.d_state, colour, sc, mode, flags);
+    hipLaunchKernelGGL(unsplit_kernel, dim3(blocks_for(nsite, 2048)), dim3(kBlock), 0, stream, cs.d_desc, phi);
+    ChainState out;
+    (void)hipMemcpyAsync(&out, cs.d_state, sizeof out, hipMemcpyDeviceToHost, stream);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(stream);
+    (void)hipFree(buf);
+    if (e1 != hipSuccess || e2 != hipSuccess)
+        return fail(ctx, MPR_ERR_HIP, "diag_half_sweep: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    if (accepted) *accepted = (int64_t)out.acc;
+    return MPR_OK;
+}
+
+int32_t mpr_diag_energy(mpr_ctx *ctx, int32_t nx, int32_t ny, const float *phi, double q, double *h_plus_ngp,
+                        void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (nx < 1 || ny < 1 || !phi || !h_plus_ngp || !(q > 0 && q <= 0.5))
+        return fail(ctx, MPR_ERR_ARG, "diag_energy: invalid argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    unsigned long long *d_e = (unsigned long long *)((char *)ctx->scratch + kEnergyOffset);
+    HIP_TRY(ctx, hipMemsetAsync(d_e, 0, 8, stream));
+    hipLaunchKernelGGL(grid_energy_kernel, dim3(blocks_for((int64_t)nx * ny, 2048)), dim3(kBlock), 0, stream, phi, nx,
+                       ny, (float)q, d_e);
+    HIP_TRY(ctx, hipGetLastError());
+    unsigned long long e = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&e, d_e, 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    *h_plus_ngp = (double)e * (1.0 / 4294967296.0);
+    return MPR_OK;
+}
+
+int32_t mpr_diag_sg_slope(mpr_ctx *ctx, const double *e, int32_t n, int32_t degree, double *slope)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!e || !slope || n < 2 || n > kMaxFit || degree < 1 || degree >= n)
+        return fail(ctx, MPR_ERR_ARG, "diag_sg_slope: invalid argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    mpr_params p;
+    mpr_default_params(&p);
+    p.n_fit = n;
+    p.sg_degree = degree;
+    const CtlParams cp = make_ctl(&p);
+    double *d = (double *)((char *)ctx->scratch + kSlopeOffset);
+    HIP_TRY(ctx, hipMemcpy(d, e, n * 8, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(ring_slope_kernel, dim3(1), dim3(1), 0, 0, d, n, cp, d + kMaxFit);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpy(slope, d + kMaxFit, 8, hipMemcpyDeviceToHost));
+    return MPR_OK;
+}
+
+}  // extern "C"

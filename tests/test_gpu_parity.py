@@ -1,0 +1,357 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Inputs are seeded and synthetic; the oracle always starts from the same
+float32 values the GPU holds (teacher forcing), so per-site comparisons are
+meaningful.  Bars (from the method's precision targets): over-relaxation-only
+angles within 1e-5 rad; fewer than 1e-6 of Metropolis decisions flipped;
+per-sweep specific energy within 1e-6; identical stopping slopes on identical
+energy series; integer and byte outputs bit-exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_1811_01604_amd as mpr  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TWO_PI = 2.0 * math.pi
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = mpr.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def colour_mask(ny, nx, colour):
+    return (np.add.outer(np.arange(ny), np.arange(nx)) % 2) == colour
+
+
+# ------------------------------------------------------------------ Philox
+def test_philox_bit_exact(ctx):
+    say("philox: 100000 counters")
+    rng = np.random.default_rng(11)
+    ctr = rng.integers(0, 2**32, size=(100000, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = 0
+    ctr[1] = 0xFFFFFFFF
+    seed = 0xDEADBEEF12345678
+    out = torch.zeros((100000, 4), dtype=torch.int32, device="cuda")
+    ctx.diag_philox(dev(ctr.view(np.int32), torch.int32), seed, out)
+    got = out.cpu().numpy().view(np.uint32)
+    for i in list(range(300)) + list(range(99700, 100000)):
+        want = oracle.philox4x32_10(ctr[i], [seed & 0xFFFFFFFF, seed >> 32])
+        assert np.array_equal(got[i], want), i
+
+
+# ---------------------------------------------------------------- data map
+@pytest.mark.parametrize("shape", [(64, 64), (37, 129), (1, 2), (300, 1)])
+def test_map_bit_exact(ctx, shape):
+    ny, nx = shape
+    say("map", shape)
+    rng = np.random.default_rng(ny * 1000 + nx)
+    z = rng.normal(50, 10, size=shape).astype(np.float32)
+    m = (rng.random(shape) < 0.6).astype(np.uint8)
+    m.flat[:2] = 1
+    phi = torch.zeros(shape, device="cuda")
+    zz = ctx.map_to_angles(mpr.images([shape]), dev(z), dev(m, torch.uint8), phi)
+    po, zo = oracle.map_to_angles(z.astype(np.float64), m)
+    assert np.array_equal(zz, zo)
+    assert np.array_equal(phi.cpu().numpy().view(np.uint32), po.astype(np.float32).view(np.uint32))
+
+
+def test_map_batch_and_errors(ctx):
+    shapes = [(16, 20), (9, 7), (33, 3)]
+    rng = np.random.default_rng(5)
+    zs = [rng.normal(size=s).astype(np.float32) * (b + 1) for b, s in enumerate(shapes)]
+    ms = [(rng.random(s) < 0.5).astype(np.uint8) for s in shapes]
+    for m in ms:
+        m.flat[:2] = 1
+    z = np.concatenate([a.ravel() for a in zs])
+    m = np.concatenate([a.ravel() for a in ms])
+    phi = torch.zeros(z.size, device="cuda")
+    zz = ctx.map_to_angles(mpr.images(shapes), dev(z), dev(m, torch.uint8), phi)
+    off = 0
+    for b, s in enumerate(shapes):
+        po, zo = oracle.map_to_angles(zs[b].astype(np.float64), ms[b])
+        n = s[0] * s[1]
+        assert np.array_equal(zz[2 * b:2 * b + 2], zo)
+        assert np.array_equal(phi[off:off + n].cpu().numpy(), po.astype(np.float32).ravel())
+        off += n
+    with pytest.raises(mpr.MprError) as e:
+        ctx.map_to_angles(mpr.images([(4, 4)]), dev(np.full(16, 3.0, np.float32)),
+                          dev(np.ones(16, np.uint8), torch.uint8), torch.zeros(16, device="cuda"))
+    assert e.value.code == mpr.MPR_ERR_DEGENERATE
+    bad = np.arange(16, dtype=np.float32)
+    bad[3] = np.inf
+    with pytest.raises(mpr.MprError) as e:
+        ctx.map_to_angles(mpr.images([(4, 4)]), dev(bad), dev(np.ones(16, np.uint8), torch.uint8),
+                          torch.zeros(16, device="cuda"))
+    assert e.value.code == mpr.MPR_ERR_ARG
+
+
+# ---------------------------------------------------- teacher-forced sweeps
+def smooth_state(ny, nx, nu, kappa, p_removed, noise, seed):
+    """Sample angles of a smooth field with the gaps near their true values."""
+    z = synth.matern_field(nx, ny, nu, kappa, 50.0, 10.0, seed).astype(np.float32)
+    m = synth.random_mask(nx, ny, p_removed, seed + 1)
+    phi = TWO_PI * (z.astype(np.float64) - z.min()) / (z.max() - z.min())
+    rng = np.random.default_rng(seed + 2)
+    g = m == 0
+    phi[g] = np.mod(phi[g] + rng.normal(0, noise, size=g.sum()), TWO_PI)
+    return phi.astype(np.float32), m
+
+
+def run_pair(ctx, phi32, m, colour, T, a, sweep, mode=0, chain=0, stream_id=0, seed=3000):
+    """One half-sweep on the GPU and in the oracle from the same float32 state."""
+    ny, nx = phi32.shape
+    g = dev(phi32)
+    fl = torch.zeros((ny, nx), dtype=torch.uint8, device="cuda")
+    acc_g = ctx.diag_half_sweep(g, dev(m, torch.uint8), colour, T, a, sweep, chain=chain, stream_id=stream_id,
+                                seed=seed, mode=mode, flags=fl)
+    po, acc_o, fo = oracle.half_sweep(phi32.astype(np.float64), m, colour, T, a, sweep, chain=chain,
+                                      stream=stream_id, seed=seed, mode=mode, with_flags=True)
+    return g.cpu().numpy(), acc_g, fl.cpu().numpy(), po, acc_o, fo
+
+
+@pytest.mark.parametrize("kind", ["uniform", "smooth"])
+@pytest.mark.parametrize("shape", [(64, 64), (97, 131), (1, 40), (40, 1)])
+def test_over_relaxation_only_teacher_forced(ctx, kind, shape):
+    ny, nx = shape
+    say("OR-only", kind, shape)
+    rng = np.random.default_rng(ny + 7 * nx)
+    if kind == "uniform":
+        phi = rng.uniform(0, TWO_PI, size=shape).astype(np.float32)
+        m = (rng.random(shape) < 0.3).astype(np.uint8)
+    else:
+        phi, m = smooth_state(max(ny, 2), max(nx, 2), 2.5, 0.05, 0.5, 0.01, 21)
+        phi, m = phi[:ny, :nx].copy(), m[:ny, :nx].copy()
+    keep_flips = 0
+    for colour in (0, 1):
+        pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 0.1, 1.0, 0, mode=1)
+        assert acc_g == 0 and acc_o == 0
+        sel = colour_mask(ny, nx, colour) & (m == 0)
+        kf = ((fg & 1) != (fo & 1)) & sel
+        keep_flips += int(kf.sum())
+        ok = sel & ~kf
+        if ok.any():
+            assert np.max(np.abs(pg[ok].astype(np.float64) - po[ok])) <= 1e-5
+        fixed = m == 1
+        assert np.array_equal(pg[fixed], phi[fixed])
+        phi = pg
+    assert keep_flips <= 1, keep_flips
+
+
+LOW_T = [2.6e-4, 1.0e-3, 0.1]
+
+
+@pytest.mark.parametrize("T", LOW_T)
+def test_metropolis_decisions_teacher_forced(ctx, T):
+    """Chains of half-sweeps; at every step the oracle redoes it from the GPU's state."""
+    say("decisions T =", T)
+    ny, nx = 384, 517
+    phi, m = smooth_state(ny, nx, 2.5, 0.05, 0.5, 0.02, 31)
+    n_dec = n_flip = n_fp64 = 0
+    max_err = 0.0
+    step = 0
+    for a in (1.0, 4.0, 40.0):
+        for sweep in range(3):
+            for colour in (0, 1):
+                pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, T, a, 100 * step + sweep)
+                sel = colour_mask(ny, nx, colour) & (m == 0)
+                flip = (((fg ^ fo) & 3) != 0) & sel
+                n_dec += int(sel.sum())
+                n_flip += int(flip.sum())
+                n_fp64 += int(((fg & 16) != 0).sum())
+                ok = sel & ~flip
+                max_err = max(max_err, float(np.max(np.abs(pg[ok].astype(np.float64) - po[ok]))))
+                phi = pg
+            step += 1
+    say(f"  decisions {n_dec}, flips {n_flip}, double-precision path {n_fp64 / n_dec:.2e}, max |dphi| {max_err:.2e}")
+    assert n_flip <= max(0, int(1e-6 * n_dec)), (n_flip, n_dec)
+    assert max_err <= 1e-5
+
+
+def test_accept_count_and_energy_teacher_forced(ctx):
+    ny, nx = 130, 257
+    phi, m = smooth_state(ny, nx, 1.5, 0.1, 0.66, 0.05, 41)
+    for colour in (0, 1):
+        pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 2e-3, 3.0, 7)
+        assert acc_g == int(((fg & 2) != 0).sum())
+        assert acc_g == acc_o
+        phi = pg
+    # energy of the resulting state, as the simulation accumulates it
+    hp = ctx.diag_energy(dev(phi))
+    ngp = oracle.bond_count(nx, ny)
+    ho = oracle.energy(phi.astype(np.float64)) + ngp
+    assert abs(hp - ho) / ngp <= 1e-6
+    assert abs(hp / ho - 1.0) <= 1e-4
+
+
+@pytest.mark.parametrize("shape", [(1, 2), (2, 1), (3, 3), (5, 2), (2, 7), (1, 9)])
+def test_degenerate_and_tiny_grids(ctx, shape):
+    ny, nx = shape
+    rng = np.random.default_rng(nx * 10 + ny)
+    phi = rng.uniform(0, TWO_PI, size=shape).astype(np.float32)
+    m = np.zeros(shape, np.uint8)
+    for colour in (0, 1):
+        pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 0.5, 1.0, 3)
+        sel = colour_mask(ny, nx, colour)
+        assert np.array_equal(fg[sel] & 3, fo[sel] & 3)
+        assert np.max(np.abs(pg.astype(np.float64) - po)) <= 1e-5
+        phi = pg
+
+
+# -------------------------------------------------------------- SG slope
+def test_sg_slope_matches_oracle(ctx):
+    rng = np.random.default_rng(3)
+    for degree in (1, 2, 3):
+        for n in (5, 20, 33, 64):
+            e = -0.99 + 1e-4 * np.cumsum(rng.normal(size=n))
+            g = ctx.diag_sg_slope(e, degree)
+            o = oracle.sg_slope(e, degree)
+            assert abs(g - o) <= 1e-9 * max(abs(o), 1e-6)
+            assert (g >= 0) == (o >= 0)
+
+
+# ------------------------------------------------------------- end to end
+def pipeline_gpu(ctx, im, prm, T=None):
+    shapes = [(im.ny, im.nx)]
+    imgs = mpr.images(shapes)
+    z = dev(im.z.astype(np.float32))
+    mk = dev(im.mask, torch.uint8)
+    phi = torch.zeros_like(z)
+    zz = ctx.map_to_angles(imgs, z, mk, phi)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    e_s, T_hat, cl = ctx.estimate_temperature(imgs, phi, mk, prm, ws)
+    if T is not None:
+        T_hat = np.array([T])
+    ps = torch.zeros_like(z)
+    st = ctx.simulate(imgs, phi, mk, T_hat, prm, ws, ps)
+    zh = torch.zeros_like(z)
+    ctx.predict(imgs, z, mk, ps, zz, prm.R * prm.K, zh)
+    return dict(phi=phi.cpu().numpy(), zz=zz, e_s=e_s[0], T=T_hat[0], clamped=cl[0], phi_sum=ps.cpu().numpy(),
+                stats=st, z_hat=zh.cpu().numpy())
+
+
+def test_temperature_estimate_matches_oracle(ctx):
+    im = synth.workload_l64()
+    prm = mpr.default_params(table_nT=12, table_T_lo=0.01, table_T_hi=2.0, table_burn=100, table_meas=300, K=1)
+    out = pipeline_gpu(ctx, im, prm)
+    e_s_o, _ = oracle.sample_energy(out["phi"].astype(np.float64), im.mask)
+    assert abs(out["e_s"] - e_s_o) <= 1e-12
+    Tg = oracle.temperature_grid(12, 0.01, 2.0)
+    et = oracle.energy_table(64, 64, Tg, 100, 300, seed=prm.seed)
+    T_o, cl = oracle.invert_temperature(Tg, et, e_s_o)
+    say(f"T_hat gpu {out['T']:.5f} oracle {T_o:.5f}")
+    assert not cl and not out["clamped"]
+    assert abs(out["T"] / T_o - 1.0) < 0.03
+
+
+def test_simulate_free_running_short_chains(ctx):
+    """After one sweep GPU and oracle agree per site; divergence grows afterwards."""
+    im = synth.workload_l64()
+    z32 = im.z.astype(np.float32).astype(np.float64)
+    po_phi, zz = oracle.map_to_angles(z32, im.mask)
+    for n_sweeps in (1, 2, 4, 8):
+        prm = mpr.default_params(R=1, K=1, fixed_relax=n_sweeps - 1, seed=77)
+        out = pipeline_gpu(ctx, im, prm, T=0.15)
+        opr = oracle.default_params(R=1, K=1, fixed_relax=n_sweeps - 1, seed=77)
+        ps, st, _, _ = oracle.simulate(out["phi"].astype(np.float64), im.mask, 0.15, opr)
+        g = im.mask == 0
+        d = np.abs(out["phi_sum"][g].astype(np.float64) - ps[g])
+        frac = float(np.mean(d <= 1e-5))
+        say(f"  {n_sweeps} sweep(s): {frac:.5f} of gap sites within 1e-5")
+        if n_sweeps == 1:
+            assert frac >= 0.999
+        assert out["stats"][0]["relax_sweeps"] == st[0]["relax_sweeps"] == n_sweeps - 1
+
+
+def test_simulate_stopping_rule_l64(ctx):
+    """Full C1 pipeline: stopping decisions, relaxation length and MAE vs the oracle."""
+    im = synth.workload_l64()
+    prm = mpr.default_params(R=8, K=10, table_nT=12, table_T_lo=0.01, table_T_hi=2.0, table_burn=100,
+                             table_meas=300)
+    out = pipeline_gpu(ctx, im, prm)
+    opr = oracle.default_params(R=8, K=10, seed=prm.seed)
+    ps, st, _, _ = oracle.simulate(out["phi"].astype(np.float64), im.mask, out["T"], opr)
+    zo = oracle.predict(im.z.astype(np.float32).astype(np.float64), im.mask, ps, 80, out["zz"])
+    zt = im.z.astype(np.float32).astype(np.float64)
+    mg = synth.validation_measures(zt, out["z_hat"].astype(np.float64), im.mask)
+    mo = synth.validation_measures(zt, zo, im.mask)
+    rs_g = [s["relax_sweeps"] for s in out["stats"]]
+    rs_o = [s["relax_sweeps"] for s in st]
+    say(f"  MAAE gpu {mg['MAAE']:.4f} oracle {mo['MAAE']:.4f}; relax gpu {rs_g} oracle {rs_o}")
+    for s in out["stats"]:
+        t = s["relax_sweeps"] - 1
+        assert t >= prm.n_fit and t % prm.n_f == 0 and s["k_last"] >= 0 and not s["not_converged"]
+    assert abs(np.mean(rs_g) - np.mean(rs_o)) <= 10
+    assert abs(mg["MAAE"] / mo["MAAE"] - 1.0) < 0.03
+    # samples copied exactly
+    s = im.mask == 1
+    assert np.array_equal(out["z_hat"][s], im.z.astype(np.float32)[s])
+
+
+def test_predict_matches_oracle_bit_exact(ctx):
+    rng = np.random.default_rng(9)
+    shape = (33, 47)
+    z = rng.normal(5, 2, size=shape).astype(np.float32)
+    m = (rng.random(shape) < 0.5).astype(np.uint8)
+    ps = (rng.random(shape) * TWO_PI * 7).astype(np.float32)
+    zz = np.array([float(z[m == 1].min()), float(z[m == 1].max())])
+    zh = torch.zeros(shape, device="cuda")
+    ctx.predict(mpr.images([shape]), dev(z), dev(m, torch.uint8), dev(ps), zz, 7, zh)
+    zo = oracle.predict(z.astype(np.float64), m, ps.astype(np.float64), 7, zz)
+    assert np.array_equal(zh.cpu().numpy(), zo.astype(np.float32))
+
+
+def test_no_gap_image_and_batch_independence(ctx):
+    """An image's result does not depend on the batch around it (same image id)."""
+    a = synth.workload_l64()
+    b_z = synth.matern_field(40, 24, 1.5, 0.1, 50, 10, 5)
+    b_m = synth.random_mask(40, 24, 0.4, 6)
+    full = np.ones((10, 12), np.uint8)
+    c_z = synth.matern_field(12, 10, 0.5, 0.2, 50, 10, 7)
+    prm = mpr.default_params(R=2, K=3)
+    T = np.array([0.15, 0.02, 0.1])
+    parts = [(a.z, a.mask), (b_z, b_m), (c_z, full)]
+    shapes = [p[0].shape for p in parts]
+
+    def run(sel):
+        sh = [shapes[i] for i in sel]
+        imgs = mpr.images(sh, ids=list(sel))
+        z = dev(np.concatenate([parts[i][0].astype(np.float32).ravel() for i in sel]))
+        mk = dev(np.concatenate([parts[i][1].ravel() for i in sel]), torch.uint8)
+        phi = torch.zeros_like(z)
+        ctx.map_to_angles(imgs, z, mk, phi)
+        ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+        ps = torch.zeros_like(z)
+        ctx.simulate(imgs, phi, mk, T[list(sel)], prm, ws, ps)
+        out, off = {}, 0
+        for i in sel:
+            n = shapes[i][0] * shapes[i][1]
+            out[i] = ps[off:off + n].cpu().numpy()
+            off += n
+        return out
+
+    together = run([0, 1, 2])
+    for i in range(3):
+        alone = run([i])
+        assert np.array_equal(together[i], alone[i]), i
+    assert np.all(together[2] == 0.0)

@@ -1,0 +1,75 @@
+"""CPU checks of the HIP library: it builds, loads and exports the C ABI.
+
+No compute call is made here (there is no GPU in the build container).
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1811_01604_amd as mpr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "mpr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mpr.load()
+    declared = header_symbols()
+    assert declared == sorted(mpr.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_library_is_gfx950_code_object():
+    data = open(mpr.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_struct_layouts_match_header():
+    # sizes implied by the header's field order (natural alignment)
+    assert C.sizeof(mpr.Image) == 24
+    assert C.sizeof(mpr.Params) == 96
+    assert C.sizeof(mpr.ChainStats) == 32
+
+
+def test_default_params_and_workspace_size():
+    p = mpr.default_params()
+    assert (p.q, p.R, p.K, p.n_f, p.n_fit, p.sg_degree) == (0.5, 1, 100, 5, 20, 1)
+    assert (p.a_targ, p.k_a, p.i_max, p.fixed_relax, p.eq_a_mode) == (0.3, 3.0, 20000, -1, 0)
+    assert (p.table_nT, p.table_burn, p.table_meas) == (32, 200, 400)
+    lib = mpr.load()
+    imgs = mpr.images([(64, 64)])
+    ws1 = lib.mpr_workspace_size(imgs, 1, C.byref(p))
+    p.R = 64
+    ws64 = lib.mpr_workspace_size(imgs, 1, C.byref(p))
+    assert 0 < ws1 < ws64
+    # each chain holds two 64 x 64 half-grids (stride 64) and their sum arrays
+    assert ws64 >= 64 * 2 * 2 * 64 * 64 * 4
+    p.R = 0
+    assert lib.mpr_workspace_size(imgs, 1, C.byref(p)) < 0
+    p.R = 1
+    p.n_fit = 65
+    assert lib.mpr_workspace_size(imgs, 1, C.byref(p)) < 0
+
+
+def test_calls_without_device_fail_cleanly():
+    lib = mpr.load()
+    if os.environ.get("HIP_VISIBLE_DEVICES", None) is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                pytest.skip("a GPU is present")
+        except ImportError:
+            pass
+    h = C.c_void_p()
+    rc = lib.mpr_create(C.byref(h), 0)
+    assert rc == mpr.MPR_ERR_HIP and not h
+    assert lib.mpr_map_to_angles(None, None, 0, None, None, None, None, None) == mpr.MPR_ERR_ARG
+    assert lib.mpr_last_error(None) == b"null context"
