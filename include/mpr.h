@@ -203,12 +203,15 @@ int32_t mpr_diag_philox(mpr_ctx *ctx, const uint32_t *ctr, uint64_t seed, int64_
  *         spin, bit 1 = proposal accepted, bit 2 = proposal wrapped,
  *         bit 3 = site updated, bit 4 = decided by the double-precision path
  *   accepted (host, int64, out, nullable)
+ *   bond_energy (host, double, out, nullable): for colour 1, the sweep's own
+ *         accumulation of H + N_GP = sum over bonds of (1 - cos(q dphi))
+ *         after the update (every bond has one colour-1 end)
  * (sweep, chain, stream_id) select the random numbers as in mpr_simulate. */
 int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi,
                             const uint8_t *sampled, int32_t colour, double T, double a,
                             double q, uint64_t seed, uint32_t sweep, uint32_t chain,
                             uint32_t stream_id, int32_t mode, uint8_t *flags,
-                            int64_t *accepted, void *stream);
+                            int64_t *accepted, double *bond_energy, void *stream);
 
 /* H + N_GP of an nx x ny grid of angles (dev, float) as the simulation
  * accumulates it: sum over bonds of (1 - cos(q (phi_i - phi_j))) in fixed

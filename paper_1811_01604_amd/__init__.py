@@ -103,7 +103,7 @@ def _declare(L):
         "mpr_profile_enable": (i32, [P, i32]),
         "mpr_profile_read": (i32, [P, C.POINTER(Profile)]),
         "mpr_diag_philox": (i32, [P, P, u64, i64, P, P]),
-        "mpr_diag_half_sweep": (i32, [P, i32, i32, P, P, i32, d, d, d, u64, u32, u32, u32, i32, P, P, P]),
+        "mpr_diag_half_sweep": (i32, [P, i32, i32, P, P, i32, d, d, d, u64, u32, u32, u32, i32, P, P, P, P]),
         "mpr_diag_energy": (i32, [P, i32, i32, P, d, P, P]),
         "mpr_diag_sg_slope": (i32, [P, P, i32, i32, P]),
     }
@@ -225,13 +225,16 @@ class Context:
                                              _stream(stream)))
 
     def diag_half_sweep(self, phi, sampled, colour, T, a, sweep, chain=0, stream_id=0, seed=3000, q=0.5,
-                        mode=0, flags=None, stream=None) -> int:
+                        mode=0, flags=None, stream=None, with_energy=False):
+        """One half-sweep in place; returns the accepted count (and the fused
+        bond-energy sum H + N_GP when with_energy)."""
         ny, nx = phi.shape
         acc = C.c_int64()
+        en = C.c_double()
         self._check(self.lib.mpr_diag_half_sweep(self._h, nx, ny, _ptr(phi), _ptr(sampled), colour, T, a, q, seed,
                                                  sweep, chain, stream_id, mode, _ptr(flags), C.byref(acc),
-                                                 _stream(stream)))
-        return acc.value
+                                                 C.byref(en), _stream(stream)))
+        return (acc.value, en.value) if with_energy else acc.value
 
     def diag_energy(self, phi, q=0.5, stream=None) -> float:
         ny, nx = phi.shape

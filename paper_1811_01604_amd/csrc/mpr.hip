@@ -105,36 +105,33 @@ __global__ void init_chains_kernel(const ChainDesc *__restrict__ descs, const in
     }
 }
 
-// Half-sweep of colour `colour` for every chain (blockIdx.y = chain).  Each
-// thread takes two neighbouring sites h0 = 2k and h0 + 1 of one half-row;
-// they share one Philox call.
+// Half-sweep of colour `colour` for every chain (blockIdx.y = chain).  A
+// block covers 4 half-rows x 64 site pairs; each thread takes the two
+// neighbouring sites h0 = 2k and h0 + 1 of one half-row, which share one
+// Philox call.
 template <bool DIAG>
-__global__ __launch_bounds__(kBlock) void half_sweep_kernel(const ChainDesc *__restrict__ descs,
-                                                            ChainState *__restrict__ states, int colour,
-                                                            SweepConsts sc, int or_only,
-                                                            uint8_t *__restrict__ flags)
+__device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ descs,
+                                                ChainState *__restrict__ states, int colour, SweepConsts sc,
+                                                int or_only, uint8_t *__restrict__ flags)
 {
     ChainState *stp = states + blockIdx.y;
     const int phase = stp->phase;
     if (phase == PH_DONE) return;
     const ChainDesc d = descs[blockIdx.y];
-    const int half = d.S >> 1;
-    const int64_t total = (int64_t)d.ny * half;
-    if ((int64_t)blockIdx.x * blockDim.x >= total) return;
-    ChainState st;
-    st.sweep = stp->sweep;
-    st.inv_T = stp->inv_T;
-    st.dscale = stp->dscale;
-    st.T = stp->T;
-    st.a_cur = stp->a_cur;
+    const int nby = (d.ny + 3) >> 2;
+    if ((int)blockIdx.x >= d.nbx * nby) return;
+    const int by = (int)blockIdx.x / d.nbx;
+    const int bx = (int)blockIdx.x - by * d.nbx;
+    const int y = by * 4 + (int)(threadIdx.x >> 6);
+    const int h0 = 2 * (bx * 64 + (int)(threadIdx.x & 63));
+    const uint32_t sweep = stp->sweep;
+    const float inv_T = stp->inv_T, dscale = stp->dscale;
+    const double T64 = stp->T, a64 = stp->a_cur;
     const bool want_energy = (colour == 1) && (phase != PH_EQ);
     const bool want_acc = phase != PH_EQ;
-    unsigned long long efx = 0ull, nacc = 0ull;
+    uint32_t e_thread = 0u, acc_thread = 0u;
 
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < total) {
-        const int y = (int)(p / half);
-        const int h0 = 2 * (int)(p - (int64_t)y * half);
+    if (y < d.ny) {
         const int s = (y + colour) & 1;
         const int W = (d.nx - s + 1) >> 1;
         const int Wo = (d.nx + s) >> 1;
@@ -145,67 +142,62 @@ __global__ __launch_bounds__(kBlock) void half_sweep_kernel(const ChainDesc *__r
             const float2 v = *reinterpret_cast<const float2 *>(mine + h0);
             float oL = 0.0f, oM = 0.0f, oR = 0.0f;
             const bool vL = h0 + s - 1 >= 0, vM = h0 + s < Wo, vR = h0 + s + 1 < Wo;
-            if (vL) oL = oth[h0 + s - 1];
-            if (vM) oM = oth[h0 + s];
-            if (vR) oR = oth[h0 + s + 1];
+            if (vL) oL = angle_of(oth[h0 + s - 1]);
+            if (vM) oM = angle_of(oth[h0 + s]);
+            if (vR) oR = angle_of(oth[h0 + s + 1]);
             float2 up = make_float2(0.0f, 0.0f), dn = make_float2(0.0f, 0.0f);
             const bool vU = y > 0, vD = y + 1 < d.ny;
             if (vU) up = *reinterpret_cast<const float2 *>(oth - d.S + h0);
             if (vD) dn = *reinterpret_cast<const float2 *>(oth + d.S + h0);
-            // neighbour unit vectors (cos, sin of q*phi); missing ones are 0
-            float cL = 0.f, sL = 0.f, cM = 0.f, sM = 0.f, cR = 0.f, sR = 0.f;
-            float cU0 = 0.f, sU0 = 0.f, cU1 = 0.f, sU1 = 0.f, cD0 = 0.f, sD0 = 0.f, cD1 = 0.f, sD1 = 0.f;
-            oL = angle_of(oL);
-            oM = angle_of(oM);
-            oR = angle_of(oR);
             up.x = angle_of(up.x);
             up.y = angle_of(up.y);
             dn.x = angle_of(dn.x);
             dn.y = angle_of(dn.y);
-            if (vL) sincosf(sc.q * oL, &sL, &cL);
-            if (vM) sincosf(sc.q * oM, &sM, &cM);
-            if (vR && two) sincosf(sc.q * oR, &sR, &cR);
-            if (vU) {
-                sincosf(sc.q * up.x, &sU0, &cU0);
-                if (two) sincosf(sc.q * up.y, &sU1, &cU1);
-            }
-            if (vD) {
-                sincosf(sc.q * dn.x, &sD0, &cD0);
-                if (two) sincosf(sc.q * dn.y, &sD1, &cD1);
-            }
             const bool fixed0 = is_fixed(v.x), fixed1 = !two || is_fixed(v.y);
-            float u0 = 0.f, r0 = 0.f, u1 = 0.f, r1 = 0.f;
+            const float a0 = angle_of(v.x), a1 = angle_of(v.y);
+            float u0 = 0.5f, r0 = 0.5f, u1 = 0.5f, r1 = 0.5f;
             if (!or_only && (!fixed0 || !fixed1)) {
-                const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * h0 + s), st.sweep, d.chain,
-                                d.image_id};
+                const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * h0 + s), sweep, d.chain, d.image_id};
                 const U4 w = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
                 u0 = unit24(w.x);
                 r0 = unit24(w.y);
                 u1 = unit24(w.z);
                 r1 = unit24(w.w);
             }
-            float out0 = v.x, out1 = v.y;
-            uint32_t f0 = 0u, f1 = 0u;
-            // site h0: left oL, right oM, up up.x, down dn.x
-            const float nb0[4] = {oL, oM, up.x, dn.x};
-            const float nc0[4] = {cL, cM, cU0, cD0};
-            const float ns0[4] = {sL, sM, sU0, sD0};
+            // site h0: left oL, right oM, up, down; site h0 + 1: left oM, right oR
             const uint32_t val0 = (vL ? 1u : 0u) | (vM ? 2u : 0u) | (vU ? 4u : 0u) | (vD ? 8u : 0u);
-            // site h0+1: left oM, right oR, up up.y, down dn.y
-            const float nb1[4] = {oM, oR, up.y, dn.y};
-            const float nc1[4] = {cM, cR, cU1, cD1};
-            const float ns1[4] = {sM, sR, sU1, sD1};
             const uint32_t val1 = 1u | (vR ? 2u : 0u) | (vU ? 4u : 0u) | (vD ? 8u : 0u);
-            if (!fixed0) {
-                const SiteOut o = update_site(v.x, nb0, val0, nc0, ns0, u0, r0, st, sc, or_only != 0);
-                out0 = o.phi;
-                f0 = o.flags;
+            SiteOut o0, o1;
+            bool n0 = true, n1 = true;
+            if (sc.half) {
+                o0 = update_site(a0, oL, oM, up.x, dn.x, val0, u0, r0, inv_T, dscale, or_only != 0, &n0);
+                o1 = update_site(a1, oM, oR, up.y, dn.y, val1, u1, r1, inv_T, dscale, or_only != 0, &n1);
+            } else {
+                const float nb0[4] = {oL, oM, up.x, dn.x}, nb1[4] = {oM, oR, up.y, dn.y};
+                o0.phi = a0;
+                o0.e_bonds = o0.e_before = site_energy(a0, nb0, val0, sc.q);
+                o0.flags = 0u;
+                o1.phi = a1;
+                o1.e_bonds = o1.e_before = site_energy(a1, nb1, val1, sc.q);
+                o1.flags = 0u;
             }
-            if (!fixed1) {
-                const SiteOut o = update_site(v.y, nb1, val1, nc1, ns1, u1, r1, st, sc, or_only != 0);
-                out1 = o.phi;
-                f1 = o.flags;
+            n0 = n0 && !fixed0;
+            n1 = n1 && !fixed1;
+            if (n0 || n1) {
+                // rare: redo in double precision (one inlined copy for both sites)
+                for (int k = 0; k < 2; ++k) {
+                    if (k ? n1 : n0) {
+                        const SiteOut f = update_site_fp64(
+                            (double)(k ? a1 : a0), k ? oM : oL, k ? oR : oM, k ? up.y : up.x, k ? dn.y : dn.x,
+                            k ? val1 : val0, (double)(k ? u1 : u0), (double)(k ? r1 : r0), a64, T64, sc.q64,
+                            or_only != 0);
+                        if (k) o1 = f;
+                        else o0 = f;
+                    }
+                }
             }
+            const float out0 = fixed0 ? v.x : o0.phi;
+            const float out1 = fixed1 ? v.y : o1.phi;
             if (two) {
                 *reinterpret_cast<float2 *>(mine + h0) = make_float2(out0, out1);
             } else if (!fixed0) {
@@ -216,17 +208,12 @@ __global__ __launch_bounds__(kBlock) void half_sweep_kernel(const ChainDesc *__r
                 if (!fixed0) acc[h0] += out0;
                 if (two && !fixed1) acc[h0 + 1] += out1;
             }
-            if (want_acc) nacc = ((f0 & F_ACCEPTED) ? 1ull : 0ull) + ((f1 & F_ACCEPTED) ? 1ull : 0ull);
-            if (want_energy) {
-                float c0, s0;
-                sincosf(sc.q * angle_of(out0), &s0, &c0);
-                efx = site_energy_fx(c0, s0, nc0, ns0, val0);
-                if (two) {
-                    float c1, s1;
-                    sincosf(sc.q * angle_of(out1), &s1, &c1);
-                    efx += site_energy_fx(c1, s1, nc1, ns1, val1);
-                }
-            }
+            const uint32_t f0 = fixed0 ? 0u : o0.flags, f1 = fixed1 ? 0u : o1.flags;
+            acc_thread = ((f0 >> 1) & 1u) + ((f1 >> 1) & 1u);
+            // a sampled site's bonds are unchanged by this half-sweep
+            if (want_energy)
+                e_thread = energy_fx(fixed0 ? o0.e_before : o0.e_bonds) +
+                           (two ? energy_fx(fixed1 ? o1.e_before : o1.e_bonds) : 0u);
             if (DIAG && flags) {
                 const int64_t x0 = 2 * h0 + s;
                 flags[(int64_t)y * d.nx + x0] = (uint8_t)f0;
@@ -235,28 +222,49 @@ __global__ __launch_bounds__(kBlock) void half_sweep_kernel(const ChainDesc *__r
         }
     }
     if (!want_acc) return;
-    // block reduction of the two counters
+    // Block sums of the energy (split in 16-bit halves so that 32-bit lane
+    // sums cannot overflow) and of the accepted count (packed in the top byte).
+    uint32_t lo = (e_thread & 0xFFFFu) | (acc_thread << 24);
+    uint32_t hi = e_thread >> 16;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        efx += __shfl_xor(efx, off);
-        nacc += __shfl_xor(nacc, off);
+        lo += __shfl_xor(lo, off);
+        hi += __shfl_xor(hi, off);
     }
-    __shared__ unsigned long long red[2][kBlock / 64];
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-        red[0][wid] = efx;
-        red[1][wid] = nacc;
+    __shared__ uint32_t red[2][kBlock / 64];
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wid] = lo;
+        red[1][wid] = hi;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long e = 0ull, a = 0ull;
         for (int i = 0; i < kBlock / 64; ++i) {
-            e += red[0][i];
-            a += red[1][i];
+            e += ((unsigned long long)red[1][i] << 16) + (red[0][i] & 0xFFFFFFu);
+            a += red[0][i] >> 24;
         }
         if (e) atomicAdd(&stp->e_fx, e);
         if (a) atomicAdd(&stp->acc, a);
     }
+}
+
+template <bool DIAG>
+__global__ __launch_bounds__(kBlock) void half_sweep_kernel(const ChainDesc *__restrict__ descs,
+                                                            ChainState *__restrict__ states, int colour,
+                                                            SweepConsts sc, int or_only,
+                                                            uint8_t *__restrict__ flags)
+{
+    half_sweep_body<DIAG>(descs, states, colour, sc, or_only, flags);
+}
+
+// The same sweep for the unconditional e(T, L) runs (a separate symbol so
+// that profiles tell the two workloads apart).
+__global__ __launch_bounds__(kBlock) void table_half_sweep_kernel(const ChainDesc *__restrict__ descs,
+                                                                  ChainState *__restrict__ states, int colour,
+                                                                  SweepConsts sc)
+{
+    half_sweep_body<false>(descs, states, colour, sc, 0, nullptr);
 }
 
 __device__ void set_derived(ChainState &st, double q)
@@ -283,8 +291,8 @@ __global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *
     const unsigned long long acc = st.acc, efx = st.e_fx;
     st.acc = 0ull;
     st.e_fx = 0ull;
-    // 1 + e = (H + N_GP) / N_GP, H + N_GP = sum (1 - cos) = efx * 2^-32
-    const double ope = (double)efx * (1.0 / 4294967296.0) / (double)d.ngp;
+    // 1 + e = (H + N_GP) / N_GP with H + N_GP = sum over bonds of (1 - cos)
+    const double ope = (double)efx * kEnergyUnit / (double)d.ngp;
     if (st.phase == PH_RELAX) {
         const double A = (double)acc / (double)d.P;
         if (A < cp.a_targ) st.a_relax = 1.0 + (double)(t + 1u) / cp.k_a;
@@ -363,15 +371,13 @@ __global__ void grid_energy_kernel(const float *__restrict__ phi, int nx, int ny
         const int y = (int)(i / nx);
         const int x = (int)(i - (int64_t)y * nx);
         if (((x + y) & 1) != 1) continue;
-        float nc[4] = {0.f, 0.f, 0.f, 0.f}, ns[4] = {0.f, 0.f, 0.f, 0.f};
+        float nb[4] = {0.f, 0.f, 0.f, 0.f};
         uint32_t valid = 0u;
-        if (x > 0) { sincosf(q * phi[i - 1], &ns[0], &nc[0]); valid |= 1u; }
-        if (x + 1 < nx) { sincosf(q * phi[i + 1], &ns[1], &nc[1]); valid |= 2u; }
-        if (y > 0) { sincosf(q * phi[i - nx], &ns[2], &nc[2]); valid |= 4u; }
-        if (y + 1 < ny) { sincosf(q * phi[i + nx], &ns[3], &nc[3]); valid |= 8u; }
-        float ci, si;
-        sincosf(q * phi[i], &si, &ci);
-        e += site_energy_fx(ci, si, nc, ns, valid);
+        if (x > 0) { nb[0] = phi[i - 1]; valid |= 1u; }
+        if (x + 1 < nx) { nb[1] = phi[i + 1]; valid |= 2u; }
+        if (y > 0) { nb[2] = phi[i - nx]; valid |= 4u; }
+        if (y + 1 < ny) { nb[3] = phi[i + nx]; valid |= 8u; }
+        e += energy_fx(site_energy(phi[i], nb, valid, q));
     }
     for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
     if ((threadIdx.x & 63) == 0 && e) atomicAdd(out, e);
@@ -708,6 +714,8 @@ SweepConsts make_sc(double q, uint64_t seed)
     sc.q64 = q;
     sc.seed_lo = (uint32_t)seed;
     sc.seed_hi = (uint32_t)(seed >> 32);
+    sc.half = q == 0.5 ? 1 : 0;
+    sc.pad = 0;
     return sc;
 }
 
@@ -721,12 +729,12 @@ struct ChainSet {
     ChainDesc *d_desc = nullptr;
     ChainState *d_state = nullptr;
     int64_t *d_offset = nullptr;
-    int max_half_total = 0;       // max over chains of ny * S / 2 (pairs)
+    int64_t max_blocks = 0;       // max over chains of sweep blocks
 };
 
 // Runs sweeps until every chain is done.  Returns 0 or an error code.
 int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stream, int64_t max_sweeps,
-               int poll_every)
+               int poll_every, bool table)
 {
     const int n = (int)cs.desc.size();
     unsigned int *d_done = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kDoneOffset);
@@ -737,7 +745,7 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     if (already == (unsigned int)n) return MPR_OK;
     const CtlParams cp = make_ctl(p);
     const SweepConsts sc = make_sc(p->q, p->seed);
-    const dim3 grid((unsigned)((cs.max_half_total + kBlock - 1) / kBlock), (unsigned)n);
+    const dim3 grid((unsigned)cs.max_blocks, (unsigned)n);
     const int cblocks = (n + 63) / 64;
     unsigned long long *d_work = reinterpret_cast<unsigned long long *>((char *)ctx->scratch + kWorkOffset);
     if (ctx->profile) {
@@ -751,10 +759,14 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
         int j = 0;
         for (; j < poll_every && done_sweeps < max_sweeps; ++j, ++done_sweeps) {
             if (ctx->profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * j], stream));
-            hipLaunchKernelGGL(half_sweep_kernel<false>, grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state, 0, sc,
-                               0, nullptr);
-            hipLaunchKernelGGL(half_sweep_kernel<false>, grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state, 1, sc,
-                               0, nullptr);
+            for (int colour = 0; colour < 2; ++colour) {
+                if (table)
+                    hipLaunchKernelGGL(table_half_sweep_kernel, grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
+                                       colour, sc);
+                else
+                    hipLaunchKernelGGL(half_sweep_kernel<false>, grid, dim3(kBlock), 0, stream, cs.d_desc,
+                                       cs.d_state, colour, sc, 0, nullptr);
+            }
             if (ctx->profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * j + 1], stream));
             hipLaunchKernelGGL(control_kernel, dim3(cblocks), dim3(64), 0, stream, cs.d_desc, cs.d_state, n, cp,
                                d_done, d_work);
@@ -812,6 +824,7 @@ bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc)
     d.nx = nx;
     d.ny = ny;
     d.S = half_stride(nx);
+    d.nbx = (d.S / 2 + 63) / 64;
     for (int c = 0; c < 2; ++c) {
         d.h[c] = (float *)cv.take(hg);
         d.acc[c] = with_acc ? (float *)cv.take(hg) : nullptr;
@@ -1061,7 +1074,7 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
                 cs.desc.push_back(d);
                 cs.state.push_back(fresh_state(Tg[k], PH_TABLE));
                 cs.offset.push_back(0);
-                cs.max_half_total = std::max<int64_t>(cs.max_half_total, (int64_t)d.ny * d.S / 2);
+                cs.max_blocks = std::max<int64_t>(cs.max_blocks, (int64_t)d.nbx * ((d.ny + 3) / 4));
             }
             int rc = upload_chains(ctx, cs, cv, stream, p->q);
             if (rc) return rc;
@@ -1069,7 +1082,8 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
             hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), p->table_nT), dim3(kBlock), 0, stream,
                                cs.d_desc, cs.d_offset, nullptr, nullptr, nullptr, 0u, 0u, 1);
             HIP_TRY(ctx, hipGetLastError());
-            rc = run_chains(ctx, cs, p, stream, (int64_t)p->table_burn + p->table_meas, p->table_burn + p->table_meas);
+            rc = run_chains(ctx, cs, p, stream, (int64_t)p->table_burn + p->table_meas, p->table_burn + p->table_meas,
+                            true);
             if (rc) return rc;
             HIP_TRY(ctx, hipMemcpyAsync(cs.state.data(), cs.d_state, cs.state.size() * sizeof(ChainState),
                                         hipMemcpyDeviceToHost, stream));
@@ -1149,7 +1163,7 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
             if (phase == PH_EQ && !p->eq_a_mode) st.a_cur = 1.0;
             cs.state.push_back(st);
             cs.offset.push_back(imgs[b].offset);
-            cs.max_half_total = std::max<int64_t>(cs.max_half_total, (int64_t)ny * d.S / 2);
+            cs.max_blocks = std::max<int64_t>(cs.max_blocks, (int64_t)d.nbx * ((d.ny + 3) / 4));
         }
     }
     int rc = upload_chains(ctx, cs, cv, stream, p->q);
@@ -1165,7 +1179,7 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
                        (uint32_t)(p->seed >> 32), 0);
     HIP_TRY(ctx, hipGetLastError());
     const int64_t relax_cap = p->fixed_relax >= 0 ? p->fixed_relax : (int64_t)p->i_max + 1;
-    rc = run_chains(ctx, cs, p, stream, relax_cap + p->K + 1, p->n_f);
+    rc = run_chains(ctx, cs, p, stream, relax_cap + p->K + 1, p->n_f, false);
     if (rc) return rc;
     hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, cs.d_desc, d_img,
                        p->R, p->K, sampled, phi_sum);
@@ -1260,7 +1274,8 @@ int32_t mpr_diag_philox(mpr_ctx *ctx, const uint32_t *ctr, uint64_t seed, int64_
 
 int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, const uint8_t *sampled, int32_t colour,
                             double T, double a, double q, uint64_t seed, uint32_t sweep, uint32_t chain,
-                            uint32_t stream_id, int32_t mode, uint8_t *flags, int64_t *accepted, void *stream_)
+                            uint32_t stream_id, int32_t mode, uint8_t *flags, int64_t *accepted,
+                            double *bond_energy, void *stream_)
 {
     if (!ctx) return MPR_ERR_ARG;
     if (nx < 1 || ny < 1 || (int64_t)nx * ny < 2 || !phi || !sampled || (colour != 0 && colour != 1) || !(T > 0) ||
@@ -1300,8 +1315,7 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
                        cs.d_offset, phi, sampled, phi, 0u, 0u, 0);
     if (flags) (void)hipMemsetAsync(flags, 0, nsite, stream);
     const SweepConsts sc = make_sc(q, seed);
-    const int64_t pairs = (int64_t)ny * d.S / 2;
-    hipLaunchKernelGGL(half_sweep_kernel<true>, dim3((unsigned)((pairs + kBlock - 1) / kBlock), 1), dim3(kBlock), 0,
+    hipLaunchKernelGGL(half_sweep_kernel<true>, dim3((unsigned)(cs.desc[0].nbx * ((ny + 3) / 4)), 1), dim3(kBlock), 0,
                        stream, cs.d_desc, cs.d_state, colour, sc, mode, flags);
     hipLaunchKernelGGL(unsplit_kernel, dim3(blocks_for(nsite, 2048)), dim3(kBlock), 0, stream, cs.d_desc, phi);
     ChainState out;
@@ -1312,6 +1326,7 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
     if (e1 != hipSuccess || e2 != hipSuccess)
         return fail(ctx, MPR_ERR_HIP, "diag_half_sweep: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
     if (accepted) *accepted = (int64_t)out.acc;
+    if (bond_energy) *bond_energy = (double)out.e_fx * kEnergyUnit;
     return MPR_OK;
 }
 
@@ -1331,7 +1346,7 @@ int32_t mpr_diag_energy(mpr_ctx *ctx, int32_t nx, int32_t ny, const float *phi, 
     unsigned long long e = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&e, d_e, 8, hipMemcpyDeviceToHost, stream));
     HIP_TRY(ctx, hipStreamSynchronize(stream));
-    *h_plus_ngp = (double)e * (1.0 / 4294967296.0);
+    *h_plus_ngp = (double)e * kEnergyUnit;
     return MPR_OK;
 }
 

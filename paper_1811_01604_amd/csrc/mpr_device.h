@@ -32,7 +32,7 @@ struct ChainDesc {
     int32_t nx, ny, S;    // grid size and half-row stride
     uint32_t image_id;    // Philox counter word 3
     uint32_t chain;       // Philox counter word 2
-    int32_t pad;
+    int32_t nbx;          // sweep blocks per 4-row band (64 site pairs each)
     int64_t P;            // number of gap sites
     int64_t ngp;          // number of bonds
 };
@@ -47,7 +47,7 @@ struct ChainState {
     double T;
     double a_cur;          // a used by the next sweep
     double a_relax;        // a of the relaxation rule
-    unsigned long long e_fx;   // sum over bonds of |u_i - u_j|^2 in units of 2^-31
+    unsigned long long e_fx;   // sum over bonds of 1 - cos(q (phi_i - phi_j)), units of 2^-27
     unsigned long long acc;    // accepted proposals in the current sweep
     double k;              // last energy slope
     double A_last;
@@ -101,24 +101,35 @@ struct SweepConsts {
     float two_pi_q;   // period of q*phi
     double q64;
     uint32_t seed_lo, seed_hi;
+    int32_t half;     // q == 1/2: single-precision fast path
+    int32_t pad;
 };
 
 // ------------------------------------------------- double-precision path
+// Result of one site's update.
+struct SiteOut {
+    float phi;       // new angle
+    float e_bonds;   // sum over the site's bonds of 1 - cos(q (phi_new - phi_j))
+    float e_before;  // the same sum before the update
+    uint32_t flags;
+};
+
 // The whole update of one site in double precision, in the same steps and
 // order as the plain definition: local q-field, reflection with the keep
 // rule, wrapped proposal, Delta H as the difference of the two local
-// energies, and the acceptance test.  Used when the single-precision
-// decision is too close to call.
-__device__ __noinline__ float update_site_fp64(double phi, const float nb[4], uint32_t valid,
-                                               double u, double r, double a, double T,
-                                               double q, uint32_t *flags)
+// energies, and the acceptance test.  Used for any q other than 1/2 and when
+// the single-precision decision is too close to call.
+__device__ __noinline__ SiteOut update_site_fp64(double phi, float n0, float n1, float n2, float n3,
+                                                 uint32_t valid, double u, double r, double a, double T,
+                                                 double q, bool or_only)
 {
 #pragma clang fp contract(off)
     double sx = 0.0, sy = 0.0;
     int nnb = 0;
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
         if (valid & (1u << j)) {
-            const double v = (double)nb[j];
+            const double v = (double)(j == 0 ? n0 : j == 1 ? n1 : j == 2 ? n2 : n3);
             sx += cos(q * v);
             sy += sin(q * v);
             ++nnb;
@@ -137,130 +148,186 @@ __device__ __noinline__ float update_site_fp64(double phi, const float nb[4], ui
             f |= F_KEPT;
         }
     }
+    double h1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (valid & (1u << j)) h1 -= cos(q * (p1 - (double)(j == 0 ? n0 : j == 1 ? n1 : j == 2 ? n2 : n3)));
+    SiteOut o;
+    o.e_before = (float)((double)nnb + h1);
+    if (or_only) {
+        o.phi = (float)p1;
+        o.e_bonds = (float)((double)nnb + h1);
+        o.flags = f;
+        return o;
+    }
     const double raw = p1 + kTwoPi * (u - 0.5) / a;
     double p2 = raw;
     if (p2 < 0.0) p2 += kTwoPi;
     else if (p2 >= kTwoPi) p2 -= kTwoPi;
     if (p2 >= kTwoPi || p2 < 0.0) p2 = 0.0;
     if (raw < 0.0 || raw >= kTwoPi) f |= F_WRAPPED;
-    double h2 = 0.0, h1 = 0.0;
+    double h2 = 0.0;
+#pragma unroll
     for (int j = 0; j < 4; ++j)
-        if (valid & (1u << j)) h2 -= cos(q * (p2 - (double)nb[j]));
-    for (int j = 0; j < 4; ++j)
-        if (valid & (1u << j)) h1 -= cos(q * (p1 - (double)nb[j]));
+        if (valid & (1u << j)) h2 -= cos(q * (p2 - (double)(j == 0 ? n0 : j == 1 ? n1 : j == 2 ? n2 : n3)));
     const double dH = h2 - h1;
     const bool acc = (dH <= 0.0) || (exp(-dH / T) > r);
     if (acc) f |= F_ACCEPTED;
-    *flags = f;
-    return (float)(acc ? p2 : p1);
+    o.phi = (float)(acc ? p2 : p1);
+    o.e_bonds = (float)((double)nnb + (acc ? h2 : h1));
+    o.flags = f;
+    return o;
 }
 
-// --------------------------------------------------- single-site update
-struct SiteOut {
-    float phi;       // new angle
-    uint32_t flags;
-};
-
-// Algorithm 1 for one gap site in single precision.
-//   phi        current angle of the site
-//   nb[4]      neighbour angles (left, right, up, down), valid bits in `valid`
-//   nc, ns     cos / sin of q * neighbour angle (0 for missing neighbours)
-//   u, r       the site's two uniforms
-// Over-relaxation reflects theta = q*phi about Psi = arg(h), h = sum of the
-// neighbour unit vectors: theta' = 2 Psi - theta, kept when it leaves
-// [0, 2 pi q).  The Metropolis energy change of theta'' = theta' + delta is
-// evaluated without cancellation: with d = theta' - Psi,
-//   H(theta'') - H(theta') = |h| (cos d - cos(d + delta))
-//                          = 2 |h| sin(d + delta/2) sin(delta/2)
-// when the proposal does not wrap, and directly otherwise.  Decisions whose
-// margin |ln r + Delta H / T| is inside a bound on the rounding error, and
-// reflections or proposals that land within rounding of the domain's ends,
-// are redone in double precision.
-__device__ __forceinline__ SiteOut update_site(float phi, const float nb[4], uint32_t valid,
-                                               const float nc[4], const float ns[4],
-                                               float u, float r, const ChainState &st,
-                                               const SweepConsts &sc, bool or_only)
+// ------------------------------------------------ single-precision math
+// Minimax polynomials fitted for this library (least squares with Lawson
+// reweighting on Chebyshev nodes):
+//   sin x, |x| <= pi/2: x (1 + x^2 P(x^2)), relative error 5e-9;
+//   cos x, |x| <= pi/2: Q(x^2) of degree 8, absolute error 5e-8;
+//   atan t, |t| <= 1:   t (1 + t^2 R(t^2)), relative error 1.5e-8.
+__device__ __forceinline__ float sin_poly(float x)
 {
-    const float hx = (nc[0] + nc[1]) + (nc[2] + nc[3]);
-    const float hy = (ns[0] + ns[1]) + (ns[2] + ns[3]);
-    const float th = sc.q * phi;
-    const float psi = atan2f(hy, hx);
-    const float raw1 = 2.0f * psi - th;
-    const bool degenerate = (hx == 0.0f && hy == 0.0f);
-    bool kept = degenerate || !(raw1 >= 0.0f && raw1 < sc.two_pi_q);
+    const float x2 = x * x;
+    float p = fmaf(x2, 2.601902224e-06f, -1.980741799e-04f);
+    p = fmaf(p, x2, 8.333025500e-03f);
+    p = fmaf(p, x2, -1.666665673e-01f);
+    return fmaf(p * x2, x, x);
+}
+
+__device__ __forceinline__ float cos_poly(float x)
+{
+    const float x2 = x * x;
+    float p = fmaf(x2, 2.315392157e-05f, -1.385370386e-03f);
+    p = fmaf(p, x2, 4.166358337e-02f);
+    p = fmaf(p, x2, -4.999990463e-01f);
+    return fmaf(p, x2, 9.999999404e-01f);
+}
+
+// atan2(y, x) in (-pi, pi]: octant reduction to t = min/max in [0, 1].
+__device__ __forceinline__ float atan2_poly(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float t2 = t * t;
+    float p = fmaf(t2, 2.849767916e-03f, -1.606814750e-02f);
+    p = fmaf(p, t2, 4.269074649e-02f);
+    p = fmaf(p, t2, -7.504229993e-02f);
+    p = fmaf(p, t2, 1.064090431e-01f);
+    p = fmaf(p, t2, -1.420363635e-01f);
+    p = fmaf(p, t2, 1.999261826e-01f);
+    p = fmaf(p, t2, -3.333307207e-01f);
+    float a = fmaf(p * t2, t, t);
+    a = ay > ax ? 1.57079637f - a : a;
+    a = x < 0.0f ? 3.14159274f - a : a;
+    return y < 0.0f ? -a : a;
+}
+
+// Algorithm 1 for one site, q = 1/2, in single precision (computed for
+// sampled sites too; the caller discards those results).
+//   phi        current angle; th = phi / 2
+//   n0..n3     neighbour angles (left, right, up, down), valid bits in `valid`
+//   u, r       the site's two uniforms
+// With D_j = th - th_j (exact in float when the angles are close), the
+// local field relative to the spin is A = sum cos D_j = |h| cos(th - Psi)
+// and B = sum sin D_j = |h| sin(th - Psi), computed from sin and cos of D_j/2
+// so that both stay accurate for nearly aligned spins.  Over-relaxation:
+// th' = th + 2 d with d = Psi - th = atan2(-B, A), kept if th' leaves
+// [0, pi).  With Bs = |h| sin(th' - Psi) (= -B, or B when kept) and the
+// proposal th'' = th' + delta, the energy change is
+//   H(th'') - H(th') = 2 A sin^2(delta/2) + Bs sin(delta)        (no wrap)
+//                    = 2 A cos^2(delta/2) - Bs sin(delta)        (wrapped by pi)
+// with no cancellation.  The reflection keeps the energy, so the site's
+// bond energy afterwards is sum (1 - cos D_j) plus Delta H if accepted.
+// need64 is set for a decision whose margin |ln r + dH/T| lies inside a
+// bound on its rounding error, a reflection or proposal within 4e-6 of the
+// ends of [0, pi), and a weak field (|h| < 1/4: neighbours split between
+// both ends of [0, 2 pi), where Psi is ill-conditioned in single precision).
+__device__ __forceinline__ SiteOut update_site(float phi, float n0, float n1, float n2, float n3,
+                                               uint32_t valid, float u, float r, float inv_T, float dscale,
+                                               bool or_only, bool *need64)
+{
+    const float th = 0.5f * phi;
+    const float nb[4] = {n0, n1, n2, n3};
+    float A_small = 0.0f, B = 0.0f, S1 = 0.0f;
+    float nnb = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool v = (valid >> j) & 1u;
+        const float dj = v ? th - 0.5f * nb[j] : 0.0f;
+        const float hj = 0.5f * dj;
+        const float sj = sin_poly(hj);
+        const float cj = cos_poly(hj);
+        const float s2 = 2.0f * sj;
+        B = fmaf(s2, cj, B);              // sin D_j
+        A_small = fmaf(s2, sj, A_small);  // 1 - cos D_j
+        S1 += fabsf(dj);
+        nnb += v ? 1.0f : 0.0f;
+    }
+    const float A = nnb - A_small;
+    const float d1 = atan2_poly(-B, A);
+    const float raw1 = fmaf(2.0f, d1, th);
+    const float pi_f = 3.14159274f;
     const float tb = 4.0e-6f;
-    bool close = fabsf(raw1) < tb || fabsf(raw1 - sc.two_pi_q) < tb;
+    bool close = (A * A + B * B) < 0.0625f || fabsf(raw1) < tb || fabsf(raw1 - pi_f) < tb;
+    const bool kept = !(raw1 >= 0.0f && raw1 < pi_f);
     const float th1 = kept ? th : raw1;
-    const float d1 = kept ? (th - psi) : (psi - th);
     SiteOut o;
+    o.e_before = A_small;
     if (or_only) {
-        o.phi = th1 / sc.q;
+        *need64 = close;
+        o.phi = 2.0f * th1;
+        o.e_bonds = A_small;
         o.flags = F_UPDATED | (kept ? F_KEPT : 0u);
-        if (close) {
-            // Decide the keep rule in double precision as well.
-            double sx = 0.0, sy = 0.0;
-            for (int j = 0; j < 4; ++j)
-                if (valid & (1u << j)) {
-                    sx += cos(sc.q64 * (double)nb[j]);
-                    sy += sin(sc.q64 * (double)nb[j]);
-                }
-            const double p1 = (2.0 * atan2(sy, sx) - sc.q64 * (double)phi) / sc.q64;
-            const bool k64 = !(p1 >= 0.0 && p1 < kTwoPi);
-            o.phi = k64 ? phi : (float)p1;
-            o.flags = F_UPDATED | F_FP64 | (k64 ? F_KEPT : 0u);
-        }
         return o;
     }
-    const float delta = (u - 0.5f) * st.dscale;
+    const float Bs = kept ? B : -B;
+    const float delta = (u - 0.5f) * dscale;
+    const float hd = 0.5f * delta;
+    const float sh = sin_poly(hd), ch = cos_poly(hd);
+    const float sd = 2.0f * sh * ch;
     const float raw2 = th1 + delta;
-    const bool wrapped = raw2 < 0.0f || raw2 >= sc.two_pi_q;
-    close = close || fabsf(raw2) < tb || fabsf(raw2 - sc.two_pi_q) < tb;
-    float th2 = raw2 < 0.0f ? raw2 + sc.two_pi_q : (raw2 >= sc.two_pi_q ? raw2 - sc.two_pi_q : raw2);
-    if (th2 >= sc.two_pi_q || th2 < 0.0f) th2 = 0.0f;
-    const float hmag = sqrtf(hx * hx + hy * hy);
-    float dH;
-    if (!wrapped) {
-        const float hd = 0.5f * delta;
-        dH = 2.0f * hmag * sinf(d1 + hd) * sinf(hd);
-    } else {
-        dH = hmag * (cosf(d1) - cosf(th2 - psi));
-    }
-    const float x = dH * st.inv_T;
-    const float lr = logf(r);
+    const bool wrapped = raw2 < 0.0f || raw2 >= pi_f;
+    close = close || fabsf(raw2) < tb || fabsf(raw2 - pi_f) < tb || r == 0.0f;
+    const float th2 = raw2 < 0.0f ? raw2 + pi_f : (raw2 >= pi_f ? raw2 - pi_f : raw2);
+    const float w2 = 2.0f * (wrapped ? ch * ch : sh * sh);
+    const float dH = fmaf(A, w2, wrapped ? -Bs * sd : Bs * sd);
+    const float x = dH * inv_T;
+    const float lr = __logf(r);
     const float m = -x - lr;
-    const bool acc = (r == 0.0f) || (m > 0.0f);
-    // Rounding-error bound of m (generous): errors of the neighbour sums and
-    // of Psi enter through d times |delta| (times 2 for a wrapped proposal);
-    // the rest is relative to Delta H, ln r and their ratio.
-    const float err_dH = 8.0e-6f * (1.0f + hmag) * (fabsf(delta) + (wrapped ? 2.0f : 0.0f))
-                         + 8.0e-6f * fabsf(dH) * (1.0f + 1.0f / fmaxf(hmag, 1.0e-3f));
-    const float err_m = err_dH * st.inv_T + 1.0e-6f * (fabsf(x) + fabsf(lr)) + 1.0e-30f;
-    if (close || fabsf(m) <= err_m || degenerate) {
-        o.phi = update_site_fp64((double)phi, nb, valid, (double)u, (double)r, st.a_cur, st.T,
-                                 sc.q64, &o.flags);
-        return o;
-    }
-    o.phi = (acc ? th2 : th1) / sc.q;
+    // Rounding-error bound of m: B carries a relative error ~6e-7 of
+    // sum |D_j|, A an absolute one ~1e-6; the rest is relative.
+    const float err_dH = 2.0e-6f * (S1 + (fabsf(A) + fabsf(B)) * fabsf(sd)) * fabsf(sd) + 2.0e-6f * w2 +
+                         2.0e-6f * fabsf(dH);
+    const float band = err_dH * inv_T + 1.0e-6f * (fabsf(x) + fabsf(lr)) + 1.0e-6f;
+    *need64 = close || !(fabsf(m) > band);
+    const bool acc = m > 0.0f;
+    o.phi = 2.0f * (acc ? th2 : th1);
+    o.e_bonds = acc ? A_small + dH : A_small;
     o.flags = F_UPDATED | (kept ? F_KEPT : 0u) | (wrapped ? F_WRAPPED : 0u) | (acc ? F_ACCEPTED : 0u);
     return o;
 }
 
-// Bond energy sum of one site in fixed point: sum over its bonds of
-// |u_i - u_j|^2 = 2 (1 - cos(q (phi_i - phi_j))), scaled by 2^31 and
-// truncated, so that integer sums over sites do not depend on their order.
-__device__ __forceinline__ unsigned long long site_energy_fx(float ci, float si, const float *nc,
-                                                             const float *ns, uint32_t valid)
+// Bond energies of a site in fixed point: units of 2^-27, rounded, so that
+// integer sums over sites do not depend on their order (a site has at most
+// 4 bonds of at most 2 each, so a value stays below 2^30).
+constexpr float kEnergyScale = 134217728.0f;
+constexpr double kEnergyUnit = 1.0 / 134217728.0;
+
+__device__ __forceinline__ uint32_t energy_fx(float e) { return (uint32_t)fmaf(e, kEnergyScale, 0.5f); }
+
+// Sum over the bonds of one site of 1 - cos(q (phi_i - phi_j)) = 2 sin^2(D/2),
+// D = q (phi_i - phi_j), straight from the angles.
+__device__ __forceinline__ float site_energy(float phi, const float nb[4], uint32_t valid, float q)
 {
     float e = 0.0f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        if (valid & (1u << j)) {
-            const float dx = ci - nc[j];
-            const float dy = si - ns[j];
-            e = fmaf(dx, dx, fmaf(dy, dy, e));
-        }
+        const bool v = (valid >> j) & 1u;
+        const float sj = sin_poly(v ? 0.5f * q * (phi - nb[j]) : 0.0f);
+        e = fmaf(2.0f * sj, sj, e);
     }
-    return (unsigned long long)((double)e * 2147483648.0);
+    return e;
 }
 
 }  // namespace mpr

@@ -191,11 +191,20 @@ def test_metropolis_decisions_teacher_forced(ctx, T):
 def test_accept_count_and_energy_teacher_forced(ctx):
     ny, nx = 130, 257
     phi, m = smooth_state(ny, nx, 1.5, 0.1, 0.66, 0.05, 41)
-    for colour in (0, 1):
-        pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 2e-3, 3.0, 7)
-        assert acc_g == int(((fg & 2) != 0).sum())
-        assert acc_g == acc_o
-        phi = pg
+    ngp = oracle.bond_count(nx, ny)
+    for T, a in ((2e-3, 3.0), (2.6e-4, 20.0), (0.2, 1.0)):
+        for colour in (0, 1):
+            pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, T, a, 7)
+            assert acc_g == int(((fg & 2) != 0).sum())
+            assert acc_g == acc_o
+            if colour == 1:
+                # the sweep's own energy sum (from its update terms) against
+                # the oracle's energy of the state it wrote: |de| <= 1e-6
+                g = dev(phi)
+                _, e_fused = ctx.diag_half_sweep(g, dev(m, torch.uint8), 1, T, a, 7, with_energy=True)
+                e_o = oracle.energy(g.cpu().numpy().astype(np.float64)) + ngp
+                assert abs(e_fused - e_o) / ngp <= 1e-6, (e_fused, e_o)
+            phi = pg
     # energy of the resulting state, as the simulation accumulates it
     hp = ctx.diag_energy(dev(phi))
     ngp = oracle.bond_count(nx, ny)
