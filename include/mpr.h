@@ -79,9 +79,13 @@ typedef struct {
     int32_t table_nT;
     int32_t table_burn;
     int32_t table_meas;
-    int32_t reserved;
+    int32_t tile_rows;    /* sweep block shape: 1, 2, 4 or 8 half-rows x (256 / rows)
+                             site pairs; 0 = autotune (results do not depend on it) */
     double table_T_lo, table_T_hi;
     uint64_t seed;        /* Philox key */
+    int32_t sweeps_per_launch;  /* sweeps per captured graph between done-checks;
+                                   0 = chosen from the measured sweep time */
+    int32_t reserved;
 } mpr_params;
 
 /* Per chain results of mpr_simulate (R per image, image-major). */
@@ -101,7 +105,8 @@ void mpr_destroy(mpr_ctx *ctx);
 const char *mpr_last_error(const mpr_ctx *ctx);
 /* Defaults: q=0.5, R=1, K=100, n_f=5, n_fit=20, sg_degree=1, i_max=20000,
  * a_targ=0.3, k_a=3, fixed_relax=-1, eq_a_mode=0, table 32 points over
- * [1e-5, 10], 200 + 400 sweeps, seed 3000. */
+ * [1e-5, 10], 200 + 400 sweeps, seed 3000, tile_rows=0 and
+ * sweeps_per_launch=0 (automatic). */
 void mpr_default_params(mpr_params *p);
 
 /* Device workspace bytes needed by mpr_estimate_temperature and
@@ -141,7 +146,11 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_
                                  void *stream);
 
 /* Algorithm 2 steps 2, 5 and 6 with Algorithm 1 sweeps on the GPU, for all
- * images and R chains per image at once.  Each chain starts from U(0, 2 pi)
+ * images and R chains per image at once: every half-sweep is one launch over
+ * the blocks of all chains of the (ragged) batch, and groups of sweeps are
+ * replayed as a captured HIP graph.  Unless tile_rows is set, the first
+ * sweeps of a new batch shape time each block shape and the fastest is kept
+ * for that shape (cached in ctx).  Each chain starts from U(0, 2 pi)
  * gap angles (or phi_init), relaxes with the hybrid update until the energy
  * slope is >= 0 or i_max (or fixed_relax sweeps), then runs K equilibrium
  * sweeps.  Random numbers are Philox4x32-10 keyed by (seed; site, sweep,

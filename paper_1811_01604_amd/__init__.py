@@ -49,8 +49,9 @@ class Params(C.Structure):
         ("n_fit", C.c_int32), ("sg_degree", C.c_int32), ("i_max", C.c_int32),
         ("a_targ", C.c_double), ("k_a", C.c_double), ("fixed_relax", C.c_int32),
         ("eq_a_mode", C.c_int32), ("table_nT", C.c_int32), ("table_burn", C.c_int32),
-        ("table_meas", C.c_int32), ("reserved", C.c_int32), ("table_T_lo", C.c_double),
-        ("table_T_hi", C.c_double), ("seed", C.c_uint64),
+        ("table_meas", C.c_int32), ("tile_rows", C.c_int32), ("table_T_lo", C.c_double),
+        ("table_T_hi", C.c_double), ("seed", C.c_uint64), ("sweeps_per_launch", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

@@ -105,25 +105,44 @@ __global__ void init_chains_kernel(const ChainDesc *__restrict__ descs, const in
     }
 }
 
-// Half-sweep of colour `colour` for every chain (blockIdx.y = chain).  A
-// block covers 4 half-rows x 64 site pairs; each thread takes the two
-// neighbouring sites h0 = 2k and h0 + 1 of one half-row, which share one
-// Philox call.
-template <bool DIAG>
-__device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ descs,
-                                                ChainState *__restrict__ states, int colour, SweepConsts sc,
-                                                int or_only, uint8_t *__restrict__ flags)
+// Chain of a flattened block index: start[c] <= b < start[c + 1].  The
+// search runs on block-uniform values, so it stays in scalar registers.
+__device__ __forceinline__ int find_chain(const int64_t *__restrict__ start, int n, int64_t b)
 {
-    ChainState *stp = states + blockIdx.y;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Half-sweep of colour `colour` for every chain of a (possibly ragged)
+// batch in one launch.  The blocks of all chains are laid end to end
+// (start[] = prefix sums of blocks per chain).  A 256-thread block covers
+// ROWS half-rows x (256 / ROWS) site pairs; each thread takes the two
+// neighbouring sites h0 = 2k and h0 + 1 of one half-row, which share one
+// Philox call.  Results do not depend on ROWS: random numbers are keyed by
+// site and energies are summed in fixed point.
+template <bool DIAG, int ROWS>
+__device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ descs,
+                                                ChainState *__restrict__ states,
+                                                const int64_t *__restrict__ start, int n_chains, int colour,
+                                                SweepConsts sc, int or_only, uint8_t *__restrict__ flags)
+{
+    constexpr int PX = kBlock / ROWS;
+    const int c = find_chain(start, n_chains, (int64_t)blockIdx.x);
+    ChainState *stp = states + c;
     const int phase = stp->phase;
     if (phase == PH_DONE) return;
-    const ChainDesc d = descs[blockIdx.y];
-    const int nby = (d.ny + 3) >> 2;
-    if ((int)blockIdx.x >= d.nbx * nby) return;
-    const int by = (int)blockIdx.x / d.nbx;
-    const int bx = (int)blockIdx.x - by * d.nbx;
-    const int y = by * 4 + (int)(threadIdx.x >> 6);
-    const int h0 = 2 * (bx * 64 + (int)(threadIdx.x & 63));
+    const ChainDesc d = descs[c];
+    const int lb = (int)((int64_t)blockIdx.x - start[c]);
+    const int nbx = ((d.S >> 1) + PX - 1) / PX;
+    const int by = lb / nbx;
+    const int bx = lb - by * nbx;
+    const int y = by * ROWS + (int)(threadIdx.x / PX);
+    const int h0 = 2 * (bx * PX + (int)(threadIdx.x % PX));
     const uint32_t sweep = stp->sweep;
     const float inv_T = stp->inv_T, dscale = stp->dscale;
     const double T64 = stp->T, a64 = stp->a_cur;
@@ -137,8 +156,10 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
         const int Wo = (d.nx + s) >> 1;
         if (h0 < W) {
             const bool two = (h0 + 1) < W;
-            float *mine = d.h[colour] + (int64_t)y * d.S;
-            const float *oth = d.h[colour ^ 1] + (int64_t)y * d.S;
+            // select by value: indexing d.h with a runtime colour would put
+            // the descriptor in memory
+            float *mine = (colour ? d.h[1] : d.h[0]) + (int64_t)y * d.S;
+            const float *oth = (colour ? d.h[0] : d.h[1]) + (int64_t)y * d.S;
             const float2 v = *reinterpret_cast<const float2 *>(mine + h0);
             float oL = 0.0f, oM = 0.0f, oR = 0.0f;
             const bool vL = h0 + s - 1 >= 0, vM = h0 + s < Wo, vR = h0 + s + 1 < Wo;
@@ -203,8 +224,9 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
             } else if (!fixed0) {
                 mine[h0] = out0;
             }
-            if (phase == PH_EQ && d.acc[colour]) {
-                float *acc = d.acc[colour] + (int64_t)y * d.S;
+            float *accp = colour ? d.acc[1] : d.acc[0];
+            if (phase == PH_EQ && accp) {
+                float *acc = accp + (int64_t)y * d.S;
                 if (!fixed0) acc[h0] += out0;
                 if (two && !fixed1) acc[h0 + 1] += out1;
             }
@@ -249,22 +271,25 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
     }
 }
 
-template <bool DIAG>
+template <bool DIAG, int ROWS>
 __global__ __launch_bounds__(kBlock) void half_sweep_kernel(const ChainDesc *__restrict__ descs,
-                                                            ChainState *__restrict__ states, int colour,
-                                                            SweepConsts sc, int or_only,
+                                                            ChainState *__restrict__ states,
+                                                            const int64_t *__restrict__ start, int n_chains,
+                                                            int colour, SweepConsts sc, int or_only,
                                                             uint8_t *__restrict__ flags)
 {
-    half_sweep_body<DIAG>(descs, states, colour, sc, or_only, flags);
+    half_sweep_body<DIAG, ROWS>(descs, states, start, n_chains, colour, sc, or_only, flags);
 }
 
 // The same sweep for the unconditional e(T, L) runs (a separate symbol so
 // that profiles tell the two workloads apart).
+template <int ROWS>
 __global__ __launch_bounds__(kBlock) void table_half_sweep_kernel(const ChainDesc *__restrict__ descs,
-                                                                  ChainState *__restrict__ states, int colour,
-                                                                  SweepConsts sc)
+                                                                  ChainState *__restrict__ states,
+                                                                  const int64_t *__restrict__ start,
+                                                                  int n_chains, int colour, SweepConsts sc)
 {
-    half_sweep_body<false>(descs, states, colour, sc, 0, nullptr);
+    half_sweep_body<false, ROWS>(descs, states, start, n_chains, colour, sc, 0, nullptr);
 }
 
 __device__ void set_derived(ChainState &st, double q)
@@ -545,9 +570,14 @@ struct mpr_ctx {
     std::string err;
     void *scratch = nullptr;          // small device scratch (partials, counters)
     unsigned int *done_host = nullptr;  // pinned
+    // sweeps run on a context-owned stream (captured into HIP graphs),
+    // ordered after and before the caller's stream with two events
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+    // tuned block shape (tile rows) by batch shape
+    std::map<std::tuple<int, int, int, int>, int> tuned_rows;
     // profiling
     bool profile = false;
-    std::vector<hipEvent_t> events;
     double prof_ms = 0.0;
     int64_t prof_launches = 0;
     // e(T, L) tables: key -> (1 + e) per temperature
@@ -602,7 +632,9 @@ bool valid_params(const mpr_params *p)
     return p && p->q > 0.0 && p->q <= 0.5 && p->R >= 1 && p->K >= 0 && p->n_f >= 1 && p->n_fit >= 2 &&
            p->n_fit <= kMaxFit && p->sg_degree >= 1 && p->sg_degree <= 4 && p->sg_degree < p->n_fit &&
            p->k_a > 0.0 && p->a_targ >= 0.0 && p->table_nT >= 2 && p->table_meas >= 1 && p->table_burn >= 0 &&
-           p->table_T_lo > 0.0 && p->table_T_hi > p->table_T_lo;
+           p->table_T_lo > 0.0 && p->table_T_hi > p->table_T_lo &&
+           (p->tile_rows == 0 || p->tile_rows == 1 || p->tile_rows == 2 || p->tile_rows == 4 || p->tile_rows == 8) &&
+           p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096;
 }
 
 bool valid_images(const mpr_image *imgs, int n)
@@ -626,6 +658,7 @@ int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     const int64_t chains = (int64_t)n * p->R;
     b += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
     b += round_up(chains * 8, 256) + round_up((int64_t)n * sizeof(ImgDev), 256) + 4096;
+    b += round_up(4 * (chains + 1) * 8, 256);
     return b;
 }
 
@@ -640,6 +673,7 @@ int64_t table_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     best += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
     best += round_up(chains * 8, 256) + round_up((int64_t)n * sizeof(ImgDev), 256) + 4096;
     best += round_up((int64_t)n * kMapBlocks * 16, 256);
+    best += round_up(4 * (chains + 1) * 8, 256);
     return best;
 }
 
@@ -721,6 +755,15 @@ SweepConsts make_sc(double q, uint64_t seed)
 
 int blocks_for(int64_t n, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, cap)); }
 
+constexpr int kRowChoices[4] = {1, 2, 4, 8};
+
+// Sweep blocks of one chain for a block shape of `rows` half-rows.
+int64_t chain_blocks(const ChainDesc &d, int rows)
+{
+    const int px = kBlock / rows;
+    return (int64_t)((d.S / 2 + px - 1) / px) * ((d.ny + rows - 1) / rows);
+}
+
 // A set of chains resident in the workspace.
 struct ChainSet {
     std::vector<ChainDesc> desc;
@@ -729,15 +772,43 @@ struct ChainSet {
     ChainDesc *d_desc = nullptr;
     ChainState *d_state = nullptr;
     int64_t *d_offset = nullptr;
-    int64_t max_blocks = 0;       // max over chains of sweep blocks
+    int64_t *d_start[4] = {nullptr, nullptr, nullptr, nullptr};  // block prefix sums per shape
+    int64_t total_blocks[4] = {0, 0, 0, 0};
 };
 
+template <int ROWS>
+void launch_half_rows(hipStream_t st, const ChainSet &cs, int v, bool table, int colour, const SweepConsts &sc)
+{
+    const int n = (int)cs.desc.size();
+    const dim3 grid((unsigned)cs.total_blocks[v]);
+    if (table)
+        hipLaunchKernelGGL(table_half_sweep_kernel<ROWS>, grid, dim3(kBlock), 0, st, cs.d_desc, cs.d_state,
+                           cs.d_start[v], n, colour, sc);
+    else
+        hipLaunchKernelGGL((half_sweep_kernel<false, ROWS>), grid, dim3(kBlock), 0, st, cs.d_desc, cs.d_state,
+                           cs.d_start[v], n, colour, sc, 0, nullptr);
+}
+
+void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colour, const SweepConsts &sc)
+{
+    switch (kRowChoices[v]) {
+        case 1: launch_half_rows<1>(st, cs, v, table, colour, sc); break;
+        case 2: launch_half_rows<2>(st, cs, v, table, colour, sc); break;
+        case 4: launch_half_rows<4>(st, cs, v, table, colour, sc); break;
+        default: launch_half_rows<8>(st, cs, v, table, colour, sc); break;
+    }
+}
+
 // Runs sweeps until every chain is done.  Returns 0 or an error code.
+// Sweeps run on ctx->gstream: a few direct sweeps per block shape first (to
+// tune it, unless fixed or cached), then groups of `spl` sweeps replayed as
+// a captured graph, checking the done-counter after each group.
 int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stream, int64_t max_sweeps,
                int poll_every, bool table)
 {
     const int n = (int)cs.desc.size();
     unsigned int *d_done = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kDoneOffset);
+    unsigned long long *d_work = reinterpret_cast<unsigned long long *>((char *)ctx->scratch + kWorkOffset);
     HIP_TRY(ctx, hipMemsetAsync(d_done, 0, sizeof(unsigned int), stream));
     unsigned int already = 0;
     for (const auto &s : cs.state)
@@ -745,46 +816,119 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     if (already == (unsigned int)n) return MPR_OK;
     const CtlParams cp = make_ctl(p);
     const SweepConsts sc = make_sc(p->q, p->seed);
-    const dim3 grid((unsigned)cs.max_blocks, (unsigned)n);
     const int cblocks = (n + 63) / 64;
-    unsigned long long *d_work = reinterpret_cast<unsigned long long *>((char *)ctx->scratch + kWorkOffset);
-    if (ctx->profile) {
-        while ((int)ctx->events.size() < 2 * poll_every) {
-            hipEvent_t ev;
-            HIP_TRY(ctx, hipEventCreate(&ev));
-            ctx->events.push_back(ev);
+    hipStream_t st = ctx->gstream;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_in, stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->ev_in, 0));
+
+    auto sweeps = [&](int v, int count) {
+        for (int i = 0; i < count; ++i) {
+            launch_half(st, cs, v, table, 0, sc);
+            launch_half(st, cs, v, table, 1, sc);
+            hipLaunchKernelGGL(control_kernel, dim3(cblocks), dim3(64), 0, st, cs.d_desc, cs.d_state, n, cp, d_done,
+                               d_work);
         }
-    }
-    for (int64_t done_sweeps = 0; done_sweeps < max_sweeps;) {
-        int j = 0;
-        for (; j < poll_every && done_sweeps < max_sweeps; ++j, ++done_sweeps) {
-            if (ctx->profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * j], stream));
-            for (int colour = 0; colour < 2; ++colour) {
-                if (table)
-                    hipLaunchKernelGGL(table_half_sweep_kernel, grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
-                                       colour, sc);
-                else
-                    hipLaunchKernelGGL(half_sweep_kernel<false>, grid, dim3(kBlock), 0, stream, cs.d_desc,
-                                       cs.d_state, colour, sc, 0, nullptr);
-            }
-            if (ctx->profile) HIP_TRY(ctx, hipEventRecord(ctx->events[2 * j + 1], stream));
-            hipLaunchKernelGGL(control_kernel, dim3(cblocks), dim3(64), 0, stream, cs.d_desc, cs.d_state, n, cp,
-                               d_done, d_work);
-        }
+    };
+    int64_t done_sweeps = 0;
+    bool finished = false;
+    // Runs `count` sweeps directly or as graph `ge`, timed; then polls.
+    auto block = [&](int v, int count, hipGraphExec_t ge, float *ms_out) -> int {
+        HIP_TRY(ctx, hipEventRecord(ctx->ev_t0, st));
+        if (ge) HIP_TRY(ctx, hipGraphLaunch(ge, st));
+        else sweeps(v, count);
         HIP_TRY(ctx, hipGetLastError());
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->done_host, d_done, sizeof(unsigned int), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        HIP_TRY(ctx, hipEventRecord(ctx->ev_t1, st));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->done_host, d_done, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        float ms = 0.0f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
+        if (ms_out) *ms_out = ms;
         if (ctx->profile) {
-            for (int k = 0; k < j; ++k) {
-                float ms = 0.0f;
-                HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
-                ctx->prof_ms += ms;
-                ctx->prof_launches += 2;
+            ctx->prof_ms += ms;
+            ctx->prof_launches += 2 * (int64_t)count;
+        }
+        done_sweeps += count;
+        finished = *ctx->done_host + already >= (unsigned int)n;
+        return MPR_OK;
+    };
+
+    // block shape: fixed, cached, or tuned on the first sweeps
+    int v = -1;
+    for (int k = 0; k < 4; ++k)
+        if (p->tile_rows == kRowChoices[k]) v = k;
+    int maxnx = 0, maxny = 0;
+    for (const auto &d : cs.desc) {
+        maxnx = std::max(maxnx, d.nx);
+        maxny = std::max(maxny, d.ny);
+    }
+    const auto key = std::make_tuple(table ? 1 : 0, n, maxnx, maxny);
+    float sweep_ms = -1.0f;
+    if (v < 0) {
+        auto it = ctx->tuned_rows.find(key);
+        if (it != ctx->tuned_rows.end()) v = it->second;
+    }
+    if (v < 0) {
+        const int ts = std::max(1, std::min(poll_every, 3));
+        float best = 0.0f;
+        int tried = 0;
+        for (int k = 0; k < 4 && !finished && done_sweeps + ts <= max_sweeps; ++k, ++tried) {
+            float ms = 0.0f;
+            int rc = block(k, ts, nullptr, &ms);
+            if (rc) return rc;
+            if (v < 0 || ms < best) {
+                best = ms;
+                v = k;
             }
         }
-        if (*ctx->done_host + already >= (unsigned int)n) return MPR_OK;
+        if (v < 0) v = 2;
+        else sweep_ms = best / (float)ts;
+        if (tried == 4) ctx->tuned_rows[key] = v;
     }
-    return fail(ctx, MPR_ERR_HIP, "chains did not finish within %lld sweeps", (long long)max_sweeps);
+    // sweeps per graph: at least about a millisecond of work per done-check
+    int spl = p->sweeps_per_launch > 0 ? p->sweeps_per_launch : poll_every;
+    if (p->sweeps_per_launch <= 0 && sweep_ms > 0.0f && (float)spl * sweep_ms < 1.0f)
+        spl = std::min(64, poll_every * (int)std::ceil(1.0f / ((float)poll_every * sweep_ms)));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t ge = nullptr;
+    if (!finished && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        sweeps(v, spl);
+        if (hipStreamEndCapture(st, &graph) != hipSuccess ||
+            hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0) != hipSuccess)
+            ge = nullptr;
+    }
+    (void)hipGetLastError();
+    int rc = MPR_OK;
+    while (!finished && done_sweeps < max_sweeps) {
+        rc = block(v, spl, ge, nullptr);
+        if (rc) break;
+    }
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_out, st));
+    HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev_out, 0));
+    if (!finished) return fail(ctx, MPR_ERR_HIP, "chains did not finish within %lld sweeps", (long long)max_sweeps);
+    return MPR_OK;
+}
+
+// Fills the per-shape block prefix sums of a chain set (in the workspace).
+int upload_starts(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream)
+{
+    const int n = (int)cs.desc.size();
+    std::vector<int64_t> h((size_t)4 * (n + 1));
+    for (int k = 0; k < 4; ++k) {
+        int64_t *sk = h.data() + (size_t)k * (n + 1);
+        sk[0] = 0;
+        for (int c = 0; c < n; ++c) sk[c + 1] = sk[c] + chain_blocks(cs.desc[c], kRowChoices[k]);
+        cs.total_blocks[k] = sk[n];
+        if (sk[n] >= ((int64_t)1 << 31)) return fail(ctx, MPR_ERR_ARG, "batch too large for one launch");
+    }
+    int64_t *d = (int64_t *)cv.take((int64_t)h.size() * 8);
+    if (!d) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+    for (int k = 0; k < 4; ++k) cs.d_start[k] = d + (size_t)k * (n + 1);
+    HIP_TRY(ctx, hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    return MPR_OK;
 }
 
 ChainState fresh_state(double T, int phase)
@@ -814,7 +958,7 @@ int upload_chains(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream, do
     HIP_TRY(ctx, hipMemcpyAsync(cs.d_desc, cs.desc.data(), n * sizeof(ChainDesc), hipMemcpyHostToDevice, stream));
     HIP_TRY(ctx, hipMemcpyAsync(cs.d_state, cs.state.data(), n * sizeof(ChainState), hipMemcpyHostToDevice, stream));
     HIP_TRY(ctx, hipMemcpyAsync(cs.d_offset, cs.offset.data(), n * 8, hipMemcpyHostToDevice, stream));
-    return MPR_OK;
+    return upload_starts(ctx, cs, cv, stream);
 }
 
 // Allocates both half-grids (and accumulators) of a chain from the workspace.
@@ -824,7 +968,6 @@ bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc)
     d.nx = nx;
     d.ny = ny;
     d.S = half_stride(nx);
-    d.nbx = (d.S / 2 + 63) / 64;
     for (int c = 0; c < 2; ++c) {
         d.h[c] = (float *)cv.take(hg);
         d.acc[c] = with_acc ? (float *)cv.take(hg) : nullptr;
@@ -900,9 +1043,12 @@ int32_t mpr_create(mpr_ctx **out, int32_t device)
     mpr_ctx *ctx = new mpr_ctx();
     ctx->device = device;
     if (hipMalloc(&ctx->scratch, kScratchBytes) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->done_host, sizeof(unsigned int), hipHostMallocDefault) != hipSuccess) {
-        if (ctx->scratch) (void)hipFree(ctx->scratch);
-        delete ctx;
+        hipHostMalloc((void **)&ctx->done_host, sizeof(unsigned int), hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&ctx->ev_t0) != hipSuccess || hipEventCreate(&ctx->ev_t1) != hipSuccess) {
+        mpr_destroy(ctx);
         return MPR_ERR_HIP;
     }
     *out = ctx;
@@ -913,7 +1059,10 @@ void mpr_destroy(mpr_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
-    for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
+    if (ctx->gstream) (void)hipStreamSynchronize(ctx->gstream);
+    for (hipEvent_t ev : {ctx->ev_in, ctx->ev_out, ctx->ev_t0, ctx->ev_t1})
+        if (ev) (void)hipEventDestroy(ev);
+    if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->done_host) (void)hipHostFree(ctx->done_host);
     delete ctx;
@@ -942,6 +1091,8 @@ void mpr_default_params(mpr_params *p)
     p->table_T_lo = 1e-5;
     p->table_T_hi = 10.0;
     p->seed = 3000;
+    p->tile_rows = 0;
+    p->sweeps_per_launch = 0;
 }
 
 int64_t mpr_workspace_size(const mpr_image *imgs, int32_t n, const mpr_params *p)
@@ -1074,7 +1225,6 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
                 cs.desc.push_back(d);
                 cs.state.push_back(fresh_state(Tg[k], PH_TABLE));
                 cs.offset.push_back(0);
-                cs.max_blocks = std::max<int64_t>(cs.max_blocks, (int64_t)d.nbx * ((d.ny + 3) / 4));
             }
             int rc = upload_chains(ctx, cs, cv, stream, p->q);
             if (rc) return rc;
@@ -1082,8 +1232,7 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
             hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), p->table_nT), dim3(kBlock), 0, stream,
                                cs.d_desc, cs.d_offset, nullptr, nullptr, nullptr, 0u, 0u, 1);
             HIP_TRY(ctx, hipGetLastError());
-            rc = run_chains(ctx, cs, p, stream, (int64_t)p->table_burn + p->table_meas, p->table_burn + p->table_meas,
-                            true);
+            rc = run_chains(ctx, cs, p, stream, (int64_t)p->table_burn + p->table_meas, 50, true);
             if (rc) return rc;
             HIP_TRY(ctx, hipMemcpyAsync(cs.state.data(), cs.d_state, cs.state.size() * sizeof(ChainState),
                                         hipMemcpyDeviceToHost, stream));
@@ -1163,7 +1312,6 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
             if (phase == PH_EQ && !p->eq_a_mode) st.a_cur = 1.0;
             cs.state.push_back(st);
             cs.offset.push_back(imgs[b].offset);
-            cs.max_blocks = std::max<int64_t>(cs.max_blocks, (int64_t)d.nbx * ((d.ny + 3) / 4));
         }
     }
     int rc = upload_chains(ctx, cs, cv, stream, p->q);
@@ -1284,7 +1432,7 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t hg = half_grid_bytes(nx, ny);
-    const int64_t bytes = 2 * round_up(hg, 256) + 4096;
+    const int64_t bytes = 2 * round_up(hg, 256) + 8192;
     void *buf = nullptr;
     HIP_TRY(ctx, hipMalloc(&buf, bytes));
     Carver cv{(char *)buf, bytes};
@@ -1315,8 +1463,8 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
                        cs.d_offset, phi, sampled, phi, 0u, 0u, 0);
     if (flags) (void)hipMemsetAsync(flags, 0, nsite, stream);
     const SweepConsts sc = make_sc(q, seed);
-    hipLaunchKernelGGL(half_sweep_kernel<true>, dim3((unsigned)(cs.desc[0].nbx * ((ny + 3) / 4)), 1), dim3(kBlock), 0,
-                       stream, cs.d_desc, cs.d_state, colour, sc, mode, flags);
+    hipLaunchKernelGGL((half_sweep_kernel<true, 4>), dim3((unsigned)cs.total_blocks[2]), dim3(kBlock), 0, stream,
+                       cs.d_desc, cs.d_state, cs.d_start[2], 1, colour, sc, mode, flags);
     hipLaunchKernelGGL(unsplit_kernel, dim3(blocks_for(nsite, 2048)), dim3(kBlock), 0, stream, cs.d_desc, phi);
     ChainState out;
     (void)hipMemcpyAsync(&out, cs.d_state, sizeof out, hipMemcpyDeviceToHost, stream);
