@@ -228,6 +228,10 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi,
 int32_t mpr_diag_energy(mpr_ctx *ctx, int32_t nx, int32_t ny, const float *phi, double q,
                         double *h_plus_ngp, void *stream);
 
+/* Plain device copy of `bytes` (multiple of 16, 16-byte aligned pointers):
+ * the known-size reference for calibrating HBM byte counters. */
+int32_t mpr_diag_copy(mpr_ctx *ctx, const void *src, void *dst, int64_t bytes, void *stream);
+
 /* The device stopping-rule slope: derivative at the newest point of the
  * degree-`degree` least-squares polynomial through e[0..n-1] (host). */
 int32_t mpr_diag_sg_slope(mpr_ctx *ctx, const double *e, int32_t n, int32_t degree,

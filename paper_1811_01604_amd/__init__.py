@@ -24,7 +24,7 @@ EXPORTS = [
     "mpr_create", "mpr_destroy", "mpr_last_error", "mpr_default_params", "mpr_workspace_size",
     "mpr_map_to_angles", "mpr_estimate_temperature", "mpr_simulate", "mpr_predict",
     "mpr_profile_enable", "mpr_profile_read",
-    "mpr_diag_philox", "mpr_diag_half_sweep", "mpr_diag_energy", "mpr_diag_sg_slope",
+    "mpr_diag_philox", "mpr_diag_half_sweep", "mpr_diag_copy", "mpr_diag_energy", "mpr_diag_sg_slope",
 ]
 
 
@@ -105,6 +105,7 @@ def _declare(L):
         "mpr_profile_read": (i32, [P, C.POINTER(Profile)]),
         "mpr_diag_philox": (i32, [P, P, u64, i64, P, P]),
         "mpr_diag_half_sweep": (i32, [P, i32, i32, P, P, i32, d, d, d, u64, u32, u32, u32, i32, P, P, P, P]),
+        "mpr_diag_copy": (i32, [P, P, P, i64, P]),
         "mpr_diag_energy": (i32, [P, i32, i32, P, d, P, P]),
         "mpr_diag_sg_slope": (i32, [P, P, i32, i32, P]),
     }
@@ -236,6 +237,10 @@ class Context:
                                                  sweep, chain, stream_id, mode, _ptr(flags), C.byref(acc),
                                                  C.byref(en), _stream(stream)))
         return (acc.value, en.value) if with_energy else acc.value
+
+    def diag_copy(self, src, dst, stream=None):
+        n = src.numel() * src.element_size()
+        self._check(self.lib.mpr_diag_copy(self._h, _ptr(src), _ptr(dst), n, _stream(stream)))
 
     def diag_energy(self, phi, q=0.5, stream=None) -> float:
         ny, nx = phi.shape

@@ -555,6 +555,13 @@ __global__ void philox_kernel(const uint32_t *__restrict__ ctr, uint32_t k0, uin
     out[4 * i + 3] = w.w;
 }
 
+// Plain copy of n 16-byte words: the calibration probe for HBM byte counters.
+__global__ void copy_probe_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 __global__ void ring_slope_kernel(const double *e, int n, CtlParams cp, double *out)
 {
     double ring[kMaxFit];
@@ -1475,6 +1482,22 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
         return fail(ctx, MPR_ERR_HIP, "diag_half_sweep: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
     if (accepted) *accepted = (int64_t)out.acc;
     if (bond_energy) *bond_energy = (double)out.e_fx * kEnergyUnit;
+    return MPR_OK;
+}
+
+int32_t mpr_diag_copy(mpr_ctx *ctx, const void *src, void *dst, int64_t bytes, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!src || !dst || bytes < 0 || bytes % 16 != 0 || ((uintptr_t)src | (uintptr_t)dst) % 16 != 0)
+        return fail(ctx, MPR_ERR_ARG, "diag_copy: invalid argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    const int64_t n = bytes / 16;
+    if (n > 0)
+        hipLaunchKernelGGL(copy_probe_kernel, dim3(blocks_for(n, 8192)), dim3(kBlock), 0, stream,
+                           (const float4 *)src, (float4 *)dst, n);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
     return MPR_OK;
 }
 
