@@ -178,6 +178,66 @@ int32_t mpr_predict(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
                     const double *zmin_zmax, int32_t M, float *z_hat, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Warm start: a residual CNN that predicts starting gap angles from the
+ * sampled ones (replacing the U(0, 2 pi) start of Algorithm 2 step 2.2;
+ * the chain then runs to the same stopping rule).  Architecture: input
+ * (cos q phi, sin q phi, 1) at sampled sites, 0 at gaps, zero-padded to 32
+ * channels; stem conv + ReLU; 8 blocks h <- h + conv(ReLU(conv(h))); head
+ * conv whose channels 0, 1 estimate (cos q phi, sin q phi).  All convs are
+ * 3x3, 32 -> 32 channels, zero padding; bfloat16 weights and activations,
+ * float accumulation on the matrix cores.
+ *
+ * Tensors: x, y, dy are NHWC bfloat16 (n x h x w x 32) device buffers;
+ * phi, target and sampled are n x h x w (target: 2 floats per site, the
+ * (cos q phi, sin q phi) to learn).  params (float, mpr_cnn_param_count())
+ * holds per layer W[tap][c_in][c_out] (tap = 3 (dy+1) + (dx+1)) then
+ * b[c_out], 18 layers (stem, 8 x 2 block convs, head); grads has the same
+ * layout.  packed (mpr_cnn_packed_bytes()) holds the bfloat16 copies the
+ * kernels read; refresh it with mpr_cnn_pack after every parameter change. */
+int64_t mpr_cnn_param_count(void);
+int64_t mpr_cnn_packed_bytes(void);
+/* Device workspace for forward (training = 0: inference, 1: keep the
+ * activations for mpr_cnn_backward) on n images of h x w; < 0 if invalid. */
+int64_t mpr_cnn_workspace_size(int32_t n, int32_t h, int32_t w, int32_t training);
+int32_t mpr_cnn_pack(mpr_ctx *ctx, const float *params, void *packed, void *stream);
+int32_t mpr_cnn_encode(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *phi,
+                       const uint8_t *sampled, void *x, void *stream);
+int32_t mpr_cnn_forward(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *params,
+                        const void *packed, const void *x, void *ws, int64_t ws_bytes,
+                        int32_t training, void *y, void *stream);
+/* Mean over the n_gaps gap sites of the squared (cos, sin) error of y's
+ * channels 0, 1 (host *loss), and its gradient dy (all 32 channels; zero at
+ * sampled sites).  ws needs 8 bytes per 256 sites. */
+int32_t mpr_cnn_loss(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void *y,
+                     const float *target, const uint8_t *sampled, int64_t n_gaps, void *dy,
+                     void *ws, int64_t ws_bytes, double *loss, void *stream);
+/* Gradients of every layer from dy, using the activations a training
+ * forward pass left in ws (same ws, same x). */
+int32_t mpr_cnn_backward(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *params,
+                         const void *packed, const void *x, const void *dy, void *ws,
+                         int64_t ws_bytes, float *grads, void *stream);
+/* One Adam step (bias-corrected; step counts from 1) on params with moment
+ * buffers m, v (float, zero-initialised by the caller). */
+int32_t mpr_cnn_opt_step(mpr_ctx *ctx, float *params, const float *grads, float *m, float *v,
+                         int64_t step, double lr, double beta1, double beta2, double eps,
+                         void *stream);
+/* Starting angles at gap sites: phi = atan2(max(s, 0), c) / q, capped below
+ * 2 pi (the gap entries of phi_init for mpr_simulate; 0 at samples). */
+int32_t mpr_cnn_decode(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void *y,
+                       const uint8_t *sampled, float *phi_init, void *stream);
+/* Diagnostics: one conv layer (wpack in the forward or dgrad layout of
+ * mpr_cnn_pack; bias, add, ref nullable: out = ReLU?(conv + bias + add),
+ * zeroed where ref <= 0), and one layer's weight and bias gradients
+ * (grads: 9*32*32 + 32 floats; gout multiplied by (gref > 0) when gref is
+ * given; ws >= 256*4*(9*32*32+32)*4 bytes). */
+int32_t mpr_cnn_diag_conv(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void *in,
+                          const void *wpack, const float *bias, const void *add, const void *ref,
+                          int32_t relu, void *out, void *stream);
+int32_t mpr_cnn_diag_wgrad(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void *in,
+                           const void *gout, const void *gref, float *grads, void *ws,
+                           int64_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Profiling.  While enabled, mpr_simulate and mpr_estimate_temperature
  * bracket every sweep's two half-sweep launches with HIP events on the
  * caller's stream, and count the work done: chain-sweeps, gap-site updates

@@ -24,6 +24,9 @@ EXPORTS = [
     "mpr_create", "mpr_destroy", "mpr_last_error", "mpr_default_params", "mpr_workspace_size",
     "mpr_map_to_angles", "mpr_estimate_temperature", "mpr_simulate", "mpr_predict",
     "mpr_profile_enable", "mpr_profile_read",
+    "mpr_cnn_param_count", "mpr_cnn_packed_bytes", "mpr_cnn_workspace_size", "mpr_cnn_pack", "mpr_cnn_encode",
+    "mpr_cnn_forward", "mpr_cnn_loss", "mpr_cnn_backward", "mpr_cnn_opt_step", "mpr_cnn_decode",
+    "mpr_cnn_diag_conv", "mpr_cnn_diag_wgrad",
     "mpr_diag_philox", "mpr_diag_half_sweep", "mpr_diag_copy", "mpr_diag_energy", "mpr_diag_sg_slope",
 ]
 
@@ -101,6 +104,18 @@ def _declare(L):
         "mpr_estimate_temperature": (i32, [P, IMG, i32, P, P, PRM, P, i64, P, P, P, P]),
         "mpr_simulate": (i32, [P, IMG, i32, P, P, P, PRM, P, P, i64, P, C.POINTER(ChainStats), P]),
         "mpr_predict": (i32, [P, IMG, i32, P, P, P, P, i32, P, P]),
+        "mpr_cnn_param_count": (i64, []),
+        "mpr_cnn_packed_bytes": (i64, []),
+        "mpr_cnn_workspace_size": (i64, [i32, i32, i32, i32]),
+        "mpr_cnn_pack": (i32, [P, P, P, P]),
+        "mpr_cnn_encode": (i32, [P, i32, i32, i32, P, P, P, P]),
+        "mpr_cnn_forward": (i32, [P, i32, i32, i32, P, P, P, P, i64, i32, P, P]),
+        "mpr_cnn_loss": (i32, [P, i32, i32, i32, P, P, P, i64, P, P, i64, P, P]),
+        "mpr_cnn_backward": (i32, [P, i32, i32, i32, P, P, P, P, P, i64, P, P]),
+        "mpr_cnn_opt_step": (i32, [P, P, P, P, P, i64, d, d, d, d, P]),
+        "mpr_cnn_decode": (i32, [P, i32, i32, i32, P, P, P, P]),
+        "mpr_cnn_diag_conv": (i32, [P, i32, i32, i32, P, P, P, P, P, i32, P, P]),
+        "mpr_cnn_diag_wgrad": (i32, [P, i32, i32, i32, P, P, P, P, P, i64, P]),
         "mpr_profile_enable": (i32, [P, i32]),
         "mpr_profile_read": (i32, [P, C.POINTER(Profile)]),
         "mpr_diag_philox": (i32, [P, P, u64, i64, P, P]),
@@ -211,6 +226,64 @@ class Context:
         zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)
         self._check(self.lib.mpr_predict(self._h, imgs, len(imgs), _ptr(z), _ptr(sampled), _ptr(phi_sum),
                                          zz.ctypes.data_as(C.c_void_p), M, _ptr(z_hat), _stream(stream)))
+
+    # -------------------------------------------------------- warm start
+    # Tensors: x, y, dy are (n, h, w, 32) bfloat16; phi, sampled (n, h, w);
+    # target (n, h, w, 2) float; params / grads / Adam moments float vectors.
+    def cnn_param_count(self) -> int:
+        return int(self.lib.mpr_cnn_param_count())
+
+    def cnn_packed_bytes(self) -> int:
+        return int(self.lib.mpr_cnn_packed_bytes())
+
+    def cnn_workspace_size(self, n, h, w, training) -> int:
+        return int(self.lib.mpr_cnn_workspace_size(n, h, w, 1 if training else 0))
+
+    def cnn_pack(self, params, packed, stream=None):
+        self._check(self.lib.mpr_cnn_pack(self._h, _ptr(params), _ptr(packed), _stream(stream)))
+
+    def cnn_encode(self, phi, sampled, x, stream=None):
+        n, h, w = phi.shape
+        self._check(self.lib.mpr_cnn_encode(self._h, n, h, w, _ptr(phi), _ptr(sampled), _ptr(x), _stream(stream)))
+
+    def cnn_forward(self, params, packed, x, ws, y, training=False, stream=None):
+        n, h, w, _ = x.shape
+        self._check(self.lib.mpr_cnn_forward(self._h, n, h, w, _ptr(params), _ptr(packed), _ptr(x), _ptr(ws),
+                                             ws.numel() * ws.element_size(), 1 if training else 0, _ptr(y),
+                                             _stream(stream)))
+
+    def cnn_loss(self, y, target, sampled, n_gaps, dy, ws, stream=None) -> float:
+        n, h, w, _ = y.shape
+        out = C.c_double()
+        self._check(self.lib.mpr_cnn_loss(self._h, n, h, w, _ptr(y), _ptr(target), _ptr(sampled), int(n_gaps),
+                                          _ptr(dy), _ptr(ws), ws.numel() * ws.element_size(), C.byref(out),
+                                          _stream(stream)))
+        return out.value
+
+    def cnn_backward(self, params, packed, x, dy, ws, grads, stream=None):
+        n, h, w, _ = x.shape
+        self._check(self.lib.mpr_cnn_backward(self._h, n, h, w, _ptr(params), _ptr(packed), _ptr(x), _ptr(dy),
+                                              _ptr(ws), ws.numel() * ws.element_size(), _ptr(grads),
+                                              _stream(stream)))
+
+    def cnn_opt_step(self, params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self._check(self.lib.mpr_cnn_opt_step(self._h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(step),
+                                              lr, beta1, beta2, eps, _stream(stream)))
+
+    def cnn_decode(self, y, sampled, phi_init, stream=None):
+        n, h, w, _ = y.shape
+        self._check(self.lib.mpr_cnn_decode(self._h, n, h, w, _ptr(y), _ptr(sampled), _ptr(phi_init),
+                                            _stream(stream)))
+
+    def cnn_diag_conv(self, x, wpack, bias, out, add=None, ref=None, relu=False, stream=None):
+        n, h, w, _ = x.shape
+        self._check(self.lib.mpr_cnn_diag_conv(self._h, n, h, w, _ptr(x), _ptr(wpack), _ptr(bias), _ptr(add),
+                                               _ptr(ref), 1 if relu else 0, _ptr(out), _stream(stream)))
+
+    def cnn_diag_wgrad(self, x, gout, grads, ws, gref=None, stream=None):
+        n, h, w, _ = x.shape
+        self._check(self.lib.mpr_cnn_diag_wgrad(self._h, n, h, w, _ptr(x), _ptr(gout), _ptr(gref), _ptr(grads),
+                                                _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
 
     # ---------------------------------------------------------- profiling
     def profile_enable(self, on=True):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpr.so")
-SOURCES = ["mpr.hip"]
+SOURCES = ["mpr.hip", "cnn.hip"]
 HEADERS = ["mpr_device.h"]
 
 HIPCC_FLAGS = [

@@ -1,0 +1,608 @@
+// Warm-start network for the MPR chains on gfx950: a residual CNN of 3x3
+// convolutions with 32 channels, bfloat16 weights and activations, float
+// accumulation on the matrix cores (v_mfma_f32_32x32x16_bf16).
+//
+// Tensors are NHWC bfloat16 with C = 32 channels (64 bytes per pixel).  A
+// conv layer's float master weights are W[tap][ci][co] (tap = 3 (dy+1) +
+// (dx+1)) followed by b[co]; they are packed to bfloat16 in two layouts:
+//   forward  F[tap][co][ci] = W[tap][ci][co]
+//   dgrad    D[tap][ci][co] = W[8 - tap][ci][co]   (input gradient = a
+//            forward conv of the output gradient with flipped taps and the
+//            channel roles swapped)
+// so that one kernel serves both; its epilogue adds the bias, an optional
+// residual tensor, and applies ReLU or the ReLU derivative (zero where a
+// reference activation is <= 0).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpr.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+constexpr int CH = 32;
+constexpr int NBLK = 8;
+constexpr int NLAYER = 2 + 2 * NBLK;
+constexpr int WSZ = 9 * CH * CH;            // weights per layer
+constexpr int LSZ = WSZ + CH;                // weights + bias per layer
+constexpr int TH = 8, TW = 32;               // output tile (rows x cols)
+constexpr int PIXS = 40;                     // staged pixel stride in bf16 (80 B)
+constexpr int IN_T = (TH + 2) * (TW + 2);    // staged input pixels
+constexpr int WG_BLOCKS = 256;               // persistent blocks of the weight-gradient kernel
+constexpr int WG_PART = WSZ + CH;            // floats per partial
+
+struct ConvArgs {
+    const bf16 *in;        // N x H x W x 32
+    const bf16 *w;         // packed [9][32 out][32 in]
+    const float *bias;     // [32] or null
+    const bf16 *add;       // residual, same shape as out, or null
+    const bf16 *ref;       // zero the output where ref <= 0, or null
+    bf16 *out;
+    int N, H, W;
+    int relu;
+};
+
+// Stages the (TH+2) x (TW+2) input pixels around an output tile into LDS,
+// zero outside the image.
+__device__ __forceinline__ void stage_tile(const bf16 *__restrict__ src, bf16 *tile, int n, int H, int W, int y0,
+                                           int x0, const bf16 *__restrict__ ref)
+{
+    for (int k = threadIdx.x; k < IN_T * 4; k += blockDim.x) {
+        const int chunk = k & 3, pix = k >> 2;
+        const int r = pix / (TW + 2), c = pix - r * (TW + 2);
+        const int gy = y0 - 1 + r, gx = x0 - 1 + c;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+            const int64_t off = (((int64_t)n * H + gy) * W + gx) * CH + chunk * 8;
+            v = *reinterpret_cast<const uint4 *>(src + off);
+            (void)ref;
+        }
+        *reinterpret_cast<uint4 *>(tile + pix * PIXS + chunk * 8) = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
+{
+    __shared__ __attribute__((aligned(16))) bf16 tile[IN_T * PIXS];
+    const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + TH - 1) / TH;
+    int b = blockIdx.x;
+    const int tx = b % tiles_x;
+    b /= tiles_x;
+    const int ty = b % tiles_y;
+    const int n = b / tiles_y;
+    const int y0 = ty * TH, x0 = tx * TW;
+    stage_tile(a.in, tile, n, a.H, a.W, y0, x0, nullptr);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, kq = lane >> 5;
+    // B operands (weights): lane holds out-channel m, in-channels kh*16 + kq*8 .. +7
+    bf16x8 wb[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int kh = 0; kh < 2; ++kh)
+            wb[t][kh] = *reinterpret_cast<const bf16x8 *>(a.w + ((t * CH + m) * CH + kh * 16 + kq * 8));
+    __syncthreads();
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        const int row = wave * 2 + mt;
+        f32x16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            // A operand: pixel (row + dy, m + dx), channels kh*16 + kq*8 .. +7
+            const bf16 *src = tile + ((row + 1 + dy) * (TW + 2) + (m + 1 + dx)) * PIXS + kq * 8;
+#pragma unroll
+            for (int kh = 0; kh < 2; ++kh) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(src + kh * 16);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, wb[t][kh], acc, 0, 0, 0);
+            }
+        }
+        // D: lane holds out-channel m for tile columns 8 (i/4) + 4 kq + (i%4)
+        const int gy = y0 + row;
+        if (gy < a.H) {
+            const float bias = a.bias ? a.bias[m] : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int gx = x0 + 8 * (i >> 2) + 4 * kq + (i & 3);
+                if (gx >= a.W) continue;
+                const int64_t idx = (((int64_t)n * a.H + gy) * a.W + gx) * CH + m;
+                float v = acc[i] + bias;
+                if (a.add) v += (float)a.add[idx];
+                if (a.relu) v = fmaxf(v, 0.0f);
+                if (a.ref && !((float)a.ref[idx] > 0.0f)) v = 0.0f;
+                a.out[idx] = (bf16)v;
+            }
+        }
+    }
+}
+
+struct WgradArgs {
+    const bf16 *in;     // layer input, N x H x W x 32
+    const bf16 *gout;   // output gradient, N x H x W x 32
+    const bf16 *gref;   // multiply gout by (gref > 0), or null
+    float *partial;     // [gridDim.x * 4][WG_PART]
+    int N, H, W;
+};
+
+// Weight and bias gradients of one conv layer: dW[tap][ci][co] = sum over
+// pixels of in(p + tap)[ci] * gout(p)[co]; db[co] = sum of gout(p)[co].
+// Persistent blocks loop over output tiles; each wave accumulates its own
+// partial sums, written out per wave and reduced in a fixed order.
+__global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(WgradArgs a)
+{
+    __shared__ __attribute__((aligned(16))) bf16 itile[IN_T * PIXS];
+    __shared__ __attribute__((aligned(16))) bf16 gtile[TH * TW * PIXS];
+    const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + TH - 1) / TH;
+    const int n_tiles = tiles_x * tiles_y * a.N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, kq = lane >> 5;
+    f32x16 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[t][i] = 0.0f;
+    float db = 0.0f;
+    for (int tile_id = blockIdx.x; tile_id < n_tiles; tile_id += gridDim.x) {
+        int b = tile_id;
+        const int tx = b % tiles_x;
+        b /= tiles_x;
+        const int ty = b % tiles_y;
+        const int n = b / tiles_y;
+        const int y0 = ty * TH, x0 = tx * TW;
+        __syncthreads();
+        stage_tile(a.in, itile, n, a.H, a.W, y0, x0, nullptr);
+        for (int k = threadIdx.x; k < TH * TW * 4; k += blockDim.x) {
+            const int chunk = k & 3, pix = k >> 2;
+            const int r = pix / TW, c = pix - r * TW;
+            const int gy = y0 + r, gx = x0 + c;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (gy < a.H && gx < a.W) {
+                const int64_t off = (((int64_t)n * a.H + gy) * a.W + gx) * CH + chunk * 8;
+                v = *reinterpret_cast<const uint4 *>(a.gout + off);
+                if (a.gref) {
+                    const uint4 rv = *reinterpret_cast<const uint4 *>(a.gref + off);
+                    const bf16 *rp = reinterpret_cast<const bf16 *>(&rv);
+                    bf16 *vp = reinterpret_cast<bf16 *>(&v);
+                    for (int j = 0; j < 8; ++j)
+                        if (!((float)rp[j] > 0.0f)) vp[j] = (bf16)0.0f;
+                }
+            }
+            *reinterpret_cast<uint4 *>(gtile + pix * PIXS + chunk * 8) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const int row = wave * 2 + mt;
+#pragma unroll
+            for (int kc = 0; kc < 2; ++kc) {
+                // B[k = pixel][n = co]: lane holds co = m, pixels kc*16 + kq*8 .. +7 of this row
+                bf16x8 bv;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    bv[i] = gtile[(row * TW + kc * 16 + kq * 8 + i) * PIXS + m];
+                    db += (float)bv[i];
+                }
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    const int dy = t / 3 - 1, dx = t % 3 - 1;
+                    // A[m = ci][k = pixel]: lane holds ci = m at the shifted pixels
+                    bf16x8 av;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        av[i] = itile[((row + 1 + dy) * (TW + 2) + kc * 16 + kq * 8 + i + 1 + dx) * PIXS + m];
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[t], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // D[m = ci][n = co]: lane holds co = m for ci = 8 (i/4) + 4 kq + (i%4)
+    float *part = a.partial + (int64_t)(blockIdx.x * 4 + wave) * WG_PART;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int ci = 8 * (i >> 2) + 4 * kq + (i & 3);
+            part[(t * CH + ci) * CH + m] = acc[t][i];
+        }
+    db += __shfl_xor(db, 32);
+    if (kq == 0) part[WSZ + m] = db;
+}
+
+// grads[j] = sum over partials p of partial[p][j], in order.
+__global__ void wgrad_reduce_kernel(const float *__restrict__ partial, int n_parts, float *__restrict__ grads)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= WG_PART) return;
+    float s = 0.0f;
+    for (int p = 0; p < n_parts; ++p) s += partial[(int64_t)p * WG_PART + j];
+    grads[j] = s;
+}
+
+// Network input: (cos q phi, sin q phi, 1) at sampled sites, zeros elsewhere.
+__global__ void encode_kernel(const float *__restrict__ phi, const uint8_t *__restrict__ sampled, int64_t npix,
+                              float q, bf16 *__restrict__ x)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    bf16 v[CH];
+    for (int c = 0; c < CH; ++c) v[c] = (bf16)0.0f;
+    if (sampled[p]) {
+        const float th = q * fabsf(phi[p]);
+        v[0] = (bf16)cosf(th);
+        v[1] = (bf16)sinf(th);
+        v[2] = (bf16)1.0f;
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(x + p * CH);
+    const uint4 *s = reinterpret_cast<const uint4 *>(v);
+    for (int k = 0; k < 4; ++k) dst[k] = s[k];
+}
+
+// Head output -> starting gap angle: atan2(max(s, 0), c) / q, below 2 pi.
+__global__ void decode_kernel(const bf16 *__restrict__ y, const uint8_t *__restrict__ sampled, int64_t npix, float q,
+                              float *__restrict__ phi)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    if (sampled[p]) {
+        phi[p] = 0.0f;
+        return;
+    }
+    const float c = (float)y[p * CH], s = (float)y[p * CH + 1];
+    const float th = atan2f(fmaxf(s, 0.0f), c);
+    phi[p] = fminf(th / q, 6.28318501f);
+}
+
+// Masked squared error on channels 0, 1 and its gradient (bf16, all channels).
+__global__ void loss_kernel(const bf16 *__restrict__ y, const float *__restrict__ target,
+                            const uint8_t *__restrict__ sampled, int64_t npix, float inv_n, bf16 *__restrict__ dy,
+                            double *__restrict__ partial)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double l = 0.0;
+    if (p < npix) {
+        bf16 g[CH];
+        for (int c = 0; c < CH; ++c) g[c] = (bf16)0.0f;
+        if (!sampled[p]) {
+            const float d0 = (float)y[p * CH] - target[2 * p];
+            const float d1 = (float)y[p * CH + 1] - target[2 * p + 1];
+            l = (double)d0 * d0 + (double)d1 * d1;
+            g[0] = (bf16)(2.0f * d0 * inv_n);
+            g[1] = (bf16)(2.0f * d1 * inv_n);
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(dy + p * CH);
+        const uint4 *s = reinterpret_cast<const uint4 *>(g);
+        for (int k = 0; k < 4; ++k) dst[k] = s[k];
+    }
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// bfloat16 packs of every layer: forward [tap][co][ci] and dgrad [tap][ci][co] (flipped taps).
+__global__ void pack_kernel(const float *__restrict__ params, bf16 *__restrict__ packed)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= NLAYER * WSZ) return;
+    const int layer = j / WSZ, r = j - layer * WSZ;
+    const int t = r / (CH * CH), rem = r - t * CH * CH;
+    const int o = rem / CH, i = rem - o * CH;
+    const float *W = params + (int64_t)layer * LSZ;
+    bf16 *F = packed + (int64_t)layer * 2 * WSZ;
+    bf16 *D = F + WSZ;
+    F[(t * CH + o) * CH + i] = (bf16)W[(t * CH + i) * CH + o];        // F[t][o][i] = W[t][i][o]
+    D[(t * CH + o) * CH + i] = (bf16)W[((8 - t) * CH + o) * CH + i];  // D[t][ci=o][co=i] = W[8-t][o][i]
+}
+
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ mo,
+                            float *__restrict__ ve, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                            float c2)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float gj = g[j];
+    const float mj = b1 * mo[j] + (1.0f - b1) * gj;
+    const float vj = b2 * ve[j] + (1.0f - b2) * gj * gj;
+    mo[j] = mj;
+    ve[j] = vj;
+    p[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+}
+
+}  // namespace
+
+// ===================================================================== host
+
+int mpr_set_error(mpr_ctx *ctx, int code, const char *msg);  // defined with the context
+
+namespace {
+
+int cfail(mpr_ctx *ctx, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return mpr_set_error(ctx, code, buf);
+}
+
+#define CHIP(ctx, expr)                                                                                  \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return cfail((ctx), MPR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t act_bytes(int n, int h, int w) { return ((int64_t)n * h * w * CH * 2 + 255) / 256 * 256; }
+
+bool shape_ok(int n, int h, int w) { return n >= 1 && h >= 1 && w >= 1 && (int64_t)n * h * w <= ((int64_t)1 << 31); }
+
+int64_t conv_blocks(int n, int h, int w) { return (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW); }
+
+void launch_conv(hipStream_t st, const bf16 *in, const bf16 *wpack, const float *bias, const bf16 *add,
+                 const bf16 *ref, int relu, bf16 *out, int n, int h, int w)
+{
+    ConvArgs a;
+    a.in = in;
+    a.w = wpack;
+    a.bias = bias;
+    a.add = add;
+    a.ref = ref;
+    a.out = out;
+    a.N = n;
+    a.H = h;
+    a.W = w;
+    a.relu = relu;
+    hipLaunchKernelGGL(conv3x3_kernel, dim3((unsigned)conv_blocks(n, h, w)), dim3(256), 0, st, a);
+}
+
+void launch_wgrad(hipStream_t st, const bf16 *in, const bf16 *gout, const bf16 *gref, float *partial, float *grads,
+                  int n, int h, int w)
+{
+    WgradArgs a;
+    a.in = in;
+    a.gout = gout;
+    a.gref = gref;
+    a.partial = partial;
+    a.N = n;
+    a.H = h;
+    a.W = w;
+    const int blocks = (int)std::min<int64_t>(WG_BLOCKS, conv_blocks(n, h, w));
+    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((WG_PART + 255) / 256), dim3(256), 0, st, partial, blocks * 4,
+                       grads);
+}
+
+// Activation buffers of a training forward pass inside the workspace.
+struct Acts {
+    bf16 *h[NBLK + 1];  // h[0] stem output, h[b+1] block b output
+    bf16 *t[NBLK];      // block b inner activation
+    bf16 *g0, *g1;      // backward scratch
+    float *partial;
+};
+
+bool carve_acts(void *ws, int64_t ws_bytes, int n, int h, int w, bool training, Acts &A)
+{
+    char *p = (char *)ws;
+    const int64_t ab = act_bytes(n, h, w);
+    int64_t used = 0;
+    auto take = [&](int64_t b) -> char * {
+        if (used + b > ws_bytes) return nullptr;
+        char *r = p + used;
+        used += (b + 255) / 256 * 256;
+        return r;
+    };
+    if (training) {
+        for (int k = 0; k <= NBLK; ++k)
+            if (!(A.h[k] = (bf16 *)take(ab))) return false;
+        for (int k = 0; k < NBLK; ++k)
+            if (!(A.t[k] = (bf16 *)take(ab))) return false;
+        if (!(A.g0 = (bf16 *)take(ab)) || !(A.g1 = (bf16 *)take(ab))) return false;
+        if (!(A.partial = (float *)take((int64_t)WG_BLOCKS * 4 * WG_PART * 4))) return false;
+    } else {
+        // inference: ping-pong h and one t
+        bf16 *b0 = (bf16 *)take(ab), *b1 = (bf16 *)take(ab), *b2 = (bf16 *)take(ab);
+        if (!b0 || !b1 || !b2) return false;
+        for (int k = 0; k <= NBLK; ++k) A.h[k] = (k & 1) ? b1 : b0;
+        for (int k = 0; k < NBLK; ++k) A.t[k] = b2;
+        A.g0 = A.g1 = nullptr;
+        A.partial = nullptr;
+    }
+    return true;
+}
+
+const bf16 *fwd_pack(const void *packed, int layer) { return (const bf16 *)packed + (int64_t)layer * 2 * WSZ; }
+const bf16 *dgrad_pack(const void *packed, int layer) { return fwd_pack(packed, layer) + WSZ; }
+const float *bias_of(const float *params, int layer) { return params + (int64_t)layer * LSZ + WSZ; }
+
+}  // namespace
+
+extern "C" {
+
+int64_t mpr_cnn_param_count(void) { return (int64_t)NLAYER * LSZ; }
+
+int64_t mpr_cnn_packed_bytes(void) { return (int64_t)NLAYER * 2 * WSZ * 2; }
+
+int64_t mpr_cnn_workspace_size(int32_t n, int32_t h, int32_t w, int32_t training)
+{
+    if (!shape_ok(n, h, w)) return -1;
+    const int64_t ab = act_bytes(n, h, w);
+    if (training) return (2 * NBLK + 3) * ab + (int64_t)WG_BLOCKS * 4 * WG_PART * 4 + 4096;
+    return 3 * ab + 4096;
+}
+
+int32_t mpr_cnn_pack(mpr_ctx *ctx, const float *params, void *packed, void *stream)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!params || !packed) return cfail(ctx, MPR_ERR_ARG, "cnn_pack: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(pack_kernel, dim3((NLAYER * WSZ + 255) / 256), dim3(256), 0, st, params, (bf16 *)packed);
+    CHIP(ctx, hipGetLastError());
+    CHIP(ctx, hipStreamSynchronize(st));
+    return MPR_OK;
+}
+
+int32_t mpr_cnn_encode(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *phi, const uint8_t *sampled,
+                       void *x, void *stream)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!shape_ok(n, h, w) || !phi || !sampled || !x) return cfail(ctx, MPR_ERR_ARG, "cnn_encode: invalid argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t np = (int64_t)n * h * w;
+    hipLaunchKernelGGL(encode_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, phi, sampled, np, 0.5f,
+                       (bf16 *)x);
+    CHIP(ctx, hipGetLastError());
+    CHIP(ctx, hipStreamSynchronize(st));
+    return MPR_OK;
+}
+
+int32_t mpr_cnn_forward(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *params, const void *packed,
+                        const void *x, void *ws, int64_t ws_bytes, int32_t training, void *y, void *stream)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!shape_ok(n, h, w) || !params || !packed || !x || !ws || !y)
+        return cfail(ctx, MPR_ERR_ARG, "cnn_forward: invalid argument");
+    if (ws_bytes < mpr_cnn_workspace_size(n, h, w, training))
+        return cfail(ctx, MPR_ERR_WORKSPACE, "cnn_forward: workspace too small");
+    Acts A;
+    if (!carve_acts(ws, ws_bytes, n, h, w, training != 0, A)) return cfail(ctx, MPR_ERR_WORKSPACE, "workspace");
+    hipStream_t st = (hipStream_t)stream;
+    launch_conv(st, (const bf16 *)x, fwd_pack(packed, 0), bias_of(params, 0), nullptr, nullptr, 1, A.h[0], n, h, w);
+    for (int b = 0; b < NBLK; ++b) {
+        launch_conv(st, A.h[b], fwd_pack(packed, 1 + 2 * b), bias_of(params, 1 + 2 * b), nullptr, nullptr, 1, A.t[b],
+                    n, h, w);
+        launch_conv(st, A.t[b], fwd_pack(packed, 2 + 2 * b), bias_of(params, 2 + 2 * b), A.h[b], nullptr, 0,
+                    A.h[b + 1], n, h, w);
+    }
+    launch_conv(st, A.h[NBLK], fwd_pack(packed, NLAYER - 1), bias_of(params, NLAYER - 1), nullptr, nullptr, 0,
+                (bf16 *)y, n, h, w);
+    CHIP(ctx, hipGetLastError());
+    CHIP(ctx, hipStreamSynchronize(st));
+    return MPR_OK;
+}
+
+int32_t mpr_cnn_loss(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void *y, const float *target,
+                     const uint8_t *sampled, int64_t n_gaps, void *dy, void *ws, int64_t ws_bytes, double *loss,
+                     void *stream)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!shape_ok(n, h, w) || !y || !target || !sampled || !dy || !loss || !ws || n_gaps < 0)
+        return cfail(ctx, MPR_ERR_ARG, "cnn_loss: invalid argument");
+    const int64_t np = (int64_t)n * h * w;
+    const unsigned blocks = (unsigned)((np + 255) / 256);
+    if (ws_bytes < (int64_t)blocks * 8) return cfail(ctx, MPR_ERR_WORKSPACE, "cnn_loss: workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    double *partial = (double *)ws;
+    hipLaunchKernelGGL(loss_kernel, dim3(blocks), dim3(256), 0, st, (const bf16 *)y, target, sampled, np,
+                       n_gaps > 0 ? 1.0f / (float)n_gaps : 0.0f, (bf16 *)dy, partial);
+    CHIP(ctx, hipGetLastError());
+    std::vector<double> hp(blocks);
+    CHIP(ctx, hipMemcpyAsync(hp.data(), partial, blocks * sizeof(double), hipMemcpyDeviceToHost, st));
+    CHIP(ctx, hipStreamSynchronize(st));
+    double s = 0.0;
+    for (double v : hp) s += v;
+    *loss = n_gaps > 0 ? s / (double)n_gaps : 0.0;
+    return MPR_OK;
+}
+
+int32_t mpr_cnn_backward(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *params, const void *packed,
+                         const void *x, const void *dy, void *ws, int64_t ws_bytes, float *grads, void *stream)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!shape_ok(n, h, w) || !params || !packed || !x || !dy || !ws || !grads)
+        return cfail(ctx, MPR_ERR_ARG, "cnn_backward: invalid argument");
+    if (ws_bytes < mpr_cnn_workspace_size(n, h, w, 1))
+        return cfail(ctx, MPR_ERR_WORKSPACE, "cnn_backward: workspace too small");
+    Acts A;
+    if (!carve_acts(ws, ws_bytes, n, h, w, true, A)) return cfail(ctx, MPR_ERR_WORKSPACE, "workspace");
+    hipStream_t st = (hipStream_t)stream;
+    const bf16 *g = (const bf16 *)dy;
+    float *G = grads;
+    // head
+    launch_wgrad(st, A.h[NBLK], g, nullptr, A.partial, G + (int64_t)(NLAYER - 1) * LSZ, n, h, w);
+    bf16 *dh = A.g0, *dt = A.g1;
+    launch_conv(st, g, dgrad_pack(packed, NLAYER - 1), nullptr, nullptr, nullptr, 0, dh, n, h, w);
+    for (int b = NBLK - 1; b >= 0; --b) {
+        const int l2 = 2 + 2 * b, l1 = 1 + 2 * b;
+        launch_wgrad(st, A.t[b], dh, nullptr, A.partial, G + (int64_t)l2 * LSZ, n, h, w);
+        launch_conv(st, dh, dgrad_pack(packed, l2), nullptr, nullptr, A.t[b], 0, dt, n, h, w);
+        launch_wgrad(st, A.h[b], dt, nullptr, A.partial, G + (int64_t)l1 * LSZ, n, h, w);
+        // dh <- dh + dgrad(dt) (in place: each output reads only its own dh entry)
+        launch_conv(st, dt, dgrad_pack(packed, l1), nullptr, dh, nullptr, 0, dh, n, h, w);
+    }
+    // stem: gradient through its ReLU applied while staging
+    launch_wgrad(st, (const bf16 *)x, dh, A.h[0], A.partial, G, n, h, w);
+    CHIP(ctx, hipGetLastError());
+    CHIP(ctx, hipStreamSynchronize(st));
+    return MPR_OK;
+}
+
+int32_t mpr_cnn_opt_step(mpr_ctx *ctx, float *params, const float *grads, float *m, float *v, int64_t step,
+                         double lr, double beta1, double beta2, double eps, void *stream)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!params || !grads || !m || !v || step < 1) return cfail(ctx, MPR_ERR_ARG, "cnn_opt_step: invalid argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = mpr_cnn_param_count();
+    const float c1 = (float)(1.0 - std::pow(beta1, (double)step));
+    const float c2 = (float)(1.0 - std::pow(beta2, (double)step));
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, params, grads, m, v, n,
+                       (float)lr, (float)beta1, (float)beta2, (float)eps, c1, c2);
+    CHIP(ctx, hipGetLastError());
+    CHIP(ctx, hipStreamSynchronize(st));
+    return MPR_OK;
+}
+
+int32_t mpr_cnn_decode(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void *y, const uint8_t *sampled,
+                       float *phi_init, void *stream)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!shape_ok(n, h, w) || !y || !sampled || !phi_init) return cfail(ctx, MPR_ERR_ARG, "cnn_decode: invalid argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t np = (int64_t)n * h * w;
+    hipLaunchKernelGGL(decode_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, (const bf16 *)y, sampled,
+                       np, 0.5f, phi_init);
+    CHIP(ctx, hipGetLastError());
+    CHIP(ctx, hipStreamSynchronize(st));
+    return MPR_OK;
+}
+
+int32_t mpr_cnn_diag_conv(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void *in, const void *wpack,
+                          const float *bias, const void *add, const void *ref, int32_t relu, void *out, void *stream)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!shape_ok(n, h, w) || !in || !wpack || !out) return cfail(ctx, MPR_ERR_ARG, "cnn_diag_conv: invalid argument");
+    hipStream_t st = (hipStream_t)stream;
+    launch_conv(st, (const bf16 *)in, (const bf16 *)wpack, bias, (const bf16 *)add, (const bf16 *)ref, relu,
+                (bf16 *)out, n, h, w);
+    CHIP(ctx, hipGetLastError());
+    CHIP(ctx, hipStreamSynchronize(st));
+    return MPR_OK;
+}
+
+int32_t mpr_cnn_diag_wgrad(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void *in, const void *gout,
+                           const void *gref, float *grads, void *ws, int64_t ws_bytes, void *stream)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!shape_ok(n, h, w) || !in || !gout || !grads || !ws) return cfail(ctx, MPR_ERR_ARG, "cnn_diag_wgrad: invalid argument");
+    if (ws_bytes < (int64_t)WG_BLOCKS * 4 * WG_PART * 4) return cfail(ctx, MPR_ERR_WORKSPACE, "cnn_diag_wgrad: workspace");
+    hipStream_t st = (hipStream_t)stream;
+    launch_wgrad(st, (const bf16 *)in, (const bf16 *)gout, (const bf16 *)gref, (float *)ws, grads, n, h, w);
+    CHIP(ctx, hipGetLastError());
+    CHIP(ctx, hipStreamSynchronize(st));
+    return MPR_OK;
+}
+
+}  // extern "C"

@@ -593,6 +593,13 @@ struct mpr_ctx {
         tables;
 };
 
+// Records an error text on the context (also used by the network kernels' host code).
+int mpr_set_error(mpr_ctx *ctx, int code, const char *msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
 namespace {
 
 int fail(mpr_ctx *ctx, int code, const char *fmt, ...)
