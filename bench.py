@@ -10,8 +10,10 @@ random) and resident on the GPU before timing starts.
 
 Prints one JSON line: site-updates/s (gap-site updates summed over chains and
 sweeps, divided by wall time), the roofline of the half-sweep kernel (useful
-bytes per launch over its event-timed duration, against 8 TB/s HBM), and the
-FP64 oracle's rate on a bounded sample of the same workload on this host.
+bytes per launch over its event-timed duration, against 8 TB/s HBM), the
+time to fill at equal MAE with the learned warm start against the plain
+random start (L=2048, random and cloud masks), and the FP64 oracle's rate on
+a bounded sample of the same workload on this host.
 """
 from __future__ import annotations
 
@@ -101,6 +103,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB plain copy first (calibrates HBM byte counters)")
+    ap.add_argument("--warm-seeds", type=int, default=8,
+                    help="images per mask type for the warm-start comparison at L=2048 (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sweep has no multi-GPU path "
@@ -200,6 +204,23 @@ def main():
             "sweep_kernel_time_share": prof["sweep_kernel_ms"] * 1e-3 / dt,
         },
     }
+    if args.warm_seeds > 0:
+        from paper_1811_01604_amd import warmstart
+        if os.path.exists(warmstart.DEFAULT_WEIGHTS):
+            log("warm start vs plain start at L=2048")
+            params, info = warmstart.load()
+            model = warmstart.WarmStart(ctx, params)
+            ws_summary = warmstart.evaluate(ctx, model, size=2048, seeds=args.warm_seeds)
+            out["warm_start"] = {
+                "workload": "Gaussian Matern nu=1.5 kappa=0.05 N(50,10); 2048x2048; 50% random and 50% cloud "
+                            "gaps; M=100 as one chain (R=1, K=100); T_hat shared; time = network inference "
+                            "(warm) + simulate + predict",
+                "network": f"8-block residual CNN, 32 channels, bf16 MFMA; trained on {info['samples']} "
+                           f"library simulations of {info['size']}^2 images",
+                **ws_summary,
+            }
+        else:
+            out["warm_start"] = None
     ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -76,6 +76,13 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        # torch ships its own HIP runtime with the same soname as the one the
+        # library links; loading torch first makes the process use exactly
+        # one runtime (the library then binds to torch's copy).
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         from . import build as _build
         try:
