@@ -89,6 +89,38 @@ def cpu_baseline(im, T: float, sweeps: int, seed: int) -> dict:
                       f"single thread, {dt:.1f} s"}
 
 
+def cnn_inference(ctx, model, size: int = 2048, reps: int = 5) -> dict:
+    """Event-timed warm-start network inference on one size x size image.
+    Algorithmic HBM bytes per pixel: each of the 18 convolutions reads its
+    32-channel bf16 input and writes its output (2 x 64 B), and the 8
+    residual convolutions also read the skip tensor (64 B): 2816 B; flops per
+    pixel: 18 x 2 x 9 x 32 x 32."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(5)
+    phi = torch.from_numpy(rng.uniform(0, 2 * np.pi, size=(1, size, size)).astype(np.float32)).cuda()
+    sm = torch.from_numpy((rng.random((1, size, size)) < 0.5).astype(np.uint8)).cuda()
+    x = torch.empty((1, size, size, 32), dtype=torch.bfloat16, device="cuda")
+    y = torch.empty_like(x)
+    ws = torch.empty(ctx.cnn_workspace_size(1, size, size, False), dtype=torch.uint8, device="cuda")
+    ctx.cnn_encode(phi, sm, x)
+    ms = []
+    for i in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.cnn_forward(model.p, model.packed, x, ws, y, training=False)
+        e1.record()
+        torch.cuda.synchronize()
+        if i:
+            ms.append(e0.elapsed_time(e1))
+    t = float(np.median(ms)) * 1e-3
+    px = size * size
+    nbytes, flops = 2816.0 * px, 18 * 2 * 9 * 32 * 32 * float(px)
+    return {"image": f"{size}x{size}", "forward_ms": t * 1e3, "bound": "hbm", "achieved": nbytes / t / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_forward": nbytes, "tflops": flops / t / 1e12, "bf16_mfma_peak_tflops": 2500.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,7 +231,8 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, prm.R),
-            "kernel": "half_sweep_kernel",
+            "kernel": ("half_sweep_compact_kernel" if prof["last_tile"] & mpr.TILE_COMPACT else "half_sweep_kernel"),
+            "tile_rows": prof["last_tile"] & 0xFF,
             "launch_ms": launch_ms, "useful_bytes_per_launch": bytes_per_launch,
             "sweep_kernel_time_share": prof["sweep_kernel_ms"] * 1e-3 / dt,
         },
@@ -210,6 +243,9 @@ def main():
             log("warm start vs plain start at L=2048")
             params, info = warmstart.load()
             model = warmstart.WarmStart(ctx, params)
+            cnn = cnn_inference(ctx, model)
+            log(f"  network inference 2048^2: {cnn['forward_ms']:.2f} ms, {cnn['achieved']:.0f} GB/s, "
+                f"{cnn['tflops']:.0f} TFLOP/s")
             ws_summary = warmstart.evaluate(ctx, model, size=2048, seeds=args.warm_seeds)
             out["warm_start"] = {
                 "workload": "Gaussian Matern nu=1.5 kappa=0.05 N(50,10); 2048x2048; 50% random and 50% cloud "
@@ -218,6 +254,7 @@ def main():
                 "network": f"8-block residual CNN, 32 channels, bf16 MFMA; trained on {info['samples']} "
                            f"library simulations of {info['size']}^2 images",
                 **ws_summary,
+                "inference_roofline": cnn,
             }
         else:
             out["warm_start"] = None

@@ -45,6 +45,10 @@ enum {
     MPR_ERR_HIP = 4          /* a HIP runtime call failed */
 };
 
+/* Flag of mpr_params.tile_rows (and the tile argument of
+ * mpr_diag_half_sweep): the compacted sweep shape. */
+#define MPR_TILE_COMPACT 0x100
+
 typedef struct mpr_ctx mpr_ctx;
 
 /* One image of a (possibly ragged) batch. */
@@ -61,7 +65,8 @@ typedef struct {
  * leaves the defaults to earlier work; mpr_default_params fills the values
  * this library uses. */
 typedef struct {
-    double q;             /* coupling exponent, 1/2 (Section 2.2) */
+    double q;             /* coupling exponent; must be 1/2 (Section 2.2), other
+                             values are rejected with MPR_ERR_ARG */
     int32_t R;            /* independent chains per image */
     int32_t K;            /* equilibrium states per chain; M = R * K realizations */
     int32_t n_f;          /* slope checked every n_f sweeps ... */
@@ -80,7 +85,9 @@ typedef struct {
     int32_t table_burn;
     int32_t table_meas;
     int32_t tile_rows;    /* sweep block shape: 1, 2, 4 or 8 half-rows x (256 / rows)
-                             site pairs; 0 = autotune (results do not depend on it) */
+                             site pairs, or 2, 4 or 8 half-rows | MPR_TILE_COMPACT for
+                             (1024 / rows) sites with the gap sites compacted onto
+                             lanes; 0 = autotune (results do not depend on it) */
     double table_T_lo, table_T_hi;
     uint64_t seed;        /* Philox key */
     int32_t sweeps_per_launch;  /* sweeps per captured graph between done-checks;
@@ -250,6 +257,9 @@ typedef struct {
     int64_t chain_sweeps;     /* sweeps summed over chains that were active */
     int64_t site_updates;     /* gap-site updates summed over those sweeps */
     double useful_bytes;      /* sum of (4 nx ny + 4 P) over those sweeps */
+    int32_t last_tile;        /* block shape of the last simulation's sweeps, as
+                                 mpr_params.tile_rows (rows | MPR_TILE_COMPACT) */
+    int32_t reserved;
 } mpr_profile;
 
 int32_t mpr_profile_enable(mpr_ctx *ctx, int32_t on);
@@ -268,6 +278,8 @@ int32_t mpr_diag_philox(mpr_ctx *ctx, const uint32_t *ctr, uint64_t seed, int64_
  * colour = (x + y) & 1) of an nx x ny grid in place.
  *   phi (dev, float, in/out), sampled (dev, uint8)
  *   mode 0: full hybrid update; 1: over-relaxation only
+ *   tile: block shape as mpr_params.tile_rows (0 = 4 half-rows, plain);
+ *         every shape gives the same results
  *   flags (dev, uint8, out, nullable): per site bit 0 = reflection kept the
  *         spin, bit 1 = proposal accepted, bit 2 = proposal wrapped,
  *         bit 3 = site updated, bit 4 = decided by the double-precision path
@@ -279,7 +291,7 @@ int32_t mpr_diag_philox(mpr_ctx *ctx, const uint32_t *ctr, uint64_t seed, int64_
 int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi,
                             const uint8_t *sampled, int32_t colour, double T, double a,
                             double q, uint64_t seed, uint32_t sweep, uint32_t chain,
-                            uint32_t stream_id, int32_t mode, uint8_t *flags,
+                            uint32_t stream_id, int32_t mode, int32_t tile, uint8_t *flags,
                             int64_t *accepted, double *bond_energy, void *stream);
 
 /* H + N_GP of an nx x ny grid of angles (dev, float) as the simulation

@@ -60,7 +60,8 @@ class Params(C.Structure):
 
 class Profile(C.Structure):
     _fields_ = [("sweep_kernel_ms", C.c_double), ("sweep_launches", C.c_int64),
-                ("chain_sweeps", C.c_int64), ("site_updates", C.c_int64), ("useful_bytes", C.c_double)]
+                ("chain_sweeps", C.c_int64), ("site_updates", C.c_int64), ("useful_bytes", C.c_double),
+                ("last_tile", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ChainStats(C.Structure):
@@ -98,6 +99,9 @@ def load(path: str = LIB_PATH):
     return lib
 
 
+TILE_COMPACT = 0x100  # Params.tile_rows flag: the compacted sweep shape
+
+
 def _declare(L):
     P, i32, i64, u32, u64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
     IMG, PRM = C.POINTER(Image), C.POINTER(Params)
@@ -126,7 +130,7 @@ def _declare(L):
         "mpr_profile_enable": (i32, [P, i32]),
         "mpr_profile_read": (i32, [P, C.POINTER(Profile)]),
         "mpr_diag_philox": (i32, [P, P, u64, i64, P, P]),
-        "mpr_diag_half_sweep": (i32, [P, i32, i32, P, P, i32, d, d, d, u64, u32, u32, u32, i32, P, P, P, P]),
+        "mpr_diag_half_sweep": (i32, [P, i32, i32, P, P, i32, d, d, d, u64, u32, u32, u32, i32, i32, P, P, P, P]),
         "mpr_diag_copy": (i32, [P, P, P, i64, P]),
         "mpr_diag_energy": (i32, [P, i32, i32, P, d, P, P]),
         "mpr_diag_sg_slope": (i32, [P, P, i32, i32, P]),
@@ -307,15 +311,16 @@ class Context:
                                              _stream(stream)))
 
     def diag_half_sweep(self, phi, sampled, colour, T, a, sweep, chain=0, stream_id=0, seed=3000, q=0.5,
-                        mode=0, flags=None, stream=None, with_energy=False):
+                        mode=0, flags=None, stream=None, with_energy=False, tile=0):
         """One half-sweep in place; returns the accepted count (and the fused
-        bond-energy sum H + N_GP when with_energy)."""
+        bond-energy sum H + N_GP when with_energy).  tile: block shape as
+        Params.tile_rows (0 = default)."""
         ny, nx = phi.shape
         acc = C.c_int64()
         en = C.c_double()
         self._check(self.lib.mpr_diag_half_sweep(self._h, nx, ny, _ptr(phi), _ptr(sampled), colour, T, a, q, seed,
-                                                 sweep, chain, stream_id, mode, _ptr(flags), C.byref(acc),
-                                                 C.byref(en), _stream(stream)))
+                                                 sweep, chain, stream_id, mode, int(tile), _ptr(flags),
+                                                 C.byref(acc), C.byref(en), _stream(stream)))
         return (acc.value, en.value) if with_energy else acc.value
 
     def diag_copy(self, src, dst, stream=None):

@@ -188,20 +188,9 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
             // site h0: left oL, right oM, up, down; site h0 + 1: left oM, right oR
             const uint32_t val0 = (vL ? 1u : 0u) | (vM ? 2u : 0u) | (vU ? 4u : 0u) | (vD ? 8u : 0u);
             const uint32_t val1 = 1u | (vR ? 2u : 0u) | (vU ? 4u : 0u) | (vD ? 8u : 0u);
-            SiteOut o0, o1;
             bool n0 = true, n1 = true;
-            if (sc.half) {
-                o0 = update_site(a0, oL, oM, up.x, dn.x, val0, u0, r0, inv_T, dscale, or_only != 0, &n0);
-                o1 = update_site(a1, oM, oR, up.y, dn.y, val1, u1, r1, inv_T, dscale, or_only != 0, &n1);
-            } else {
-                const float nb0[4] = {oL, oM, up.x, dn.x}, nb1[4] = {oM, oR, up.y, dn.y};
-                o0.phi = a0;
-                o0.e_bonds = o0.e_before = site_energy(a0, nb0, val0, sc.q);
-                o0.flags = 0u;
-                o1.phi = a1;
-                o1.e_bonds = o1.e_before = site_energy(a1, nb1, val1, sc.q);
-                o1.flags = 0u;
-            }
+            SiteOut o0 = update_site(a0, oL, oM, up.x, dn.x, val0, u0, r0, inv_T, dscale, or_only != 0, &n0);
+            SiteOut o1 = update_site(a1, oM, oR, up.y, dn.y, val1, u1, r1, inv_T, dscale, or_only != 0, &n1);
             n0 = n0 && !fixed0;
             n1 = n1 && !fixed1;
             if (n0 || n1) {
@@ -231,7 +220,7 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
                 if (two && !fixed1) acc[h0 + 1] += out1;
             }
             const uint32_t f0 = fixed0 ? 0u : o0.flags, f1 = fixed1 ? 0u : o1.flags;
-            acc_thread = ((f0 >> 1) & 1u) + ((f1 >> 1) & 1u);
+            acc_thread = (!fixed0 && o0.accepted ? 1u : 0u) + (!fixed1 && o1.accepted ? 1u : 0u);
             // a sampled site's bonds are unchanged by this half-sweep
             if (want_energy)
                 e_thread = energy_fx(fixed0 ? o0.e_before : o0.e_bonds) +
@@ -290,6 +279,223 @@ __global__ __launch_bounds__(kBlock) void table_half_sweep_kernel(const ChainDes
                                                                   int n_chains, int colour, SweepConsts sc)
 {
     half_sweep_body<false, ROWS>(descs, states, start, n_chains, colour, sc, 0, nullptr);
+}
+
+// The same half-sweep with the gap sites compacted onto consecutive lanes
+// (q = 1/2 only).  A block covers CR half-rows x (1024 / CR) sites, two
+// site pairs per thread.  Pass 1 (one lane per pair) reads the pairs, draws
+// the pair's Philox words and lists the block's gap sites in site order in
+// LDS (wave ballots + a prefix over the block's waves); pass 2 runs the
+// update for the listed sites, 256 at a time, so sampled sites cost no
+// update lanes; pass 3 gives sampled sites of colour 1 their bond energies
+// when the sweep's energy is wanted.  Every site gets the arithmetic of the
+// plain kernel, so the results are bit-identical to it.
+constexpr int kCompactSites = 4 * kBlock;
+
+template <bool DIAG, int CR>
+__device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restrict__ descs,
+                                                        ChainState *__restrict__ states,
+                                                        const int64_t *__restrict__ start, int n_chains,
+                                                        int colour, SweepConsts sc, int or_only,
+                                                        uint8_t *__restrict__ flags)
+{
+    constexpr int PPR = kCompactSites / CR / 2;  // site pairs per block row
+    constexpr int NW = kBlock / 64;
+    // list entry: Philox words for u and r (top 24 bits each) and the site's
+    // index in the block (10 bits: low 8 in the u word, high 2 in the r word)
+    __shared__ uint2 gap_list[kCompactSites];
+    __shared__ uint16_t fixed_list[kCompactSites];
+    __shared__ uint32_t wave_count[2][2][NW];  // [list][pair of the thread][wave]
+    __shared__ uint32_t red[2][NW];
+
+    const int c = find_chain(start, n_chains, (int64_t)blockIdx.x);
+    ChainState *stp = states + c;
+    const int phase = stp->phase;
+    if (phase == PH_DONE) return;
+    const ChainDesc d = descs[c];
+    const int lb = (int)((int64_t)blockIdx.x - start[c]);
+    const int nbx = ((d.S >> 1) + PPR - 1) / PPR;
+    const int by = lb / nbx;
+    const int bx = lb - by * nbx;
+    const uint32_t sweep = stp->sweep;
+    const float inv_T = stp->inv_T, dscale = stp->dscale;
+    const double T64 = stp->T, a64 = stp->a_cur;
+    const bool want_energy = (colour == 1) && (phase != PH_EQ);
+    const bool want_acc = phase != PH_EQ;
+    float *const mine_base = colour ? d.h[1] : d.h[0];
+    const float *const oth_base = colour ? d.h[0] : d.h[1];
+    float *const acc_base = (phase == PH_EQ) ? (colour ? d.acc[1] : d.acc[0]) : nullptr;
+
+    // pass 1: pairs t and t + 256 of the block
+    bool gap[2][2], fix[2][2];
+    uint32_t wu[2][2], wr[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int pi = (int)threadIdx.x + j * kBlock;
+        const int y = by * CR + pi / PPR;
+        const int h0 = 2 * (bx * PPR + pi % PPR);
+        gap[j][0] = gap[j][1] = fix[j][0] = fix[j][1] = false;
+        wu[j][0] = wu[j][1] = wr[j][0] = wr[j][1] = 0u;
+        if (y < d.ny) {
+            const int s = (y + colour) & 1;
+            const int W = (d.nx - s + 1) >> 1;
+            if (h0 < W) {
+                const bool two = (h0 + 1) < W;
+                const float2 v = *reinterpret_cast<const float2 *>(mine_base + (int64_t)y * d.S + h0);
+                gap[j][0] = !is_fixed(v.x);
+                gap[j][1] = two && !is_fixed(v.y);
+                fix[j][0] = want_energy && !gap[j][0];
+                fix[j][1] = want_energy && two && !gap[j][1];
+                if (!or_only && (gap[j][0] || gap[j][1])) {
+                    const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * h0 + s), sweep, d.chain,
+                                    d.image_id};
+                    const U4 w = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
+                    wu[j][0] = w.x;
+                    wr[j][0] = w.y;
+                    wu[j][1] = w.z;
+                    wr[j][1] = w.w;
+                }
+            }
+        }
+    }
+    // positions in the two lists: pair j = 0 of every thread first, then j = 1
+    const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t pre[2][2];
+#pragma unroll
+    for (int L = 0; L < 2; ++L)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint64_t b0 = __ballot(L ? fix[j][0] : gap[j][0]);
+            const uint64_t b1 = __ballot(L ? fix[j][1] : gap[j][1]);
+            pre[L][j] = (uint32_t)(__popcll(b0 & below) + __popcll(b1 & below));
+            if (lane == 0) wave_count[L][j][wid] = (uint32_t)(__popcll(b0) + __popcll(b1));
+        }
+    __syncthreads();
+    int n_list[2];
+#pragma unroll
+    for (int L = 0; L < 2; ++L) {
+        uint32_t base0 = 0u, base1 = 0u, tot0 = 0u, tot1 = 0u;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c0 = wave_count[L][0][w], c1 = wave_count[L][1][w];
+            base0 += (w < wid) ? c0 : 0u;
+            base1 += (w < wid) ? c1 : 0u;
+            tot0 += c0;
+            tot1 += c1;
+        }
+        n_list[L] = (int)(tot0 + tot1);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            uint32_t pos = (j ? tot0 + base1 : base0) + pre[L][j];
+            const uint32_t pi = threadIdx.x + (uint32_t)j * kBlock;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const uint32_t idx = 2u * pi + (uint32_t)k;
+                if (L == 0 && gap[j][k]) {
+                    gap_list[pos] = make_uint2((wu[j][k] & 0xFFFFFF00u) | (idx & 0xFFu),
+                                               (wr[j][k] & 0xFFFFFF00u) | (idx >> 8));
+                    ++pos;
+                }
+                if (L == 1 && fix[j][k]) {
+                    fixed_list[pos] = (uint16_t)idx;
+                    ++pos;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // site of a list index: row, half-row position, colour offset, valid neighbours
+    auto locate = [&](uint32_t idx, int &y, int &h, int &s, uint32_t &valid) {
+        const int pi = (int)(idx >> 1);
+        y = by * CR + pi / PPR;
+        h = 2 * (bx * PPR + pi % PPR) + (int)(idx & 1u);
+        s = (y + colour) & 1;
+        const int Wo = (d.nx + s) >> 1;
+        valid = (h + s - 1 >= 0 ? 1u : 0u) | (h + s < Wo ? 2u : 0u) | (y > 0 ? 4u : 0u) | (y + 1 < d.ny ? 8u : 0u);
+    };
+    auto neighbours = [&](int y, int h, int s, uint32_t valid, float &nL, float &nR, float &nU, float &nD) {
+        const float *orow = oth_base + (int64_t)y * d.S;
+        nL = (valid & 1u) ? angle_of(orow[h + s - 1]) : 0.0f;
+        nR = (valid & 2u) ? angle_of(orow[h + s]) : 0.0f;
+        nU = (valid & 4u) ? angle_of(orow[h - d.S]) : 0.0f;
+        nD = (valid & 8u) ? angle_of(orow[h + d.S]) : 0.0f;
+    };
+
+    // a thread sees at most 5 sites (4 gap sites), each below 2^30 in energy units
+    uint64_t e_thread = 0u;
+    uint32_t acc_thread = 0u;
+    // pass 2: the listed gap sites
+    for (int i = (int)threadIdx.x; i < n_list[0]; i += kBlock) {
+        const uint2 e = gap_list[i];
+        const uint32_t idx = (e.x & 0xFFu) | ((e.y & 0xFFu) << 8);
+        int y, h, s;
+        uint32_t valid;
+        locate(idx, y, h, s, valid);
+        float nL, nR, nU, nD;
+        neighbours(y, h, s, valid, nL, nR, nU, nD);
+        float *mp = mine_base + (int64_t)y * d.S + h;
+        const float a = angle_of(*mp);
+        // the low 8 bits of each word hold the index; unit24 uses the top 24
+        const float u = or_only ? 0.5f : unit24(e.x);
+        const float r = or_only ? 0.5f : unit24(e.y);
+        bool n64 = true;
+        SiteOut o = update_site(a, nL, nR, nU, nD, valid, u, r, inv_T, dscale, or_only != 0, &n64);
+        if (n64)
+            o = update_site_fp64((double)a, nL, nR, nU, nD, valid, (double)u, (double)r, a64, T64, sc.q64,
+                                 or_only != 0);
+        *mp = o.phi;
+        if (acc_base) acc_base[(int64_t)y * d.S + h] += o.phi;
+        acc_thread += o.accepted ? 1u : 0u;
+        if (want_energy) e_thread += energy_fx(o.e_bonds);
+        if (DIAG && flags) flags[(int64_t)y * d.nx + 2 * h + s] = (uint8_t)o.flags;
+    }
+    // pass 3: bond energies of the sampled sites of colour 1
+    for (int i = (int)threadIdx.x; i < n_list[1]; i += kBlock) {
+        int y, h, s;
+        uint32_t valid;
+        locate((uint32_t)fixed_list[i], y, h, s, valid);
+        float nL, nR, nU, nD;
+        neighbours(y, h, s, valid, nL, nR, nU, nD);
+        const float a = angle_of(mine_base[(int64_t)y * d.S + h]);
+        e_thread += energy_fx(bond_energy_half(0.5f * a, nL, nR, nU, nD, valid));
+    }
+    if (!want_acc) return;
+    // wave sums without carries: 64 x 16-bit low parts stay below 2^22, the
+    // accepted count (<= 256 per wave) takes bits 22-31, the high parts
+    // (< 2^19 per lane) sum in their own word
+    uint32_t lo = (uint32_t)(e_thread & 0xFFFFu) | (acc_thread << 22);
+    uint32_t hi = (uint32_t)(e_thread >> 16);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo += __shfl_xor(lo, off);
+        hi += __shfl_xor(hi, off);
+    }
+    if (lane == 0) {
+        red[0][wid] = lo;
+        red[1][wid] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long e = 0ull, a = 0ull;
+        for (int i = 0; i < NW; ++i) {
+            e += ((unsigned long long)red[1][i] << 16) + (red[0][i] & 0x3FFFFFu);
+            a += red[0][i] >> 22;
+        }
+        if (e) atomicAdd(&stp->e_fx, e);
+        if (a) atomicAdd(&stp->acc, a);
+    }
+}
+
+template <bool DIAG, int CR>
+__global__ __launch_bounds__(kBlock) void half_sweep_compact_kernel(const ChainDesc *__restrict__ descs,
+                                                                    ChainState *__restrict__ states,
+                                                                    const int64_t *__restrict__ start,
+                                                                    int n_chains, int colour, SweepConsts sc,
+                                                                    int or_only, uint8_t *__restrict__ flags)
+{
+    half_sweep_compact_body<DIAG, CR>(descs, states, start, n_chains, colour, sc, or_only, flags);
 }
 
 __device__ void set_derived(ChainState &st, double q)
@@ -587,6 +793,7 @@ struct mpr_ctx {
     bool profile = false;
     double prof_ms = 0.0;
     int64_t prof_launches = 0;
+    int32_t last_tile = 0;
     // e(T, L) tables: key -> (1 + e) per temperature
     std::map<std::tuple<int, int, double, int, double, double, int, int, double, double, uint64_t>,
              std::vector<double>>
@@ -641,13 +848,33 @@ struct Carver {
     }
 };
 
+// Sweep block shapes: half-rows per block, and whether gap sites are
+// compacted onto lanes (1024 sites per block) or not (512 sites per block).
+struct Shape {
+    int rows;
+    bool compact;
+};
+constexpr int kNumShapes = 7;
+constexpr int kNumPlainShapes = 4;
+constexpr Shape kShapes[kNumShapes] = {{1, false}, {2, false}, {4, false}, {8, false},
+                                       {2, true},  {4, true},  {8, true}};
+constexpr int kDefaultShape = 2;  // plain, 4 half-rows
+
+// Shape index of a tile_rows value (rows | MPR_TILE_COMPACT), or -1.
+int shape_of(int tile)
+{
+    for (int k = 0; k < kNumShapes; ++k)
+        if (tile == (kShapes[k].rows | (kShapes[k].compact ? MPR_TILE_COMPACT : 0))) return k;
+    return -1;
+}
+
 bool valid_params(const mpr_params *p)
 {
-    return p && p->q > 0.0 && p->q <= 0.5 && p->R >= 1 && p->K >= 0 && p->n_f >= 1 && p->n_fit >= 2 &&
+    return p && p->q == 0.5 && p->R >= 1 && p->K >= 0 && p->n_f >= 1 && p->n_fit >= 2 &&
            p->n_fit <= kMaxFit && p->sg_degree >= 1 && p->sg_degree <= 4 && p->sg_degree < p->n_fit &&
            p->k_a > 0.0 && p->a_targ >= 0.0 && p->table_nT >= 2 && p->table_meas >= 1 && p->table_burn >= 0 &&
            p->table_T_lo > 0.0 && p->table_T_hi > p->table_T_lo &&
-           (p->tile_rows == 0 || p->tile_rows == 1 || p->tile_rows == 2 || p->tile_rows == 4 || p->tile_rows == 8) &&
+           (p->tile_rows == 0 || shape_of(p->tile_rows) >= 0) &&
            p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096;
 }
 
@@ -672,7 +899,7 @@ int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     const int64_t chains = (int64_t)n * p->R;
     b += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
     b += round_up(chains * 8, 256) + round_up((int64_t)n * sizeof(ImgDev), 256) + 4096;
-    b += round_up(4 * (chains + 1) * 8, 256);
+    b += round_up(kNumShapes * (chains + 1) * 8, 256);
     return b;
 }
 
@@ -687,7 +914,7 @@ int64_t table_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     best += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
     best += round_up(chains * 8, 256) + round_up((int64_t)n * sizeof(ImgDev), 256) + 4096;
     best += round_up((int64_t)n * kMapBlocks * 16, 256);
-    best += round_up(4 * (chains + 1) * 8, 256);
+    best += round_up(kNumShapes * (chains + 1) * 8, 256);
     return best;
 }
 
@@ -769,13 +996,12 @@ SweepConsts make_sc(double q, uint64_t seed)
 
 int blocks_for(int64_t n, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, cap)); }
 
-constexpr int kRowChoices[4] = {1, 2, 4, 8};
-
-// Sweep blocks of one chain for a block shape of `rows` half-rows.
-int64_t chain_blocks(const ChainDesc &d, int rows)
+// Sweep blocks of one chain for block shape k.
+int64_t chain_blocks(const ChainDesc &d, int k)
 {
-    const int px = kBlock / rows;
-    return (int64_t)((d.S / 2 + px - 1) / px) * ((d.ny + rows - 1) / rows);
+    const Shape sh = kShapes[k];
+    const int px = sh.compact ? kCompactSites / sh.rows / 2 : kBlock / sh.rows;  // site pairs per block row
+    return (int64_t)((d.S / 2 + px - 1) / px) * ((d.ny + sh.rows - 1) / sh.rows);
 }
 
 // A set of chains resident in the workspace.
@@ -786,8 +1012,8 @@ struct ChainSet {
     ChainDesc *d_desc = nullptr;
     ChainState *d_state = nullptr;
     int64_t *d_offset = nullptr;
-    int64_t *d_start[4] = {nullptr, nullptr, nullptr, nullptr};  // block prefix sums per shape
-    int64_t total_blocks[4] = {0, 0, 0, 0};
+    int64_t *d_start[kNumShapes] = {};  // block prefix sums per shape
+    int64_t total_blocks[kNumShapes] = {};
 };
 
 template <int ROWS>
@@ -803,9 +1029,28 @@ void launch_half_rows(hipStream_t st, const ChainSet &cs, int v, bool table, int
                            cs.d_start[v], n, colour, sc, 0, nullptr);
 }
 
+template <int CR>
+void launch_half_compact(hipStream_t st, const ChainSet &cs, int v, int colour, const SweepConsts &sc)
+{
+    const int n = (int)cs.desc.size();
+    hipLaunchKernelGGL((half_sweep_compact_kernel<false, CR>), dim3((unsigned)cs.total_blocks[v]), dim3(kBlock), 0,
+                       st, cs.d_desc, cs.d_state, cs.d_start[v], n, colour, sc, 0, nullptr);
+}
+
+// One half-sweep of every chain in shape v (the e(T, L) runs use the plain
+// shapes only).
 void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colour, const SweepConsts &sc)
 {
-    switch (kRowChoices[v]) {
+    const Shape sh = kShapes[v];
+    if (sh.compact && !table) {
+        switch (sh.rows) {
+            case 2: launch_half_compact<2>(st, cs, v, colour, sc); break;
+            case 4: launch_half_compact<4>(st, cs, v, colour, sc); break;
+            default: launch_half_compact<8>(st, cs, v, colour, sc); break;
+        }
+        return;
+    }
+    switch (sh.rows) {
         case 1: launch_half_rows<1>(st, cs, v, table, colour, sc); break;
         case 2: launch_half_rows<2>(st, cs, v, table, colour, sc); break;
         case 4: launch_half_rows<4>(st, cs, v, table, colour, sc); break;
@@ -867,9 +1112,9 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     };
 
     // block shape: fixed, cached, or tuned on the first sweeps
-    int v = -1;
-    for (int k = 0; k < 4; ++k)
-        if (p->tile_rows == kRowChoices[k]) v = k;
+    const int n_shapes = table ? kNumPlainShapes : kNumShapes;
+    int v = p->tile_rows ? shape_of(p->tile_rows) : -1;
+    if (v >= n_shapes) v = kDefaultShape;
     int maxnx = 0, maxny = 0;
     for (const auto &d : cs.desc) {
         maxnx = std::max(maxnx, d.nx);
@@ -885,7 +1130,7 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
         const int ts = std::max(1, std::min(poll_every, 3));
         float best = 0.0f;
         int tried = 0;
-        for (int k = 0; k < 4 && !finished && done_sweeps + ts <= max_sweeps; ++k, ++tried) {
+        for (int k = 0; k < n_shapes && !finished && done_sweeps + ts <= max_sweeps; ++k, ++tried) {
             float ms = 0.0f;
             int rc = block(k, ts, nullptr, &ms);
             if (rc) return rc;
@@ -894,10 +1139,11 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
                 v = k;
             }
         }
-        if (v < 0) v = 2;
+        if (v < 0) v = kDefaultShape;
         else sweep_ms = best / (float)ts;
-        if (tried == 4) ctx->tuned_rows[key] = v;
+        if (tried == n_shapes) ctx->tuned_rows[key] = v;
     }
+    if (!table) ctx->last_tile = kShapes[v].rows | (kShapes[v].compact ? MPR_TILE_COMPACT : 0);
     // sweeps per graph: at least about a millisecond of work per done-check
     int spl = p->sweeps_per_launch > 0 ? p->sweeps_per_launch : poll_every;
     if (p->sweeps_per_launch <= 0 && sweep_ms > 0.0f && (float)spl * sweep_ms < 1.0f)
@@ -929,17 +1175,17 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
 int upload_starts(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream)
 {
     const int n = (int)cs.desc.size();
-    std::vector<int64_t> h((size_t)4 * (n + 1));
-    for (int k = 0; k < 4; ++k) {
+    std::vector<int64_t> h((size_t)kNumShapes * (n + 1));
+    for (int k = 0; k < kNumShapes; ++k) {
         int64_t *sk = h.data() + (size_t)k * (n + 1);
         sk[0] = 0;
-        for (int c = 0; c < n; ++c) sk[c + 1] = sk[c] + chain_blocks(cs.desc[c], kRowChoices[k]);
+        for (int c = 0; c < n; ++c) sk[c + 1] = sk[c] + chain_blocks(cs.desc[c], k);
         cs.total_blocks[k] = sk[n];
         if (sk[n] >= ((int64_t)1 << 31)) return fail(ctx, MPR_ERR_ARG, "batch too large for one launch");
     }
     int64_t *d = (int64_t *)cv.take((int64_t)h.size() * 8);
     if (!d) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
-    for (int k = 0; k < 4; ++k) cs.d_start[k] = d + (size_t)k * (n + 1);
+    for (int k = 0; k < kNumShapes; ++k) cs.d_start[k] = d + (size_t)k * (n + 1);
     HIP_TRY(ctx, hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, stream));
     HIP_TRY(ctx, hipStreamSynchronize(stream));
     return MPR_OK;
@@ -1412,6 +1658,8 @@ int32_t mpr_profile_read(mpr_ctx *ctx, mpr_profile *out)
     HIP_TRY(ctx, hipMemcpy(w, (char *)ctx->scratch + kWorkOffset, sizeof w, hipMemcpyDeviceToHost));
     out->sweep_kernel_ms = ctx->prof_ms;
     out->sweep_launches = ctx->prof_launches;
+    out->last_tile = ctx->last_tile;
+    out->reserved = 0;
     out->chain_sweeps = (int64_t)w[0];
     out->site_updates = (int64_t)w[1];
     out->useful_bytes = (double)w[2];
@@ -1436,12 +1684,13 @@ int32_t mpr_diag_philox(mpr_ctx *ctx, const uint32_t *ctr, uint64_t seed, int64_
 
 int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, const uint8_t *sampled, int32_t colour,
                             double T, double a, double q, uint64_t seed, uint32_t sweep, uint32_t chain,
-                            uint32_t stream_id, int32_t mode, uint8_t *flags, int64_t *accepted,
+                            uint32_t stream_id, int32_t mode, int32_t tile, uint8_t *flags, int64_t *accepted,
                             double *bond_energy, void *stream_)
 {
     if (!ctx) return MPR_ERR_ARG;
+    const int v = tile ? shape_of(tile) : kDefaultShape;
     if (nx < 1 || ny < 1 || (int64_t)nx * ny < 2 || !phi || !sampled || (colour != 0 && colour != 1) || !(T > 0) ||
-        !(a > 0) || !(q > 0 && q <= 0.5) || (mode != 0 && mode != 1))
+        !(a > 0) || q != 0.5 || (mode != 0 && mode != 1) || v < 0)
         return fail(ctx, MPR_ERR_ARG, "diag_half_sweep: invalid argument");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
@@ -1477,8 +1726,32 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
                        cs.d_offset, phi, sampled, phi, 0u, 0u, 0);
     if (flags) (void)hipMemsetAsync(flags, 0, nsite, stream);
     const SweepConsts sc = make_sc(q, seed);
-    hipLaunchKernelGGL((half_sweep_kernel<true, 4>), dim3((unsigned)cs.total_blocks[2]), dim3(kBlock), 0, stream,
-                       cs.d_desc, cs.d_state, cs.d_start[2], 1, colour, sc, mode, flags);
+    const dim3 grid((unsigned)cs.total_blocks[v]);
+    const Shape sh = kShapes[v];
+    if (sh.compact) {
+        if (sh.rows == 2)
+            hipLaunchKernelGGL((half_sweep_compact_kernel<true, 2>), grid, dim3(kBlock), 0, stream, cs.d_desc,
+                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, flags);
+        else if (sh.rows == 4)
+            hipLaunchKernelGGL((half_sweep_compact_kernel<true, 4>), grid, dim3(kBlock), 0, stream, cs.d_desc,
+                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, flags);
+        else
+            hipLaunchKernelGGL((half_sweep_compact_kernel<true, 8>), grid, dim3(kBlock), 0, stream, cs.d_desc,
+                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, flags);
+    } else {
+        if (sh.rows == 1)
+            hipLaunchKernelGGL((half_sweep_kernel<true, 1>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
+                               cs.d_start[v], 1, colour, sc, mode, flags);
+        else if (sh.rows == 2)
+            hipLaunchKernelGGL((half_sweep_kernel<true, 2>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
+                               cs.d_start[v], 1, colour, sc, mode, flags);
+        else if (sh.rows == 4)
+            hipLaunchKernelGGL((half_sweep_kernel<true, 4>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
+                               cs.d_start[v], 1, colour, sc, mode, flags);
+        else
+            hipLaunchKernelGGL((half_sweep_kernel<true, 8>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
+                               cs.d_start[v], 1, colour, sc, mode, flags);
+    }
     hipLaunchKernelGGL(unsplit_kernel, dim3(blocks_for(nsite, 2048)), dim3(kBlock), 0, stream, cs.d_desc, phi);
     ChainState out;
     (void)hipMemcpyAsync(&out, cs.d_state, sizeof out, hipMemcpyDeviceToHost, stream);

@@ -92,7 +92,8 @@ __device__ __forceinline__ float unit24(uint32_t w)
 
 // ------------------------------------------------------------- sign bit
 __device__ __forceinline__ bool is_fixed(float v) { return (__float_as_uint(v) >> 31) != 0u; }
-__device__ __forceinline__ float angle_of(float v) { return __uint_as_float(__float_as_uint(v) & 0x7FFFFFFFu); }
+// fabsf clears the sign bit (also of -0.0) and folds into instruction modifiers
+__device__ __forceinline__ float angle_of(float v) { return fabsf(v); }
 __device__ __forceinline__ float mark_fixed(float a) { return __uint_as_float(__float_as_uint(a) | 0x80000000u); }
 
 // Sweep parameters shared by a launch.
@@ -112,6 +113,7 @@ struct SiteOut {
     float e_bonds;   // sum over the site's bonds of 1 - cos(q (phi_new - phi_j))
     float e_before;  // the same sum before the update
     uint32_t flags;
+    bool accepted;   // flags & F_ACCEPTED, kept apart so that unused flag bits fold away
 };
 
 // The whole update of one site in double precision, in the same steps and
@@ -158,6 +160,7 @@ __device__ __noinline__ SiteOut update_site_fp64(double phi, float n0, float n1,
         o.phi = (float)p1;
         o.e_bonds = (float)((double)nnb + h1);
         o.flags = f;
+        o.accepted = false;
         return o;
     }
     const double raw = p1 + kTwoPi * (u - 0.5) / a;
@@ -176,6 +179,7 @@ __device__ __noinline__ SiteOut update_site_fp64(double phi, float n0, float n1,
     o.phi = (float)(acc ? p2 : p1);
     o.e_bonds = (float)((double)nnb + (acc ? h2 : h1));
     o.flags = f;
+    o.accepted = acc;
     return o;
 }
 
@@ -201,6 +205,26 @@ __device__ __forceinline__ float cos_poly(float x)
     p = fmaf(p, x2, 4.166358337e-02f);
     p = fmaf(p, x2, -4.999990463e-01f);
     return fmaf(p, x2, 9.999999404e-01f);
+}
+
+// The same polynomials taking a full angle d and returning 2 sin(d/2) and
+// cos(d/2) from d2 = d * d: every coefficient is the one above divided by a
+// power of two, so the results equal 2 sin_poly(d/2) and cos_poly(d/2) bit
+// for bit, without the halving and doubling.
+__device__ __forceinline__ float sin2_half_poly(float d, float d2)
+{
+    float p = fmaf(d2, 2.601902224e-06f / 256.0f, -1.980741799e-04f / 64.0f);
+    p = fmaf(p, d2, 8.333025500e-03f / 16.0f);
+    p = fmaf(p, d2, -1.666665673e-01f / 4.0f);
+    return fmaf(p * d2, d, d);
+}
+
+__device__ __forceinline__ float cos_half_poly(float d2)
+{
+    float p = fmaf(d2, 2.315392157e-05f / 256.0f, -1.385370386e-03f / 64.0f);
+    p = fmaf(p, d2, 4.166358337e-02f / 16.0f);
+    p = fmaf(p, d2, -4.999990463e-01f / 4.0f);
+    return fmaf(p, d2, 9.999999404e-01f);
 }
 
 // atan2(y, x) in (-pi, pi]: octant reduction to t = min/max in [0, 1].
@@ -249,22 +273,20 @@ __device__ __forceinline__ SiteOut update_site(float phi, float n0, float n1, fl
 {
     const float th = 0.5f * phi;
     const float nb[4] = {n0, n1, n2, n3};
-    float A_small = 0.0f, B = 0.0f, S1 = 0.0f;
-    float nnb = 0.0f;
+    float A2 = 0.0f, B = 0.0f, S1 = 0.0f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const bool v = (valid >> j) & 1u;
         const float dj = v ? th - 0.5f * nb[j] : 0.0f;
-        const float hj = 0.5f * dj;
-        const float sj = sin_poly(hj);
-        const float cj = cos_poly(hj);
-        const float s2 = 2.0f * sj;
-        B = fmaf(s2, cj, B);              // sin D_j
-        A_small = fmaf(s2, sj, A_small);  // 1 - cos D_j
+        const float d2 = dj * dj;
+        const float s2 = sin2_half_poly(dj, d2);  // 2 sin(D_j / 2)
+        const float cj = cos_half_poly(d2);
+        B = fmaf(s2, cj, B);        // sin D_j
+        A2 = fmaf(s2, s2, A2);      // 2 (1 - cos D_j)
         S1 += fabsf(dj);
-        nnb += v ? 1.0f : 0.0f;
     }
-    const float A = nnb - A_small;
+    const float A_small = 0.5f * A2;
+    const float A = (float)__popc(valid & 15u) - A_small;
     const float d1 = atan2_poly(-B, A);
     const float raw1 = fmaf(2.0f, d1, th);
     const float pi_f = 3.14159274f;
@@ -279,33 +301,53 @@ __device__ __forceinline__ SiteOut update_site(float phi, float n0, float n1, fl
         o.phi = 2.0f * th1;
         o.e_bonds = A_small;
         o.flags = F_UPDATED | (kept ? F_KEPT : 0u);
+        o.accepted = false;
         return o;
     }
     const float Bs = kept ? B : -B;
     const float delta = (u - 0.5f) * dscale;
-    const float hd = 0.5f * delta;
-    const float sh = sin_poly(hd), ch = cos_poly(hd);
-    const float sd = 2.0f * sh * ch;
+    const float dd2 = delta * delta;
+    const float sh2 = sin2_half_poly(delta, dd2), ch = cos_half_poly(dd2);  // 2 sin(delta/2), cos(delta/2)
+    const float sd = sh2 * ch;
     const float raw2 = th1 + delta;
     const bool wrapped = raw2 < 0.0f || raw2 >= pi_f;
     close = close || fabsf(raw2) < tb || fabsf(raw2 - pi_f) < tb || r == 0.0f;
     const float th2 = raw2 < 0.0f ? raw2 + pi_f : (raw2 >= pi_f ? raw2 - pi_f : raw2);
-    const float w2 = 2.0f * (wrapped ? ch * ch : sh * sh);
+    const float w2 = wrapped ? 2.0f * (ch * ch) : 0.5f * (sh2 * sh2);
     const float dH = fmaf(A, w2, wrapped ? -Bs * sd : Bs * sd);
     const float x = dH * inv_T;
-    const float lr = __logf(r);
+    const float lr = __builtin_amdgcn_logf(r) * 0.693147182f;  // r >= 2^-24 here: no denormals
     const float m = -x - lr;
     // Rounding-error bound of m: B carries a relative error ~6e-7 of
-    // sum |D_j|, A an absolute one ~1e-6; the rest is relative.
-    const float err_dH = 2.0e-6f * (S1 + (fabsf(A) + fabsf(B)) * fabsf(sd)) * fabsf(sd) + 2.0e-6f * w2 +
-                         2.0e-6f * fabsf(dH);
-    const float band = err_dH * inv_T + 1.0e-6f * (fabsf(x) + fabsf(lr)) + 1.0e-6f;
+    // sum |D_j|, A an absolute one ~1e-6; the rest is relative:
+    //   err(dH) <= 2e-6 ((S1 + (|A| + |B|) |sd|) |sd| + w2 + |dH|),
+    //   band = err(dH) / T + 1e-6 (|x| + |ln r|) + 1e-6.
+    const float t_err = fmaf(fmaf(fabsf(A) + fabsf(B), fabsf(sd), S1), fabsf(sd), w2);
+    const float band = fmaf(t_err, 2.0e-6f * inv_T, fmaf(3.0e-6f, fabsf(x), fmaf(1.0e-6f, fabsf(lr), 1.0e-6f)));
     *need64 = close || !(fabsf(m) > band);
     const bool acc = m > 0.0f;
     o.phi = 2.0f * (acc ? th2 : th1);
     o.e_bonds = acc ? A_small + dH : A_small;
     o.flags = F_UPDATED | (kept ? F_KEPT : 0u) | (wrapped ? F_WRAPPED : 0u) | (acc ? F_ACCEPTED : 0u);
+    o.accepted = acc;
     return o;
+}
+
+// Sum over the bonds of a site of 1 - cos D_j (q = 1/2, th = phi / 2), in
+// the same operations and order as update_site, so that a sampled site's
+// energy equals the value update_site would report for it.
+__device__ __forceinline__ float bond_energy_half(float th, float n0, float n1, float n2, float n3, uint32_t valid)
+{
+    const float nb[4] = {n0, n1, n2, n3};
+    float A2 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool v = (valid >> j) & 1u;
+        const float dj = v ? th - 0.5f * nb[j] : 0.0f;
+        const float s2 = sin2_half_poly(dj, dj * dj);
+        A2 = fmaf(s2, s2, A2);
+    }
+    return 0.5f * A2;
 }
 
 // Bond energies of a site in fixed point: units of 2^-27, rounded, so that

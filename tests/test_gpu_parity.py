@@ -118,23 +118,28 @@ def smooth_state(ny, nx, nu, kappa, p_removed, noise, seed):
     return phi.astype(np.float32), m
 
 
-def run_pair(ctx, phi32, m, colour, T, a, sweep, mode=0, chain=0, stream_id=0, seed=3000):
+PLAIN, COMPACT = 0, 4 | mpr.TILE_COMPACT  # default plain shape; compacted 4-row shape
+ALL_TILES = [1, 2, 4, 8, 2 | mpr.TILE_COMPACT, 4 | mpr.TILE_COMPACT, 8 | mpr.TILE_COMPACT]
+
+
+def run_pair(ctx, phi32, m, colour, T, a, sweep, mode=0, chain=0, stream_id=0, seed=3000, tile=PLAIN):
     """One half-sweep on the GPU and in the oracle from the same float32 state."""
     ny, nx = phi32.shape
     g = dev(phi32)
     fl = torch.zeros((ny, nx), dtype=torch.uint8, device="cuda")
     acc_g = ctx.diag_half_sweep(g, dev(m, torch.uint8), colour, T, a, sweep, chain=chain, stream_id=stream_id,
-                                seed=seed, mode=mode, flags=fl)
+                                seed=seed, mode=mode, flags=fl, tile=tile)
     po, acc_o, fo = oracle.half_sweep(phi32.astype(np.float64), m, colour, T, a, sweep, chain=chain,
                                       stream=stream_id, seed=seed, mode=mode, with_flags=True)
     return g.cpu().numpy(), acc_g, fl.cpu().numpy(), po, acc_o, fo
 
 
+@pytest.mark.parametrize("tile", [PLAIN, COMPACT])
 @pytest.mark.parametrize("kind", ["uniform", "smooth"])
 @pytest.mark.parametrize("shape", [(64, 64), (97, 131), (1, 40), (40, 1)])
-def test_over_relaxation_only_teacher_forced(ctx, kind, shape):
+def test_over_relaxation_only_teacher_forced(ctx, kind, shape, tile):
     ny, nx = shape
-    say("OR-only", kind, shape)
+    say("OR-only", kind, shape, "tile", tile)
     rng = np.random.default_rng(ny + 7 * nx)
     if kind == "uniform":
         phi = rng.uniform(0, TWO_PI, size=shape).astype(np.float32)
@@ -144,7 +149,7 @@ def test_over_relaxation_only_teacher_forced(ctx, kind, shape):
         phi, m = phi[:ny, :nx].copy(), m[:ny, :nx].copy()
     keep_flips = 0
     for colour in (0, 1):
-        pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 0.1, 1.0, 0, mode=1)
+        pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 0.1, 1.0, 0, mode=1, tile=tile)
         assert acc_g == 0 and acc_o == 0
         sel = colour_mask(ny, nx, colour) & (m == 0)
         kf = ((fg & 1) != (fo & 1)) & sel
@@ -161,10 +166,11 @@ def test_over_relaxation_only_teacher_forced(ctx, kind, shape):
 LOW_T = [2.6e-4, 1.0e-3, 0.1]
 
 
+@pytest.mark.parametrize("tile", [PLAIN, COMPACT])
 @pytest.mark.parametrize("T", LOW_T)
-def test_metropolis_decisions_teacher_forced(ctx, T):
+def test_metropolis_decisions_teacher_forced(ctx, T, tile):
     """Chains of half-sweeps; at every step the oracle redoes it from the GPU's state."""
-    say("decisions T =", T)
+    say("decisions T =", T, "tile", tile)
     ny, nx = 384, 517
     phi, m = smooth_state(ny, nx, 2.5, 0.05, 0.5, 0.02, 31)
     n_dec = n_flip = n_fp64 = 0
@@ -173,7 +179,7 @@ def test_metropolis_decisions_teacher_forced(ctx, T):
     for a in (1.0, 4.0, 40.0):
         for sweep in range(3):
             for colour in (0, 1):
-                pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, T, a, 100 * step + sweep)
+                pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, T, a, 100 * step + sweep, tile=tile)
                 sel = colour_mask(ny, nx, colour) & (m == 0)
                 flip = (((fg ^ fo) & 3) != 0) & sel
                 n_dec += int(sel.sum())
@@ -188,20 +194,21 @@ def test_metropolis_decisions_teacher_forced(ctx, T):
     assert max_err <= 1e-5
 
 
-def test_accept_count_and_energy_teacher_forced(ctx):
+@pytest.mark.parametrize("tile", [PLAIN, COMPACT])
+def test_accept_count_and_energy_teacher_forced(ctx, tile):
     ny, nx = 130, 257
     phi, m = smooth_state(ny, nx, 1.5, 0.1, 0.66, 0.05, 41)
     ngp = oracle.bond_count(nx, ny)
     for T, a in ((2e-3, 3.0), (2.6e-4, 20.0), (0.2, 1.0)):
         for colour in (0, 1):
-            pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, T, a, 7)
+            pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, T, a, 7, tile=tile)
             assert acc_g == int(((fg & 2) != 0).sum())
             assert acc_g == acc_o
             if colour == 1:
                 # the sweep's own energy sum (from its update terms) against
                 # the oracle's energy of the state it wrote: |de| <= 1e-6
                 g = dev(phi)
-                _, e_fused = ctx.diag_half_sweep(g, dev(m, torch.uint8), 1, T, a, 7, with_energy=True)
+                _, e_fused = ctx.diag_half_sweep(g, dev(m, torch.uint8), 1, T, a, 7, with_energy=True, tile=tile)
                 e_o = oracle.energy(g.cpu().numpy().astype(np.float64)) + ngp
                 assert abs(e_fused - e_o) / ngp <= 1e-6, (e_fused, e_o)
             phi = pg
@@ -213,14 +220,15 @@ def test_accept_count_and_energy_teacher_forced(ctx):
     assert abs(hp / ho - 1.0) <= 1e-4
 
 
+@pytest.mark.parametrize("tile", [PLAIN, COMPACT])
 @pytest.mark.parametrize("shape", [(1, 2), (2, 1), (3, 3), (5, 2), (2, 7), (1, 9)])
-def test_degenerate_and_tiny_grids(ctx, shape):
+def test_degenerate_and_tiny_grids(ctx, shape, tile):
     ny, nx = shape
     rng = np.random.default_rng(nx * 10 + ny)
     phi = rng.uniform(0, TWO_PI, size=shape).astype(np.float32)
     m = np.zeros(shape, np.uint8)
     for colour in (0, 1):
-        pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 0.5, 1.0, 3)
+        pg, acc_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 0.5, 1.0, 3, tile=tile)
         sel = colour_mask(ny, nx, colour)
         assert np.array_equal(fg[sel] & 3, fo[sel] & 3)
         assert np.max(np.abs(pg.astype(np.float64) - po)) <= 1e-5
@@ -399,8 +407,9 @@ def test_l1024_prediction_matches_oracle(ctx):
 
 @pytest.mark.parametrize("shape", [(64, 64), (45, 211)])
 def test_results_independent_of_block_shape_and_graph_size(ctx, shape):
-    """Every block shape (rows 1, 2, 4, 8, autotuned) and graph size gives
-    bit-identical sums, statistics and stopping decisions."""
+    """Every block shape (plain rows 1, 2, 4, 8; compacted rows 2, 4, 8;
+    autotuned) and graph size gives bit-identical sums, statistics and
+    stopping decisions."""
     ny, nx = shape
     z = synth.matern_field(nx, ny, 1.5, 0.1, 50, 10, 17)
     m = synth.random_mask(nx, ny, 0.5, 18)
@@ -410,7 +419,8 @@ def test_results_independent_of_block_shape_and_graph_size(ctx, shape):
     phi = torch.zeros_like(zd)
     ctx.map_to_angles(imgs, zd, mk, phi)
     ref = None
-    for rows, spl in ((4, 5), (1, 5), (2, 7), (8, 1), (0, 0), (4, 64)):
+    for rows, spl in ((4, 5), (1, 5), (2, 7), (8, 1), (0, 0), (4, 64), (2 | mpr.TILE_COMPACT, 5),
+                      (4 | mpr.TILE_COMPACT, 3), (8 | mpr.TILE_COMPACT, 64)):
         prm = mpr.default_params(R=3, K=4, tile_rows=rows, sweeps_per_launch=spl)
         ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
         ps = torch.zeros_like(zd)
@@ -420,3 +430,28 @@ def test_results_independent_of_block_shape_and_graph_size(ctx, shape):
             ref = out
         else:
             assert out == ref, (rows, spl)
+
+
+@pytest.mark.parametrize("p_removed", [0.0, 0.33, 0.66, 1.0])
+@pytest.mark.parametrize("shape", [(67, 1100), (300, 129)])
+def test_half_sweep_identical_for_every_tile(ctx, shape, p_removed):
+    """One half-sweep per colour in every block shape: angles, flags,
+    accepted counts and the fused energy are bit-identical (the shapes wider
+    than the grid and the ragged right and bottom edges included)."""
+    ny, nx = shape
+    say("tiles", shape, p_removed)
+    phi, m = smooth_state(ny, nx, 1.5, 0.1, 0.5, 0.05, 51)
+    rng = np.random.default_rng(52)
+    m = (rng.random(shape) >= p_removed).astype(np.uint8)
+    mk = dev(m, torch.uint8)
+    for colour in (0, 1):
+        ref = None
+        for tile in ALL_TILES:
+            g = dev(phi)
+            fl = torch.zeros((ny, nx), dtype=torch.uint8, device="cuda")
+            acc, e = ctx.diag_half_sweep(g, mk, colour, 1e-3, 4.0, 11, flags=fl, with_energy=True, tile=tile)
+            out = (g.cpu().numpy().tobytes(), fl.cpu().numpy().tobytes(), acc, e)
+            if ref is None:
+                ref = out
+            else:
+                assert out == ref, (tile, colour)
