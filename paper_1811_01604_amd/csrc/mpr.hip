@@ -45,6 +45,24 @@ constexpr int64_t kWorkOffset = 1024;    // three work counters (profiling)
 constexpr int64_t kEnergyOffset = 2048;  // diag energy accumulator
 constexpr int64_t kSlopeOffset = 4096;   // diag slope input / output
 constexpr int64_t kVarOffset = 65536;    // per-call partials
+constexpr int kCompactSites = 4 * kBlock;  // sites per block of the compacted sweep shapes
+
+// Sites whose single-precision decision is too close to call are not written
+// by the sweep kernels: they set the site's bit in their block's mask (one
+// bit per site of the block, site = 2 pair + slot) and the block's bit in a
+// bitmap, and redo_fp64_kernel redoes them in double precision afterwards.
+// Keeping the double-precision code out of the sweep kernels keeps them at
+// fewer than 64 registers.
+struct Redo {
+    uint32_t *mask;    // words_per_block per sweep block (flattened block index)
+    uint32_t *blocks;  // one bit per sweep block
+};
+
+__device__ __forceinline__ void defer_redo(const Redo &rd, uint32_t gb, int words, uint32_t idx)
+{
+    atomicOr(&rd.mask[(size_t)gb * words + (idx >> 5)], 1u << (idx & 31u));
+    atomicOr(&rd.blocks[gb >> 5], 1u << (gb & 31u));
+}
 
 // Parameters of the control kernel.
 struct CtlParams {
@@ -129,7 +147,7 @@ template <bool DIAG, int ROWS>
 __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ descs,
                                                 ChainState *__restrict__ states,
                                                 const int64_t *__restrict__ start, int n_chains, int colour,
-                                                SweepConsts sc, int or_only, uint8_t *__restrict__ flags)
+                                                SweepConsts sc, int or_only, Redo rd, uint8_t *__restrict__ flags)
 {
     constexpr int PX = kBlock / ROWS;
     const int c = find_chain(start, n_chains, (int64_t)blockIdx.x);
@@ -145,7 +163,6 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
     const int h0 = 2 * (bx * PX + (int)(threadIdx.x % PX));
     const uint32_t sweep = stp->sweep;
     const float inv_T = stp->inv_T, dscale = stp->dscale;
-    const double T64 = stp->T, a64 = stp->a_cur;
     const bool want_energy = (colour == 1) && (phase != PH_EQ);
     const bool want_acc = phase != PH_EQ;
     uint32_t e_thread = 0u, acc_thread = 0u;
@@ -191,44 +208,34 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
             bool n0 = true, n1 = true;
             SiteOut o0 = update_site(a0, oL, oM, up.x, dn.x, val0, u0, r0, inv_T, dscale, or_only != 0, &n0);
             SiteOut o1 = update_site(a1, oM, oR, up.y, dn.y, val1, u1, r1, inv_T, dscale, or_only != 0, &n1);
+            // too close to call: left unchanged here, redone in double precision
             n0 = n0 && !fixed0;
             n1 = n1 && !fixed1;
-            if (n0 || n1) {
-                // rare: redo in double precision (one inlined copy for both sites)
-                for (int k = 0; k < 2; ++k) {
-                    if (k ? n1 : n0) {
-                        const SiteOut f = update_site_fp64(
-                            (double)(k ? a1 : a0), k ? oM : oL, k ? oR : oM, k ? up.y : up.x, k ? dn.y : dn.x,
-                            k ? val1 : val0, (double)(k ? u1 : u0), (double)(k ? r1 : r0), a64, T64, sc.q64,
-                            or_only != 0);
-                        if (k) o1 = f;
-                        else o0 = f;
-                    }
-                }
-            }
-            const float out0 = fixed0 ? v.x : o0.phi;
-            const float out1 = fixed1 ? v.y : o1.phi;
+            if (n0) defer_redo(rd, blockIdx.x, 2 * kBlock / 32, 2u * threadIdx.x);
+            if (n1) defer_redo(rd, blockIdx.x, 2 * kBlock / 32, 2u * threadIdx.x + 1u);
+            const bool w0 = !fixed0 && !n0, w1 = two && !fixed1 && !n1;  // sites written here
+            const float out0 = w0 ? o0.phi : v.x;
+            const float out1 = w1 ? o1.phi : v.y;
             if (two) {
                 *reinterpret_cast<float2 *>(mine + h0) = make_float2(out0, out1);
-            } else if (!fixed0) {
+            } else if (w0) {
                 mine[h0] = out0;
             }
             float *accp = colour ? d.acc[1] : d.acc[0];
             if (phase == PH_EQ && accp) {
                 float *acc = accp + (int64_t)y * d.S;
-                if (!fixed0) acc[h0] += out0;
-                if (two && !fixed1) acc[h0 + 1] += out1;
+                if (w0) acc[h0] += out0;
+                if (w1) acc[h0 + 1] += out1;
             }
-            const uint32_t f0 = fixed0 ? 0u : o0.flags, f1 = fixed1 ? 0u : o1.flags;
-            acc_thread = (!fixed0 && o0.accepted ? 1u : 0u) + (!fixed1 && o1.accepted ? 1u : 0u);
+            acc_thread = (w0 && o0.accepted ? 1u : 0u) + (w1 && o1.accepted ? 1u : 0u);
             // a sampled site's bonds are unchanged by this half-sweep
             if (want_energy)
-                e_thread = energy_fx(fixed0 ? o0.e_before : o0.e_bonds) +
-                           (two ? energy_fx(fixed1 ? o1.e_before : o1.e_bonds) : 0u);
+                e_thread = (fixed0 ? energy_fx(o0.e_before) : (w0 ? energy_fx(o0.e_bonds) : 0u)) +
+                           (!two ? 0u : fixed1 ? energy_fx(o1.e_before) : (w1 ? energy_fx(o1.e_bonds) : 0u));
             if (DIAG && flags) {
                 const int64_t x0 = 2 * h0 + s;
-                flags[(int64_t)y * d.nx + x0] = (uint8_t)f0;
-                if (two) flags[(int64_t)y * d.nx + x0 + 2] = (uint8_t)f1;
+                if (w0) flags[(int64_t)y * d.nx + x0] = (uint8_t)o0.flags;
+                if (w1) flags[(int64_t)y * d.nx + x0 + 2] = (uint8_t)o1.flags;
             }
         }
     }
@@ -264,10 +271,10 @@ template <bool DIAG, int ROWS>
 __global__ __launch_bounds__(kBlock) void half_sweep_kernel(const ChainDesc *__restrict__ descs,
                                                             ChainState *__restrict__ states,
                                                             const int64_t *__restrict__ start, int n_chains,
-                                                            int colour, SweepConsts sc, int or_only,
+                                                            int colour, SweepConsts sc, int or_only, Redo rd,
                                                             uint8_t *__restrict__ flags)
 {
-    half_sweep_body<DIAG, ROWS>(descs, states, start, n_chains, colour, sc, or_only, flags);
+    half_sweep_body<DIAG, ROWS>(descs, states, start, n_chains, colour, sc, or_only, rd, flags);
 }
 
 // The same sweep for the unconditional e(T, L) runs (a separate symbol so
@@ -276,9 +283,9 @@ template <int ROWS>
 __global__ __launch_bounds__(kBlock) void table_half_sweep_kernel(const ChainDesc *__restrict__ descs,
                                                                   ChainState *__restrict__ states,
                                                                   const int64_t *__restrict__ start,
-                                                                  int n_chains, int colour, SweepConsts sc)
+                                                                  int n_chains, int colour, SweepConsts sc, Redo rd)
 {
-    half_sweep_body<false, ROWS>(descs, states, start, n_chains, colour, sc, 0, nullptr);
+    half_sweep_body<false, ROWS>(descs, states, start, n_chains, colour, sc, 0, rd, nullptr);
 }
 
 // The same half-sweep with the gap sites compacted onto consecutive lanes
@@ -290,13 +297,11 @@ __global__ __launch_bounds__(kBlock) void table_half_sweep_kernel(const ChainDes
 // update lanes; pass 3 gives sampled sites of colour 1 their bond energies
 // when the sweep's energy is wanted.  Every site gets the arithmetic of the
 // plain kernel, so the results are bit-identical to it.
-constexpr int kCompactSites = 4 * kBlock;
-
 template <bool DIAG, int CR>
 __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restrict__ descs,
                                                         ChainState *__restrict__ states,
                                                         const int64_t *__restrict__ start, int n_chains,
-                                                        int colour, SweepConsts sc, int or_only,
+                                                        int colour, SweepConsts sc, int or_only, Redo rd,
                                                         uint8_t *__restrict__ flags)
 {
     constexpr int PPR = kCompactSites / CR / 2;  // site pairs per block row
@@ -319,7 +324,6 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
     const int bx = lb - by * nbx;
     const uint32_t sweep = stp->sweep;
     const float inv_T = stp->inv_T, dscale = stp->dscale;
-    const double T64 = stp->T, a64 = stp->a_cur;
     const bool want_energy = (colour == 1) && (phase != PH_EQ);
     const bool want_acc = phase != PH_EQ;
     float *const mine_base = colour ? d.h[1] : d.h[0];
@@ -441,10 +445,11 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
         const float u = or_only ? 0.5f : unit24(e.x);
         const float r = or_only ? 0.5f : unit24(e.y);
         bool n64 = true;
-        SiteOut o = update_site(a, nL, nR, nU, nD, valid, u, r, inv_T, dscale, or_only != 0, &n64);
-        if (n64)
-            o = update_site_fp64((double)a, nL, nR, nU, nD, valid, (double)u, (double)r, a64, T64, sc.q64,
-                                 or_only != 0);
+        const SiteOut o = update_site(a, nL, nR, nU, nD, valid, u, r, inv_T, dscale, or_only != 0, &n64);
+        if (n64) {  // too close to call: redone in double precision afterwards
+            defer_redo(rd, blockIdx.x, kCompactSites / 32, idx);
+            continue;
+        }
         *mp = o.phi;
         if (acc_base) acc_base[(int64_t)y * d.S + h] += o.phi;
         acc_thread += o.accepted ? 1u : 0u;
@@ -493,9 +498,90 @@ __global__ __launch_bounds__(kBlock) void half_sweep_compact_kernel(const ChainD
                                                                     ChainState *__restrict__ states,
                                                                     const int64_t *__restrict__ start,
                                                                     int n_chains, int colour, SweepConsts sc,
-                                                                    int or_only, uint8_t *__restrict__ flags)
+                                                                    int or_only, Redo rd, uint8_t *__restrict__ flags)
 {
-    half_sweep_compact_body<DIAG, CR>(descs, states, start, n_chains, colour, sc, or_only, flags);
+    half_sweep_compact_body<DIAG, CR>(descs, states, start, n_chains, colour, sc, or_only, rd, flags);
+}
+
+// The deferred double-precision updates of one half-sweep (block shape
+// `rows`, `compact`): each flagged site is redone by update_site_fp64 from
+// the inputs the sweep saw (it left the site unchanged), with the same
+// random numbers, written, and its accepted count and bond energy added to
+// its chain.  The bits are cleared on the way, so the buffers are zero
+// again for the next half-sweep.
+template <bool DIAG>
+__global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__restrict__ descs,
+                                                           ChainState *__restrict__ states,
+                                                           const int64_t *__restrict__ start, int n_chains,
+                                                           int64_t total_blocks, int rows, int compact, int colour,
+                                                           SweepConsts sc, int or_only, Redo rd,
+                                                           uint8_t *__restrict__ flags)
+{
+    const int words = compact ? kCompactSites / 32 : 2 * kBlock / 32;
+    const int ppr = compact ? kCompactSites / rows / 2 : kBlock / rows;  // site pairs per block row
+    const int64_t nw = (total_blocks + 31) >> 5;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t bits = rd.blocks[w];
+        if (!bits) continue;
+        rd.blocks[w] = 0u;
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1u;
+            const int64_t gb = (w << 5) + b;
+            const int c = find_chain(start, n_chains, gb);
+            ChainState *stp = states + c;
+            const ChainDesc d = descs[c];
+            const int lb = (int)(gb - start[c]);
+            const int nbx = ((d.S >> 1) + ppr - 1) / ppr;
+            const int by = lb / nbx;
+            const int bx = lb - by * nbx;
+            const int phase = stp->phase;
+            const bool want_energy = (colour == 1) && (phase != PH_EQ);
+            const bool want_acc = phase != PH_EQ;
+            float *mine = colour ? d.h[1] : d.h[0];
+            const float *oth = colour ? d.h[0] : d.h[1];
+            float *accp = (phase == PH_EQ) ? (colour ? d.acc[1] : d.acc[0]) : nullptr;
+            for (int k = 0; k < words; ++k) {
+                uint32_t m = rd.mask[gb * words + k];
+                if (!m) continue;
+                rd.mask[gb * words + k] = 0u;
+                while (m) {
+                    const int bit = __ffs(m) - 1;
+                    m &= m - 1u;
+                    const int idx = 32 * k + bit;
+                    const int pi = idx >> 1, slot = idx & 1;
+                    const int y = by * rows + pi / ppr;
+                    const int h = 2 * (bx * ppr + pi % ppr) + slot;
+                    const int s = (y + colour) & 1;
+                    const int Wo = (d.nx + s) >> 1;
+                    const uint32_t valid = (h + s - 1 >= 0 ? 1u : 0u) | (h + s < Wo ? 2u : 0u) |
+                                           (y > 0 ? 4u : 0u) | (y + 1 < d.ny ? 8u : 0u);
+                    const float *orow = oth + (int64_t)y * d.S;
+                    const float nL = (valid & 1u) ? angle_of(orow[h + s - 1]) : 0.0f;
+                    const float nR = (valid & 2u) ? angle_of(orow[h + s]) : 0.0f;
+                    const float nU = (valid & 4u) ? angle_of(orow[h - d.S]) : 0.0f;
+                    const float nD = (valid & 8u) ? angle_of(orow[h + d.S]) : 0.0f;
+                    float *mp = mine + (int64_t)y * d.S + h;
+                    const float a = angle_of(*mp);
+                    float u = 0.5f, r = 0.5f;
+                    if (!or_only) {
+                        const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * (h & ~1) + s), stp->sweep,
+                                        d.chain, d.image_id};
+                        const U4 wd = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
+                        u = unit24(slot ? wd.z : wd.x);
+                        r = unit24(slot ? wd.w : wd.y);
+                    }
+                    const SiteOut o = update_site_fp64((double)a, nL, nR, nU, nD, valid, (double)u, (double)r,
+                                                       stp->a_cur, stp->T, sc.q64, or_only != 0);
+                    *mp = o.phi;
+                    if (accp) accp[(int64_t)y * d.S + h] += o.phi;
+                    if (want_acc && o.accepted) atomicAdd(&stp->acc, 1ull);
+                    if (want_energy) atomicAdd(&stp->e_fx, (unsigned long long)energy_fx(o.e_bonds));
+                    if (DIAG && flags) flags[(int64_t)y * d.nx + 2 * h + s] = (uint8_t)o.flags;
+                }
+            }
+        }
+    }
 }
 
 __device__ void set_derived(ChainState &st, double q)
@@ -868,6 +954,32 @@ int shape_of(int tile)
     return -1;
 }
 
+// Sweep blocks of one chain (half-row stride S, ny rows) for block shape k.
+int64_t shape_blocks(int S, int ny, int k)
+{
+    const Shape sh = kShapes[k];
+    const int px = sh.compact ? kCompactSites / sh.rows / 2 : kBlock / sh.rows;  // site pairs per block row
+    return (int64_t)((S / 2 + px - 1) / px) * ((ny + sh.rows - 1) / sh.rows);
+}
+
+int64_t chain_blocks(const ChainDesc &d, int k) { return shape_blocks(d.S, d.ny, k); }
+
+// Mask words per sweep block of shape k (one bit per site of the block).
+int redo_words(int k) { return (kShapes[k].compact ? kCompactSites : 2 * kBlock) / 32; }
+
+// Workspace bytes of the deferred-redo buffers for `chains` chains of an
+// nx x ny grid (an upper bound over every block shape).
+int64_t redo_bytes(int nx, int ny, int64_t chains)
+{
+    int64_t words = 0, blocks = 0;
+    for (int k = 0; k < kNumShapes; ++k) {
+        const int64_t b = shape_blocks(half_stride(nx), ny, k);
+        words = std::max(words, b * redo_words(k));
+        blocks = std::max(blocks, b);
+    }
+    return chains * (words * 4 + blocks / 8 + 8) + 1024;
+}
+
 bool valid_params(const mpr_params *p)
 {
     return p && p->q == 0.5 && p->R >= 1 && p->K >= 0 && p->n_f >= 1 && p->n_fit >= 2 &&
@@ -900,6 +1012,7 @@ int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     b += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
     b += round_up(chains * 8, 256) + round_up((int64_t)n * sizeof(ImgDev), 256) + 4096;
     b += round_up(kNumShapes * (chains + 1) * 8, 256);
+    for (int i = 0; i < n; ++i) b += redo_bytes(imgs[i].nx, imgs[i].ny, p->R);
     return b;
 }
 
@@ -915,7 +1028,9 @@ int64_t table_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     best += round_up(chains * 8, 256) + round_up((int64_t)n * sizeof(ImgDev), 256) + 4096;
     best += round_up((int64_t)n * kMapBlocks * 16, 256);
     best += round_up(kNumShapes * (chains + 1) * 8, 256);
-    return best;
+    int64_t rb = 0;
+    for (int i = 0; i < n; ++i) rb = std::max(rb, redo_bytes(imgs[i].nx, imgs[i].ny, chains));
+    return best + rb;
 }
 
 // Derivative at the newest point of the degree-d least-squares polynomial
@@ -996,13 +1111,6 @@ SweepConsts make_sc(double q, uint64_t seed)
 
 int blocks_for(int64_t n, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, cap)); }
 
-// Sweep blocks of one chain for block shape k.
-int64_t chain_blocks(const ChainDesc &d, int k)
-{
-    const Shape sh = kShapes[k];
-    const int px = sh.compact ? kCompactSites / sh.rows / 2 : kBlock / sh.rows;  // site pairs per block row
-    return (int64_t)((d.S / 2 + px - 1) / px) * ((d.ny + sh.rows - 1) / sh.rows);
-}
 
 // A set of chains resident in the workspace.
 struct ChainSet {
@@ -1014,6 +1122,7 @@ struct ChainSet {
     int64_t *d_offset = nullptr;
     int64_t *d_start[kNumShapes] = {};  // block prefix sums per shape
     int64_t total_blocks[kNumShapes] = {};
+    Redo redo = {nullptr, nullptr};      // deferred double-precision updates (zeroed)
 };
 
 template <int ROWS>
@@ -1023,10 +1132,10 @@ void launch_half_rows(hipStream_t st, const ChainSet &cs, int v, bool table, int
     const dim3 grid((unsigned)cs.total_blocks[v]);
     if (table)
         hipLaunchKernelGGL(table_half_sweep_kernel<ROWS>, grid, dim3(kBlock), 0, st, cs.d_desc, cs.d_state,
-                           cs.d_start[v], n, colour, sc);
+                           cs.d_start[v], n, colour, sc, cs.redo);
     else
         hipLaunchKernelGGL((half_sweep_kernel<false, ROWS>), grid, dim3(kBlock), 0, st, cs.d_desc, cs.d_state,
-                           cs.d_start[v], n, colour, sc, 0, nullptr);
+                           cs.d_start[v], n, colour, sc, 0, cs.redo, nullptr);
 }
 
 template <int CR>
@@ -1034,7 +1143,19 @@ void launch_half_compact(hipStream_t st, const ChainSet &cs, int v, int colour, 
 {
     const int n = (int)cs.desc.size();
     hipLaunchKernelGGL((half_sweep_compact_kernel<false, CR>), dim3((unsigned)cs.total_blocks[v]), dim3(kBlock), 0,
-                       st, cs.d_desc, cs.d_state, cs.d_start[v], n, colour, sc, 0, nullptr);
+                       st, cs.d_desc, cs.d_state, cs.d_start[v], n, colour, sc, 0, cs.redo, nullptr);
+}
+
+// The deferred double-precision updates after a half-sweep in shape v.
+template <bool DIAG>
+void launch_redo(hipStream_t st, const ChainSet &cs, int v, int colour, const SweepConsts &sc, int or_only,
+                 uint8_t *flags)
+{
+    const int64_t nw = (cs.total_blocks[v] + 31) / 32;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kBlock - 1) / kBlock, 1024));
+    hipLaunchKernelGGL((redo_fp64_kernel<DIAG>), dim3(grid), dim3(kBlock), 0, st, cs.d_desc, cs.d_state,
+                       cs.d_start[v], (int)cs.desc.size(), cs.total_blocks[v], kShapes[v].rows,
+                       kShapes[v].compact ? 1 : 0, colour, sc, or_only, cs.redo, flags);
 }
 
 // One half-sweep of every chain in shape v (the e(T, L) runs use the plain
@@ -1048,14 +1169,15 @@ void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colo
             case 4: launch_half_compact<4>(st, cs, v, colour, sc); break;
             default: launch_half_compact<8>(st, cs, v, colour, sc); break;
         }
-        return;
+    } else {
+        switch (sh.rows) {
+            case 1: launch_half_rows<1>(st, cs, v, table, colour, sc); break;
+            case 2: launch_half_rows<2>(st, cs, v, table, colour, sc); break;
+            case 4: launch_half_rows<4>(st, cs, v, table, colour, sc); break;
+            default: launch_half_rows<8>(st, cs, v, table, colour, sc); break;
+        }
     }
-    switch (sh.rows) {
-        case 1: launch_half_rows<1>(st, cs, v, table, colour, sc); break;
-        case 2: launch_half_rows<2>(st, cs, v, table, colour, sc); break;
-        case 4: launch_half_rows<4>(st, cs, v, table, colour, sc); break;
-        default: launch_half_rows<8>(st, cs, v, table, colour, sc); break;
-    }
+    launch_redo<false>(st, cs, v, colour, sc, 0, nullptr);
 }
 
 // Runs sweeps until every chain is done.  Returns 0 or an error code.
@@ -1186,6 +1308,17 @@ int upload_starts(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream)
     int64_t *d = (int64_t *)cv.take((int64_t)h.size() * 8);
     if (!d) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
     for (int k = 0; k < kNumShapes; ++k) cs.d_start[k] = d + (size_t)k * (n + 1);
+    int64_t words = 0, blocks = 0;
+    for (int k = 0; k < kNumShapes; ++k) {
+        words = std::max(words, cs.total_blocks[k] * redo_words(k));
+        blocks = std::max(blocks, cs.total_blocks[k]);
+    }
+    const int64_t mask_bytes = words * 4, bits_bytes = (blocks + 31) / 32 * 4;
+    cs.redo.mask = (uint32_t *)cv.take(mask_bytes);
+    cs.redo.blocks = (uint32_t *)cv.take(bits_bytes);
+    if (!cs.redo.mask || !cs.redo.blocks) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+    HIP_TRY(ctx, hipMemsetAsync(cs.redo.mask, 0, mask_bytes, stream));
+    HIP_TRY(ctx, hipMemsetAsync(cs.redo.blocks, 0, bits_bytes, stream));
     HIP_TRY(ctx, hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, stream));
     HIP_TRY(ctx, hipStreamSynchronize(stream));
     return MPR_OK;
@@ -1695,7 +1828,7 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t hg = half_grid_bytes(nx, ny);
-    const int64_t bytes = 2 * round_up(hg, 256) + 8192;
+    const int64_t bytes = 2 * round_up(hg, 256) + 8192 + redo_bytes(nx, ny, 1);
     void *buf = nullptr;
     HIP_TRY(ctx, hipMalloc(&buf, bytes));
     Carver cv{(char *)buf, bytes};
@@ -1728,30 +1861,32 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
     const SweepConsts sc = make_sc(q, seed);
     const dim3 grid((unsigned)cs.total_blocks[v]);
     const Shape sh = kShapes[v];
+    const Redo rd = cs.redo;
     if (sh.compact) {
         if (sh.rows == 2)
             hipLaunchKernelGGL((half_sweep_compact_kernel<true, 2>), grid, dim3(kBlock), 0, stream, cs.d_desc,
-                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, flags);
+                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, rd, flags);
         else if (sh.rows == 4)
             hipLaunchKernelGGL((half_sweep_compact_kernel<true, 4>), grid, dim3(kBlock), 0, stream, cs.d_desc,
-                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, flags);
+                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, rd, flags);
         else
             hipLaunchKernelGGL((half_sweep_compact_kernel<true, 8>), grid, dim3(kBlock), 0, stream, cs.d_desc,
-                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, flags);
+                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, rd, flags);
     } else {
         if (sh.rows == 1)
             hipLaunchKernelGGL((half_sweep_kernel<true, 1>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
-                               cs.d_start[v], 1, colour, sc, mode, flags);
+                               cs.d_start[v], 1, colour, sc, mode, rd, flags);
         else if (sh.rows == 2)
             hipLaunchKernelGGL((half_sweep_kernel<true, 2>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
-                               cs.d_start[v], 1, colour, sc, mode, flags);
+                               cs.d_start[v], 1, colour, sc, mode, rd, flags);
         else if (sh.rows == 4)
             hipLaunchKernelGGL((half_sweep_kernel<true, 4>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
-                               cs.d_start[v], 1, colour, sc, mode, flags);
+                               cs.d_start[v], 1, colour, sc, mode, rd, flags);
         else
             hipLaunchKernelGGL((half_sweep_kernel<true, 8>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
-                               cs.d_start[v], 1, colour, sc, mode, flags);
+                               cs.d_start[v], 1, colour, sc, mode, rd, flags);
     }
+    launch_redo<true>(stream, cs, v, colour, sc, mode, flags);
     hipLaunchKernelGGL(unsplit_kernel, dim3(blocks_for(nsite, 2048)), dim3(kBlock), 0, stream, cs.d_desc, phi);
     ChainState out;
     (void)hipMemcpyAsync(&out, cs.d_state, sizeof out, hipMemcpyDeviceToHost, stream);
