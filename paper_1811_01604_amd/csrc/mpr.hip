@@ -520,14 +520,22 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
     const int words = compact ? kCompactSites / 32 : 2 * kBlock / 32;
     const int ppr = compact ? kCompactSites / rows / 2 : kBlock / rows;  // site pairs per block row
     const int64_t nw = (total_blocks + 31) >> 5;
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t bits = rd.blocks[w];
-        if (!bits) continue;
-        rd.blocks[w] = 0u;
-        while (bits) {
-            const int b = __ffs(bits) - 1;
-            bits &= bits - 1u;
-            const int64_t gb = (w << 5) + b;
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    // each wave reads 64 bitmap words at a time; the 32 blocks of a flagged
+    // word go to lanes 0-31, so flagged sites of different blocks run in parallel
+    for (int64_t w0 = wave * 64; w0 < nw; w0 += n_waves * 64) {
+        const int64_t wl = w0 + lane;
+        const uint32_t mine_bits = wl < nw ? rd.blocks[wl] : 0u;
+        uint64_t todo = __ballot(mine_bits != 0u);
+        if (wl < nw && mine_bits) rd.blocks[wl] = 0u;
+        while (todo) {
+            const int src = __ffsll((long long)todo) - 1;
+            todo &= todo - 1ull;
+            const uint32_t bits = __shfl(mine_bits, src);
+            if (lane >= 32 || !((bits >> lane) & 1u)) continue;
+            const int64_t gb = ((w0 + src) << 5) + lane;
             const int c = find_chain(start, n_chains, gb);
             ChainState *stp = states + c;
             const ChainDesc d = descs[c];
