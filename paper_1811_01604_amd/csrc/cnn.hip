@@ -71,60 +71,203 @@ __device__ __forceinline__ void stage_tile(const bf16 *__restrict__ src, bf16 *t
     }
 }
 
-__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
+// Forward convolution (and, with the dgrad packing, the input gradient).
+// Persistent blocks of 4 waves loop over 16 x 32-pixel output tiles.  The
+// layer's packed weights are copied to LDS once per block (rows of 32
+// input channels padded to 80 bytes, like the staged pixels, so 16-byte
+// reads are conflict-free); a tile's (16+2) x (32+2) input pixels are
+// staged in LDS, and the next tile's pixels are loaded into registers while
+// the current tile computes.  Wave w computes output rows 4w .. 4w+3 with
+// v_mfma_f32_32x32x16_bf16 taking the weights as A (32 output channels x 16
+// input channels) and the pixels as B (16 input channels x 32 pixels): per
+// column shift and channel half, the three taps' weight operands are read
+// once and each staged input row once, feeding the up to three output rows
+// it touches.  Each lane ends with 16 channels of one pixel (4 runs of 4),
+// so the epilogue moves 8-byte vectors, and the residual input of a tile is
+// loaded before its products so that it arrives while they run.
+constexpr int CTH = 16, CTW = 32;                 // output tile of the forward conv
+constexpr int C_IN_W = CTW + 2;                   // staged input columns
+constexpr int C_IN_T = (CTH + 2) * C_IN_W;        // staged input pixels
+constexpr int C_CHUNKS = C_IN_T * 4;              // 16-byte chunks per staged tile
+constexpr int C_PER_THREAD = (C_CHUNKS + 255) / 256;
+constexpr int C_W_ROWS = 9 * CH;                  // packed weight rows (tap, out-channel)
+
+__device__ __forceinline__ void conv_tile_origin(int tile, int tiles_x, int tiles_y, int &n, int &y0, int &x0)
 {
-    __shared__ __attribute__((aligned(16))) bf16 tile[IN_T * PIXS];
-    const int tiles_x = (a.W + TW - 1) / TW, tiles_y = (a.H + TH - 1) / TH;
-    int b = blockIdx.x;
-    const int tx = b % tiles_x;
-    b /= tiles_x;
-    const int ty = b % tiles_y;
-    const int n = b / tiles_y;
-    const int y0 = ty * TH, x0 = tx * TW;
-    stage_tile(a.in, tile, n, a.H, a.W, y0, x0, nullptr);
+    const int tx = tile % tiles_x;
+    const int rest = tile / tiles_x;
+    const int ty = rest % tiles_y;
+    n = rest / tiles_y;
+    y0 = ty * CTH;
+    x0 = tx * CTW;
+}
+
+// Loads this thread's chunks of a staged tile.  Every load is issued (a
+// chunk outside the image reads a clamped in-image address and its bit in
+// `valid` is cleared; conv_store_tile writes zeros for it): a fixed number of
+// loads in flight lets later waits for other loads leave these outstanding.
+__device__ __forceinline__ void conv_load_tile(const bf16 *__restrict__ src, int n, int H, int W, int y0, int x0,
+                                               uint4 (&r)[C_PER_THREAD], uint32_t &valid)
+{
+    valid = 0u;
+#pragma unroll
+    for (int j = 0; j < C_PER_THREAD; ++j) {
+        const int k = min((int)threadIdx.x + 256 * j, C_CHUNKS - 1);
+        const int chunk = k & 3, pix = k >> 2;
+        const int rr = pix / C_IN_W, cc = pix - rr * C_IN_W;
+        const int gy = y0 - 1 + rr, gx = x0 - 1 + cc;
+        const bool ok = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        valid |= ok ? (1u << j) : 0u;
+        const int gyc = min(max(gy, 0), H - 1), gxc = min(max(gx, 0), W - 1);
+        r[j] = *reinterpret_cast<const uint4 *>(src + (((int64_t)n * H + gyc) * W + gxc) * CH + chunk * 8);
+    }
+}
+
+__device__ __forceinline__ void conv_store_tile(bf16 *tile, const uint4 (&r)[C_PER_THREAD], uint32_t valid)
+{
+#pragma unroll
+    for (int j = 0; j < C_PER_THREAD; ++j) {
+        const int k = (int)threadIdx.x + 256 * j;
+        if (k < C_CHUNKS)
+            *reinterpret_cast<uint4 *>(tile + (k >> 2) * PIXS + (k & 3) * 8) =
+                ((valid >> j) & 1u) ? r[j] : make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+// SIDE: bit 0 = the layer adds a residual input, bit 1 = its output is
+// zeroed where a ReLU reference is <= 0 (the residual, else the reference,
+// is loaded ahead; with both, the reference is read in the epilogue)
+template <int SIDE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void conv3x3_kernel(ConvArgs a)
+{
+    __shared__ __attribute__((aligned(16))) bf16 tile[C_IN_T * PIXS];
+    __shared__ __attribute__((aligned(16))) bf16 wl[C_W_ROWS * PIXS];
+    __shared__ float bl[CH];
+    const int tiles_x = (a.W + CTW - 1) / CTW, tiles_y = (a.H + CTH - 1) / CTH;
+    const int n_tiles = tiles_x * tiles_y * a.N;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, kq = lane >> 5;
-    // B operands (weights): lane holds out-channel m, in-channels kh*16 + kq*8 .. +7
-    bf16x8 wb[9][2];
-#pragma unroll
-    for (int t = 0; t < 9; ++t)
-#pragma unroll
-        for (int kh = 0; kh < 2; ++kh)
-            wb[t][kh] = *reinterpret_cast<const bf16x8 *>(a.w + ((t * CH + m) * CH + kh * 16 + kq * 8));
+    for (int k = threadIdx.x; k < C_W_ROWS * 4; k += blockDim.x)
+        *reinterpret_cast<uint4 *>(wl + (k >> 2) * PIXS + (k & 3) * 8) =
+            *reinterpret_cast<const uint4 *>(a.w + (k >> 2) * CH + (k & 3) * 8);
+    if (threadIdx.x < CH) bl[threadIdx.x] = a.bias ? a.bias[threadIdx.x] : 0.0f;
+    uint4 pre[C_PER_THREAD];
+    uint32_t pre_valid = 0u;
+    int tile_id = blockIdx.x;
+    if (tile_id < n_tiles) {
+        int n, y0, x0;
+        conv_tile_origin(tile_id, tiles_x, tiles_y, n, y0, x0);
+        conv_load_tile(a.in, n, a.H, a.W, y0, x0, pre, pre_valid);
+        conv_store_tile(tile, pre, pre_valid);
+    }
     __syncthreads();
+    // Per tile: side loads, next tile's loads, products from LDS; barrier;
+    // the next tile into LDS (its wait comes before this tile's stores, so
+    // it never waits for them); epilogue; barrier.
+    for (; tile_id < n_tiles; tile_id += gridDim.x) {
+        int n, y0, x0;
+        conv_tile_origin(tile_id, tiles_x, tiles_y, n, y0, x0);
+        // D: lane holds pixel column m, channels 8 j + 4 kq + (0 .. 3) in acc[4 j .. 4 j + 3]
+        const int gx = x0 + m;
+        // the residual input (or the ReLU reference of a gradient) of the
+        // tile's outputs, loaded ahead of the products
+        uint2 addv[4][4];
+        const bf16 *side = (SIDE & 1) ? a.add : a.ref;
+        if (SIDE) {
+            // outputs outside the image are never stored: their loads read a
+            // clamped pixel instead of being selected away, so that no wait
+            // for these loads (or the prefetch after them) is needed here
+            const int gxc = min(gx, a.W - 1);
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-        const int row = wave * 2 + mt;
-        f32x16 acc;
+            for (int o = 0; o < 4; ++o) {
+                const int gyc = min(y0 + 4 * wave + o, a.H - 1);
+                const int64_t pix = ((int64_t)n * a.H + gyc) * a.W + gxc;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+                for (int j = 0; j < 4; ++j)
+                    addv[o][j] = *reinterpret_cast<const uint2 *>(side + pix * CH + 8 * j + 4 * kq);
+            }
+        }
+        // the next tile's pixels, issued after the side loads (the wait
+        // counter is in order) and unconditionally (a fixed count in flight;
+        // a block's last tile re-reads itself)
+        {
+            const int next = tile_id + (int)gridDim.x < n_tiles ? tile_id + (int)gridDim.x : tile_id;
+            int n2, y2, x2;
+            conv_tile_origin(next, tiles_x, tiles_y, n2, y2, x2);
+            conv_load_tile(a.in, n2, a.H, a.W, y2, x2, pre, pre_valid);
+        }
+        // keep the loads above ahead of the products (the scheduler would
+        // otherwise sink them to their use and expose their latency)
+        __builtin_amdgcn_sched_barrier(0);
+        f32x16 acc[4];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int dy = t / 3 - 1, dx = t % 3 - 1;
-            // A operand: pixel (row + dy, m + dx), channels kh*16 + kq*8 .. +7
-            const bf16 *src = tile + ((row + 1 + dy) * (TW + 2) + (m + 1 + dx)) * PIXS + kq * 8;
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[o][i] = 0.0f;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
             for (int kh = 0; kh < 2; ++kh) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(src + kh * 16);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, wb[t][kh], acc, 0, 0, 0);
-            }
-        }
-        // D: lane holds out-channel m for tile columns 8 (i/4) + 4 kq + (i%4)
-        const int gy = y0 + row;
-        if (gy < a.H) {
-            const float bias = a.bias ? a.bias[m] : 0.0f;
+                // weights of taps (dy, dx - 1), dy = -1, 0, 1: out-channel m, in-channels kh*16 + kq*8 .. +7
+                bf16x8 wa[3];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int gx = x0 + 8 * (i >> 2) + 4 * kq + (i & 3);
-                if (gx >= a.W) continue;
-                const int64_t idx = (((int64_t)n * a.H + gy) * a.W + gx) * CH + m;
-                float v = acc[i] + bias;
-                if (a.add) v += (float)a.add[idx];
-                if (a.relu) v = fmaxf(v, 0.0f);
-                if (a.ref && !((float)a.ref[idx] > 0.0f)) v = 0.0f;
-                a.out[idx] = (bf16)v;
+                for (int d = 0; d < 3; ++d)
+                    wa[d] = *reinterpret_cast<const bf16x8 *>(wl + ((d * 3 + dx) * CH + m) * PIXS + kh * 16 + kq * 8);
+                // staged row ir is input row 4 wave + ir - 1 of the tile
+#pragma unroll
+                for (int ir = 0; ir < 6; ++ir) {
+                    const bf16x8 pb = *reinterpret_cast<const bf16x8 *>(
+                        tile + ((4 * wave + ir) * C_IN_W + m + dx) * PIXS + kh * 16 + kq * 8);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const int o = ir - d;  // output row fed through tap dy = d - 1
+                        if (o < 0 || o > 3) continue;
+                        acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[d], pb, acc[o], 0, 0, 0);
+                    }
+                }
+            }
+        __syncthreads();  // every wave is done reading this tile from LDS
+        if (tile_id + (int)gridDim.x < n_tiles) conv_store_tile(tile, pre, pre_valid);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int gy = y0 + 4 * wave + o;
+            if (gy >= a.H || gx >= a.W) continue;
+            const int64_t pix = ((int64_t)n * a.H + gy) * a.W + gx;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c0 = 8 * j + 4 * kq;
+                const int64_t idx = pix * CH + c0;
+                float v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = acc[o][4 * j + r] + bl[c0 + r];
+                if (SIDE & 1) {
+                    // bf16 -> float by bit position (keeps the loaded words whole until here)
+                    const uint2 w2 = addv[o][j];
+                    v[0] += __uint_as_float(w2.x << 16);
+                    v[1] += __uint_as_float(w2.x & 0xFFFF0000u);
+                    v[2] += __uint_as_float(w2.y << 16);
+                    v[3] += __uint_as_float(w2.y & 0xFFFF0000u);
+                }
+                if (a.relu)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r], 0.0f);
+                if (SIDE & 2) {
+                    // prefetched unless the layer also has a residual input
+                    const uint2 rf = (SIDE & 1) ? *reinterpret_cast<const uint2 *>(a.ref + idx) : addv[o][j];
+                    const float rv[4] = {__uint_as_float(rf.x << 16), __uint_as_float(rf.x & 0xFFFF0000u),
+                                         __uint_as_float(rf.y << 16), __uint_as_float(rf.y & 0xFFFF0000u)};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (!(rv[r] > 0.0f)) v[r] = 0.0f;
+                }
+                uint2 ov;
+                bf16 *op = reinterpret_cast<bf16 *>(&ov);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) op[r] = (bf16)v[r];
+                *reinterpret_cast<uint2 *>(a.out + idx) = ov;
             }
         }
+        __syncthreads();  // the next tile is in LDS
     }
 }
 
@@ -365,7 +508,15 @@ void launch_conv(hipStream_t st, const bf16 *in, const bf16 *wpack, const float 
     a.H = h;
     a.W = w;
     a.relu = relu;
-    hipLaunchKernelGGL(conv3x3_kernel, dim3((unsigned)conv_blocks(n, h, w)), dim3(256), 0, st, a);
+    // persistent: two blocks per compute unit (256 CUs), or one per tile if fewer
+    const int64_t tiles = (int64_t)n * ((h + CTH - 1) / CTH) * ((w + CTW - 1) / CTW);
+    const dim3 grid((unsigned)std::min<int64_t>(tiles, 512));
+    switch ((add ? 1 : 0) | (ref ? 2 : 0)) {
+        case 0: hipLaunchKernelGGL(conv3x3_kernel<0>, grid, dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL(conv3x3_kernel<1>, grid, dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL(conv3x3_kernel<2>, grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL(conv3x3_kernel<3>, grid, dim3(256), 0, st, a); break;
+    }
 }
 
 void launch_wgrad(hipStream_t st, const bf16 *in, const bf16 *gout, const bf16 *gref, float *partial, float *grads,

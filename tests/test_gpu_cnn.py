@@ -98,6 +98,8 @@ def test_conv_forward_and_epilogues(ctx, shape):
     close(from_dev(out), cnn.conv(x, W, b) + add)
     ctx.cnn_diag_conv(xd, fwd, None, out, ref=refd)
     close(from_dev(out), cnn.conv(x, W) * (ref > 0))
+    ctx.cnn_diag_conv(xd, fwd, bias, out, add=addd, ref=refd, relu=True)
+    close(from_dev(out), np.maximum(cnn.conv(x, W, b) + add, 0) * (ref > 0))
 
 
 @pytest.mark.parametrize("shape", [(2, 19, 45), (1, 40, 64)])
