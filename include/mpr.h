@@ -92,7 +92,9 @@ typedef struct {
     uint64_t seed;        /* Philox key */
     int32_t sweeps_per_launch;  /* sweeps per captured graph between done-checks;
                                    0 = chosen from the measured sweep time */
-    int32_t reserved;
+    int32_t spread;       /* 1: also keep, per chain and site, the squared deviations
+                             of the equilibrium states from their running mean (K > 1;
+                             needed for mpr_simulate's phi_m2 then; more workspace) */
 } mpr_params;
 
 /* Per chain results of mpr_simulate (R per image, image-major). */
@@ -167,13 +169,20 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_
  *   T_hat (host, double[n_images])
  *   phi_init (dev, float, nullable)  starting gap angles in [0, 2 pi)
  *   phi_sum (dev, float, out)  sum of the M = R*K states at gap sites, 0 at samples
+ *   phi_m2 (dev, float, out, nullable)  sum over the M states of (phi - mean)^2
+ *           at gap sites, 0 at samples (the realizations' spread; Algorithm 2
+ *           step 7 returns statistics of the M realizations).  With K > 1 it
+ *           needs p->spread = 1 (each chain keeps a running sum of squared
+ *           deviations, Welford's update); chains are combined with the
+ *           spread of their means.
  *   stats (host, mpr_chain_stats[n_images * R], out, nullable)
  * An image without gaps is left unchanged (phi_sum 0).
- * Errors: MPR_ERR_WORKSPACE if ws_bytes is too small. */
+ * Errors: MPR_ERR_WORKSPACE if ws_bytes is too small; MPR_ERR_ARG for phi_m2
+ * with K > 1 and p->spread = 0. */
 int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
                      const float *phi, const uint8_t *sampled, const double *T_hat,
                      const mpr_params *p, const float *phi_init, void *workspace,
-                     int64_t ws_bytes, float *phi_sum, mpr_chain_stats *stats,
+                     int64_t ws_bytes, float *phi_sum, float *phi_m2, mpr_chain_stats *stats,
                      void *stream);
 
 /* Algorithm 2 steps 6.3 and 7 with the mean as the statistic:
@@ -183,6 +192,15 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
 int32_t mpr_predict(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
                     const float *z, const uint8_t *sampled, const float *phi_sum,
                     const double *zmin_zmax, int32_t M, float *z_hat, void *stream);
+
+/* Spread of the prediction (Algorithm 2 step 7, statistics of the M
+ * realizations besides their mean): z_std = standard deviation over the M
+ * states of G^{-1}(phi) = (z_max - z_min) / (2 pi) sqrt(phi_m2 / (M - 1)) at
+ * gap sites; 0 at sampled sites and when M = 1.
+ *   sampled, phi_m2 (from mpr_simulate), z_std (out): dev; zmin_zmax: host. */
+int32_t mpr_spread(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
+                   const uint8_t *sampled, const float *phi_m2, const double *zmin_zmax,
+                   int32_t M, float *z_std, void *stream);
 
 /* ------------------------------------------------------------------ */
 /* Warm start: a residual CNN that predicts starting gap angles from the

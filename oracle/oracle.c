@@ -32,6 +32,9 @@
  *  - e(T, L) comes from unconditional runs started from phi = pi, with the
  *    relaxation-phase rule for a, averaged over the measured sweeps; the
  *    temperature is read off a monotone fit of log(1 + e) against log T.
+ *  - Besides the mean, the statistic of the M realizations reported is
+ *    their sample standard deviation (denominator M - 1) after the back
+ *    transform, which is linear in phi.
  */
 #include <math.h>
 #include <stdint.h>
@@ -323,7 +326,7 @@ double oracle_sg_slope(const double *e, int n, int degree)
  * chain. */
 int oracle_simulate(int nx, int ny, const double *phi, const uint8_t *sampled, double T,
                     const oracle_params *p, const double *phi_init, double *phi_sum,
-                    oracle_chain_stats *stats, double *e_trace, int trace_len,
+                    double *phi_sq_sum, oracle_chain_stats *stats, double *e_trace, int trace_len,
                     double *phi_last)
 {
     if (nx <= 0 || ny <= 0 || p->R < 1 || p->K < 0 || !(T > 0.0) || p->n_f < 1 || p->n_fit < 2)
@@ -333,6 +336,8 @@ int oracle_simulate(int nx, int ny, const double *phi, const uint8_t *sampled, d
     for (long i = 0; i < n; ++i) if (!sampled[i]) ++P;
     double n_gp = (double)oracle_bond_count(nx, ny);
     for (long i = 0; i < n; ++i) phi_sum[i] = 0.0;
+    if (phi_sq_sum)
+        for (long i = 0; i < n; ++i) phi_sq_sum[i] = 0.0;
     double *s = (double *)malloc(sizeof(double) * n);
     int cap = (p->fixed_relax >= 0 ? p->fixed_relax : p->i_max + 1) + 1;
     double *eh = (double *)malloc(sizeof(double) * (size_t)cap);
@@ -391,7 +396,10 @@ int oracle_simulate(int nx, int ny, const double *phi, const uint8_t *sampled, d
             }
             ++t;
             for (long i = 0; i < n; ++i)
-                if (!sampled[i]) phi_sum[i] += s[i];
+                if (!sampled[i]) {
+                    phi_sum[i] += s[i];
+                    if (phi_sq_sum) phi_sq_sum[i] += s[i] * s[i];
+                }
         }
         if (phi_last && r == p->R - 1) memcpy(phi_last, s, sizeof(double) * n);
     }
@@ -414,6 +422,26 @@ void oracle_predict(int nx, int ny, const double *z, const uint8_t *sampled, con
             double t = (phi_sum[i] / (double)M) / O_TWO_PI;
             z_hat[i] = zmin_zmax[0] * (1.0 - t) + zmin_zmax[1] * t;
         }
+    }
+}
+
+/* Algorithm 2 step 7, the realizations' spread: the sample standard
+ * deviation over the M states of z = G^{-1}(phi), with G^{-1} linear in phi:
+ * z_std = (z_max - z_min) / (2 pi) * sqrt((S2 - S1^2 / M) / (M - 1)) for the
+ * sums S1 of phi and S2 of phi^2 (negative rounding residue clipped to 0);
+ * 0 at sampled sites and for M = 1. */
+void oracle_spread(int nx, int ny, const uint8_t *sampled, const double *phi_sum, const double *phi_sq_sum,
+                   int M, const double *zmin_zmax, double *z_std)
+{
+    long n = (long)nx * ny;
+    double scale = (zmin_zmax[1] - zmin_zmax[0]) / O_TWO_PI;
+    for (long i = 0; i < n; ++i) {
+        double v = 0.0;
+        if (!sampled[i] && M > 1) {
+            double m2 = phi_sq_sum[i] - phi_sum[i] * phi_sum[i] / (double)M;
+            v = scale * sqrt((m2 > 0.0 ? m2 : 0.0) / (double)(M - 1));
+        }
+        z_std[i] = v;
     }
 }
 

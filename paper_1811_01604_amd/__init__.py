@@ -22,7 +22,7 @@ FLAG_KEPT, FLAG_ACCEPTED, FLAG_WRAPPED, FLAG_UPDATED, FLAG_FP64 = 1, 2, 4, 8, 16
 # Every symbol include/mpr.h declares.
 EXPORTS = [
     "mpr_create", "mpr_destroy", "mpr_last_error", "mpr_default_params", "mpr_workspace_size",
-    "mpr_map_to_angles", "mpr_estimate_temperature", "mpr_simulate", "mpr_predict",
+    "mpr_map_to_angles", "mpr_estimate_temperature", "mpr_simulate", "mpr_predict", "mpr_spread",
     "mpr_profile_enable", "mpr_profile_read",
     "mpr_cnn_param_count", "mpr_cnn_packed_bytes", "mpr_cnn_workspace_size", "mpr_cnn_pack", "mpr_cnn_encode",
     "mpr_cnn_forward", "mpr_cnn_loss", "mpr_cnn_backward", "mpr_cnn_opt_step", "mpr_cnn_decode",
@@ -54,7 +54,7 @@ class Params(C.Structure):
         ("eq_a_mode", C.c_int32), ("table_nT", C.c_int32), ("table_burn", C.c_int32),
         ("table_meas", C.c_int32), ("tile_rows", C.c_int32), ("table_T_lo", C.c_double),
         ("table_T_hi", C.c_double), ("seed", C.c_uint64), ("sweeps_per_launch", C.c_int32),
-        ("reserved", C.c_int32),
+        ("spread", C.c_int32),
     ]
 
 
@@ -113,8 +113,9 @@ def _declare(L):
         "mpr_workspace_size": (i64, [IMG, i32, PRM]),
         "mpr_map_to_angles": (i32, [P, IMG, i32, P, P, P, P, P]),
         "mpr_estimate_temperature": (i32, [P, IMG, i32, P, P, PRM, P, i64, P, P, P, P]),
-        "mpr_simulate": (i32, [P, IMG, i32, P, P, P, PRM, P, P, i64, P, C.POINTER(ChainStats), P]),
+        "mpr_simulate": (i32, [P, IMG, i32, P, P, P, PRM, P, P, i64, P, P, C.POINTER(ChainStats), P]),
         "mpr_predict": (i32, [P, IMG, i32, P, P, P, P, i32, P, P]),
+        "mpr_spread": (i32, [P, IMG, i32, P, P, P, i32, P, P]),
         "mpr_cnn_param_count": (i64, []),
         "mpr_cnn_packed_bytes": (i64, []),
         "mpr_cnn_workspace_size": (i64, [i32, i32, i32, i32]),
@@ -223,13 +224,14 @@ class Context:
             _stream(stream)))
         return e_s, T, cl
 
-    def simulate(self, imgs, phi, sampled, T_hat, params, ws, phi_sum, phi_init=None, stream=None):
+    def simulate(self, imgs, phi, sampled, T_hat, params, ws, phi_sum, phi_init=None, stream=None, phi_m2=None):
         n = len(imgs)
         T = np.ascontiguousarray(T_hat, dtype=np.float64)
         st = (ChainStats * (n * params.R))()
         self._check(self.lib.mpr_simulate(
             self._h, imgs, n, _ptr(phi), _ptr(sampled), T.ctypes.data_as(C.c_void_p), C.byref(params),
-            _ptr(phi_init), _ptr(ws), ws.numel() * ws.element_size(), _ptr(phi_sum), st, _stream(stream)))
+            _ptr(phi_init), _ptr(ws), ws.numel() * ws.element_size(), _ptr(phi_sum), _ptr(phi_m2), st,
+            _stream(stream)))
         return [dict(relax_sweeps=s.relax_sweeps, not_converged=s.not_converged, a_final=s.a_final,
                      A_last=s.A_last, k_last=s.k_last) for s in st]
 
@@ -237,6 +239,11 @@ class Context:
         zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)
         self._check(self.lib.mpr_predict(self._h, imgs, len(imgs), _ptr(z), _ptr(sampled), _ptr(phi_sum),
                                          zz.ctypes.data_as(C.c_void_p), M, _ptr(z_hat), _stream(stream)))
+
+    def spread(self, imgs, sampled, phi_m2, zmin_zmax, M, z_std, stream=None):
+        zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)
+        self._check(self.lib.mpr_spread(self._h, imgs, len(imgs), _ptr(sampled), _ptr(phi_m2),
+                                        zz.ctypes.data_as(C.c_void_p), M, _ptr(z_std), _stream(stream)))
 
     # -------------------------------------------------------- warm start
     # Tensors: x, y, dy are (n, h, w, 32) bfloat16; phi, sampled (n, h, w);

@@ -120,6 +120,7 @@ __global__ void init_chains_kernel(const ChainDesc *__restrict__ descs, const in
         }
         d.h[c][(int64_t)y * d.S + h] = v;
         if (d.acc[c]) d.acc[c][(int64_t)y * d.S + h] = 0.0f;
+        if (d.m2[c]) d.m2[c][(int64_t)y * d.S + h] = 0.0f;
     }
 }
 
@@ -224,8 +225,11 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
             float *accp = colour ? d.acc[1] : d.acc[0];
             if (phase == PH_EQ && accp) {
                 float *acc = accp + (int64_t)y * d.S;
-                if (w0) acc[h0] += out0;
-                if (w1) acc[h0 + 1] += out1;
+                float *m2p = colour ? d.m2[1] : d.m2[0];
+                float *m2 = m2p ? m2p + (int64_t)y * d.S : nullptr;
+                const float ik = stp->inv_k, ikm1 = stp->inv_km1;
+                if (w0) accumulate_state(acc + h0, m2 ? m2 + h0 : nullptr, out0, ik, ikm1);
+                if (w1) accumulate_state(acc + h0 + 1, m2 ? m2 + h0 + 1 : nullptr, out1, ik, ikm1);
             }
             acc_thread = (w0 && o0.accepted ? 1u : 0u) + (w1 && o1.accepted ? 1u : 0u);
             // a sampled site's bonds are unchanged by this half-sweep
@@ -329,6 +333,7 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
     float *const mine_base = colour ? d.h[1] : d.h[0];
     const float *const oth_base = colour ? d.h[0] : d.h[1];
     float *const acc_base = (phase == PH_EQ) ? (colour ? d.acc[1] : d.acc[0]) : nullptr;
+    float *const m2_base = acc_base ? (colour ? d.m2[1] : d.m2[0]) : nullptr;
 
     // pass 1: pairs t and t + 256 of the block
     bool gap[2][2], fix[2][2];
@@ -451,7 +456,9 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
             continue;
         }
         *mp = o.phi;
-        if (acc_base) acc_base[(int64_t)y * d.S + h] += o.phi;
+        if (acc_base)
+            accumulate_state(acc_base + (int64_t)y * d.S + h, m2_base ? m2_base + (int64_t)y * d.S + h : nullptr,
+                             o.phi, stp->inv_k, stp->inv_km1);
         acc_thread += o.accepted ? 1u : 0u;
         if (want_energy) e_thread += energy_fx(o.e_bonds);
         if (DIAG && flags) flags[(int64_t)y * d.nx + 2 * h + s] = (uint8_t)o.flags;
@@ -549,6 +556,7 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
             float *mine = colour ? d.h[1] : d.h[0];
             const float *oth = colour ? d.h[0] : d.h[1];
             float *accp = (phase == PH_EQ) ? (colour ? d.acc[1] : d.acc[0]) : nullptr;
+            float *m2p = accp ? (colour ? d.m2[1] : d.m2[0]) : nullptr;
             for (int k = 0; k < words; ++k) {
                 uint32_t m = rd.mask[gb * words + k];
                 if (!m) continue;
@@ -582,7 +590,9 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
                     const SiteOut o = update_site_fp64((double)a, nL, nR, nU, nD, valid, (double)u, (double)r,
                                                        stp->a_cur, stp->T, sc.q64, or_only != 0);
                     *mp = o.phi;
-                    if (accp) accp[(int64_t)y * d.S + h] += o.phi;
+                    if (accp)
+                        accumulate_state(accp + (int64_t)y * d.S + h, m2p ? m2p + (int64_t)y * d.S + h : nullptr,
+                                         o.phi, stp->inv_k, stp->inv_km1);
                     if (want_acc && o.accepted) atomicAdd(&stp->acc, 1ull);
                     if (want_energy) atomicAdd(&stp->e_fx, (unsigned long long)energy_fx(o.e_bonds));
                     if (DIAG && flags) flags[(int64_t)y * d.nx + 2 * h + s] = (uint8_t)o.flags;
@@ -636,10 +646,18 @@ __global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *
             st.eq_left = cp.K;
             st.phase = cp.K > 0 ? PH_EQ : PH_DONE;
             st.a_cur = cp.eq_a_mode ? st.a_relax : 1.0;
+            st.inv_k = 1.0f;
+            st.inv_km1 = 0.0f;
         }
     } else if (st.phase == PH_EQ) {
         st.sweep = t + 1u;
-        if (--st.eq_left <= 0) st.phase = PH_DONE;
+        if (--st.eq_left <= 0) {
+            st.phase = PH_DONE;
+        } else {
+            const int k = cp.K - st.eq_left + 1;  // the next sweep's state number
+            st.inv_k = 1.0f / (float)k;
+            st.inv_km1 = 1.0f / (float)(k - 1);
+        }
     } else {  // PH_TABLE
         const double A = (double)acc / (double)d.P;
         if (A < cp.a_targ) st.a_relax = 1.0 + (double)(t + 1u) / cp.k_a;
@@ -654,23 +672,54 @@ __global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *
 }
 
 // phi_sum at every site of image blockIdx.y: sum over its R chains of the
-// equilibrium sums (K > 1) or the final states (K == 1).
+// equilibrium sums (K > 1) or the final states (K == 1).  With phi_m2, also
+// the sum over the R K states of the squared deviation from their mean: two
+// passes over the R final states (K == 1), or the chains' own sums combined
+// with the spread of their means (Chan et al.'s pairwise rule, K > 1).
 __global__ void finalize_kernel(const ChainDesc *__restrict__ descs, const ImgDev *__restrict__ imgs, int R,
-                                int K, const uint8_t *__restrict__ sampled, float *__restrict__ phi_sum)
+                                int K, const uint8_t *__restrict__ sampled, float *__restrict__ phi_sum,
+                                float *__restrict__ phi_m2)
 {
     const ImgDev im = imgs[blockIdx.y];
     const int64_t n = (int64_t)im.nx * im.ny;
     const ChainDesc *dc = descs + (int64_t)blockIdx.y * R;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        float s = 0.0f;
+        float s = 0.0f, q = 0.0f;
         if (!sampled[im.offset + i] && K > 0) {
             const int y = (int)(i / im.nx);
             const int x = (int)(i - (int64_t)y * im.nx);
             const int c = (x + y) & 1;
             const int64_t j = (int64_t)y * dc[0].S + (x >> 1);
             for (int r = 0; r < R; ++r) s += (K > 1) ? dc[r].acc[c][j] : angle_of(dc[r].h[c][j]);
+            if (phi_m2) {
+                const float mean = s / (float)(R * K);
+                for (int r = 0; r < R; ++r) {
+                    const float d = ((K > 1) ? dc[r].acc[c][j] / (float)K : angle_of(dc[r].h[c][j])) - mean;
+                    q = fmaf((float)K * d, d, q);
+                    if (K > 1) q += dc[r].m2[c][j];
+                }
+            }
         }
         phi_sum[im.offset + i] = s;
+        if (phi_m2) phi_m2[im.offset + i] = q;
+    }
+}
+
+// Spread of the prediction: the standard deviation over the M realizations
+// of z = G^{-1}(phi), which is (z_max - z_min) / (2 pi) times that of phi,
+// sqrt(m2 / (M - 1)); zero at sampled sites and for M = 1.
+__global__ void spread_kernel(const ImgDev *__restrict__ imgs, const double *__restrict__ zmin_zmax, int M,
+                              const uint8_t *__restrict__ sampled, const float *__restrict__ phi_m2,
+                              float *__restrict__ z_std)
+{
+    const ImgDev im = imgs[blockIdx.y];
+    const int64_t n = (int64_t)im.nx * im.ny;
+    const double scale = (zmin_zmax[2 * blockIdx.y + 1] - zmin_zmax[2 * blockIdx.y]) / kTwoPi;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = im.offset + i;
+        float v = 0.0f;
+        if (!sampled[k] && M > 1) v = (float)(scale * sqrt(fmax((double)phi_m2[k], 0.0) / (double)(M - 1)));
+        z_std[k] = v;
     }
 }
 
@@ -995,7 +1044,7 @@ bool valid_params(const mpr_params *p)
            p->k_a > 0.0 && p->a_targ >= 0.0 && p->table_nT >= 2 && p->table_meas >= 1 && p->table_burn >= 0 &&
            p->table_T_lo > 0.0 && p->table_T_hi > p->table_T_lo &&
            (p->tile_rows == 0 || shape_of(p->tile_rows) >= 0) &&
-           p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096;
+           p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096 && (p->spread == 0 || p->spread == 1);
 }
 
 bool valid_images(const mpr_image *imgs, int n)
@@ -1014,7 +1063,7 @@ int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     int64_t b = 0;
     for (int i = 0; i < n; ++i) {
         const int64_t hg = round_up(half_grid_bytes(imgs[i].nx, imgs[i].ny), 256);
-        b += (int64_t)p->R * 2 * hg * (p->K > 1 ? 2 : 1);
+        b += (int64_t)p->R * 2 * hg * (p->K > 1 ? (p->spread ? 3 : 2) : 1);
     }
     const int64_t chains = (int64_t)n * p->R;
     b += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
@@ -1342,6 +1391,8 @@ ChainState fresh_state(double T, int phase)
     s.a_cur = 1.0;
     s.a_relax = 1.0;
     s.k = -1.0;
+    s.inv_k = 1.0f;
+    s.inv_km1 = 0.0f;
     return s;
 }
 
@@ -1363,7 +1414,7 @@ int upload_chains(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream, do
 }
 
 // Allocates both half-grids (and accumulators) of a chain from the workspace.
-bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc)
+bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc, bool with_m2 = false)
 {
     const int64_t hg = half_grid_bytes(nx, ny);
     d.nx = nx;
@@ -1372,7 +1423,8 @@ bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc)
     for (int c = 0; c < 2; ++c) {
         d.h[c] = (float *)cv.take(hg);
         d.acc[c] = with_acc ? (float *)cv.take(hg) : nullptr;
-        if (!d.h[c] || (with_acc && !d.acc[c])) return false;
+        d.m2[c] = with_acc && with_m2 ? (float *)cv.take(hg) : nullptr;
+        if (!d.h[c] || (with_acc && !d.acc[c]) || (with_acc && with_m2 && !d.m2[c])) return false;
     }
     return true;
 }
@@ -1494,6 +1546,7 @@ void mpr_default_params(mpr_params *p)
     p->seed = 3000;
     p->tile_rows = 0;
     p->sweeps_per_launch = 0;
+    p->spread = 0;
 }
 
 int64_t mpr_workspace_size(const mpr_image *imgs, int32_t n, const mpr_params *p)
@@ -1651,11 +1704,13 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
 
 int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *phi, const uint8_t *sampled,
                      const double *T_hat, const mpr_params *p, const float *phi_init, void *ws, int64_t ws_bytes,
-                     float *phi_sum, mpr_chain_stats *stats, void *stream_)
+                     float *phi_sum, float *phi_m2, mpr_chain_stats *stats, void *stream_)
 {
     if (!ctx) return MPR_ERR_ARG;
     if (!valid_images(imgs, n) || !valid_params(p) || !phi || !sampled || !T_hat || !phi_sum)
         return fail(ctx, MPR_ERR_ARG, "simulate: invalid argument");
+    if (phi_m2 && p->K > 1 && !p->spread)
+        return fail(ctx, MPR_ERR_ARG, "simulate: phi_m2 with K > 1 needs params.spread = 1");
     for (int b = 0; b < n; ++b)
         if (!(T_hat[b] > 0.0) || !std::isfinite(T_hat[b])) return fail(ctx, MPR_ERR_ARG, "image %d: bad T_hat", b);
     if (!ws || ws_bytes < sim_bytes(imgs, n, p)) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
@@ -1699,7 +1754,8 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
         for (int r = 0; r < p->R; ++r) {
             ChainDesc d;
             std::memset(&d, 0, sizeof d);
-            if (!carve_chain(cv, d, nx, ny, p->K > 1)) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+            if (!carve_chain(cv, d, nx, ny, p->K > 1, p->spread != 0))
+                return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
             d.image_id = imgs[b].id;
             d.chain = (uint32_t)r;
             d.P = gaps[b];
@@ -1731,7 +1787,7 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
     rc = run_chains(ctx, cs, p, stream, relax_cap + p->K + 1, p->n_f, false);
     if (rc) return rc;
     hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, cs.d_desc, d_img,
-                       p->R, p->K, sampled, phi_sum);
+                       p->R, p->K, sampled, phi_sum, phi_m2);
     HIP_TRY(ctx, hipGetLastError());
     if (stats) {
         HIP_TRY(ctx, hipMemcpyAsync(cs.state.data(), cs.d_state, cs.state.size() * sizeof(ChainState),
@@ -1776,6 +1832,34 @@ int32_t mpr_predict(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float 
                        sampled, phi_sum, z_hat);
     HIP_TRY(ctx, hipGetLastError());
     // the host arrays above must outlive the copies
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    return MPR_OK;
+}
+
+int32_t mpr_spread(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const uint8_t *sampled, const float *phi_m2,
+                   const double *zmin_zmax, int32_t M, float *z_std, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!valid_images(imgs, n) || !sampled || !phi_m2 || !zmin_zmax || !z_std || M < 1)
+        return fail(ctx, MPR_ERR_ARG, "spread: invalid argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    const int64_t need = round_up((int64_t)n * sizeof(ImgDev), 256) + (int64_t)n * 16;
+    if (need > (int64_t)kScratchBytes - kVarOffset) return fail(ctx, MPR_ERR_ARG, "too many images in one call");
+    char *sp = (char *)ctx->scratch + kVarOffset;
+    ImgDev *d_img = (ImgDev *)sp;
+    double *d_zmm = (double *)(sp + round_up((int64_t)n * sizeof(ImgDev), 256));
+    std::vector<ImgDev> hi(n);
+    int64_t maxn = 0;
+    for (int b = 0; b < n; ++b) {
+        hi[b] = {imgs[b].offset, imgs[b].nx, imgs[b].ny};
+        maxn = std::max(maxn, (int64_t)imgs[b].nx * imgs[b].ny);
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(d_img, hi.data(), n * sizeof(ImgDev), hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_zmm, zmin_zmax, n * 16, hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(spread_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, d_img, d_zmm, M,
+                       sampled, phi_m2, z_std);
+    HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipStreamSynchronize(stream));
     return MPR_OK;
 }

@@ -29,10 +29,12 @@ constexpr int kMaxFit = 64;
 struct ChainDesc {
     float *h[2];          // colour half-grids, ny * S each
     float *acc[2];        // equilibrium sums (K > 1), or null
+    float *m2[2];         // sums of squared deviations from the running mean
+                          // of the equilibrium states (K > 1, spread wanted), or null
     int32_t nx, ny, S;    // grid size and half-row stride
     uint32_t image_id;    // Philox counter word 3
     uint32_t chain;       // Philox counter word 2
-    int32_t nbx;          // sweep blocks per 4-row band (64 site pairs each)
+    int32_t pad;
     int64_t P;            // number of gap sites
     int64_t ngp;          // number of bonds
 };
@@ -55,6 +57,8 @@ struct ChainState {
     int32_t relax_sweeps;
     int32_t not_converged;
     int32_t eq_left;
+    float inv_k;           // 1 / k and 1 / (k - 1) for the k-th equilibrium state
+    float inv_km1;         // of the next sweep (k = 1: 1 and 0)
     int32_t pad;
     double ring[kMaxFit];  // last n_fit values of 1 + e
 };
@@ -372,6 +376,18 @@ __device__ __forceinline__ float bond_energy_half(float th, float n0, float n1, 
         A2 = fmaf(s2, s2, A2);
     }
     return 0.5f * A2;
+}
+
+// Adds the k-th equilibrium state phi of a site to its running sum acc and,
+// when m2 is given, to the sum of squared deviations from the running mean
+// (Welford's update with the mean taken from the sum: mean_{k-1} = acc
+// inv_km1 before, mean_k = acc inv_k after; k = 1 adds exactly zero).
+__device__ __forceinline__ void accumulate_state(float *acc, float *m2, float phi, float inv_k, float inv_km1)
+{
+    const float s0 = *acc;
+    const float s1 = s0 + phi;
+    *acc = s1;
+    if (m2) *m2 = fmaf(phi - s0 * inv_km1, phi - s1 * inv_k, *m2);
 }
 
 // Bond energies of a site in fixed point: units of 2^-27, rounded, so that

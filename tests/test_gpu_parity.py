@@ -260,11 +260,17 @@ def pipeline_gpu(ctx, im, prm, T=None):
     if T is not None:
         T_hat = np.array([T])
     ps = torch.zeros_like(z)
-    st = ctx.simulate(imgs, phi, mk, T_hat, prm, ws, ps)
+    m2 = torch.zeros_like(z) if (prm.K <= 1 or prm.spread) else None
+    st = ctx.simulate(imgs, phi, mk, T_hat, prm, ws, ps, phi_m2=m2)
     zh = torch.zeros_like(z)
     ctx.predict(imgs, z, mk, ps, zz, prm.R * prm.K, zh)
-    return dict(phi=phi.cpu().numpy(), zz=zz, e_s=e_s[0], T=T_hat[0], clamped=cl[0], phi_sum=ps.cpu().numpy(),
-                stats=st, z_hat=zh.cpu().numpy())
+    out = dict(phi=phi.cpu().numpy(), zz=zz, e_s=e_s[0], T=T_hat[0], clamped=cl[0], phi_sum=ps.cpu().numpy(),
+               stats=st, z_hat=zh.cpu().numpy())
+    if m2 is not None:
+        zs = torch.zeros_like(z)
+        ctx.spread(imgs, mk, m2, zz, prm.R * prm.K, zs)
+        out.update(phi_m2=m2.cpu().numpy(), z_std=zs.cpu().numpy())
+    return out
 
 
 def test_temperature_estimate_matches_oracle(ctx):
@@ -381,15 +387,25 @@ def test_l1024_prediction_matches_oracle(ctx):
     difference is no larger than the GPU's own seed-to-seed spread."""
     im = synth.workload_l1024()
     say("L=1024 pipeline on the GPU")
-    prm = mpr.default_params(R=1, K=100, seed=3001)
+    prm = mpr.default_params(R=1, K=100, seed=3001, spread=1)
     g1 = pipeline_gpu(ctx, im, prm)
-    prm2 = mpr.default_params(R=1, K=100, seed=4001)
+    prm2 = mpr.default_params(R=1, K=100, seed=4001, spread=1)
     g2 = pipeline_gpu(ctx, im, prm2, T=g1["T"])
     say(f"  T_hat {g1['T']:.4e}, relax sweeps {g1['stats'][0]['relax_sweeps']}; oracle run (about 30 s)")
     zt = im.z.astype(np.float32).astype(np.float64)
-    ps, st, _, _ = oracle.simulate(g1["phi"].astype(np.float64), im.mask, g1["T"],
-                                   oracle.default_params(R=1, K=100, seed=3001))
+    ps, st, _, _, pq = oracle.simulate(g1["phi"].astype(np.float64), im.mask, g1["T"],
+                                       oracle.default_params(R=1, K=100, seed=3001), want_sq=True)
     zo = oracle.predict(zt, im.mask, ps, 100, g1["zz"])
+    # the realizations' spread (standard deviation of the 100 states per site)
+    so = oracle.spread(im.mask, ps, pq, 100, g1["zz"])
+    gap0 = im.mask == 0
+    m_g, m_g2, m_o = (float(np.mean(a[gap0])) for a in (g1["z_std"], g2["z_std"], so))
+    d_so = float(np.mean(np.abs(g1["z_std"][gap0] - so[gap0])))
+    d_ss = float(np.mean(np.abs(g1["z_std"][gap0] - g2["z_std"][gap0])))
+    say(f"  spread: mean z_std gpu {m_g:.5f} (seed 2: {m_g2:.5f}) oracle {m_o:.5f}; mean |gpu - oracle| "
+        f"{d_so:.3e}, |seed1 - seed2| {d_ss:.3e}")
+    assert abs(m_g / m_o - 1.0) <= 0.03
+    assert d_so <= 1.5 * d_ss
     gap = im.mask == 0
     mae_g = float(np.mean(np.abs(g1["z_hat"][gap] - zt[gap])))
     mae_g2 = float(np.mean(np.abs(g2["z_hat"][gap] - zt[gap])))
@@ -455,3 +471,41 @@ def test_half_sweep_identical_for_every_tile(ctx, shape, p_removed):
                 ref = out
             else:
                 assert out == ref, (tile, colour)
+
+
+@pytest.mark.parametrize("R,K", [(2, 3), (4, 1), (1, 5)])
+def test_spread_matches_oracle_early_sweeps(ctx, R, K):
+    """The realizations' spread after the first sweeps, where GPU and oracle
+    chains still agree site by site: the sum of squared deviations (Welford
+    per chain for K > 1, two passes over the final states for K = 1) and the
+    back-transformed standard deviation match the oracle's plain sums on
+    99% of gap sites; sampled sites are 0."""
+    im = synth.workload_l64()
+    prm = mpr.default_params(R=R, K=K, fixed_relax=0, seed=91, spread=1)
+    out = pipeline_gpu(ctx, im, prm, T=0.15)
+    opr = oracle.default_params(R=R, K=K, fixed_relax=0, seed=91)
+    ps, _, _, _, pq = oracle.simulate(out["phi"].astype(np.float64), im.mask, 0.15, opr, want_sq=True)
+    M = R * K
+    m2_o = pq - ps * ps / M
+    so = oracle.spread(im.mask, ps, pq, M, out["zz"])
+    g = im.mask == 0
+    ok_m2 = np.abs(out["phi_m2"][g] - m2_o[g]) <= 1e-4 * np.maximum(1.0, m2_o[g]) + 2e-5
+    ok_sd = np.abs(out["z_std"][g] - so[g]) <= 1e-3 * np.maximum(1.0, so[g]) + 1e-3
+    say(f"  R={R} K={K}: m2 agrees on {ok_m2.mean():.4f}, z_std on {ok_sd.mean():.4f} of gap sites")
+    assert ok_m2.mean() >= 0.99 and ok_sd.mean() >= 0.99
+    assert np.all(out["phi_m2"][~g] == 0) and np.all(out["z_std"][~g] == 0)
+    if M == 1:
+        assert np.all(out["z_std"] == 0)
+
+
+def test_spread_needs_flag_for_equilibrium_sums(ctx):
+    im = synth.workload_l64()
+    imgs = mpr.images([(im.ny, im.nx)])
+    mk = dev(im.mask, torch.uint8)
+    phi = dev(np.where(im.mask == 1, 1.0, 0.0).astype(np.float32))
+    prm = mpr.default_params(R=1, K=3)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    ps, m2 = torch.zeros_like(phi), torch.zeros_like(phi)
+    with pytest.raises(mpr.MprError) as e:
+        ctx.simulate(imgs, phi, mk, np.array([0.1]), prm, ws, ps, phi_m2=m2)
+    assert e.value.code == mpr.MPR_ERR_ARG

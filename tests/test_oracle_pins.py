@@ -417,6 +417,38 @@ def test_no_gaps_is_a_no_op():
     assert np.array_equal(oracle.predict(z, m, ps, 3, zz), z)
 
 
+# ---------------------------------------- spread of the realizations
+def test_spread_equals_std_of_recorded_states():
+    """Algorithm 2 step 7 statistics: the oracle's sums over R chains x K
+    equilibrium states reproduce numpy's mean and sample standard deviation
+    (ddof=1) of the back-transformed states, recorded here sweep by sweep."""
+    z = synth.matern_field(9, 7, 0.5, 0.2, 50, 10, 5)
+    m = synth.random_mask(9, 7, 0.4, 6)
+    phi, zz = oracle.map_to_angles(z, m)
+    T, R, K, seed = 0.3, 2, 4, 11
+    p = oracle.default_params(R=R, K=K, fixed_relax=0, seed=seed)
+    ps, st, _, _, pq = oracle.simulate(phi, m, T, p, want_sq=True)
+    states = []
+    for r in range(R):
+        s_ = phi.copy()
+        for y, x in zip(*np.nonzero(m == 0)):
+            s_[y, x] = 2 * math.pi * oracle.site_uniforms(seed, 9, int(x), int(y), oracle.INIT_SWEEP, r, 0)[0]
+        for t in range(K):
+            for colour in (0, 1):
+                s_, _, _ = oracle.half_sweep(s_, m, colour, T, 1.0, t, chain=r, seed=seed)
+            states.append(s_.copy())
+    states = np.array(states)
+    g = m == 0
+    assert np.allclose(ps[g], states.sum(0)[g], rtol=0, atol=1e-12)
+    zs = zz[0] + (zz[1] - zz[0]) * states / (2 * math.pi)
+    ref = zs.std(axis=0, ddof=1)
+    got = oracle.spread(m, ps, pq, R * K, zz)
+    assert np.max(np.abs(got[g] - ref[g])) <= 1e-9 * max(1.0, float(ref[g].max()))
+    assert np.all(got[~g] == 0) and ref[g].min() > 0
+    # one realization has no spread
+    assert np.all(oracle.spread(m, ps / (R * K), pq / (R * K), 1, zz) == 0)
+
+
 # --------------------------------------- the paper's printed validation
 @pytest.mark.slow
 def test_reproduces_paper_table2_validation_measures():
