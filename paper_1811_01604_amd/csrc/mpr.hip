@@ -178,16 +178,17 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
             // the descriptor in memory
             float *mine = (colour ? d.h[1] : d.h[0]) + (int64_t)y * d.S;
             const float *oth = (colour ? d.h[0] : d.h[1]) + (int64_t)y * d.S;
-            const float2 v = *reinterpret_cast<const float2 *>(mine + h0);
-            float oL = 0.0f, oM = 0.0f, oR = 0.0f;
             const bool vL = h0 + s - 1 >= 0, vM = h0 + s < Wo, vR = h0 + s + 1 < Wo;
-            if (vL) oL = angle_of(oth[h0 + s - 1]);
-            if (vM) oM = angle_of(oth[h0 + s]);
-            if (vR) oR = angle_of(oth[h0 + s + 1]);
-            float2 up = make_float2(0.0f, 0.0f), dn = make_float2(0.0f, 0.0f);
             const bool vU = y > 0, vD = y + 1 < d.ny;
-            if (vU) up = *reinterpret_cast<const float2 *>(oth - d.S + h0);
-            if (vD) dn = *reinterpret_cast<const float2 *>(oth + d.S + h0);
+            // every load is issued, from a clamped in-row position when the
+            // neighbour is missing (update_site ignores it by its valid bit),
+            // so that all of them are in flight at once
+            const float2 v = gld2(mine + h0);
+            const float oL = angle_of(gld(oth + max(h0 + s - 1, 0)));
+            const float oM = angle_of(gld(oth + h0 + s));  // h0 + s <= S - 1
+            const float oR = angle_of(gld(oth + min(h0 + s + 1, d.S - 1)));
+            float2 up = gld2(oth + (vU ? -(int64_t)d.S : 0) + h0);
+            float2 dn = gld2(oth + (vD ? (int64_t)d.S : 0) + h0);
             up.x = angle_of(up.x);
             up.y = angle_of(up.y);
             dn.x = angle_of(dn.x);
@@ -218,9 +219,9 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
             const float out0 = w0 ? o0.phi : v.x;
             const float out1 = w1 ? o1.phi : v.y;
             if (two) {
-                *reinterpret_cast<float2 *>(mine + h0) = make_float2(out0, out1);
+                gst2(mine + h0, make_float2(out0, out1));
             } else if (w0) {
-                mine[h0] = out0;
+                gst(mine + h0, out0);
             }
             float *accp = colour ? d.acc[1] : d.acc[0];
             if (phase == PH_EQ && accp) {
@@ -335,36 +336,41 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
     float *const acc_base = (phase == PH_EQ) ? (colour ? d.acc[1] : d.acc[0]) : nullptr;
     float *const m2_base = acc_base ? (colour ? d.m2[1] : d.m2[0]) : nullptr;
 
-    // pass 1: pairs t and t + 256 of the block
+    // pass 1: pairs t and t + 256 of the block; both pairs are read before
+    // either draws its random numbers, so that the two loads overlap
     bool gap[2][2], fix[2][2];
     uint32_t wu[2][2], wr[2][2];
+    float2 pv[2];
+    bool in[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int pi = (int)threadIdx.x + j * kBlock;
         const int y = by * CR + pi / PPR;
         const int h0 = 2 * (bx * PPR + pi % PPR);
-        gap[j][0] = gap[j][1] = fix[j][0] = fix[j][1] = false;
+        const int s = (y + colour) & 1;
+        in[j] = y < d.ny && h0 < ((d.nx - s + 1) >> 1);
+        // rows and pairs outside the grid read pair 0 of row 0 instead
+        pv[j] = gld2(mine_base + (in[j] ? (int64_t)y * d.S + h0 : 0));
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int pi = (int)threadIdx.x + j * kBlock;
+        const int y = by * CR + pi / PPR;
+        const int h0 = 2 * (bx * PPR + pi % PPR);
+        const int s = (y + colour) & 1;
+        const bool two = in[j] && (h0 + 1) < ((d.nx - s + 1) >> 1);
+        gap[j][0] = in[j] && !is_fixed(pv[j].x);
+        gap[j][1] = two && !is_fixed(pv[j].y);
+        fix[j][0] = want_energy && in[j] && !gap[j][0];
+        fix[j][1] = want_energy && two && !gap[j][1];
         wu[j][0] = wu[j][1] = wr[j][0] = wr[j][1] = 0u;
-        if (y < d.ny) {
-            const int s = (y + colour) & 1;
-            const int W = (d.nx - s + 1) >> 1;
-            if (h0 < W) {
-                const bool two = (h0 + 1) < W;
-                const float2 v = *reinterpret_cast<const float2 *>(mine_base + (int64_t)y * d.S + h0);
-                gap[j][0] = !is_fixed(v.x);
-                gap[j][1] = two && !is_fixed(v.y);
-                fix[j][0] = want_energy && !gap[j][0];
-                fix[j][1] = want_energy && two && !gap[j][1];
-                if (!or_only && (gap[j][0] || gap[j][1])) {
-                    const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * h0 + s), sweep, d.chain,
-                                    d.image_id};
-                    const U4 w = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
-                    wu[j][0] = w.x;
-                    wr[j][0] = w.y;
-                    wu[j][1] = w.z;
-                    wr[j][1] = w.w;
-                }
-            }
+        if (!or_only && (gap[j][0] || gap[j][1])) {
+            const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * h0 + s), sweep, d.chain, d.image_id};
+            const U4 w = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
+            wu[j][0] = w.x;
+            wr[j][0] = w.y;
+            wu[j][1] = w.z;
+            wr[j][1] = w.w;
         }
     }
     // positions in the two lists: pair j = 0 of every thread first, then j = 1
@@ -424,38 +430,61 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
         const int Wo = (d.nx + s) >> 1;
         valid = (h + s - 1 >= 0 ? 1u : 0u) | (h + s < Wo ? 2u : 0u) | (y > 0 ? 4u : 0u) | (y + 1 < d.ny ? 8u : 0u);
     };
+    // all four loads are issued, from clamped positions for missing
+    // neighbours (ignored by their valid bits), so that they overlap
     auto neighbours = [&](int y, int h, int s, uint32_t valid, float &nL, float &nR, float &nU, float &nD) {
         const float *orow = oth_base + (int64_t)y * d.S;
-        nL = (valid & 1u) ? angle_of(orow[h + s - 1]) : 0.0f;
-        nR = (valid & 2u) ? angle_of(orow[h + s]) : 0.0f;
-        nU = (valid & 4u) ? angle_of(orow[h - d.S]) : 0.0f;
-        nD = (valid & 8u) ? angle_of(orow[h + d.S]) : 0.0f;
+        nL = angle_of(gld(orow + max(h + s - 1, 0)));
+        nR = angle_of(gld(orow + min(h + s, d.S - 1)));
+        nU = angle_of(gld(orow + ((valid & 4u) ? -(int64_t)d.S : 0) + h));
+        nD = angle_of(gld(orow + ((valid & 8u) ? (int64_t)d.S : 0) + h));
     };
 
     // a thread sees at most 5 sites (4 gap sites), each below 2^30 in energy units
     uint64_t e_thread = 0u;
     uint32_t acc_thread = 0u;
-    // pass 2: the listed gap sites
-    for (int i = (int)threadIdx.x; i < n_list[0]; i += kBlock) {
-        const uint2 e = gap_list[i];
-        const uint32_t idx = (e.x & 0xFFu) | ((e.y & 0xFFu) << 8);
+    // pass 2: the listed gap sites, 256 at a time; the next site's inputs
+    // are fetched before the current one is computed (unconditionally, from
+    // a clamped list index, so that waiting for the current inputs never
+    // waits for these)
+    struct Item {
+        uint2 e;
         int y, h, s;
         uint32_t valid;
-        locate(idx, y, h, s, valid);
-        float nL, nR, nU, nD;
-        neighbours(y, h, s, valid, nL, nR, nU, nD);
+        float a, nL, nR, nU, nD;  // raw words: the sign bit is cleared at use
+    };
+    auto fetch = [&](int i, Item &it) {
+        it.e = gap_list[i];
+        locate((it.e.x & 0xFFu) | ((it.e.y & 0xFFu) << 8), it.y, it.h, it.s, it.valid);
+        const float *orow = oth_base + (int64_t)it.y * d.S;
+        it.nL = gld(orow + max(it.h + it.s - 1, 0));
+        it.nR = gld(orow + min(it.h + it.s, d.S - 1));
+        it.nU = gld(orow + ((it.valid & 4u) ? -(int64_t)d.S : 0) + it.h);
+        it.nD = gld(orow + ((it.valid & 8u) ? (int64_t)d.S : 0) + it.h);
+        it.a = gld(mine_base + (int64_t)it.y * d.S + it.h);
+    };
+    const int n_gap = n_list[0];
+    Item cur;
+    if ((int)threadIdx.x < n_gap) fetch((int)threadIdx.x, cur);
+    for (int i = (int)threadIdx.x; i < n_gap; i += kBlock) {
+        Item nxt;
+        fetch(min(i + kBlock, n_gap - 1), nxt);
+        const uint32_t idx = (cur.e.x & 0xFFu) | ((cur.e.y & 0xFFu) << 8);
+        const int y = cur.y, h = cur.h, s = cur.s;
+        const uint32_t valid = cur.valid;
         float *mp = mine_base + (int64_t)y * d.S + h;
-        const float a = angle_of(*mp);
         // the low 8 bits of each word hold the index; unit24 uses the top 24
-        const float u = or_only ? 0.5f : unit24(e.x);
-        const float r = or_only ? 0.5f : unit24(e.y);
+        const float u = or_only ? 0.5f : unit24(cur.e.x);
+        const float r = or_only ? 0.5f : unit24(cur.e.y);
         bool n64 = true;
-        const SiteOut o = update_site(a, nL, nR, nU, nD, valid, u, r, inv_T, dscale, or_only != 0, &n64);
+        const SiteOut o = update_site(angle_of(cur.a), angle_of(cur.nL), angle_of(cur.nR), angle_of(cur.nU),
+                                      angle_of(cur.nD), valid, u, r, inv_T, dscale, or_only != 0, &n64);
+        cur = nxt;
         if (n64) {  // too close to call: redone in double precision afterwards
             defer_redo(rd, blockIdx.x, kCompactSites / 32, idx);
             continue;
         }
-        *mp = o.phi;
+        gst(mp, o.phi);
         if (acc_base)
             accumulate_state(acc_base + (int64_t)y * d.S + h, m2_base ? m2_base + (int64_t)y * d.S + h : nullptr,
                              o.phi, stp->inv_k, stp->inv_km1);
@@ -470,7 +499,7 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
         locate((uint32_t)fixed_list[i], y, h, s, valid);
         float nL, nR, nU, nD;
         neighbours(y, h, s, valid, nL, nR, nU, nD);
-        const float a = angle_of(mine_base[(int64_t)y * d.S + h]);
+        const float a = angle_of(gld(mine_base + (int64_t)y * d.S + h));
         e_thread += energy_fx(bond_energy_half(0.5f * a, nL, nR, nU, nD, valid));
     }
     if (!want_acc) return;

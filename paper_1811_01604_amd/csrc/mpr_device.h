@@ -378,16 +378,36 @@ __device__ __forceinline__ float bond_energy_half(float th, float n0, float n1, 
     return 0.5f * A2;
 }
 
+// Loads and stores through global-address-space pointers (the chain
+// descriptors hold generic ones, which would otherwise give flat accesses).
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) v2f gv2f;
+__device__ __forceinline__ float gld(const float *p) { return *(const gfloat *)p; }
+__device__ __forceinline__ float2 gld2(const float *p)
+{
+    const v2f v = *(const gv2f *)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(float *p, float v) { *(gfloat *)p = v; }
+__device__ __forceinline__ void gst2(float *p, float2 v)
+{
+    v2f w;
+    w.x = v.x;
+    w.y = v.y;
+    *(gv2f *)p = w;
+}
+
 // Adds the k-th equilibrium state phi of a site to its running sum acc and,
 // when m2 is given, to the sum of squared deviations from the running mean
 // (Welford's update with the mean taken from the sum: mean_{k-1} = acc
 // inv_km1 before, mean_k = acc inv_k after; k = 1 adds exactly zero).
 __device__ __forceinline__ void accumulate_state(float *acc, float *m2, float phi, float inv_k, float inv_km1)
 {
-    const float s0 = *acc;
+    const float s0 = gld(acc);
     const float s1 = s0 + phi;
-    *acc = s1;
-    if (m2) *m2 = fmaf(phi - s0 * inv_km1, phi - s1 * inv_k, *m2);
+    gst(acc, s1);
+    if (m2) gst(m2, fmaf(phi - s0 * inv_km1, phi - s1 * inv_k, gld(m2)));
 }
 
 // Bond energies of a site in fixed point: units of 2^-27, rounded, so that
