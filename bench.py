@@ -56,10 +56,11 @@ def kernel_source_sha() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, chains: int):
+def measured_traffic(workload: str, chains: int, tile: int):
     """HBM bytes per half-sweep launch from the committed rocprofv3 counter
     runs (FETCH_SIZE + WRITE_SIZE, scaled by the copy-probe calibration), or
-    None when they were taken on other kernel sources or another workload."""
+    None when they were taken on other kernel sources, another workload or
+    another sweep block shape."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -67,7 +68,7 @@ def measured_traffic(workload: str, chains: int):
         return None
     if t.get("source_sha256") != kernel_source_sha() or t.get("workload") != workload or t.get("chains") != chains:
         return None
-    return t.get("traffic_bytes_per_launch")
+    return (t.get("by_tile") or {}).get(str(tile), {}).get("traffic_bytes_per_launch")
 
 
 def cpu_baseline(im, T: float, sweeps: int, seed: int) -> dict:
@@ -135,6 +136,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB plain copy first (calibrates HBM byte counters)")
+    ap.add_argument("--tile", default="auto",
+                    help="sweep block shape: auto (tuned), or rows 1/2/4/8, with a 'c' suffix for the compacted "
+                         "shapes 2c/4c/8c (for profiling runs that must see one kernel)")
     ap.add_argument("--warm-seeds", type=int, default=8,
                     help="images per mask type for the warm-start comparison at L=2048 (0 = skip)")
     args = ap.parse_args()
@@ -159,7 +163,10 @@ def main():
     phi = torch.zeros_like(z)
     ps = torch.zeros_like(z)
     zh = torch.zeros_like(z)
-    prm = mpr.default_params(R=args.chains, K=args.K, fixed_relax=args.fixed_sweeps)
+    tile = 0
+    if args.tile != "auto":
+        tile = int(args.tile.rstrip("c")) | (mpr.TILE_COMPACT if args.tile.endswith("c") else 0)
+    prm = mpr.default_params(R=args.chains, K=args.K, fixed_relax=args.fixed_sweeps, tile_rows=tile)
     ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
     P = int((im.mask == 0).sum())
     M = prm.R * prm.K
@@ -230,7 +237,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, prm.R),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, prm.R, prof["last_tile"]),
             "kernel": ("half_sweep_compact_kernel" if prof["last_tile"] & mpr.TILE_COMPACT else "half_sweep_kernel"),
             "tile_rows": prof["last_tile"] & 0xFF,
             "launch_ms": launch_ms, "useful_bytes_per_launch": bytes_per_launch,
