@@ -95,6 +95,13 @@ typedef struct {
     int32_t spread;       /* 1: also keep, per chain and site, the squared deviations
                              of the equilibrium states from their running mean (K > 1;
                              needed for mpr_simulate's phi_m2 then; more workspace) */
+    int32_t fp64;         /* 1: the chains of mpr_simulate store and update their angles
+                             in double precision (the paper's DP runs, Section 4, Tables
+                             2 and 3); twice the workspace per chain; plain block shapes
+                             only (tile_rows without MPR_TILE_COMPACT).  Inputs and
+                             outputs stay float; sums are taken in double and rounded
+                             once.  The temperature estimate is unaffected. */
+    int32_t reserved2;    /* 0 */
 } mpr_params;
 
 /* Per chain results of mpr_simulate (R per image, image-major). */
@@ -311,6 +318,16 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi,
                             double q, uint64_t seed, uint32_t sweep, uint32_t chain,
                             uint32_t stream_id, int32_t mode, int32_t tile, uint8_t *flags,
                             int64_t *accepted, double *bond_energy, void *stream);
+
+/* mpr_diag_half_sweep for a grid of double angles (phi: dev, double,
+ * in/out) through the double-precision sweep of mpr_params.fp64: the same
+ * arguments (tile: 0 or a plain shape), flags bit 4 set at every updated
+ * site, and bond_energy summed in fixed point of 2^-30. */
+int32_t mpr_diag_half_sweep_fp64(mpr_ctx *ctx, int32_t nx, int32_t ny, double *phi,
+                                 const uint8_t *sampled, int32_t colour, double T, double a,
+                                 double q, uint64_t seed, uint32_t sweep, uint32_t chain,
+                                 uint32_t stream_id, int32_t mode, int32_t tile, uint8_t *flags,
+                                 int64_t *accepted, double *bond_energy, void *stream);
 
 /* H + N_GP of an nx x ny grid of angles (dev, float) as the simulation
  * accumulates it: sum over bonds of (1 - cos(q (phi_i - phi_j))) in fixed

@@ -27,7 +27,7 @@ EXPORTS = [
     "mpr_cnn_param_count", "mpr_cnn_packed_bytes", "mpr_cnn_workspace_size", "mpr_cnn_pack", "mpr_cnn_encode",
     "mpr_cnn_forward", "mpr_cnn_loss", "mpr_cnn_backward", "mpr_cnn_opt_step", "mpr_cnn_decode",
     "mpr_cnn_diag_conv", "mpr_cnn_diag_wgrad",
-    "mpr_diag_philox", "mpr_diag_half_sweep", "mpr_diag_copy", "mpr_diag_energy", "mpr_diag_sg_slope",
+    "mpr_diag_philox", "mpr_diag_half_sweep", "mpr_diag_half_sweep_fp64", "mpr_diag_copy", "mpr_diag_energy", "mpr_diag_sg_slope",
 ]
 
 
@@ -54,7 +54,7 @@ class Params(C.Structure):
         ("eq_a_mode", C.c_int32), ("table_nT", C.c_int32), ("table_burn", C.c_int32),
         ("table_meas", C.c_int32), ("tile_rows", C.c_int32), ("table_T_lo", C.c_double),
         ("table_T_hi", C.c_double), ("seed", C.c_uint64), ("sweeps_per_launch", C.c_int32),
-        ("spread", C.c_int32),
+        ("spread", C.c_int32), ("fp64", C.c_int32), ("reserved2", C.c_int32),
     ]
 
 
@@ -132,6 +132,8 @@ def _declare(L):
         "mpr_profile_read": (i32, [P, C.POINTER(Profile)]),
         "mpr_diag_philox": (i32, [P, P, u64, i64, P, P]),
         "mpr_diag_half_sweep": (i32, [P, i32, i32, P, P, i32, d, d, d, u64, u32, u32, u32, i32, i32, P, P, P, P]),
+        "mpr_diag_half_sweep_fp64": (i32, [P, i32, i32, P, P, i32, d, d, d, u64, u32, u32, u32, i32, i32, P, P, P,
+                                           P]),
         "mpr_diag_copy": (i32, [P, P, P, i64, P]),
         "mpr_diag_energy": (i32, [P, i32, i32, P, d, P, P]),
         "mpr_diag_sg_slope": (i32, [P, P, i32, i32, P]),
@@ -328,6 +330,20 @@ class Context:
         self._check(self.lib.mpr_diag_half_sweep(self._h, nx, ny, _ptr(phi), _ptr(sampled), colour, T, a, q, seed,
                                                  sweep, chain, stream_id, mode, int(tile), _ptr(flags),
                                                  C.byref(acc), C.byref(en), _stream(stream)))
+        return (acc.value, en.value) if with_energy else acc.value
+
+    def diag_half_sweep_fp64(self, phi, sampled, colour, T, a, sweep, chain=0, stream_id=0, seed=3000, q=0.5,
+                             mode=0, flags=None, stream=None, with_energy=False, tile=0):
+        """diag_half_sweep on a float64 grid through the double-precision sweep."""
+        import torch
+        if phi.dtype != torch.float64:
+            raise TypeError("phi must be float64")
+        ny, nx = phi.shape
+        acc = C.c_int64()
+        en = C.c_double()
+        self._check(self.lib.mpr_diag_half_sweep_fp64(self._h, nx, ny, _ptr(phi), _ptr(sampled), colour, T, a, q,
+                                                      seed, sweep, chain, stream_id, mode, int(tile), _ptr(flags),
+                                                      C.byref(acc), C.byref(en), _stream(stream)))
         return (acc.value, en.value) if with_energy else acc.value
 
     def diag_copy(self, src, dst, stream=None):

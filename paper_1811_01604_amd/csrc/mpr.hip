@@ -67,6 +67,8 @@ __device__ __forceinline__ void defer_redo(const Redo &rd, uint32_t gb, int word
 // Parameters of the control kernel.
 struct CtlParams {
     double a_targ, k_a, q;
+    double e_unit;        // energy fixed-point unit of the sweep kernels
+    int32_t angle_bytes;  // bytes per stored angle (4 or 8), for the work counters
     int32_t n_f, n_fit, i_max, fixed_relax, eq_a_mode, K, burn, meas;
     double w[kMaxFit];  // Savitzky-Golay derivative weights, oldest first
 };
@@ -92,10 +94,12 @@ __device__ double ring_slope(const double *ring, uint32_t t, int n_fit, const do
     return s;
 }
 
+// (fp64: the chains hold doubles; a gap starts at 2 pi u in double, as in
+// the plain definition.)
 __global__ void init_chains_kernel(const ChainDesc *__restrict__ descs, const int64_t *__restrict__ offsets,
                                    const float *__restrict__ phi, const uint8_t *__restrict__ sampled,
                                    const float *__restrict__ phi_init, uint32_t seed_lo, uint32_t seed_hi,
-                                   int table_mode)
+                                   int table_mode, int fp64)
 {
     const ChainDesc d = descs[blockIdx.y];
     const int64_t n = (int64_t)d.nx * d.ny;
@@ -105,22 +109,51 @@ __global__ void init_chains_kernel(const ChainDesc *__restrict__ descs, const in
         const int x = (int)(i - (int64_t)y * d.nx);
         const int c = (x + y) & 1;
         const int h = x >> 1;
-        float v;
+        double v;
+        bool fixed = false;
         if (table_mode) {
-            v = (float)kPi;
+            v = kPi;
         } else if (sampled[off + i]) {
-            v = mark_fixed(fabsf(phi[off + i]));
+            v = (double)fabsf(phi[off + i]);
+            fixed = true;
         } else if (phi_init) {
-            v = phi_init[off + i];
+            v = (double)phi_init[off + i];
         } else {
             U4 ctr = {(uint32_t)y * (uint32_t)d.nx + ((uint32_t)x & ~2u), kInitSweep, d.chain, d.image_id};
             const U4 w = philox4x32_10(ctr, seed_lo, seed_hi);
             const uint32_t word = ((x >> 1) & 1) ? w.z : w.x;
-            v = (float)(kTwoPi * (double)unit24(word));
+            v = kTwoPi * (double)unit24(word);
         }
-        d.h[c][(int64_t)y * d.S + h] = v;
-        if (d.acc[c]) d.acc[c][(int64_t)y * d.S + h] = 0.0f;
-        if (d.m2[c]) d.m2[c][(int64_t)y * d.S + h] = 0.0f;
+        const int64_t j = (int64_t)y * d.S + h;
+        // select by value: indexing the descriptor with c would put it in memory
+        float *hp = c ? d.h[1] : d.h[0];
+        float *ap = c ? d.acc[1] : d.acc[0];
+        float *mp = c ? d.m2[1] : d.m2[0];
+        if (fp64) {
+            ((double *)hp)[j] = fixed ? mark_fixed_d(v) : v;
+            if (ap) ((double *)ap)[j] = 0.0;
+            if (mp) ((double *)mp)[j] = 0.0;
+        } else {
+            hp[j] = fixed ? mark_fixed((float)v) : (float)v;
+            if (ap) ap[j] = 0.0f;
+            if (mp) mp[j] = 0.0f;
+        }
+    }
+}
+
+// A full row-major grid of double angles (gaps: the starting state) into the
+// half-grids of one double-precision chain, samples marked.
+__global__ void split_fp64_kernel(const ChainDesc *__restrict__ descs, const double *__restrict__ phi,
+                                  const uint8_t *__restrict__ sampled)
+{
+    const ChainDesc d = descs[0];
+    const int64_t n = (int64_t)d.nx * d.ny;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / d.nx);
+        const int x = (int)(i - (int64_t)y * d.nx);
+        const double v = fabs(phi[i]);
+        double *hp = (double *)(((x + y) & 1) ? d.h[1] : d.h[0]);
+        hp[(int64_t)y * d.S + (x >> 1)] = sampled[i] ? mark_fixed_d(v) : v;
     }
 }
 
@@ -631,6 +664,114 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
     }
 }
 
+// The double-precision sweep: the layout of half_sweep_body (a thread per
+// pair of neighbouring sites of one half-row, one Philox call per pair) on
+// half-grids of doubles, each site updated by update_site_d.  Every decision
+// is final here, so nothing is deferred.  Bond energies are summed in fixed
+// point of 2^-30.
+template <bool DIAG, int ROWS>
+__global__ __launch_bounds__(kBlock) void half_sweep_fp64_kernel(const ChainDesc *__restrict__ descs,
+                                                                 ChainState *__restrict__ states,
+                                                                 const int64_t *__restrict__ start, int n_chains,
+                                                                 int colour, SweepConsts sc, int or_only,
+                                                                 uint8_t *__restrict__ flags)
+{
+    constexpr int PX = kBlock / ROWS;
+    const int c = find_chain(start, n_chains, (int64_t)blockIdx.x);
+    ChainState *stp = states + c;
+    const int phase = stp->phase;
+    if (phase == PH_DONE) return;
+    const ChainDesc d = descs[c];
+    const int lb = (int)((int64_t)blockIdx.x - start[c]);
+    const int nbx = ((d.S >> 1) + PX - 1) / PX;
+    const int by = lb / nbx;
+    const int bx = lb - by * nbx;
+    const int y = by * ROWS + (int)(threadIdx.x / PX);
+    const int h0 = 2 * (bx * PX + (int)(threadIdx.x % PX));
+    const uint32_t sweep = stp->sweep;
+    const double T = stp->T, a = stp->a_cur;
+    const bool want_energy = (colour == 1) && (phase != PH_EQ);
+    const bool want_acc = phase != PH_EQ;
+    unsigned long long e_thread = 0ull;
+    uint32_t acc_thread = 0u;
+
+    if (y < d.ny) {
+        const int s = (y + colour) & 1;
+        const int W = (d.nx - s + 1) >> 1;
+        const int Wo = (d.nx + s) >> 1;
+        if (h0 < W) {
+            const bool two = (h0 + 1) < W;
+            double *mine = (double *)(colour ? d.h[1] : d.h[0]) + (int64_t)y * d.S;
+            const double *oth = (const double *)(colour ? d.h[0] : d.h[1]) + (int64_t)y * d.S;
+            const bool vL = h0 + s - 1 >= 0, vM = h0 + s < Wo, vR = h0 + s + 1 < Wo;
+            const bool vU = y > 0, vD = y + 1 < d.ny;
+            const double2 v = gldd2(mine + h0);
+            const double oL = fabs(gldd(oth + max(h0 + s - 1, 0)));
+            const double oM = fabs(gldd(oth + h0 + s));
+            const double oR = fabs(gldd(oth + min(h0 + s + 1, d.S - 1)));
+            const double2 up = gldd2(oth + (vU ? -(int64_t)d.S : 0) + h0);
+            const double2 dn = gldd2(oth + (vD ? (int64_t)d.S : 0) + h0);
+            const bool fixed0 = is_fixed_d(v.x), fixed1 = !two || is_fixed_d(v.y);
+            double u0 = 0.5, r0 = 0.5, u1 = 0.5, r1 = 0.5;
+            if (!or_only && (!fixed0 || !fixed1)) {
+                const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * h0 + s), sweep, d.chain, d.image_id};
+                const U4 w = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
+                u0 = (double)unit24(w.x);
+                r0 = (double)unit24(w.y);
+                u1 = (double)unit24(w.z);
+                r1 = (double)unit24(w.w);
+            }
+            const uint32_t val0 = (vL ? 1u : 0u) | (vM ? 2u : 0u) | (vU ? 4u : 0u) | (vD ? 8u : 0u);
+            const uint32_t val1 = 1u | (vR ? 2u : 0u) | (vU ? 4u : 0u) | (vD ? 8u : 0u);
+            const SiteOutD o0 = update_site_d(fabs(v.x), oL, oM, fabs(up.x), fabs(dn.x), val0, u0, r0, a, T,
+                                              or_only != 0);
+            const SiteOutD o1 = update_site_d(fabs(v.y), oM, oR, fabs(up.y), fabs(dn.y), val1, u1, r1, a, T,
+                                              or_only != 0);
+            const bool w0 = !fixed0, w1 = two && !fixed1;
+            const double out0 = w0 ? o0.phi : v.x;
+            const double out1 = w1 ? o1.phi : v.y;
+            if (two) gstd2(mine + h0, make_double2(out0, out1));
+            else if (w0) gstd(mine + h0, out0);
+            double *accp = (double *)(colour ? d.acc[1] : d.acc[0]);
+            if (phase == PH_EQ && accp) {
+                double *acc = accp + (int64_t)y * d.S;
+                double *m2p = (double *)(colour ? d.m2[1] : d.m2[0]);
+                double *m2 = m2p ? m2p + (int64_t)y * d.S : nullptr;
+                const double ik = stp->inv_k_d, ikm1 = stp->inv_km1_d;
+                if (w0) accumulate_state_d(acc + h0, m2 ? m2 + h0 : nullptr, out0, ik, ikm1);
+                if (w1) accumulate_state_d(acc + h0 + 1, m2 ? m2 + h0 + 1 : nullptr, out1, ik, ikm1);
+            }
+            acc_thread = (w0 && o0.accepted ? 1u : 0u) + (w1 && o1.accepted ? 1u : 0u);
+            if (want_energy)
+                e_thread = energy_fx_d(fixed0 ? o0.e_before : o0.e_bonds) +
+                           (!two ? 0ull : energy_fx_d(fixed1 ? o1.e_before : o1.e_bonds));
+            if (DIAG && flags) {
+                const int64_t x0 = 2 * h0 + s;
+                if (w0) flags[(int64_t)y * d.nx + x0] = (uint8_t)o0.flags;
+                if (w1) flags[(int64_t)y * d.nx + x0 + 2] = (uint8_t)o1.flags;
+            }
+        }
+    }
+    if (!want_acc) return;
+    // block sums: a thread's energy is below 2^34 and its count at most 2,
+    // so 64-bit lane sums hold both (count in the top 8 bits)
+    unsigned long long sum = e_thread | ((unsigned long long)acc_thread << 56);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    __shared__ unsigned long long red[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long e = 0ull, n = 0ull;
+        for (int i = 0; i < kBlock / 64; ++i) {
+            e += red[i] & 0x00FFFFFFFFFFFFFFull;
+            n += red[i] >> 56;
+        }
+        if (e) atomicAdd(&stp->e_fx, e);
+        if (n) atomicAdd(&stp->acc, n);
+    }
+}
+
 __device__ void set_derived(ChainState &st, double q)
 {
     st.inv_T = (float)(1.0 / st.T);
@@ -650,13 +791,13 @@ __global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *
     // work counters: chain-sweeps, gap-site updates, useful bytes
     atomicAdd(&work[0], 1ull);
     atomicAdd(&work[1], (unsigned long long)d.P);
-    atomicAdd(&work[2], (unsigned long long)(4 * (int64_t)d.nx * d.ny + 4 * d.P));
+    atomicAdd(&work[2], (unsigned long long)(cp.angle_bytes * ((int64_t)d.nx * d.ny + d.P)));
     const uint32_t t = st.sweep;
     const unsigned long long acc = st.acc, efx = st.e_fx;
     st.acc = 0ull;
     st.e_fx = 0ull;
     // 1 + e = (H + N_GP) / N_GP with H + N_GP = sum over bonds of (1 - cos)
-    const double ope = (double)efx * kEnergyUnit / (double)d.ngp;
+    const double ope = (double)efx * cp.e_unit / (double)d.ngp;
     if (st.phase == PH_RELAX) {
         const double A = (double)acc / (double)d.P;
         if (A < cp.a_targ) st.a_relax = 1.0 + (double)(t + 1u) / cp.k_a;
@@ -677,6 +818,8 @@ __global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *
             st.a_cur = cp.eq_a_mode ? st.a_relax : 1.0;
             st.inv_k = 1.0f;
             st.inv_km1 = 0.0f;
+            st.inv_k_d = 1.0;
+            st.inv_km1_d = 0.0;
         }
     } else if (st.phase == PH_EQ) {
         st.sweep = t + 1u;
@@ -686,6 +829,8 @@ __global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *
             const int k = cp.K - st.eq_left + 1;  // the next sweep's state number
             st.inv_k = 1.0f / (float)k;
             st.inv_km1 = 1.0f / (float)(k - 1);
+            st.inv_k_d = 1.0 / (double)k;
+            st.inv_km1_d = 1.0 / (double)(k - 1);
         }
     } else {  // PH_TABLE
         const double A = (double)acc / (double)d.P;
@@ -734,6 +879,39 @@ __global__ void finalize_kernel(const ChainDesc *__restrict__ descs, const ImgDe
     }
 }
 
+// finalize_kernel for double-precision chains: the same sums taken in
+// double and rounded once.
+__global__ void finalize_fp64_kernel(const ChainDesc *__restrict__ descs, const ImgDev *__restrict__ imgs, int R,
+                                     int K, const uint8_t *__restrict__ sampled, float *__restrict__ phi_sum,
+                                     float *__restrict__ phi_m2)
+{
+    const ImgDev im = imgs[blockIdx.y];
+    const int64_t n = (int64_t)im.nx * im.ny;
+    const ChainDesc *dc = descs + (int64_t)blockIdx.y * R;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0, q = 0.0;
+        if (!sampled[im.offset + i] && K > 0) {
+            const int y = (int)(i / im.nx);
+            const int x = (int)(i - (int64_t)y * im.nx);
+            const int c = (x + y) & 1;
+            const int64_t j = (int64_t)y * dc[0].S + (x >> 1);
+            for (int r = 0; r < R; ++r)
+                s += (K > 1) ? ((const double *)dc[r].acc[c])[j] : fabs(((const double *)dc[r].h[c])[j]);
+            if (phi_m2) {
+                const double mean = s / (double)(R * K);
+                for (int r = 0; r < R; ++r) {
+                    const double dv = ((K > 1) ? ((const double *)dc[r].acc[c])[j] / (double)K
+                                               : fabs(((const double *)dc[r].h[c])[j])) - mean;
+                    q = fma((double)K * dv, dv, q);
+                    if (K > 1) q += ((const double *)dc[r].m2[c])[j];
+                }
+            }
+        }
+        phi_sum[im.offset + i] = (float)s;
+        if (phi_m2) phi_m2[im.offset + i] = (float)q;
+    }
+}
+
 // Spread of the prediction: the standard deviation over the M realizations
 // of z = G^{-1}(phi), which is (z_max - z_min) / (2 pi) times that of phi,
 // sqrt(m2 / (M - 1)); zero at sampled sites and for M = 1.
@@ -752,6 +930,19 @@ __global__ void spread_kernel(const ImgDev *__restrict__ imgs, const double *__r
     }
 }
 
+// Half-grids of one double-precision chain back to a full row-major grid.
+__global__ void unsplit_fp64_kernel(const ChainDesc *__restrict__ descs, double *__restrict__ phi)
+{
+    const ChainDesc d = descs[0];
+    const int64_t n = (int64_t)d.nx * d.ny;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / d.nx);
+        const int x = (int)(i - (int64_t)y * d.nx);
+        const double *hp = (const double *)(((x + y) & 1) ? d.h[1] : d.h[0]);
+        phi[i] = fabs(hp[(int64_t)y * d.S + (x >> 1)]);
+    }
+}
+
 // Half-grids of one chain back to a full row-major grid of angles.
 __global__ void unsplit_kernel(const ChainDesc *__restrict__ descs, float *__restrict__ phi)
 {
@@ -760,7 +951,8 @@ __global__ void unsplit_kernel(const ChainDesc *__restrict__ descs, float *__res
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(i / d.nx);
         const int x = (int)(i - (int64_t)y * d.nx);
-        phi[i] = angle_of(d.h[(x + y) & 1][(int64_t)y * d.S + (x >> 1)]);
+        const float *hp = ((x + y) & 1) ? d.h[1] : d.h[0];
+        phi[i] = angle_of(hp[(int64_t)y * d.S + (x >> 1)]);
     }
 }
 
@@ -1004,7 +1196,8 @@ int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 int half_stride(int nx) { return (int)round_up((nx + 1) / 2, 64); }
 
-int64_t half_grid_bytes(int nx, int ny) { return (int64_t)ny * half_stride(nx) * 4; }
+// Bytes of one half-grid of `eb`-byte angles.
+int64_t half_grid_bytes(int nx, int ny, int eb = 4) { return (int64_t)ny * half_stride(nx) * eb; }
 
 // Simple bump allocator over the caller's workspace.
 struct Carver {
@@ -1073,7 +1266,8 @@ bool valid_params(const mpr_params *p)
            p->k_a > 0.0 && p->a_targ >= 0.0 && p->table_nT >= 2 && p->table_meas >= 1 && p->table_burn >= 0 &&
            p->table_T_lo > 0.0 && p->table_T_hi > p->table_T_lo &&
            (p->tile_rows == 0 || shape_of(p->tile_rows) >= 0) &&
-           p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096 && (p->spread == 0 || p->spread == 1);
+           p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096 && (p->spread == 0 || p->spread == 1) &&
+           (p->fp64 == 0 || (p->fp64 == 1 && (p->tile_rows & MPR_TILE_COMPACT) == 0));
 }
 
 bool valid_images(const mpr_image *imgs, int n)
@@ -1091,7 +1285,7 @@ int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
 {
     int64_t b = 0;
     for (int i = 0; i < n; ++i) {
-        const int64_t hg = round_up(half_grid_bytes(imgs[i].nx, imgs[i].ny), 256);
+        const int64_t hg = round_up(half_grid_bytes(imgs[i].nx, imgs[i].ny, p->fp64 ? 8 : 4), 256);
         b += (int64_t)p->R * 2 * hg * (p->K > 1 ? (p->spread ? 3 : 2) : 1);
     }
     const int64_t chains = (int64_t)n * p->R;
@@ -1178,6 +1372,8 @@ CtlParams make_ctl(const mpr_params *p)
     cp.K = p->K;
     cp.burn = p->table_burn;
     cp.meas = p->table_meas;
+    cp.e_unit = kEnergyUnit;
+    cp.angle_bytes = 4;
     sg_weights(p->n_fit, p->sg_degree, cp.w);
     return cp;
 }
@@ -1209,6 +1405,7 @@ struct ChainSet {
     int64_t *d_start[kNumShapes] = {};  // block prefix sums per shape
     int64_t total_blocks[kNumShapes] = {};
     Redo redo = {nullptr, nullptr};      // deferred double-precision updates (zeroed)
+    bool fp64 = false;                   // double-precision chains (plain shapes, no deferral)
 };
 
 template <int ROWS>
@@ -1244,10 +1441,35 @@ void launch_redo(hipStream_t st, const ChainSet &cs, int v, int colour, const Sw
                        kShapes[v].compact ? 1 : 0, colour, sc, or_only, cs.redo, flags);
 }
 
-// One half-sweep of every chain in shape v (the e(T, L) runs use the plain
-// shapes only).
+template <bool DIAG, int ROWS>
+void launch_half_fp64_rows(hipStream_t st, const ChainSet &cs, int v, int colour, const SweepConsts &sc, int or_only,
+                           uint8_t *flags)
+{
+    hipLaunchKernelGGL((half_sweep_fp64_kernel<DIAG, ROWS>), dim3((unsigned)cs.total_blocks[v]), dim3(kBlock), 0, st,
+                       cs.d_desc, cs.d_state, cs.d_start[v], (int)cs.desc.size(), colour, sc, or_only, flags);
+}
+
+// One half-sweep of double-precision chains in plain shape v.
+template <bool DIAG>
+void launch_half_fp64(hipStream_t st, const ChainSet &cs, int v, int colour, const SweepConsts &sc, int or_only,
+                      uint8_t *flags)
+{
+    switch (kShapes[v].rows) {
+        case 1: launch_half_fp64_rows<DIAG, 1>(st, cs, v, colour, sc, or_only, flags); break;
+        case 2: launch_half_fp64_rows<DIAG, 2>(st, cs, v, colour, sc, or_only, flags); break;
+        case 4: launch_half_fp64_rows<DIAG, 4>(st, cs, v, colour, sc, or_only, flags); break;
+        default: launch_half_fp64_rows<DIAG, 8>(st, cs, v, colour, sc, or_only, flags); break;
+    }
+}
+
+// One half-sweep of every chain in shape v (the e(T, L) runs and the
+// double-precision chains use the plain shapes only).
 void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colour, const SweepConsts &sc)
 {
+    if (cs.fp64) {
+        launch_half_fp64<false>(st, cs, v, colour, sc, 0, nullptr);
+        return;
+    }
     const Shape sh = kShapes[v];
     if (sh.compact && !table) {
         switch (sh.rows) {
@@ -1281,7 +1503,11 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     for (const auto &s : cs.state)
         if (s.phase == PH_DONE) ++already;
     if (already == (unsigned int)n) return MPR_OK;
-    const CtlParams cp = make_ctl(p);
+    CtlParams cp = make_ctl(p);
+    if (cs.fp64) {
+        cp.e_unit = kEnergyUnit64;
+        cp.angle_bytes = 8;
+    }
     const SweepConsts sc = make_sc(p->q, p->seed);
     const int cblocks = (n + 63) / 64;
     hipStream_t st = ctx->gstream;
@@ -1320,7 +1546,7 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     };
 
     // block shape: fixed, cached, or tuned on the first sweeps
-    const int n_shapes = table ? kNumPlainShapes : kNumShapes;
+    const int n_shapes = (table || cs.fp64) ? kNumPlainShapes : kNumShapes;
     int v = p->tile_rows ? shape_of(p->tile_rows) : -1;
     if (v >= n_shapes) v = kDefaultShape;
     int maxnx = 0, maxny = 0;
@@ -1328,7 +1554,7 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
         maxnx = std::max(maxnx, d.nx);
         maxny = std::max(maxny, d.ny);
     }
-    const auto key = std::make_tuple(table ? 1 : 0, n, maxnx, maxny);
+    const auto key = std::make_tuple((table ? 1 : 0) | (cs.fp64 ? 2 : 0), n, maxnx, maxny);
     float sweep_ms = -1.0f;
     if (v < 0) {
         auto it = ctx->tuned_rows.find(key);
@@ -1422,6 +1648,8 @@ ChainState fresh_state(double T, int phase)
     s.k = -1.0;
     s.inv_k = 1.0f;
     s.inv_km1 = 0.0f;
+    s.inv_k_d = 1.0;
+    s.inv_km1_d = 0.0;
     return s;
 }
 
@@ -1442,10 +1670,11 @@ int upload_chains(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream, do
     return upload_starts(ctx, cs, cv, stream);
 }
 
-// Allocates both half-grids (and accumulators) of a chain from the workspace.
-bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc, bool with_m2 = false)
+// Allocates both half-grids (and accumulators) of a chain of `eb`-byte
+// angles from the workspace.
+bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc, bool with_m2 = false, int eb = 4)
 {
-    const int64_t hg = half_grid_bytes(nx, ny);
+    const int64_t hg = half_grid_bytes(nx, ny, eb);
     d.nx = nx;
     d.ny = ny;
     d.S = half_stride(nx);
@@ -1576,6 +1805,7 @@ void mpr_default_params(mpr_params *p)
     p->tile_rows = 0;
     p->sweeps_per_launch = 0;
     p->spread = 0;
+    p->fp64 = 0;
 }
 
 int64_t mpr_workspace_size(const mpr_image *imgs, int32_t n, const mpr_params *p)
@@ -1713,7 +1943,7 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
             if (rc) return rc;
             const int64_t maxn = (int64_t)imgs[b].nx * imgs[b].ny;
             hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), p->table_nT), dim3(kBlock), 0, stream,
-                               cs.d_desc, cs.d_offset, nullptr, nullptr, nullptr, 0u, 0u, 1);
+                               cs.d_desc, cs.d_offset, nullptr, nullptr, nullptr, 0u, 0u, 1, 0);
             HIP_TRY(ctx, hipGetLastError());
             rc = run_chains(ctx, cs, p, stream, (int64_t)p->table_burn + p->table_meas, 50, true);
             if (rc) return rc;
@@ -1783,7 +2013,7 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
         for (int r = 0; r < p->R; ++r) {
             ChainDesc d;
             std::memset(&d, 0, sizeof d);
-            if (!carve_chain(cv, d, nx, ny, p->K > 1, p->spread != 0))
+            if (!carve_chain(cv, d, nx, ny, p->K > 1, p->spread != 0, p->fp64 ? 8 : 4))
                 return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
             d.image_id = imgs[b].id;
             d.chain = (uint32_t)r;
@@ -1800,23 +2030,29 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
             cs.offset.push_back(imgs[b].offset);
         }
     }
+    cs.fp64 = p->fp64 != 0;
+    const int eb = cs.fp64 ? 8 : 4;
     int rc = upload_chains(ctx, cs, cv, stream, p->q);
     if (rc) return rc;
     int64_t maxn = 0;
     for (int b = 0; b < n; ++b) maxn = std::max(maxn, (int64_t)imgs[b].nx * imgs[b].ny);
     for (auto &d : cs.desc) {
-        HIP_TRY(ctx, hipMemsetAsync(d.h[0], 0, half_grid_bytes(d.nx, d.ny), stream));
-        HIP_TRY(ctx, hipMemsetAsync(d.h[1], 0, half_grid_bytes(d.nx, d.ny), stream));
+        HIP_TRY(ctx, hipMemsetAsync(d.h[0], 0, half_grid_bytes(d.nx, d.ny, eb), stream));
+        HIP_TRY(ctx, hipMemsetAsync(d.h[1], 0, half_grid_bytes(d.nx, d.ny, eb), stream));
     }
     hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), (unsigned)cs.desc.size()), dim3(kBlock), 0,
                        stream, cs.d_desc, cs.d_offset, phi, sampled, phi_init, (uint32_t)p->seed,
-                       (uint32_t)(p->seed >> 32), 0);
+                       (uint32_t)(p->seed >> 32), 0, cs.fp64 ? 1 : 0);
     HIP_TRY(ctx, hipGetLastError());
     const int64_t relax_cap = p->fixed_relax >= 0 ? p->fixed_relax : (int64_t)p->i_max + 1;
     rc = run_chains(ctx, cs, p, stream, relax_cap + p->K + 1, p->n_f, false);
     if (rc) return rc;
-    hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, cs.d_desc, d_img,
-                       p->R, p->K, sampled, phi_sum, phi_m2);
+    if (cs.fp64)
+        hipLaunchKernelGGL(finalize_fp64_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, cs.d_desc,
+                           d_img, p->R, p->K, sampled, phi_sum, phi_m2);
+    else
+        hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, cs.d_desc,
+                           d_img, p->R, p->K, sampled, phi_sum, phi_m2);
     HIP_TRY(ctx, hipGetLastError());
     if (stats) {
         HIP_TRY(ctx, hipMemcpyAsync(cs.state.data(), cs.d_state, cs.state.size() * sizeof(ChainState),
@@ -1977,7 +2213,7 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
     const int64_t nsite = (int64_t)nx * ny;
     // the gap values of phi are the starting state
     hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(nsite, 2048), 1), dim3(kBlock), 0, stream, cs.d_desc,
-                       cs.d_offset, phi, sampled, phi, 0u, 0u, 0);
+                       cs.d_offset, phi, sampled, phi, 0u, 0u, 0, 0);
     if (flags) (void)hipMemsetAsync(flags, 0, nsite, stream);
     const SweepConsts sc = make_sc(q, seed);
     const dim3 grid((unsigned)cs.total_blocks[v]);
@@ -2018,6 +2254,63 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
         return fail(ctx, MPR_ERR_HIP, "diag_half_sweep: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
     if (accepted) *accepted = (int64_t)out.acc;
     if (bond_energy) *bond_energy = (double)out.e_fx * kEnergyUnit;
+    return MPR_OK;
+}
+
+int32_t mpr_diag_half_sweep_fp64(mpr_ctx *ctx, int32_t nx, int32_t ny, double *phi, const uint8_t *sampled,
+                                 int32_t colour, double T, double a, double q, uint64_t seed, uint32_t sweep,
+                                 uint32_t chain, uint32_t stream_id, int32_t mode, int32_t tile, uint8_t *flags,
+                                 int64_t *accepted, double *bond_energy, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    const int v = tile ? shape_of(tile) : kDefaultShape;
+    if (nx < 1 || ny < 1 || (int64_t)nx * ny < 2 || !phi || !sampled || (colour != 0 && colour != 1) || !(T > 0) ||
+        !(a > 0) || q != 0.5 || (mode != 0 && mode != 1) || v < 0 || kShapes[v].compact)
+        return fail(ctx, MPR_ERR_ARG, "diag_half_sweep_fp64: invalid argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    const int64_t hg = half_grid_bytes(nx, ny, 8);
+    const int64_t bytes = 2 * round_up(hg, 256) + 8192 + redo_bytes(nx, ny, 1);
+    void *buf = nullptr;
+    HIP_TRY(ctx, hipMalloc(&buf, bytes));
+    Carver cv{(char *)buf, bytes};
+    ChainSet cs;
+    cs.fp64 = true;
+    ChainDesc d;
+    std::memset(&d, 0, sizeof d);
+    carve_chain(cv, d, nx, ny, false, false, 8);
+    d.image_id = stream_id;
+    d.chain = chain;
+    d.P = 1;
+    d.ngp = (int64_t)nx * (ny - 1) + (int64_t)ny * (nx - 1);
+    cs.desc.push_back(d);
+    ChainState st = fresh_state(T, PH_RELAX);
+    st.sweep = sweep;
+    st.a_cur = a;
+    cs.state.push_back(st);
+    cs.offset.push_back(0);
+    int rc = upload_chains(ctx, cs, cv, stream, q);
+    if (rc) {
+        (void)hipFree(buf);
+        return rc;
+    }
+    (void)hipMemsetAsync(d.h[0], 0, hg, stream);
+    (void)hipMemsetAsync(d.h[1], 0, hg, stream);
+    const int64_t nsite = (int64_t)nx * ny;
+    hipLaunchKernelGGL(split_fp64_kernel, dim3(blocks_for(nsite, 2048)), dim3(kBlock), 0, stream, cs.d_desc, phi,
+                       sampled);
+    if (flags) (void)hipMemsetAsync(flags, 0, nsite, stream);
+    launch_half_fp64<true>(stream, cs, v, colour, make_sc(q, seed), mode, flags);
+    hipLaunchKernelGGL(unsplit_fp64_kernel, dim3(blocks_for(nsite, 2048)), dim3(kBlock), 0, stream, cs.d_desc, phi);
+    ChainState out;
+    (void)hipMemcpyAsync(&out, cs.d_state, sizeof out, hipMemcpyDeviceToHost, stream);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(stream);
+    (void)hipFree(buf);
+    if (e1 != hipSuccess || e2 != hipSuccess)
+        return fail(ctx, MPR_ERR_HIP, "diag_half_sweep_fp64: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    if (accepted) *accepted = (int64_t)out.acc;
+    if (bond_energy) *bond_energy = (double)out.e_fx * kEnergyUnit64;
     return MPR_OK;
 }
 

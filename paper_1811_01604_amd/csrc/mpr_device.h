@@ -27,6 +27,7 @@ constexpr int kMaxFit = 64;
 
 // Static description of one chain (one image x one realization).
 struct ChainDesc {
+    // In double-precision chains h, acc and m2 point to doubles.
     float *h[2];          // colour half-grids, ny * S each
     float *acc[2];        // equilibrium sums (K > 1), or null
     float *m2[2];         // sums of squared deviations from the running mean
@@ -60,6 +61,8 @@ struct ChainState {
     float inv_k;           // 1 / k and 1 / (k - 1) for the k-th equilibrium state
     float inv_km1;         // of the next sweep (k = 1: 1 and 0)
     int32_t pad;
+    double inv_k_d;        // the same in double (double-precision chains)
+    double inv_km1_d;
     double ring[kMaxFit];  // last n_fit values of 1 + e
 };
 
@@ -430,6 +433,164 @@ __device__ __forceinline__ float site_energy(float phi, const float nb[4], uint3
         e = fmaf(2.0f * sj, sj, e);
     }
     return e;
+}
+
+// ------------------------------------------------ double-precision chains
+// The double-precision variant of the sweep (the paper's DP runs, Section 4,
+// Tables 2 and 3): half-grids of doubles, the sign bit again marking the
+// sampled sites, and every step of update_site carried out in double
+// precision, so that no decision needs a second look.
+__device__ __forceinline__ bool is_fixed_d(double v) { return __double_as_longlong(v) < 0; }
+__device__ __forceinline__ double mark_fixed_d(double a)
+{
+    return __longlong_as_double(__double_as_longlong(a) | (long long)0x8000000000000000ull);
+}
+
+// 2 sin(d/2) and cos(d/2) for |d| <= pi from d2 = d * d: their Taylor
+// series in d, with coefficients (-1)^k / (4^k (2k+1)!) and
+// (-1)^k / (4^k (2k)!) rounded to double; the first omitted terms are below
+// 1e-18 and 2e-17 (relative and absolute).
+__device__ __forceinline__ double sin2_half_d(double d, double d2)
+{
+    double p = -3.135923479699833e-23;
+    p = fma(p, d2, 4.289943320229371e-20);
+    p = fma(p, d2, -4.667458332409556e-17);
+    p = fma(p, d2, 3.920664999224027e-14);
+    p = fma(p, d2, -2.446494959515793e-11);
+    p = fma(p, d2, 1.076457782186949e-08);
+    p = fma(p, d2, -3.1001984126984127e-06);
+    p = fma(p, d2, 0.0005208333333333333);
+    p = fma(p, d2, -0.041666666666666664);
+    return fma(d * d2, p, d);
+}
+
+__device__ __forceinline__ double cos_half_d(double d2)
+{
+    double p = -2.1211603623510776e-28;
+    p = fma(p, d2, 3.919904349624791e-25);
+    p = fma(p, d2, -5.958254611429682e-22);
+    p = fma(p, d2, 7.292903644389931e-19);
+    p = fma(p, d2, -7.001187498614334e-16);
+    p = fma(p, d2, 5.096864498991235e-13);
+    p = fma(p, d2, -2.691144455467372e-10);
+    p = fma(p, d2, 9.68812003968254e-08);
+    p = fma(p, d2, -2.170138888888889e-05);
+    p = fma(p, d2, 0.0026041666666666665);
+    p = fma(p, d2, -0.125);
+    return fma(p, d2, 1.0);
+}
+
+// Result of one double-precision site update.
+struct SiteOutD {
+    double phi;       // new angle
+    double e_bonds;   // sum over the site's bonds of 1 - cos(q (phi_new - phi_j))
+    double e_before;  // the same sum before the update
+    uint32_t flags;
+    bool accepted;
+};
+
+// Algorithm 1 for one site, q = 1/2, in double precision: the steps and the
+// cancellation-free energy change of update_site (see there), with the
+// proposal, wrap and acceptance test in the form of their plain definition:
+// phi'' = phi' + 2 pi (u - 1/2) / a taken mod 2 pi, accepted when
+// Delta H <= 0 or exp(-Delta H / T) > r.
+__device__ __forceinline__ SiteOutD update_site_d(double phi, double n0, double n1, double n2, double n3,
+                                                  uint32_t valid, double u, double r, double a, double T,
+                                                  bool or_only)
+{
+    const double th = 0.5 * phi;
+    const double nb[4] = {n0, n1, n2, n3};
+    double A2 = 0.0, B = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool v = (valid >> j) & 1u;
+        const double dj = v ? th - 0.5 * nb[j] : 0.0;
+        const double d2 = dj * dj;
+        const double s2 = sin2_half_d(dj, d2);  // 2 sin(D_j / 2)
+        B = fma(s2, cos_half_d(d2), B);         // sin D_j
+        A2 = fma(s2, s2, A2);                   // 2 (1 - cos D_j)
+    }
+    const double A_small = 0.5 * A2;
+    const int nnb = __popc(valid & 15u);
+    const double A = (double)nnb - A_small;
+    SiteOutD o;
+    o.e_before = A_small;
+    // reflection of th about the field direction: th' = th + 2 atan2(-B, A),
+    // kept when it leaves [0, pi) (or when there is no field)
+    double th1 = th;
+    bool kept = true;
+    if (nnb > 0 && (A != 0.0 || B != 0.0)) {
+        const double raw1 = fma(2.0, atan2_fp64(-B, A), th);
+        if (raw1 >= 0.0 && raw1 < kPi) {
+            th1 = raw1;
+            kept = false;
+        }
+    }
+    uint32_t f = F_UPDATED | F_FP64 | (kept ? F_KEPT : 0u);
+    if (or_only) {
+        o.phi = 2.0 * th1;
+        o.e_bonds = A_small;
+        o.flags = f;
+        o.accepted = false;
+        return o;
+    }
+    const double Bs = kept ? B : -B;  // |h| sin(th' - Psi)
+    const double dphi = kTwoPi * (u - 0.5) / a;
+    const double delta = 0.5 * dphi;
+    const double raw2 = 2.0 * th1 + dphi;
+    const bool wrapped = raw2 < 0.0 || raw2 >= kTwoPi;
+    double p2 = raw2 < 0.0 ? raw2 + kTwoPi : (raw2 >= kTwoPi ? raw2 - kTwoPi : raw2);
+    if (p2 >= kTwoPi || p2 < 0.0) p2 = 0.0;
+    const double dd2 = delta * delta;
+    const double sh2 = sin2_half_d(delta, dd2), ch = cos_half_d(dd2);  // 2 sin(delta/2), cos(delta/2)
+    const double sd = sh2 * ch;                                          // sin delta
+    const double w2 = wrapped ? 2.0 * (ch * ch) : 0.5 * (sh2 * sh2);
+    const double dH = fma(A, w2, wrapped ? -Bs * sd : Bs * sd);
+    const bool acc = (dH <= 0.0) || (exp(-dH / T) > r);
+    if (wrapped) f |= F_WRAPPED;
+    if (acc) f |= F_ACCEPTED;
+    o.phi = acc ? p2 : 2.0 * th1;
+    o.e_bonds = acc ? A_small + dH : A_small;
+    o.flags = f;
+    o.accepted = acc;
+    return o;
+}
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) v2d gv2d;
+__device__ __forceinline__ double gldd(const double *p) { return *(const gdouble *)p; }
+__device__ __forceinline__ double2 gldd2(const double *p)
+{
+    const v2d v = *(const gv2d *)p;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gstd(double *p, double v) { *(gdouble *)p = v; }
+__device__ __forceinline__ void gstd2(double *p, double2 v)
+{
+    v2d w;
+    w.x = v.x;
+    w.y = v.y;
+    *(gv2d *)p = w;
+}
+
+// accumulate_state for double-precision chains.
+__device__ __forceinline__ void accumulate_state_d(double *acc, double *m2, double phi, double inv_k, double inv_km1)
+{
+    const double s0 = gldd(acc);
+    const double s1 = s0 + phi;
+    gstd(acc, s1);
+    if (m2) gstd(m2, fma(phi - s0 * inv_km1, phi - s1 * inv_k, gldd(m2)));
+}
+
+// Bond energies of a double-precision site in fixed point, units of 2^-30
+// (at most 8 per site, so a chain of up to 2^30 sites of one colour sums
+// below 2^63).
+constexpr double kEnergyScale64 = 1073741824.0;
+constexpr double kEnergyUnit64 = 1.0 / 1073741824.0;
+__device__ __forceinline__ unsigned long long energy_fx_d(double e)
+{
+    return (unsigned long long)fma(e, kEnergyScale64, 0.5);
 }
 
 }  // namespace mpr

@@ -1,0 +1,269 @@
+"""GPU parity of the double-precision sweep (mpr_params.fp64) against the
+FP64 oracle.
+
+Both sides compute in double, so the bars are far tighter than for the
+single-precision sweep: teacher-forced half-sweeps take the same decisions
+at every site and agree in angle to rounding; free-running chains track the
+oracle's site by site through relaxation and the equilibrium states; the
+stopping rule stops at the same sweep.  The GPU's energy sums are fixed
+point of 2^-30 per site, so a colour's sum is within (sites) x 2^-31 of the
+exact one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_1811_01604_amd as mpr  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TWO_PI = 2.0 * math.pi
+PLAIN_TILES = [1, 2, 4, 8]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = mpr.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def colour_mask(ny, nx, colour):
+    return (np.add.outer(np.arange(ny), np.arange(nx)) % 2) == colour
+
+
+def smooth_state(ny, nx, nu, kappa, p_removed, noise, seed):
+    """Double angles of a smooth field, gaps perturbed around their true values."""
+    z = synth.matern_field(nx, ny, nu, kappa, 50.0, 10.0, seed)
+    m = synth.random_mask(nx, ny, p_removed, seed + 1)
+    phi = TWO_PI * (z - z.min()) / (z.max() - z.min())
+    rng = np.random.default_rng(seed + 2)
+    g = m == 0
+    phi[g] = np.mod(phi[g] + rng.normal(0, noise, size=g.sum()), TWO_PI)
+    return phi, m
+
+
+def run_pair(ctx, phi, m, colour, T, a, sweep, mode=0, seed=3000, tile=0):
+    """One half-sweep on the GPU (double) and in the oracle from the same state."""
+    ny, nx = phi.shape
+    g = dev(phi)
+    fl = torch.zeros((ny, nx), dtype=torch.uint8, device="cuda")
+    acc_g, e_g = ctx.diag_half_sweep_fp64(g, dev(m, torch.uint8), colour, T, a, sweep, seed=seed, mode=mode,
+                                          flags=fl, with_energy=True, tile=tile)
+    po, acc_o, fo = oracle.half_sweep(phi, m, colour, T, a, sweep, seed=seed, mode=mode, with_flags=True)
+    return g.cpu().numpy(), acc_g, e_g, fl.cpu().numpy(), po, acc_o, fo
+
+
+@pytest.mark.parametrize("kind", ["uniform", "smooth"])
+@pytest.mark.parametrize("shape", [(64, 64), (97, 131), (1, 40), (40, 1)])
+def test_fp64_over_relaxation_only(ctx, kind, shape):
+    ny, nx = shape
+    say("fp64 OR-only", kind, shape)
+    rng = np.random.default_rng(ny + 7 * nx)
+    if kind == "uniform":
+        phi = rng.uniform(0, TWO_PI, size=shape)
+        m = (rng.random(shape) < 0.3).astype(np.uint8)
+    else:
+        phi, m = smooth_state(max(ny, 2), max(nx, 2), 2.5, 0.05, 0.5, 0.01, 21)
+        phi, m = phi[:ny, :nx].copy(), m[:ny, :nx].copy()
+    for colour in (0, 1):
+        pg, acc_g, _, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 0.1, 1.0, 0, mode=1)
+        assert acc_g == 0 and acc_o == 0
+        sel = colour_mask(ny, nx, colour) & (m == 0)
+        assert np.array_equal(fg[sel] & 15, fo[sel] & 15)
+        if sel.any():
+            assert np.max(np.abs(pg[sel] - po[sel])) <= 1e-11
+        fixed = m == 1
+        assert np.array_equal(pg[fixed], phi[fixed])
+        phi = pg
+
+
+@pytest.mark.parametrize("T", [2.6e-4, 1.0e-3, 0.1])
+def test_fp64_decisions_teacher_forced(ctx, T):
+    """Every Metropolis decision equals the oracle's, down to T = 2.6e-4;
+    angles agree to 1e-11 rad; accepted counts are equal; the fused energy
+    is the oracle's energy of the written state within the fixed-point bound."""
+    say("fp64 decisions T =", T)
+    ny, nx = 384, 517
+    phi, m = smooth_state(ny, nx, 2.5, 0.05, 0.5, 0.02, 31)
+    ngp = oracle.bond_count(nx, ny)
+    n1 = int(colour_mask(ny, nx, 1).sum())
+    n_dec = 0
+    max_err = 0.0
+    step = 0
+    for a in (1.0, 4.0, 40.0):
+        for sweep in range(3):
+            for colour in (0, 1):
+                pg, acc_g, e_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, T, a, 100 * step + sweep)
+                sel = colour_mask(ny, nx, colour) & (m == 0)
+                n_dec += int(sel.sum())
+                assert np.array_equal(fg[sel] & 15, fo[sel] & 15), (a, sweep, colour)
+                assert acc_g == acc_o
+                max_err = max(max_err, float(np.max(np.abs(pg[sel] - po[sel]))))
+                if colour == 1:
+                    e_o = oracle.energy(po) + ngp
+                    assert abs(e_g - e_o) <= n1 * 2.0 ** -31 + 1e-9 * ngp, (e_g, e_o)
+                phi = pg
+            step += 1
+    say(f"  decisions {n_dec}, all equal; max |dphi| {max_err:.2e}")
+    assert max_err <= 1e-11
+
+
+@pytest.mark.parametrize("shape", [(1, 2), (2, 1), (3, 3), (5, 2), (2, 7), (1, 9)])
+def test_fp64_degenerate_and_tiny_grids(ctx, shape):
+    ny, nx = shape
+    rng = np.random.default_rng(nx * 10 + ny)
+    phi = rng.uniform(0, TWO_PI, size=shape)
+    m = np.zeros(shape, np.uint8)
+    for colour in (0, 1):
+        pg, acc_g, _, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 0.5, 1.0, 3)
+        sel = colour_mask(ny, nx, colour)
+        assert np.array_equal(fg[sel] & 15, fo[sel] & 15)
+        assert acc_g == acc_o
+        assert np.max(np.abs(pg - po)) <= 1e-11
+        phi = pg
+
+
+@pytest.mark.parametrize("p_removed", [0.0, 0.5, 1.0])
+@pytest.mark.parametrize("shape", [(67, 1100), (300, 129)])
+def test_fp64_half_sweep_identical_for_every_tile(ctx, shape, p_removed):
+    ny, nx = shape
+    phi, _ = smooth_state(ny, nx, 1.5, 0.1, 0.5, 0.05, 51)
+    m = (np.random.default_rng(52).random(shape) >= p_removed).astype(np.uint8)
+    mk = dev(m, torch.uint8)
+    for colour in (0, 1):
+        ref = None
+        for tile in PLAIN_TILES:
+            g = dev(phi)
+            fl = torch.zeros((ny, nx), dtype=torch.uint8, device="cuda")
+            acc, e = ctx.diag_half_sweep_fp64(g, mk, colour, 1e-3, 4.0, 11, flags=fl, with_energy=True, tile=tile)
+            out = (g.cpu().numpy().tobytes(), fl.cpu().numpy().tobytes(), acc, e)
+            if ref is None:
+                ref = out
+            else:
+                assert out == ref, (tile, colour)
+
+
+def simulate_gpu(ctx, phi32, mask, T, prm):
+    """mpr_simulate on one image from float sample angles; float outputs."""
+    ny, nx = phi32.shape
+    imgs = mpr.images([(ny, nx)])
+    ph = dev(phi32, torch.float32)
+    mk = dev(mask, torch.uint8)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    ps = torch.zeros_like(ph)
+    m2 = torch.zeros_like(ph) if (prm.K <= 1 or prm.spread) else None
+    st = ctx.simulate(imgs, ph, mk, np.array([T]), prm, ws, ps, phi_m2=m2)
+    return ps.cpu().numpy(), (m2.cpu().numpy() if m2 is not None else None), st
+
+
+def l64_angles():
+    im = synth.workload_l64()
+    po, zz = oracle.map_to_angles(im.z.astype(np.float32).astype(np.float64), im.mask)
+    return im, po.astype(np.float32)
+
+
+@pytest.mark.parametrize("n_relax", [1, 10, 40])
+def test_fp64_free_running_chains_track_oracle(ctx, n_relax):
+    """R = 2 chains, n_relax relaxation sweeps and K = 3 states at T = 0.15,
+    from the same float sample angles: the sums of the states agree with the
+    oracle's at every gap site to the float rounding of the output."""
+    im, phi32 = l64_angles()
+    prm = mpr.default_params(R=2, K=3, fixed_relax=n_relax, seed=77, fp64=1)
+    ps, _, st = simulate_gpu(ctx, phi32, im.mask, 0.15, prm)
+    opr = oracle.default_params(R=2, K=3, fixed_relax=n_relax, seed=77)
+    po, sto, _, _ = oracle.simulate(phi32.astype(np.float64), im.mask, 0.15, opr)
+    g = im.mask == 0
+    d = np.abs(ps[g].astype(np.float64) - po[g])
+    say(f"  fp64, {n_relax} relaxation sweeps: max |phi_sum gpu - oracle| {d.max():.2e}")
+    assert d.max() <= 4e-6  # sums below 6 pi, float rounding of the output
+    assert [s["relax_sweeps"] for s in st] == [s["relax_sweeps"] for s in sto] == [n_relax] * 2
+    assert [s["a_final"] for s in st] == [s["a_final"] for s in sto]
+
+
+def test_fp64_stopping_rule_and_spread_match_oracle(ctx):
+    """The whole simulation with the stopping rule (R = 4, K = 10, spread on):
+    each chain stops at the oracle's sweep with its slope, and the sums of
+    the states and of their squared deviations agree site by site."""
+    im, phi32 = l64_angles()
+    T = 0.05
+    prm = mpr.default_params(R=4, K=10, seed=5, fp64=1, spread=1)
+    ps, m2, st = simulate_gpu(ctx, phi32, im.mask, T, prm)
+    opr = oracle.default_params(R=4, K=10, seed=5)
+    po, sto, _, _, pq = oracle.simulate(phi32.astype(np.float64), im.mask, T, opr, want_sq=True)
+    rs_g = [s["relax_sweeps"] for s in st]
+    rs_o = [s["relax_sweeps"] for s in sto]
+    say(f"  fp64 stopping: gpu {rs_g} oracle {rs_o}")
+    assert rs_g == rs_o
+    # the slope is sum_j w_j e_j with the least-squares weights w_j = (j - c) /
+    # sum (j - c)^2 over the last n_fit energies; each GPU e_j is within
+    # (colour-1 sites) x 2^-31 / N_GP of the exact one (fixed-point rounding)
+    j = np.arange(prm.n_fit) - 0.5 * (prm.n_fit - 1)
+    w_abs = float(np.sum(np.abs(j)) / np.sum(j * j))
+    ngp = oracle.bond_count(64, 64)
+    tol_k = w_abs * int(colour_mask(64, 64, 1).sum()) * 2.0 ** -31 / ngp
+    for a, b in zip(st, sto):
+        assert abs(a["k_last"] - b["k_last"]) <= tol_k + 1e-12 * abs(b["k_last"]), (a["k_last"], b["k_last"])
+        assert a["a_final"] == b["a_final"]
+    g = im.mask == 0
+    d = np.abs(ps[g].astype(np.float64) - po[g])
+    m2_o = pq - po * po / 40.0
+    dm = np.abs(m2[g].astype(np.float64) - m2_o[g])
+    say(f"  max |phi_sum diff| {d.max():.2e}, max |m2 diff| {dm.max():.2e}")
+    assert d.max() <= 4e-5  # sums below 80 pi
+    assert np.all(dm <= 1e-6 * np.maximum(1.0, m2_o[g]) + 1e-7)
+    assert np.all(ps[~g] == 0) and np.all(m2[~g] == 0)
+
+
+def test_fp64_batch_matches_single_and_rejects_compact_shape(ctx):
+    """A ragged batch in double precision gives each image the result it
+    gets alone; compacted block shapes are refused for double chains."""
+    im = synth.workload_l64()
+    shapes = [(64, 64), (24, 40)]
+    zs = [im.z, synth.matern_field(40, 24, 1.5, 0.1, 50, 10, 5)]
+    ms = [im.mask, synth.random_mask(40, 24, 0.4, 6)]
+    prm = mpr.default_params(R=2, K=3, fp64=1)
+    T = np.array([0.15, 0.02])
+
+    def run(sel):
+        imgs = mpr.images([shapes[i] for i in sel], ids=list(sel))
+        z = dev(np.concatenate([zs[i].astype(np.float32).ravel() for i in sel]), torch.float32)
+        mk = dev(np.concatenate([ms[i].ravel() for i in sel]), torch.uint8)
+        phi = torch.zeros_like(z)
+        ctx.map_to_angles(imgs, z, mk, phi)
+        ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+        ps = torch.zeros_like(z)
+        ctx.simulate(imgs, phi, mk, T[list(sel)], prm, ws, ps)
+        out, off = {}, 0
+        for i in sel:
+            n = shapes[i][0] * shapes[i][1]
+            out[i] = ps[off:off + n].cpu().numpy()
+            off += n
+        return out
+
+    both = run([0, 1])
+    for i in range(2):
+        assert np.array_equal(both[i], run([i])[i]), i
+    bad = mpr.default_params(R=1, K=1, fp64=1, tile_rows=4 | mpr.TILE_COMPACT)
+    imgs = mpr.images([(8, 8)])
+    assert ctx.workspace_size(imgs, bad) < 0
+    with pytest.raises(mpr.MprError) as e:
+        ctx.simulate(imgs, torch.zeros(64, device="cuda"), torch.zeros(64, dtype=torch.uint8, device="cuda"),
+                     np.array([0.1]), bad, torch.empty(1 << 20, dtype=torch.uint8, device="cuda"),
+                     torch.zeros(64, device="cuda"))
+    assert e.value.code == mpr.MPR_ERR_ARG
