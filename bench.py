@@ -56,11 +56,12 @@ def kernel_source_sha() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, chains: int, tile: int):
+def measured_traffic(workload: str, chains: int, key: str):
     """HBM bytes per half-sweep launch from the committed rocprofv3 counter
     runs (FETCH_SIZE + WRITE_SIZE, scaled by the copy-probe calibration), or
     None when they were taken on other kernel sources, another workload or
-    another sweep block shape."""
+    another sweep kernel (key: the block shape's tile_rows value, prefixed
+    "fp64-" for the double-precision sweep)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -68,7 +69,7 @@ def measured_traffic(workload: str, chains: int, tile: int):
         return None
     if t.get("source_sha256") != kernel_source_sha() or t.get("workload") != workload or t.get("chains") != chains:
         return None
-    return (t.get("by_tile") or {}).get(str(tile), {}).get("traffic_bytes_per_launch")
+    return (t.get("by_tile") or {}).get(key, {}).get("traffic_bytes_per_launch")
 
 
 def cpu_baseline(im, T: float, sweeps: int, seed: int) -> dict:
@@ -139,6 +140,8 @@ def main():
     ap.add_argument("--tile", default="auto",
                     help="sweep block shape: auto (tuned), or rows 1/2/4/8, with a 'c' suffix for the compacted "
                          "shapes 2c/4c/8c (for profiling runs that must see one kernel)")
+    ap.add_argument("--fp64", action="store_true",
+                    help="run the chains in double precision (the paper's DP variant; plain block shapes)")
     ap.add_argument("--warm-seeds", type=int, default=8,
                     help="images per mask type for the warm-start comparison at L=2048 (0 = skip)")
     args = ap.parse_args()
@@ -166,7 +169,8 @@ def main():
     tile = 0
     if args.tile != "auto":
         tile = int(args.tile.rstrip("c")) | (mpr.TILE_COMPACT if args.tile.endswith("c") else 0)
-    prm = mpr.default_params(R=args.chains, K=args.K, fixed_relax=args.fixed_sweeps, tile_rows=tile)
+    prm = mpr.default_params(R=args.chains, K=args.K, fixed_relax=args.fixed_sweeps, tile_rows=tile,
+                             fp64=1 if args.fp64 else 0)
     ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
     P = int((im.mask == 0).sum())
     M = prm.R * prm.K
@@ -225,7 +229,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.fp64 else "f32",
         "data": "synthetic",
         "config": {
             "workload": desc,
@@ -237,8 +241,11 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, prm.R, prof["last_tile"]),
-            "kernel": ("half_sweep_compact_kernel" if prof["last_tile"] & mpr.TILE_COMPACT else "half_sweep_kernel"),
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(args.workload, prm.R,
+                                        ("fp64-" if args.fp64 else "") + str(prof["last_tile"])),
+            "kernel": ("half_sweep_fp64_kernel" if args.fp64 else
+                       "half_sweep_compact_kernel" if prof["last_tile"] & mpr.TILE_COMPACT else "half_sweep_kernel"),
             "tile_rows": prof["last_tile"] & 0xFF,
             "launch_ms": launch_ms, "useful_bytes_per_launch": bytes_per_launch,
             "sweep_kernel_time_share": prof["sweep_kernel_ms"] * 1e-3 / dt,

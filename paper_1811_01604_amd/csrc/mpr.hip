@@ -573,11 +573,14 @@ __global__ __launch_bounds__(kBlock) void half_sweep_compact_kernel(const ChainD
 }
 
 // The deferred double-precision updates of one half-sweep (block shape
-// `rows`, `compact`): each flagged site is redone by update_site_fp64 from
-// the inputs the sweep saw (it left the site unchanged), with the same
-// random numbers, written, and its accepted count and bond energy added to
-// its chain.  The bits are cleared on the way, so the buffers are zero
-// again for the next half-sweep.
+// `rows`, `compact`): each flagged site is redone by update_site_d from the
+// inputs the sweep saw (it left the site unchanged), with the same random
+// numbers, written back in single precision, and its accepted count and
+// bond energy added to its chain.  A wave takes one bitmap word (32 sweep
+// blocks) at a time; its lanes split over (flagged block, mask word), 64 /
+// words blocks per pass, and a lane redoes the sites of its mask word.  The
+// bits are cleared on the way, so the buffers are zero again for the next
+// half-sweep.
 template <bool DIAG>
 __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__restrict__ descs,
                                                            ChainState *__restrict__ states,
@@ -586,25 +589,28 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
                                                            SweepConsts sc, int or_only, Redo rd,
                                                            uint8_t *__restrict__ flags)
 {
-    const int words = compact ? kCompactSites / 32 : 2 * kBlock / 32;
+    const int words = compact ? kCompactSites / 32 : 2 * kBlock / 32;  // 32 or 16
+    const int per = 64 / words;                                         // blocks per pass
     const int ppr = compact ? kCompactSites / rows / 2 : kBlock / rows;  // site pairs per block row
     const int64_t nw = (total_blocks + 31) >> 5;
     const int lane = (int)(threadIdx.x & 63);
+    const int slot = lane / words, k = lane % words;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    // each wave reads 64 bitmap words at a time; the 32 blocks of a flagged
-    // word go to lanes 0-31, so flagged sites of different blocks run in parallel
-    for (int64_t w0 = wave * 64; w0 < nw; w0 += n_waves * 64) {
-        const int64_t wl = w0 + lane;
-        const uint32_t mine_bits = wl < nw ? rd.blocks[wl] : 0u;
-        uint64_t todo = __ballot(mine_bits != 0u);
-        if (wl < nw && mine_bits) rd.blocks[wl] = 0u;
-        while (todo) {
-            const int src = __ffsll((long long)todo) - 1;
-            todo &= todo - 1ull;
-            const uint32_t bits = __shfl(mine_bits, src);
-            if (lane >= 32 || !((bits >> lane) & 1u)) continue;
-            const int64_t gb = ((w0 + src) << 5) + lane;
+    for (int64_t wi = wave; wi < nw; wi += n_waves) {
+        uint32_t bits = rd.blocks[wi];
+        if (!bits) continue;
+        if (lane == 0) rd.blocks[wi] = 0u;
+        while (bits) {
+            // this lane's block: the slot-th lowest set bit of this pass
+            uint32_t b = bits;
+            for (int i = 0; i < slot; ++i) b &= b - 1u;
+            for (int i = 0; i < per; ++i) bits &= bits - 1u;
+            if (!b) continue;
+            const int64_t gb = (wi << 5) + (__ffs(b) - 1);
+            uint32_t m = rd.mask[gb * words + k];
+            if (!m) continue;
+            rd.mask[gb * words + k] = 0u;
             const int c = find_chain(start, n_chains, gb);
             ChainState *stp = states + c;
             const ChainDesc d = descs[c];
@@ -619,46 +625,42 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
             const float *oth = colour ? d.h[0] : d.h[1];
             float *accp = (phase == PH_EQ) ? (colour ? d.acc[1] : d.acc[0]) : nullptr;
             float *m2p = accp ? (colour ? d.m2[1] : d.m2[0]) : nullptr;
-            for (int k = 0; k < words; ++k) {
-                uint32_t m = rd.mask[gb * words + k];
-                if (!m) continue;
-                rd.mask[gb * words + k] = 0u;
-                while (m) {
-                    const int bit = __ffs(m) - 1;
-                    m &= m - 1u;
-                    const int idx = 32 * k + bit;
-                    const int pi = idx >> 1, slot = idx & 1;
-                    const int y = by * rows + pi / ppr;
-                    const int h = 2 * (bx * ppr + pi % ppr) + slot;
-                    const int s = (y + colour) & 1;
-                    const int Wo = (d.nx + s) >> 1;
-                    const uint32_t valid = (h + s - 1 >= 0 ? 1u : 0u) | (h + s < Wo ? 2u : 0u) |
-                                           (y > 0 ? 4u : 0u) | (y + 1 < d.ny ? 8u : 0u);
-                    const float *orow = oth + (int64_t)y * d.S;
-                    const float nL = (valid & 1u) ? angle_of(orow[h + s - 1]) : 0.0f;
-                    const float nR = (valid & 2u) ? angle_of(orow[h + s]) : 0.0f;
-                    const float nU = (valid & 4u) ? angle_of(orow[h - d.S]) : 0.0f;
-                    const float nD = (valid & 8u) ? angle_of(orow[h + d.S]) : 0.0f;
-                    float *mp = mine + (int64_t)y * d.S + h;
-                    const float a = angle_of(*mp);
-                    float u = 0.5f, r = 0.5f;
-                    if (!or_only) {
-                        const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * (h & ~1) + s), stp->sweep,
-                                        d.chain, d.image_id};
-                        const U4 wd = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
-                        u = unit24(slot ? wd.z : wd.x);
-                        r = unit24(slot ? wd.w : wd.y);
-                    }
-                    const SiteOut o = update_site_fp64((double)a, nL, nR, nU, nD, valid, (double)u, (double)r,
-                                                       stp->a_cur, stp->T, sc.q64, or_only != 0);
-                    *mp = o.phi;
-                    if (accp)
-                        accumulate_state(accp + (int64_t)y * d.S + h, m2p ? m2p + (int64_t)y * d.S + h : nullptr,
-                                         o.phi, stp->inv_k, stp->inv_km1);
-                    if (want_acc && o.accepted) atomicAdd(&stp->acc, 1ull);
-                    if (want_energy) atomicAdd(&stp->e_fx, (unsigned long long)energy_fx(o.e_bonds));
-                    if (DIAG && flags) flags[(int64_t)y * d.nx + 2 * h + s] = (uint8_t)o.flags;
+            while (m) {
+                const int bit = __ffs(m) - 1;
+                m &= m - 1u;
+                const int idx = 32 * k + bit;
+                const int pi = idx >> 1, sl = idx & 1;
+                const int y = by * rows + pi / ppr;
+                const int h = 2 * (bx * ppr + pi % ppr) + sl;
+                const int s = (y + colour) & 1;
+                const int Wo = (d.nx + s) >> 1;
+                const uint32_t valid = (h + s - 1 >= 0 ? 1u : 0u) | (h + s < Wo ? 2u : 0u) |
+                                       (y > 0 ? 4u : 0u) | (y + 1 < d.ny ? 8u : 0u);
+                const float *orow = oth + (int64_t)y * d.S;
+                const float nL = (valid & 1u) ? angle_of(orow[h + s - 1]) : 0.0f;
+                const float nR = (valid & 2u) ? angle_of(orow[h + s]) : 0.0f;
+                const float nU = (valid & 4u) ? angle_of(orow[h - d.S]) : 0.0f;
+                const float nD = (valid & 8u) ? angle_of(orow[h + d.S]) : 0.0f;
+                float *mp = mine + (int64_t)y * d.S + h;
+                const float a = angle_of(*mp);
+                float u = 0.5f, r = 0.5f;
+                if (!or_only) {
+                    const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * (h & ~1) + s), stp->sweep,
+                                    d.chain, d.image_id};
+                    const U4 wd = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
+                    u = unit24(sl ? wd.z : wd.x);
+                    r = unit24(sl ? wd.w : wd.y);
                 }
+                const SiteOutD o = update_site_d((double)a, (double)nL, (double)nR, (double)nU, (double)nD, valid,
+                                                 (double)u, (double)r, stp->a_cur, stp->T, or_only != 0);
+                const float out = (float)o.phi;
+                *mp = out;
+                if (accp)
+                    accumulate_state(accp + (int64_t)y * d.S + h, m2p ? m2p + (int64_t)y * d.S + h : nullptr, out,
+                                     stp->inv_k, stp->inv_km1);
+                if (want_acc && o.accepted) atomicAdd(&stp->acc, 1ull);
+                if (want_energy) atomicAdd(&stp->e_fx, (unsigned long long)energy_fx((float)o.e_bonds));
+                if (DIAG && flags) flags[(int64_t)y * d.nx + 2 * h + s] = (uint8_t)o.flags;
             }
         }
     }
@@ -1434,8 +1436,9 @@ template <bool DIAG>
 void launch_redo(hipStream_t st, const ChainSet &cs, int v, int colour, const SweepConsts &sc, int or_only,
                  uint8_t *flags)
 {
+    // a wave per bitmap word, at most 16384 waves
     const int64_t nw = (cs.total_blocks[v] + 31) / 32;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kBlock - 1) / kBlock, 1024));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 3) / 4, 4096));
     hipLaunchKernelGGL((redo_fp64_kernel<DIAG>), dim3(grid), dim3(kBlock), 0, st, cs.d_desc, cs.d_state,
                        cs.d_start[v], (int)cs.desc.size(), cs.total_blocks[v], kShapes[v].rows,
                        kShapes[v].compact ? 1 : 0, colour, sc, or_only, cs.redo, flags);

@@ -147,73 +147,6 @@ __device__ __forceinline__ double atan2_fp64(double y, double x)
     return y < 0.0 ? -a : a;
 }
 
-// The whole update of one site in double precision, in the same steps and
-// order as the plain definition: local q-field, reflection with the keep
-// rule, wrapped proposal, Delta H as the difference of the two local
-// energies, and the acceptance test.  Used when the single-precision
-// decision is too close to call.
-__device__ __noinline__ SiteOut update_site_fp64(double phi, float n0, float n1, float n2, float n3,
-                                                 uint32_t valid, double u, double r, double a, double T,
-                                                 double q, bool or_only)
-{
-#pragma clang fp contract(off)
-    double sx = 0.0, sy = 0.0;
-    int nnb = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (valid & (1u << j)) {
-            const double v = (double)(j == 0 ? n0 : j == 1 ? n1 : j == 2 ? n2 : n3);
-            sx += cos(q * v);
-            sy += sin(q * v);
-            ++nnb;
-        }
-    }
-    double p1;
-    uint32_t f = F_UPDATED | F_FP64;
-    if (nnb == 0 || (sx == 0.0 && sy == 0.0)) {
-        p1 = phi;
-        f |= F_KEPT;
-    } else {
-        const double psi = atan2_fp64(sy, sx);
-        p1 = (2.0 * psi - q * phi) / q;
-        if (!(p1 >= 0.0 && p1 < kTwoPi)) {
-            p1 = phi;
-            f |= F_KEPT;
-        }
-    }
-    double h1 = 0.0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if (valid & (1u << j)) h1 -= cos(q * (p1 - (double)(j == 0 ? n0 : j == 1 ? n1 : j == 2 ? n2 : n3)));
-    SiteOut o;
-    o.e_before = (float)((double)nnb + h1);
-    if (or_only) {
-        o.phi = (float)p1;
-        o.e_bonds = (float)((double)nnb + h1);
-        o.flags = f;
-        o.accepted = false;
-        return o;
-    }
-    const double raw = p1 + kTwoPi * (u - 0.5) / a;
-    double p2 = raw;
-    if (p2 < 0.0) p2 += kTwoPi;
-    else if (p2 >= kTwoPi) p2 -= kTwoPi;
-    if (p2 >= kTwoPi || p2 < 0.0) p2 = 0.0;
-    if (raw < 0.0 || raw >= kTwoPi) f |= F_WRAPPED;
-    double h2 = 0.0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if (valid & (1u << j)) h2 -= cos(q * (p2 - (double)(j == 0 ? n0 : j == 1 ? n1 : j == 2 ? n2 : n3)));
-    const double dH = h2 - h1;
-    const bool acc = (dH <= 0.0) || (exp(-dH / T) > r);
-    if (acc) f |= F_ACCEPTED;
-    o.phi = (float)(acc ? p2 : p1);
-    o.e_bonds = (float)((double)nnb + (acc ? h2 : h1));
-    o.flags = f;
-    o.accepted = acc;
-    return o;
-}
-
 // ------------------------------------------------ single-precision math
 // Minimax polynomials fitted for this library (least squares with Lawson
 // reweighting on Chebyshev nodes):
