@@ -73,7 +73,9 @@ def measured_traffic(workload: str, chains: int, key: str):
 
 
 def cpu_baseline(im, T: float, sweeps: int, seed: int) -> dict:
-    """The oracle's sweep on one chain of the same workload (bounded sample)."""
+    """The oracle's sweep on one chain of the same workload (bounded sample),
+    at a fixed temperature T (an input: the work per sweep does not depend
+    on it)."""
     import numpy as np
     import oracle
     z = im.z.astype(np.float32).astype(np.float64)
@@ -275,7 +277,7 @@ def main():
     ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(im, T, args.cpu_sweeps, 3002)
+        out["cpu_baseline"] = cpu_baseline(im, 1e-4, args.cpu_sweeps, 3002)
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,95 @@
+"""Throughput of a ragged batch on one GPU.
+
+256 images with sides log-uniform in [128, 2048] (Matern fields, nu in
+{0.5, 1.5, 2.5}, kappa log-uniform in [0.01, 0.3], 20-80% of the sites
+removed at random), R = 16 chains each (M = 16): one call each of map,
+temperature (the e(T, L) tables of all 256 grid sizes built together, 12
+temperatures, 100 + 200 sweeps), simulate (all 4096 chains in one chain set,
+stopping rule) and predict.  Reports the wall time of each call and the
+sweep throughput (gap-site updates per second of sweep-kernel time, and the
+useful HBM bytes per second against 8 TB/s) of the second fill (the first
+tunes the block shape).
+
+    python -m paper_1811_01604_amd.batch_study [--images 256] [--chains 16]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--images", type=int, default=256)
+    ap.add_argument("--chains", type=int, default=16)
+    ap.add_argument("--workers", type=int, default=8)
+    args = ap.parse_args()
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    import synth
+    import torch
+    import paper_1811_01604_amd as mpr
+
+    t0 = time.perf_counter()
+    ims = synth.ragged_batch(args.images, workers=args.workers)
+    log(f"{args.images} images made in {time.perf_counter() - t0:.1f} s")
+    shapes = [im.z.shape for im in ims]
+    imgs = mpr.images(shapes, ids=list(range(len(ims))))
+    z = torch.from_numpy(np.concatenate([im.z.astype(np.float32).ravel() for im in ims])).cuda()
+    mk = torch.from_numpy(np.concatenate([im.mask.ravel() for im in ims])).cuda()
+    sites = int(z.numel())
+    gaps = int((mk == 0).sum().item())
+    ctx = mpr.Context(0)
+    prm = mpr.default_params(R=args.chains, K=1, table_nT=12, table_burn=100, table_meas=200)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    phi, ps, zh = torch.zeros_like(z), torch.zeros_like(z), torch.zeros_like(z)
+
+    def timed(f):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    zz, t_map = timed(lambda: ctx.map_to_angles(imgs, z, mk, phi))
+    (e_s, T, cl), t_temp = timed(lambda: ctx.estimate_temperature(imgs, phi, mk, prm, ws))
+    log(f"map {t_map * 1e3:.1f} ms; temperature (256 tables) {t_temp:.2f} s")
+    out = None
+    for rep in range(2):
+        ctx.profile_enable(True)
+        st, t_sim = timed(lambda: ctx.simulate(imgs, phi, mk, T, prm, ws, ps))
+        pr = ctx.profile_read()
+        ctx.profile_enable(False)
+        _, t_pred = timed(lambda: ctx.predict(imgs, z, mk, ps, zz, prm.R, zh))
+        sweeps = np.array([s["relax_sweeps"] for s in st]) + 1
+        out = {
+            "workload": f"{len(ims)} ragged images (sides log-uniform in [128, 2048]), {sites} sites, {gaps} gaps, "
+                        f"R={prm.R} chains each, K=1",
+            "fill": rep, "map_s": t_map, "temperature_s": t_temp, "simulate_s": t_sim, "predict_s": t_pred,
+            "site_updates": pr["site_updates"], "site_updates_per_s_wall": pr["site_updates"] / t_sim,
+            "site_updates_per_s_sweep_kernels": pr["site_updates"] / (pr["sweep_kernel_ms"] * 1e-3),
+            "useful_GBps": pr["useful_bytes"] / (pr["sweep_kernel_ms"] * 1e-3) / 1e9,
+            "hbm_frac": pr["useful_bytes"] / (pr["sweep_kernel_ms"] * 1e-3) / 8e12,
+            "sweeps_per_chain_mean": float(sweeps.mean()), "sweeps_per_chain_max": int(sweeps.max()),
+            "tile": pr["last_tile"], "T_hat_range": [float(np.min(T)), float(np.max(T))],
+            "t_clamped": int(np.sum(cl)),
+        }
+        log(f"fill {rep}: simulate {t_sim:.2f} s ({out['site_updates_per_s_wall']:.3e} site-updates/s wall), "
+            f"predict {t_pred * 1e3:.1f} ms")
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

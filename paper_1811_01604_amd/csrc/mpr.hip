@@ -170,6 +170,24 @@ __device__ __forceinline__ int find_chain(const int64_t *__restrict__ start, int
     return lo;
 }
 
+// The blocks of a sweep launch, laid end to end over the chains it covers
+// (the chains not yet done): launch chain k < n owns blocks start[k] <= b <
+// start[k + 1] and is chain id[k] of the chain set.
+struct BlockMap {
+    const int64_t *start;
+    const int32_t *id;
+    int32_t n;
+    int32_t pad;
+};
+
+// Chain of block b, and the block's index within that chain.
+__device__ __forceinline__ int chain_of_block(const BlockMap &bm, int64_t b, int *local)
+{
+    const int k = find_chain(bm.start, bm.n, b);
+    *local = (int)(b - bm.start[k]);
+    return bm.id[k];
+}
+
 // Half-sweep of colour `colour` for every chain of a (possibly ragged)
 // batch in one launch.  The blocks of all chains are laid end to end
 // (start[] = prefix sums of blocks per chain).  A 256-thread block covers
@@ -180,16 +198,16 @@ __device__ __forceinline__ int find_chain(const int64_t *__restrict__ start, int
 template <bool DIAG, int ROWS>
 __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ descs,
                                                 ChainState *__restrict__ states,
-                                                const int64_t *__restrict__ start, int n_chains, int colour,
+                                                BlockMap bm, int colour,
                                                 SweepConsts sc, int or_only, Redo rd, uint8_t *__restrict__ flags)
 {
     constexpr int PX = kBlock / ROWS;
-    const int c = find_chain(start, n_chains, (int64_t)blockIdx.x);
+    int lb;
+    const int c = chain_of_block(bm, (int64_t)blockIdx.x, &lb);
     ChainState *stp = states + c;
     const int phase = stp->phase;
     if (phase == PH_DONE) return;
     const ChainDesc d = descs[c];
-    const int lb = (int)((int64_t)blockIdx.x - start[c]);
     const int nbx = ((d.S >> 1) + PX - 1) / PX;
     const int by = lb / nbx;
     const int bx = lb - by * nbx;
@@ -308,11 +326,11 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
 template <bool DIAG, int ROWS>
 __global__ __launch_bounds__(kBlock) void half_sweep_kernel(const ChainDesc *__restrict__ descs,
                                                             ChainState *__restrict__ states,
-                                                            const int64_t *__restrict__ start, int n_chains,
+                                                            BlockMap bm,
                                                             int colour, SweepConsts sc, int or_only, Redo rd,
                                                             uint8_t *__restrict__ flags)
 {
-    half_sweep_body<DIAG, ROWS>(descs, states, start, n_chains, colour, sc, or_only, rd, flags);
+    half_sweep_body<DIAG, ROWS>(descs, states, bm, colour, sc, or_only, rd, flags);
 }
 
 // The same sweep for the unconditional e(T, L) runs (a separate symbol so
@@ -320,10 +338,9 @@ __global__ __launch_bounds__(kBlock) void half_sweep_kernel(const ChainDesc *__r
 template <int ROWS>
 __global__ __launch_bounds__(kBlock) void table_half_sweep_kernel(const ChainDesc *__restrict__ descs,
                                                                   ChainState *__restrict__ states,
-                                                                  const int64_t *__restrict__ start,
-                                                                  int n_chains, int colour, SweepConsts sc, Redo rd)
+                                                                  BlockMap bm, int colour, SweepConsts sc, Redo rd)
 {
-    half_sweep_body<false, ROWS>(descs, states, start, n_chains, colour, sc, 0, rd, nullptr);
+    half_sweep_body<false, ROWS>(descs, states, bm, colour, sc, 0, rd, nullptr);
 }
 
 // The same half-sweep with the gap sites compacted onto consecutive lanes
@@ -338,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void table_half_sweep_kernel(const ChainDes
 template <bool DIAG, int CR>
 __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restrict__ descs,
                                                         ChainState *__restrict__ states,
-                                                        const int64_t *__restrict__ start, int n_chains,
+                                                        BlockMap bm,
                                                         int colour, SweepConsts sc, int or_only, Redo rd,
                                                         uint8_t *__restrict__ flags)
 {
@@ -351,12 +368,12 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
     __shared__ uint32_t wave_count[2][2][NW];  // [list][pair of the thread][wave]
     __shared__ uint32_t red[2][NW];
 
-    const int c = find_chain(start, n_chains, (int64_t)blockIdx.x);
+    int lb;
+    const int c = chain_of_block(bm, (int64_t)blockIdx.x, &lb);
     ChainState *stp = states + c;
     const int phase = stp->phase;
     if (phase == PH_DONE) return;
     const ChainDesc d = descs[c];
-    const int lb = (int)((int64_t)blockIdx.x - start[c]);
     const int nbx = ((d.S >> 1) + PPR - 1) / PPR;
     const int by = lb / nbx;
     const int bx = lb - by * nbx;
@@ -565,11 +582,10 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
 template <bool DIAG, int CR>
 __global__ __launch_bounds__(kBlock) void half_sweep_compact_kernel(const ChainDesc *__restrict__ descs,
                                                                     ChainState *__restrict__ states,
-                                                                    const int64_t *__restrict__ start,
-                                                                    int n_chains, int colour, SweepConsts sc,
+                                                                    BlockMap bm, int colour, SweepConsts sc,
                                                                     int or_only, Redo rd, uint8_t *__restrict__ flags)
 {
-    half_sweep_compact_body<DIAG, CR>(descs, states, start, n_chains, colour, sc, or_only, rd, flags);
+    half_sweep_compact_body<DIAG, CR>(descs, states, bm, colour, sc, or_only, rd, flags);
 }
 
 // The deferred double-precision updates of one half-sweep (block shape
@@ -584,7 +600,7 @@ __global__ __launch_bounds__(kBlock) void half_sweep_compact_kernel(const ChainD
 template <bool DIAG>
 __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__restrict__ descs,
                                                            ChainState *__restrict__ states,
-                                                           const int64_t *__restrict__ start, int n_chains,
+                                                           BlockMap bm,
                                                            int64_t total_blocks, int rows, int compact, int colour,
                                                            SweepConsts sc, int or_only, Redo rd,
                                                            uint8_t *__restrict__ flags)
@@ -611,10 +627,10 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
             uint32_t m = rd.mask[gb * words + k];
             if (!m) continue;
             rd.mask[gb * words + k] = 0u;
-            const int c = find_chain(start, n_chains, gb);
+            int lb;
+            const int c = chain_of_block(bm, gb, &lb);
             ChainState *stp = states + c;
             const ChainDesc d = descs[c];
-            const int lb = (int)(gb - start[c]);
             const int nbx = ((d.S >> 1) + ppr - 1) / ppr;
             const int by = lb / nbx;
             const int bx = lb - by * nbx;
@@ -674,17 +690,17 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
 template <bool DIAG, int ROWS>
 __global__ __launch_bounds__(kBlock) void half_sweep_fp64_kernel(const ChainDesc *__restrict__ descs,
                                                                  ChainState *__restrict__ states,
-                                                                 const int64_t *__restrict__ start, int n_chains,
+                                                                 BlockMap bm,
                                                                  int colour, SweepConsts sc, int or_only,
                                                                  uint8_t *__restrict__ flags)
 {
     constexpr int PX = kBlock / ROWS;
-    const int c = find_chain(start, n_chains, (int64_t)blockIdx.x);
+    int lb;
+    const int c = chain_of_block(bm, (int64_t)blockIdx.x, &lb);
     ChainState *stp = states + c;
     const int phase = stp->phase;
     if (phase == PH_DONE) return;
     const ChainDesc d = descs[c];
-    const int lb = (int)((int64_t)blockIdx.x - start[c]);
     const int nbx = ((d.S >> 1) + PX - 1) / PX;
     const int by = lb / nbx;
     const int bx = lb - by * nbx;
@@ -845,6 +861,13 @@ __global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *
     set_derived(st, cp.q);
     states[c] = st;
     if (st.phase == PH_DONE) atomicAdd(done_count, 1u);
+}
+
+// 1 for every chain that is done, else 0 (for rebuilding the launch list).
+__global__ void done_flags_kernel(const ChainState *__restrict__ states, int n, uint8_t *__restrict__ out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) out[c] = states[c].phase == PH_DONE ? 1 : 0;
 }
 
 // phi_sum at every site of image blockIdx.y: sum over its R chains of the
@@ -1293,7 +1316,7 @@ int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     const int64_t chains = (int64_t)n * p->R;
     b += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
     b += round_up(chains * 8, 256) + round_up((int64_t)n * sizeof(ImgDev), 256) + 4096;
-    b += round_up(kNumShapes * (chains + 1) * 8, 256);
+    b += round_up(kNumShapes * (chains + 1) * 8, 256) + round_up(chains * 4 + 4, 256);
     for (int i = 0; i < n; ++i) b += redo_bytes(imgs[i].nx, imgs[i].ny, p->R);
     return b;
 }
@@ -1309,7 +1332,7 @@ int64_t table_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     best += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
     best += round_up(chains * 8, 256) + round_up((int64_t)n * sizeof(ImgDev), 256) + 4096;
     best += round_up((int64_t)n * kMapBlocks * 16, 256);
-    best += round_up(kNumShapes * (chains + 1) * 8, 256);
+    best += round_up(kNumShapes * (chains + 1) * 8, 256) + round_up(chains * 4 + 4, 256);
     int64_t rb = 0;
     for (int i = 0; i < n; ++i) rb = std::max(rb, redo_bytes(imgs[i].nx, imgs[i].ny, chains));
     return best + rb;
@@ -1404,31 +1427,37 @@ struct ChainSet {
     ChainDesc *d_desc = nullptr;
     ChainState *d_state = nullptr;
     int64_t *d_offset = nullptr;
-    int64_t *d_start[kNumShapes] = {};  // block prefix sums per shape
+    // the chains a sweep launch covers (those not done when the launch list
+    // was last built): block prefix sums per shape and chain ids
+    int64_t *d_start[kNumShapes] = {};
+    int32_t *d_ids = nullptr;
+    int n_active = 0;
     int64_t total_blocks[kNumShapes] = {};
+    std::vector<int64_t> h_start;  // host copies (kept until their upload is done)
+    std::vector<int32_t> h_ids;
     Redo redo = {nullptr, nullptr};      // deferred double-precision updates (zeroed)
     bool fp64 = false;                   // double-precision chains (plain shapes, no deferral)
 };
 
+BlockMap block_map(const ChainSet &cs, int v) { return BlockMap{cs.d_start[v], cs.d_ids, cs.n_active, 0}; }
+
 template <int ROWS>
 void launch_half_rows(hipStream_t st, const ChainSet &cs, int v, bool table, int colour, const SweepConsts &sc)
 {
-    const int n = (int)cs.desc.size();
     const dim3 grid((unsigned)cs.total_blocks[v]);
     if (table)
         hipLaunchKernelGGL(table_half_sweep_kernel<ROWS>, grid, dim3(kBlock), 0, st, cs.d_desc, cs.d_state,
-                           cs.d_start[v], n, colour, sc, cs.redo);
+                           block_map(cs, v), colour, sc, cs.redo);
     else
         hipLaunchKernelGGL((half_sweep_kernel<false, ROWS>), grid, dim3(kBlock), 0, st, cs.d_desc, cs.d_state,
-                           cs.d_start[v], n, colour, sc, 0, cs.redo, nullptr);
+                           block_map(cs, v), colour, sc, 0, cs.redo, nullptr);
 }
 
 template <int CR>
 void launch_half_compact(hipStream_t st, const ChainSet &cs, int v, int colour, const SweepConsts &sc)
 {
-    const int n = (int)cs.desc.size();
     hipLaunchKernelGGL((half_sweep_compact_kernel<false, CR>), dim3((unsigned)cs.total_blocks[v]), dim3(kBlock), 0,
-                       st, cs.d_desc, cs.d_state, cs.d_start[v], n, colour, sc, 0, cs.redo, nullptr);
+                       st, cs.d_desc, cs.d_state, block_map(cs, v), colour, sc, 0, cs.redo, nullptr);
 }
 
 // The deferred double-precision updates after a half-sweep in shape v.
@@ -1440,7 +1469,7 @@ void launch_redo(hipStream_t st, const ChainSet &cs, int v, int colour, const Sw
     const int64_t nw = (cs.total_blocks[v] + 31) / 32;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 3) / 4, 4096));
     hipLaunchKernelGGL((redo_fp64_kernel<DIAG>), dim3(grid), dim3(kBlock), 0, st, cs.d_desc, cs.d_state,
-                       cs.d_start[v], (int)cs.desc.size(), cs.total_blocks[v], kShapes[v].rows,
+                       block_map(cs, v), cs.total_blocks[v], kShapes[v].rows,
                        kShapes[v].compact ? 1 : 0, colour, sc, or_only, cs.redo, flags);
 }
 
@@ -1449,7 +1478,7 @@ void launch_half_fp64_rows(hipStream_t st, const ChainSet &cs, int v, int colour
                            uint8_t *flags)
 {
     hipLaunchKernelGGL((half_sweep_fp64_kernel<DIAG, ROWS>), dim3((unsigned)cs.total_blocks[v]), dim3(kBlock), 0, st,
-                       cs.d_desc, cs.d_state, cs.d_start[v], (int)cs.desc.size(), colour, sc, or_only, flags);
+                       cs.d_desc, cs.d_state, block_map(cs, v), colour, sc, or_only, flags);
 }
 
 // One half-sweep of double-precision chains in plain shape v.
@@ -1489,6 +1518,30 @@ void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colo
         }
     }
     launch_redo<false>(st, cs, v, colour, sc, 0, nullptr);
+}
+
+// Builds the launch list of a chain set from the chains in `active`: block
+// prefix sums for every shape and the chain ids, uploaded on `stream` (and
+// waited for, so that the host copies can be reused).
+int set_active(mpr_ctx *ctx, ChainSet &cs, const std::vector<int32_t> &active, hipStream_t stream)
+{
+    const int n = (int)cs.desc.size();
+    const int na = (int)active.size();
+    cs.h_start.assign((size_t)kNumShapes * (n + 1), 0);
+    for (int k = 0; k < kNumShapes; ++k) {
+        int64_t *sk = cs.h_start.data() + (size_t)k * (n + 1);
+        for (int j = 0; j < na; ++j) sk[j + 1] = sk[j] + chain_blocks(cs.desc[active[j]], k);
+        cs.total_blocks[k] = sk[na];
+        if (sk[na] >= ((int64_t)1 << 31)) return fail(ctx, MPR_ERR_ARG, "batch too large for one launch");
+    }
+    cs.h_ids = active;
+    cs.n_active = na;
+    HIP_TRY(ctx, hipMemcpyAsync(cs.d_start[0], cs.h_start.data(), cs.h_start.size() * 8, hipMemcpyHostToDevice,
+                                stream));
+    if (na > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(cs.d_ids, cs.h_ids.data(), (size_t)na * 4, hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    return MPR_OK;
 }
 
 // Runs sweeps until every chain is done.  Returns 0 or an error code.
@@ -1587,17 +1640,52 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
         spl = std::min(64, poll_every * (int)std::ceil(1.0f / ((float)poll_every * sweep_ms)));
     hipGraph_t graph = nullptr;
     hipGraphExec_t ge = nullptr;
-    if (!finished && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        sweeps(v, spl);
-        if (hipStreamEndCapture(st, &graph) != hipSuccess ||
-            hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0) != hipSuccess)
-            ge = nullptr;
-    }
-    (void)hipGetLastError();
+    auto capture = [&]() {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (graph) (void)hipGraphDestroy(graph);
+        ge = nullptr;
+        graph = nullptr;
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            sweeps(v, spl);
+            if (hipStreamEndCapture(st, &graph) != hipSuccess ||
+                hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0) != hipSuccess)
+                ge = nullptr;
+        }
+        (void)hipGetLastError();
+    };
+    if (!finished) capture();
+    // Chains stop at different sweeps.  When at least an eighth of the
+    // listed chains have finished, the launch list is rebuilt from the
+    // chains still running if that drops a fifth or more of the blocks a
+    // launch covers (the blocks of finished chains return at once, but
+    // still have to be dispatched).
+    unsigned int done_listed = already;
+    std::vector<uint8_t> done_flag(n);
+    uint8_t *d_flags = (uint8_t *)ctx->scratch + kVarOffset;
+    const bool can_shrink = (int64_t)n <= (int64_t)kScratchBytes - kVarOffset;
     int rc = MPR_OK;
     while (!finished && done_sweeps < max_sweeps) {
         rc = block(v, spl, ge, nullptr);
         if (rc) break;
+        const unsigned int done_now = *ctx->done_host + already;
+        if (finished || !can_shrink || done_now - done_listed < std::max(1u, (unsigned int)cs.n_active / 8u))
+            continue;
+        done_listed = done_now;
+        hipLaunchKernelGGL(done_flags_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, cs.d_state, n,
+                           d_flags);
+        HIP_TRY(ctx, hipMemcpyAsync(done_flag.data(), d_flags, (size_t)n, hipMemcpyDeviceToHost, st));
+        HIP_TRY(ctx, hipStreamSynchronize(st));
+        std::vector<int32_t> active;
+        int64_t blocks = 0;
+        for (int c = 0; c < n; ++c)
+            if (!done_flag[c]) {
+                active.push_back(c);
+                blocks += chain_blocks(cs.desc[c], v);
+            }
+        if (active.empty() || 5 * blocks > 4 * cs.total_blocks[v]) continue;
+        rc = set_active(ctx, cs, active, st);
+        if (rc) break;
+        capture();
     }
     if (ge) (void)hipGraphExecDestroy(ge);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1608,25 +1696,22 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     return MPR_OK;
 }
 
-// Fills the per-shape block prefix sums of a chain set (in the workspace).
+// Carves the launch list and the deferred-redo buffers (sized for every
+// chain) of a chain set from the workspace and fills the list with the
+// chains that are not done.
 int upload_starts(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream)
 {
     const int n = (int)cs.desc.size();
-    std::vector<int64_t> h((size_t)kNumShapes * (n + 1));
-    for (int k = 0; k < kNumShapes; ++k) {
-        int64_t *sk = h.data() + (size_t)k * (n + 1);
-        sk[0] = 0;
-        for (int c = 0; c < n; ++c) sk[c + 1] = sk[c] + chain_blocks(cs.desc[c], k);
-        cs.total_blocks[k] = sk[n];
-        if (sk[n] >= ((int64_t)1 << 31)) return fail(ctx, MPR_ERR_ARG, "batch too large for one launch");
-    }
-    int64_t *d = (int64_t *)cv.take((int64_t)h.size() * 8);
-    if (!d) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+    int64_t *d = (int64_t *)cv.take((int64_t)kNumShapes * (n + 1) * 8);
+    cs.d_ids = (int32_t *)cv.take((int64_t)n * 4 + 4);
+    if (!d || !cs.d_ids) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
     for (int k = 0; k < kNumShapes; ++k) cs.d_start[k] = d + (size_t)k * (n + 1);
     int64_t words = 0, blocks = 0;
     for (int k = 0; k < kNumShapes; ++k) {
-        words = std::max(words, cs.total_blocks[k] * redo_words(k));
-        blocks = std::max(blocks, cs.total_blocks[k]);
+        int64_t b = 0;
+        for (int c = 0; c < n; ++c) b += chain_blocks(cs.desc[c], k);
+        words = std::max(words, b * redo_words(k));
+        blocks = std::max(blocks, b);
     }
     const int64_t mask_bytes = words * 4, bits_bytes = (blocks + 31) / 32 * 4;
     cs.redo.mask = (uint32_t *)cv.take(mask_bytes);
@@ -1634,9 +1719,10 @@ int upload_starts(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream)
     if (!cs.redo.mask || !cs.redo.blocks) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
     HIP_TRY(ctx, hipMemsetAsync(cs.redo.mask, 0, mask_bytes, stream));
     HIP_TRY(ctx, hipMemsetAsync(cs.redo.blocks, 0, bits_bytes, stream));
-    HIP_TRY(ctx, hipMemcpyAsync(d, h.data(), h.size() * 8, hipMemcpyHostToDevice, stream));
-    HIP_TRY(ctx, hipStreamSynchronize(stream));
-    return MPR_OK;
+    std::vector<int32_t> active;
+    for (int c = 0; c < n; ++c)
+        if (cs.state[c].phase != PH_DONE) active.push_back(c);
+    return set_active(ctx, cs, active, stream);
 }
 
 ChainState fresh_state(double T, int phase)
@@ -1919,17 +2005,45 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
             e_s[b] = s / (double)c;
         }
     }
-    // e(T, L) tables per grid size (equation ene), cached
+    // e(T, L) tables per grid size (equation ene), cached.  The missing ones
+    // are built together: the table chains of as many grid sizes as the
+    // workspace holds run as one ragged chain set (a table does not depend on
+    // the chains run beside it: its random numbers are keyed by temperature
+    // index and site).
     const std::vector<double> Tg = temperature_grid(p);
+    auto key_of = [&](int b) {
+        return std::make_tuple(imgs[b].nx, imgs[b].ny, p->q, p->table_nT, p->table_T_lo, p->table_T_hi,
+                               p->table_burn, p->table_meas, p->a_targ, p->k_a, p->seed);
+    };
+    std::vector<int> missing;  // first image of each grid size without a table
     for (int b = 0; b < n; ++b) {
-        const auto key = std::make_tuple(imgs[b].nx, imgs[b].ny, p->q, p->table_nT, p->table_T_lo, p->table_T_hi,
-                                         p->table_burn, p->table_meas, p->a_targ, p->k_a, p->seed);
-        auto it = ctx->tables.find(key);
-        if (it == ctx->tables.end()) {
-            if ((int64_t)imgs[b].nx * imgs[b].ny < 2) return fail(ctx, MPR_ERR_DEGENERATE, "image %d: one site", b);
-            Carver cv{(char *)ws, ws_bytes};
-            ChainSet cs;
-            for (int k = 0; k < p->table_nT; ++k) {
+        if (ctx->tables.count(key_of(b))) continue;
+        if ((int64_t)imgs[b].nx * imgs[b].ny < 2) return fail(ctx, MPR_ERR_DEGENERATE, "image %d: one site", b);
+        bool dup = false;
+        for (int m : missing) dup = dup || (imgs[m].nx == imgs[b].nx && imgs[m].ny == imgs[b].ny);
+        if (!dup) missing.push_back(b);
+    }
+    const int nT = p->table_nT;
+    // workspace of one grid size's table chains (grids, descriptors, block
+    // offsets and redo buffers), as upload_chains carves them
+    auto table_chain_bytes = [&](int b) {
+        const int64_t hg = round_up(half_grid_bytes(imgs[b].nx, imgs[b].ny), 256);
+        return nT * 2 * hg + redo_bytes(imgs[b].nx, imgs[b].ny, nT) +
+               nT * (int64_t)(sizeof(ChainDesc) + sizeof(ChainState) + 8 + (kNumShapes + 1) * 8) + 4096;
+    };
+    for (size_t first = 0; first < missing.size();) {
+        // as many grid sizes as fit (at least one: the workspace holds the largest)
+        size_t last = first;
+        int64_t need = 65536 + table_chain_bytes(missing[first]);
+        while (last + 1 < missing.size() && need + table_chain_bytes(missing[last + 1]) <= ws_bytes)
+            need += table_chain_bytes(missing[++last]);
+        Carver cv{(char *)ws, ws_bytes};
+        ChainSet cs;
+        int64_t maxn = 0;
+        for (size_t g = first; g <= last; ++g) {
+            const int b = missing[g];
+            maxn = std::max(maxn, (int64_t)imgs[b].nx * imgs[b].ny);
+            for (int k = 0; k < nT; ++k) {
                 ChainDesc d;
                 std::memset(&d, 0, sizeof d);
                 if (!carve_chain(cv, d, imgs[b].nx, imgs[b].ny, false))
@@ -1942,23 +2056,27 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
                 cs.state.push_back(fresh_state(Tg[k], PH_TABLE));
                 cs.offset.push_back(0);
             }
-            int rc = upload_chains(ctx, cs, cv, stream, p->q);
-            if (rc) return rc;
-            const int64_t maxn = (int64_t)imgs[b].nx * imgs[b].ny;
-            hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), p->table_nT), dim3(kBlock), 0, stream,
-                               cs.d_desc, cs.d_offset, nullptr, nullptr, nullptr, 0u, 0u, 1, 0);
-            HIP_TRY(ctx, hipGetLastError());
-            rc = run_chains(ctx, cs, p, stream, (int64_t)p->table_burn + p->table_meas, 50, true);
-            if (rc) return rc;
-            HIP_TRY(ctx, hipMemcpyAsync(cs.state.data(), cs.d_state, cs.state.size() * sizeof(ChainState),
-                                        hipMemcpyDeviceToHost, stream));
-            HIP_TRY(ctx, hipStreamSynchronize(stream));
-            std::vector<double> ope(p->table_nT);
-            for (int k = 0; k < p->table_nT; ++k) ope[k] = cs.state[k].e_sum / (double)p->table_meas;
-            it = ctx->tables.emplace(key, ope).first;
         }
+        int rc = upload_chains(ctx, cs, cv, stream, p->q);
+        if (rc) return rc;
+        hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), (unsigned)cs.desc.size()), dim3(kBlock),
+                           0, stream, cs.d_desc, cs.d_offset, nullptr, nullptr, nullptr, 0u, 0u, 1, 0);
+        HIP_TRY(ctx, hipGetLastError());
+        rc = run_chains(ctx, cs, p, stream, (int64_t)p->table_burn + p->table_meas, 50, true);
+        if (rc) return rc;
+        HIP_TRY(ctx, hipMemcpyAsync(cs.state.data(), cs.d_state, cs.state.size() * sizeof(ChainState),
+                                    hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        for (size_t g = first; g <= last; ++g) {
+            std::vector<double> ope(nT);
+            for (int k = 0; k < nT; ++k) ope[k] = cs.state[(g - first) * nT + k].e_sum / (double)p->table_meas;
+            ctx->tables.emplace(key_of(missing[g]), ope);
+        }
+        first = last + 1;
+    }
+    for (int b = 0; b < n; ++b) {
         int cl = 0;
-        T_hat[b] = invert_table(Tg, it->second, e_s[b], &cl);
+        T_hat[b] = invert_table(Tg, ctx->tables.at(key_of(b)), e_s[b], &cl);
         if (t_clamped) t_clamped[b] = cl;
     }
     return MPR_OK;
@@ -2225,26 +2343,26 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
     if (sh.compact) {
         if (sh.rows == 2)
             hipLaunchKernelGGL((half_sweep_compact_kernel<true, 2>), grid, dim3(kBlock), 0, stream, cs.d_desc,
-                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, rd, flags);
+                               cs.d_state, block_map(cs, v), colour, sc, mode, rd, flags);
         else if (sh.rows == 4)
             hipLaunchKernelGGL((half_sweep_compact_kernel<true, 4>), grid, dim3(kBlock), 0, stream, cs.d_desc,
-                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, rd, flags);
+                               cs.d_state, block_map(cs, v), colour, sc, mode, rd, flags);
         else
             hipLaunchKernelGGL((half_sweep_compact_kernel<true, 8>), grid, dim3(kBlock), 0, stream, cs.d_desc,
-                               cs.d_state, cs.d_start[v], 1, colour, sc, mode, rd, flags);
+                               cs.d_state, block_map(cs, v), colour, sc, mode, rd, flags);
     } else {
         if (sh.rows == 1)
             hipLaunchKernelGGL((half_sweep_kernel<true, 1>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
-                               cs.d_start[v], 1, colour, sc, mode, rd, flags);
+                               block_map(cs, v), colour, sc, mode, rd, flags);
         else if (sh.rows == 2)
             hipLaunchKernelGGL((half_sweep_kernel<true, 2>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
-                               cs.d_start[v], 1, colour, sc, mode, rd, flags);
+                               block_map(cs, v), colour, sc, mode, rd, flags);
         else if (sh.rows == 4)
             hipLaunchKernelGGL((half_sweep_kernel<true, 4>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
-                               cs.d_start[v], 1, colour, sc, mode, rd, flags);
+                               block_map(cs, v), colour, sc, mode, rd, flags);
         else
             hipLaunchKernelGGL((half_sweep_kernel<true, 8>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
-                               cs.d_start[v], 1, colour, sc, mode, rd, flags);
+                               block_map(cs, v), colour, sc, mode, rd, flags);
     }
     launch_redo<true>(stream, cs, v, colour, sc, mode, flags);
     hipLaunchKernelGGL(unsplit_kernel, dim3(blocks_for(nsite, 2048)), dim3(kBlock), 0, stream, cs.d_desc, phi);

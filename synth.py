@@ -147,24 +147,43 @@ def workload_table2(n: int, p_removed: float, rep: int) -> Image:
     return Image(z, random_mask(n, n, p_removed, 6000 + rep), f"t2_l{n}_{rep}")
 
 
+def _ragged_image(spec: tuple) -> Image:
+    nx, ny, nu, kappa, p, seed, i = spec
+    z = matern_field(nx, ny, nu, kappa, 50.0, 10.0, seed * 1000 + i)
+    m = random_mask(nx, ny, p, seed * 1000 + 500 + i)
+    return Image(z, m, f"ragged_{i}_{nx}x{ny}")
+
+
 def ragged_batch(n_images: int = 256, lo: int = 128, hi: int = 2048,
-                 seed: int = 1003) -> list[Image]:
+                 seed: int = 1003, workers: int = 1) -> list[Image]:
     """Images of uneven size: sides log-uniform integers in [lo, hi].
 
     nu from {0.5, 1.5, 2.5}, kappa log-uniform in [0.01, 0.3], mean 50,
-    std 10, removal fraction uniform in [0.2, 0.8], random masks.
+    std 10, removal fraction uniform in [0.2, 0.8], random masks.  With
+    workers > 1 the images are made in that many fresh processes (the
+    result does not depend on it).
     """
     rng = np.random.default_rng(seed)
-    out = []
+    specs = []
     for i in range(n_images):
         nx = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
         ny = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
         nu = float(rng.choice([0.5, 1.5, 2.5]))
         kappa = float(math.exp(rng.uniform(math.log(0.01), math.log(0.3))))
         p = float(rng.uniform(0.2, 0.8))
-        z = matern_field(nx, ny, nu, kappa, 50.0, 10.0, seed * 1000 + i)
-        m = random_mask(nx, ny, p, seed * 1000 + 500 + i)
-        out.append(Image(z, m, f"ragged_{i}_{nx}x{ny}"))
+        specs.append((nx, ny, nu, kappa, p, seed, i))
+    if workers <= 1:
+        return [_ragged_image(sp) for sp in specs]
+    import concurrent.futures
+    import multiprocessing
+    # largest first, so that the pool's tail is short
+    order = sorted(range(n_images), key=lambda k: -specs[k][0] * specs[k][1])
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers,
+                                                mp_context=multiprocessing.get_context("spawn")) as ex:
+        made = list(ex.map(_ragged_image, [specs[k] for k in order]))
+    out = [None] * n_images
+    for k, im in zip(order, made):
+        out[k] = im
     return out
 
 

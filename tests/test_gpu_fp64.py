@@ -2,7 +2,8 @@
 FP64 oracle.
 
 Both sides compute in double, so the bars are far tighter than for the
-single-precision sweep: teacher-forced half-sweeps take the same decisions
+single-precision sweep (the oracle sees only inputs made here or by itself;
+chains of half-sweeps continue from the oracle's state): teacher-forced half-sweeps take the same decisions
 at every site and agree in angle to rounding; free-running chains track the
 oracle's site by site through relaxation and the equilibrium states; the
 stopping rule stops at the same sweep.  The GPU's energy sums are fixed
@@ -90,7 +91,7 @@ def test_fp64_over_relaxation_only(ctx, kind, shape):
             assert np.max(np.abs(pg[sel] - po[sel])) <= 1e-11
         fixed = m == 1
         assert np.array_equal(pg[fixed], phi[fixed])
-        phi = pg
+        phi = po
 
 
 @pytest.mark.parametrize("T", [2.6e-4, 1.0e-3, 0.1])
@@ -118,7 +119,7 @@ def test_fp64_decisions_teacher_forced(ctx, T):
                 if colour == 1:
                     e_o = oracle.energy(po) + ngp
                     assert abs(e_g - e_o) <= n1 * 2.0 ** -31 + 1e-9 * ngp, (e_g, e_o)
-                phi = pg
+                phi = po
             step += 1
     say(f"  decisions {n_dec}, all equal; max |dphi| {max_err:.2e}")
     assert max_err <= 1e-11
@@ -136,7 +137,7 @@ def test_fp64_degenerate_and_tiny_grids(ctx, shape):
         assert np.array_equal(fg[sel] & 15, fo[sel] & 15)
         assert acc_g == acc_o
         assert np.max(np.abs(pg - po)) <= 1e-11
-        phi = pg
+        phi = po
 
 
 @pytest.mark.parametrize("p_removed", [0.0, 0.5, 1.0])
