@@ -80,11 +80,13 @@ def _declare(L):
     L.oracle_half_sweep.restype = i64
     L.oracle_sg_slope.argtypes = [P, i32, i32]
     L.oracle_sg_slope.restype = d
-    L.oracle_simulate.argtypes = [i32, i32, P, P, d, C.POINTER(Params), P, P, P,
+    L.oracle_simulate.argtypes = [i32, i32, P, P, d, C.POINTER(Params), P, P, P, P,
                                   C.POINTER(ChainStats), P, i32, P]
     L.oracle_simulate.restype = i32
     L.oracle_predict.argtypes = [i32, i32, P, P, P, i32, P, P]
     L.oracle_spread.argtypes = [i32, i32, P, P, P, i32, P, P]
+    L.oracle_quantiles.argtypes = [i32, i32, P, P, P, i32, P, i32, P, P]
+    L.oracle_quantiles.restype = i32
     L.oracle_energy_table.argtypes = [i32, i32, d, i32, P, i32, i32, d, d, u64, u32, P]
     L.oracle_energy_table.restype = i32
     L.oracle_temperature_grid.argtypes = [i32, d, d, P]
@@ -181,29 +183,36 @@ def sg_slope(e, degree=1) -> float:
     return lib().oracle_sg_slope(_p(e), e.size, degree)
 
 
-def simulate(phi, sampled, T, params: Params, phi_init=None, trace_len=0, want_last=False, want_sq=False):
-    """Returns (phi_sum, stats, e_trace, phi_last), plus phi_sq_sum (sum of
-    the squared states at gap sites) when want_sq."""
+def simulate(phi, sampled, T, params: Params, phi_init=None, trace_len=0, want_last=False, want_sq=False,
+             want_states=False):
+    """Returns (phi_sum, stats, e_trace, phi_last), then phi_sq_sum (sum of
+    the squared states at gap sites) when want_sq, then the M = R K states
+    (array M x ny x nx, state r K + k) when want_states."""
     phi, s = _f64(phi), _u8(sampled)
     ny, nx = phi.shape
     phi_sum = np.zeros_like(phi)
     phi_sq = np.zeros_like(phi) if want_sq else None
+    states = np.zeros((params.R * params.K,) + phi.shape) if want_states else None
     stats = (ChainStats * params.R)()
     trace = np.zeros((params.R, trace_len)) if trace_len else None
     last = np.zeros_like(phi) if want_last else None
     init = _f64(phi_init) if phi_init is not None else None
     rc = lib().oracle_simulate(nx, ny, _p(phi), _p(s), T, C.byref(params),
                                _p(init) if init is not None else None, _p(phi_sum),
-                               _p(phi_sq) if phi_sq is not None else None, stats,
+                               _p(phi_sq) if phi_sq is not None else None,
+                               _p(states) if states is not None else None, stats,
                                _p(trace) if trace is not None else None, trace_len,
                                _p(last) if last is not None else None)
     if rc:
         raise OracleError(rc, "simulate")
     st = [dict(relax_sweeps=c.relax_sweeps, not_converged=c.not_converged, a_final=c.a_final,
                A_last=c.A_last, k_last=c.k_last) for c in stats]
+    out = (phi_sum, st, trace, last)
     if want_sq:
-        return phi_sum, st, trace, last, phi_sq
-    return phi_sum, st, trace, last
+        out += (phi_sq,)
+    if want_states:
+        out += (states,)
+    return out
 
 
 def spread(sampled, phi_sum, phi_sq_sum, M, zmin_zmax):
@@ -214,6 +223,21 @@ def spread(sampled, phi_sum, phi_sq_sum, M, zmin_zmax):
     zz = _f64(zmin_zmax)
     out = np.zeros_like(ps)
     lib().oracle_spread(nx, ny, _p(s), _p(ps), _p(pq), M, _p(zz), _p(out))
+    return out
+
+
+def quantiles(z, sampled, states, probs, zmin_zmax):
+    """Per-site quantiles (probs) of the back-transformed states (M x ny x nx);
+    data values at sampled sites.  Returns an array len(probs) x ny x nx."""
+    z, s = _f64(z), _u8(sampled)
+    st = _f64(states)
+    pr = _f64(probs)
+    ny, nx = z.shape
+    out = np.zeros((pr.size, ny, nx))
+    zz = _f64(zmin_zmax)
+    rc = lib().oracle_quantiles(nx, ny, _p(z), _p(s), _p(st), st.shape[0], _p(pr), pr.size, _p(zz), _p(out))
+    if rc:
+        raise OracleError(rc, "quantiles")
     return out
 
 

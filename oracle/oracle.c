@@ -32,9 +32,11 @@
  *  - e(T, L) comes from unconditional runs started from phi = pi, with the
  *    relaxation-phase rule for a, averaged over the measured sweeps; the
  *    temperature is read off a monotone fit of log(1 + e) against log T.
- *  - Besides the mean, the statistic of the M realizations reported is
+ *  - Besides the mean, the statistics of the M realizations reported are
  *    their sample standard deviation (denominator M - 1) after the back
- *    transform, which is linear in phi.
+ *    transform, which is linear in phi, and their quantiles: linear
+ *    interpolation between order statistics (Hyndman and Fan's definition
+ *    7), back-transformed like the mean.
  */
 #include <math.h>
 #include <stdint.h>
@@ -323,11 +325,12 @@ double oracle_sg_slope(const double *e, int n, int degree)
  * phi_sum receives the sum of the M realizations at the gap sites (0 at the
  * samples).  e_trace (nullable, R x trace_len) receives e after each
  * relaxation sweep.  phi_last (nullable) receives the final state of the last
- * chain. */
+ * chain.  phi_states (nullable, M x nx*ny) receives every equilibrium state,
+ * state r*K + k of chain r after its k-th equilibrium sweep. */
 int oracle_simulate(int nx, int ny, const double *phi, const uint8_t *sampled, double T,
                     const oracle_params *p, const double *phi_init, double *phi_sum,
-                    double *phi_sq_sum, oracle_chain_stats *stats, double *e_trace, int trace_len,
-                    double *phi_last)
+                    double *phi_sq_sum, double *phi_states, oracle_chain_stats *stats, double *e_trace,
+                    int trace_len, double *phi_last)
 {
     if (nx <= 0 || ny <= 0 || p->R < 1 || p->K < 0 || !(T > 0.0) || p->n_f < 1 || p->n_fit < 2)
         return O_ERR_ARG;
@@ -400,6 +403,7 @@ int oracle_simulate(int nx, int ny, const double *phi, const uint8_t *sampled, d
                     phi_sum[i] += s[i];
                     if (phi_sq_sum) phi_sq_sum[i] += s[i] * s[i];
                 }
+            if (phi_states) memcpy(phi_states + ((long)r * p->K + j) * n, s, sizeof(double) * n);
         }
         if (phi_last && r == p->R - 1) memcpy(phi_last, s, sizeof(double) * n);
     }
@@ -443,6 +447,52 @@ void oracle_spread(int nx, int ny, const uint8_t *sampled, const double *phi_sum
         }
         z_std[i] = v;
     }
+}
+
+/* The p-quantile of v[0..M-1] (sorted in place): linear interpolation
+ * between the order statistics v_(floor h) and v_(floor h + 1), h = (M - 1) p
+ * (Hyndman and Fan 1996, definition 7). */
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+static double quantile_sorted(const double *v, int M, double p)
+{
+    double h = (double)(M - 1) * p;
+    int lo = (int)floor(h);
+    if (lo >= M - 1) return v[M - 1];
+    return v[lo] + (h - (double)lo) * (v[lo + 1] - v[lo]);
+}
+
+/* Algorithm 2 step 7, quantiles of the M realizations: at each gap site the
+ * p-quantile of the M states of phi (states[m * nx*ny + i]), back-transformed
+ * like the mean, z = z_min (1 - t) + z_max t with t = phi_p / (2 pi) (G^{-1}
+ * is increasing, so this is the p-quantile of the back-transformed states);
+ * sampled sites get their data value.  out[k * nx*ny + i] for probs[k]. */
+int oracle_quantiles(int nx, int ny, const double *z, const uint8_t *sampled, const double *states, int M,
+                     const double *probs, int nq, const double *zmin_zmax, double *out)
+{
+    if (nx <= 0 || ny <= 0 || M < 1 || nq < 1) return O_ERR_ARG;
+    for (int k = 0; k < nq; ++k)
+        if (!(probs[k] >= 0.0 && probs[k] <= 1.0)) return O_ERR_ARG;
+    long n = (long)nx * ny;
+    double *v = (double *)malloc(sizeof(double) * M);
+    for (long i = 0; i < n; ++i) {
+        if (sampled[i]) {
+            for (int k = 0; k < nq; ++k) out[k * n + i] = z[i];
+            continue;
+        }
+        for (int m = 0; m < M; ++m) v[m] = states[(long)m * n + i];
+        qsort(v, (size_t)M, sizeof(double), cmp_double);
+        for (int k = 0; k < nq; ++k) {
+            double t = quantile_sorted(v, M, probs[k]) / O_TWO_PI;
+            out[k * n + i] = zmin_zmax[0] * (1.0 - t) + zmin_zmax[1] * t;
+        }
+    }
+    free(v);
+    return O_OK;
 }
 
 /* ---------------------------------------------------------- temperature */

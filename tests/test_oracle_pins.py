@@ -479,3 +479,40 @@ def test_reproduces_paper_table2_validation_measures():
         for k in ("MAAE", "MAARE", "MRASE"):
             assert abs(np.mean(acc[k]) / g[k] - 1.0) < 0.04, (key, k, np.mean(acc[k]), g[k])
         assert abs(np.mean(acc["MARE"]) - g["MARE"]) < 0.3, (key, np.mean(acc["MARE"]), g["MARE"])
+
+
+def test_recorded_states_and_quantiles():
+    """Quantiles of the M realizations (Algorithm 2 step 7): the oracle's
+    per-site quantiles equal numpy's linear-interpolation quantiles of the
+    back-transformed recorded states; the recorded states sum to the
+    simulation's own sums; p = 0 and 1 give the extremes, an odd M's median
+    is a state; sampled sites get their data value."""
+    rng = np.random.default_rng(23)
+    ny, nx = 10, 12
+    z = synth.matern_field(nx, ny, 1.5, 0.2, 50.0, 10.0, 3)
+    m = (rng.random((ny, nx)) < 0.6).astype(np.uint8)
+    phi, zz = oracle.map_to_angles(z, m)
+    p = oracle.default_params(R=3, K=5, fixed_relax=4, seed=8)
+    ps, _, _, _, pq, states = oracle.simulate(phi, m, 0.2, p, want_sq=True, want_states=True)
+    M = p.R * p.K
+    g = m == 0
+    assert states.shape == (M, ny, nx)
+    assert np.allclose(states.sum(0)[g], ps[g], rtol=1e-13, atol=0)
+    assert np.allclose((states ** 2).sum(0)[g], pq[g], rtol=1e-13, atol=0)
+    # the last chain's states differ from sweep to sweep (they are states, not copies)
+    assert np.max(np.abs(states[-1] - states[-2])[g]) > 1e-3
+    probs = np.array([0.0, 0.05, 0.25, 0.5, 0.75, 0.95, 1.0])
+    q = oracle.quantiles(z, m, states, probs, zz)
+    zs = zz[0] * (1 - states / TWO_PI) + zz[1] * (states / TWO_PI)
+    want = np.quantile(zs, probs, axis=0, method="linear")
+    assert np.allclose(q[:, g], want[:, g], rtol=0, atol=1e-10)
+    assert np.all(q[:, ~g] == z[~g])
+    assert np.all(np.diff(q[:, g], axis=0) >= -1e-12)
+    assert np.allclose(q[0][g], zs.min(0)[g], atol=1e-10) and np.allclose(q[-1][g], zs.max(0)[g], atol=1e-10)
+    # odd M: the median is the middle order statistic itself
+    med = oracle.quantiles(z, m, states, [0.5], zz)[0]
+    assert np.allclose(med[g], np.sort(zs, axis=0)[M // 2][g], atol=1e-10)
+    one = oracle.quantiles(z, m, states[:1], probs, zz)
+    assert np.allclose(one[:, g], zs[0][g][None, :], atol=1e-10)
+    with pytest.raises(oracle.OracleError):
+        oracle.quantiles(z, m, states, [1.5], zz)
