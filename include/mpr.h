@@ -182,6 +182,11 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_
  *           needs p->spread = 1 (each chain keeps a running sum of squared
  *           deviations, Welford's update); chains are combined with the
  *           spread of their means.
+ *   phi_states (dev, float, out, nullable)  every equilibrium state: state
+ *           m = r*K + k (chain r after its k-th equilibrium sweep) of the site at
+ *           packed position j is phi_states[m * N + j], N = max over images of
+ *           offset + nx*ny (all sites of the image, samples included); M*N floats.
+ *           Adds a pass over each chain's grid per equilibrium sweep.
  *   stats (host, mpr_chain_stats[n_images * R], out, nullable)
  * An image without gaps is left unchanged (phi_sum 0).
  * Errors: MPR_ERR_WORKSPACE if ws_bytes is too small; MPR_ERR_ARG for phi_m2
@@ -189,8 +194,8 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_
 int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
                      const float *phi, const uint8_t *sampled, const double *T_hat,
                      const mpr_params *p, const float *phi_init, void *workspace,
-                     int64_t ws_bytes, float *phi_sum, float *phi_m2, mpr_chain_stats *stats,
-                     void *stream);
+                     int64_t ws_bytes, float *phi_sum, float *phi_m2, float *phi_states,
+                     mpr_chain_stats *stats, void *stream);
 
 /* Algorithm 2 steps 6.3 and 7 with the mean as the statistic:
  * z_hat = z_min (1 - t) + z_max t with t = (phi_sum / M) / (2 pi) at gaps
@@ -199,6 +204,21 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
 int32_t mpr_predict(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
                     const float *z, const uint8_t *sampled, const float *phi_sum,
                     const double *zmin_zmax, int32_t M, float *z_hat, void *stream);
+
+/* Quantiles of the prediction (Algorithm 2 step 7, statistics of the M
+ * realizations): at each gap site the probs[k]-quantile of the M states of
+ * phi_states (as written by mpr_simulate; M <= 256), by linear interpolation
+ * between the order statistics around h = (M - 1) p (Hyndman and Fan's
+ * definition 7), back-transformed like the mean, z = z_min (1 - t) + z_max t
+ * with t = phi_p / (2 pi) (double precision, rounded once); sampled sites get
+ * their data value z.  z_q[k * N + j] (N as for phi_states) for 1 <= nq <= 64
+ * probabilities in [0, 1].
+ *   z, sampled, phi_states, z_q (out): dev; probs, zmin_zmax: host.
+ * Errors: MPR_ERR_ARG for M or nq out of range or p outside [0, 1]. */
+int32_t mpr_quantiles(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images, const float *z,
+                      const uint8_t *sampled, const float *phi_states, int32_t M,
+                      const double *probs, int32_t nq, const double *zmin_zmax, float *z_q,
+                      void *stream);
 
 /* Spread of the prediction (Algorithm 2 step 7, statistics of the M
  * realizations besides their mean): z_std = standard deviation over the M

@@ -23,6 +23,7 @@ FLAG_KEPT, FLAG_ACCEPTED, FLAG_WRAPPED, FLAG_UPDATED, FLAG_FP64 = 1, 2, 4, 8, 16
 EXPORTS = [
     "mpr_create", "mpr_destroy", "mpr_last_error", "mpr_default_params", "mpr_workspace_size",
     "mpr_map_to_angles", "mpr_estimate_temperature", "mpr_simulate", "mpr_predict", "mpr_spread",
+    "mpr_quantiles",
     "mpr_profile_enable", "mpr_profile_read",
     "mpr_cnn_param_count", "mpr_cnn_packed_bytes", "mpr_cnn_workspace_size", "mpr_cnn_pack", "mpr_cnn_encode",
     "mpr_cnn_forward", "mpr_cnn_loss", "mpr_cnn_backward", "mpr_cnn_opt_step", "mpr_cnn_decode",
@@ -113,7 +114,8 @@ def _declare(L):
         "mpr_workspace_size": (i64, [IMG, i32, PRM]),
         "mpr_map_to_angles": (i32, [P, IMG, i32, P, P, P, P, P]),
         "mpr_estimate_temperature": (i32, [P, IMG, i32, P, P, PRM, P, i64, P, P, P, P]),
-        "mpr_simulate": (i32, [P, IMG, i32, P, P, P, PRM, P, P, i64, P, P, C.POINTER(ChainStats), P]),
+        "mpr_simulate": (i32, [P, IMG, i32, P, P, P, PRM, P, P, i64, P, P, P, C.POINTER(ChainStats), P]),
+        "mpr_quantiles": (i32, [P, IMG, i32, P, P, P, i32, P, i32, P, P, P]),
         "mpr_predict": (i32, [P, IMG, i32, P, P, P, P, i32, P, P]),
         "mpr_spread": (i32, [P, IMG, i32, P, P, P, i32, P, P]),
         "mpr_cnn_param_count": (i64, []),
@@ -226,13 +228,15 @@ class Context:
             _stream(stream)))
         return e_s, T, cl
 
-    def simulate(self, imgs, phi, sampled, T_hat, params, ws, phi_sum, phi_init=None, stream=None, phi_m2=None):
+    def simulate(self, imgs, phi, sampled, T_hat, params, ws, phi_sum, phi_init=None, stream=None, phi_m2=None,
+                 phi_states=None):
         n = len(imgs)
         T = np.ascontiguousarray(T_hat, dtype=np.float64)
         st = (ChainStats * (n * params.R))()
         self._check(self.lib.mpr_simulate(
             self._h, imgs, n, _ptr(phi), _ptr(sampled), T.ctypes.data_as(C.c_void_p), C.byref(params),
-            _ptr(phi_init), _ptr(ws), ws.numel() * ws.element_size(), _ptr(phi_sum), _ptr(phi_m2), st,
+            _ptr(phi_init), _ptr(ws), ws.numel() * ws.element_size(), _ptr(phi_sum), _ptr(phi_m2),
+            _ptr(phi_states), st,
             _stream(stream)))
         return [dict(relax_sweeps=s.relax_sweeps, not_converged=s.not_converged, a_final=s.a_final,
                      A_last=s.A_last, k_last=s.k_last) for s in st]
@@ -241,6 +245,15 @@ class Context:
         zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)
         self._check(self.lib.mpr_predict(self._h, imgs, len(imgs), _ptr(z), _ptr(sampled), _ptr(phi_sum),
                                          zz.ctypes.data_as(C.c_void_p), M, _ptr(z_hat), _stream(stream)))
+
+    def quantiles(self, imgs, z, sampled, phi_states, M, probs, zmin_zmax, z_q, stream=None):
+        """Per-site quantiles (probs) of the M recorded states, back-transformed;
+        z_q holds len(probs) rows of the packed sites."""
+        pr = np.ascontiguousarray(probs, dtype=np.float64)
+        zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)
+        self._check(self.lib.mpr_quantiles(self._h, imgs, len(imgs), _ptr(z), _ptr(sampled), _ptr(phi_states), M,
+                                           pr.ctypes.data_as(C.c_void_p), pr.size, zz.ctypes.data_as(C.c_void_p),
+                                           _ptr(z_q), _stream(stream)))
 
     def spread(self, imgs, sampled, phi_m2, zmin_zmax, M, z_std, stream=None):
         zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)

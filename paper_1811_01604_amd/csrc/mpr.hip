@@ -46,6 +46,7 @@ constexpr int64_t kEnergyOffset = 2048;  // diag energy accumulator
 constexpr int64_t kSlopeOffset = 4096;   // diag slope input / output
 constexpr int64_t kVarOffset = 65536;    // per-call partials
 constexpr int kCompactSites = 4 * kBlock;  // sites per block of the compacted sweep shapes
+constexpr int kRecordSegs = 32;            // blocks per chain of record_states_kernel
 
 // Sites whose single-precision decision is too close to call are not written
 // by the sweep kernels: they set the site's bit in their block's mask (one
@@ -937,6 +938,89 @@ __global__ void finalize_fp64_kernel(const ChainDesc *__restrict__ descs, const 
     }
 }
 
+// Records the current states of the listed chains that are in their
+// equilibrium phase (after both half-sweeps of an equilibrium sweep, before
+// the control kernel counts it): state r K + k of chain r after its k-th
+// equilibrium sweep goes to out[(r K + k) n_total + offset + i], row-major
+// over the image's sites (samples included).  `segs` blocks per listed chain.
+__global__ void record_states_kernel(const ChainDesc *__restrict__ descs, const ChainState *__restrict__ states,
+                                     const int64_t *__restrict__ offsets, const int32_t *__restrict__ ids,
+                                     int segs, int K, int fp64, int64_t n_total, float *__restrict__ out)
+{
+    const int c = ids[blockIdx.x / segs];
+    const ChainState *stp = states + c;
+    if (stp->phase != PH_EQ) return;
+    const ChainDesc d = descs[c];
+    const int64_t n = (int64_t)d.nx * d.ny;
+    const int64_t m = (int64_t)d.chain * K + (K - stp->eq_left);
+    float *o = out + m * n_total + offsets[c];
+    const int seg = (int)(blockIdx.x % segs);
+    for (int64_t i = (int64_t)seg * blockDim.x + threadIdx.x; i < n; i += (int64_t)segs * blockDim.x) {
+        const int y = (int)(i / d.nx);
+        const int x = (int)(i - (int64_t)y * d.nx);
+        const int64_t j = (int64_t)y * d.S + (x >> 1);
+        const float *hp = ((x + y) & 1) ? d.h[1] : d.h[0];
+        o[i] = fp64 ? (float)fabs(((const double *)hp)[j]) : angle_of(hp[j]);
+    }
+}
+
+// Quantiles of the M realizations at each gap site of image blockIdx.y: the
+// M states (states[m n_total + site]) are sorted in LDS (insertion sort, one
+// wave per block, a lane's values 64 apart so that lanes use distinct banks),
+// the p-quantile interpolates linearly between the order statistics around
+// h = (M - 1) p, and is back-transformed like the mean (double precision,
+// rounded once).  Sampled sites get their data value.
+constexpr int kQuantileLanes = 64;
+constexpr int kMaxQuantileStates = 256;
+
+__global__ __launch_bounds__(kQuantileLanes) void quantile_kernel(const ImgDev *__restrict__ imgs,
+                                                                  const double *__restrict__ zmm,
+                                                                  const double *__restrict__ probs, int nq,
+                                                                  const float *__restrict__ z,
+                                                                  const uint8_t *__restrict__ sampled,
+                                                                  const float *__restrict__ st, int M,
+                                                                  int64_t n_total, float *__restrict__ out)
+{
+#pragma clang fp contract(off)
+    __shared__ float v[kMaxQuantileStates * kQuantileLanes];
+    const ImgDev im = imgs[blockIdx.y];
+    const int64_t n = (int64_t)im.nx * im.ny;
+    const double lo = zmm[2 * blockIdx.y], hi = zmm[2 * blockIdx.y + 1];
+    const int t = threadIdx.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * kQuantileLanes; i0 < n; i0 += (int64_t)gridDim.x * kQuantileLanes) {
+        const int64_t i = i0 + t;
+        if (i >= n) continue;
+        const int64_t k = im.offset + i;
+        if (sampled[k]) {
+            for (int q = 0; q < nq; ++q) out[q * n_total + k] = z[k];
+            continue;
+        }
+        for (int m = 0; m < M; ++m) {
+            // insertion of state m into the sorted prefix
+            const float x = st[(int64_t)m * n_total + k];
+            int j = m - 1;
+            while (j >= 0 && v[j * kQuantileLanes + t] > x) {
+                v[(j + 1) * kQuantileLanes + t] = v[j * kQuantileLanes + t];
+                --j;
+            }
+            v[(j + 1) * kQuantileLanes + t] = x;
+        }
+        for (int q = 0; q < nq; ++q) {
+            const double h = (double)(M - 1) * probs[q];
+            const int a = (int)floor(h);
+            double phi_p;
+            if (a >= M - 1) {
+                phi_p = (double)v[(M - 1) * kQuantileLanes + t];
+            } else {
+                const double va = (double)v[a * kQuantileLanes + t], vb = (double)v[(a + 1) * kQuantileLanes + t];
+                phi_p = va + (h - (double)a) * (vb - va);
+            }
+            const double tt = phi_p / kTwoPi;
+            out[q * n_total + k] = (float)(lo * (1.0 - tt) + hi * tt);
+        }
+    }
+}
+
 // Spread of the prediction: the standard deviation over the M realizations
 // of z = G^{-1}(phi), which is (z_max - z_min) / (2 pi) times that of phi,
 // sqrt(m2 / (M - 1)); zero at sampled sites and for M = 1.
@@ -1437,6 +1521,9 @@ struct ChainSet {
     std::vector<int32_t> h_ids;
     Redo redo = {nullptr, nullptr};      // deferred double-precision updates (zeroed)
     bool fp64 = false;                   // double-precision chains (plain shapes, no deferral)
+    float *states_out = nullptr;         // recorded equilibrium states (nullable)
+    int64_t states_n_total = 0;          // sites of the whole batch (stride of a state)
+    int K = 0;
 };
 
 BlockMap block_map(const ChainSet &cs, int v) { return BlockMap{cs.d_start[v], cs.d_ids, cs.n_active, 0}; }
@@ -1574,6 +1661,10 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
         for (int i = 0; i < count; ++i) {
             launch_half(st, cs, v, table, 0, sc);
             launch_half(st, cs, v, table, 1, sc);
+            if (cs.states_out && cs.n_active > 0)
+                hipLaunchKernelGGL(record_states_kernel, dim3((unsigned)(cs.n_active * kRecordSegs)), dim3(kBlock), 0,
+                                   st, cs.d_desc, cs.d_state, cs.d_offset, cs.d_ids, kRecordSegs, cs.K,
+                                   cs.fp64 ? 1 : 0, cs.states_n_total, cs.states_out);
             hipLaunchKernelGGL(control_kernel, dim3(cblocks), dim3(64), 0, st, cs.d_desc, cs.d_state, n, cp, d_done,
                                d_work);
         }
@@ -2084,7 +2175,7 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
 
 int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *phi, const uint8_t *sampled,
                      const double *T_hat, const mpr_params *p, const float *phi_init, void *ws, int64_t ws_bytes,
-                     float *phi_sum, float *phi_m2, mpr_chain_stats *stats, void *stream_)
+                     float *phi_sum, float *phi_m2, float *phi_states, mpr_chain_stats *stats, void *stream_)
 {
     if (!ctx) return MPR_ERR_ARG;
     if (!valid_images(imgs, n) || !valid_params(p) || !phi || !sampled || !T_hat || !phi_sum)
@@ -2152,6 +2243,12 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
         }
     }
     cs.fp64 = p->fp64 != 0;
+    cs.K = p->K;
+    if (phi_states && p->K > 0) {
+        cs.states_out = phi_states;
+        for (int b = 0; b < n; ++b)
+            cs.states_n_total = std::max(cs.states_n_total, imgs[b].offset + (int64_t)imgs[b].nx * imgs[b].ny);
+    }
     const int eb = cs.fp64 ? 8 : 4;
     int rc = upload_chains(ctx, cs, cv, stream, p->q);
     if (rc) return rc;
@@ -2218,6 +2315,44 @@ int32_t mpr_predict(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float 
                        sampled, phi_sum, z_hat);
     HIP_TRY(ctx, hipGetLastError());
     // the host arrays above must outlive the copies
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    return MPR_OK;
+}
+
+int32_t mpr_quantiles(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *z, const uint8_t *sampled,
+                      const float *phi_states, int32_t M, const double *probs, int32_t nq, const double *zmin_zmax,
+                      float *z_q, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!valid_images(imgs, n) || !z || !sampled || !phi_states || !probs || !zmin_zmax || !z_q || M < 1 ||
+        M > kMaxQuantileStates || nq < 1 || nq > 64)
+        return fail(ctx, MPR_ERR_ARG, "quantiles: invalid argument (1 <= M <= %d, 1 <= nq <= 64)",
+                    kMaxQuantileStates);
+    for (int k = 0; k < nq; ++k)
+        if (!(probs[k] >= 0.0 && probs[k] <= 1.0)) return fail(ctx, MPR_ERR_ARG, "quantiles: p outside [0, 1]");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    const int64_t img_bytes = round_up((int64_t)n * sizeof(ImgDev), 256);
+    const int64_t need = img_bytes + round_up((int64_t)n * 16, 256) + nq * 8;
+    if (need > (int64_t)kScratchBytes - kVarOffset) return fail(ctx, MPR_ERR_ARG, "too many images in one call");
+    char *sp = (char *)ctx->scratch + kVarOffset;
+    ImgDev *d_img = (ImgDev *)sp;
+    double *d_zmm = (double *)(sp + img_bytes);
+    double *d_probs = (double *)(sp + img_bytes + round_up((int64_t)n * 16, 256));
+    std::vector<ImgDev> hi(n);
+    int64_t maxn = 0, n_total = 0;
+    for (int b = 0; b < n; ++b) {
+        hi[b] = {imgs[b].offset, imgs[b].nx, imgs[b].ny};
+        maxn = std::max(maxn, (int64_t)imgs[b].nx * imgs[b].ny);
+        n_total = std::max(n_total, imgs[b].offset + (int64_t)imgs[b].nx * imgs[b].ny);
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(d_img, hi.data(), n * sizeof(ImgDev), hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_zmm, zmin_zmax, n * 16, hipMemcpyHostToDevice, stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_probs, probs, nq * 8, hipMemcpyHostToDevice, stream));
+    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((maxn + kQuantileLanes - 1) / kQuantileLanes, 8192));
+    hipLaunchKernelGGL(quantile_kernel, dim3(gx, n), dim3(kQuantileLanes), 0, stream, d_img, d_zmm, d_probs, nq, z,
+                       sampled, phi_states, M, n_total, z_q);
+    HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipStreamSynchronize(stream));
     return MPR_OK;
 }
