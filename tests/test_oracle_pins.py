@@ -516,3 +516,55 @@ def test_recorded_states_and_quantiles():
     assert np.allclose(one[:, g], zs[0][g][None, :], atol=1e-10)
     with pytest.raises(oracle.OracleError):
         oracle.quantiles(z, m, states, [1.5], zz)
+
+
+# ------------------------------------------------ coupling exponents q < 1/2
+@pytest.mark.parametrize("q", [0.3, 0.125])
+def test_over_relaxation_conserves_energy_and_is_an_involution_for_q(q):
+    """The q-aware reflection keeps the q energy and undoes itself for q < 1/2 too."""
+    rng = np.random.default_rng(41)
+    phi = rng.uniform(0, TWO_PI, size=(18, 22))
+    m = (rng.random(phi.shape) < 0.3).astype(np.uint8)
+    e0 = mpr_energy_numpy(phi, q)
+    p = phi
+    for sweep in range(3):
+        for colour in (0, 1):
+            p, acc, _ = oracle.half_sweep(p, m, colour, 0.1, 1.0, sweep, q=q, mode=oracle.MODE_OR_ONLY)
+    assert abs(mpr_energy_numpy(p, q) - e0) < 1e-12
+    assert np.max(np.abs(p - phi)) > 0.1
+    p1, _, f = oracle.half_sweep(phi, m, 0, 0.1, 1.0, 0, q=q, mode=oracle.MODE_OR_ONLY, with_flags=True)
+    p2, _, _ = oracle.half_sweep(p1, m, 0, 0.1, 1.0, 0, q=q, mode=oracle.MODE_OR_ONLY)
+    assert np.max(np.abs(p2 - phi)) < 1e-12
+    # with q < 1/2 the reflected angle leaves [0, 2 pi) more often: some spins are kept
+    assert ((f & oracle.FLAG_KEPT) != 0).sum() > 0
+
+
+@pytest.mark.parametrize("q,T,a", [(0.3, 0.2, 1.0), (0.2, 0.05, 4.0)])
+def test_single_site_chain_matches_conditional_density_for_q(q, T, a):
+    """A gap site with 4 fixed neighbours samples exp(sum_j cos(q (phi - phi_j)) / T)."""
+    rng = np.random.default_rng(9)
+    phi = rng.uniform(0.3, TWO_PI - 0.3, size=(3, 3))
+    m = np.ones((3, 3), np.uint8)
+    m[1, 1] = 0
+    nbrs = [phi[1, 0], phi[1, 2], phi[0, 1], phi[2, 1]]
+    g = np.linspace(0.0, TWO_PI, 20001)
+    logp = np.cos(q * (g[:, None] - np.asarray(nbrs)[None, :])).sum(1) / T
+    w = np.exp(logp - logp.max())
+    c = scipy.integrate.cumulative_trapezoid(w, g, initial=0.0)
+    c /= c[-1]
+    p = phi.copy()
+    samples = []
+    for t in range(4000 * 10):
+        p, _, _ = oracle.half_sweep(p, m, 0, T, a, t, seed=4321, q=q)
+        if t % 10 == 9:
+            samples.append(p[1, 1])
+    res = scipy.stats.kstest(np.array(samples), lambda v: np.interp(v, g, c))
+    assert res.pvalue > 1e-3, res
+
+
+@pytest.mark.parametrize("q", [0.3, 0.2])
+def test_energy_table_high_temperature_limit_for_q(q):
+    """T -> infinity: e -> -E[cos(q (u1 - u2))] = -(sin(pi q) / (pi q))^2."""
+    e = oracle.energy_table(8, 8, [1.0e4], 50, 2000, seed=5, q=q)[0]
+    want = -(math.sin(math.pi * q) / (math.pi * q)) ** 2
+    assert abs(e - want) < 3e-3, (e, want)
