@@ -65,8 +65,9 @@ typedef struct {
  * leaves the defaults to earlier work; mpr_default_params fills the values
  * this library uses. */
 typedef struct {
-    double q;             /* coupling exponent; must be 1/2 (Section 2.2), other
-                             values are rejected with MPR_ERR_ARG */
+    double q;             /* coupling exponent: 1/2 (Section 2.2), or 0 < q < 1/2 with
+                             fp64 = 1 (the single-precision sweep is written for 1/2;
+                             see mpr_select_q); other values: MPR_ERR_ARG */
     int32_t R;            /* independent chains per image */
     int32_t K;            /* equilibrium states per chain; M = R * K realizations */
     int32_t n_f;          /* slope checked every n_f sweeps ... */
@@ -204,6 +205,30 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
 int32_t mpr_predict(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
                     const float *z, const uint8_t *sampled, const float *phi_sum,
                     const double *zmin_zmax, int32_t M, float *z_hat, void *stream);
+
+/* Learnable coupling exponent.  The paper fixes q = 1/2 (Section 2.2: any
+ * q <= 1/2 keeps 0 and 2 pi apart) and gives no rule to choose it; this call
+ * chooses q for one image from the candidates q_grid[0..nq-1] (each in
+ * (0, 1/2], nq <= 64) by hold-out validation: the samples whose site uniform
+ * (Philox4x32-10, key seed, counter (y nx + x, 0xFFFFFFFE, 0, 0x40000000),
+ * word 0) is below `holdout` (0 < holdout < 1) are hidden; for each q the
+ * remaining samples give T_hat(q) (mpr_estimate_temperature with p->q = q),
+ * mpr_simulate (R, K of p; double-precision chains for q < 1/2) and
+ * mpr_predict fill the hidden sites, scored by their mean absolute error.
+ *   z, sampled (dev, the image at img->offset)
+ *   val_mae (host, double[nq], out): the error for each candidate
+ *   T_hat (host, double[nq], out, nullable): the temperature for each
+ *   q_best (host, out): the candidate with the smallest error (on a tie, the
+ *         larger q)
+ *   workspace: mpr_select_q_workspace_size bytes (dev).
+ * Errors: MPR_ERR_ARG for bad arguments or K < 1; MPR_ERR_DEGENERATE when no
+ * sample is held out or too few remain. */
+int64_t mpr_select_q_workspace_size(const mpr_image *img, const mpr_params *p, const double *q_grid,
+                                    int32_t nq);
+int32_t mpr_select_q(mpr_ctx *ctx, const mpr_image *img, const float *z, const uint8_t *sampled,
+                     const mpr_params *p, const double *q_grid, int32_t nq, double holdout,
+                     void *workspace, int64_t ws_bytes, double *val_mae, double *T_hat,
+                     double *q_best, void *stream);
 
 /* Quantiles of the prediction (Algorithm 2 step 7, statistics of the M
  * realizations): at each gap site the probs[k]-quantile of the M states of

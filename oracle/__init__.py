@@ -86,6 +86,7 @@ def _declare(L):
     L.oracle_predict.argtypes = [i32, i32, P, P, P, i32, P, P]
     L.oracle_spread.argtypes = [i32, i32, P, P, P, i32, P, P]
     L.oracle_quantiles.argtypes = [i32, i32, P, P, P, i32, P, i32, P, P]
+    L.oracle_holdout_mask.argtypes = [i32, i32, P, u64, d, P]
     L.oracle_quantiles.restype = i32
     L.oracle_energy_table.argtypes = [i32, i32, d, i32, P, i32, i32, d, d, u64, u32, P]
     L.oracle_energy_table.restype = i32
@@ -239,6 +240,46 @@ def quantiles(z, sampled, states, probs, zmin_zmax):
     if rc:
         raise OracleError(rc, "quantiles")
     return out
+
+
+def holdout_mask(sampled, seed, hold):
+    """1 at the samples kept for fitting, 0 at gaps and held-out samples."""
+    s = _u8(sampled)
+    ny, nx = s.shape
+    fit = np.zeros_like(s)
+    lib().oracle_holdout_mask(nx, ny, _p(s), seed, hold, _p(fit))
+    return fit
+
+
+def select_q(z, sampled, params: Params, q_grid, holdout, nT, T_lo, T_hi, burn, meas):
+    """The hold-out choice of q (the paper gives no rule): hide the samples
+    of holdout_mask, and for each candidate q estimate T from the rest
+    (sample energy and the e(T, L) table with that q), simulate, predict the
+    hidden samples and take their mean absolute error; the smallest wins (on
+    a tie, the larger q).  Returns (q_best, errors, temperatures)."""
+    z = _f64(z)
+    s = _u8(sampled)
+    ny, nx = z.shape
+    fit = holdout_mask(s, params.seed, holdout)
+    hidden = (s == 1) & (fit == 0)
+    phi, zz = map_to_angles(z, fit)
+    Tg = temperature_grid(nT, T_lo, T_hi)
+    errs, temps = [], []
+    for q in q_grid:
+        e_s, _ = sample_energy(phi, fit, q)
+        et = energy_table(nx, ny, Tg, burn, meas, a_targ=params.a_targ, k_a=params.k_a, seed=params.seed, q=q)
+        T, _ = invert_temperature(Tg, et, e_s)
+        p = Params.from_buffer_copy(params)
+        p.q = q
+        ps, _, _, _ = simulate(phi, fit, T, p)
+        zh = predict(z, fit, ps, p.R * p.K, zz)
+        errs.append(float(np.mean(np.abs(z[hidden] - zh[hidden]))))
+        temps.append(T)
+    best = 0
+    for k in range(1, len(q_grid)):
+        if errs[k] < errs[best] or (errs[k] == errs[best] and q_grid[k] > q_grid[best]):
+            best = k
+    return q_grid[best], np.array(errs), np.array(temps)
 
 
 def predict(z, sampled, phi_sum, M, zmin_zmax):

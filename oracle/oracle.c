@@ -113,6 +113,23 @@ void oracle_site_uniforms(uint64_t seed, int nx, int x, int y, uint32_t sweep,
     *r = (double)(w[2 * sel + 1] >> 8) * (1.0 / 16777216.0);
 }
 
+/* Samples kept for fitting when a fraction `hold` of them is held out for
+ * validation (the choice of q, which the paper leaves open): the sample at
+ * index i = y*nx + x is held out when (w >> 8) 2^-24 < hold for word w = word 0
+ * of Philox4x32-10 with counter (i, 0xFFFFFFFE, 0, 0x40000000), key = seed. */
+void oracle_holdout_mask(int nx, int ny, const uint8_t *sampled, uint64_t seed, double hold, uint8_t *fit)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    long n = (long)nx * ny;
+    for (long i = 0; i < n; ++i) {
+        fit[i] = 0;
+        if (!sampled[i]) continue;
+        uint32_t ctr[4] = {(uint32_t)i, 0xFFFFFFFEu, 0u, 0x40000000u}, w[4];
+        oracle_philox4x32_10(ctr, key, w);
+        fit[i] = ((double)(w[0] >> 8) * (1.0 / 16777216.0) < hold) ? 0 : 1;
+    }
+}
+
 /* ------------------------------------------------------------ data map */
 /* Equation (map), Algorithm 2 step 3.1: phi = 2 pi (z - z_min)/(z_max - z_min)
  * at the sampled sites; z_min, z_max over the samples.  Gaps get 0. */

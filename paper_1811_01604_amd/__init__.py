@@ -23,7 +23,7 @@ FLAG_KEPT, FLAG_ACCEPTED, FLAG_WRAPPED, FLAG_UPDATED, FLAG_FP64 = 1, 2, 4, 8, 16
 EXPORTS = [
     "mpr_create", "mpr_destroy", "mpr_last_error", "mpr_default_params", "mpr_workspace_size",
     "mpr_map_to_angles", "mpr_estimate_temperature", "mpr_simulate", "mpr_predict", "mpr_spread",
-    "mpr_quantiles",
+    "mpr_quantiles", "mpr_select_q", "mpr_select_q_workspace_size",
     "mpr_profile_enable", "mpr_profile_read",
     "mpr_cnn_param_count", "mpr_cnn_packed_bytes", "mpr_cnn_workspace_size", "mpr_cnn_pack", "mpr_cnn_encode",
     "mpr_cnn_forward", "mpr_cnn_loss", "mpr_cnn_backward", "mpr_cnn_opt_step", "mpr_cnn_decode",
@@ -116,6 +116,8 @@ def _declare(L):
         "mpr_estimate_temperature": (i32, [P, IMG, i32, P, P, PRM, P, i64, P, P, P, P]),
         "mpr_simulate": (i32, [P, IMG, i32, P, P, P, PRM, P, P, i64, P, P, P, C.POINTER(ChainStats), P]),
         "mpr_quantiles": (i32, [P, IMG, i32, P, P, P, i32, P, i32, P, P, P]),
+        "mpr_select_q_workspace_size": (i64, [IMG, PRM, P, i32]),
+        "mpr_select_q": (i32, [P, IMG, P, P, PRM, P, i32, d, P, i64, P, P, P, P]),
         "mpr_predict": (i32, [P, IMG, i32, P, P, P, P, i32, P, P]),
         "mpr_spread": (i32, [P, IMG, i32, P, P, P, i32, P, P]),
         "mpr_cnn_param_count": (i64, []),
@@ -254,6 +256,24 @@ class Context:
         self._check(self.lib.mpr_quantiles(self._h, imgs, len(imgs), _ptr(z), _ptr(sampled), _ptr(phi_states), M,
                                            pr.ctypes.data_as(C.c_void_p), pr.size, zz.ctypes.data_as(C.c_void_p),
                                            _ptr(z_q), _stream(stream)))
+
+    def select_q_workspace_size(self, img, params, q_grid) -> int:
+        qg = np.ascontiguousarray(q_grid, dtype=np.float64)
+        return int(self.lib.mpr_select_q_workspace_size(img, C.byref(params), qg.ctypes.data_as(C.c_void_p),
+                                                        qg.size))
+
+    def select_q(self, img, z, sampled, params, q_grid, holdout, ws, stream=None):
+        """Hold-out choice of q for one image (img: a one-image array from
+        images()); returns (q_best, validation MAE per q, T_hat per q)."""
+        qg = np.ascontiguousarray(q_grid, dtype=np.float64)
+        mae = np.zeros(qg.size)
+        T = np.zeros(qg.size)
+        qb = C.c_double()
+        self._check(self.lib.mpr_select_q(self._h, img, _ptr(z), _ptr(sampled), C.byref(params),
+                                          qg.ctypes.data_as(C.c_void_p), qg.size, holdout, _ptr(ws),
+                                          ws.numel() * ws.element_size(), mae.ctypes.data_as(C.c_void_p),
+                                          T.ctypes.data_as(C.c_void_p), C.byref(qb), _stream(stream)))
+        return qb.value, mae, T
 
     def spread(self, imgs, sampled, phi_m2, zmin_zmax, M, z_std, stream=None):
         zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)

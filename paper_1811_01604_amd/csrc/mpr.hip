@@ -669,7 +669,8 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
                     r = unit24(sl ? wd.w : wd.y);
                 }
                 const SiteOutD o = update_site_d((double)a, (double)nL, (double)nR, (double)nU, (double)nD, valid,
-                                                 (double)u, (double)r, stp->a_cur, stp->T, or_only != 0);
+                                                 (double)u, (double)r, stp->a_cur, stp->T, sc.q64,
+                                                 or_only != 0);
                 const float out = (float)o.phi;
                 *mp = out;
                 if (accp)
@@ -743,9 +744,9 @@ __global__ __launch_bounds__(kBlock) void half_sweep_fp64_kernel(const ChainDesc
             const uint32_t val0 = (vL ? 1u : 0u) | (vM ? 2u : 0u) | (vU ? 4u : 0u) | (vD ? 8u : 0u);
             const uint32_t val1 = 1u | (vR ? 2u : 0u) | (vU ? 4u : 0u) | (vD ? 8u : 0u);
             const SiteOutD o0 = update_site_d(fabs(v.x), oL, oM, fabs(up.x), fabs(dn.x), val0, u0, r0, a, T,
-                                              or_only != 0);
+                                              sc.q64, or_only != 0);
             const SiteOutD o1 = update_site_d(fabs(v.y), oM, oR, fabs(up.y), fabs(dn.y), val1, u1, r1, a, T,
-                                              or_only != 0);
+                                              sc.q64, or_only != 0);
             const bool w0 = !fixed0, w1 = two && !fixed1;
             const double out0 = w0 ? o0.phi : v.x;
             const double out1 = w1 ? o1.phi : v.y;
@@ -1018,6 +1019,61 @@ __global__ __launch_bounds__(kQuantileLanes) void quantile_kernel(const ImgDev *
             const double tt = phi_p / kTwoPi;
             out[q * n_total + k] = (float)(lo * (1.0 - tt) + hi * tt);
         }
+    }
+}
+
+// The sampled sites kept for fitting when a fraction `hold` of them is held
+// out for validation: a sample is held out when the uniform of its site,
+// word 0 of Philox4x32-10 with counter (y nx + x, 0xFFFFFFFE, 0, 0x40000000)
+// and the seed as key, is below `hold`.
+constexpr uint32_t kHoldoutSweep = 0xFFFFFFFEu;
+constexpr uint32_t kHoldoutStream = 0x40000000u;
+
+__global__ void holdout_kernel(int nx, int ny, const uint8_t *__restrict__ sampled, uint32_t seed_lo,
+                               uint32_t seed_hi, double hold, uint8_t *__restrict__ fit)
+{
+    const int64_t n = (int64_t)nx * ny;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t keep = 0;
+        if (sampled[i]) {
+            const U4 w = philox4x32_10(U4{(uint32_t)i, kHoldoutSweep, 0u, kHoldoutStream}, seed_lo, seed_hi);
+            keep = (double)unit24(w.x) < hold ? 0 : 1;
+        }
+        fit[i] = keep;
+    }
+}
+
+// Partial sums of |z - z_hat| and counts over the held-out samples
+// (sampled but not kept for fitting), one pair per block.
+__global__ void holdout_error_kernel(int64_t n, const float *__restrict__ z, const uint8_t *__restrict__ sampled,
+                                     const uint8_t *__restrict__ fit, const float *__restrict__ z_hat,
+                                     double *__restrict__ psum, unsigned long long *__restrict__ pcount)
+{
+    double s = 0.0;
+    unsigned long long c = 0ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (sampled[i] && !fit[i]) {
+            s += fabs((double)z[i] - (double)z_hat[i]);
+            ++c;
+        }
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off);
+        c += __shfl_xor(c, off);
+    }
+    __shared__ double ss[kBlock / 64];
+    __shared__ unsigned long long sc[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) {
+        ss[threadIdx.x >> 6] = s;
+        sc[threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; ++i) {
+            ss[0] += ss[i];
+            sc[0] += sc[i];
+        }
+        psum[blockIdx.x] = ss[0];
+        pcount[blockIdx.x] = sc[0];
     }
 }
 
@@ -1370,7 +1426,10 @@ int64_t redo_bytes(int nx, int ny, int64_t chains)
 
 bool valid_params(const mpr_params *p)
 {
-    return p && p->q == 0.5 && p->R >= 1 && p->K >= 0 && p->n_f >= 1 && p->n_fit >= 2 &&
+    // q = 1/2 (the paper's value) runs on either sweep; 0 < q < 1/2 on the
+    // double-precision one (the single-precision kernels are written for 1/2)
+    return p && (p->q == 0.5 || (p->q > 0.0 && p->q < 0.5 && p->fp64 == 1)) && p->R >= 1 && p->K >= 0 &&
+           p->n_f >= 1 && p->n_fit >= 2 &&
            p->n_fit <= kMaxFit && p->sg_degree >= 1 && p->sg_degree <= 4 && p->sg_degree < p->n_fit &&
            p->k_a > 0.0 && p->a_targ >= 0.0 && p->table_nT >= 2 && p->table_meas >= 1 && p->table_burn >= 0 &&
            p->table_T_lo > 0.0 && p->table_T_hi > p->table_T_lo &&
@@ -1405,11 +1464,15 @@ int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     return b;
 }
 
+// Table chains run in double precision when q != 1/2 (the single-precision
+// kernels are written for q = 1/2).
+int table_angle_bytes(const mpr_params *p) { return p->q == 0.5 ? 4 : 8; }
+
 int64_t table_bytes(const mpr_image *imgs, int n, const mpr_params *p)
 {
     int64_t best = 0;
     for (int i = 0; i < n; ++i) {
-        const int64_t hg = round_up(half_grid_bytes(imgs[i].nx, imgs[i].ny), 256);
+        const int64_t hg = round_up(half_grid_bytes(imgs[i].nx, imgs[i].ny, table_angle_bytes(p)), 256);
         best = std::max(best, (int64_t)p->table_nT * 2 * hg);
     }
     const int64_t chains = p->table_nT;
@@ -2117,8 +2180,9 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
     const int nT = p->table_nT;
     // workspace of one grid size's table chains (grids, descriptors, block
     // offsets and redo buffers), as upload_chains carves them
+    const int teb = table_angle_bytes(p);
     auto table_chain_bytes = [&](int b) {
-        const int64_t hg = round_up(half_grid_bytes(imgs[b].nx, imgs[b].ny), 256);
+        const int64_t hg = round_up(half_grid_bytes(imgs[b].nx, imgs[b].ny, teb), 256);
         return nT * 2 * hg + redo_bytes(imgs[b].nx, imgs[b].ny, nT) +
                nT * (int64_t)(sizeof(ChainDesc) + sizeof(ChainState) + 8 + (kNumShapes + 1) * 8) + 4096;
     };
@@ -2130,6 +2194,7 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
             need += table_chain_bytes(missing[++last]);
         Carver cv{(char *)ws, ws_bytes};
         ChainSet cs;
+        cs.fp64 = teb == 8;
         int64_t maxn = 0;
         for (size_t g = first; g <= last; ++g) {
             const int b = missing[g];
@@ -2137,7 +2202,7 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
             for (int k = 0; k < nT; ++k) {
                 ChainDesc d;
                 std::memset(&d, 0, sizeof d);
-                if (!carve_chain(cv, d, imgs[b].nx, imgs[b].ny, false))
+                if (!carve_chain(cv, d, imgs[b].nx, imgs[b].ny, false, false, teb))
                     return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
                 d.image_id = kTableStream;
                 d.chain = (uint32_t)k;
@@ -2151,7 +2216,7 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
         int rc = upload_chains(ctx, cs, cv, stream, p->q);
         if (rc) return rc;
         hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), (unsigned)cs.desc.size()), dim3(kBlock),
-                           0, stream, cs.d_desc, cs.d_offset, nullptr, nullptr, nullptr, 0u, 0u, 1, 0);
+                           0, stream, cs.d_desc, cs.d_offset, nullptr, nullptr, nullptr, 0u, 0u, 1, cs.fp64 ? 1 : 0);
         HIP_TRY(ctx, hipGetLastError());
         rc = run_chains(ctx, cs, p, stream, (int64_t)p->table_burn + p->table_meas, 50, true);
         if (rc) return rc;
@@ -2385,6 +2450,102 @@ int32_t mpr_spread(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const uint8_t
     return MPR_OK;
 }
 
+// Workspace of mpr_select_q: four per-site buffers of the image and the
+// largest simulation/temperature workspace over the candidate q.
+int64_t select_q_bytes(const mpr_image *img, const mpr_params *p, const double *q_grid, int nq)
+{
+    const int64_t n = (int64_t)img->nx * img->ny;
+    mpr_image im0 = *img;
+    im0.offset = 0;
+    int64_t best = 0;
+    for (int k = 0; k < nq; ++k) {
+        mpr_params pk = *p;
+        pk.q = q_grid[k];
+        pk.fp64 = q_grid[k] == 0.5 ? p->fp64 : 1;
+        if (!valid_params(&pk)) return -1;
+        best = std::max(best, std::max(sim_bytes(&im0, 1, &pk), table_bytes(&im0, 1, &pk)));
+    }
+    return best + round_up(n, 256) + 3 * round_up(4 * n, 256) + 1024;
+}
+
+int64_t mpr_select_q_workspace_size(const mpr_image *img, const mpr_params *p, const double *q_grid, int32_t nq)
+{
+    if (!valid_images(img, 1) || !p || !q_grid || nq < 1) return -1;
+    return select_q_bytes(img, p, q_grid, nq);
+}
+
+int32_t mpr_select_q(mpr_ctx *ctx, const mpr_image *img, const float *z, const uint8_t *sampled, const mpr_params *p,
+                     const double *q_grid, int32_t nq, double holdout, void *ws, int64_t ws_bytes, double *val_mae,
+                     double *T_hat, double *q_best, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!valid_images(img, 1) || !z || !sampled || !p || !q_grid || nq < 1 || nq > 64 || !(holdout > 0.0) ||
+        !(holdout < 1.0) || !val_mae || !q_best || p->K < 1)
+        return fail(ctx, MPR_ERR_ARG, "select_q: invalid argument");
+    const int64_t need = select_q_bytes(img, p, q_grid, nq);
+    if (need < 0) return fail(ctx, MPR_ERR_ARG, "select_q: a candidate q is outside (0, 1/2]");
+    if (!ws || ws_bytes < need) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t stream = (hipStream_t)stream_;
+    const int64_t n = (int64_t)img->nx * img->ny;
+    mpr_image im0 = *img;
+    im0.offset = 0;
+    const float *zi = z + img->offset;
+    const uint8_t *si = sampled + img->offset;
+    // per-site buffers first, the calls' workspace after them
+    const int64_t head = round_up(n, 256) + 3 * round_up(4 * n, 256);
+    uint8_t *fit = (uint8_t *)ws;
+    float *phi = (float *)((char *)ws + round_up(n, 256));
+    float *psum = (float *)((char *)phi + round_up(4 * n, 256));
+    float *zhat = (float *)((char *)psum + round_up(4 * n, 256));
+    void *iws = (char *)ws + head;
+    const int64_t inner = ws_bytes - head;
+    hipLaunchKernelGGL(holdout_kernel, dim3(blocks_for(n, 2048)), dim3(kBlock), 0, stream, img->nx, img->ny, si,
+                       (uint32_t)p->seed, (uint32_t)(p->seed >> 32), holdout, fit);
+    HIP_TRY(ctx, hipGetLastError());
+    double zmm[2];
+    int rc = mpr_map_to_angles(ctx, &im0, 1, zi, fit, phi, zmm, stream);
+    if (rc) return rc;
+    double *d_ps = (double *)((char *)ctx->scratch + kVarOffset);
+    unsigned long long *d_pc = (unsigned long long *)(d_ps + kMapBlocks);
+    int best = -1;
+    for (int k = 0; k < nq; ++k) {
+        mpr_params pk = *p;
+        pk.q = q_grid[k];
+        pk.fp64 = q_grid[k] == 0.5 ? p->fp64 : 1;
+        double e_s = 0.0, T = 0.0;
+        rc = mpr_estimate_temperature(ctx, &im0, 1, phi, fit, &pk, iws, inner, &e_s, &T, nullptr, stream);
+        if (rc) return rc;
+        rc = mpr_simulate(ctx, &im0, 1, phi, fit, &T, &pk, nullptr, iws, inner, psum, nullptr, nullptr, nullptr,
+                          stream);
+        if (rc) return rc;
+        rc = mpr_predict(ctx, &im0, 1, zi, fit, psum, zmm, pk.R * pk.K, zhat, stream);
+        if (rc) return rc;
+        hipLaunchKernelGGL(holdout_error_kernel, dim3(kMapBlocks), dim3(kBlock), 0, stream, n, zi, si, fit, zhat,
+                           d_ps, d_pc);
+        HIP_TRY(ctx, hipGetLastError());
+        double hs[kMapBlocks];
+        unsigned long long hc[kMapBlocks];
+        HIP_TRY(ctx, hipMemcpyAsync(hs, d_ps, sizeof hs, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipMemcpyAsync(hc, d_pc, sizeof hc, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        double sum = 0.0;
+        unsigned long long cnt = 0;
+        for (int b = 0; b < kMapBlocks; ++b) {
+            sum += hs[b];
+            cnt += hc[b];
+        }
+        if (cnt == 0) return fail(ctx, MPR_ERR_DEGENERATE, "select_q: no sample held out");
+        val_mae[k] = sum / (double)cnt;
+        if (T_hat) T_hat[k] = T;
+        // smallest error; on a tie the larger q
+        if (best < 0 || val_mae[k] < val_mae[best] || (val_mae[k] == val_mae[best] && q_grid[k] > q_grid[best]))
+            best = k;
+    }
+    *q_best = q_grid[best];
+    return MPR_OK;
+}
+
 int32_t mpr_profile_enable(mpr_ctx *ctx, int32_t on)
 {
     if (!ctx) return MPR_ERR_ARG;
@@ -2521,7 +2682,7 @@ int32_t mpr_diag_half_sweep_fp64(mpr_ctx *ctx, int32_t nx, int32_t ny, double *p
     if (!ctx) return MPR_ERR_ARG;
     const int v = tile ? shape_of(tile) : kDefaultShape;
     if (nx < 1 || ny < 1 || (int64_t)nx * ny < 2 || !phi || !sampled || (colour != 0 && colour != 1) || !(T > 0) ||
-        !(a > 0) || q != 0.5 || (mode != 0 && mode != 1) || v < 0 || kShapes[v].compact)
+        !(a > 0) || !(q > 0.0 && q <= 0.5) || (mode != 0 && mode != 1) || v < 0 || kShapes[v].compact)
         return fail(ctx, MPR_ERR_ARG, "diag_half_sweep_fp64: invalid argument");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;

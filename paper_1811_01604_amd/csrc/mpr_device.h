@@ -422,22 +422,26 @@ struct SiteOutD {
     bool accepted;
 };
 
-// Algorithm 1 for one site, q = 1/2, in double precision: the steps and the
-// cancellation-free energy change of update_site (see there), with the
+// Algorithm 1 for one site in double precision, for 0 < q <= 1/2: the steps
+// of update_site in the variable th = q phi in [0, 2 pi q) (reflection
+// th' = th + 2 atan2(-B, A), kept when it leaves that range), with the
 // proposal, wrap and acceptance test in the form of their plain definition:
-// phi'' = phi' + 2 pi (u - 1/2) / a taken mod 2 pi, accepted when
-// Delta H <= 0 or exp(-Delta H / T) > r.
+// phi'' = phi' + 2 pi (u - 1/2) / a taken mod 2 pi, accepted when Delta H <= 0
+// or exp(-Delta H / T) > r.  The energy change uses the cancellation-free
+// form Delta H = 2 A sin^2(d / 2) + B_s sin d for the move d = th'' - th' in
+// th (q delta phi, shifted by -+2 pi q when the proposal wraps; |d| <= pi).
 __device__ __forceinline__ SiteOutD update_site_d(double phi, double n0, double n1, double n2, double n3,
-                                                  uint32_t valid, double u, double r, double a, double T,
+                                                  uint32_t valid, double u, double r, double a, double T, double q,
                                                   bool or_only)
 {
-    const double th = 0.5 * phi;
+    const double period = kTwoPi * q;  // range of th
+    const double th = q * phi;
     const double nb[4] = {n0, n1, n2, n3};
     double A2 = 0.0, B = 0.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const bool v = (valid >> j) & 1u;
-        const double dj = v ? th - 0.5 * nb[j] : 0.0;
+        const double dj = v ? th - q * nb[j] : 0.0;
         const double d2 = dj * dj;
         const double s2 = sin2_half_d(dj, d2);  // 2 sin(D_j / 2)
         B = fma(s2, cos_half_d(d2), B);         // sin D_j
@@ -448,20 +452,19 @@ __device__ __forceinline__ SiteOutD update_site_d(double phi, double n0, double 
     const double A = (double)nnb - A_small;
     SiteOutD o;
     o.e_before = A_small;
-    // reflection of th about the field direction: th' = th + 2 atan2(-B, A),
-    // kept when it leaves [0, pi) (or when there is no field)
-    double th1 = th;
+    double th1 = th, p1 = phi;
     bool kept = true;
     if (nnb > 0 && (A != 0.0 || B != 0.0)) {
         const double raw1 = fma(2.0, atan2_fp64(-B, A), th);
-        if (raw1 >= 0.0 && raw1 < kPi) {
+        if (raw1 >= 0.0 && raw1 < period) {
             th1 = raw1;
+            p1 = raw1 / q;
             kept = false;
         }
     }
     uint32_t f = F_UPDATED | F_FP64 | (kept ? F_KEPT : 0u);
     if (or_only) {
-        o.phi = 2.0 * th1;
+        o.phi = p1;
         o.e_bonds = A_small;
         o.flags = f;
         o.accepted = false;
@@ -469,20 +472,19 @@ __device__ __forceinline__ SiteOutD update_site_d(double phi, double n0, double 
     }
     const double Bs = kept ? B : -B;  // |h| sin(th' - Psi)
     const double dphi = kTwoPi * (u - 0.5) / a;
-    const double delta = 0.5 * dphi;
-    const double raw2 = 2.0 * th1 + dphi;
+    const double raw2 = p1 + dphi;
     const bool wrapped = raw2 < 0.0 || raw2 >= kTwoPi;
     double p2 = raw2 < 0.0 ? raw2 + kTwoPi : (raw2 >= kTwoPi ? raw2 - kTwoPi : raw2);
     if (p2 >= kTwoPi || p2 < 0.0) p2 = 0.0;
-    const double dd2 = delta * delta;
-    const double sh2 = sin2_half_d(delta, dd2), ch = cos_half_d(dd2);  // 2 sin(delta/2), cos(delta/2)
-    const double sd = sh2 * ch;                                          // sin delta
-    const double w2 = wrapped ? 2.0 * (ch * ch) : 0.5 * (sh2 * sh2);
-    const double dH = fma(A, w2, wrapped ? -Bs * sd : Bs * sd);
+    const double d = q * dphi + (raw2 < 0.0 ? period : (raw2 >= kTwoPi ? -period : 0.0));
+    const double dd2 = d * d;
+    const double sh2 = sin2_half_d(d, dd2);   // 2 sin(d/2)
+    const double sd = sh2 * cos_half_d(dd2);  // sin d
+    const double dH = fma(A, 0.5 * (sh2 * sh2), Bs * sd);
     const bool acc = (dH <= 0.0) || (exp(-dH / T) > r);
     if (wrapped) f |= F_WRAPPED;
     if (acc) f |= F_ACCEPTED;
-    o.phi = acc ? p2 : 2.0 * th1;
+    o.phi = acc ? p2 : p1;
     o.e_bonds = acc ? A_small + dH : A_small;
     o.flags = f;
     o.accepted = acc;

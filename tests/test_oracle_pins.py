@@ -568,3 +568,38 @@ def test_energy_table_high_temperature_limit_for_q(q):
     e = oracle.energy_table(8, 8, [1.0e4], 50, 2000, seed=5, q=q)[0]
     want = -(math.sin(math.pi * q) / (math.pi * q)) ** 2
     assert abs(e - want) < 3e-3, (e, want)
+
+
+def test_holdout_mask_and_q_selection():
+    """The hold-out mask hides about the asked fraction of samples and only
+    samples, from the same Philox words as the site uniforms (word 0 of the
+    counter (i, 0xFFFFFFFE, 0, 0x40000000)); the q choice returns the
+    candidate with the smallest hold-out error, each error being that of a
+    plain fill of the hidden samples at that q."""
+    rng = np.random.default_rng(5)
+    ny, nx = 40, 50
+    m = (rng.random((ny, nx)) < 0.6).astype(np.uint8)
+    fit = oracle.holdout_mask(m, 77, 0.25)
+    hidden = (m == 1) & (fit == 0)
+    assert np.all(fit[m == 0] == 0)
+    frac = hidden.sum() / m.sum()
+    assert abs(frac - 0.25) < 4 * math.sqrt(0.25 * 0.75 / m.sum())
+    # word 0 of the counter equals the oracle's Philox on the same counter
+    i = int(np.flatnonzero(m.ravel())[3])
+    w = oracle.philox4x32_10([i, 0xFFFFFFFE, 0, 0x40000000], [77, 0])
+    assert bool(fit.ravel()[i]) == ((w[0] >> 8) / 2.0 ** 24 >= 0.25)
+    z = synth.matern_field(24, 20, 1.5, 0.2, 50.0, 10.0, 8)
+    mm = synth.random_mask(24, 20, 0.4, 9)
+    prm = oracle.default_params(R=2, K=5, seed=31)
+    qb, errs, temps = oracle.select_q(z, mm, prm, [0.25, 0.5], 0.3, 8, 1e-3, 2.0, 30, 60)
+    assert qb == [0.25, 0.5][int(np.argmin(errs))] and np.all(temps > 0)
+    # the error of q = 1/2 is that of the plain fill with the hidden samples as gaps
+    fit2 = oracle.holdout_mask(mm, 31, 0.3)
+    phi, zz = oracle.map_to_angles(z, fit2)
+    e_s, _ = oracle.sample_energy(phi, fit2)
+    Tg = oracle.temperature_grid(8, 1e-3, 2.0)
+    T, _ = oracle.invert_temperature(Tg, oracle.energy_table(24, 20, Tg, 30, 60, seed=31), e_s)
+    ps, _, _, _ = oracle.simulate(phi, fit2, T, prm)
+    zh = oracle.predict(z, fit2, ps, 10, zz)
+    h2 = (mm == 1) & (fit2 == 0)
+    assert abs(errs[1] - np.mean(np.abs(z[h2] - zh[h2]))) < 1e-12
