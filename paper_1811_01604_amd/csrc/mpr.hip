@@ -228,19 +228,20 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
             const bool two = (h0 + 1) < W;
             // select by value: indexing d.h with a runtime colour would put
             // the descriptor in memory
-            float *mine = (colour ? d.h[1] : d.h[0]) + (int64_t)y * d.S;
-            const float *oth = (colour ? d.h[0] : d.h[1]) + (int64_t)y * d.S;
+            float *mine = colour ? d.h[1] : d.h[0];
+            const float *oth = colour ? d.h[0] : d.h[1];
+            const int row = y * d.S;
             const bool vL = h0 + s - 1 >= 0, vM = h0 + s < Wo, vR = h0 + s + 1 < Wo;
             const bool vU = y > 0, vD = y + 1 < d.ny;
             // every load is issued, from a clamped in-row position when the
             // neighbour is missing (update_site ignores it by its valid bit),
             // so that all of them are in flight at once
-            const float2 v = gld2(mine + h0);
-            const float oL = angle_of(gld(oth + max(h0 + s - 1, 0)));
-            const float oM = angle_of(gld(oth + h0 + s));  // h0 + s <= S - 1
-            const float oR = angle_of(gld(oth + min(h0 + s + 1, d.S - 1)));
-            float2 up = gld2(oth + (vU ? -(int64_t)d.S : 0) + h0);
-            float2 dn = gld2(oth + (vD ? (int64_t)d.S : 0) + h0);
+            const float2 v = gldi2(mine, (uint32_t)(row + h0));
+            const float oL = angle_of(gldi(oth, (uint32_t)(row + max(h0 + s - 1, 0))));
+            const float oM = angle_of(gldi(oth, (uint32_t)(row + h0 + s)));  // h0 + s <= S - 1
+            const float oR = angle_of(gldi(oth, (uint32_t)(row + min(h0 + s + 1, d.S - 1))));
+            float2 up = gldi2(oth, (uint32_t)(row + (vU ? -d.S : 0) + h0));
+            float2 dn = gldi2(oth, (uint32_t)(row + (vD ? d.S : 0) + h0));
             up.x = angle_of(up.x);
             up.y = angle_of(up.y);
             dn.x = angle_of(dn.x);
@@ -271,18 +272,19 @@ __device__ __forceinline__ void half_sweep_body(const ChainDesc *__restrict__ de
             const float out0 = w0 ? o0.phi : v.x;
             const float out1 = w1 ? o1.phi : v.y;
             if (two) {
-                gst2(mine + h0, make_float2(out0, out1));
+                v2f w;
+                w.x = out0;
+                w.y = out1;
+                *(gv2f *)gaddr(mine, (uint32_t)(row + h0)) = w;
             } else if (w0) {
-                gst(mine + h0, out0);
+                gsti(mine, (uint32_t)(row + h0), out0);
             }
             float *accp = colour ? d.acc[1] : d.acc[0];
             if (phase == PH_EQ && accp) {
-                float *acc = accp + (int64_t)y * d.S;
                 float *m2p = colour ? d.m2[1] : d.m2[0];
-                float *m2 = m2p ? m2p + (int64_t)y * d.S : nullptr;
                 const float ik = stp->inv_k, ikm1 = stp->inv_km1;
-                if (w0) accumulate_state(acc + h0, m2 ? m2 + h0 : nullptr, out0, ik, ikm1);
-                if (w1) accumulate_state(acc + h0 + 1, m2 ? m2 + h0 + 1 : nullptr, out1, ik, ikm1);
+                if (w0) accumulate_state_i(accp, m2p, (uint32_t)(row + h0), out0, ik, ikm1);
+                if (w1) accumulate_state_i(accp, m2p, (uint32_t)(row + h0 + 1), out1, ik, ikm1);
             }
             acc_thread = (w0 && o0.accepted ? 1u : 0u) + (w1 && o1.accepted ? 1u : 0u);
             // a sampled site's bonds are unchanged by this half-sweep
@@ -401,7 +403,7 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
         const int s = (y + colour) & 1;
         in[j] = y < d.ny && h0 < ((d.nx - s + 1) >> 1);
         // rows and pairs outside the grid read pair 0 of row 0 instead
-        pv[j] = gld2(mine_base + (in[j] ? (int64_t)y * d.S + h0 : 0));
+        pv[j] = gldi2(mine_base, in[j] ? (uint32_t)(y * d.S + h0) : 0u);
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -484,11 +486,11 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
     // all four loads are issued, from clamped positions for missing
     // neighbours (ignored by their valid bits), so that they overlap
     auto neighbours = [&](int y, int h, int s, uint32_t valid, float &nL, float &nR, float &nU, float &nD) {
-        const float *orow = oth_base + (int64_t)y * d.S;
-        nL = angle_of(gld(orow + max(h + s - 1, 0)));
-        nR = angle_of(gld(orow + min(h + s, d.S - 1)));
-        nU = angle_of(gld(orow + ((valid & 4u) ? -(int64_t)d.S : 0) + h));
-        nD = angle_of(gld(orow + ((valid & 8u) ? (int64_t)d.S : 0) + h));
+        const int row = y * d.S;
+        nL = angle_of(gldi(oth_base, (uint32_t)(row + max(h + s - 1, 0))));
+        nR = angle_of(gldi(oth_base, (uint32_t)(row + min(h + s, d.S - 1))));
+        nU = angle_of(gldi(oth_base, (uint32_t)(row + ((valid & 4u) ? -d.S : 0) + h)));
+        nD = angle_of(gldi(oth_base, (uint32_t)(row + ((valid & 8u) ? d.S : 0) + h)));
     };
 
     // a thread sees at most 5 sites (4 gap sites), each below 2^30 in energy units
@@ -507,12 +509,12 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
     auto fetch = [&](int i, Item &it) {
         it.e = gap_list[i];
         locate((it.e.x & 0xFFu) | ((it.e.y & 0xFFu) << 8), it.y, it.h, it.s, it.valid);
-        const float *orow = oth_base + (int64_t)it.y * d.S;
-        it.nL = gld(orow + max(it.h + it.s - 1, 0));
-        it.nR = gld(orow + min(it.h + it.s, d.S - 1));
-        it.nU = gld(orow + ((it.valid & 4u) ? -(int64_t)d.S : 0) + it.h);
-        it.nD = gld(orow + ((it.valid & 8u) ? (int64_t)d.S : 0) + it.h);
-        it.a = gld(mine_base + (int64_t)it.y * d.S + it.h);
+        const int row = it.y * d.S;
+        it.nL = gldi(oth_base, (uint32_t)(row + max(it.h + it.s - 1, 0)));
+        it.nR = gldi(oth_base, (uint32_t)(row + min(it.h + it.s, d.S - 1)));
+        it.nU = gldi(oth_base, (uint32_t)(row + ((it.valid & 4u) ? -d.S : 0) + it.h));
+        it.nD = gldi(oth_base, (uint32_t)(row + ((it.valid & 8u) ? d.S : 0) + it.h));
+        it.a = gldi(mine_base, (uint32_t)(row + it.h));
     };
     const int n_gap = n_list[0];
     Item cur;
@@ -523,7 +525,7 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
         const uint32_t idx = (cur.e.x & 0xFFu) | ((cur.e.y & 0xFFu) << 8);
         const int y = cur.y, h = cur.h, s = cur.s;
         const uint32_t valid = cur.valid;
-        float *mp = mine_base + (int64_t)y * d.S + h;
+        const uint32_t site = (uint32_t)(y * d.S + h);
         // the low 8 bits of each word hold the index; unit24 uses the top 24
         const float u = or_only ? 0.5f : unit24(cur.e.x);
         const float r = or_only ? 0.5f : unit24(cur.e.y);
@@ -535,10 +537,8 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
             defer_redo(rd, blockIdx.x, kCompactSites / 32, idx);
             continue;
         }
-        gst(mp, o.phi);
-        if (acc_base)
-            accumulate_state(acc_base + (int64_t)y * d.S + h, m2_base ? m2_base + (int64_t)y * d.S + h : nullptr,
-                             o.phi, stp->inv_k, stp->inv_km1);
+        gsti(mine_base, site, o.phi);
+        if (acc_base) accumulate_state_i(acc_base, m2_base, site, o.phi, stp->inv_k, stp->inv_km1);
         acc_thread += o.accepted ? 1u : 0u;
         if (want_energy) e_thread += energy_fx(o.e_bonds);
         if (DIAG && flags) flags[(int64_t)y * d.nx + 2 * h + s] = (uint8_t)o.flags;
@@ -550,7 +550,7 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
         locate((uint32_t)fixed_list[i], y, h, s, valid);
         float nL, nR, nU, nD;
         neighbours(y, h, s, valid, nL, nR, nU, nD);
-        const float a = angle_of(gld(mine_base + (int64_t)y * d.S + h));
+        const float a = angle_of(gldi(mine_base, (uint32_t)(y * d.S + h)));
         e_thread += energy_fx(bond_energy_half(0.5f * a, nL, nR, nU, nD, valid));
     }
     if (!want_acc) return;
@@ -1444,6 +1444,8 @@ bool valid_images(const mpr_image *imgs, int n)
     for (int b = 0; b < n; ++b) {
         if (imgs[b].nx < 1 || imgs[b].ny < 1 || imgs[b].offset < 0) return false;
         if ((int64_t)imgs[b].nx * imgs[b].ny > (int64_t)1 << 31) return false;
+        // the sweep kernels address a single-precision half-grid with 32-bit byte offsets
+        if (half_grid_bytes(imgs[b].nx, imgs[b].ny) >= ((int64_t)1 << 32)) return false;
         if (imgs[b].id >= 0x80000000u) return false;
     }
     return true;
@@ -2596,8 +2598,9 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
 {
     if (!ctx) return MPR_ERR_ARG;
     const int v = tile ? shape_of(tile) : kDefaultShape;
-    if (nx < 1 || ny < 1 || (int64_t)nx * ny < 2 || !phi || !sampled || (colour != 0 && colour != 1) || !(T > 0) ||
-        !(a > 0) || q != 0.5 || (mode != 0 && mode != 1) || v < 0)
+    if (nx < 1 || ny < 1 || (int64_t)nx * ny < 2 || half_grid_bytes(nx, ny) >= ((int64_t)1 << 32) || !phi ||
+        !sampled || (colour != 0 && colour != 1) || !(T > 0) || !(a > 0) || q != 0.5 || (mode != 0 && mode != 1) ||
+        v < 0)
         return fail(ctx, MPR_ERR_ARG, "diag_half_sweep: invalid argument");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
@@ -2681,8 +2684,9 @@ int32_t mpr_diag_half_sweep_fp64(mpr_ctx *ctx, int32_t nx, int32_t ny, double *p
 {
     if (!ctx) return MPR_ERR_ARG;
     const int v = tile ? shape_of(tile) : kDefaultShape;
-    if (nx < 1 || ny < 1 || (int64_t)nx * ny < 2 || !phi || !sampled || (colour != 0 && colour != 1) || !(T > 0) ||
-        !(a > 0) || !(q > 0.0 && q <= 0.5) || (mode != 0 && mode != 1) || v < 0 || kShapes[v].compact)
+    if (nx < 1 || ny < 1 || (int64_t)nx * ny < 2 || half_grid_bytes(nx, ny) >= ((int64_t)1 << 32) || !phi ||
+        !sampled || (colour != 0 && colour != 1) || !(T > 0) || !(a > 0) || !(q > 0.0 && q <= 0.5) ||
+        (mode != 0 && mode != 1) || v < 0 || kShapes[v].compact)
         return fail(ctx, MPR_ERR_ARG, "diag_half_sweep_fp64: invalid argument");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;

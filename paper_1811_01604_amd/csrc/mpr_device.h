@@ -334,6 +334,23 @@ __device__ __forceinline__ void gst2(float *p, float2 v)
     *(gv2f *)p = w;
 }
 
+// The same through a uniform base pointer and a 32-bit element index, so
+// that the address is the base plus a zero-extended 32-bit byte offset (the
+// scalar-base form of a global access, with no 64-bit address arithmetic per
+// lane).  The caller keeps the byte offset below 2^32 (a single-precision
+// half-grid is smaller than 4 GiB).
+__device__ __forceinline__ const gfloat *gaddr(const float *base, uint32_t i)
+{
+    return (const gfloat *)((const char *)base + (uint64_t)(i << 2));
+}
+__device__ __forceinline__ float gldi(const float *base, uint32_t i) { return *gaddr(base, i); }
+__device__ __forceinline__ float2 gldi2(const float *base, uint32_t i)
+{
+    const v2f v = *(const gv2f *)gaddr(base, i);
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gsti(float *base, uint32_t i, float v) { *(gfloat *)gaddr(base, i) = v; }
+
 // Adds the k-th equilibrium state phi of a site to its running sum acc and,
 // when m2 is given, to the sum of squared deviations from the running mean
 // (Welford's update with the mean taken from the sum: mean_{k-1} = acc
@@ -344,6 +361,16 @@ __device__ __forceinline__ void accumulate_state(float *acc, float *m2, float ph
     const float s1 = s0 + phi;
     gst(acc, s1);
     if (m2) gst(m2, fmaf(phi - s0 * inv_km1, phi - s1 * inv_k, gld(m2)));
+}
+
+// accumulate_state at element i of uniform base pointers.
+__device__ __forceinline__ void accumulate_state_i(float *acc, float *m2, uint32_t i, float phi, float inv_k,
+                                                   float inv_km1)
+{
+    const float s0 = gldi(acc, i);
+    const float s1 = s0 + phi;
+    gsti(acc, i, s1);
+    if (m2) gsti(m2, i, fmaf(phi - s0 * inv_km1, phi - s1 * inv_k, gldi(m2, i)));
 }
 
 // Bond energies of a site in fixed point: units of 2^-27, rounded, so that
