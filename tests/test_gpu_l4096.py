@@ -10,6 +10,8 @@ kappa=0.02 std 0.5; 66% random gaps or 40% cloud gaps).
     first sweeps), the cloud case from the true angles plus noise with
     a = 20 (late relaxation), both at T = 6e-5 (near this workload's
     estimate).
+  - The recorded realizations at full size and their quantiles at sampled
+    sites against the oracle.
   - The launch configuration the benchmark times (R = 100 chains, K = 1,
     stopping rule) gives each chain the relaxation it gets in a 2-chain
     launch, and the same sums in the plain and both compacted shapes (the
@@ -123,3 +125,41 @@ def test_l4096_benchmark_launch_matches_smaller_launches(ctx):
     assert st2 == ref_st[:2]
     g = im.mask == 0
     assert np.all(ref_ps[~g] == 0) and np.all((ref_ps[g] >= 0) & (ref_ps[g] < TWO_PI * 100))
+
+
+def test_l4096_recorded_states_and_quantiles(ctx):
+    """The benchmark's launch (100 chains, K = 1, stopping rule) with every
+    realization recorded (6.7 GB): the states sum to phi_sum, samples are
+    recorded with their angle, and the quantiles at 2000 sampled gap sites
+    equal the oracle's quantiles of those sites' 100 recorded values."""
+    im = synth.workload_l4096("random")
+    ny, nx = im.z.shape
+    imgs = mpr.images([im.z.shape])
+    z = torch.from_numpy(im.z.astype(np.float32)).cuda()
+    mk = torch.from_numpy(im.mask).cuda()
+    phi = torch.zeros_like(z)
+    zz = ctx.map_to_angles(imgs, z, mk, phi)
+    prm = mpr.default_params(R=100, K=1)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    ps = torch.zeros_like(z)
+    st = torch.empty((100, ny * nx), dtype=torch.float32, device="cuda")
+    ctx.simulate(imgs, phi, mk, np.array([T]), prm, ws, ps, phi_states=st)
+    del ws
+    probs = [0.05, 0.5, 0.95]
+    zq = torch.empty((len(probs), ny * nx), dtype=torch.float32, device="cuda")
+    ctx.quantiles(imgs, z, mk, st, 100, probs, zz, zq)
+    g = (im.mask == 0).ravel()
+    tot = st.double().sum(0)
+    d = (tot - ps.view(-1).double()).abs()[torch.from_numpy(g).cuda()]
+    # phi_sum adds the 100 float states in float: 99 roundings of partial sums
+    # below 200 pi, each at most half an ulp of 512..1024 (2^-15)
+    assert float(d.max()) <= 99 * 2.0 ** -15
+    s_idx = torch.from_numpy(np.flatnonzero(~g)[:1000]).cuda()
+    assert torch.equal(st[:, s_idx], phi.view(-1)[s_idx].unsqueeze(0).expand(100, -1))
+    rng = np.random.default_rng(3)
+    sites = np.sort(rng.choice(np.flatnonzero(g), size=2000, replace=False))
+    vals = st[:, torch.from_numpy(sites).cuda()].cpu().numpy().astype(np.float64)  # 100 x 2000
+    # the oracle on a 1 x 2000 "image" of those sites (all gaps)
+    qo = oracle.quantiles(np.zeros((1, 2000)), np.zeros((1, 2000), np.uint8), vals.reshape(100, 1, 2000), probs, zz)
+    got = zq[:, torch.from_numpy(sites).cuda()].cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), qo.reshape(len(probs), 2000).astype(np.float32).view(np.uint32))
