@@ -41,6 +41,7 @@ constexpr uint32_t kInitSweep = 0xFFFFFFFFu;
 // Layout of the context's device scratch: fixed slots, then a region for
 // per-call partial results.
 constexpr int64_t kDoneOffset = 0;       // done-chain counter
+constexpr int64_t kTicketOffset = 256;   // last-block ticket of the redo kernel with the control fused
 constexpr int64_t kWorkOffset = 1024;    // three work counters (profiling)
 constexpr int64_t kEnergyOffset = 2048;  // diag energy accumulator
 constexpr int64_t kSlopeOffset = 4096;   // diag slope input / output
@@ -589,6 +590,78 @@ __global__ __launch_bounds__(kBlock) void half_sweep_compact_kernel(const ChainD
     half_sweep_compact_body<DIAG, CR>(descs, states, bm, colour, sc, or_only, rd, flags);
 }
 
+__device__ void set_derived(ChainState &st, double q)
+{
+    st.inv_T = (float)(1.0 / st.T);
+    st.dscale = (float)(kTwoPi * q / st.a_cur);
+}
+
+// Algorithm 2 steps 5.2-5.5 (relaxation), 6 (equilibrium states) and the
+// e(T, L) runs for chain c, after both half-sweeps of a sweep.
+__device__ __forceinline__ void control_chain(const ChainDesc *__restrict__ descs, ChainState *__restrict__ states,
+                                              int c, const CtlParams &cp, unsigned int *done_count,
+                                              unsigned long long *work)
+{
+    // in place: a copy would put the ring buffer in scratch memory
+    ChainState &st = states[c];
+    if (st.phase == PH_DONE) return;
+    const ChainDesc d = descs[c];
+    // work counters: chain-sweeps, gap-site updates, useful bytes
+    atomicAdd(&work[0], 1ull);
+    atomicAdd(&work[1], (unsigned long long)d.P);
+    atomicAdd(&work[2], (unsigned long long)(cp.angle_bytes * ((int64_t)d.nx * d.ny + d.P)));
+    const uint32_t t = st.sweep;
+    const unsigned long long acc = st.acc, efx = st.e_fx;
+    st.acc = 0ull;
+    st.e_fx = 0ull;
+    // 1 + e = (H + N_GP) / N_GP with H + N_GP = sum over bonds of (1 - cos)
+    const double ope = (double)efx * cp.e_unit / (double)d.ngp;
+    if (st.phase == PH_RELAX) {
+        const double A = (double)acc / (double)d.P;
+        if (A < cp.a_targ) st.a_relax = 1.0 + (double)(t + 1u) / cp.k_a;
+        st.ring[t % (uint32_t)cp.n_fit] = ope;
+        if (t >= (uint32_t)cp.n_fit && t % (uint32_t)cp.n_f == 0u) st.k = ring_slope(st.ring, t, cp.n_fit, cp.w);
+        st.A_last = A;
+        const uint32_t tn = t + 1u;
+        st.sweep = tn;
+        bool stop;
+        if (cp.fixed_relax >= 0) stop = tn >= (uint32_t)cp.fixed_relax;
+        else stop = !(st.k < 0.0 && (int64_t)tn <= (int64_t)cp.i_max);
+        st.a_cur = st.a_relax;
+        if (stop) {
+            st.relax_sweeps = (int32_t)tn;
+            st.not_converged = (cp.fixed_relax < 0 && st.k < 0.0) ? 1 : 0;
+            st.eq_left = cp.K;
+            st.phase = cp.K > 0 ? PH_EQ : PH_DONE;
+            st.a_cur = cp.eq_a_mode ? st.a_relax : 1.0;
+            st.inv_k = 1.0f;
+            st.inv_km1 = 0.0f;
+            st.inv_k_d = 1.0;
+            st.inv_km1_d = 0.0;
+        }
+    } else if (st.phase == PH_EQ) {
+        st.sweep = t + 1u;
+        if (--st.eq_left <= 0) {
+            st.phase = PH_DONE;
+        } else {
+            const int k = cp.K - st.eq_left + 1;  // the next sweep's state number
+            st.inv_k = 1.0f / (float)k;
+            st.inv_km1 = 1.0f / (float)(k - 1);
+            st.inv_k_d = 1.0 / (double)k;
+            st.inv_km1_d = 1.0 / (double)(k - 1);
+        }
+    } else {  // PH_TABLE
+        const double A = (double)acc / (double)d.P;
+        if (A < cp.a_targ) st.a_relax = 1.0 + (double)(t + 1u) / cp.k_a;
+        st.a_cur = st.a_relax;
+        if ((int64_t)t >= (int64_t)cp.burn) st.e_sum += ope;
+        st.sweep = t + 1u;
+        if ((int64_t)t + 1 >= (int64_t)cp.burn + cp.meas) st.phase = PH_DONE;
+    }
+    set_derived(st, cp.q);
+    if (st.phase == PH_DONE) atomicAdd(done_count, 1u);
+}
+
 // The deferred double-precision updates of one half-sweep (block shape
 // `rows`, `compact`): each flagged site is redone by update_site_d from the
 // inputs the sweep saw (it left the site unchanged), with the same random
@@ -597,14 +670,26 @@ __global__ __launch_bounds__(kBlock) void half_sweep_compact_kernel(const ChainD
 // blocks) at a time; its lanes split over (flagged block, mask word), 64 /
 // words blocks per pass, and a lane redoes the sites of its mask word.  The
 // bits are cleared on the way, so the buffers are zero again for the next
-// half-sweep.
+// half-sweep.  With `ctl` set (after the colour-1 half-sweep) the last block
+// to finish also runs the per-sweep control of all n_all chains, which saves
+// the control kernel's launch; it finds out that it is last from the ticket
+// counter, which it resets.
+struct FusedControl {
+    CtlParams cp;
+    unsigned int *ticket;  // zero before the first launch; the last block resets it
+    unsigned int *done_count;
+    unsigned long long *work;
+    int32_t n_all;
+    int32_t on;
+};
+
 template <bool DIAG>
 __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__restrict__ descs,
                                                            ChainState *__restrict__ states,
                                                            BlockMap bm,
                                                            int64_t total_blocks, int rows, int compact, int colour,
                                                            SweepConsts sc, int or_only, Redo rd,
-                                                           uint8_t *__restrict__ flags)
+                                                           uint8_t *__restrict__ flags, FusedControl ctl)
 {
     const int words = compact ? kCompactSites / 32 : 2 * kBlock / 32;  // 32 or 16
     const int per = 64 / words;                                         // blocks per pass
@@ -682,6 +767,19 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
             }
         }
     }
+    if (!ctl.on) return;
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(ctl.ticket, 1u) == gridDim.x - 1u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // the other blocks' counts and energies are visible
+    for (int c = (int)threadIdx.x; c < ctl.n_all; c += (int)blockDim.x)
+        control_chain(descs, states, c, ctl.cp, ctl.done_count, ctl.work);
+    if (threadIdx.x == 0) *ctl.ticket = 0u;
 }
 
 // The double-precision sweep: the layout of half_sweep_body (a thread per
@@ -792,77 +890,12 @@ __global__ __launch_bounds__(kBlock) void half_sweep_fp64_kernel(const ChainDesc
     }
 }
 
-__device__ void set_derived(ChainState &st, double q)
-{
-    st.inv_T = (float)(1.0 / st.T);
-    st.dscale = (float)(kTwoPi * q / st.a_cur);
-}
-
-// Algorithm 2 steps 5.2-5.5 (relaxation), 6 (equilibrium states) and the
-// e(T, L) runs, one thread per chain, after both half-sweeps of a sweep.
+// control_chain for every chain, one thread per chain.
 __global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *__restrict__ states, int n,
                                CtlParams cp, unsigned int *done_count, unsigned long long *work)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    ChainState st = states[c];
-    if (st.phase == PH_DONE) return;
-    const ChainDesc d = descs[c];
-    // work counters: chain-sweeps, gap-site updates, useful bytes
-    atomicAdd(&work[0], 1ull);
-    atomicAdd(&work[1], (unsigned long long)d.P);
-    atomicAdd(&work[2], (unsigned long long)(cp.angle_bytes * ((int64_t)d.nx * d.ny + d.P)));
-    const uint32_t t = st.sweep;
-    const unsigned long long acc = st.acc, efx = st.e_fx;
-    st.acc = 0ull;
-    st.e_fx = 0ull;
-    // 1 + e = (H + N_GP) / N_GP with H + N_GP = sum over bonds of (1 - cos)
-    const double ope = (double)efx * cp.e_unit / (double)d.ngp;
-    if (st.phase == PH_RELAX) {
-        const double A = (double)acc / (double)d.P;
-        if (A < cp.a_targ) st.a_relax = 1.0 + (double)(t + 1u) / cp.k_a;
-        st.ring[t % (uint32_t)cp.n_fit] = ope;
-        if (t >= (uint32_t)cp.n_fit && t % (uint32_t)cp.n_f == 0u) st.k = ring_slope(st.ring, t, cp.n_fit, cp.w);
-        st.A_last = A;
-        const uint32_t tn = t + 1u;
-        st.sweep = tn;
-        bool stop;
-        if (cp.fixed_relax >= 0) stop = tn >= (uint32_t)cp.fixed_relax;
-        else stop = !(st.k < 0.0 && (int64_t)tn <= (int64_t)cp.i_max);
-        st.a_cur = st.a_relax;
-        if (stop) {
-            st.relax_sweeps = (int32_t)tn;
-            st.not_converged = (cp.fixed_relax < 0 && st.k < 0.0) ? 1 : 0;
-            st.eq_left = cp.K;
-            st.phase = cp.K > 0 ? PH_EQ : PH_DONE;
-            st.a_cur = cp.eq_a_mode ? st.a_relax : 1.0;
-            st.inv_k = 1.0f;
-            st.inv_km1 = 0.0f;
-            st.inv_k_d = 1.0;
-            st.inv_km1_d = 0.0;
-        }
-    } else if (st.phase == PH_EQ) {
-        st.sweep = t + 1u;
-        if (--st.eq_left <= 0) {
-            st.phase = PH_DONE;
-        } else {
-            const int k = cp.K - st.eq_left + 1;  // the next sweep's state number
-            st.inv_k = 1.0f / (float)k;
-            st.inv_km1 = 1.0f / (float)(k - 1);
-            st.inv_k_d = 1.0 / (double)k;
-            st.inv_km1_d = 1.0 / (double)(k - 1);
-        }
-    } else {  // PH_TABLE
-        const double A = (double)acc / (double)d.P;
-        if (A < cp.a_targ) st.a_relax = 1.0 + (double)(t + 1u) / cp.k_a;
-        st.a_cur = st.a_relax;
-        if ((int64_t)t >= (int64_t)cp.burn) st.e_sum += ope;
-        st.sweep = t + 1u;
-        if ((int64_t)t + 1 >= (int64_t)cp.burn + cp.meas) st.phase = PH_DONE;
-    }
-    set_derived(st, cp.q);
-    states[c] = st;
-    if (st.phase == PH_DONE) atomicAdd(done_count, 1u);
+    if (c < n) control_chain(descs, states, c, cp, done_count, work);
 }
 
 // 1 for every chain that is done, else 0 (for rebuilding the launch list).
@@ -1555,13 +1588,9 @@ CtlParams make_ctl(const mpr_params *p)
 SweepConsts make_sc(double q, uint64_t seed)
 {
     SweepConsts sc;
-    sc.q = (float)q;
-    sc.two_pi_q = (float)(kTwoPi * q);
     sc.q64 = q;
     sc.seed_lo = (uint32_t)seed;
     sc.seed_hi = (uint32_t)(seed >> 32);
-    sc.half = q == 0.5 ? 1 : 0;
-    sc.pad = 0;
     return sc;
 }
 
@@ -1615,14 +1644,17 @@ void launch_half_compact(hipStream_t st, const ChainSet &cs, int v, int colour, 
 // The deferred double-precision updates after a half-sweep in shape v.
 template <bool DIAG>
 void launch_redo(hipStream_t st, const ChainSet &cs, int v, int colour, const SweepConsts &sc, int or_only,
-                 uint8_t *flags)
+                 uint8_t *flags, const FusedControl *ctl = nullptr)
 {
+    FusedControl fc;
+    if (ctl) fc = *ctl;
+    else std::memset(&fc, 0, sizeof fc);
     // a wave per bitmap word, at most 16384 waves
     const int64_t nw = (cs.total_blocks[v] + 31) / 32;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 3) / 4, 4096));
     hipLaunchKernelGGL((redo_fp64_kernel<DIAG>), dim3(grid), dim3(kBlock), 0, st, cs.d_desc, cs.d_state,
                        block_map(cs, v), cs.total_blocks[v], kShapes[v].rows,
-                       kShapes[v].compact ? 1 : 0, colour, sc, or_only, cs.redo, flags);
+                       kShapes[v].compact ? 1 : 0, colour, sc, or_only, cs.redo, flags, fc);
 }
 
 template <bool DIAG, int ROWS>
@@ -1647,8 +1679,10 @@ void launch_half_fp64(hipStream_t st, const ChainSet &cs, int v, int colour, con
 }
 
 // One half-sweep of every chain in shape v (the e(T, L) runs and the
-// double-precision chains use the plain shapes only).
-void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colour, const SweepConsts &sc)
+// double-precision chains use the plain shapes only); `ctl` (single
+// precision only) makes the redo kernel run the per-sweep control as well.
+void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colour, const SweepConsts &sc,
+                 const FusedControl *ctl = nullptr)
 {
     if (cs.fp64) {
         launch_half_fp64<false>(st, cs, v, colour, sc, 0, nullptr);
@@ -1669,7 +1703,7 @@ void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colo
             default: launch_half_rows<8>(st, cs, v, table, colour, sc); break;
         }
     }
-    launch_redo<false>(st, cs, v, colour, sc, 0, nullptr);
+    launch_redo<false>(st, cs, v, colour, sc, 0, nullptr, ctl);
 }
 
 // Builds the launch list of a chain set from the chains in `active`: block
@@ -1705,8 +1739,10 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
 {
     const int n = (int)cs.desc.size();
     unsigned int *d_done = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kDoneOffset);
+    unsigned int *d_ticket = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kTicketOffset);
     unsigned long long *d_work = reinterpret_cast<unsigned long long *>((char *)ctx->scratch + kWorkOffset);
     HIP_TRY(ctx, hipMemsetAsync(d_done, 0, sizeof(unsigned int), stream));
+    HIP_TRY(ctx, hipMemsetAsync(d_ticket, 0, sizeof(unsigned int), stream));
     unsigned int already = 0;
     for (const auto &s : cs.state)
         if (s.phase == PH_DONE) ++already;
@@ -1722,16 +1758,29 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     HIP_TRY(ctx, hipEventRecord(ctx->ev_in, stream));
     HIP_TRY(ctx, hipStreamWaitEvent(st, ctx->ev_in, 0));
 
+    // the control runs at the end of the colour-1 redo kernel unless
+    // something must run between them (the state record) or there is no
+    // redo kernel (double-precision chains)
+    const bool fuse = !cs.fp64 && !cs.states_out;
+    FusedControl fc;
+    std::memset(&fc, 0, sizeof fc);
+    fc.cp = cp;
+    fc.ticket = d_ticket;
+    fc.done_count = d_done;
+    fc.work = d_work;
+    fc.n_all = n;
+    fc.on = 1;
     auto sweeps = [&](int v, int count) {
         for (int i = 0; i < count; ++i) {
             launch_half(st, cs, v, table, 0, sc);
-            launch_half(st, cs, v, table, 1, sc);
+            launch_half(st, cs, v, table, 1, sc, fuse ? &fc : nullptr);
             if (cs.states_out && cs.n_active > 0)
                 hipLaunchKernelGGL(record_states_kernel, dim3((unsigned)(cs.n_active * kRecordSegs)), dim3(kBlock), 0,
                                    st, cs.d_desc, cs.d_state, cs.d_offset, cs.d_ids, kRecordSegs, cs.K,
                                    cs.fp64 ? 1 : 0, cs.states_n_total, cs.states_out);
-            hipLaunchKernelGGL(control_kernel, dim3(cblocks), dim3(64), 0, st, cs.d_desc, cs.d_state, n, cp, d_done,
-                               d_work);
+            if (!fuse)
+                hipLaunchKernelGGL(control_kernel, dim3(cblocks), dim3(64), 0, st, cs.d_desc, cs.d_state, n, cp,
+                                   d_done, d_work);
         }
     };
     int64_t done_sweeps = 0;

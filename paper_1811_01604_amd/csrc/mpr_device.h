@@ -105,12 +105,8 @@ __device__ __forceinline__ float mark_fixed(float a) { return __uint_as_float(__
 
 // Sweep parameters shared by a launch.
 struct SweepConsts {
-    float q;          // coupling exponent
-    float two_pi_q;   // period of q*phi
-    double q64;
-    uint32_t seed_lo, seed_hi;
-    int32_t half;     // q == 1/2: single-precision fast path
-    int32_t pad;
+    double q64;                 // coupling exponent (the single-precision kernels assume 1/2)
+    uint32_t seed_lo, seed_hi;  // Philox key
 };
 
 // ------------------------------------------------- double-precision path
@@ -320,19 +316,7 @@ typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) v2f gv2f;
 __device__ __forceinline__ float gld(const float *p) { return *(const gfloat *)p; }
-__device__ __forceinline__ float2 gld2(const float *p)
-{
-    const v2f v = *(const gv2f *)p;
-    return make_float2(v.x, v.y);
-}
 __device__ __forceinline__ void gst(float *p, float v) { *(gfloat *)p = v; }
-__device__ __forceinline__ void gst2(float *p, float2 v)
-{
-    v2f w;
-    w.x = v.x;
-    w.y = v.y;
-    *(gv2f *)p = w;
-}
 
 // The same through a uniform base pointer and a 32-bit element index, so
 // that the address is the base plus a zero-extended 32-bit byte offset (the
