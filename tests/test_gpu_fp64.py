@@ -268,3 +268,31 @@ def test_fp64_batch_matches_single_and_rejects_compact_shape(ctx):
                      np.array([0.1]), bad, torch.empty(1 << 20, dtype=torch.uint8, device="cuda"),
                      torch.zeros(64, device="cuda"))
     assert e.value.code == mpr.MPR_ERR_ARG
+
+
+def test_affine_change_of_the_data_transforms_the_prediction(ctx):
+    """z -> a z + b leaves the angles unchanged up to rounding (equation
+    map), so the prediction becomes a z_hat + b; with double-precision chains
+    the rounding of the transformed inputs does not send the chains apart."""
+    im = synth.workload_l64()
+    shape = im.z.shape
+    imgs = mpr.images([shape])
+    mk = dev(im.mask, torch.uint8)
+    out = []
+    for a, b in ((1.0, 0.0), (3.0, 7.0), (0.25, -40.0)):
+        z32 = (a * im.z + b).astype(np.float32)
+        z = dev(z32, torch.float32)
+        phi = torch.zeros_like(z)
+        zz = ctx.map_to_angles(imgs, z, mk, phi)
+        prm = mpr.default_params(R=2, K=5, fixed_relax=20, seed=3, fp64=1)
+        ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+        ps, zh = torch.zeros_like(z), torch.zeros_like(z)
+        ctx.simulate(imgs, phi, mk, np.array([0.1]), prm, ws, ps)
+        ctx.predict(imgs, z, mk, ps, zz, 10, zh)
+        out.append((a, b, zh.cpu().numpy().astype(np.float64), z32))
+    _, _, ref, _ = out[0]
+    g = im.mask == 0
+    for a, b, zh, z32 in out[1:]:
+        assert np.array_equal(zh[~g], z32[~g].astype(np.float64))
+        err = np.max(np.abs((zh[g] - b) / a - ref[g]))
+        assert err <= 1e-3, (a, b, err)  # float rounding of the transformed data and outputs
