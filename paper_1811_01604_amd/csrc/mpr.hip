@@ -1110,6 +1110,69 @@ __global__ void holdout_error_kernel(int64_t n, const float *__restrict__ z, con
     }
 }
 
+// Sorts v[0..N-1] ascending with Batcher's odd-even merge sort, a fixed
+// network of compare-exchanges: with N a compile-time constant and every loop
+// unrolled, all indices are constants, so v stays in registers.
+template <int N>
+__device__ __forceinline__ void odd_even_merge_sort(float (&v)[N])
+{
+#pragma unroll
+    for (int p = 1; p < N; p <<= 1)
+#pragma unroll
+        for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+            for (int j = k % p; j + k < N; j += 2 * k)
+#pragma unroll
+                for (int i = 0; i < k; ++i)
+                    if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        const float a = v[i + j], b = v[i + j + k];
+                        v[i + j] = fminf(a, b);
+                        v[i + j + k] = fmaxf(a, b);
+                    }
+}
+
+// quantile_kernel for M <= N states per site with the sort in registers (a
+// thread per site; states beyond M are +inf and sort last); the order
+// statistics at the runtime positions are picked by unrolled selects.
+template <int N>
+__global__ __launch_bounds__(kBlock) void quantile_net_kernel(const ImgDev *__restrict__ imgs,
+                                                              const double *__restrict__ zmm,
+                                                              const double *__restrict__ probs, int nq,
+                                                              const float *__restrict__ z,
+                                                              const uint8_t *__restrict__ sampled,
+                                                              const float *__restrict__ st, int M, int64_t n_total,
+                                                              float *__restrict__ out)
+{
+#pragma clang fp contract(off)
+    const ImgDev im = imgs[blockIdx.y];
+    const int64_t n = (int64_t)im.nx * im.ny;
+    const double lo = zmm[2 * blockIdx.y], hi = zmm[2 * blockIdx.y + 1];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = im.offset + i;
+        if (sampled[k]) {
+            for (int q = 0; q < nq; ++q) out[q * n_total + k] = z[k];
+            continue;
+        }
+        float v[N];
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = m < M ? st[(int64_t)m * n_total + k] : INFINITY;
+        odd_even_merge_sort<N>(v);
+        for (int q = 0; q < nq; ++q) {
+            const double h = (double)(M - 1) * probs[q];
+            const int a = (int)floor(h);
+            float va = v[0], vb = v[0];
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                va = m == a ? v[m] : va;
+                vb = m == a + 1 ? v[m] : vb;
+            }
+            const double phi_p = a >= M - 1 ? (double)va : (double)va + (h - (double)a) * ((double)vb - (double)va);
+            const double tt = phi_p / kTwoPi;
+            out[q * n_total + k] = (float)(lo * (1.0 - tt) + hi * tt);
+        }
+    }
+}
+
 // Spread of the prediction: the standard deviation over the M realizations
 // of z = G^{-1}(phi), which is (z_max - z_min) / (2 pi) times that of phi,
 // sqrt(m2 / (M - 1)); zero at sampled sites and for M = 1.
@@ -2465,9 +2528,27 @@ int32_t mpr_quantiles(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const floa
     HIP_TRY(ctx, hipMemcpyAsync(d_img, hi.data(), n * sizeof(ImgDev), hipMemcpyHostToDevice, stream));
     HIP_TRY(ctx, hipMemcpyAsync(d_zmm, zmin_zmax, n * 16, hipMemcpyHostToDevice, stream));
     HIP_TRY(ctx, hipMemcpyAsync(d_probs, probs, nq * 8, hipMemcpyHostToDevice, stream));
-    const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((maxn + kQuantileLanes - 1) / kQuantileLanes, 8192));
-    hipLaunchKernelGGL(quantile_kernel, dim3(gx, n), dim3(kQuantileLanes), 0, stream, d_img, d_zmm, d_probs, nq, z,
-                       sampled, phi_states, M, n_total, z_q);
+    if (M <= 128) {
+        // sort in registers: a network of the smallest power-of-two size >= M
+        const int gb = blocks_for(maxn, 8192);
+        if (M <= 16)
+            hipLaunchKernelGGL(quantile_net_kernel<16>, dim3(gb, n), dim3(kBlock), 0, stream, d_img, d_zmm, d_probs,
+                               nq, z, sampled, phi_states, M, n_total, z_q);
+        else if (M <= 32)
+            hipLaunchKernelGGL(quantile_net_kernel<32>, dim3(gb, n), dim3(kBlock), 0, stream, d_img, d_zmm, d_probs,
+                               nq, z, sampled, phi_states, M, n_total, z_q);
+        else if (M <= 64)
+            hipLaunchKernelGGL(quantile_net_kernel<64>, dim3(gb, n), dim3(kBlock), 0, stream, d_img, d_zmm, d_probs,
+                               nq, z, sampled, phi_states, M, n_total, z_q);
+        else
+            hipLaunchKernelGGL(quantile_net_kernel<128>, dim3(gb, n), dim3(kBlock), 0, stream, d_img, d_zmm, d_probs,
+                               nq, z, sampled, phi_states, M, n_total, z_q);
+    } else {
+        const int gx =
+            (int)std::max<int64_t>(1, std::min<int64_t>((maxn + kQuantileLanes - 1) / kQuantileLanes, 8192));
+        hipLaunchKernelGGL(quantile_kernel, dim3(gx, n), dim3(kQuantileLanes), 0, stream, d_img, d_zmm, d_probs, nq,
+                           z, sampled, phi_states, M, n_total, z_q);
+    }
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipStreamSynchronize(stream));
     return MPR_OK;
