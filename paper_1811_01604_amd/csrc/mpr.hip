@@ -430,9 +430,12 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
     // positions in the two lists: pair j = 0 of every thread first, then j = 1
     const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t pre[2][2];
+    // (the list of sampled sites is only wanted for the sweep's energy: the
+    // block-uniform test skips its half of the work in the other half-sweeps)
+    uint32_t pre[2][2] = {{0u, 0u}, {0u, 0u}};
 #pragma unroll
-    for (int L = 0; L < 2; ++L)
+    for (int L = 0; L < 2; ++L) {
+        if (L == 1 && !want_energy) continue;
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const uint64_t b0 = __ballot(L ? fix[j][0] : gap[j][0]);
@@ -440,10 +443,12 @@ __device__ __forceinline__ void half_sweep_compact_body(const ChainDesc *__restr
             pre[L][j] = (uint32_t)(__popcll(b0 & below) + __popcll(b1 & below));
             if (lane == 0) wave_count[L][j][wid] = (uint32_t)(__popcll(b0) + __popcll(b1));
         }
+    }
     __syncthreads();
-    int n_list[2];
+    int n_list[2] = {0, 0};
 #pragma unroll
     for (int L = 0; L < 2; ++L) {
+        if (L == 1 && !want_energy) continue;
         uint32_t base0 = 0u, base1 = 0u, tot0 = 0u, tot1 = 0u;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
