@@ -72,6 +72,24 @@ def measured_traffic(workload: str, chains: int, key: str):
     return (t.get("by_tile") or {}).get(key, {}).get("traffic_bytes_per_launch")
 
 
+def measured_valu(workload: str, chains: int, key: str, launch_ms: float):
+    """VALU wave-instructions per launch from the committed counter runs
+    (SQ_INSTS_VALU) and the issue rate they give at the live launch time and
+    the 2.4 GHz peak clock, per SIMD (1024 of them); None as for traffic."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_sha() or t.get("workload") != workload or t.get("chains") != chains:
+        return None
+    v = (t.get("by_tile") or {}).get(key, {}).get("valu_insts_per_launch")
+    if not v:
+        return None
+    return {"wave_insts_per_launch": v, "issue_per_simd_cycle": v / (1024 * launch_ms * 1e-3 * 2.4e9),
+            "fp32_fma_issue_limit_per_simd_cycle": 0.25}
+
+
 def cpu_baseline(im, T: float, sweeps: int, seed: int) -> dict:
     """The oracle's sweep on one chain of the same workload (bounded sample),
     at a fixed temperature T (an input: the work per sweep does not depend
@@ -251,6 +269,8 @@ def main():
             "tile_rows": prof["last_tile"] & 0xFF,
             "launch_ms": launch_ms, "useful_bytes_per_launch": bytes_per_launch,
             "sweep_kernel_time_share": prof["sweep_kernel_ms"] * 1e-3 / dt,
+            "valu": (None if args.fp64 else
+                     measured_valu(args.workload, prm.R, str(prof["last_tile"]), launch_ms)),
         },
     }
     if args.warm_seeds > 0:
