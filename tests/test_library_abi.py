@@ -73,3 +73,25 @@ def test_calls_without_device_fail_cleanly():
     assert rc == mpr.MPR_ERR_HIP and not h
     assert lib.mpr_map_to_angles(None, None, 0, None, None, None, None, None) == mpr.MPR_ERR_ARG
     assert lib.mpr_last_error(None) == b"null context"
+
+
+def test_size_limits_and_q_validation():
+    """Host checks: at most 2^31 sites per image, and a single-precision
+    half-grid (rows of ceil(nx/2) rounded up to 64 floats) below 4 GiB, the
+    limit of the sweep kernels' 32-bit offsets; q in (0, 1/2], below 1/2
+    only with double-precision chains."""
+    lib = mpr.load()
+    p = mpr.default_params(R=1, K=1)
+    ws = lambda shape, prm: lib.mpr_workspace_size(mpr.images([shape]), 1, C.byref(prm))
+    assert ws((46000, 46000), p) > 0          # 46000 x 23040 x 4 B = 3.95 GiB
+    assert ws((46340, 46340), p) < 0          # 46340 x 23232 x 4 B = 4.01 GiB
+    assert ws((65536, 32768), p) < 0          # 2^31 sites, half-grid 4 GiB
+    assert ws((46341, 46341), p) < 0          # more than 2^31 sites
+    for q, fp64, ok in ((0.5, 0, True), (0.5, 1, True), (0.3, 1, True), (0.3, 0, False), (0.0, 1, False),
+                        (0.6, 1, False)):
+        prm = mpr.default_params(R=1, K=1, q=q, fp64=fp64)
+        assert (ws((64, 64), prm) > 0) == ok, (q, fp64)
+    qs = (C.c_double * 2)(0.25, 0.5)
+    assert lib.mpr_select_q_workspace_size(mpr.images([(64, 64)]), C.byref(p), qs, 2) > 0
+    bad = (C.c_double * 2)(0.25, 0.75)
+    assert lib.mpr_select_q_workspace_size(mpr.images([(64, 64)]), C.byref(p), bad, 2) < 0
