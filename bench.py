@@ -285,13 +285,17 @@ def main():
             ws_summary = warmstart.evaluate(ctx, model, size=2048, seeds=args.warm_seeds)
             out["warm_start"] = {
                 "workload": "Gaussian Matern nu=1.5 kappa=0.05 N(50,10); 2048x2048; 50% random and 50% cloud "
-                            "gaps; M=100 as one chain (R=1, K=100); T_hat shared; time = network inference "
-                            "(warm) + simulate + predict",
+                            "gaps; M=100 as one chain (R=1, K=100; layout_100x1: 100 chains of one state); "
+                            "T_hat shared; time = network inference (warm) + simulate + predict",
                 "network": f"8-block residual CNN, 32 channels, bf16 MFMA; trained on {info['samples']} "
                            f"library simulations of {info['size']}^2 images",
                 **ws_summary,
                 "inference_roofline": cnn,
             }
+            # the same comparison with the M = 100 realizations as 100 chains of one
+            # state each, where the relaxation is the whole cost of a fill
+            out["warm_start"]["layout_100x1"] = warmstart.evaluate(ctx, model, size=2048, seeds=args.warm_seeds,
+                                                                   R=100, K=1)
         else:
             out["warm_start"] = None
     ctx.close()

@@ -229,17 +229,19 @@ def _eval_field(args):
     return z.astype(np.float32), m
 
 
-def evaluate(ctx, model, size: int = 2048, seeds: int = 8, K: int = 100, workers: int = 8):
-    """Plain random start vs warm start on fresh images: sweeps to stop,
-    time to fill (warm start inference + simulate + predict, T_hat shared)
-    and MAE of the prediction at the gaps, for random and cloud masks."""
+def evaluate(ctx, model, size: int = 2048, seeds: int = 8, K: int = 100, workers: int = 8, R: int = 1):
+    """Plain random start vs warm start on fresh images: sweeps to stop
+    (mean over the R chains), time to fill (warm start inference + simulate
+    + predict, T_hat shared) and MAE of the prediction at the gaps, for
+    random and cloud masks; M = R K realizations (every chain starts from
+    the same warm angles)."""
     import torch
     import paper_1811_01604_amd as mpr
     cases = [(kind, size, s) for kind in ("random", "cloud") for s in range(seeds)]
     with mp.get_context("spawn").Pool(workers) as pool:
         data = pool.map(_eval_field, cases)
     imgs = mpr.images([(size, size)])
-    prm = mpr.default_params(R=1, K=K, seed=4242)
+    prm = mpr.default_params(R=R, K=K, seed=4242)
     out = {}
     for (kind, _, s), (z, m) in zip(cases, data):
         zd = torch.from_numpy(z).cuda()
@@ -258,15 +260,15 @@ def evaluate(ctx, model, size: int = 2048, seeds: int = 8, K: int = 100, workers
             if mode == "warm":
                 model(phi.view(1, size, size), md.view(1, size, size), init.view(1, size, size))
             st = ctx.simulate(imgs, phi, md, T, prm, ws, ps, phi_init=init)
-            ctx.predict(imgs, zd, md, ps, zz, K, zh)
+            ctx.predict(imgs, zd, md, ps, zz, R * K, zh)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             mae = float(np.mean(np.abs(zh.cpu().numpy()[g] - z[g])))
-            res[mode] = {"sweeps": st[0]["relax_sweeps"], "time_s": dt, "mae": mae}
+            res[mode] = {"sweeps": float(np.mean([c["relax_sweeps"] for c in st])), "time_s": dt, "mae": mae}
         out.setdefault(kind, []).append(res)
-        log(f"  {kind} seed {s}: plain {res['plain']['sweeps']} sweeps {res['plain']['time_s'] * 1e3:.0f} ms "
-            f"MAE {res['plain']['mae']:.4f} | warm {res['warm']['sweeps']} sweeps {res['warm']['time_s'] * 1e3:.0f} ms "
-            f"MAE {res['warm']['mae']:.4f}")
+        log(f"  ({R},{K}) {kind} seed {s}: plain {res['plain']['sweeps']:.1f} sweeps "
+            f"{res['plain']['time_s'] * 1e3:.0f} ms MAE {res['plain']['mae']:.4f} | warm {res['warm']['sweeps']:.1f} "
+            f"sweeps {res['warm']['time_s'] * 1e3:.0f} ms MAE {res['warm']['mae']:.4f}")
     summary = {}
     for kind, rows in out.items():
         f = lambda mode, key: float(np.mean([r[mode][key] for r in rows]))
