@@ -123,3 +123,39 @@ def test_recorded_states_of_double_precision_chains(ctx):
     assert np.max(np.abs(st[:, g].astype(np.float64) - sto[:, g])) <= 1e-6
     qo = oracle.quantiles(im.z.astype(np.float32).astype(np.float64), im.mask, sto, PROBS, zz)
     assert np.max(np.abs(zq[:, g] - qo[:, g])) <= 1e-4
+
+
+def test_recorded_states_of_a_ragged_batch_equal_the_images_alone(ctx):
+    """Two images of different sizes in one call: each image's recorded
+    states (and quantiles) equal those of the image run alone, bit for bit."""
+    shapes = [(64, 64), (24, 40)]
+    zs = [synth.workload_l64().z, synth.matern_field(40, 24, 1.5, 0.1, 50, 10, 5)]
+    ms = [synth.workload_l64().mask, synth.random_mask(40, 24, 0.4, 6)]
+    prm = mpr.default_params(R=2, K=3, fixed_relax=4, seed=19)
+    T = np.array([0.15, 0.05])
+    M = prm.R * prm.K
+
+    def run(sel):
+        imgs = mpr.images([shapes[i] for i in sel], ids=list(sel))
+        z = dev(np.concatenate([zs[i].astype(np.float32).ravel() for i in sel]))
+        mk = dev(np.concatenate([ms[i].ravel() for i in sel]), torch.uint8)
+        phi = torch.zeros_like(z)
+        zz = ctx.map_to_angles(imgs, z, mk, phi)
+        ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+        ps = torch.zeros_like(z)
+        st = torch.zeros((M, z.numel()), device="cuda")
+        ctx.simulate(imgs, phi, mk, T[list(sel)], prm, ws, ps, phi_states=st)
+        zq = torch.zeros((len(PROBS), z.numel()), device="cuda")
+        ctx.quantiles(imgs, z, mk, st, M, PROBS, zz, zq)
+        out, off = {}, 0
+        for i in sel:
+            n = shapes[i][0] * shapes[i][1]
+            out[i] = (st[:, off:off + n].cpu().numpy(), zq[:, off:off + n].cpu().numpy())
+            off += n
+        return out
+
+    both = run([0, 1])
+    for i in range(2):
+        alone = run([i])[i]
+        assert np.array_equal(both[i][0].view(np.uint32), alone[0].view(np.uint32)), i
+        assert np.array_equal(both[i][1].view(np.uint32), alone[1].view(np.uint32)), i
