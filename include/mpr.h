@@ -102,7 +102,11 @@ typedef struct {
                              only (tile_rows without MPR_TILE_COMPACT).  Inputs and
                              outputs stay float; sums are taken in double and rounded
                              once.  The temperature estimate is unaffected. */
-    int32_t reserved2;    /* 0 */
+    int32_t table_side_cap;  /* 0: the e(T, L) table of an nx x ny image is built on nx x ny;
+                                >= 2: on min(nx, cap) x min(ny, cap), so that the images larger
+                                than cap share one table (e(T, L) approaches its L -> infinity
+                                limit with an error of order 1/L; it trades that bias for a
+                                table cost bounded by cap^2 sites).  1 is invalid. */
 } mpr_params;
 
 /* Per chain results of mpr_simulate (R per image, image-major). */

@@ -55,7 +55,7 @@ class Params(C.Structure):
         ("eq_a_mode", C.c_int32), ("table_nT", C.c_int32), ("table_burn", C.c_int32),
         ("table_meas", C.c_int32), ("tile_rows", C.c_int32), ("table_T_lo", C.c_double),
         ("table_T_hi", C.c_double), ("seed", C.c_uint64), ("sweeps_per_launch", C.c_int32),
-        ("spread", C.c_int32), ("fp64", C.c_int32), ("reserved2", C.c_int32),
+        ("spread", C.c_int32), ("fp64", C.c_int32), ("table_side_cap", C.c_int32),
     ]
 
 

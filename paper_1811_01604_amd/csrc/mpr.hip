@@ -1536,7 +1536,8 @@ bool valid_params(const mpr_params *p)
            p->table_T_lo > 0.0 && p->table_T_hi > p->table_T_lo &&
            (p->tile_rows == 0 || shape_of(p->tile_rows) >= 0) &&
            p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096 && (p->spread == 0 || p->spread == 1) &&
-           (p->fp64 == 0 || (p->fp64 == 1 && (p->tile_rows & MPR_TILE_COMPACT) == 0));
+           (p->fp64 == 0 || (p->fp64 == 1 && (p->tile_rows & MPR_TILE_COMPACT) == 0)) &&
+           (p->table_side_cap == 0 || p->table_side_cap >= 2);
 }
 
 bool valid_images(const mpr_image *imgs, int n)
@@ -1571,11 +1572,23 @@ int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
 // kernels are written for q = 1/2).
 int table_angle_bytes(const mpr_params *p) { return p->q == 0.5 ? 4 : 8; }
 
+// Grid on which the e(T, L) table of an image is built: its own, or each
+// side capped at table_side_cap.
+struct TableGrid {
+    int32_t nx, ny;
+};
+TableGrid table_grid(const mpr_image &im, const mpr_params *p)
+{
+    const int32_t c = p->table_side_cap;
+    return c > 0 ? TableGrid{std::min(im.nx, c), std::min(im.ny, c)} : TableGrid{im.nx, im.ny};
+}
+
 int64_t table_bytes(const mpr_image *imgs, int n, const mpr_params *p)
 {
     int64_t best = 0;
     for (int i = 0; i < n; ++i) {
-        const int64_t hg = round_up(half_grid_bytes(imgs[i].nx, imgs[i].ny, table_angle_bytes(p)), 256);
+        const TableGrid t = table_grid(imgs[i], p);
+        const int64_t hg = round_up(half_grid_bytes(t.nx, t.ny, table_angle_bytes(p)), 256);
         best = std::max(best, (int64_t)p->table_nT * 2 * hg);
     }
     const int64_t chains = p->table_nT;
@@ -1584,7 +1597,10 @@ int64_t table_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     best += round_up((int64_t)n * kMapBlocks * 16, 256);
     best += round_up(kNumShapes * (chains + 1) * 8, 256) + round_up(chains * 4 + 4, 256);
     int64_t rb = 0;
-    for (int i = 0; i < n; ++i) rb = std::max(rb, redo_bytes(imgs[i].nx, imgs[i].ny, chains));
+    for (int i = 0; i < n; ++i) {
+        const TableGrid t = table_grid(imgs[i], p);
+        rb = std::max(rb, redo_bytes(t.nx, t.ny, chains));
+    }
     return best + rb;
 }
 
@@ -2168,6 +2184,7 @@ void mpr_default_params(mpr_params *p)
     p->sweeps_per_launch = 0;
     p->spread = 0;
     p->fp64 = 0;
+    p->table_side_cap = 0;
 }
 
 int64_t mpr_workspace_size(const mpr_image *imgs, int32_t n, const mpr_params *p)
@@ -2278,22 +2295,24 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
             e_s[b] = s / (double)c;
         }
     }
-    // e(T, L) tables per grid size (equation ene), cached.  The missing ones
-    // are built together: the table chains of as many grid sizes as the
-    // workspace holds run as one ragged chain set (a table does not depend on
-    // the chains run beside it: its random numbers are keyed by temperature
-    // index and site).
+    // e(T, L) tables per table grid size (equation ene), cached.  The
+    // missing ones are built together: the table chains of as many grid
+    // sizes as the workspace holds run as one ragged chain set (a table does
+    // not depend on the chains run beside it: its random numbers are keyed by
+    // temperature index and site).
     const std::vector<double> Tg = temperature_grid(p);
+    std::vector<TableGrid> tg(n);
+    for (int b = 0; b < n; ++b) tg[b] = table_grid(imgs[b], p);
     auto key_of = [&](int b) {
-        return std::make_tuple(imgs[b].nx, imgs[b].ny, p->q, p->table_nT, p->table_T_lo, p->table_T_hi,
-                               p->table_burn, p->table_meas, p->a_targ, p->k_a, p->seed);
+        return std::make_tuple(tg[b].nx, tg[b].ny, p->q, p->table_nT, p->table_T_lo, p->table_T_hi, p->table_burn,
+                               p->table_meas, p->a_targ, p->k_a, p->seed);
     };
-    std::vector<int> missing;  // first image of each grid size without a table
+    std::vector<int> missing;  // first image of each table grid size without a table
     for (int b = 0; b < n; ++b) {
         if (ctx->tables.count(key_of(b))) continue;
-        if ((int64_t)imgs[b].nx * imgs[b].ny < 2) return fail(ctx, MPR_ERR_DEGENERATE, "image %d: one site", b);
+        if ((int64_t)tg[b].nx * tg[b].ny < 2) return fail(ctx, MPR_ERR_DEGENERATE, "image %d: one site", b);
         bool dup = false;
-        for (int m : missing) dup = dup || (imgs[m].nx == imgs[b].nx && imgs[m].ny == imgs[b].ny);
+        for (int m : missing) dup = dup || (tg[m].nx == tg[b].nx && tg[m].ny == tg[b].ny);
         if (!dup) missing.push_back(b);
     }
     const int nT = p->table_nT;
@@ -2301,8 +2320,8 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
     // offsets and redo buffers), as upload_chains carves them
     const int teb = table_angle_bytes(p);
     auto table_chain_bytes = [&](int b) {
-        const int64_t hg = round_up(half_grid_bytes(imgs[b].nx, imgs[b].ny, teb), 256);
-        return nT * 2 * hg + redo_bytes(imgs[b].nx, imgs[b].ny, nT) +
+        const int64_t hg = round_up(half_grid_bytes(tg[b].nx, tg[b].ny, teb), 256);
+        return nT * 2 * hg + redo_bytes(tg[b].nx, tg[b].ny, nT) +
                nT * (int64_t)(sizeof(ChainDesc) + sizeof(ChainState) + 8 + (kNumShapes + 1) * 8) + 4096;
     };
     for (size_t first = 0; first < missing.size();) {
@@ -2317,16 +2336,17 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
         int64_t maxn = 0;
         for (size_t g = first; g <= last; ++g) {
             const int b = missing[g];
-            maxn = std::max(maxn, (int64_t)imgs[b].nx * imgs[b].ny);
+            const int64_t tnx = tg[b].nx, tny = tg[b].ny;
+            maxn = std::max(maxn, tnx * tny);
             for (int k = 0; k < nT; ++k) {
                 ChainDesc d;
                 std::memset(&d, 0, sizeof d);
-                if (!carve_chain(cv, d, imgs[b].nx, imgs[b].ny, false, false, teb))
+                if (!carve_chain(cv, d, (int)tnx, (int)tny, false, false, teb))
                     return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
                 d.image_id = kTableStream;
                 d.chain = (uint32_t)k;
-                d.P = (int64_t)imgs[b].nx * imgs[b].ny;
-                d.ngp = (int64_t)imgs[b].nx * (imgs[b].ny - 1) + (int64_t)imgs[b].ny * (imgs[b].nx - 1);
+                d.P = tnx * tny;
+                d.ngp = tnx * (tny - 1) + tny * (tnx - 1);
                 cs.desc.push_back(d);
                 cs.state.push_back(fresh_state(Tg[k], PH_TABLE));
                 cs.offset.push_back(0);

@@ -463,12 +463,11 @@ __device__ __forceinline__ SiteOutD update_site_d(double phi, double n0, double 
     const double A = (double)nnb - A_small;
     SiteOutD o;
     o.e_before = A_small;
-    double th1 = th, p1 = phi;
+    double p1 = phi;
     bool kept = true;
     if (nnb > 0 && (A != 0.0 || B != 0.0)) {
         const double raw1 = fma(2.0, atan2_fp64(-B, A), th);
         if (raw1 >= 0.0 && raw1 < period) {
-            th1 = raw1;
             p1 = raw1 / q;
             kept = false;
         }

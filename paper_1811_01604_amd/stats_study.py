@@ -1,4 +1,5 @@
-"""Cost of the realizations' statistics and of the choice of q, on one GPU.
+"""Cost of the realizations' statistics, of the choice of q and of the
+temperature tables, on one GPU.
 
   - Quantiles: the L=4096 workload (lognormal, 66% random gaps) with its 100
     chains' final states recorded (6.7 GB), then mpr_quantiles for the 5%,
@@ -95,6 +96,39 @@ def q_choice(ctx, mpr, synth, torch, nu, kappa, seed):
             "select_s (tables cached)": t_sel, "gap_MAE_at_q_best": out["chosen"], "gap_MAE_at_half": out["half"]}
 
 
+def table_cap(mpr, synth, torch):
+    im = synth.workload_l4096("random")
+    imgs = mpr.images([im.z.shape])
+    z = torch.from_numpy(im.z.astype(np.float32)).cuda()
+    mk = torch.from_numpy(im.mask).cuda()
+    g = im.mask == 0
+    rows = []
+    for cap in (256, 1024, 0):
+        ctx = mpr.Context(0)
+        prm = mpr.default_params(R=100, K=1, table_side_cap=cap)
+        ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+        phi, ps, zh = torch.zeros_like(z), torch.zeros_like(z), torch.zeros_like(z)
+        zz = ctx.map_to_angles(imgs, z, mk, phi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e_s, T, cl = ctx.estimate_temperature(imgs, phi, mk, prm, ws)
+        torch.cuda.synchronize()
+        t_tab = time.perf_counter() - t0
+        ctx.simulate(imgs, phi, mk, T, prm, ws, ps)
+        ctx.predict(imgs, z, mk, ps, zz, 100, zh)
+        mae = float(np.mean(np.abs(zh.cpu().numpy()[g] - im.z.astype(np.float32)[g])))
+        rows.append({"table_grid": "4096x4096" if cap == 0 else f"{cap}x{cap}", "build_s": t_tab,
+                     "T_hat": float(T[0]), "clamped": bool(cl[0]), "gap_MAE": mae})
+        del ws
+        ctx.close()
+        log(f"table {rows[-1]['table_grid']}: built in {t_tab:.3f} s, T_hat {T[0]:.4e}, MAE {mae:.6f}")
+    full = rows[-1]["T_hat"]
+    for r in rows:
+        r["T_hat_over_full"] = r["T_hat"] / full
+    return {"measure": "table_side_cap", "workload": "4096x4096 lognormal, 66% random gaps, R=100, K=1",
+            "table": "32 temperatures on [1e-5, 10], 200 + 400 sweeps", "rows": rows}
+
+
 def main():
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
@@ -111,6 +145,7 @@ def main():
         log(f"select_q nu={nu}: q* {r['q_best']}, hold-out MAE {r['holdout_mae']}, gap MAE q* "
             f"{r['gap_MAE_at_q_best']:.4f} vs q=1/2 {r['gap_MAE_at_half']:.4f}, {r['select_s (tables cached)']:.3f} s")
     ctx.close()
+    print(json.dumps(table_cap(mpr, synth, torch)), flush=True)
 
 
 if __name__ == "__main__":

@@ -299,6 +299,48 @@ def test_temperature_estimate_matches_oracle(ctx):
     assert abs(out["T"] / T_o - 1.0) < 0.03
 
 
+def test_temperature_table_on_capped_grid(ctx):  # ctx: skips without a GPU; the test uses fresh contexts
+    """table_side_cap = 64: the e(T, L) table of a 150 x 200 image (and of a
+    90 x 100 one in the same call, which shares it) is the one of a 64 x 64
+    grid.  A later uncapped call on a 64 x 64 image in the same context, which
+    finds that table cached, gives the T_hat bit for bit that a fresh context
+    gives after building the 64 x 64 table itself; the big image's T_hat is
+    the oracle's inversion of the 64 x 64 table within 3%."""
+    tab = dict(table_nT=12, table_T_lo=0.01, table_T_hi=2.0, table_burn=100, table_meas=300, K=1)
+    big = [synth.matern_field(200, 150, 0.5, 0.2, 50.0, 10.0, 31), synth.matern_field(100, 90, 0.5, 0.2, 50.0, 10.0, 32)]
+    bmask = [synth.random_mask(200, 150, 0.5, 33), synth.random_mask(100, 90, 0.5, 34)]
+    small = synth.workload_l64()
+
+    def estimate(c, zs, ms, prm):
+        imgs = mpr.images([z.shape for z in zs])
+        z = dev(np.concatenate([a.astype(np.float32).ravel() for a in zs]))
+        mk = dev(np.concatenate([a.ravel() for a in ms]), torch.uint8)
+        phi = torch.zeros_like(z)
+        ctx_zz = c.map_to_angles(imgs, z, mk, phi)
+        ws = torch.empty(c.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+        return c.estimate_temperature(imgs, phi, mk, prm, ws), ctx_zz
+
+    a, b = mpr.Context(0), mpr.Context(0)
+    try:
+        (e_big, T_big, cl_big), _ = estimate(a, big, bmask, mpr.default_params(table_side_cap=64, **tab))
+        (_, T_a, _), _ = estimate(a, [small.z], [small.mask], mpr.default_params(**tab))
+        (_, T_b, _), _ = estimate(b, [small.z], [small.mask], mpr.default_params(**tab))
+    finally:
+        a.close()
+        b.close()
+    assert T_a[0] == T_b[0]
+    Tg = oracle.temperature_grid(12, 0.01, 2.0)
+    et = oracle.energy_table(64, 64, Tg, 100, 300, seed=mpr.default_params().seed)
+    for i in range(2):
+        po, _ = oracle.map_to_angles(big[i].astype(np.float32).astype(np.float64), bmask[i])
+        e_o, _ = oracle.sample_energy(po.astype(np.float32).astype(np.float64), bmask[i])
+        assert abs(e_big[i] - e_o) <= 1e-12
+        T_o, cl_o = oracle.invert_temperature(Tg, et, e_o)
+        say(f"image {i}: T_hat gpu {T_big[i]:.5f}, oracle (64 x 64 table) {T_o:.5f}")
+        assert not cl_big[i] and not cl_o
+        assert abs(T_big[i] / T_o - 1.0) < 0.03
+
+
 def test_simulate_free_running_short_chains(ctx):
     """After one sweep GPU and oracle agree per site; divergence grows afterwards."""
     im = synth.workload_l64()
