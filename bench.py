@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--K", type=int, default=1)
     ap.add_argument("--fixed-sweeps", type=int, default=-1,
                     help="relax exactly this many sweeps instead of the stopping rule")
-    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--cpu-sweeps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB plain copy first (calibrates HBM byte counters)")

@@ -1927,18 +1927,27 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     int spl = p->sweeps_per_launch > 0 ? p->sweeps_per_launch : poll_every;
     if (p->sweeps_per_launch <= 0 && sweep_ms > 0.0f && (float)spl * sweep_ms < 1.0f)
         spl = std::min(64, poll_every * (int)std::ceil(1.0f / ((float)poll_every * sweep_ms)));
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t ge = nullptr;
+    // the captured sweep group, released on every return path
+    struct Captured {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        void release()
+        {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            exec = nullptr;
+            graph = nullptr;
+        }
+        ~Captured() { release(); }
+    } cap;
+    hipGraphExec_t &ge = cap.exec;
     auto capture = [&]() {
-        if (ge) (void)hipGraphExecDestroy(ge);
-        if (graph) (void)hipGraphDestroy(graph);
-        ge = nullptr;
-        graph = nullptr;
+        cap.release();
         if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             sweeps(v, spl);
-            if (hipStreamEndCapture(st, &graph) != hipSuccess ||
-                hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0) != hipSuccess)
-                ge = nullptr;
+            if (hipStreamEndCapture(st, &cap.graph) != hipSuccess ||
+                hipGraphInstantiate(&cap.exec, cap.graph, nullptr, nullptr, 0) != hipSuccess)
+                cap.exec = nullptr;
         }
         (void)hipGetLastError();
     };
@@ -1976,8 +1985,7 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
         if (rc) break;
         capture();
     }
-    if (ge) (void)hipGraphExecDestroy(ge);
-    if (graph) (void)hipGraphDestroy(graph);
+    cap.release();
     if (rc) return rc;
     HIP_TRY(ctx, hipEventRecord(ctx->ev_out, st));
     HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev_out, 0));

@@ -231,6 +231,30 @@ def test_fp64_stopping_rule_and_spread_match_oracle(ctx):
     assert np.all(ps[~g] == 0) and np.all(m2[~g] == 0)
 
 
+@pytest.mark.parametrize("fp64", [1, 0])
+def test_relaxation_only_runs_zero_states(ctx, fp64):
+    """K = 0: the chains relax to the stopping rule and record no state, so
+    the sums are zero everywhere (sampled sites included) and the spread too.
+    Double-precision chains stop at the oracle's sweeps with its final a;
+    single-precision ones relax for as many sweeps as with K = 10, the same
+    chains before their equilibrium phase."""
+    im, phi32 = l64_angles()
+    T = 0.15
+    prm = mpr.default_params(R=2, K=0, seed=5, fp64=fp64)
+    ps, m2, st = simulate_gpu(ctx, phi32, im.mask, T, prm)
+    assert not ps.any() and not m2.any()
+    if fp64:
+        _, sto, _, _ = oracle.simulate(phi32.astype(np.float64), im.mask, T, oracle.default_params(R=2, K=0, seed=5))
+        ref = [(s["relax_sweeps"], s["a_final"]) for s in sto]
+    else:
+        _, _, st10 = simulate_gpu(ctx, phi32, im.mask, T, mpr.default_params(R=2, K=10, seed=5, spread=1))
+        ref = [(s["relax_sweeps"], s["a_final"]) for s in st10]
+    got = [(s["relax_sweeps"], s["a_final"]) for s in st]
+    say(f"  K=0 fp64={fp64}: {got} against {ref}")
+    assert got == ref
+    assert all(s["relax_sweeps"] > 0 and not s["not_converged"] for s in st)
+
+
 def test_fp64_batch_matches_single_and_rejects_compact_shape(ctx):
     """A ragged batch in double precision gives each image the result it
     gets alone; compacted block shapes are refused for double chains."""
