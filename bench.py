@@ -111,6 +111,42 @@ def cpu_baseline(im, T: float, sweeps: int, seed: int) -> dict:
                       f"single thread, {dt:.1f} s"}
 
 
+def cpu_baseline_scaling(sizes, fractions=(0.33, 0.66), T: float = 0.09, full_fill_max: int = 1024):
+    """The oracle on the lattice-size study's images (Whittle-Matern nu=0.5,
+    kappa=0.2, N(50, 10), a fraction p removed at random; the images the GPU
+    study fills), one JSON line per (L, p).  Up to L = full_fill_max a whole
+    fill as the GPU study times it: R = 1 chain, the stopping rule, K = 100
+    states, at a fixed temperature T (the GPU study's T_hat for these images
+    lies in 0.08-0.09; the e(T, L) table is excluded on both sides).  Larger
+    L: one sweep, timed, as the per-sweep cost."""
+    import numpy as np
+    import oracle
+    import synth
+    for L in sizes:
+        for p in fractions:
+            im = synth.workload_table2(L, p, 0)
+            z = im.z.astype(np.float32).astype(np.float64)
+            phi, _ = oracle.map_to_angles(z, im.mask)
+            P = int((im.mask == 0).sum())
+            row = {"L": L, "p_removed": p, "gap_sites": P, "T": T, "cores": 1, "kind": "oracle"}
+            if L <= full_fill_max:
+                prm = oracle.default_params(R=1, K=100, seed=7000)
+                t0 = time.perf_counter()
+                _, st, _, _ = oracle.simulate(phi, im.mask, T, prm)
+                dt = time.perf_counter() - t0
+                sweeps = st[0]["relax_sweeps"] + 1 + 100
+                row.update(fill_s=dt, relax_sweeps=st[0]["relax_sweeps"], sweeps=sweeps,
+                           site_updates_per_s=sweeps * P / dt)
+            else:
+                prm = oracle.default_params(R=1, K=1, fixed_relax=0, seed=7000)
+                t0 = time.perf_counter()
+                oracle.simulate(phi, im.mask, T, prm)
+                dt = time.perf_counter() - t0
+                row.update(fill_s=None, sweep_s=dt, site_updates_per_s=P / dt)
+            log(f"oracle L={L} p={p}: {json.dumps(row)}")
+            print(json.dumps(row), flush=True)
+
+
 def cnn_inference(ctx, model, size: int = 2048, reps: int = 5) -> dict:
     """Event-timed warm-start network inference on one size x size image.
     Algorithmic HBM bytes per pixel: each of the 18 convolutions reads its
@@ -155,6 +191,10 @@ def main():
                     help="relax exactly this many sweeps instead of the stopping rule")
     ap.add_argument("--cpu-sweeps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-scaling", default="",
+                    help="only the CPU baseline of the lattice-size study: time the oracle on its images "
+                         "at these comma-separated sizes L (p = 0.33 and 0.66), one JSON line per case, "
+                         "and exit (no GPU work)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB plain copy first (calibrates HBM byte counters)")
     ap.add_argument("--tile", default="auto",
@@ -165,6 +205,9 @@ def main():
     ap.add_argument("--warm-seeds", type=int, default=8,
                     help="images per mask type for the warm-start comparison at L=2048 (0 = skip)")
     args = ap.parse_args()
+    if args.cpu_scaling:
+        cpu_baseline_scaling([int(v) for v in args.cpu_scaling.split(",")])
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sweep has no multi-GPU path "
               f"in this library.", file=sys.stderr)

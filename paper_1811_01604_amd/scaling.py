@@ -13,7 +13,10 @@ a fraction p of sites removed at random.  For each (L, p):
 
     python -m paper_1811_01604_amd.scaling [--sizes 32,64,...] [--fractions ...]
 
-prints one JSON line per case and a markdown table at the end.
+prints one JSON line per case and a markdown table at the end.  Defaults: L
+from 32 to 8192 at p = 0.33 and 0.66, and p from 0.05 to 0.95 at L = 2048.
+The CPU side of the comparison (the oracle on the same images) is timed by
+the benchmark script's --cpu-scaling option.
 """
 from __future__ import annotations
 
@@ -82,9 +85,9 @@ def run_case(ctx, L: int, p: float, rep: int = 0, K: int = 100) -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--sizes", default="32,64,128,256,512,1024,2048,4096")
+    ap.add_argument("--sizes", default="32,64,128,256,512,1024,2048,4096,8192")
     ap.add_argument("--size-fractions", default="0.33,0.66")
-    ap.add_argument("--fraction-size", type=int, default=1024)
+    ap.add_argument("--fraction-size", type=int, default=2048)
     ap.add_argument("--fractions", default="0.05,0.2,0.35,0.5,0.65,0.8,0.95")
     args = ap.parse_args()
     import paper_1811_01604_amd as mpr
