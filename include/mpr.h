@@ -20,6 +20,10 @@
  *    pointers are host memory.  The caller owns every buffer, including the
  *    device workspace sized by mpr_workspace_size.  The library does not
  *    allocate device memory in these calls (the mpr_diag_* calls excepted).
+ *    Every call checks its (dev) pointers with hipPointerGetAttributes and
+ *    refuses one that is not device memory of the context's device (or
+ *    managed memory) with MPR_ERR_ARG; it cannot check their extent, which
+ *    is the caller's to size as each call states.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is
  *    enqueued on it and every call synchronises the stream before it
  *    returns.

@@ -169,12 +169,10 @@ def images(shapes, ids=None):
     return arr
 
 
-def _ptr(t):
-    if t is None:
-        return None
-    if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
-    return C.c_void_p(t.data_ptr())
+def sites_of(imgs) -> int:
+    """Length of the packed per-site buffers of a batch: the end of its
+    furthest image."""
+    return max(int(im.offset) + int(im.nx) * int(im.ny) for im in imgs)
 
 
 def _stream(stream):
@@ -210,52 +208,105 @@ class Context:
         if rc != MPR_OK:
             raise MprError(rc, self.lib.mpr_last_error(self._h).decode())
 
+    def _t(self, t, name, dtype=None, numel=0, optional=False, nbytes=0):
+        """Device pointer of tensor t after checking it: on this context's
+        GPU, contiguous, of dtype (None: any, for workspaces) and holding at
+        least numel elements (and nbytes bytes), the extent the call reads or
+        writes.  A host tensor or a short buffer would otherwise reach a
+        kernel."""
+        import torch
+        if t is None:
+            if optional:
+                return None
+            raise ValueError(f"{name}: a tensor is required")
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.device.index != self.device:
+            raise ValueError(f"{name}: must be a tensor on cuda:{self.device}")
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: must be contiguous")
+        if t.numel() < numel:
+            raise ValueError(f"{name}: {t.numel()} elements, the call needs {numel}")
+        if t.numel() * t.element_size() < nbytes:
+            raise ValueError(f"{name}: {t.numel() * t.element_size()} bytes, the call needs {nbytes}")
+        return C.c_void_p(t.data_ptr())
+
+    def _cnn_sizes(self, n, h, w):
+        return n * h * w, int(self.lib.mpr_cnn_param_count()), int(self.lib.mpr_cnn_packed_bytes())
+
     # -------------------------------------------------------------- calls
     def workspace_size(self, imgs, params) -> int:
         return int(self.lib.mpr_workspace_size(imgs, len(imgs), C.byref(params)))
 
     def map_to_angles(self, imgs, z, sampled, phi, stream=None) -> np.ndarray:
+        import torch
+        n = sites_of(imgs)
         zz = np.zeros(2 * len(imgs))
-        self._check(self.lib.mpr_map_to_angles(self._h, imgs, len(imgs), _ptr(z), _ptr(sampled), _ptr(phi),
+        self._check(self.lib.mpr_map_to_angles(self._h, imgs, len(imgs), self._t(z, "z", torch.float32, n),
+                                               self._t(sampled, "sampled", torch.uint8, n),
+                                               self._t(phi, "phi", torch.float32, n),
                                                zz.ctypes.data_as(C.c_void_p), _stream(stream)))
         return zz
 
     def estimate_temperature(self, imgs, phi, sampled, params, ws, stream=None):
+        import torch
         n = len(imgs)
+        ns = sites_of(imgs)
         e_s, T = np.zeros(n), np.zeros(n)
         cl = np.zeros(n, dtype=np.int32)
         self._check(self.lib.mpr_estimate_temperature(
-            self._h, imgs, n, _ptr(phi), _ptr(sampled), C.byref(params), _ptr(ws), ws.numel() * ws.element_size(),
+            self._h, imgs, n, self._t(phi, "phi", torch.float32, ns), self._t(sampled, "sampled", torch.uint8, ns),
+            C.byref(params), self._t(ws, "ws"), ws.numel() * ws.element_size(),
             e_s.ctypes.data_as(C.c_void_p), T.ctypes.data_as(C.c_void_p), cl.ctypes.data_as(C.c_void_p),
             _stream(stream)))
         return e_s, T, cl
 
     def simulate(self, imgs, phi, sampled, T_hat, params, ws, phi_sum, phi_init=None, stream=None, phi_m2=None,
                  phi_states=None):
+        import torch
         n = len(imgs)
+        ns = sites_of(imgs)
         T = np.ascontiguousarray(T_hat, dtype=np.float64)
+        if T.size < n:
+            raise ValueError(f"T_hat: {T.size} values for {n} images")
         st = (ChainStats * (n * params.R))()
+        f32 = torch.float32
         self._check(self.lib.mpr_simulate(
-            self._h, imgs, n, _ptr(phi), _ptr(sampled), T.ctypes.data_as(C.c_void_p), C.byref(params),
-            _ptr(phi_init), _ptr(ws), ws.numel() * ws.element_size(), _ptr(phi_sum), _ptr(phi_m2),
-            _ptr(phi_states), st,
+            self._h, imgs, n, self._t(phi, "phi", f32, ns), self._t(sampled, "sampled", torch.uint8, ns),
+            T.ctypes.data_as(C.c_void_p), C.byref(params), self._t(phi_init, "phi_init", f32, ns, optional=True),
+            self._t(ws, "ws"), ws.numel() * ws.element_size(), self._t(phi_sum, "phi_sum", f32, ns),
+            self._t(phi_m2, "phi_m2", f32, ns, optional=True),
+            self._t(phi_states, "phi_states", f32, max(0, params.R * params.K) * ns, optional=True), st,
             _stream(stream)))
         return [dict(relax_sweeps=s.relax_sweeps, not_converged=s.not_converged, a_final=s.a_final,
                      A_last=s.A_last, k_last=s.k_last) for s in st]
 
     def predict(self, imgs, z, sampled, phi_sum, zmin_zmax, M, z_hat, stream=None):
+        import torch
+        ns = sites_of(imgs)
         zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)
-        self._check(self.lib.mpr_predict(self._h, imgs, len(imgs), _ptr(z), _ptr(sampled), _ptr(phi_sum),
-                                         zz.ctypes.data_as(C.c_void_p), M, _ptr(z_hat), _stream(stream)))
+        if zz.size < 2 * len(imgs):
+            raise ValueError("zmin_zmax: two values per image")
+        self._check(self.lib.mpr_predict(self._h, imgs, len(imgs), self._t(z, "z", torch.float32, ns),
+                                         self._t(sampled, "sampled", torch.uint8, ns),
+                                         self._t(phi_sum, "phi_sum", torch.float32, ns),
+                                         zz.ctypes.data_as(C.c_void_p), M, self._t(z_hat, "z_hat", torch.float32, ns),
+                                         _stream(stream)))
 
     def quantiles(self, imgs, z, sampled, phi_states, M, probs, zmin_zmax, z_q, stream=None):
         """Per-site quantiles (probs) of the M recorded states, back-transformed;
         z_q holds len(probs) rows of the packed sites."""
+        import torch
+        ns = sites_of(imgs)
         pr = np.ascontiguousarray(probs, dtype=np.float64)
         zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)
-        self._check(self.lib.mpr_quantiles(self._h, imgs, len(imgs), _ptr(z), _ptr(sampled), _ptr(phi_states), M,
+        if zz.size < 2 * len(imgs):
+            raise ValueError("zmin_zmax: two values per image")
+        self._check(self.lib.mpr_quantiles(self._h, imgs, len(imgs), self._t(z, "z", torch.float32, ns),
+                                           self._t(sampled, "sampled", torch.uint8, ns),
+                                           self._t(phi_states, "phi_states", torch.float32, max(M, 0) * ns), M,
                                            pr.ctypes.data_as(C.c_void_p), pr.size, zz.ctypes.data_as(C.c_void_p),
-                                           _ptr(z_q), _stream(stream)))
+                                           self._t(z_q, "z_q", torch.float32, pr.size * ns), _stream(stream)))
 
     def select_q_workspace_size(self, img, params, q_grid) -> int:
         qg = np.ascontiguousarray(q_grid, dtype=np.float64)
@@ -265,20 +316,29 @@ class Context:
     def select_q(self, img, z, sampled, params, q_grid, holdout, ws, stream=None):
         """Hold-out choice of q for one image (img: a one-image array from
         images()); returns (q_best, validation MAE per q, T_hat per q)."""
+        import torch
+        ns = sites_of(img[:1])
         qg = np.ascontiguousarray(q_grid, dtype=np.float64)
         mae = np.zeros(qg.size)
         T = np.zeros(qg.size)
         qb = C.c_double()
-        self._check(self.lib.mpr_select_q(self._h, img, _ptr(z), _ptr(sampled), C.byref(params),
-                                          qg.ctypes.data_as(C.c_void_p), qg.size, holdout, _ptr(ws),
+        self._check(self.lib.mpr_select_q(self._h, img, self._t(z, "z", torch.float32, ns),
+                                          self._t(sampled, "sampled", torch.uint8, ns), C.byref(params),
+                                          qg.ctypes.data_as(C.c_void_p), qg.size, holdout, self._t(ws, "ws"),
                                           ws.numel() * ws.element_size(), mae.ctypes.data_as(C.c_void_p),
                                           T.ctypes.data_as(C.c_void_p), C.byref(qb), _stream(stream)))
         return qb.value, mae, T
 
     def spread(self, imgs, sampled, phi_m2, zmin_zmax, M, z_std, stream=None):
+        import torch
+        ns = sites_of(imgs)
         zz = np.ascontiguousarray(zmin_zmax, dtype=np.float64)
-        self._check(self.lib.mpr_spread(self._h, imgs, len(imgs), _ptr(sampled), _ptr(phi_m2),
-                                        zz.ctypes.data_as(C.c_void_p), M, _ptr(z_std), _stream(stream)))
+        if zz.size < 2 * len(imgs):
+            raise ValueError("zmin_zmax: two values per image")
+        self._check(self.lib.mpr_spread(self._h, imgs, len(imgs), self._t(sampled, "sampled", torch.uint8, ns),
+                                        self._t(phi_m2, "phi_m2", torch.float32, ns),
+                                        zz.ctypes.data_as(C.c_void_p), M, self._t(z_std, "z_std", torch.float32, ns),
+                                        _stream(stream)))
 
     # -------------------------------------------------------- warm start
     # Tensors: x, y, dy are (n, h, w, 32) bfloat16; phi, sampled (n, h, w);
@@ -293,50 +353,91 @@ class Context:
         return int(self.lib.mpr_cnn_workspace_size(n, h, w, 1 if training else 0))
 
     def cnn_pack(self, params, packed, stream=None):
-        self._check(self.lib.mpr_cnn_pack(self._h, _ptr(params), _ptr(packed), _stream(stream)))
+        import torch
+        _, pc, pb = self._cnn_sizes(0, 0, 0)
+        self._check(self.lib.mpr_cnn_pack(self._h, self._t(params, "params", torch.float32, pc),
+                                          self._t(packed, "packed", nbytes=pb), _stream(stream)))
 
     def cnn_encode(self, phi, sampled, x, stream=None):
+        import torch
         n, h, w = phi.shape
-        self._check(self.lib.mpr_cnn_encode(self._h, n, h, w, _ptr(phi), _ptr(sampled), _ptr(x), _stream(stream)))
+        px, _, _ = self._cnn_sizes(n, h, w)
+        self._check(self.lib.mpr_cnn_encode(self._h, n, h, w, self._t(phi, "phi", torch.float32, px),
+                                            self._t(sampled, "sampled", torch.uint8, px),
+                                            self._t(x, "x", torch.bfloat16, 32 * px), _stream(stream)))
 
     def cnn_forward(self, params, packed, x, ws, y, training=False, stream=None):
+        import torch
         n, h, w, _ = x.shape
-        self._check(self.lib.mpr_cnn_forward(self._h, n, h, w, _ptr(params), _ptr(packed), _ptr(x), _ptr(ws),
-                                             ws.numel() * ws.element_size(), 1 if training else 0, _ptr(y),
-                                             _stream(stream)))
+        px, pc, pb = self._cnn_sizes(n, h, w)
+        self._check(self.lib.mpr_cnn_forward(self._h, n, h, w, self._t(params, "params", torch.float32, pc),
+                                             self._t(packed, "packed", nbytes=pb),
+                                             self._t(x, "x", torch.bfloat16, 32 * px), self._t(ws, "ws"),
+                                             ws.numel() * ws.element_size(), 1 if training else 0,
+                                             self._t(y, "y", torch.bfloat16, 32 * px), _stream(stream)))
 
     def cnn_loss(self, y, target, sampled, n_gaps, dy, ws, stream=None) -> float:
+        import torch
         n, h, w, _ = y.shape
+        px, _, _ = self._cnn_sizes(n, h, w)
         out = C.c_double()
-        self._check(self.lib.mpr_cnn_loss(self._h, n, h, w, _ptr(y), _ptr(target), _ptr(sampled), int(n_gaps),
-                                          _ptr(dy), _ptr(ws), ws.numel() * ws.element_size(), C.byref(out),
-                                          _stream(stream)))
+        self._check(self.lib.mpr_cnn_loss(self._h, n, h, w, self._t(y, "y", torch.bfloat16, 32 * px),
+                                          self._t(target, "target", torch.float32, 2 * px),
+                                          self._t(sampled, "sampled", torch.uint8, px), int(n_gaps),
+                                          self._t(dy, "dy", torch.bfloat16, 32 * px), self._t(ws, "ws"),
+                                          ws.numel() * ws.element_size(), C.byref(out), _stream(stream)))
         return out.value
 
     def cnn_backward(self, params, packed, x, dy, ws, grads, stream=None):
+        import torch
         n, h, w, _ = x.shape
-        self._check(self.lib.mpr_cnn_backward(self._h, n, h, w, _ptr(params), _ptr(packed), _ptr(x), _ptr(dy),
-                                              _ptr(ws), ws.numel() * ws.element_size(), _ptr(grads),
-                                              _stream(stream)))
+        px, pc, pb = self._cnn_sizes(n, h, w)
+        self._check(self.lib.mpr_cnn_backward(self._h, n, h, w, self._t(params, "params", torch.float32, pc),
+                                              self._t(packed, "packed", nbytes=pb),
+                                              self._t(x, "x", torch.bfloat16, 32 * px),
+                                              self._t(dy, "dy", torch.bfloat16, 32 * px), self._t(ws, "ws"),
+                                              ws.numel() * ws.element_size(),
+                                              self._t(grads, "grads", torch.float32, pc), _stream(stream)))
 
     def cnn_opt_step(self, params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
-        self._check(self.lib.mpr_cnn_opt_step(self._h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(step),
-                                              lr, beta1, beta2, eps, _stream(stream)))
+        import torch
+        _, pc, _ = self._cnn_sizes(0, 0, 0)
+        f32 = torch.float32
+        self._check(self.lib.mpr_cnn_opt_step(self._h, self._t(params, "params", f32, pc),
+                                              self._t(grads, "grads", f32, pc), self._t(m, "m", f32, pc),
+                                              self._t(v, "v", f32, pc), int(step), lr, beta1, beta2, eps,
+                                              _stream(stream)))
 
     def cnn_decode(self, y, sampled, phi_init, stream=None):
+        import torch
         n, h, w, _ = y.shape
-        self._check(self.lib.mpr_cnn_decode(self._h, n, h, w, _ptr(y), _ptr(sampled), _ptr(phi_init),
-                                            _stream(stream)))
+        px, _, _ = self._cnn_sizes(n, h, w)
+        self._check(self.lib.mpr_cnn_decode(self._h, n, h, w, self._t(y, "y", torch.bfloat16, 32 * px),
+                                            self._t(sampled, "sampled", torch.uint8, px),
+                                            self._t(phi_init, "phi_init", torch.float32, px), _stream(stream)))
 
     def cnn_diag_conv(self, x, wpack, bias, out, add=None, ref=None, relu=False, stream=None):
+        import torch
         n, h, w, _ = x.shape
-        self._check(self.lib.mpr_cnn_diag_conv(self._h, n, h, w, _ptr(x), _ptr(wpack), _ptr(bias), _ptr(add),
-                                               _ptr(ref), 1 if relu else 0, _ptr(out), _stream(stream)))
+        px = n * h * w
+        bf = torch.bfloat16
+        self._check(self.lib.mpr_cnn_diag_conv(self._h, n, h, w, self._t(x, "x", bf, 32 * px),
+                                               self._t(wpack, "wpack", nbytes=9 * 32 * 32 * 2),
+                                               self._t(bias, "bias", torch.float32, 32, optional=True),
+                                               self._t(add, "add", bf, 32 * px, optional=True),
+                                               self._t(ref, "ref", bf, 32 * px, optional=True), 1 if relu else 0,
+                                               self._t(out, "out", bf, 32 * px), _stream(stream)))
 
     def cnn_diag_wgrad(self, x, gout, grads, ws, gref=None, stream=None):
+        import torch
         n, h, w, _ = x.shape
-        self._check(self.lib.mpr_cnn_diag_wgrad(self._h, n, h, w, _ptr(x), _ptr(gout), _ptr(gref), _ptr(grads),
-                                                _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+        px = n * h * w
+        bf = torch.bfloat16
+        self._check(self.lib.mpr_cnn_diag_wgrad(self._h, n, h, w, self._t(x, "x", bf, 32 * px),
+                                                self._t(gout, "gout", bf, 32 * px),
+                                                self._t(gref, "gref", bf, 32 * px, optional=True),
+                                                self._t(grads, "grads", torch.float32, 9 * 32 * 32 + 32),
+                                                self._t(ws, "ws"), ws.numel() * ws.element_size(), _stream(stream)))
 
     # ---------------------------------------------------------- profiling
     def profile_enable(self, on=True):
@@ -349,19 +450,23 @@ class Context:
 
     # -------------------------------------------------------- diagnostics
     def diag_philox(self, ctr, seed, out, stream=None):
-        self._check(self.lib.mpr_diag_philox(self._h, _ptr(ctr), seed, ctr.numel() // 4, _ptr(out),
-                                             _stream(stream)))
+        n = ctr.numel() // 4
+        self._check(self.lib.mpr_diag_philox(self._h, self._t(ctr, "ctr", nbytes=16 * n), seed, n,
+                                             self._t(out, "out", nbytes=16 * n), _stream(stream)))
 
     def diag_half_sweep(self, phi, sampled, colour, T, a, sweep, chain=0, stream_id=0, seed=3000, q=0.5,
                         mode=0, flags=None, stream=None, with_energy=False, tile=0):
         """One half-sweep in place; returns the accepted count (and the fused
         bond-energy sum H + N_GP when with_energy).  tile: block shape as
         Params.tile_rows (0 = default)."""
+        import torch
         ny, nx = phi.shape
         acc = C.c_int64()
         en = C.c_double()
-        self._check(self.lib.mpr_diag_half_sweep(self._h, nx, ny, _ptr(phi), _ptr(sampled), colour, T, a, q, seed,
-                                                 sweep, chain, stream_id, mode, int(tile), _ptr(flags),
+        self._check(self.lib.mpr_diag_half_sweep(self._h, nx, ny, self._t(phi, "phi", torch.float32, nx * ny),
+                                                 self._t(sampled, "sampled", torch.uint8, nx * ny), colour, T, a,
+                                                 q, seed, sweep, chain, stream_id, mode, int(tile),
+                                                 self._t(flags, "flags", torch.uint8, nx * ny, optional=True),
                                                  C.byref(acc), C.byref(en), _stream(stream)))
         return (acc.value, en.value) if with_energy else acc.value
 
@@ -374,19 +479,24 @@ class Context:
         ny, nx = phi.shape
         acc = C.c_int64()
         en = C.c_double()
-        self._check(self.lib.mpr_diag_half_sweep_fp64(self._h, nx, ny, _ptr(phi), _ptr(sampled), colour, T, a, q,
-                                                      seed, sweep, chain, stream_id, mode, int(tile), _ptr(flags),
+        self._check(self.lib.mpr_diag_half_sweep_fp64(self._h, nx, ny, self._t(phi, "phi", torch.float64, nx * ny),
+                                                      self._t(sampled, "sampled", torch.uint8, nx * ny), colour, T,
+                                                      a, q, seed, sweep, chain, stream_id, mode, int(tile),
+                                                      self._t(flags, "flags", torch.uint8, nx * ny, optional=True),
                                                       C.byref(acc), C.byref(en), _stream(stream)))
         return (acc.value, en.value) if with_energy else acc.value
 
     def diag_copy(self, src, dst, stream=None):
         n = src.numel() * src.element_size()
-        self._check(self.lib.mpr_diag_copy(self._h, _ptr(src), _ptr(dst), n, _stream(stream)))
+        self._check(self.lib.mpr_diag_copy(self._h, self._t(src, "src"), self._t(dst, "dst", nbytes=n), n,
+                                           _stream(stream)))
 
     def diag_energy(self, phi, q=0.5, stream=None) -> float:
+        import torch
         ny, nx = phi.shape
         out = C.c_double()
-        self._check(self.lib.mpr_diag_energy(self._h, nx, ny, _ptr(phi), q, C.byref(out), _stream(stream)))
+        self._check(self.lib.mpr_diag_energy(self._h, nx, ny, self._t(phi, "phi", torch.float32, nx * ny), q,
+                                             C.byref(out), _stream(stream)))
         return out.value
 
     def diag_sg_slope(self, e, degree=1) -> float:

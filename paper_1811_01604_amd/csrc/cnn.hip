@@ -19,7 +19,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mpr.h"
@@ -469,6 +471,9 @@ __global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, 
 // ===================================================================== host
 
 int mpr_set_error(mpr_ctx *ctx, int code, const char *msg);  // defined with the context
+// MPR_ERR_ARG unless every non-null pointer is device memory of the context's device
+int mpr_check_device(mpr_ctx *ctx, const char *call,
+                     std::initializer_list<std::pair<const char *, const void *>> ptrs);
 
 namespace {
 
@@ -598,6 +603,7 @@ int32_t mpr_cnn_pack(mpr_ctx *ctx, const float *params, void *packed, void *stre
 {
     if (!ctx) return MPR_ERR_ARG;
     if (!params || !packed) return cfail(ctx, MPR_ERR_ARG, "cnn_pack: null pointer");
+    if (int rc = mpr_check_device(ctx, "cnn_pack", {{"params", params}, {"packed", packed}})) return rc;
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(pack_kernel, dim3((NLAYER * WSZ + 255) / 256), dim3(256), 0, st, params, (bf16 *)packed);
     CHIP(ctx, hipGetLastError());
@@ -610,6 +616,7 @@ int32_t mpr_cnn_encode(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const floa
 {
     if (!ctx) return MPR_ERR_ARG;
     if (!shape_ok(n, h, w) || !phi || !sampled || !x) return cfail(ctx, MPR_ERR_ARG, "cnn_encode: invalid argument");
+    if (int rc = mpr_check_device(ctx, "cnn_encode", {{"phi", phi}, {"sampled", sampled}, {"x", x}})) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int64_t np = (int64_t)n * h * w;
     hipLaunchKernelGGL(encode_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, phi, sampled, np, 0.5f,
@@ -625,6 +632,9 @@ int32_t mpr_cnn_forward(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const flo
     if (!ctx) return MPR_ERR_ARG;
     if (!shape_ok(n, h, w) || !params || !packed || !x || !ws || !y)
         return cfail(ctx, MPR_ERR_ARG, "cnn_forward: invalid argument");
+    if (int rc = mpr_check_device(ctx, "cnn_forward",
+                                  {{"params", params}, {"packed", packed}, {"x", x}, {"workspace", ws}, {"y", y}}))
+        return rc;
     if (ws_bytes < mpr_cnn_workspace_size(n, h, w, training))
         return cfail(ctx, MPR_ERR_WORKSPACE, "cnn_forward: workspace too small");
     Acts A;
@@ -651,6 +661,9 @@ int32_t mpr_cnn_loss(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void *
     if (!ctx) return MPR_ERR_ARG;
     if (!shape_ok(n, h, w) || !y || !target || !sampled || !dy || !loss || !ws || n_gaps < 0)
         return cfail(ctx, MPR_ERR_ARG, "cnn_loss: invalid argument");
+    if (int rc = mpr_check_device(ctx, "cnn_loss",
+                                  {{"y", y}, {"target", target}, {"sampled", sampled}, {"dy", dy}, {"workspace", ws}}))
+        return rc;
     const int64_t np = (int64_t)n * h * w;
     const unsigned blocks = (unsigned)((np + 255) / 256);
     if (ws_bytes < (int64_t)blocks * 8) return cfail(ctx, MPR_ERR_WORKSPACE, "cnn_loss: workspace too small");
@@ -674,6 +687,10 @@ int32_t mpr_cnn_backward(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const fl
     if (!ctx) return MPR_ERR_ARG;
     if (!shape_ok(n, h, w) || !params || !packed || !x || !dy || !ws || !grads)
         return cfail(ctx, MPR_ERR_ARG, "cnn_backward: invalid argument");
+    if (int rc = mpr_check_device(ctx, "cnn_backward",
+                                  {{"params", params}, {"packed", packed}, {"x", x}, {"dy", dy}, {"workspace", ws},
+                                   {"grads", grads}}))
+        return rc;
     if (ws_bytes < mpr_cnn_workspace_size(n, h, w, 1))
         return cfail(ctx, MPR_ERR_WORKSPACE, "cnn_backward: workspace too small");
     Acts A;
@@ -705,6 +722,8 @@ int32_t mpr_cnn_opt_step(mpr_ctx *ctx, float *params, const float *grads, float 
 {
     if (!ctx) return MPR_ERR_ARG;
     if (!params || !grads || !m || !v || step < 1) return cfail(ctx, MPR_ERR_ARG, "cnn_opt_step: invalid argument");
+    if (int rc = mpr_check_device(ctx, "cnn_opt_step", {{"params", params}, {"grads", grads}, {"m", m}, {"v", v}}))
+        return rc;
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = mpr_cnn_param_count();
     const float c1 = (float)(1.0 - std::pow(beta1, (double)step));
@@ -721,6 +740,8 @@ int32_t mpr_cnn_decode(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void
 {
     if (!ctx) return MPR_ERR_ARG;
     if (!shape_ok(n, h, w) || !y || !sampled || !phi_init) return cfail(ctx, MPR_ERR_ARG, "cnn_decode: invalid argument");
+    if (int rc = mpr_check_device(ctx, "cnn_decode", {{"y", y}, {"sampled", sampled}, {"phi_init", phi_init}}))
+        return rc;
     hipStream_t st = (hipStream_t)stream;
     const int64_t np = (int64_t)n * h * w;
     hipLaunchKernelGGL(decode_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, (const bf16 *)y, sampled,
@@ -735,6 +756,9 @@ int32_t mpr_cnn_diag_conv(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const v
 {
     if (!ctx) return MPR_ERR_ARG;
     if (!shape_ok(n, h, w) || !in || !wpack || !out) return cfail(ctx, MPR_ERR_ARG, "cnn_diag_conv: invalid argument");
+    if (int rc = mpr_check_device(ctx, "cnn_diag_conv",
+                                  {{"in", in}, {"wpack", wpack}, {"bias", bias}, {"add", add}, {"ref", ref}, {"out", out}}))
+        return rc;
     hipStream_t st = (hipStream_t)stream;
     launch_conv(st, (const bf16 *)in, (const bf16 *)wpack, bias, (const bf16 *)add, (const bf16 *)ref, relu,
                 (bf16 *)out, n, h, w);
@@ -748,6 +772,9 @@ int32_t mpr_cnn_diag_wgrad(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const 
 {
     if (!ctx) return MPR_ERR_ARG;
     if (!shape_ok(n, h, w) || !in || !gout || !grads || !ws) return cfail(ctx, MPR_ERR_ARG, "cnn_diag_wgrad: invalid argument");
+    if (int rc = mpr_check_device(ctx, "cnn_diag_wgrad",
+                                  {{"in", in}, {"gout", gout}, {"gref", gref}, {"grads", grads}, {"workspace", ws}}))
+        return rc;
     if (ws_bytes < (int64_t)WG_BLOCKS * 4 * WG_PART * 4) return cfail(ctx, MPR_ERR_WORKSPACE, "cnn_diag_wgrad: workspace");
     hipStream_t st = (hipStream_t)stream;
     launch_wgrad(st, (const bf16 *)in, (const bf16 *)gout, (const bf16 *)gref, (float *)ws, grads, n, h, w);

@@ -21,9 +21,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "../../include/mpr.h"
@@ -1437,6 +1439,30 @@ int mpr_set_error(mpr_ctx *ctx, int code, const char *msg)
     return code;
 }
 
+// Checks the device pointers of a call (name, pointer; null ones are
+// skipped, the callers test the required ones first): each must be device
+// memory of the context's device, or managed memory.  A host pointer would
+// otherwise reach a kernel and fault the GPU.  Returns MPR_OK, or
+// MPR_ERR_ARG with an error text naming the argument.
+int mpr_check_device(mpr_ctx *ctx, const char *call,
+                     std::initializer_list<std::pair<const char *, const void *>> ptrs)
+{
+    for (const auto &np : ptrs) {
+        if (!np.second) continue;
+        hipPointerAttribute_t a;
+        std::memset(&a, 0, sizeof a);
+        const hipError_t e = hipPointerGetAttributes(&a, np.second);
+        if (e != hipSuccess) (void)hipGetLastError();  // not an address HIP knows: clear the error
+        const bool managed = a.isManaged || a.type == hipMemoryTypeManaged || a.type == hipMemoryTypeUnified;
+        if (e != hipSuccess || !(managed || (a.type == hipMemoryTypeDevice && a.device == ctx->device))) {
+            char buf[256];
+            snprintf(buf, sizeof buf, "%s: %s is not device memory of device %d", call, np.first, ctx->device);
+            return mpr_set_error(ctx, MPR_ERR_ARG, buf);
+        }
+    }
+    return MPR_OK;
+}
+
 namespace {
 
 int fail(mpr_ctx *ctx, int code, const char *fmt, ...)
@@ -2207,6 +2233,7 @@ int32_t mpr_map_to_angles(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const 
     if (!ctx) return MPR_ERR_ARG;
     if (!valid_images(imgs, n) || !z || !sampled || !phi || !zmin_zmax)
         return fail(ctx, MPR_ERR_ARG, "map_to_angles: invalid argument");
+    if (int rc = mpr_check_device(ctx, "map_to_angles", {{"z", z}, {"sampled", sampled}, {"phi", phi}})) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     const int chunk = (int)((kScratchBytes - kVarOffset - 4096) / (kMapBlocks * 24 + 64));
@@ -2272,6 +2299,8 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
     if (!valid_images(imgs, n) || !valid_params(p) || !phi || !sampled || !e_s || !T_hat)
         return fail(ctx, MPR_ERR_ARG, "estimate_temperature: invalid argument");
     if (!ws || ws_bytes < table_bytes(imgs, n, p)) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+    if (int rc = mpr_check_device(ctx, "estimate_temperature", {{"phi", phi}, {"sampled", sampled}, {"workspace", ws}}))
+        return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     // e_s per image (equation mpr-sse)
@@ -2392,6 +2421,10 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
     if (!ctx) return MPR_ERR_ARG;
     if (!valid_images(imgs, n) || !valid_params(p) || !phi || !sampled || !T_hat || !phi_sum)
         return fail(ctx, MPR_ERR_ARG, "simulate: invalid argument");
+    if (int rc = mpr_check_device(ctx, "simulate",
+                                  {{"phi", phi}, {"sampled", sampled}, {"phi_init", phi_init}, {"workspace", ws},
+                                   {"phi_sum", phi_sum}, {"phi_m2", phi_m2}, {"phi_states", phi_states}}))
+        return rc;
     if (phi_m2 && p->K > 1 && !p->spread)
         return fail(ctx, MPR_ERR_ARG, "simulate: phi_m2 with K > 1 needs params.spread = 1");
     for (int b = 0; b < n; ++b)
@@ -2508,6 +2541,9 @@ int32_t mpr_predict(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float 
     if (!ctx) return MPR_ERR_ARG;
     if (!valid_images(imgs, n) || !z || !sampled || !phi_sum || !zmin_zmax || !z_hat || M < 1)
         return fail(ctx, MPR_ERR_ARG, "predict: invalid argument");
+    if (int rc = mpr_check_device(ctx, "predict",
+                                  {{"z", z}, {"sampled", sampled}, {"phi_sum", phi_sum}, {"z_hat", z_hat}}))
+        return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t need = round_up((int64_t)n * sizeof(ImgDev), 256) + (int64_t)n * 16;
@@ -2542,6 +2578,9 @@ int32_t mpr_quantiles(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const floa
                     kMaxQuantileStates);
     for (int k = 0; k < nq; ++k)
         if (!(probs[k] >= 0.0 && probs[k] <= 1.0)) return fail(ctx, MPR_ERR_ARG, "quantiles: p outside [0, 1]");
+    if (int rc = mpr_check_device(ctx, "quantiles",
+                                  {{"z", z}, {"sampled", sampled}, {"phi_states", phi_states}, {"z_q", z_q}}))
+        return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t img_bytes = round_up((int64_t)n * sizeof(ImgDev), 256);
@@ -2593,6 +2632,8 @@ int32_t mpr_spread(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const uint8_t
     if (!ctx) return MPR_ERR_ARG;
     if (!valid_images(imgs, n) || !sampled || !phi_m2 || !zmin_zmax || !z_std || M < 1)
         return fail(ctx, MPR_ERR_ARG, "spread: invalid argument");
+    if (int rc = mpr_check_device(ctx, "spread", {{"sampled", sampled}, {"phi_m2", phi_m2}, {"z_std", z_std}}))
+        return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t need = round_up((int64_t)n * sizeof(ImgDev), 256) + (int64_t)n * 16;
@@ -2650,6 +2691,7 @@ int32_t mpr_select_q(mpr_ctx *ctx, const mpr_image *img, const float *z, const u
     const int64_t need = select_q_bytes(img, p, q_grid, nq);
     if (need < 0) return fail(ctx, MPR_ERR_ARG, "select_q: a candidate q is outside (0, 1/2]");
     if (!ws || ws_bytes < need) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
+    if (int rc = mpr_check_device(ctx, "select_q", {{"z", z}, {"sampled", sampled}, {"workspace", ws}})) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t n = (int64_t)img->nx * img->ny;
@@ -2744,6 +2786,7 @@ int32_t mpr_diag_philox(mpr_ctx *ctx, const uint32_t *ctr, uint64_t seed, int64_
 {
     if (!ctx) return MPR_ERR_ARG;
     if (!ctr || !out || n < 0) return fail(ctx, MPR_ERR_ARG, "diag_philox: invalid argument");
+    if (int rc = mpr_check_device(ctx, "diag_philox", {{"ctr", ctr}, {"out", out}})) return rc;
     if (n == 0) return MPR_OK;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
@@ -2765,6 +2808,8 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
         !sampled || (colour != 0 && colour != 1) || !(T > 0) || !(a > 0) || q != 0.5 || (mode != 0 && mode != 1) ||
         v < 0)
         return fail(ctx, MPR_ERR_ARG, "diag_half_sweep: invalid argument");
+    if (int rc = mpr_check_device(ctx, "diag_half_sweep", {{"phi", phi}, {"sampled", sampled}, {"flags", flags}}))
+        return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t hg = half_grid_bytes(nx, ny);
@@ -2851,6 +2896,8 @@ int32_t mpr_diag_half_sweep_fp64(mpr_ctx *ctx, int32_t nx, int32_t ny, double *p
         !sampled || (colour != 0 && colour != 1) || !(T > 0) || !(a > 0) || !(q > 0.0 && q <= 0.5) ||
         (mode != 0 && mode != 1) || v < 0 || kShapes[v].compact)
         return fail(ctx, MPR_ERR_ARG, "diag_half_sweep_fp64: invalid argument");
+    if (int rc = mpr_check_device(ctx, "diag_half_sweep_fp64", {{"phi", phi}, {"sampled", sampled}, {"flags", flags}}))
+        return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t hg = half_grid_bytes(nx, ny, 8);
@@ -2903,6 +2950,7 @@ int32_t mpr_diag_copy(mpr_ctx *ctx, const void *src, void *dst, int64_t bytes, v
     if (!ctx) return MPR_ERR_ARG;
     if (!src || !dst || bytes < 0 || bytes % 16 != 0 || ((uintptr_t)src | (uintptr_t)dst) % 16 != 0)
         return fail(ctx, MPR_ERR_ARG, "diag_copy: invalid argument");
+    if (int rc = mpr_check_device(ctx, "diag_copy", {{"src", src}, {"dst", dst}})) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     const int64_t n = bytes / 16;
@@ -2920,6 +2968,7 @@ int32_t mpr_diag_energy(mpr_ctx *ctx, int32_t nx, int32_t ny, const float *phi, 
     if (!ctx) return MPR_ERR_ARG;
     if (nx < 1 || ny < 1 || !phi || !h_plus_ngp || !(q > 0 && q <= 0.5))
         return fail(ctx, MPR_ERR_ARG, "diag_energy: invalid argument");
+    if (int rc = mpr_check_device(ctx, "diag_energy", {{"phi", phi}})) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t stream = (hipStream_t)stream_;
     unsigned long long *d_e = (unsigned long long *)((char *)ctx->scratch + kEnergyOffset);

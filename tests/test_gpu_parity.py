@@ -79,6 +79,55 @@ def test_map_bit_exact(ctx, shape):
     assert np.array_equal(phi.cpu().numpy().view(np.uint32), po.astype(np.float32).view(np.uint32))
 
 
+def test_binding_checks_dtype_and_extent(ctx):
+    """Tensors of the wrong dtype or shorter than the batch's packed sites are
+    refused before the call; the right ones go through."""
+    imgs = mpr.images([(8, 8), (4, 6)])
+    z = torch.linspace(0.0, 1.0, 88, device="cuda")
+    mk = torch.zeros(88, dtype=torch.uint8, device="cuda")
+    mk[::3] = 1
+    phi = torch.zeros(88, device="cuda")
+    with pytest.raises(TypeError, match="z: dtype"):
+        ctx.map_to_angles(imgs, z.double(), mk, phi)
+    with pytest.raises(TypeError, match="sampled: dtype"):
+        ctx.map_to_angles(imgs, z, mk.float(), phi)
+    with pytest.raises(ValueError, match="phi: 87 elements, the call needs 88"):
+        ctx.map_to_angles(imgs, z, mk, phi[:87])
+    with pytest.raises(ValueError, match="must be contiguous"):
+        ctx.map_to_angles(imgs, z, mk, torch.zeros(176, device="cuda")[::2])
+    ctx.map_to_angles(imgs, z, mk, phi)
+    prm = mpr.default_params(R=2, K=3)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    ps = torch.zeros_like(phi)
+    with pytest.raises(ValueError, match="phi_states: 527 elements, the call needs 528"):
+        ctx.simulate(imgs, phi, mk, np.array([0.1, 0.1]), prm, ws, ps, phi_states=torch.zeros(527, device="cuda"))
+    with pytest.raises(ValueError, match="T_hat: 1 values for 2 images"):
+        ctx.simulate(imgs, phi, mk, np.array([0.1]), prm, ws, ps)
+
+
+def test_library_refuses_host_memory(ctx):
+    """The C ABI checks its device pointers itself: pinned host memory passed
+    as phi (through the raw C call, past the binding's checks) is refused
+    with MPR_ERR_ARG naming the argument.  Pinned memory is readable by a
+    kernel, so nothing would fault if the check let it through."""
+    imgs = mpr.images([(8, 8)])
+    z = torch.linspace(0.0, 1.0, 64, device="cuda")
+    mk = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    mk[::3] = 1
+    host = torch.zeros(64, dtype=torch.float32).pin_memory()
+    zz = np.zeros(2)
+    import ctypes as C
+    rc = ctx.lib.mpr_map_to_angles(ctx._h, imgs, 1, C.c_void_p(z.data_ptr()), C.c_void_p(mk.data_ptr()),
+                                   C.c_void_p(host.data_ptr()), zz.ctypes.data_as(C.c_void_p), None)
+    assert rc == mpr.MPR_ERR_ARG
+    assert ctx.lib.mpr_last_error(ctx._h).decode() == "map_to_angles: phi is not device memory of device 0"
+    assert not host.any()
+    # an interior pointer of a device allocation is accepted
+    big = torch.zeros(64 + 37, device="cuda")
+    ctx.map_to_angles(imgs, z, mk, big[37:])
+    assert big[37:][mk == 1].max() > 0
+
+
 def test_map_batch_and_errors(ctx):
     shapes = [(16, 20), (9, 7), (33, 3)]
     rng = np.random.default_rng(5)

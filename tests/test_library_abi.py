@@ -112,3 +112,27 @@ def test_table_side_cap_bounds_the_table_workspace():
     assert ws(mpr.default_params(R=1, K=1, table_side_cap=1)) < 0
     assert ws(mpr.default_params(R=1, K=1, table_side_cap=2)) > 0
     assert mpr.default_params().table_side_cap == 0
+
+
+def test_binding_rejects_host_tensors_and_short_buffers():
+    """The binding checks every tensor before the C call: a host tensor, a
+    wrong dtype or a buffer shorter than the images would reach a kernel as a
+    bad device pointer.  The checks run without a device (the context is made
+    without calling mpr_create)."""
+    torch = pytest.importorskip("torch")
+    ctx = mpr.Context.__new__(mpr.Context)
+    ctx.lib = mpr.load()
+    ctx._h = C.c_void_p()
+    ctx.device = 0
+    imgs = mpr.images([(8, 8), (4, 6)])
+    assert mpr.sites_of(imgs) == 88
+    z = torch.zeros(88)
+    with pytest.raises(ValueError, match="z: must be a tensor on cuda:0"):
+        ctx.map_to_angles(imgs, z, z, z)
+    with pytest.raises(ValueError, match="a tensor is required"):
+        ctx._t(None, "phi_sum", torch.float32, 88)
+    assert ctx._t(None, "phi_init", torch.float32, 88, optional=True) is None
+    fake = torch.empty(0, device="meta")  # not on cuda: refused like a host tensor
+    with pytest.raises(ValueError, match="must be a tensor on cuda:0"):
+        ctx._t(fake, "phi", torch.float32, 88)
+    ctx._h = C.c_void_p()  # nothing to destroy
