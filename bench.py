@@ -86,8 +86,11 @@ def measured_valu(workload: str, chains: int, key: str, launch_ms: float):
     v = (t.get("by_tile") or {}).get(key, {}).get("valu_insts_per_launch")
     if not v:
         return None
-    return {"wave_insts_per_launch": v, "issue_per_simd_cycle": v / (1024 * launch_ms * 1e-3 * 2.4e9),
-            "fp32_fma_issue_limit_per_simd_cycle": 0.25}
+    rate = v / (1024 * launch_ms * 1e-3 * 2.4e9)
+    # binding: the kernel issues VALU instructions at (or above) the rate of
+    # 4-cycle FP32 FMAs, so the VALU, not HBM, sets its time
+    return {"wave_insts_per_launch": v, "issue_per_simd_cycle": rate, "fp32_fma_issue_limit_per_simd_cycle": 0.25,
+            "binding": rate >= 0.9 * 0.25}
 
 
 def cpu_baseline(im, T: float, sweeps: int, seed: int) -> dict:
