@@ -204,7 +204,7 @@ def main():
                     help="sweep block shape: auto (tuned), or rows 1/2/4/8, with a 'c' suffix for the compacted "
                          "shapes 2c/4c/8c (for profiling runs that must see one kernel)")
     ap.add_argument("--fp64", action="store_true",
-                    help="run the chains in double precision (the paper's DP variant; plain block shapes)")
+                    help="run the chains in double precision (the paper's DP variant)")
     ap.add_argument("--warm-seeds", type=int, default=8,
                     help="images per mask type for the warm-start comparison at L=2048 (0 = skip)")
     args = ap.parse_args()
@@ -310,8 +310,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(args.workload, prm.R,
                                         ("fp64-" if args.fp64 else "") + str(prof["last_tile"])),
-            "kernel": ("half_sweep_fp64_kernel" if args.fp64 else
-                       "half_sweep_compact_kernel" if prof["last_tile"] & mpr.TILE_COMPACT else "half_sweep_kernel"),
+            "kernel": ("half_sweep_" + ("fp64_" if args.fp64 else "") +
+                       ("compact_kernel" if prof["last_tile"] & mpr.TILE_COMPACT else "kernel")),
             "tile_rows": prof["last_tile"] & 0xFF,
             "launch_ms": launch_ms, "useful_bytes_per_launch": bytes_per_launch,
             "sweep_kernel_time_share": prof["sweep_kernel_ms"] * 1e-3 / dt,

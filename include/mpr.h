@@ -102,10 +102,10 @@ typedef struct {
                              needed for mpr_simulate's phi_m2 then; more workspace) */
     int32_t fp64;         /* 1: the chains of mpr_simulate store and update their angles
                              in double precision (the paper's DP runs, Section 4, Tables
-                             2 and 3); twice the workspace per chain; plain block shapes
-                             only (tile_rows without MPR_TILE_COMPACT).  Inputs and
-                             outputs stay float; sums are taken in double and rounded
-                             once.  The temperature estimate is unaffected. */
+                             2 and 3); twice the workspace per chain; every block shape
+                             (the e(T, L) table chains of q < 1/2 take the plain ones).
+                             Inputs and outputs stay float; sums are taken in double and
+                             rounded once.  The temperature estimate is unaffected. */
     int32_t table_side_cap;  /* 0: the e(T, L) table of an nx x ny image is built on nx x ny;
                                 >= 2: on min(nx, cap) x min(ny, cap), so that the images larger
                                 than cap share one table (e(T, L) approaches its L -> infinity

@@ -897,6 +897,211 @@ __global__ __launch_bounds__(kBlock) void half_sweep_fp64_kernel(const ChainDesc
     }
 }
 
+// The double-precision sweep with the gap sites compacted onto consecutive
+// lanes: the list building of half_sweep_compact_body (1024 sites per block,
+// CR half-rows, two site pairs per thread, the pair's Philox words drawn in
+// pass 1) on double half-grids, each listed gap site updated by
+// update_site_d and each sampled site of colour 1 given its bond energy by
+// bond_energy_d when the sweep's energy is wanted.  Per site the arithmetic
+// is that of half_sweep_fp64_kernel, so the results are bit-identical to it.
+template <bool DIAG, int CR>
+__global__ __launch_bounds__(kBlock) void half_sweep_fp64_compact_kernel(const ChainDesc *__restrict__ descs,
+                                                                         ChainState *__restrict__ states,
+                                                                         BlockMap bm, int colour, SweepConsts sc,
+                                                                         int or_only, uint8_t *__restrict__ flags)
+{
+    constexpr int PPR = kCompactSites / CR / 2;  // site pairs per block row
+    constexpr int NW = kBlock / 64;
+    __shared__ uint2 gap_list[kCompactSites];  // as in half_sweep_compact_body
+    __shared__ uint16_t fixed_list[kCompactSites];
+    __shared__ uint32_t wave_count[2][2][NW];
+    __shared__ unsigned long long red[NW];
+
+    int lb;
+    const int c = chain_of_block(bm, (int64_t)blockIdx.x, &lb);
+    ChainState *stp = states + c;
+    const int phase = stp->phase;
+    if (phase == PH_DONE) return;
+    const ChainDesc d = descs[c];
+    const int nbx = ((d.S >> 1) + PPR - 1) / PPR;
+    const int by = lb / nbx;
+    const int bx = lb - by * nbx;
+    const uint32_t sweep = stp->sweep;
+    const double T = stp->T, a_cur = stp->a_cur;
+    const bool want_energy = (colour == 1) && (phase != PH_EQ);
+    const bool want_acc = phase != PH_EQ;
+    double *const mine = (double *)(colour ? d.h[1] : d.h[0]);
+    const double *const oth = (const double *)(colour ? d.h[0] : d.h[1]);
+    double *const accp = (phase == PH_EQ) ? (double *)(colour ? d.acc[1] : d.acc[0]) : nullptr;
+    double *const m2p = accp ? (double *)(colour ? d.m2[1] : d.m2[0]) : nullptr;
+
+    // pass 1: pairs t and t + 256 of the block, both read first
+    bool gap[2][2], fix[2][2];
+    uint32_t wu[2][2], wr[2][2];
+    double2 pv[2];
+    bool in[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int pi = (int)threadIdx.x + j * kBlock;
+        const int y = by * CR + pi / PPR;
+        const int h0 = 2 * (bx * PPR + pi % PPR);
+        const int s = (y + colour) & 1;
+        in[j] = y < d.ny && h0 < ((d.nx - s + 1) >> 1);
+        // rows and pairs outside the grid read pair 0 of row 0 instead
+        pv[j] = gldd2(mine + (in[j] ? (int64_t)y * d.S + h0 : 0));
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int pi = (int)threadIdx.x + j * kBlock;
+        const int y = by * CR + pi / PPR;
+        const int h0 = 2 * (bx * PPR + pi % PPR);
+        const int s = (y + colour) & 1;
+        const bool two = in[j] && (h0 + 1) < ((d.nx - s + 1) >> 1);
+        gap[j][0] = in[j] && !is_fixed_d(pv[j].x);
+        gap[j][1] = two && !is_fixed_d(pv[j].y);
+        fix[j][0] = want_energy && in[j] && !gap[j][0];
+        fix[j][1] = want_energy && two && !gap[j][1];
+        wu[j][0] = wu[j][1] = wr[j][0] = wr[j][1] = 0u;
+        if (!or_only && (gap[j][0] || gap[j][1])) {
+            const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * h0 + s), sweep, d.chain, d.image_id};
+            const U4 w = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
+            wu[j][0] = w.x;
+            wr[j][0] = w.y;
+            wu[j][1] = w.z;
+            wr[j][1] = w.w;
+        }
+    }
+    const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t pre[2][2] = {{0u, 0u}, {0u, 0u}};
+#pragma unroll
+    for (int L = 0; L < 2; ++L) {
+        if (L == 1 && !want_energy) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint64_t b0 = __ballot(L ? fix[j][0] : gap[j][0]);
+            const uint64_t b1 = __ballot(L ? fix[j][1] : gap[j][1]);
+            pre[L][j] = (uint32_t)(__popcll(b0 & below) + __popcll(b1 & below));
+            if (lane == 0) wave_count[L][j][wid] = (uint32_t)(__popcll(b0) + __popcll(b1));
+        }
+    }
+    __syncthreads();
+    int n_list[2] = {0, 0};
+#pragma unroll
+    for (int L = 0; L < 2; ++L) {
+        if (L == 1 && !want_energy) continue;
+        uint32_t base0 = 0u, base1 = 0u, tot0 = 0u, tot1 = 0u;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c0 = wave_count[L][0][w], c1 = wave_count[L][1][w];
+            base0 += (w < wid) ? c0 : 0u;
+            base1 += (w < wid) ? c1 : 0u;
+            tot0 += c0;
+            tot1 += c1;
+        }
+        n_list[L] = (int)(tot0 + tot1);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            uint32_t pos = (j ? tot0 + base1 : base0) + pre[L][j];
+            const uint32_t pi = threadIdx.x + (uint32_t)j * kBlock;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const uint32_t idx = 2u * pi + (uint32_t)k;
+                if (L == 0 && gap[j][k]) {
+                    gap_list[pos] = make_uint2((wu[j][k] & 0xFFFFFF00u) | (idx & 0xFFu),
+                                               (wr[j][k] & 0xFFFFFF00u) | (idx >> 8));
+                    ++pos;
+                }
+                if (L == 1 && fix[j][k]) {
+                    fixed_list[pos] = (uint16_t)idx;
+                    ++pos;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // a listed site: row, half-row position, colour offset, valid neighbours,
+    // and its four neighbours (loaded from clamped positions when missing)
+    auto locate = [&](uint32_t idx, int &y, int &h, int &s, uint32_t &valid) {
+        const int pi = (int)(idx >> 1);
+        y = by * CR + pi / PPR;
+        h = 2 * (bx * PPR + pi % PPR) + (int)(idx & 1u);
+        s = (y + colour) & 1;
+        const int Wo = (d.nx + s) >> 1;
+        valid = (h + s - 1 >= 0 ? 1u : 0u) | (h + s < Wo ? 2u : 0u) | (y > 0 ? 4u : 0u) | (y + 1 < d.ny ? 8u : 0u);
+    };
+    auto neighbours = [&](int y, int h, int s, uint32_t valid, double &nL, double &nR, double &nU, double &nD) {
+        const double *orow = oth + (int64_t)y * d.S;
+        nL = fabs(gldd(orow + max(h + s - 1, 0)));
+        nR = fabs(gldd(orow + min(h + s, d.S - 1)));
+        nU = fabs(gldd(orow + ((valid & 4u) ? -(int64_t)d.S : 0) + h));
+        nD = fabs(gldd(orow + ((valid & 8u) ? (int64_t)d.S : 0) + h));
+    };
+
+    // a thread takes at most 4 gap and 4 sampled sites, each below 2^33 in
+    // energy units: the energy stays below 2^44 over a block, the count
+    // (at most 1024) rides in the top 12 bits
+    unsigned long long e_thread = 0ull;
+    uint32_t acc_thread = 0u;
+    // pass 2: the listed gap sites.  Unrolled over a thread's at most four
+    // entries: in a loop the compiler keeps the double update's constants in
+    // registers across iterations (~116 VGPRs, 4 waves per SIMD); unrolled,
+    // the kernel takes 50 (8 waves)
+#pragma unroll
+    for (int k = 0; k < kCompactSites / kBlock; ++k) {
+        const int i = (int)threadIdx.x + k * kBlock;
+        if (i >= n_list[0]) break;
+        const uint2 e = gap_list[i];
+        int y, h, s;
+        uint32_t valid;
+        locate((e.x & 0xFFu) | ((e.y & 0xFFu) << 8), y, h, s, valid);
+        double nL, nR, nU, nD;
+        neighbours(y, h, s, valid, nL, nR, nU, nD);
+        double *sp = mine + (int64_t)y * d.S + h;
+        const double a = fabs(gldd(sp));
+        // the low 8 bits of each word hold the index; unit24 uses the top 24
+        const double u = or_only ? 0.5 : (double)unit24(e.x);
+        const double r = or_only ? 0.5 : (double)unit24(e.y);
+        const SiteOutD o = update_site_d(a, nL, nR, nU, nD, valid, u, r, a_cur, T, sc.q64, or_only != 0);
+        gstd(sp, o.phi);
+        if (accp)
+            accumulate_state_d(accp + (int64_t)y * d.S + h, m2p ? m2p + (int64_t)y * d.S + h : nullptr, o.phi,
+                               stp->inv_k_d, stp->inv_km1_d);
+        acc_thread += o.accepted ? 1u : 0u;
+        if (want_energy) e_thread += energy_fx_d(o.e_bonds);
+        if (DIAG && flags) flags[(int64_t)y * d.nx + 2 * h + s] = (uint8_t)o.flags;
+    }
+    // pass 3: bond energies of the sampled sites of colour 1
+#pragma unroll
+    for (int k = 0; k < kCompactSites / kBlock; ++k) {
+        const int i = (int)threadIdx.x + k * kBlock;
+        if (i >= n_list[1]) break;
+        int y, h, s;
+        uint32_t valid;
+        locate((uint32_t)fixed_list[i], y, h, s, valid);
+        double nL, nR, nU, nD;
+        neighbours(y, h, s, valid, nL, nR, nU, nD);
+        const double a = fabs(gldd(mine + (int64_t)y * d.S + h));
+        e_thread += energy_fx_d(bond_energy_d(a, nL, nR, nU, nD, valid, sc.q64));
+    }
+    if (!want_acc) return;
+    unsigned long long sum = e_thread | ((unsigned long long)acc_thread << 52);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    if (lane == 0) red[wid] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long e = 0ull, n = 0ull;
+        for (int i = 0; i < NW; ++i) {
+            e += red[i] & 0x000FFFFFFFFFFFFFull;
+            n += red[i] >> 52;
+        }
+        if (e) atomicAdd(&stp->e_fx, e);
+        if (n) atomicAdd(&stp->acc, n);
+    }
+}
+
 // control_chain for every chain, one thread per chain.
 __global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *__restrict__ states, int n,
                                CtlParams cp, unsigned int *done_count, unsigned long long *work)
@@ -1562,7 +1767,7 @@ bool valid_params(const mpr_params *p)
            p->table_T_lo > 0.0 && p->table_T_hi > p->table_T_lo &&
            (p->tile_rows == 0 || shape_of(p->tile_rows) >= 0) &&
            p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096 && (p->spread == 0 || p->spread == 1) &&
-           (p->fp64 == 0 || (p->fp64 == 1 && (p->tile_rows & MPR_TILE_COMPACT) == 0)) &&
+           (p->fp64 == 0 || p->fp64 == 1) &&
            (p->table_side_cap == 0 || p->table_side_cap >= 2);
 }
 
@@ -1775,11 +1980,27 @@ void launch_half_fp64_rows(hipStream_t st, const ChainSet &cs, int v, int colour
                        cs.d_desc, cs.d_state, block_map(cs, v), colour, sc, or_only, flags);
 }
 
-// One half-sweep of double-precision chains in plain shape v.
+template <bool DIAG, int CR>
+void launch_half_fp64_compact(hipStream_t st, const ChainSet &cs, int v, int colour, const SweepConsts &sc,
+                              int or_only, uint8_t *flags)
+{
+    hipLaunchKernelGGL((half_sweep_fp64_compact_kernel<DIAG, CR>), dim3((unsigned)cs.total_blocks[v]), dim3(kBlock),
+                       0, st, cs.d_desc, cs.d_state, block_map(cs, v), colour, sc, or_only, flags);
+}
+
+// One half-sweep of double-precision chains in shape v.
 template <bool DIAG>
 void launch_half_fp64(hipStream_t st, const ChainSet &cs, int v, int colour, const SweepConsts &sc, int or_only,
                       uint8_t *flags)
 {
+    if (kShapes[v].compact) {
+        switch (kShapes[v].rows) {
+            case 2: launch_half_fp64_compact<DIAG, 2>(st, cs, v, colour, sc, or_only, flags); break;
+            case 4: launch_half_fp64_compact<DIAG, 4>(st, cs, v, colour, sc, or_only, flags); break;
+            default: launch_half_fp64_compact<DIAG, 8>(st, cs, v, colour, sc, or_only, flags); break;
+        }
+        return;
+    }
     switch (kShapes[v].rows) {
         case 1: launch_half_fp64_rows<DIAG, 1>(st, cs, v, colour, sc, or_only, flags); break;
         case 2: launch_half_fp64_rows<DIAG, 2>(st, cs, v, colour, sc, or_only, flags); break;
@@ -1788,9 +2009,9 @@ void launch_half_fp64(hipStream_t st, const ChainSet &cs, int v, int colour, con
     }
 }
 
-// One half-sweep of every chain in shape v (the e(T, L) runs and the
-// double-precision chains use the plain shapes only); `ctl` (single
-// precision only) makes the redo kernel run the per-sweep control as well.
+// One half-sweep of every chain in shape v (the e(T, L) runs use the plain
+// shapes only); `ctl` (single precision only) makes the redo kernel run the
+// per-sweep control as well.
 void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colour, const SweepConsts &sc,
                  const FusedControl *ctl = nullptr)
 {
@@ -1917,7 +2138,7 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     };
 
     // block shape: fixed, cached, or tuned on the first sweeps
-    const int n_shapes = (table || cs.fp64) ? kNumPlainShapes : kNumShapes;
+    const int n_shapes = table ? kNumPlainShapes : kNumShapes;
     int v = p->tile_rows ? shape_of(p->tile_rows) : -1;
     if (v >= n_shapes) v = kDefaultShape;
     int maxnx = 0, maxny = 0;
@@ -2894,7 +3115,7 @@ int32_t mpr_diag_half_sweep_fp64(mpr_ctx *ctx, int32_t nx, int32_t ny, double *p
     const int v = tile ? shape_of(tile) : kDefaultShape;
     if (nx < 1 || ny < 1 || (int64_t)nx * ny < 2 || half_grid_bytes(nx, ny) >= ((int64_t)1 << 32) || !phi ||
         !sampled || (colour != 0 && colour != 1) || !(T > 0) || !(a > 0) || !(q > 0.0 && q <= 0.5) ||
-        (mode != 0 && mode != 1) || v < 0 || kShapes[v].compact)
+        (mode != 0 && mode != 1) || v < 0)
         return fail(ctx, MPR_ERR_ARG, "diag_half_sweep_fp64: invalid argument");
     if (int rc = mpr_check_device(ctx, "diag_half_sweep_fp64", {{"phi", phi}, {"sampled", sampled}, {"flags", flags}}))
         return rc;

@@ -441,6 +441,38 @@ struct SiteOutD {
 // or exp(-Delta H / T) > r.  The energy change uses the cancellation-free
 // form Delta H = 2 A sin^2(d / 2) + B_s sin d for the move d = th'' - th' in
 // th (q delta phi, shifted by -+2 pi q when the proposal wraps; |d| <= pi).
+// Sums over the valid neighbours of a site with th = q phi, D_j = th - q phi_j:
+// A2 = sum 2 (1 - cos D_j) and, with WITH_B, B = sum sin D_j.  The update and
+// the bond energy of a sampled site both take A2 from here, so that the two
+// round alike.
+template <bool WITH_B>
+__device__ __forceinline__ void neighbour_sums_d(double th, double q, const double nb[4], uint32_t valid, double &A2,
+                                                 double &B)
+{
+    A2 = 0.0;
+    B = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool v = (valid >> j) & 1u;
+        const double dj = v ? th - q * nb[j] : 0.0;
+        const double d2 = dj * dj;
+        const double s2 = sin2_half_d(dj, d2);         // 2 sin(D_j / 2)
+        if (WITH_B) B = fma(s2, cos_half_d(d2), B);  // sin D_j
+        A2 = fma(s2, s2, A2);                          // 2 (1 - cos D_j)
+    }
+}
+
+// Bond energy sum_j (1 - cos D_j) of a site: the e_before of update_site_d
+// (for sampled sites, which are not updated).
+__device__ __forceinline__ double bond_energy_d(double phi, double n0, double n1, double n2, double n3,
+                                                uint32_t valid, double q)
+{
+    const double nb[4] = {n0, n1, n2, n3};
+    double A2, B;
+    neighbour_sums_d<false>(q * phi, q, nb, valid, A2, B);
+    return 0.5 * A2;
+}
+
 __device__ __forceinline__ SiteOutD update_site_d(double phi, double n0, double n1, double n2, double n3,
                                                   uint32_t valid, double u, double r, double a, double T, double q,
                                                   bool or_only)
@@ -448,16 +480,8 @@ __device__ __forceinline__ SiteOutD update_site_d(double phi, double n0, double 
     const double period = kTwoPi * q;  // range of th
     const double th = q * phi;
     const double nb[4] = {n0, n1, n2, n3};
-    double A2 = 0.0, B = 0.0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const bool v = (valid >> j) & 1u;
-        const double dj = v ? th - q * nb[j] : 0.0;
-        const double d2 = dj * dj;
-        const double s2 = sin2_half_d(dj, d2);  // 2 sin(D_j / 2)
-        B = fma(s2, cos_half_d(d2), B);         // sin D_j
-        A2 = fma(s2, s2, A2);                   // 2 (1 - cos D_j)
-    }
+    double A2, B;
+    neighbour_sums_d<true>(th, q, nb, valid, A2, B);
     const double A_small = 0.5 * A2;
     const int nnb = __popc(valid & 15u);
     const double A = (double)nnb - A_small;

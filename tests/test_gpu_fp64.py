@@ -25,6 +25,7 @@ import paper_1811_01604_amd as mpr  # noqa: E402
 pytestmark = pytest.mark.gpu
 TWO_PI = 2.0 * math.pi
 PLAIN_TILES = [1, 2, 4, 8]
+COMPACT_TILES = [2 | mpr.TILE_COMPACT, 4 | mpr.TILE_COMPACT, 8 | mpr.TILE_COMPACT]
 
 
 def say(*a):
@@ -70,11 +71,12 @@ def run_pair(ctx, phi, m, colour, T, a, sweep, mode=0, seed=3000, tile=0):
     return g.cpu().numpy(), acc_g, e_g, fl.cpu().numpy(), po, acc_o, fo
 
 
+@pytest.mark.parametrize("tile", [0, 4 | mpr.TILE_COMPACT])
 @pytest.mark.parametrize("kind", ["uniform", "smooth"])
 @pytest.mark.parametrize("shape", [(64, 64), (97, 131), (1, 40), (40, 1)])
-def test_fp64_over_relaxation_only(ctx, kind, shape):
+def test_fp64_over_relaxation_only(ctx, kind, shape, tile):
     ny, nx = shape
-    say("fp64 OR-only", kind, shape)
+    say("fp64 OR-only", kind, shape, tile)
     rng = np.random.default_rng(ny + 7 * nx)
     if kind == "uniform":
         phi = rng.uniform(0, TWO_PI, size=shape)
@@ -83,7 +85,7 @@ def test_fp64_over_relaxation_only(ctx, kind, shape):
         phi, m = smooth_state(max(ny, 2), max(nx, 2), 2.5, 0.05, 0.5, 0.01, 21)
         phi, m = phi[:ny, :nx].copy(), m[:ny, :nx].copy()
     for colour in (0, 1):
-        pg, acc_g, _, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 0.1, 1.0, 0, mode=1)
+        pg, acc_g, _, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, 0.1, 1.0, 0, mode=1, tile=tile)
         assert acc_g == 0 and acc_o == 0
         sel = colour_mask(ny, nx, colour) & (m == 0)
         assert np.array_equal(fg[sel] & 15, fo[sel] & 15)
@@ -94,12 +96,14 @@ def test_fp64_over_relaxation_only(ctx, kind, shape):
         phi = po
 
 
-@pytest.mark.parametrize("T", [2.6e-4, 1.0e-3, 0.1])
-def test_fp64_decisions_teacher_forced(ctx, T):
+@pytest.mark.parametrize("T,tile", [(2.6e-4, 0), (1.0e-3, 0), (0.1, 0), (2.6e-4, 8 | mpr.TILE_COMPACT),
+                                    (0.1, 2 | mpr.TILE_COMPACT)])
+def test_fp64_decisions_teacher_forced(ctx, T, tile):
     """Every Metropolis decision equals the oracle's, down to T = 2.6e-4;
     angles agree to 1e-11 rad; accepted counts are equal; the fused energy
-    is the oracle's energy of the written state within the fixed-point bound."""
-    say("fp64 decisions T =", T)
+    is the oracle's energy of the written state within the fixed-point bound
+    (the default plain shape and the compacted ones)."""
+    say("fp64 decisions T =", T, "tile", tile)
     ny, nx = 384, 517
     phi, m = smooth_state(ny, nx, 2.5, 0.05, 0.5, 0.02, 31)
     ngp = oracle.bond_count(nx, ny)
@@ -110,7 +114,7 @@ def test_fp64_decisions_teacher_forced(ctx, T):
     for a in (1.0, 4.0, 40.0):
         for sweep in range(3):
             for colour in (0, 1):
-                pg, acc_g, e_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, T, a, 100 * step + sweep)
+                pg, acc_g, e_g, fg, po, acc_o, fo = run_pair(ctx, phi, m, colour, T, a, 100 * step + sweep, tile=tile)
                 sel = colour_mask(ny, nx, colour) & (m == 0)
                 n_dec += int(sel.sum())
                 assert np.array_equal(fg[sel] & 15, fo[sel] & 15), (a, sweep, colour)
@@ -149,7 +153,7 @@ def test_fp64_half_sweep_identical_for_every_tile(ctx, shape, p_removed):
     mk = dev(m, torch.uint8)
     for colour in (0, 1):
         ref = None
-        for tile in PLAIN_TILES:
+        for tile in PLAIN_TILES + COMPACT_TILES:
             g = dev(phi)
             fl = torch.zeros((ny, nx), dtype=torch.uint8, device="cuda")
             acc, e = ctx.diag_half_sweep_fp64(g, mk, colour, 1e-3, 4.0, 11, flags=fl, with_energy=True, tile=tile)
@@ -255,9 +259,10 @@ def test_relaxation_only_runs_zero_states(ctx, fp64):
     assert all(s["relax_sweeps"] > 0 and not s["not_converged"] for s in st)
 
 
-def test_fp64_batch_matches_single_and_rejects_compact_shape(ctx):
+def test_fp64_batch_matches_single_and_compact_shapes(ctx):
     """A ragged batch in double precision gives each image the result it
-    gets alone; compacted block shapes are refused for double chains."""
+    gets alone, and the compacted block shapes give the plain shape's sums
+    bit for bit."""
     im = synth.workload_l64()
     shapes = [(64, 64), (24, 40)]
     zs = [im.z, synth.matern_field(40, 24, 1.5, 0.1, 50, 10, 5)]
@@ -265,7 +270,7 @@ def test_fp64_batch_matches_single_and_rejects_compact_shape(ctx):
     prm = mpr.default_params(R=2, K=3, fp64=1)
     T = np.array([0.15, 0.02])
 
-    def run(sel):
+    def run(sel, prm=prm):
         imgs = mpr.images([shapes[i] for i in sel], ids=list(sel))
         z = dev(np.concatenate([zs[i].astype(np.float32).ravel() for i in sel]), torch.float32)
         mk = dev(np.concatenate([ms[i].ravel() for i in sel]), torch.uint8)
@@ -284,14 +289,10 @@ def test_fp64_batch_matches_single_and_rejects_compact_shape(ctx):
     both = run([0, 1])
     for i in range(2):
         assert np.array_equal(both[i], run([i])[i]), i
-    bad = mpr.default_params(R=1, K=1, fp64=1, tile_rows=4 | mpr.TILE_COMPACT)
-    imgs = mpr.images([(8, 8)])
-    assert ctx.workspace_size(imgs, bad) < 0
-    with pytest.raises(mpr.MprError) as e:
-        ctx.simulate(imgs, torch.zeros(64, device="cuda"), torch.zeros(64, dtype=torch.uint8, device="cuda"),
-                     np.array([0.1]), bad, torch.empty(1 << 20, dtype=torch.uint8, device="cuda"),
-                     torch.zeros(64, device="cuda"))
-    assert e.value.code == mpr.MPR_ERR_ARG
+    for tile in COMPACT_TILES:
+        c = run([0, 1], mpr.default_params(R=2, K=3, fp64=1, tile_rows=tile))
+        for i in range(2):
+            assert np.array_equal(c[i].view(np.uint32), both[i].view(np.uint32)), (tile, i)
 
 
 def test_affine_change_of_the_data_transforms_the_prediction(ctx):
