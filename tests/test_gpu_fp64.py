@@ -201,6 +201,44 @@ def test_fp64_free_running_chains_track_oracle(ctx, n_relax):
     assert [s["a_final"] for s in st] == [s["a_final"] for s in sto]
 
 
+@pytest.mark.parametrize("fp64", [1, 0])
+def test_simulate_from_given_starting_angles(ctx, fp64):
+    """phi_init, the entry the warm start uses: the chains start from given
+    gap angles (made here) instead of Philox draws.  From the same float
+    starting angles, double-precision chains run by the stopping rule track
+    the oracle's (sums to the float rounding of the output, the same stopping
+    sweeps); single-precision chains agree at 99.9% of the gap sites after
+    one sweep.  Without phi_init the result differs (the given angles are
+    used)."""
+    im, phi32 = l64_angles()
+    ny, nx = phi32.shape
+    g = im.mask == 0
+    init = np.zeros_like(phi32)
+    init[g] = np.random.default_rng(5).uniform(0, TWO_PI, size=int(g.sum())).astype(np.float32)
+    T = 0.15
+    kw = dict(R=2, K=3, seed=21) if fp64 else dict(R=1, K=1, fixed_relax=0, seed=21)
+    prm = mpr.default_params(fp64=fp64, **kw)
+    imgs = mpr.images([(ny, nx)])
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    ph, mk = dev(phi32, torch.float32), dev(im.mask, torch.uint8)
+    ps, ps0 = torch.zeros_like(ph), torch.zeros_like(ph)
+    st = ctx.simulate(imgs, ph, mk, np.array([T]), prm, ws, ps, phi_init=dev(init, torch.float32))
+    ctx.simulate(imgs, ph, mk, np.array([T]), prm, ws, ps0)
+    ps, ps0 = ps.cpu().numpy(), ps0.cpu().numpy()
+    po, sto, _, _ = oracle.simulate(phi32.astype(np.float64), im.mask, T, oracle.default_params(**kw),
+                                    phi_init=init.astype(np.float64))
+    d = np.abs(ps[g].astype(np.float64) - po[g])
+    assert np.abs(ps0[g].astype(np.float64) - po[g]).max() > 1e-2
+    if fp64:
+        say(f"  fp64 from phi_init: max |phi_sum gpu - oracle| {d.max():.2e}, relax {[s['relax_sweeps'] for s in st]}")
+        assert d.max() <= 8e-6  # sums of 6 states below 12 pi
+        assert [s["relax_sweeps"] for s in st] == [s["relax_sweeps"] for s in sto]
+    else:
+        frac = float(np.mean(d <= 1e-5))
+        say(f"  fp32 from phi_init, one sweep: {frac:.5f} of gap sites within 1e-5")
+        assert frac >= 0.999
+
+
 def test_fp64_stopping_rule_and_spread_match_oracle(ctx):
     """The whole simulation with the stopping rule (R = 4, K = 10, spread on):
     each chain stops at the oracle's sweep with its slope, and the sums of
