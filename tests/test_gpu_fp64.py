@@ -239,6 +239,25 @@ def test_simulate_from_given_starting_angles(ctx, fp64):
         assert frac >= 0.999
 
 
+@pytest.mark.parametrize("sg_degree,n_fit,n_f,eq_a_mode", [(2, 12, 3, 0), (1, 20, 5, 1), (3, 30, 4, 1)])
+def test_fp64_stopping_rule_options_match_oracle(ctx, sg_degree, n_fit, n_f, eq_a_mode):
+    """Other settings of the stopping rule (degree of the Savitzky-Golay fit,
+    its window, the check interval) and eq_a_mode = 1 (the equilibrium states
+    keep the final relaxation a): double-precision chains stop at the
+    oracle's sweeps with its a, and the sums of their states agree."""
+    im, phi32 = l64_angles()
+    kw = dict(R=2, K=4, seed=9, sg_degree=sg_degree, n_fit=n_fit, n_f=n_f, eq_a_mode=eq_a_mode)
+    ps, _, st = simulate_gpu(ctx, phi32, im.mask, 0.05, mpr.default_params(fp64=1, **kw))
+    po, sto, _, _ = oracle.simulate(phi32.astype(np.float64), im.mask, 0.05, oracle.default_params(**kw))
+    g = im.mask == 0
+    d = np.abs(ps[g].astype(np.float64) - po[g])
+    rs = [s["relax_sweeps"] for s in st]
+    say(f"  degree {sg_degree}, n_fit {n_fit}, n_f {n_f}, eq_a_mode {eq_a_mode}: relax {rs}, max |dsum| {d.max():.2e}")
+    assert rs == [s["relax_sweeps"] for s in sto]
+    assert [s["a_final"] for s in st] == [s["a_final"] for s in sto]
+    assert d.max() <= 8e-6  # sums of 8 states below 16 pi
+
+
 def test_fp64_stopping_rule_and_spread_match_oracle(ctx):
     """The whole simulation with the stopping rule (R = 4, K = 10, spread on):
     each chain stops at the oracle's sweep with its slope, and the sums of
