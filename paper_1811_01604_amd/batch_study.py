@@ -64,7 +64,7 @@ def main():
 
     zz, t_map = timed(lambda: ctx.map_to_angles(imgs, z, mk, phi))
     (e_s, T, cl), t_temp = timed(lambda: ctx.estimate_temperature(imgs, phi, mk, prm, ws))
-    log(f"map {t_map * 1e3:.1f} ms; temperature (256 tables) {t_temp:.2f} s")
+    log(f"map {t_map * 1e3:.1f} ms; temperature ({len(set(shapes))} tables) {t_temp:.2f} s")
     out = None
     for rep in range(2):
         ctx.profile_enable(True)
