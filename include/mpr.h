@@ -374,7 +374,7 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi,
 
 /* mpr_diag_half_sweep for a grid of double angles (phi: dev, double,
  * in/out) through the double-precision sweep of mpr_params.fp64: the same
- * arguments (tile: 0 or a plain shape), flags bit 4 set at every updated
+ * arguments (tile: any shape, plain or MPR_TILE_COMPACT), flags bit 4 set at every updated
  * site, and bond_energy summed in fixed point of 2^-30. */
 int32_t mpr_diag_half_sweep_fp64(mpr_ctx *ctx, int32_t nx, int32_t ny, double *phi,
                                  const uint8_t *sampled, int32_t colour, double T, double a,

@@ -1929,7 +1929,7 @@ struct ChainSet {
     std::vector<int64_t> h_start;  // host copies (kept until their upload is done)
     std::vector<int32_t> h_ids;
     Redo redo = {nullptr, nullptr};      // deferred double-precision updates (zeroed)
-    bool fp64 = false;                   // double-precision chains (plain shapes, no deferral)
+    bool fp64 = false;                   // double-precision chains (no deferred redo)
     float *states_out = nullptr;         // recorded equilibrium states (nullable)
     int64_t states_n_total = 0;          // sites of the whole batch (stride of a state)
     int K = 0;

@@ -158,19 +158,12 @@ __device__ __forceinline__ float sin_poly(float x)
     return fmaf(p * x2, x, x);
 }
 
-__device__ __forceinline__ float cos_poly(float x)
-{
-    const float x2 = x * x;
-    float p = fmaf(x2, 2.315392157e-05f, -1.385370386e-03f);
-    p = fmaf(p, x2, 4.166358337e-02f);
-    p = fmaf(p, x2, -4.999990463e-01f);
-    return fmaf(p, x2, 9.999999404e-01f);
-}
-
 // The same polynomials taking a full angle d and returning 2 sin(d/2) and
-// cos(d/2) from d2 = d * d: every coefficient is the one above divided by a
-// power of two, so the results equal 2 sin_poly(d/2) and cos_poly(d/2) bit
-// for bit, without the halving and doubling.
+// cos(d/2) from d2 = d * d: every coefficient is the |x| <= pi/2 one divided
+// by a power of two (cosine: 9.999999404e-01, -4.999990463e-01,
+// 4.166358337e-02, -1.385370386e-03, 2.315392157e-05 for x^0 .. x^8), so the
+// results equal 2 sin_poly(d/2) and the cosine polynomial at d/2 bit for bit,
+// without the halving and doubling.
 __device__ __forceinline__ float sin2_half_poly(float d, float d2)
 {
     float p = fmaf(d2, 2.601902224e-06f / 256.0f, -1.980741799e-04f / 64.0f);
