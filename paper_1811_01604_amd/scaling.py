@@ -35,7 +35,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_case(ctx, L: int, p: float, rep: int = 0, K: int = 100) -> dict:
+def run_case(ctx, L: int, p: float, rep: int = 0, K: int = 100, R: int = 1, throughput: bool = True) -> dict:
     import torch
     if ROOT not in sys.path:
         sys.path.insert(0, ROOT)
@@ -49,7 +49,7 @@ def run_case(ctx, L: int, p: float, rep: int = 0, K: int = 100) -> dict:
     # a shorter e(T, L) table than the library default (12 temperatures,
     # 100 + 200 sweeps): the study times the sweep, not the table
     base = dict(table_nT=12, table_burn=100, table_meas=200, seed=7000 + rep)
-    prm = mpr.default_params(R=1, K=K, **base)
+    prm = mpr.default_params(R=R, K=K, **base)
     ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
     zz = ctx.map_to_angles(imgs, z, mk, phi)
     ctx.estimate_temperature(imgs, phi, mk, prm, ws)  # builds and caches the table
@@ -58,12 +58,16 @@ def run_case(ctx, L: int, p: float, rep: int = 0, K: int = 100) -> dict:
     zz = ctx.map_to_angles(imgs, z, mk, phi)
     _, T, _ = ctx.estimate_temperature(imgs, phi, mk, prm, ws)
     st = ctx.simulate(imgs, phi, mk, T, prm, ws, ps)
-    ctx.predict(imgs, z, mk, ps, zz, K, zh)
+    ctx.predict(imgs, z, mk, ps, zz, R * K, zh)
     torch.cuda.synchronize()
     t_fill = time.perf_counter() - t0
     gap = im.mask == 0
     zt = im.z.astype(np.float32)
     mae = float(np.mean(np.abs(zh.cpu().numpy()[gap] - zt[gap])))
+    if not throughput:
+        return {"L": L, "p_removed": p, "rep": rep, "R": R, "K": K, "gap_sites": int(gap.sum()),
+                "relax_sweeps_mean": float(np.mean([s["relax_sweeps"] for s in st])), "time_to_fill_s": t_fill,
+                "MAE": mae}
     # throughput with the GPU full: R chains, 100 relaxation sweeps + 1 state
     R = int(min(256, max(1, (1 << 27) // (L * L))))
     prm_t = mpr.default_params(R=R, K=1, fixed_relax=100, **base)
@@ -83,13 +87,48 @@ def run_case(ctx, L: int, p: float, rep: int = 0, K: int = 100) -> dict:
     }
 
 
+def layouts(args):
+    """Time to fill and MAE of the same M in several (R, K) layouts."""
+    import paper_1811_01604_amd as mpr
+    ctx = mpr.Context(0)
+    lay = [tuple(int(v) for v in t.split("x")) for t in args.layouts.split(",")]
+    rows = []
+    for L in (int(v) for v in args.sizes.split(",")):
+        for p in (float(v) for v in args.size_fractions.split(",")):
+            for R, K in lay:
+                # an untimed fill of another field first: the block shape is tuned per chain count
+                run_case(ctx, L, p, args.reps, K=K, R=R, throughput=False)
+                rs = [run_case(ctx, L, p, rep, K=K, R=R, throughput=False) for rep in range(args.reps)]
+                r = {"L": L, "p_removed": p, "R": R, "K": K, "reps": args.reps,
+                     "time_to_fill_s": float(np.mean([x["time_to_fill_s"] for x in rs])),
+                     "MAE": float(np.mean([x["MAE"] for x in rs])),
+                     "MAE_per_rep": [x["MAE"] for x in rs],
+                     "relax_sweeps_mean": float(np.mean([x["relax_sweeps_mean"] for x in rs]))}
+                rows.append(r)
+                print(json.dumps(r), flush=True)
+                log(f"L={L} p={p} ({R},{K}): fill {r['time_to_fill_s'] * 1e3:.1f} ms, MAE {r['MAE']:.4f}")
+    ctx.close()
+    print("| L | p | (R, K) | time to fill (ms) | MAE (mean over fields) | relax sweeps |")
+    print("|---|---|---|---|---|---|")
+    for r in rows:
+        print(f"| {r['L']} | {r['p_removed']:.2f} | ({r['R']}, {r['K']}) | {r['time_to_fill_s'] * 1e3:.1f} | "
+              f"{r['MAE']:.4f} | {r['relax_sweeps_mean']:.1f} |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sizes", default="32,64,128,256,512,1024,2048,4096,8192")
     ap.add_argument("--size-fractions", default="0.33,0.66")
     ap.add_argument("--fraction-size", type=int, default=2048)
     ap.add_argument("--fractions", default="0.05,0.2,0.35,0.5,0.65,0.8,0.95")
+    ap.add_argument("--layouts", default="",
+                    help="instead of the study above: time to fill and MAE of M = R K realizations in each "
+                         "layout RxK (e.g. 1x100,4x25,10x10) for every size in --sizes at p = --size-fractions, "
+                         "over --reps fields")
+    ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
+    if args.layouts:
+        return layouts(args)
     import paper_1811_01604_amd as mpr
     ctx = mpr.Context(0)
     rows = []
