@@ -192,7 +192,7 @@ def main():
     ap.add_argument("--K", type=int, default=1)
     ap.add_argument("--fixed-sweeps", type=int, default=-1,
                     help="relax exactly this many sweeps instead of the stopping rule")
-    ap.add_argument("--cpu-sweeps", type=int, default=5)
+    ap.add_argument("--cpu-sweeps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-scaling", default="",
                     help="only the CPU baseline of the lattice-size study: time the oracle on its images "
