@@ -15,6 +15,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# a prebuilt library to load instead (the pins' mutant test builds copies of
+# oracle.c with one planted mistake each and runs the pins against them)
+_LIB_OVERRIDE = os.environ.get("MPR_ORACLE_LIB")
 
 OK, ERR_ARG, ERR_DEGENERATE = 0, 1, 2
 MODE_FULL, MODE_OR_ONLY = 0, 1
@@ -58,7 +61,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(_LIB_OVERRIDE if _LIB_OVERRIDE else build())
         _declare(_lib)
     return _lib
 
@@ -128,6 +131,29 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     lib().oracle_philox4x32_10(_p(c), _p(k), _p(out))
     return out
+
+
+def philox4x32_10_np(ctr, key) -> np.ndarray:
+    """Philox4x32-10 (Salmon et al., SC'11) of many counters at once, in numpy:
+    ctr (n, 4) uint32, key (2,) uint32 -> (n, 4) uint32.  A second, vectorised
+    implementation beside the C one (each round: two 32 x 32 -> 64-bit
+    products of counter words 0 and 2 with the round multipliers, their high
+    halves xored with words 1, 3 and the key, the key bumped by the Weyl
+    constants), for comparisons over millions of counters."""
+    c = np.array(ctr, dtype=np.uint64).reshape(-1, 4)
+    k0, k1 = np.uint64(int(key[0]) & 0xFFFFFFFF), np.uint64(int(key[1]) & 0xFFFFFFFF)
+    m0, m1 = np.uint64(0xD2511F53), np.uint64(0xCD9E8D57)
+    w0, w1 = np.uint64(0x9E3779B9), np.uint64(0xBB67AE85)
+    lo = np.uint64(0xFFFFFFFF)
+    s32 = np.uint64(32)
+    x0, x1, x2, x3 = c[:, 0], c[:, 1], c[:, 2], c[:, 3]
+    for _ in range(10):
+        p0 = m0 * x0
+        p1 = m1 * x2
+        x0, x1, x2, x3 = (p1 >> s32) ^ x1 ^ k0, p1 & lo, (p0 >> s32) ^ x3 ^ k1, p0 & lo
+        k0 = (k0 + w0) & lo
+        k1 = (k1 + w1) & lo
+    return np.stack([x0, x1, x2, x3], axis=1).astype(np.uint32)
 
 
 def site_uniforms(seed, nx, x, y, sweep, chain, stream):

@@ -56,6 +56,20 @@ def test_philox_matches_rocrand(rocrand_helper):
         want = [int(w, 16) for w in line.split()]
         got = oracle.philox4x32_10(r[:4], r[4:]).tolist()
         assert got == want, (r, got, want)
+        # the vectorised numpy implementation (used for comparisons over millions of counters)
+        assert oracle.philox4x32_10_np(r[None, :4], r[4:])[0].tolist() == want
+
+
+def test_numpy_philox_equals_c_philox_in_batches():
+    """The numpy Philox over a batch of 20000 counters (one key) equals the C
+    implementation counter by counter."""
+    rng = np.random.default_rng(17)
+    ctr = rng.integers(0, 2**32, size=(20000, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:2] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4]
+    key = np.array([0xDEADBEEF, 0x12345678], np.uint32)
+    batch = oracle.philox4x32_10_np(ctr, key)
+    for i in list(range(500)) + list(range(19500, 20000)):
+        assert np.array_equal(batch[i], oracle.philox4x32_10(ctr[i], key)), i
 
 
 def test_site_uniforms_layout_and_range():
@@ -603,3 +617,73 @@ def test_holdout_mask_and_q_selection():
     zh = oracle.predict(z, fit2, ps, 10, zz)
     h2 = (mm == 1) & (fit2 == 0)
     assert abs(errs[1] - np.mean(np.abs(z[h2] - zh[h2]))) < 1e-12
+
+
+# --------------------------------------------------------- limits of the chain
+def test_low_temperature_fill_reaches_the_energy_minimum():
+    """As T -> 0 the chains settle in the minimum of the energy (Eq.
+    Hamiltonian_mod) given the samples: the mean of 10 states at T = 1e-8
+    equals, at every gap site, the minimiser that L-BFGS finds for the energy
+    written here in closed form (gradient included), within the thermal
+    spread ~sqrt(T); at T = 1e-6 within 10x that; at T = 1e-2 it is visibly
+    farther (the test can tell temperatures apart)."""
+    from scipy.optimize import minimize
+    L = 32
+    z = synth.matern_field(L, L, 2.5, 0.1, 50.0, 10.0, 71)
+    m = synth.random_mask(L, L, 0.3, 72)
+    po, _ = oracle.map_to_angles(z, m)
+    g = m == 0
+
+    def energy_and_grad(x):
+        phi = po.copy()
+        phi[g] = x
+        th = Q * phi
+        dx, dy = th[:, 1:] - th[:, :-1], th[1:, :] - th[:-1, :]
+        e = np.sum(1.0 - np.cos(dx)) + np.sum(1.0 - np.cos(dy))
+        gth = np.zeros_like(th)
+        sx, sy = np.sin(dx), np.sin(dy)
+        gth[:, 1:] += sx
+        gth[:, :-1] -= sx
+        gth[1:, :] += sy
+        gth[:-1, :] -= sy
+        return e, Q * gth[g]
+
+    r = minimize(energy_and_grad, np.full(int(g.sum()), math.pi), jac=True, method="L-BFGS-B",
+                 bounds=[(0.0, TWO_PI)] * int(g.sum()), options=dict(maxiter=20000, ftol=1e-15, gtol=1e-12))
+    assert r.success and np.max(np.abs(r.jac)) < 1e-7  # position error below ~4e-5 rad
+    dist = {}
+    for T in (1e-2, 1e-6, 1e-8):
+        ps, _, _, _ = oracle.simulate(po, m, T, oracle.default_params(R=1, K=10, seed=5))
+        dist[T] = float(np.max(np.abs(ps[g] / 10.0 - r.x)))
+    assert dist[1e-8] <= 2e-4, dist
+    assert dist[1e-6] <= 2e-3, dist
+    assert dist[1e-2] > 10 * dist[1e-6], dist
+
+
+def test_mirrored_data_mirror_the_prediction_in_distribution():
+    """z -> z_min + z_max - z maps phi -> 2 pi - phi at the samples (exactly,
+    up to rounding) and leaves the energy unchanged, so the fill of the
+    mirrored data is the mirror of the fill in distribution: over 8 seeds
+    each, the mean absolute errors of the two fills agree within 4 standard
+    errors (and 0.5%)."""
+    im = synth.workload_l64()
+    z, m = im.z.astype(np.float64), im.mask
+    g = m == 0
+    zmin, zmax = z[m == 1].min(), z[m == 1].max()
+    zm = zmin + zmax - z
+    po, zz = oracle.map_to_angles(z, m)
+    pm, zzm = oracle.map_to_angles(zm, m)
+    assert np.max(np.abs(pm[m == 1] - (TWO_PI - po[m == 1]))) <= 1e-13
+    assert np.allclose(zzm, zz)
+    mae = {}
+    for name, phi, zr, data in (("plain", po, zz, z), ("mirror", pm, zzm, zm)):
+        v = []
+        for seed in range(8):
+            ps, _, _, _ = oracle.simulate(phi, m, 0.18, oracle.default_params(R=1, K=100, seed=100 + seed))
+            zh = oracle.predict(data, m, ps, 100, zr)
+            v.append(float(np.mean(np.abs(zh[g] - data[g]))))
+        mae[name] = np.array(v)
+    d = mae["mirror"].mean() - mae["plain"].mean()
+    se = math.sqrt(mae["mirror"].var(ddof=1) / 8 + mae["plain"].var(ddof=1) / 8)
+    assert abs(d) <= 4 * se and abs(d) <= 0.005 * mae["plain"].mean(), (mae, d, se)
+
