@@ -394,6 +394,32 @@ def test_temperature_table_on_capped_grid(ctx):  # ctx: skips without a GPU; the
         assert abs(T_big[i] / T_o - 1.0) < 0.03
 
 
+@pytest.mark.parametrize("ny,nx,seed,tol", [(40, 72, 41, 0.03), (1, 300, 43, 0.05)])
+def test_temperature_estimate_on_rectangular_and_line_images(ctx, ny, nx, seed, tol):
+    """e(T, L) of a rectangular grid (bonds nx (ny - 1) + ny (nx - 1)) and of a
+    single row: T_hat is the oracle's inversion of the oracle's table for the
+    same shape, within a few times the seed-to-seed spread of that table
+    (0.7% and 1.8%)."""
+    tab = dict(table_nT=12, table_T_lo=0.01, table_T_hi=2.0, table_burn=100, table_meas=300, K=1)
+    z = synth.matern_field(nx, max(ny, 2), 0.5, 0.2, 50.0, 10.0, seed)[:ny]
+    m = synth.random_mask(nx, ny, 0.5, seed + 1)
+    imgs = mpr.images([(ny, nx)])
+    zd, mk = dev(z.astype(np.float32)), dev(m, torch.uint8)
+    phi = torch.zeros_like(zd)
+    ctx.map_to_angles(imgs, zd, mk, phi)
+    prm = mpr.default_params(**tab)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    e_s, T_hat, cl = ctx.estimate_temperature(imgs, phi, mk, prm, ws)
+    po, _ = oracle.map_to_angles(z.astype(np.float32).astype(np.float64), m)
+    e_o, _ = oracle.sample_energy(po.astype(np.float32).astype(np.float64), m)
+    assert abs(e_s[0] - e_o) <= 1e-12
+    Tg = oracle.temperature_grid(12, 0.01, 2.0)
+    T_o, cl_o = oracle.invert_temperature(Tg, oracle.energy_table(nx, ny, Tg, 100, 300, seed=prm.seed), e_o)
+    say(f"  {ny} x {nx}: T_hat gpu {T_hat[0]:.5f} oracle {T_o:.5f}")
+    assert not cl[0] and not cl_o
+    assert abs(T_hat[0] / T_o - 1.0) < tol
+
+
 def test_simulate_free_running_short_chains(ctx):
     """After one sweep GPU and oracle agree per site; divergence grows afterwards."""
     im = synth.workload_l64()
