@@ -518,6 +518,63 @@ def test_no_gap_image_and_batch_independence(ctx):
     assert np.all(together[2] == 0.0)
 
 
+def test_images_at_arbitrary_offsets(ctx):
+    """mpr_image.offset places each image anywhere in the per-site buffers:
+    two images stored in reverse order with unused elements around them give
+    the packed batch's map, sums, spread, prediction and quantiles bit for
+    bit, and the unused elements are left as they were."""
+    a = synth.workload_l64()
+    b_z = synth.matern_field(40, 24, 1.5, 0.1, 50, 10, 5)
+    b_m = synth.random_mask(40, 24, 0.4, 6)
+    parts = [(a.z, a.mask), (b_z, b_m)]
+    prm = mpr.default_params(R=2, K=3, spread=1, seed=23)
+    T = np.array([0.15, 0.05])
+    M = prm.R * prm.K
+    probs = [0.1, 0.5, 0.9]
+
+    def run(offsets, total):
+        imgs = (mpr.Image * 2)()
+        for i, ((zz_, _), off) in enumerate(zip(parts, offsets)):
+            imgs[i].ny, imgs[i].nx = zz_.shape
+            imgs[i].offset, imgs[i].id = off, i
+        z = np.full(total, -7.0, np.float32)
+        m = np.full(total, 1, np.uint8)
+        for (zz_, mm), off in zip(parts, offsets):
+            z[off:off + zz_.size] = zz_.astype(np.float32).ravel()
+            m[off:off + zz_.size] = mm.ravel()
+        zd, mk = dev(z), dev(m, torch.uint8)
+        sentinel = -3.25
+        phi = torch.full_like(zd, sentinel)
+        zz = ctx.map_to_angles(imgs, zd, mk, phi)
+        ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+        ps, m2, zh, zs = (torch.full_like(zd, sentinel) for _ in range(4))
+        N = mpr.sites_of(imgs)  # the stride of a recorded state
+        st = torch.full((M, N), sentinel, device="cuda")
+        ctx.simulate(imgs, phi, mk, T, prm, ws, ps, phi_m2=m2, phi_states=st)
+        ctx.predict(imgs, zd, mk, ps, zz, M, zh)
+        ctx.spread(imgs, mk, m2, zz, M, zs)
+        zq = torch.full((len(probs), N), sentinel, device="cuda")
+        ctx.quantiles(imgs, zd, mk, st, M, probs, zz, zq)
+        outs = [t.cpu().numpy() for t in (phi, ps, m2, zh, zs)] + [st.cpu().numpy(), zq.cpu().numpy()]
+        used = np.zeros(total, bool)
+        for (zz_, _), off in zip(parts, offsets):
+            used[off:off + zz_.size] = True
+        for o in outs:
+            assert np.all(o[..., ~used[:o.shape[-1]]] == sentinel)  # unused elements untouched
+        per_image = []
+        for (zz_, _), off in zip(parts, offsets):
+            per_image.append([o[..., off:off + zz_.size].copy() for o in outs])
+        return zz, per_image
+
+    n0, n1 = a.z.size, b_z.size
+    zz_p, packed = run([0, n0], n0 + n1)
+    zz_s, spaced = run([n1 + 777, 129], n0 + n1 + 1500)  # reversed, with gaps
+    assert np.array_equal(zz_p, zz_s)
+    for i in range(2):
+        for k, (x, y) in enumerate(zip(packed[i], spaced[i])):
+            assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (i, k)
+
+
 # a fixed temperature near the estimate for the L=1024 workload
 T_L1024 = 2.6e-4
 
