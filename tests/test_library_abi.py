@@ -136,3 +136,25 @@ def test_binding_rejects_host_tensors_and_short_buffers():
     with pytest.raises(ValueError, match="must be a tensor on cuda:0"):
         ctx._t(fake, "phi", torch.float32, 88)
     ctx._h = C.c_void_p()  # nothing to destroy
+
+
+def test_batch_validation():
+    """An empty batch, a negative offset and an image id in the range the
+    temperature tables use for their random streams (>= 0x80000000) are
+    refused by the host checks."""
+    lib = mpr.load()
+    p = mpr.default_params(R=1, K=1)
+    ws = lambda imgs, n: lib.mpr_workspace_size(imgs, n, C.byref(p))
+    good = mpr.images([(8, 8), (4, 6)])
+    assert ws(good, 2) > 0
+    assert ws(good, 0) < 0
+    bad = mpr.images([(8, 8)], ids=[0x80000000])
+    assert ws(bad, 1) < 0
+    ok = mpr.images([(8, 8)], ids=[0x7FFFFFFF])
+    assert ws(ok, 1) > 0
+    neg = mpr.images([(8, 8)])
+    neg[0].offset = -1
+    assert ws(neg, 1) < 0
+    zero = mpr.images([(8, 8)])
+    zero[0].nx = 0
+    assert ws(zero, 1) < 0
