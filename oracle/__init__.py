@@ -84,7 +84,7 @@ def _declare(L):
     L.oracle_sg_slope.argtypes = [P, i32, i32]
     L.oracle_sg_slope.restype = d
     L.oracle_simulate.argtypes = [i32, i32, P, P, d, C.POINTER(Params), P, P, P, P,
-                                  C.POINTER(ChainStats), P, i32, P]
+                                  C.POINTER(ChainStats), P, i32, P, P, P]
     L.oracle_simulate.restype = i32
     L.oracle_predict.argtypes = [i32, i32, P, P, P, i32, P, P]
     L.oracle_spread.argtypes = [i32, i32, P, P, P, i32, P, P]
@@ -211,10 +211,13 @@ def sg_slope(e, degree=1) -> float:
 
 
 def simulate(phi, sampled, T, params: Params, phi_init=None, trace_len=0, want_last=False, want_sq=False,
-             want_states=False):
+             want_states=False, want_control=False):
     """Returns (phi_sum, stats, e_trace, phi_last), then phi_sq_sum (sum of
     the squared states at gap sites) when want_sq, then the M = R K states
-    (array M x ny x nx, state r K + k) when want_states."""
+    (array M x ny x nx, state r K + k) when want_states, then (a_trace,
+    acc_trace) when want_control: per chain and sweep t < trace_len
+    (relaxation and equilibrium) the a its proposals used and the accepted
+    count (NaN past the chain's last sweep)."""
     phi, s = _f64(phi), _u8(sampled)
     ny, nx = phi.shape
     phi_sum = np.zeros_like(phi)
@@ -224,12 +227,16 @@ def simulate(phi, sampled, T, params: Params, phi_init=None, trace_len=0, want_l
     trace = np.zeros((params.R, trace_len)) if trace_len else None
     last = np.zeros_like(phi) if want_last else None
     init = _f64(phi_init) if phi_init is not None else None
+    a_tr = np.full((params.R, trace_len), np.nan) if want_control else None
+    acc_tr = np.full((params.R, trace_len), np.nan) if want_control else None
     rc = lib().oracle_simulate(nx, ny, _p(phi), _p(s), T, C.byref(params),
                                _p(init) if init is not None else None, _p(phi_sum),
                                _p(phi_sq) if phi_sq is not None else None,
                                _p(states) if states is not None else None, stats,
                                _p(trace) if trace is not None else None, trace_len,
-                               _p(last) if last is not None else None)
+                               _p(last) if last is not None else None,
+                               _p(a_tr) if a_tr is not None else None,
+                               _p(acc_tr) if acc_tr is not None else None)
     if rc:
         raise OracleError(rc, "simulate")
     st = [dict(relax_sweeps=c.relax_sweeps, not_converged=c.not_converged, a_final=c.a_final,
@@ -239,6 +246,8 @@ def simulate(phi, sampled, T, params: Params, phi_init=None, trace_len=0, want_l
         out += (phi_sq,)
     if want_states:
         out += (states,)
+    if want_control:
+        out += ((a_tr, acc_tr),)
     return out
 
 

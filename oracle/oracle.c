@@ -343,11 +343,14 @@ double oracle_sg_slope(const double *e, int n, int degree)
  * samples).  e_trace (nullable, R x trace_len) receives e after each
  * relaxation sweep.  phi_last (nullable) receives the final state of the last
  * chain.  phi_states (nullable, M x nx*ny) receives every equilibrium state,
- * state r*K + k of chain r after its k-th equilibrium sweep. */
+ * state r*K + k of chain r after its k-th equilibrium sweep.  a_trace and
+ * acc_trace (nullable, R x trace_len) receive, for every sweep t of a chain
+ * (relaxation and equilibrium, t < trace_len), the a the sweep's proposals
+ * used and the number of proposals it accepted. */
 int oracle_simulate(int nx, int ny, const double *phi, const uint8_t *sampled, double T,
                     const oracle_params *p, const double *phi_init, double *phi_sum,
                     double *phi_sq_sum, double *phi_states, oracle_chain_stats *stats, double *e_trace,
-                    int trace_len, double *phi_last)
+                    int trace_len, double *phi_last, double *a_trace, double *acc_trace)
 {
     if (nx <= 0 || ny <= 0 || p->R < 1 || p->K < 0 || !(T > 0.0) || p->n_f < 1 || p->n_fit < 2)
         return O_ERR_ARG;
@@ -390,6 +393,8 @@ int oracle_simulate(int nx, int ny, const double *phi, const uint8_t *sampled, d
                                              (uint32_t)r, p->stream, O_MODE_FULL, NULL);
                 acc += oracle_half_sweep(nx, ny, s, sampled, 1, T, a, p->q, p->seed, (uint32_t)t,
                                          (uint32_t)r, p->stream, O_MODE_FULL, NULL);
+                if (a_trace && t < trace_len) a_trace[(long)r * trace_len + t] = a;
+                if (acc_trace && t < trace_len) acc_trace[(long)r * trace_len + t] = (double)acc;
                 A = (double)acc / (double)P;
                 if (A < p->a_targ) a = 1.0 + (double)(t + 1) / p->k_a;
                 double e = oracle_energy(nx, ny, s, p->q) / n_gp;
@@ -409,10 +414,12 @@ int oracle_simulate(int nx, int ny, const double *phi, const uint8_t *sampled, d
         double a_eq = p->eq_a_mode ? a : 1.0;
         for (int j = 0; j < p->K; ++j) {
             if (P > 0) {
-                oracle_half_sweep(nx, ny, s, sampled, 0, T, a_eq, p->q, p->seed, (uint32_t)t,
-                                  (uint32_t)r, p->stream, O_MODE_FULL, NULL);
-                oracle_half_sweep(nx, ny, s, sampled, 1, T, a_eq, p->q, p->seed, (uint32_t)t,
-                                  (uint32_t)r, p->stream, O_MODE_FULL, NULL);
+                long acc = oracle_half_sweep(nx, ny, s, sampled, 0, T, a_eq, p->q, p->seed, (uint32_t)t,
+                                             (uint32_t)r, p->stream, O_MODE_FULL, NULL);
+                acc += oracle_half_sweep(nx, ny, s, sampled, 1, T, a_eq, p->q, p->seed, (uint32_t)t,
+                                         (uint32_t)r, p->stream, O_MODE_FULL, NULL);
+                if (a_trace && t < trace_len) a_trace[(long)r * trace_len + t] = a_eq;
+                if (acc_trace && t < trace_len) acc_trace[(long)r * trace_len + t] = (double)acc;
             }
             ++t;
             for (long i = 0; i < n; ++i)

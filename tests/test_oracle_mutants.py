@@ -53,6 +53,17 @@ MUTANTS = [
      "double x0 = log(Tg[k]), x1 = log(Tg[k + 1]);\n        *T_hat = exp(x0 + (ys - yf[k]) * (x1 - x0) / (yf[k + 1] - yf[k]));",
      "double x0 = Tg[k], x1 = Tg[k + 1];\n        *T_hat = x0 + (ys - yf[k]) * (x1 - x0) / (yf[k + 1] - yf[k]);",
      "invert_temperature_on_exact_power_law"),
+    ("a-rule indexed by i instead of i + 1",
+     "if (A < p->a_targ) a = 1.0 + (double)(t + 1) / p->k_a;",
+     "if (A < p->a_targ) a = 1.0 + (double)t / p->k_a;",
+     "a_rule or control_trace"),
+    ("acceptance ratio over all sites instead of the P gaps",
+     "                A = (double)acc / (double)P;",
+     "                A = (double)acc / (double)n;",
+     "a_rule or control_trace"),
+    ("final a carried into the equilibrium sweeps",
+     "double a_eq = p->eq_a_mode ? a : 1.0;", "double a_eq = a;",
+     "a_rule or control_trace"),
 ]
 
 

@@ -422,6 +422,89 @@ def test_stopping_rule_and_imax():
     assert st[0]["relax_sweeps"] == 8 and st[0]["not_converged"] == 1
 
 
+def _a_rule_expected(acc, P, a_targ, k_a, n_relax):
+    """Algorithm 2 step 5.2 as printed, applied by the test to the accepted
+    counts: a(0) = 1; a(i+1) = 1 + (i+1)/k_a when A(i) = accepted(i)/P is
+    below the target, else a(i+1) = a(i).  Returns a(0) .. a(n_relax)."""
+    a = [1.0]
+    for i in range(n_relax):
+        A = acc[i] / P
+        a.append(1.0 + (i + 1) / k_a if A < a_targ else a[-1])
+    return a
+
+
+@pytest.mark.parametrize("a_targ,k_a,eq_a_mode,fixed", [(0.3, 3.0, 0, -1), (0.6, 2.5, 0, -1),
+                                                        (0.3, 3.0, 1, -1), (0.45, 4.0, 0, 17)])
+def test_relaxation_control_follows_the_printed_a_rule(a_targ, k_a, eq_a_mode, fixed):
+    """Algorithm 2 steps 5.2 and 6.2: the a each sweep's proposals use, read
+    from the oracle's per-sweep trace, follows the printed rule applied to the
+    sweep's accepted count over the gap count P (taken from the mask by the
+    test), and the equilibrium sweeps use a = 1 (or the final a when asked)."""
+    im = synth.workload_l64()
+    phi, _ = oracle.map_to_angles(im.z, im.mask)
+    P = int((im.mask == 0).sum())
+    K = 4
+    p = oracle.default_params(R=2, K=K, a_targ=a_targ, k_a=k_a, eq_a_mode=eq_a_mode, fixed_relax=fixed,
+                              seed=3000)
+    _, st, _, _, (a_tr, acc_tr) = oracle.simulate(phi, im.mask, 0.18, p, trace_len=400, want_control=True)
+    crossed = False
+    for c, a_row, acc_row in zip(st, a_tr, acc_tr):
+        n = c["relax_sweeps"]
+        want = _a_rule_expected(acc_row, P, a_targ, k_a, n)
+        assert list(a_row[:n]) == want[:n]
+        assert c["a_final"] == want[n]
+        a_eq = want[n] if eq_a_mode else 1.0
+        assert np.all(a_row[n:n + K] == a_eq) and np.all(np.isnan(a_row[n + K:]))
+        assert c["A_last"] == acc_row[n - 1] / P
+        # A is over the P gaps: some sweep is at or above the target while its
+        # count over all sites is below it
+        A = acc_row[:n] / P
+        crossed |= bool(np.any((A >= a_targ) & (acc_row[:n] / im.mask.size < a_targ)))
+    assert crossed
+
+
+def test_a_rule_always_below_target_gives_closed_form():
+    """With the target above every acceptance ratio (A_targ = 1.0), step 5.2
+    raises a after every relaxation sweep: a_final = 1 + relax_sweeps/k_a
+    exactly; with A_targ = 0 it never does and a stays 1."""
+    im = synth.workload_l64()
+    phi, _ = oracle.map_to_angles(im.z, im.mask)
+    for fixed in (-1, 9):
+        p = oracle.default_params(R=1, K=2, a_targ=1.0, k_a=3.0, fixed_relax=fixed, seed=3001)
+        _, st, _, _, (a_tr, _) = oracle.simulate(phi, im.mask, 0.18, p, trace_len=300, want_control=True)
+        n = st[0]["relax_sweeps"]
+        assert st[0]["a_final"] == 1.0 + n / 3.0
+        assert a_tr[0][n - 1] == 1.0 + (n - 1) / 3.0 and np.all(a_tr[0][n:n + 2] == 1.0)
+        p = oracle.default_params(R=1, K=2, a_targ=0.0, fixed_relax=fixed, seed=3001)
+        _, st, _, _, (a_tr, _) = oracle.simulate(phi, im.mask, 0.18, p, trace_len=300, want_control=True)
+        assert st[0]["a_final"] == 1.0 and np.all(a_tr[0][:st[0]["relax_sweeps"] + 2] == 1.0)
+
+
+def test_control_trace_replays_through_the_half_sweeps():
+    """The trace is what the chain did: replaying each sweep with the pinned
+    half-sweep, at the traced a, reproduces the traced accepted counts and the
+    simulation's sum of states bit for bit."""
+    z = synth.matern_field(24, 20, 0.5, 0.2, 50.0, 10.0, 11)
+    mask = synth.random_mask(24, 20, 0.5, 12)
+    phi, _ = oracle.map_to_angles(z, mask)
+    R, K, n_relax = 2, 3, 11
+    p = oracle.default_params(R=R, K=K, fixed_relax=n_relax, a_targ=0.5, seed=77)
+    ps, st, _, _, (a_tr, acc_tr) = oracle.simulate(phi, mask, 0.05, p, trace_len=40, want_control=True)
+    rng_sum = np.zeros_like(ps)
+    for r in range(R):
+        s = phi.copy()
+        u = np.array([[oracle.site_uniforms(77, 24, x, y, oracle.INIT_SWEEP, r, 0)[0] for x in range(24)]
+                      for y in range(20)])
+        s[mask == 0] = TWO_PI * u[mask == 0]
+        for t in range(n_relax + K):
+            s, a0, _ = oracle.half_sweep(s, mask, 0, 0.05, a_tr[r, t], t, chain=r, seed=77)
+            s, a1, _ = oracle.half_sweep(s, mask, 1, 0.05, a_tr[r, t], t, chain=r, seed=77)
+            assert a0 + a1 == acc_tr[r, t]
+            if t >= n_relax:
+                rng_sum[mask == 0] += s[mask == 0]
+    assert np.array_equal(rng_sum, ps)
+
+
 def test_no_gaps_is_a_no_op():
     z = synth.matern_field(8, 8, 0.5, 0.2, 50, 10, 1)
     m = np.ones((8, 8), np.uint8)
