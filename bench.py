@@ -182,6 +182,48 @@ def cnn_inference(ctx, model, size: int = 2048, reps: int = 5) -> dict:
             "bytes_per_forward": nbytes, "tflops": flops / t / 1e12, "bf16_mfma_peak_tflops": 2500.0}
 
 
+def cloud_leg(ctx, mpr, prm, steps: int) -> dict:
+    """The same fill (R chains, K states, stopping rule) on the L=4096 field
+    with the 40% cloud mask, `steps` timed fills; the e(T, L) table of the
+    grid size and the tuned block shape are the random mask's, cached in the
+    context by the main measurement."""
+    import numpy as np
+    import torch
+    im, desc = make_workload("l4096-cloud")
+    imgs = mpr.images([(im.ny, im.nx)])
+    z = torch.from_numpy(im.z.astype(np.float32)).cuda()
+    mk = torch.from_numpy(im.mask).cuda()
+    phi, ps, zh = torch.zeros_like(z), torch.zeros_like(z), torch.zeros_like(z)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    P = int((im.mask == 0).sum())
+
+    def fill():
+        zz = ctx.map_to_angles(imgs, z, mk, phi)
+        _, T, _ = ctx.estimate_temperature(imgs, phi, mk, prm, ws)
+        st = ctx.simulate(imgs, phi, mk, T, prm, ws, ps)
+        ctx.predict(imgs, z, mk, ps, zz, prm.R * prm.K, zh)
+        return st, float(T[0])
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    updates, sweeps = 0, []
+    for _ in range(steps):
+        st, T = fill()
+        s = [x["relax_sweeps"] + prm.K for x in st]
+        sweeps.extend(s)
+        updates += sum(s) * P
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g = im.mask == 0
+    mae = float(np.mean(np.abs(zh.cpu().numpy()[g] - im.z.astype(np.float32)[g])))
+    log(f"l4096 cloud: {updates / dt:.3e} site-updates/s, {dt / steps:.1f} s per fill, "
+        f"{np.mean(sweeps):.0f} sweeps per chain")
+    del ws
+    return {"workload": desc, "value": updates / dt, "unit": "site-updates/s", "steps": steps,
+            "ms_per_step": dt / steps * 1e3, "chains_R": prm.R, "states_per_chain_K": prm.K, "gap_sites": P,
+            "mean_sweeps_per_chain": float(np.mean(sweeps)), "T_hat": T, "MAE": mae}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,11 +244,15 @@ def main():
                     help="run one 1 GiB plain copy first (calibrates HBM byte counters)")
     ap.add_argument("--tile", default="auto",
                     help="sweep block shape: auto (tuned), or rows 1/2/4/8, with a 'c' suffix for the compacted "
-                         "shapes 2c/4c/8c (for profiling runs that must see one kernel)")
+                         "shapes 2c/4c/8c, or 16f/24f/32f for the fused tile sweep (for profiling runs that must "
+                         "see one kernel)")
     ap.add_argument("--fp64", action="store_true",
                     help="run the chains in double precision (the paper's DP variant)")
-    ap.add_argument("--warm-seeds", type=int, default=8,
+    ap.add_argument("--warm-seeds", type=int, default=32,
                     help="images per mask type for the warm-start comparison at L=2048 (0 = skip)")
+    ap.add_argument("--cloud-steps", type=int, default=1,
+                    help="timed steps of the same fill with the 40%% cloud mask, reported as l4096_cloud "
+                         "(0 = skip; only with the default workload)")
     args = ap.parse_args()
     if args.cpu_scaling:
         cpu_baseline_scaling([int(v) for v in args.cpu_scaling.split(",")])
@@ -220,7 +266,15 @@ def main():
     import torch
 
     import paper_1811_01604_amd as mpr
+    from paper_1811_01604_amd import warmstart
 
+    # CPU-side inputs first, before anything touches the GPU (the evaluation
+    # images are made in worker processes)
+    warm_fields = None
+    if args.warm_seeds > 0 and os.path.exists(warmstart.DEFAULT_WEIGHTS):
+        t0 = time.perf_counter()
+        warm_fields = warmstart.make_eval_fields(size=2048, seeds=args.warm_seeds, workers=8)
+        log(f"warm-start evaluation images: {len(warm_fields)} in {time.perf_counter() - t0:.1f} s")
     log(f"workload {args.workload}: generating")
     im, desc = make_workload(args.workload)
     log(f"  {im.nx}x{im.ny}, {int((im.mask == 0).sum())} gaps")
@@ -234,7 +288,8 @@ def main():
     zh = torch.zeros_like(z)
     tile = 0
     if args.tile != "auto":
-        tile = int(args.tile.rstrip("c")) | (mpr.TILE_COMPACT if args.tile.endswith("c") else 0)
+        tile = int(args.tile.rstrip("cf")) | (mpr.TILE_COMPACT if args.tile.endswith("c") else 0) | \
+            (mpr.TILE_FUSED if args.tile.endswith("f") else 0)
     prm = mpr.default_params(R=args.chains, K=args.K, fixed_relax=args.fixed_sweeps, tile_rows=tile,
                              fp64=1 if args.fp64 else 0)
     ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
@@ -310,8 +365,11 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(args.workload, prm.R,
                                         ("fp64-" if args.fp64 else "") + str(prof["last_tile"])),
-            "kernel": ("half_sweep_" + ("fp64_" if args.fp64 else "") +
+            "kernel": ("sweep_tile_kernel" if prof["last_tile"] & mpr.TILE_FUSED else
+                       "half_sweep_" + ("fp64_" if args.fp64 else "") +
                        ("compact_kernel" if prof["last_tile"] & mpr.TILE_COMPACT else "kernel")),
+            "launch": ("one fused sweep (both colours) of every running chain" if prof["last_tile"] & mpr.TILE_FUSED
+                       else "one half-sweep (one colour) of every running chain"),
             "tile_rows": prof["last_tile"] & 0xFF,
             "launch_ms": launch_ms, "useful_bytes_per_launch": bytes_per_launch,
             "sweep_kernel_time_share": prof["sweep_kernel_ms"] * 1e-3 / dt,
@@ -319,31 +377,30 @@ def main():
                      measured_valu(args.workload, prm.R, str(prof["last_tile"]), launch_ms)),
         },
     }
-    if args.warm_seeds > 0:
-        from paper_1811_01604_amd import warmstart
-        if os.path.exists(warmstart.DEFAULT_WEIGHTS):
-            log("warm start vs plain start at L=2048")
-            params, info = warmstart.load()
-            model = warmstart.WarmStart(ctx, params)
-            cnn = cnn_inference(ctx, model)
-            log(f"  network inference 2048^2: {cnn['forward_ms']:.2f} ms, {cnn['achieved']:.0f} GB/s, "
-                f"{cnn['tflops']:.0f} TFLOP/s")
-            ws_summary = warmstart.evaluate(ctx, model, size=2048, seeds=args.warm_seeds)
-            out["warm_start"] = {
-                "workload": "Gaussian Matern nu=1.5 kappa=0.05 N(50,10); 2048x2048; 50% random and 50% cloud "
-                            "gaps; M=100 as one chain (R=1, K=100; layout_100x1: 100 chains of one state); "
-                            "T_hat shared; time = network inference (warm) + simulate + predict",
-                "network": f"8-block residual CNN, 32 channels, bf16 MFMA; trained on {info['samples']} "
-                           f"library simulations of {info['size']}^2 images",
-                **ws_summary,
-                "inference_roofline": cnn,
-            }
-            # the same comparison with the M = 100 realizations as 100 chains of one
-            # state each, where the relaxation is the whole cost of a fill
-            out["warm_start"]["layout_100x1"] = warmstart.evaluate(ctx, model, size=2048, seeds=args.warm_seeds,
-                                                                   R=100, K=1)
-        else:
-            out["warm_start"] = None
+    if args.cloud_steps > 0 and args.workload == "l4096-random" and not args.fp64:
+        out["l4096_cloud"] = cloud_leg(ctx, mpr, prm, args.cloud_steps)
+    if warm_fields is not None:
+        log("warm start vs plain start at L=2048")
+        params, info = warmstart.load()
+        model = warmstart.WarmStart(ctx, params)
+        cnn = cnn_inference(ctx, model)
+        log(f"  network inference 2048^2: {cnn['forward_ms']:.2f} ms, {cnn['achieved']:.0f} GB/s, "
+            f"{cnn['tflops']:.0f} TFLOP/s")
+        layouts = ((1, 100), (4, 25), (100, 1))
+        ws_summary = warmstart.evaluate(ctx, model, warm_fields, layouts=layouts)
+        out["warm_start"] = {
+            "workload": "Gaussian Matern nu=1.5 kappa=0.05 N(50,10); 2048x2048; 50% random and 50% cloud "
+                        "gaps; M=100 realizations as (R chains, K states): 1x100 (the paper's layout), 4x25, "
+                        "100x1; T_hat shared; time = network inference (warm) + simulate + predict; MAE ratio "
+                        "warm/plain paired per image, mean and 95% CI over the images",
+            "network": f"8-block residual CNN, 32 channels, bf16 MFMA; trained on {info['samples']} "
+                       f"library simulations of {info['size']}^2 images",
+            "warm_min_states": mpr.default_params().warm_min_states,
+            "layouts": ws_summary,
+            "inference_roofline": cnn,
+        }
+    elif args.warm_seeds > 0:
+        out["warm_start"] = None
     ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

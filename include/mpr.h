@@ -49,9 +49,12 @@ enum {
     MPR_ERR_HIP = 4          /* a HIP runtime call failed */
 };
 
-/* Flag of mpr_params.tile_rows (and the tile argument of
- * mpr_diag_half_sweep): the compacted sweep shape. */
+/* Flags of mpr_params.tile_rows (and the tile argument of
+ * mpr_diag_half_sweep): the compacted sweep shape, and the fused tile sweep
+ * (a whole sweep per launch on tiles of 16, 24 or 32 rows x 128 columns
+ * staged in LDS with a two-site halo; single precision only). */
 #define MPR_TILE_COMPACT 0x100
+#define MPR_TILE_FUSED 0x200
 
 typedef struct mpr_ctx mpr_ctx;
 
@@ -92,7 +95,10 @@ typedef struct {
     int32_t tile_rows;    /* sweep block shape: 1, 2, 4 or 8 half-rows x (256 / rows)
                              site pairs, or 2, 4 or 8 half-rows | MPR_TILE_COMPACT for
                              (1024 / rows) sites with the gap sites compacted onto
-                             lanes; 0 = autotune (results do not depend on it) */
+                             lanes, or 16, 24 or 32 rows | MPR_TILE_FUSED for the fused
+                             tile sweep (single precision; a double-precision run
+                             takes the default shape instead); 0 = autotune
+                             (results do not depend on it) */
     double table_T_lo, table_T_hi;
     uint64_t seed;        /* Philox key */
     int32_t sweeps_per_launch;  /* sweeps per captured graph between done-checks;
@@ -111,6 +117,13 @@ typedef struct {
                                 than cap share one table (e(T, L) approaches its L -> infinity
                                 limit with an error of order 1/L; it trades that bias for a
                                 table cost bounded by cap^2 sites).  1 is invalid. */
+    int32_t warm_min_states; /* a call with phi_init (a warm start) needs K >= this many
+                                equilibrium states per chain, else MPR_ERR_ARG: all chains
+                                start from the same angles, and the realizations average out
+                                that start only over enough equilibrium sweeps (with K = 1 the
+                                state right after the stopping rule fires stays correlated with
+                                it).  0 turns the check off (parity tests that start the
+                                oracle and the library from the same angles). */
 } mpr_params;
 
 /* Per chain results of mpr_simulate (R per image, image-major). */
@@ -183,7 +196,8 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_
  * composition.
  *   phi, sampled (dev)  sample angles (gap entries ignored)
  *   T_hat (host, double[n_images])
- *   phi_init (dev, float, nullable)  starting gap angles in [0, 2 pi)
+ *   phi_init (dev, float, nullable)  starting gap angles, reduced into [0, 2 pi)
+ *           (sign cleared); needs K >= p->warm_min_states
  *   phi_sum (dev, float, out)  sum of the M = R*K states at gap sites, 0 at samples
  *   phi_m2 (dev, float, out, nullable)  sum over the M states of (phi - mean)^2
  *           at gap sites, 0 at samples (the realizations' spread; Algorithm 2

@@ -56,6 +56,7 @@ class Params(C.Structure):
         ("table_meas", C.c_int32), ("tile_rows", C.c_int32), ("table_T_lo", C.c_double),
         ("table_T_hi", C.c_double), ("seed", C.c_uint64), ("sweeps_per_launch", C.c_int32),
         ("spread", C.c_int32), ("fp64", C.c_int32), ("table_side_cap", C.c_int32),
+        ("warm_min_states", C.c_int32),
     ]
 
 
@@ -101,6 +102,7 @@ def load(path: str = LIB_PATH):
 
 
 TILE_COMPACT = 0x100  # Params.tile_rows flag: the compacted sweep shape
+TILE_FUSED = 0x200  # Params.tile_rows flag: the fused tile sweep (rows 16, 24 or 32)
 
 
 def _declare(L):

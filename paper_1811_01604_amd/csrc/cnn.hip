@@ -405,7 +405,9 @@ __global__ void decode_kernel(const bf16 *__restrict__ y, const uint8_t *__restr
         return;
     }
     const float c = (float)y[p * CH], s = (float)y[p * CH + 1];
-    const float th = atan2f(fmaxf(s, 0.0f), c);
+    // + 0.0f turns a -0.0 (which fmaxf may return) into +0.0: atan2(-0, c < 0)
+    // would be -pi
+    const float th = atan2f(fmaxf(s, 0.0f) + 0.0f, c);
     phi[p] = fminf(th / q, 6.28318501f);
 }
 

@@ -50,6 +50,7 @@ constexpr int64_t kSlopeOffset = 4096;   // diag slope input / output
 constexpr int64_t kVarOffset = 65536;    // per-call partials
 constexpr int kCompactSites = 4 * kBlock;  // sites per block of the compacted sweep shapes
 constexpr int kRecordSegs = 32;            // blocks per chain of record_states_kernel
+constexpr int kWarmMinStates = 25;         // default of mpr_params.warm_min_states
 
 // Sites whose single-precision decision is too close to call are not written
 // by the sweep kernels: they set the site's bit in their block's mask (one
@@ -121,7 +122,15 @@ __global__ void init_chains_kernel(const ChainDesc *__restrict__ descs, const in
             v = (double)fabsf(phi[off + i]);
             fixed = true;
         } else if (phi_init) {
+            // a given start is reduced into [0, 2 pi) with its sign bit clear
+            // (a set sign bit marks a sampled site; -0.0 included)
             v = (double)phi_init[off + i];
+            if (!(v >= 0.0 && v < kTwoPi)) {
+                v -= kTwoPi * floor(v / kTwoPi);
+                if (!(v >= 0.0 && v < kTwoPi)) v = 0.0;
+            }
+            v = fabs(v);
+            if (!fp64 && (float)v >= 6.28318548f) v = 6.28318501;  // the largest float below 2 pi
         } else {
             U4 ctr = {(uint32_t)y * (uint32_t)d.nx + ((uint32_t)x & ~2u), kInitSweep, d.chain, d.image_id};
             const U4 w = philox4x32_10(ctr, seed_lo, seed_hi);
@@ -138,7 +147,10 @@ __global__ void init_chains_kernel(const ChainDesc *__restrict__ descs, const in
             if (ap) ((double *)ap)[j] = 0.0;
             if (mp) ((double *)mp)[j] = 0.0;
         } else {
-            hp[j] = fixed ? mark_fixed((float)v) : (float)v;
+            const float hv = fixed ? mark_fixed((float)v) : (float)v;
+            hp[j] = hv;
+            float *h2 = c ? d.h2[1] : d.h2[0];
+            if (h2) h2[j] = hv;
             if (ap) ap[j] = 0.0f;
             if (mp) mp[j] = 0.0f;
         }
@@ -787,6 +799,375 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
     for (int c = (int)threadIdx.x; c < ctl.n_all; c += (int)blockDim.x)
         control_chain(descs, states, c, ctl.cp, ctl.done_count, ctl.work);
     if (threadIdx.x == 0) *ctl.ticket = 0u;
+}
+
+// ================================================================ fused tile sweep
+// A whole sweep in one launch.  A block stages one tile of both colours in
+// LDS: TH rows x 2 kTileH columns of the grid (kTileH half-columns per
+// colour) plus a halo of two rows and columns.  It updates colour 0 on the
+// tile and on the ring of sites around it, then colour 1 on the tile, which
+// so sees the colour-0 values of its neighbours after their update (the ring
+// repeats updates that the neighbouring tiles also make, with the same
+// inputs and the same random numbers, so with the same results).  Decisions
+// too close to call in single precision are redone in double precision in
+// the block after each colour, before anything reads them.  The gap sites
+// of the tile are then written to the chain's second half-grids (h2):
+// reading h and writing h2 keeps every tile's halo at the state before the
+// sweep while other tiles store theirs.  The last block to finish swaps h
+// and h2 of every chain it swept, and runs the per-sweep control.
+//
+// Within a colour the gap sites are listed in LDS first (wave ballots; each
+// wave lists the candidates it read, interleaved with the other waves at 64
+// sites, and updates its own list), so that lanes only do gap sites; with
+// the sweep's energy wanted, the colour-1 sampled sites of the tile get a
+// second list for their bond energies.  Every site gets update_site, the
+// arithmetic of the half-sweep kernels, so the results equal theirs bit for
+// bit.  `mode` 0 is the full sweep; 1 and 2 update only colour 0 or 1, in
+// place (no tile reads a value another tile writes then), for the
+// single-colour diagnostics.
+constexpr int kTileH = 64;                // half-columns per tile and colour
+constexpr int kTileLS = kTileH + 8;       // LDS row: half-columns hx0 - 4 .. hx0 + kTileH + 3
+constexpr int kTileNW = kBlock / 64;      // waves per block
+
+// The double-precision decision of one tile site (colour c, local row r,
+// half-column j) from its LDS inputs: the steps of redo_fp64_kernel.  Kept
+// out of line, so that the sweep's loops do not hold the double update's
+// constants in registers.
+__device__ __noinline__ SiteOutD tile_redo_site(const float *a, int rows, int c, int r, int j, int y0, int hx0, int nx,
+                                                int ny, uint32_t sweep, uint32_t chain, uint32_t image_id,
+                                                SweepConsts sc, int or_only, double a_cur, double T)
+{
+    const float *own = a + ((size_t)c * rows + r) * kTileLS + j;
+    const float *oth = a + ((size_t)(c ^ 1) * rows + r) * kTileLS + j;
+    const int s = (r + c) & 1;
+    const int y = y0 - 2 + r, h = hx0 - 4 + j;
+    const int Wo = (nx + s) >> 1;
+    const uint32_t valid = (h + s - 1 >= 0 ? 1u : 0u) | (h + s < Wo ? 2u : 0u) | (y > 0 ? 4u : 0u) |
+                           (y + 1 < ny ? 8u : 0u);
+    const float nL = (valid & 1u) ? angle_of(oth[s - 1]) : 0.0f;
+    const float nR = (valid & 2u) ? angle_of(oth[s]) : 0.0f;
+    const float nU = (valid & 4u) ? angle_of(oth[-kTileLS]) : 0.0f;
+    const float nD = (valid & 8u) ? angle_of(oth[kTileLS]) : 0.0f;
+    float u = 0.5f, rr = 0.5f;
+    if (!or_only) {
+        const U4 ctr = {(uint32_t)y * (uint32_t)nx + (uint32_t)(2 * (h & ~1) + s), sweep, chain, image_id};
+        const U4 w = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
+        const bool second = (h & 1) != 0;
+        u = unit24(second ? w.z : w.x);
+        rr = unit24(second ? w.w : w.y);
+    }
+    return update_site_d((double)angle_of(*own), (double)nL, (double)nR, (double)nU, (double)nD, valid, (double)u,
+                         (double)rr, a_cur, T, sc.q64, or_only != 0);
+}
+
+template <int TH>
+struct TileShared {
+    static constexpr int NA = (TH + 2) * (kTileH + 2);      // candidates of the colour-0 pass with its ring
+    static constexpr int CAP = (NA + kBlock - 1) / kBlock * 64;  // list entries per wave
+    static constexpr int RW = ((TH + 4) * kTileLS + 31) / 32;     // redo bitmap words
+    alignas(16) float a[2][TH + 4][kTileLS];  // angle words (sign bit: sampled), colour, row, half-column
+    // per wave: gap entries from the front, sampled entries from the back;
+    // entry = local row << 7 | local half-column
+    uint16_t list[kTileNW][CAP];
+    uint32_t redo[RW];
+    uint32_t red[3][kTileNW];
+    int any_redo[2];
+    int last;
+};
+
+template <bool DIAG, int TH, bool EDGE>
+__device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDesc &d, ChainState *stp, int y0,
+                                                int hx0, int mode, const SweepConsts &sc, int or_only,
+                                                uint8_t *__restrict__ flags, uint64_t &e_thread,
+                                                uint32_t &acc_thread)
+{
+    const int tid = (int)threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int phase = stp->phase;
+    const uint32_t sweep = stp->sweep;
+    const float inv_T = stp->inv_T, dscale = stp->dscale;
+    const bool eq = phase == PH_EQ;
+    float *const dst0 = mode == 0 ? d.h2[0] : d.h[0];
+    float *const dst1 = mode == 0 ? d.h2[1] : d.h[1];
+
+    // stage the tile and its halo: 18 float4 per row and colour (the colour
+    // loop outside, so that the base pointer of every load is uniform)
+    {
+        constexpr int NQ = kTileLS / 4;
+        constexpr int NLOAD = (TH + 4) * NQ;
+        constexpr int IT = (NLOAD + kBlock - 1) / kBlock;
+        v4f v[2][IT];
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const float *src = cc ? d.h[1] : d.h[0];
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int k = tid + it * kBlock;
+                const int r = k / NQ, q = k - r * NQ;
+                const int y = y0 - 2 + r, h = hx0 - 4 + 4 * q;
+                const bool in = k < NLOAD && y >= 0 && y < d.ny && h >= 0 && h < d.S;
+                // outside the grid: zeros, never a candidate (EDGE bounds)
+                // nor a valid neighbour
+                v[cc][it] = gldi4(src, in ? (uint32_t)(y * d.S + h) : 0u);
+                if (!in) v[cc][it] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int k = tid + it * kBlock;
+                const int r = k / NQ, q = k - r * NQ;
+                if (k < NLOAD) *(v4f *)&L.a[cc][r][4 * q] = v[cc][it];
+            }
+    }
+    __syncthreads();
+
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int npass = mode == 0 ? 2 : 1;
+    for (int pass = 0; pass < npass; ++pass) {
+        const int c = mode == 0 ? pass : mode - 1;
+        const bool ring = mode == 0 && c == 0;       // colour 0 of a full sweep: tile and ring
+        const bool energy = c == 1 && !eq;           // the sweep's energy comes from colour 1
+        const int ncols = ring ? kTileH + 2 : kTileH;
+        const int ncand = ring ? (TH + 2) * (kTileH + 2) : TH * kTileH;
+        const int r_lo = ring ? 1 : 2, j_lo = ring ? 3 : 4;
+        uint16_t *lst = L.list[wid];
+        // list the gap sites (and, for the energy, the sampled sites)
+        int ng = 0, ns = 0;
+        for (int base = 0; base < ncand; base += kBlock) {
+            const int i = base + wid * 64 + lane;
+            bool gap = false, smp = false;
+            uint32_t ent = 0u;
+            if (i < ncand) {
+                const int rr = ring ? i / (kTileH + 2) : i / kTileH;
+                const int r = r_lo + rr, j = j_lo + (i - rr * ncols);
+                const float v = L.a[c][r][j];
+                bool in = true;
+                if (EDGE) {
+                    const int y = y0 - 2 + r, h = hx0 - 4 + j, s = (r + c) & 1;
+                    in = y < d.ny && y >= 0 && h >= 0 && h < ((d.nx - s + 1) >> 1);
+                }
+                gap = in && !is_fixed(v);
+                smp = energy && in && is_fixed(v);
+                ent = ((uint32_t)r << 7) | (uint32_t)j;
+            }
+            const uint64_t bg = __ballot(gap), bs = __ballot(smp);
+            if (gap) lst[ng + __popcll(bg & below)] = (uint16_t)ent;
+            if (smp) lst[TileShared<TH>::CAP - 1 - (ns + __popcll(bs & below))] = (uint16_t)ent;
+            ng += __popcll(bg);
+            ns += __popcll(bs);
+        }
+        __syncthreads();
+        // the listed gap sites
+        for (int e = lane; e < ng; e += 64) {
+            const uint32_t ent = lst[e];
+            const int r = (int)(ent >> 7), j = (int)(ent & 127u);
+            const int s = (r + c) & 1;  // y0 is even
+            const float *oth = &L.a[c ^ 1][r][j];
+            const float a0 = L.a[c][r][j];
+            const float nL = angle_of(oth[s - 1]), nR = angle_of(oth[s]);
+            const float nU = angle_of(oth[-kTileLS]), nD = angle_of(oth[kTileLS]);
+            const int y = y0 - 2 + r, h = hx0 - 4 + j;
+            uint32_t valid = 15u;
+            if (EDGE) {
+                const int Wo = (d.nx + s) >> 1;
+                valid = (h + s - 1 >= 0 ? 1u : 0u) | (h + s < Wo ? 2u : 0u) | (y > 0 ? 4u : 0u) |
+                        (y + 1 < d.ny ? 8u : 0u);
+            }
+            float u = 0.5f, rr = 0.5f;
+            if (!or_only) {
+                const U4 ctr = {(uint32_t)y * (uint32_t)d.nx + (uint32_t)(2 * (h & ~1) + s), sweep, d.chain,
+                                d.image_id};
+                const U4 w = philox4x32_10(ctr, sc.seed_lo, sc.seed_hi);
+                const bool second = (h & 1) != 0;
+                u = unit24(second ? w.z : w.x);
+                rr = unit24(second ? w.w : w.y);
+            }
+            bool n64 = true;
+            const SiteOut o = update_site(a0, nL, nR, nU, nD, valid, u, rr, inv_T, dscale, or_only != 0, &n64);
+            if (n64) {  // too close to call: redone in double precision below
+                const int wi = r * kTileLS + j;
+                atomicOr(&L.redo[wi >> 5], 1u << (wi & 31));
+                L.any_redo[pass] = 1;
+                continue;
+            }
+            L.a[c][r][j] = o.phi;
+            const bool own = !ring || (r >= 2 && r < TH + 2 && j >= 4 && j < kTileH + 4);
+            if (own) {
+                acc_thread += o.accepted ? 1u : 0u;
+                if (energy) e_thread += energy_fx(o.e_bonds);
+                if (DIAG && flags) flags[(int64_t)y * d.nx + 2 * h + s] = (uint8_t)o.flags;
+            }
+        }
+        // bond energies of the tile's sampled colour-1 sites
+        for (int e = lane; e < ns; e += 64) {
+            const uint32_t ent = lst[TileShared<TH>::CAP - 1 - e];
+            const int r = (int)(ent >> 7), j = (int)(ent & 127u);
+            const int s = (r + c) & 1;
+            const float *oth = &L.a[c ^ 1][r][j];
+            const float nL = angle_of(oth[s - 1]), nR = angle_of(oth[s]);
+            const float nU = angle_of(oth[-kTileLS]), nD = angle_of(oth[kTileLS]);
+            uint32_t valid = 15u;
+            if (EDGE) {
+                const int y = y0 - 2 + r, h = hx0 - 4 + j;
+                const int Wo = (d.nx + s) >> 1;
+                valid = (h + s - 1 >= 0 ? 1u : 0u) | (h + s < Wo ? 2u : 0u) | (y > 0 ? 4u : 0u) |
+                        (y + 1 < d.ny ? 8u : 0u);
+            }
+            e_thread += energy_fx(bond_energy_half(0.5f * angle_of(L.a[c][r][j]), nL, nR, nU, nD, valid));
+        }
+        __syncthreads();
+        // the deferred decisions, in double precision from the same inputs
+        if (L.any_redo[pass]) {
+            for (int wd = tid; wd < TileShared<TH>::RW; wd += kBlock) {
+                uint32_t m = L.redo[wd];
+                if (!m) continue;
+                L.redo[wd] = 0u;
+                while (m) {
+                    const int wi = wd * 32 + __ffs(m) - 1;
+                    m &= m - 1u;
+                    const int r = wi / kTileLS, j = wi - r * kTileLS;
+                    const SiteOutD o = tile_redo_site(&L.a[0][0][0], TH + 4, c, r, j, y0, hx0, d.nx, d.ny, sweep, d.chain,
+                                                      d.image_id, sc, or_only, stp->a_cur, stp->T);
+                    const int y = y0 - 2 + r, h = hx0 - 4 + j, s = (r + c) & 1;
+                    L.a[c][r][j] = (float)o.phi;
+                    const bool own = !ring || (r >= 2 && r < TH + 2 && j >= 4 && j < kTileH + 4);
+                    if (own) {
+                        acc_thread += o.accepted ? 1u : 0u;
+                        if (energy) e_thread += energy_fx((float)o.e_bonds);
+                        if (DIAG && flags) flags[(int64_t)y * d.nx + 2 * h + s] = (uint8_t)o.flags;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // the tile's gap sites to the destination half-grids (16-byte groups
+    // holding at least one gap site), and the equilibrium sums
+    {
+        constexpr int NQ = kTileH / 4;
+        const float ik = stp->inv_k, ikm1 = stp->inv_km1;
+        for (int cc = 0; cc < 2; ++cc) {
+            if ((mode == 1 && cc == 1) || (mode == 2 && cc == 0)) continue;
+            float *const dst = cc ? dst1 : dst0;
+            float *const ap = eq ? (cc ? d.acc[1] : d.acc[0]) : nullptr;
+            float *const mp = cc ? d.m2[1] : d.m2[0];
+            for (int k = tid; k < TH * NQ; k += kBlock) {
+                const int rr = k / NQ, q = k - rr * NQ;
+                const int y = y0 + rr;
+                if (y >= d.ny) continue;
+                const int h = hx0 + 4 * q;
+                const v4f v = *(const v4f *)&L.a[cc][rr + 2][4 + 4 * q];
+                const bool g0 = !is_fixed(v.x), g1 = !is_fixed(v.y), g2 = !is_fixed(v.z), g3 = !is_fixed(v.w);
+                if (!(g0 || g1 || g2 || g3)) continue;
+                const uint32_t idx = (uint32_t)(y * d.S + h);
+                gsti4(dst, idx, v);
+                if (ap) {
+                    const int W = (d.nx - ((y + cc) & 1) + 1) >> 1;
+                    const float vv[4] = {v.x, v.y, v.z, v.w};
+                    const bool gg[4] = {g0, g1, g2, g3};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (gg[e] && h + e < W) accumulate_state_i(ap, mp, idx + (uint32_t)e, vv[e], ik, ikm1);
+                }
+            }
+        }
+    }
+}
+
+struct TileControl {
+    FusedControl f;   // f.on: run the per-sweep control in the last block
+    int32_t swap;     // full sweeps: swap h and h2 of the swept chains in the last block
+    int32_t pad;
+};
+
+template <bool DIAG, int TH>
+__global__ __launch_bounds__(kBlock) void sweep_tile_kernel(ChainDesc *__restrict__ descs,
+                                                            ChainState *__restrict__ states, BlockMap bm,
+                                                            int mode, SweepConsts sc, int or_only,
+                                                            uint8_t *__restrict__ flags, TileControl tc)
+{
+    __shared__ TileShared<TH> L;
+    const int tid = (int)threadIdx.x;
+    for (int w = tid; w < TileShared<TH>::RW; w += kBlock) L.redo[w] = 0u;
+    if (tid < 2) L.any_redo[tid] = 0;
+    // blocks go round-robin to the 8 XCDs: give each XCD a contiguous run of
+    // tiles, so that the halo rows tiles share are read through one L2
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    const uint32_t per = G >> 3, rem = G & 7u, xcd = b & 7u;
+    const int64_t lbk = (int64_t)xcd * per + (int64_t)min(xcd, rem) + (int64_t)(b >> 3);
+    int lb;
+    const int cid = chain_of_block(bm, lbk, &lb);
+    ChainState *stp = states + cid;
+    uint64_t e_thread = 0u;
+    uint32_t acc_thread = 0u;
+    const int phase = stp->phase;
+    if (phase != PH_DONE) {
+        const ChainDesc d = descs[cid];
+        const int nbx = d.S / kTileH;
+        const int ty = lb / nbx, tx = lb - ty * nbx;
+        const int y0 = ty * TH, hx0 = tx * kTileH;
+        const bool edge = !(ty >= 1 && y0 + TH + 2 <= d.ny && tx >= 1 && hx0 + kTileH + 2 <= (d.nx >> 1));
+        __syncthreads();
+        if (edge)
+            tile_sweep_body<DIAG, TH, true>(L, d, stp, y0, hx0, mode, sc, or_only, flags, e_thread, acc_thread);
+        else
+            tile_sweep_body<DIAG, TH, false>(L, d, stp, y0, hx0, mode, sc, or_only, flags, e_thread, acc_thread);
+        if (phase != PH_EQ) {
+            // block sums: energy in 16-bit halves (no carries in 32-bit lane sums)
+            uint32_t lo = (uint32_t)(e_thread & 0xFFFFu), hi = (uint32_t)(e_thread >> 16), ac = acc_thread;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                lo += __shfl_xor(lo, off);
+                hi += __shfl_xor(hi, off);
+                ac += __shfl_xor(ac, off);
+            }
+            const int wid = tid >> 6;
+            if ((tid & 63) == 0) {
+                L.red[0][wid] = lo;
+                L.red[1][wid] = hi;
+                L.red[2][wid] = ac;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                unsigned long long e = 0ull, a = 0ull;
+                for (int i = 0; i < kTileNW; ++i) {
+                    e += ((unsigned long long)L.red[1][i] << 16) + L.red[0][i];
+                    a += L.red[2][i];
+                }
+                if (e) atomicAdd(&stp->e_fx, e);
+                if (a) atomicAdd(&stp->acc, a);
+            }
+        }
+    }
+    if (!tc.swap && !tc.f.on) return;
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        L.last = atomicAdd(tc.f.ticket, 1u) == gridDim.x - 1u;
+    }
+    __syncthreads();
+    if (!L.last) return;
+    __threadfence();  // the other blocks' sums and stores are visible
+    if (tc.swap) {
+        for (int k = tid; k < bm.n; k += kBlock) {
+            const int c = bm.id[k];
+            if (states[c].phase == PH_DONE) continue;
+            ChainDesc &dd = descs[c];
+            float *t0 = dd.h[0], *t1 = dd.h[1];
+            dd.h[0] = dd.h2[0];
+            dd.h[1] = dd.h2[1];
+            dd.h2[0] = t0;
+            dd.h2[1] = t1;
+        }
+        __threadfence();
+        __syncthreads();
+    }
+    if (tc.f.on)
+        for (int c = tid; c < tc.f.n_all; c += kBlock)
+            control_chain(descs, states, c, tc.f.cp, tc.f.done_count, tc.f.work);
+    if (tid == 0) *tc.f.ticket = 0u;
 }
 
 // The double-precision sweep: the layout of half_sweep_body (a thread per
@@ -1711,22 +2092,32 @@ struct Carver {
 };
 
 // Sweep block shapes: half-rows per block, and whether gap sites are
-// compacted onto lanes (1024 sites per block) or not (512 sites per block).
+// compacted onto lanes (1024 sites per block) or not (512 sites per block);
+// or a fused tile sweep (a whole sweep per launch on tiles of `rows` rows x
+// 2 kTileH columns, single precision only).
 struct Shape {
     int rows;
     bool compact;
+    bool fused;
 };
-constexpr int kNumShapes = 7;
+constexpr int kNumShapes = 10;
 constexpr int kNumPlainShapes = 4;
-constexpr Shape kShapes[kNumShapes] = {{1, false}, {2, false}, {4, false}, {8, false},
-                                       {2, true},  {4, true},  {8, true}};
+constexpr int kNumUnfusedShapes = 7;   // the shapes of double-precision chains
+constexpr Shape kShapes[kNumShapes] = {{1, false, false}, {2, false, false}, {4, false, false}, {8, false, false},
+                                       {2, true, false},  {4, true, false},  {8, true, false},
+                                       {16, false, true}, {24, false, true}, {32, false, true}};
 constexpr int kDefaultShape = 2;  // plain, 4 half-rows
 
-// Shape index of a tile_rows value (rows | MPR_TILE_COMPACT), or -1.
+int tile_code(const Shape &sh)
+{
+    return sh.rows | (sh.compact ? MPR_TILE_COMPACT : 0) | (sh.fused ? MPR_TILE_FUSED : 0);
+}
+
+// Shape index of a tile_rows value (rows | MPR_TILE_COMPACT or MPR_TILE_FUSED), or -1.
 int shape_of(int tile)
 {
     for (int k = 0; k < kNumShapes; ++k)
-        if (tile == (kShapes[k].rows | (kShapes[k].compact ? MPR_TILE_COMPACT : 0))) return k;
+        if (tile == tile_code(kShapes[k])) return k;
     return -1;
 }
 
@@ -1734,6 +2125,7 @@ int shape_of(int tile)
 int64_t shape_blocks(int S, int ny, int k)
 {
     const Shape sh = kShapes[k];
+    if (sh.fused) return (int64_t)(S / kTileH) * ((ny + sh.rows - 1) / sh.rows);
     const int px = sh.compact ? kCompactSites / sh.rows / 2 : kBlock / sh.rows;  // site pairs per block row
     return (int64_t)((S / 2 + px - 1) / px) * ((ny + sh.rows - 1) / sh.rows);
 }
@@ -1741,7 +2133,7 @@ int64_t shape_blocks(int S, int ny, int k)
 int64_t chain_blocks(const ChainDesc &d, int k) { return shape_blocks(d.S, d.ny, k); }
 
 // Mask words per sweep block of shape k (one bit per site of the block).
-int redo_words(int k) { return (kShapes[k].compact ? kCompactSites : 2 * kBlock) / 32; }
+int redo_words(int k) { return kShapes[k].fused ? 0 : (kShapes[k].compact ? kCompactSites : 2 * kBlock) / 32; }
 
 // Workspace bytes of the deferred-redo buffers for `chains` chains of an
 // nx x ny grid (an upper bound over every block shape).
@@ -1768,7 +2160,7 @@ bool valid_params(const mpr_params *p)
            (p->tile_rows == 0 || shape_of(p->tile_rows) >= 0) &&
            p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096 && (p->spread == 0 || p->spread == 1) &&
            (p->fp64 == 0 || p->fp64 == 1) &&
-           (p->table_side_cap == 0 || p->table_side_cap >= 2);
+           (p->table_side_cap == 0 || p->table_side_cap >= 2) && p->warm_min_states >= 0;
 }
 
 bool valid_images(const mpr_image *imgs, int n)
@@ -1789,7 +2181,9 @@ int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     int64_t b = 0;
     for (int i = 0; i < n; ++i) {
         const int64_t hg = round_up(half_grid_bytes(imgs[i].nx, imgs[i].ny, p->fp64 ? 8 : 4), 256);
-        b += (int64_t)p->R * 2 * hg * (p->K > 1 ? (p->spread ? 3 : 2) : 1);
+        // angles (twice for single precision: the fused sweep's second buffer),
+        // equilibrium sums, squared deviations
+        b += (int64_t)p->R * 2 * hg * ((p->fp64 ? 1 : 2) + (p->K > 1 ? (p->spread ? 2 : 1) : 0));
     }
     const int64_t chains = (int64_t)n * p->R;
     b += round_up(chains * (int64_t)sizeof(ChainDesc), 256) + round_up(chains * (int64_t)sizeof(ChainState), 256);
@@ -2037,6 +2431,29 @@ void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colo
     launch_redo<false>(st, cs, v, colour, sc, 0, nullptr, ctl);
 }
 
+// One fused sweep of every listed chain in shape v (mode 0), or one colour
+// of it in place (mode 1, 2: diagnostics).
+template <bool DIAG>
+void launch_tile(hipStream_t st, const ChainSet &cs, int v, int mode, const SweepConsts &sc, int or_only,
+                 uint8_t *flags, const TileControl &tc)
+{
+    const dim3 grid((unsigned)cs.total_blocks[v]), blk(kBlock);
+    switch (kShapes[v].rows) {
+        case 16:
+            hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 16>), grid, blk, 0, st, cs.d_desc, cs.d_state,
+                               block_map(cs, v), mode, sc, or_only, flags, tc);
+            break;
+        case 24:
+            hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 24>), grid, blk, 0, st, cs.d_desc, cs.d_state,
+                               block_map(cs, v), mode, sc, or_only, flags, tc);
+            break;
+        default:
+            hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 32>), grid, blk, 0, st, cs.d_desc, cs.d_state,
+                               block_map(cs, v), mode, sc, or_only, flags, tc);
+            break;
+    }
+}
+
 // Builds the launch list of a chain set from the chains in `active`: block
 // prefix sums for every shape and the chain ids, uploaded on `stream` (and
 // waited for, so that the host copies can be reused).
@@ -2101,10 +2518,19 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     fc.work = d_work;
     fc.n_all = n;
     fc.on = 1;
+    TileControl tcl;
+    tcl.f = fc;
+    tcl.f.on = fuse ? 1 : 0;
+    tcl.swap = 1;
+    tcl.pad = 0;
     auto sweeps = [&](int v, int count) {
         for (int i = 0; i < count; ++i) {
-            launch_half(st, cs, v, table, 0, sc);
-            launch_half(st, cs, v, table, 1, sc, fuse ? &fc : nullptr);
+            if (kShapes[v].fused) {
+                launch_tile<false>(st, cs, v, 0, sc, 0, nullptr, tcl);
+            } else {
+                launch_half(st, cs, v, table, 0, sc);
+                launch_half(st, cs, v, table, 1, sc, fuse ? &fc : nullptr);
+            }
             if (cs.states_out && cs.n_active > 0)
                 hipLaunchKernelGGL(record_states_kernel, dim3((unsigned)(cs.n_active * kRecordSegs)), dim3(kBlock), 0,
                                    st, cs.d_desc, cs.d_state, cs.d_offset, cs.d_ids, kRecordSegs, cs.K,
@@ -2130,15 +2556,16 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
         if (ms_out) *ms_out = ms;
         if (ctx->profile) {
             ctx->prof_ms += ms;
-            ctx->prof_launches += 2 * (int64_t)count;
+            ctx->prof_launches += (kShapes[v].fused ? 1 : 2) * (int64_t)count;
         }
         done_sweeps += count;
         finished = *ctx->done_host + already >= (unsigned int)n;
         return MPR_OK;
     };
 
-    // block shape: fixed, cached, or tuned on the first sweeps
-    const int n_shapes = table ? kNumPlainShapes : kNumShapes;
+    // block shape: fixed, cached, or tuned on the first sweeps (the table
+    // chains take the plain shapes, double-precision chains every unfused one)
+    const int n_shapes = table ? kNumPlainShapes : (cs.fp64 ? kNumUnfusedShapes : kNumShapes);
     int v = p->tile_rows ? shape_of(p->tile_rows) : -1;
     if (v >= n_shapes) v = kDefaultShape;
     int maxnx = 0, maxny = 0;
@@ -2169,7 +2596,7 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
         else sweep_ms = best / (float)ts;
         if (tried == n_shapes) ctx->tuned_rows[key] = v;
     }
-    if (!table) ctx->last_tile = kShapes[v].rows | (kShapes[v].compact ? MPR_TILE_COMPACT : 0);
+    if (!table) ctx->last_tile = tile_code(kShapes[v]);
     // sweeps per graph: at least about a millisecond of work per done-check
     int spl = p->sweeps_per_launch > 0 ? p->sweeps_per_launch : poll_every;
     if (p->sweeps_per_launch <= 0 && sweep_ms > 0.0f && (float)spl * sweep_ms < 1.0f)
@@ -2305,7 +2732,8 @@ int upload_chains(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream, do
 
 // Allocates both half-grids (and accumulators) of a chain of `eb`-byte
 // angles from the workspace.
-bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc, bool with_m2 = false, int eb = 4)
+bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc, bool with_m2 = false, int eb = 4,
+                 bool with_h2 = false)
 {
     const int64_t hg = half_grid_bytes(nx, ny, eb);
     d.nx = nx;
@@ -2313,9 +2741,11 @@ bool carve_chain(Carver &cv, ChainDesc &d, int nx, int ny, bool with_acc, bool w
     d.S = half_stride(nx);
     for (int c = 0; c < 2; ++c) {
         d.h[c] = (float *)cv.take(hg);
+        d.h2[c] = with_h2 ? (float *)cv.take(hg) : nullptr;
         d.acc[c] = with_acc ? (float *)cv.take(hg) : nullptr;
         d.m2[c] = with_acc && with_m2 ? (float *)cv.take(hg) : nullptr;
-        if (!d.h[c] || (with_acc && !d.acc[c]) || (with_acc && with_m2 && !d.m2[c])) return false;
+        if (!d.h[c] || (with_h2 && !d.h2[c]) || (with_acc && !d.acc[c]) || (with_acc && with_m2 && !d.m2[c]))
+            return false;
     }
     return true;
 }
@@ -2440,6 +2870,7 @@ void mpr_default_params(mpr_params *p)
     p->spread = 0;
     p->fp64 = 0;
     p->table_side_cap = 0;
+    p->warm_min_states = kWarmMinStates;
 }
 
 int64_t mpr_workspace_size(const mpr_image *imgs, int32_t n, const mpr_params *p)
@@ -2648,6 +3079,11 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
         return rc;
     if (phi_m2 && p->K > 1 && !p->spread)
         return fail(ctx, MPR_ERR_ARG, "simulate: phi_m2 with K > 1 needs params.spread = 1");
+    if (phi_init && p->K < p->warm_min_states)
+        return fail(ctx, MPR_ERR_ARG,
+                    "simulate: a warm start (phi_init) needs K >= warm_min_states = %d equilibrium states per "
+                    "chain (K = %d): every chain starts from the same angles",
+                    p->warm_min_states, p->K);
     for (int b = 0; b < n; ++b)
         if (!(T_hat[b] > 0.0) || !std::isfinite(T_hat[b])) return fail(ctx, MPR_ERR_ARG, "image %d: bad T_hat", b);
     if (!ws || ws_bytes < sim_bytes(imgs, n, p)) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
@@ -2691,7 +3127,7 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
         for (int r = 0; r < p->R; ++r) {
             ChainDesc d;
             std::memset(&d, 0, sizeof d);
-            if (!carve_chain(cv, d, nx, ny, p->K > 1, p->spread != 0, p->fp64 ? 8 : 4))
+            if (!carve_chain(cv, d, nx, ny, p->K > 1, p->spread != 0, p->fp64 ? 8 : 4, !p->fp64))
                 return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
             d.image_id = imgs[b].id;
             d.chain = (uint32_t)r;
@@ -2720,10 +3156,11 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
     if (rc) return rc;
     int64_t maxn = 0;
     for (int b = 0; b < n; ++b) maxn = std::max(maxn, (int64_t)imgs[b].nx * imgs[b].ny);
-    for (auto &d : cs.desc) {
-        HIP_TRY(ctx, hipMemsetAsync(d.h[0], 0, half_grid_bytes(d.nx, d.ny, eb), stream));
-        HIP_TRY(ctx, hipMemsetAsync(d.h[1], 0, half_grid_bytes(d.nx, d.ny, eb), stream));
-    }
+    for (auto &d : cs.desc)
+        for (int c = 0; c < 2; ++c) {
+            HIP_TRY(ctx, hipMemsetAsync(d.h[c], 0, half_grid_bytes(d.nx, d.ny, eb), stream));
+            if (d.h2[c]) HIP_TRY(ctx, hipMemsetAsync(d.h2[c], 0, half_grid_bytes(d.nx, d.ny, eb), stream));
+        }
     hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), (unsigned)cs.desc.size()), dim3(kBlock), 0,
                        stream, cs.d_desc, cs.d_offset, phi, sampled, phi_init, (uint32_t)p->seed,
                        (uint32_t)(p->seed >> 32), 0, cs.fp64 ? 1 : 0);
@@ -3068,7 +3505,11 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
     const dim3 grid((unsigned)cs.total_blocks[v]);
     const Shape sh = kShapes[v];
     const Redo rd = cs.redo;
-    if (sh.compact) {
+    if (sh.fused) {
+        TileControl tc;
+        std::memset(&tc, 0, sizeof tc);
+        launch_tile<true>(stream, cs, v, colour + 1, sc, mode, flags, tc);
+    } else if (sh.compact) {
         if (sh.rows == 2)
             hipLaunchKernelGGL((half_sweep_compact_kernel<true, 2>), grid, dim3(kBlock), 0, stream, cs.d_desc,
                                cs.d_state, block_map(cs, v), colour, sc, mode, rd, flags);
@@ -3092,7 +3533,7 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
             hipLaunchKernelGGL((half_sweep_kernel<true, 8>), grid, dim3(kBlock), 0, stream, cs.d_desc, cs.d_state,
                                block_map(cs, v), colour, sc, mode, rd, flags);
     }
-    launch_redo<true>(stream, cs, v, colour, sc, mode, flags);
+    if (!sh.fused) launch_redo<true>(stream, cs, v, colour, sc, mode, flags);
     hipLaunchKernelGGL(unsplit_kernel, dim3(blocks_for(nsite, 2048)), dim3(kBlock), 0, stream, cs.d_desc, phi);
     ChainState out;
     (void)hipMemcpyAsync(&out, cs.d_state, sizeof out, hipMemcpyDeviceToHost, stream);

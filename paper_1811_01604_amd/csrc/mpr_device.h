@@ -32,6 +32,9 @@ struct ChainDesc {
     float *acc[2];        // equilibrium sums (K > 1), or null
     float *m2[2];         // sums of squared deviations from the running mean
                           // of the equilibrium states (K > 1, spread wanted), or null
+    float *h2[2];         // second pair of half-grids (single-precision chains): the
+                          // fused tile sweep reads h and writes h2, and the pointers
+                          // are swapped after the sweep, so h always holds the state
     int32_t nx, ny, S;    // grid size and half-row stride
     uint32_t image_id;    // Philox counter word 3
     uint32_t chain;       // Philox counter word 2
@@ -75,14 +78,29 @@ struct U4 {
 
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 {
-#pragma unroll
-    for (int i = 0; i < 10; ++i) {
+    // round 1 in plain xors: counter words 1-3 are usually uniform over a
+    // launch, so the compiler keeps their part on the scalar unit
+    {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
         U4 n;
         n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
         n.y = (uint32_t)p1;
         n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        n.w = (uint32_t)p0;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    // rounds 2-10: each three-way xor is one v_bitop3_b32 (truth table 0x96)
+#pragma unroll
+    for (int i = 1; i < 10; ++i) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        U4 n;
+        n.x = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96);
+        n.y = (uint32_t)p1;
+        n.z = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96);
         n.w = (uint32_t)p0;
         c = n;
         k0 += 0x9E3779B9u;
@@ -327,6 +345,11 @@ __device__ __forceinline__ float2 gldi2(const float *base, uint32_t i)
     return make_float2(v.x, v.y);
 }
 __device__ __forceinline__ void gsti(float *base, uint32_t i, float v) { *(gfloat *)gaddr(base, i) = v; }
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4f gv4f;
+// 16-byte load and store at element i (a multiple of 4) of a uniform base.
+__device__ __forceinline__ v4f gldi4(const float *base, uint32_t i) { return *(const gv4f *)gaddr(base, i); }
+__device__ __forceinline__ void gsti4(float *base, uint32_t i, v4f v) { *(gv4f *)gaddr(base, i) = v; }
 
 // Adds the k-th equilibrium state phi of a site to its running sum acc and,
 // when m2 is given, to the sum of squared deviations from the running mean

@@ -217,11 +217,17 @@ def test_simulate_from_given_starting_angles(ctx, fp64):
     init[g] = np.random.default_rng(5).uniform(0, TWO_PI, size=int(g.sum())).astype(np.float32)
     T = 0.15
     kw = dict(R=2, K=3, seed=21) if fp64 else dict(R=1, K=1, fixed_relax=0, seed=21)
-    prm = mpr.default_params(fp64=fp64, **kw)
+    # warm_min_states = 0: the start here is the parity input, not a warm
+    # start whose realizations must average it out
+    prm = mpr.default_params(fp64=fp64, warm_min_states=0, **kw)
     imgs = mpr.images([(ny, nx)])
     ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
     ph, mk = dev(phi32, torch.float32), dev(im.mask, torch.uint8)
     ps, ps0 = torch.zeros_like(ph), torch.zeros_like(ph)
+    with pytest.raises(mpr.MprError) as e:  # the default refuses a warm start with K < 25
+        ctx.simulate(imgs, ph, mk, np.array([T]), mpr.default_params(fp64=fp64, **kw), ws, ps,
+                     phi_init=dev(init, torch.float32))
+    assert e.value.code == mpr.MPR_ERR_ARG
     st = ctx.simulate(imgs, ph, mk, np.array([T]), prm, ws, ps, phi_init=dev(init, torch.float32))
     ctx.simulate(imgs, ph, mk, np.array([T]), prm, ws, ps0)
     ps, ps0 = ps.cpu().numpy(), ps0.cpu().numpy()
@@ -237,6 +243,45 @@ def test_simulate_from_given_starting_angles(ctx, fp64):
         frac = float(np.mean(d <= 1e-5))
         say(f"  fp32 from phi_init, one sweep: {frac:.5f} of gap sites within 1e-5")
         assert frac >= 0.999
+
+
+def test_given_start_is_reduced_into_range(ctx):
+    """phi_init values outside [0, 2 pi) are reduced into it, and -0.0 is
+    +0.0 (a set sign bit would mark the site as sampled and freeze it):
+    single-precision chains from -0.0 equal those from +0.0 bit for bit, and
+    double-precision chains from angles shifted by +-2 pi equal those from
+    the host's reduction of the same shifted values."""
+    im, phi32 = l64_angles()
+    ny, nx = phi32.shape
+    g = im.mask == 0
+    ng = int(g.sum())
+    rng = np.random.default_rng(9)
+    base = np.zeros_like(phi32)
+    base[g] = rng.uniform(0, TWO_PI, size=ng).astype(np.float32)
+    base[g] = np.where(np.arange(ng) % 7 == 0, 0.0, base[g]).astype(np.float32)
+    imgs = mpr.images([(ny, nx)])
+    ph, mk = dev(phi32, torch.float32), dev(im.mask, torch.uint8)
+
+    def fill(init, fp64):
+        prm = mpr.default_params(R=2, K=1, fixed_relax=1, fp64=fp64, warm_min_states=0, seed=31)
+        ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+        ps = torch.zeros_like(ph)
+        ctx.simulate(imgs, ph, mk, np.array([0.12]), prm, ws, ps, phi_init=dev(init, torch.float32))
+        return ps.cpu().numpy()
+
+    neg0 = base.copy()
+    neg0[g & (base == 0)] = -0.0
+    assert np.signbit(neg0[g]).sum() == int((base[g] == 0).sum()) > 0
+    assert fill(neg0, 0).tobytes() == fill(base, 0).tobytes()
+    shifted = base.copy()
+    shifted[g] = (base[g].astype(np.float64) + np.where(np.arange(ng) % 2 == 0, TWO_PI, -TWO_PI)).astype(np.float32)
+    v = shifted.astype(np.float64)
+    reduced = np.abs(v - TWO_PI * np.floor(v / TWO_PI)).astype(np.float32)
+    reduced[~g] = 0.0
+    assert np.all((reduced[g] >= 0) & (reduced[g] < TWO_PI))
+    d = np.abs(fill(shifted, 1).astype(np.float64) - fill(reduced, 1))
+    say(f"  start shifted by +-2 pi: max |phi_sum - phi_sum(reduced)| {d.max():.2e}")
+    assert d.max() <= 1e-5
 
 
 @pytest.mark.parametrize("sg_degree,n_fit,n_f,eq_a_mode", [(2, 12, 3, 0), (1, 20, 5, 1), (3, 30, 4, 1)])

@@ -1,0 +1,119 @@
+"""The fused tile sweep (one launch per sweep on LDS tiles with a halo)
+against the two half-sweep launches per sweep.
+
+Both compute Algorithm 1 on colour 0 and then colour 1 of every chain with
+the same per-site arithmetic and random numbers, so every output must be
+bit-identical: sums of the states, their squared deviations, recorded
+states, stopping decisions and the final a.  The batch mixes images smaller
+than a tile, a single row, ragged tile edges and several tiles, and starts
+from random angles, where weak local fields send many decisions to the
+double-precision path.  Parity with the oracle is in test_gpu_parity.py
+(teacher-forced half-sweeps in every shape, the fused one included).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+import paper_1811_01604_amd as mpr  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+FUSED_TILES = [16 | mpr.TILE_FUSED, 24 | mpr.TILE_FUSED, 32 | mpr.TILE_FUSED]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = mpr.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+SHAPES = [(3, 5), (1, 300), (130, 257), (70, 600), (33, 129)]
+
+
+def batch():
+    zs, ms = [], []
+    for b, (ny, nx) in enumerate(SHAPES):
+        z = synth.matern_field(nx, max(ny, 2), 1.5, 0.1, 50.0, 10.0, 60 + b)[:ny]
+        zs.append(z.astype(np.float32))
+        ms.append(synth.random_mask(nx, ny, 0.3 + 0.1 * b, 70 + b))
+    imgs = mpr.images(SHAPES)
+    z = dev(np.concatenate([a.ravel() for a in zs]))
+    mk = dev(np.concatenate([a.ravel() for a in ms]), torch.uint8)
+    return imgs, z, mk
+
+
+def run(ctx, imgs, phi, mk, T, tile, spl=0, record=False, **kw):
+    prm = mpr.default_params(tile_rows=tile, sweeps_per_launch=spl, **kw)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    ps = torch.zeros_like(phi)
+    m2 = torch.zeros_like(phi) if (prm.K <= 1 or prm.spread) else None
+    states = torch.zeros(prm.R * prm.K * phi.numel(), device="cuda") if record else None
+    st = ctx.simulate(imgs, phi, mk, T, prm, ws, ps, phi_m2=m2, phi_states=states)
+    out = {"sum": ps.cpu().numpy().tobytes(),
+           "stats": [(s["relax_sweeps"], s["not_converged"], s["k_last"], s["a_final"], s["A_last"]) for s in st]}
+    if m2 is not None:
+        out["m2"] = m2.cpu().numpy().tobytes()
+    if record:
+        out["states"] = states.cpu().numpy().tobytes()
+    return out
+
+
+@pytest.mark.parametrize("T", [2e-3, 0.05])
+def test_fused_sweep_equals_half_sweeps_on_a_ragged_batch(ctx, T):
+    """Stopping rule, R = 3 chains x K = 5 states with their spread: every
+    fused tile height and graph size equals the plain 4-row half-sweeps."""
+    imgs, z, mk = batch()
+    phi = torch.zeros_like(z)
+    ctx.map_to_angles(imgs, z, mk, phi)
+    Ts = np.full(len(SHAPES), T)
+    ref = run(ctx, imgs, phi, mk, Ts, 4, 5, R=3, K=5, spread=1)
+    say(f"  T={T}: relax sweeps {[s[0] for s in ref['stats']]}")
+    for tile, spl in [(FUSED_TILES[0], 5), (FUSED_TILES[1], 1), (FUSED_TILES[2], 64), (FUSED_TILES[2], 3)]:
+        got = run(ctx, imgs, phi, mk, Ts, tile, spl, R=3, K=5, spread=1)
+        for key in ref:
+            assert got[key] == ref[key], (tile, spl, key)
+
+
+def test_fused_sweep_with_recorded_states_and_one_state_chains(ctx):
+    """The recorded states (read between the sweep and the control, after
+    the fused sweep has swapped its buffers) and the K = 1 layout, whose sums
+    are the final states, equal those of the half-sweeps; so does a call
+    that starts from given gap angles."""
+    imgs, z, mk = batch()
+    phi = torch.zeros_like(z)
+    ctx.map_to_angles(imgs, z, mk, phi)
+    Ts = np.full(len(SHAPES), 0.01)
+    for kw in (dict(R=2, K=4, fixed_relax=7), dict(R=5, K=1)):
+        rec = kw["K"] > 1
+        ref = run(ctx, imgs, phi, mk, Ts, 2 | mpr.TILE_COMPACT, 5, record=rec, **kw)
+        for tile in FUSED_TILES:
+            got = run(ctx, imgs, phi, mk, Ts, tile, 5, record=rec, **kw)
+            for key in ref:
+                assert got[key] == ref[key], (kw, tile, key)
+
+
+def test_tuner_may_pick_any_shape_with_identical_results(ctx):
+    """An autotuned run (which times every shape, fused ones included, on
+    its first sweeps) equals a run fixed to one shape."""
+    imgs, z, mk = batch()
+    phi = torch.zeros_like(z)
+    ctx.map_to_angles(imgs, z, mk, phi)
+    Ts = np.full(len(SHAPES), 0.02)
+    a = run(ctx, imgs, phi, mk, Ts, 0, 0, R=4, K=3)
+    b = run(ctx, imgs, phi, mk, Ts, 32 | mpr.TILE_FUSED, 0, R=4, K=3)
+    assert a == b
+    say(f"  tuned shape {ctx.profile_read()['last_tile']:#x}")

@@ -31,7 +31,7 @@ import paper_1811_01604_amd as mpr  # noqa: E402
 pytestmark = pytest.mark.gpu
 TWO_PI = 2.0 * np.pi
 T = 6e-5
-TILES = [4 | mpr.TILE_COMPACT, 8 | mpr.TILE_COMPACT, 0]
+TILES = [4 | mpr.TILE_COMPACT, 8 | mpr.TILE_COMPACT, 0, 32 | mpr.TILE_FUSED]
 
 
 def say(*a):
@@ -106,7 +106,8 @@ def test_l4096_benchmark_launch_matches_smaller_launches(ctx):
     ctx.map_to_angles(imgs, z, mk, phi)
     Tn = np.array([T])
     runs = {}
-    for R, tile in ((100, 0), (100, 4 | mpr.TILE_COMPACT), (100, 8 | mpr.TILE_COMPACT), (2, 0)):
+    for R, tile in ((100, 0), (100, 4 | mpr.TILE_COMPACT), (100, 8 | mpr.TILE_COMPACT), (100, 32 | mpr.TILE_FUSED),
+                    (2, 0)):
         # the stopping rule: chains stop at different sweeps, so the launch
         # list shrinks as they finish
         prm = mpr.default_params(R=R, K=1, tile_rows=tile)
@@ -117,7 +118,7 @@ def test_l4096_benchmark_launch_matches_smaller_launches(ctx):
         del ws
         say(f"  R={R} tile {tile}: relax sweeps {sorted(set(s['relax_sweeps'] for s in st))}")
     ref_ps, ref_st = runs[(100, 0)]
-    for key in ((100, 4 | mpr.TILE_COMPACT), (100, 8 | mpr.TILE_COMPACT)):
+    for key in ((100, 4 | mpr.TILE_COMPACT), (100, 8 | mpr.TILE_COMPACT), (100, 32 | mpr.TILE_FUSED)):
         ps, st = runs[key]
         assert np.array_equal(ps.view(np.uint32), ref_ps.view(np.uint32)), key
         assert st == ref_st, key

@@ -106,7 +106,7 @@ def test_largest_image_over_relaxation_against_oracle(ctx):
     gy = torch.tensor([g[1] for g in gaps], device="cuda")
     sampled[gy, gx] = 0
     phi = torch.empty_like(phi0)
-    for tile in (0, 4 | mpr.TILE_COMPACT):
+    for tile in (0, 4 | mpr.TILE_COMPACT, 32 | mpr.TILE_FUSED):
         for colour in (0, 1):
             phi.copy_(phi0)
             ctx.diag_half_sweep(phi, sampled, colour, 0.1, 1.0, 0, mode=1, tile=tile)

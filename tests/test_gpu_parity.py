@@ -175,7 +175,9 @@ def smooth_state(ny, nx, nu, kappa, p_removed, noise, seed):
 
 
 PLAIN, COMPACT = 0, 4 | mpr.TILE_COMPACT  # default plain shape; compacted 4-row shape
-ALL_TILES = [1, 2, 4, 8, 2 | mpr.TILE_COMPACT, 4 | mpr.TILE_COMPACT, 8 | mpr.TILE_COMPACT]
+FUSED = 32 | mpr.TILE_FUSED  # fused tile sweep, 32-row tiles (one colour in the diagnostics)
+ALL_TILES = [1, 2, 4, 8, 2 | mpr.TILE_COMPACT, 4 | mpr.TILE_COMPACT, 8 | mpr.TILE_COMPACT,
+             16 | mpr.TILE_FUSED, 24 | mpr.TILE_FUSED, 32 | mpr.TILE_FUSED]
 
 
 def run_pair(ctx, phi32, m, colour, T, a, sweep, mode=0, chain=0, stream_id=0, seed=3000, tile=PLAIN):
@@ -190,7 +192,7 @@ def run_pair(ctx, phi32, m, colour, T, a, sweep, mode=0, chain=0, stream_id=0, s
     return g.cpu().numpy(), acc_g, fl.cpu().numpy(), po, acc_o, fo
 
 
-@pytest.mark.parametrize("tile", [PLAIN, COMPACT])
+@pytest.mark.parametrize("tile", [PLAIN, COMPACT, FUSED])
 @pytest.mark.parametrize("kind", ["uniform", "smooth"])
 @pytest.mark.parametrize("shape", [(64, 64), (97, 131), (1, 40), (40, 1)])
 def test_over_relaxation_only_teacher_forced(ctx, kind, shape, tile):
@@ -222,7 +224,7 @@ def test_over_relaxation_only_teacher_forced(ctx, kind, shape, tile):
 LOW_T = [2.6e-4, 1.0e-3, 0.1]
 
 
-@pytest.mark.parametrize("tile", [PLAIN, COMPACT])
+@pytest.mark.parametrize("tile", [PLAIN, COMPACT, FUSED])
 @pytest.mark.parametrize("T", LOW_T)
 def test_metropolis_decisions_teacher_forced(ctx, T, tile):
     """Chains of half-sweeps; at every step the oracle redoes it from the GPU's state."""
@@ -250,7 +252,7 @@ def test_metropolis_decisions_teacher_forced(ctx, T, tile):
     assert max_err <= 1e-5
 
 
-@pytest.mark.parametrize("tile", [PLAIN, COMPACT])
+@pytest.mark.parametrize("tile", [PLAIN, COMPACT, FUSED])
 def test_accept_count_and_energy_teacher_forced(ctx, tile):
     ny, nx = 130, 257
     phi, m = smooth_state(ny, nx, 1.5, 0.1, 0.66, 0.05, 41)
@@ -276,7 +278,7 @@ def test_accept_count_and_energy_teacher_forced(ctx, tile):
     assert abs(hp / ho - 1.0) <= 1e-4
 
 
-@pytest.mark.parametrize("tile", [PLAIN, COMPACT])
+@pytest.mark.parametrize("tile", [PLAIN, COMPACT, FUSED])
 @pytest.mark.parametrize("shape", [(1, 2), (2, 1), (3, 3), (5, 2), (2, 7), (1, 9)])
 def test_degenerate_and_tiny_grids(ctx, shape, tile):
     ny, nx = shape
@@ -626,8 +628,8 @@ def test_l1024_prediction_matches_oracle(ctx):
 @pytest.mark.parametrize("shape", [(64, 64), (45, 211)])
 def test_results_independent_of_block_shape_and_graph_size(ctx, shape):
     """Every block shape (plain rows 1, 2, 4, 8; compacted rows 2, 4, 8;
-    autotuned) and graph size gives bit-identical sums, statistics and
-    stopping decisions."""
+    fused tile sweeps of 16, 24, 32 rows; autotuned) and graph size gives
+    bit-identical sums, statistics and stopping decisions."""
     ny, nx = shape
     z = synth.matern_field(nx, ny, 1.5, 0.1, 50, 10, 17)
     m = synth.random_mask(nx, ny, 0.5, 18)
@@ -638,7 +640,8 @@ def test_results_independent_of_block_shape_and_graph_size(ctx, shape):
     ctx.map_to_angles(imgs, zd, mk, phi)
     ref = None
     for rows, spl in ((4, 5), (1, 5), (2, 7), (8, 1), (0, 0), (4, 64), (2 | mpr.TILE_COMPACT, 5),
-                      (4 | mpr.TILE_COMPACT, 3), (8 | mpr.TILE_COMPACT, 64)):
+                      (4 | mpr.TILE_COMPACT, 3), (8 | mpr.TILE_COMPACT, 64), (16 | mpr.TILE_FUSED, 5),
+                      (24 | mpr.TILE_FUSED, 1), (32 | mpr.TILE_FUSED, 64), (32 | mpr.TILE_FUSED, 3)):
         prm = mpr.default_params(R=3, K=4, tile_rows=rows, sweeps_per_launch=spl)
         ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
         ps = torch.zeros_like(zd)

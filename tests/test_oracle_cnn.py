@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import scipy.signal
 
+from cnn_bf16 import backward_bf16, forward_bf16, network_case, rounded
 from oracle import cnn
 
 
@@ -127,3 +128,31 @@ def test_bf16_rounding():
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -7
     assert abs(r[3] - 3.140625) < 1e-12
     assert np.all(np.abs(r - v) <= np.abs(v) * 2 ** -8 + 1e-300)
+
+
+def test_bf16_network_composition_matches_the_float64_network():
+    """The bfloat16 composition the GPU network test uses is the float64
+    network up to bfloat16 rounding: with the rounding replaced by the
+    identity it is cnn.forward / cnn.backward exactly, and with it the output
+    stays within a few bfloat16 steps of the float64 one."""
+    params, phi, sampled, target = network_case(3)
+    rp = rounded(params)
+    x = cnn.bf16_round(cnn.encode(phi, sampled.astype(bool)))
+    y64, acts64 = cnn.forward(rp, x)
+    y16, _ = forward_bf16(rp, x)
+    g, w = y16[..., :2].ravel(), y64[..., :2].ravel()
+    assert np.max(np.abs(g - w)) / np.max(np.abs(w)) < 5e-2
+    assert g @ w / (np.linalg.norm(g) * np.linalg.norm(w)) > 0.999
+    ident = lambda a: np.asarray(a, dtype=np.float64)  # noqa: E731
+    orig = cnn.bf16_round
+    cnn.bf16_round = ident
+    try:
+        y_id, acts_id = forward_bf16(rp, x)
+        _, dy = cnn.loss(y_id, target, sampled == 0)
+        g_id = backward_bf16(rp, acts_id, dy)
+    finally:
+        cnn.bf16_round = orig
+    assert np.array_equal(y_id, y64)
+    g64 = cnn.backward(rp, acts64, dy)
+    for (a, b), (c, d) in zip(g_id, g64):
+        assert np.allclose(a, c, rtol=1e-12, atol=1e-15) and np.allclose(b, d, rtol=1e-12, atol=1e-15)
