@@ -124,6 +124,7 @@ typedef struct {
                                 state right after the stopping rule fires stays correlated with
                                 it).  0 turns the check off (parity tests that start the
                                 oracle and the library from the same angles). */
+    int32_t reserved;        /* set to 0 (pads the struct to a multiple of 8 bytes) */
 } mpr_params;
 
 /* Per chain results of mpr_simulate (R per image, image-major). */

@@ -56,7 +56,7 @@ class Params(C.Structure):
         ("table_meas", C.c_int32), ("tile_rows", C.c_int32), ("table_T_lo", C.c_double),
         ("table_T_hi", C.c_double), ("seed", C.c_uint64), ("sweeps_per_launch", C.c_int32),
         ("spread", C.c_int32), ("fp64", C.c_int32), ("table_side_cap", C.c_int32),
-        ("warm_min_states", C.c_int32),
+        ("warm_min_states", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
