@@ -114,40 +114,84 @@ def cpu_baseline(im, T: float, sweeps: int, seed: int) -> dict:
                       f"single thread, {dt:.1f} s"}
 
 
-def cpu_baseline_scaling(sizes, fractions=(0.33, 0.66), T: float = 0.09, full_fill_max: int = 1024):
+def cpu_baseline_scaling(sizes, fractions=(0.33, 0.66), T: float = 0.09, full_fill_max: int = 1024,
+                         extra=()):
     """The oracle on the lattice-size study's images (Whittle-Matern nu=0.5,
     kappa=0.2, N(50, 10), a fraction p removed at random; the images the GPU
-    study fills), one JSON line per (L, p).  Up to L = full_fill_max a whole
-    fill as the GPU study times it: R = 1 chain, the stopping rule, K = 100
-    states, at a fixed temperature T (the GPU study's T_hat for these images
-    lies in 0.08-0.09; the e(T, L) table is excluded on both sides).  Larger
-    L: one sweep, timed, as the per-sweep cost."""
+    study fills), one JSON line per (L, p): every size in `sizes` at every
+    fraction in `fractions`, then the (L, p) pairs of `extra` (the gap-fraction
+    sweep).  Up to L = full_fill_max a whole fill as the GPU study times it:
+    R = 1 chain, the stopping rule, K = 100 states, at a fixed temperature T
+    (the GPU study's T_hat for these images lies in 0.08-0.09; the e(T, L)
+    table is excluded on both sides).  Larger L: one sweep, timed, as the
+    per-sweep cost."""
     import numpy as np
     import oracle
     import synth
-    for L in sizes:
-        for p in fractions:
-            im = synth.workload_table2(L, p, 0)
-            z = im.z.astype(np.float32).astype(np.float64)
-            phi, _ = oracle.map_to_angles(z, im.mask)
-            P = int((im.mask == 0).sum())
-            row = {"L": L, "p_removed": p, "gap_sites": P, "T": T, "cores": 1, "kind": "oracle"}
-            if L <= full_fill_max:
-                prm = oracle.default_params(R=1, K=100, seed=7000)
-                t0 = time.perf_counter()
-                _, st, _, _ = oracle.simulate(phi, im.mask, T, prm)
-                dt = time.perf_counter() - t0
-                sweeps = st[0]["relax_sweeps"] + 1 + 100
-                row.update(fill_s=dt, relax_sweeps=st[0]["relax_sweeps"], sweeps=sweeps,
-                           site_updates_per_s=sweeps * P / dt)
+    cases = [(L, p) for L in sizes for p in fractions]
+    cases += [c for c in extra if c not in cases]
+    for L, p in cases:
+        im = synth.workload_table2(L, p, 0)
+        z = im.z.astype(np.float32).astype(np.float64)
+        phi, _ = oracle.map_to_angles(z, im.mask)
+        P = int((im.mask == 0).sum())
+        row = {"L": L, "p_removed": p, "gap_sites": P, "T": T, "cores": 1, "kind": "oracle"}
+        if L <= full_fill_max:
+            prm = oracle.default_params(R=1, K=100, seed=7000)
+            t0 = time.perf_counter()
+            _, st, _, _ = oracle.simulate(phi, im.mask, T, prm)
+            dt = time.perf_counter() - t0
+            sweeps = st[0]["relax_sweeps"] + 1 + 100
+            row.update(fill_s=dt, relax_sweeps=st[0]["relax_sweeps"], sweeps=sweeps,
+                       site_updates_per_s=sweeps * P / dt)
+        else:
+            prm = oracle.default_params(R=1, K=1, fixed_relax=0, seed=7000)
+            t0 = time.perf_counter()
+            oracle.simulate(phi, im.mask, T, prm)
+            dt = time.perf_counter() - t0
+            row.update(fill_s=None, sweep_s=dt, site_updates_per_s=P / dt)
+        log(f"oracle L={L} p={p}: {json.dumps(row)}")
+        print(json.dumps(row), flush=True)
+
+
+def read_jsonl(path: str) -> list:
+    rows = []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("{"):
+                rows.append(json.loads(line))
+    return rows
+
+
+def combine_scaling(gpu_path: str, cpu_path: str) -> dict:
+    """The GPU study's rows joined with the oracle's rows of the same (L, p).
+    The oracle's time to fill is its measured whole fill where it ran one;
+    otherwise its measured per-sweep time times the GPU fill's sweep count
+    (relaxation sweeps + 1 + K), the sweeps the oracle would run from the same
+    stopping rule.  speedup = oracle time to fill / GPU time to fill (both
+    without the e(T, L) table)."""
+    cpu = {(r["L"], round(r["p_removed"], 6)): r for r in read_jsonl(cpu_path)}
+    rows = []
+    for g in read_jsonl(gpu_path):
+        if "site_updates_per_s" not in g:
+            continue
+        c = cpu.get((g["L"], round(g["p_removed"], 6)))
+        row = dict(g)
+        if c is not None:
+            if c.get("fill_s") is not None:
+                t_cpu, how = c["fill_s"], "measured fill"
             else:
-                prm = oracle.default_params(R=1, K=1, fixed_relax=0, seed=7000)
-                t0 = time.perf_counter()
-                oracle.simulate(phi, im.mask, T, prm)
-                dt = time.perf_counter() - t0
-                row.update(fill_s=None, sweep_s=dt, site_updates_per_s=P / dt)
-            log(f"oracle L={L} p={p}: {json.dumps(row)}")
-            print(json.dumps(row), flush=True)
+                t_cpu = c["sweep_s"] * (g["relax_sweeps"] + 1 + g["K"])
+                how = "measured sweep x GPU sweep count"
+            row.update(oracle_time_to_fill_s=t_cpu, oracle_fill_basis=how,
+                       oracle_site_updates_per_s=c["site_updates_per_s"], oracle_cores=c["cores"],
+                       speedup_time_to_fill=t_cpu / g["time_to_fill_s"],
+                       speedup_site_updates=g["site_updates_per_s"] / c["site_updates_per_s"])
+        rows.append(row)
+    return {"study": "time to fill and sweep throughput against lattice size L and gap fraction p "
+                     "(Whittle-Matern nu=0.5 kappa=0.2 N(50,10), random gaps; R=1 chain, stopping rule, K=100)",
+            "rows": rows}
 
 
 def cnn_inference(ctx, model, size: int = 2048, reps: int = 5) -> dict:
@@ -240,6 +284,12 @@ def main():
                     help="only the CPU baseline of the lattice-size study: time the oracle on its images "
                          "at these comma-separated sizes L (p = 0.33 and 0.66), one JSON line per case, "
                          "and exit (no GPU work)")
+    ap.add_argument("--cpu-p-sweep", default="",
+                    help="with --cpu-scaling: also the gap-fraction sweep, as L:p1,p2,... "
+                         "(e.g. 2048:0.05,0.2,0.35,0.5,0.65,0.8,0.95)")
+    ap.add_argument("--combine", nargs=2, metavar=("GPU_JSONL", "CPU_JSONL"),
+                    help="join the GPU scaling study's lines with the oracle's lines of the same (L, p) into "
+                         "one JSON document with the oracle's time to fill and the speed-up, and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB plain copy first (calibrates HBM byte counters)")
     ap.add_argument("--tile", default="auto",
@@ -254,8 +304,15 @@ def main():
                     help="timed steps of the same fill with the 40%% cloud mask, reported as l4096_cloud "
                          "(0 = skip; only with the default workload)")
     args = ap.parse_args()
+    if args.combine:
+        print(json.dumps(combine_scaling(*args.combine), indent=1))
+        return
     if args.cpu_scaling:
-        cpu_baseline_scaling([int(v) for v in args.cpu_scaling.split(",")])
+        extra = ()
+        if args.cpu_p_sweep:
+            Ls, ps = args.cpu_p_sweep.split(":")
+            extra = tuple((int(Ls), float(p)) for p in ps.split(","))
+        cpu_baseline_scaling([int(v) for v in args.cpu_scaling.split(",")], extra=extra)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the sweep has no multi-GPU path "
