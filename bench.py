@@ -114,6 +114,54 @@ def cpu_baseline(im, T: float, sweeps: int, seed: int) -> dict:
                       f"single thread, {dt:.1f} s"}
 
 
+def _oracle_chain_worker(args):
+    """One oracle chain on the image saved at `path` (gaps already drawn
+    into phi): `sweeps` sweeps, returns (site-updates, seconds)."""
+    path, T, sweeps, seed = args
+    import numpy as np
+    import oracle
+    d = np.load(path)
+    phi, mask = d["phi"].copy(), d["mask"]
+    P = int((mask == 0).sum())
+    t0 = time.perf_counter()
+    for t in range(sweeps):
+        for colour in (0, 1):
+            phi, _, _ = oracle.half_sweep(phi, mask, colour, T, 1.0 + t / 3.0, t, seed=seed)
+    return sweeps * P, time.perf_counter() - t0
+
+
+def cpu_baseline_all_cores(im, T: float, sweeps: int, seed: int, workers: int) -> dict:
+    """The same oracle sweep on `workers` independent chains at once, one
+    single-threaded oracle process per chain (the chains of a fill are
+    independent, so this is how the oracle uses every core): aggregate
+    site-updates per second of wall time, from the start of the first sweep
+    to the end of the last."""
+    import multiprocessing as mp
+    import tempfile
+    import numpy as np
+    import oracle
+    z = im.z.astype(np.float32).astype(np.float64)
+    phi, _ = oracle.map_to_angles(z, im.mask)
+    g = im.mask == 0
+    phi[g] = np.random.default_rng(seed).uniform(0.0, 2.0 * np.pi, size=int(g.sum()))
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "chain.npz")
+        np.savez(path, phi=phi, mask=im.mask)
+        pool = mp.get_context("spawn").Pool(workers)
+        try:
+            pool.map(_oracle_chain_worker, [(path, T, 0, seed)] * workers)  # start-up and imports, untimed
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_chain_worker, [(path, T, sweeps, seed + 1 + w) for w in range(workers)])
+            dt = time.perf_counter() - t0
+        finally:
+            pool.close()
+            pool.join()
+    updates = sum(r[0] for r in res)
+    return {"value": updates / dt, "unit": "site-updates/s", "cores": workers, "kind": "oracle",
+            "sample": f"{workers} independent chains, {sweeps} sweeps each ({int(g.sum())} gap sites) of the same "
+                      f"workload, one single-threaded FP64 oracle process per chain, {dt:.1f} s wall"}
+
+
 def cpu_baseline_scaling(sizes, fractions=(0.33, 0.66), T: float = 0.09, full_fill_max: int = 1024,
                          extra=()):
     """The oracle on the lattice-size study's images (Whittle-Matern nu=0.5,
@@ -280,6 +328,9 @@ def main():
                     help="relax exactly this many sweeps instead of the stopping rule")
     ap.add_argument("--cpu-sweeps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the all-cores oracle baseline (0 = the host's cores, at most 16; "
+                         "1 = skip it)")
     ap.add_argument("--cpu-scaling", default="",
                     help="only the CPU baseline of the lattice-size study: time the oracle on its images "
                          "at these comma-separated sizes L (p = 0.33 and 0.66), one JSON line per case, "
@@ -462,6 +513,11 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(im, 1e-4, args.cpu_sweeps, 3002)
+        if args.cpu_workers != 1:
+            workers = args.cpu_workers if args.cpu_workers > 1 else min(16, len(os.sched_getaffinity(0)))
+            log(f"cpu baseline (oracle), {workers} processes")
+            out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(im, 1e-4, max(1, args.cpu_sweeps // 2), 3002,
+                                                                   workers)
     print(json.dumps(out), flush=True)
 
 

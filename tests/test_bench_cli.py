@@ -68,3 +68,15 @@ def test_cpu_scaling_gap_fraction_sweep_and_join(tmp_path):
     assert b["oracle_time_to_fill_s"] == rows[2]["sweep_s"] * 141
     assert b["speedup_site_updates"] == 2e9 / rows[2]["site_updates_per_s"]
     assert "oracle_time_to_fill_s" not in c
+
+
+def test_cpu_baseline_all_cores_runs_independent_chains():
+    """The all-cores oracle leg runs one oracle process per chain and adds
+    their site-updates over the wall time."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import synth
+    im = synth.workload_table2(24, 0.5, 0)
+    out = bench.cpu_baseline_all_cores(im, 0.09, 2, 5, 2)
+    assert out["cores"] == 2 and out["kind"] == "oracle" and out["value"] > 0
+    assert "2 independent chains" in out["sample"]
