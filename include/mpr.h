@@ -221,6 +221,26 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
                      int64_t ws_bytes, float *phi_sum, float *phi_m2, float *phi_states,
                      mpr_chain_stats *stats, void *stream);
 
+/* mpr_simulate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments without the workspace, which is instead a static
+ * device array of mpr_simulate_noalloc_max_bytes() (64 MiB) that each GPU
+ * the library runs on holds until the process ends.  Every sweep is
+ * launched directly (no graph is instantiated); results equal
+ * mpr_simulate's bit for bit.  The call allocates nothing (no hipMalloc,
+ * hipFree or graph instantiation); the context was created earlier.
+ * All calls on one GPU share its array: calls that overlap in time on the
+ * same GPU (other threads, other contexts) race and must be serialised by
+ * the caller.  The call returns after its work is complete.
+ * Errors: as mpr_simulate, and MPR_ERR_WORKSPACE when the batch needs more
+ * than mpr_simulate_noalloc_max_bytes() (mpr_workspace_size of the batch). */
+int32_t mpr_simulate_noalloc(mpr_ctx *ctx, const mpr_image *imgs, int32_t n_images,
+                             const float *phi, const uint8_t *sampled, const double *T_hat,
+                             const mpr_params *p, const float *phi_init, float *phi_sum,
+                             float *phi_m2, float *phi_states, mpr_chain_stats *stats,
+                             void *stream);
+int64_t mpr_simulate_noalloc_max_bytes(void);
+
 /* Algorithm 2 steps 6.3 and 7 with the mean as the statistic:
  * z_hat = z_min (1 - t) + z_max t with t = (phi_sum / M) / (2 pi) at gaps
  * (double precision, rounded once); sampled sites are copied bit-exactly.

@@ -22,7 +22,8 @@ FLAG_KEPT, FLAG_ACCEPTED, FLAG_WRAPPED, FLAG_UPDATED, FLAG_FP64 = 1, 2, 4, 8, 16
 # Every symbol include/mpr.h declares.
 EXPORTS = [
     "mpr_create", "mpr_destroy", "mpr_last_error", "mpr_default_params", "mpr_workspace_size",
-    "mpr_map_to_angles", "mpr_estimate_temperature", "mpr_simulate", "mpr_predict", "mpr_spread",
+    "mpr_map_to_angles", "mpr_estimate_temperature", "mpr_simulate", "mpr_simulate_noalloc",
+    "mpr_simulate_noalloc_max_bytes", "mpr_predict", "mpr_spread",
     "mpr_quantiles", "mpr_select_q", "mpr_select_q_workspace_size",
     "mpr_profile_enable", "mpr_profile_read",
     "mpr_cnn_param_count", "mpr_cnn_packed_bytes", "mpr_cnn_workspace_size", "mpr_cnn_pack", "mpr_cnn_encode",
@@ -117,6 +118,8 @@ def _declare(L):
         "mpr_map_to_angles": (i32, [P, IMG, i32, P, P, P, P, P]),
         "mpr_estimate_temperature": (i32, [P, IMG, i32, P, P, PRM, P, i64, P, P, P, P]),
         "mpr_simulate": (i32, [P, IMG, i32, P, P, P, PRM, P, P, i64, P, P, P, C.POINTER(ChainStats), P]),
+        "mpr_simulate_noalloc": (i32, [P, IMG, i32, P, P, P, PRM, P, P, P, P, C.POINTER(ChainStats), P]),
+        "mpr_simulate_noalloc_max_bytes": (i64, []),
         "mpr_quantiles": (i32, [P, IMG, i32, P, P, P, i32, P, i32, P, P, P]),
         "mpr_select_q_workspace_size": (i64, [IMG, PRM, P, i32]),
         "mpr_select_q": (i32, [P, IMG, P, P, PRM, P, i32, d, P, i64, P, P, P, P]),
@@ -278,6 +281,27 @@ class Context:
             T.ctypes.data_as(C.c_void_p), C.byref(params), self._t(phi_init, "phi_init", f32, ns, optional=True),
             self._t(ws, "ws"), ws.numel() * ws.element_size(), self._t(phi_sum, "phi_sum", f32, ns),
             self._t(phi_m2, "phi_m2", f32, ns, optional=True),
+            self._t(phi_states, "phi_states", f32, max(0, params.R * params.K) * ns, optional=True), st,
+            _stream(stream)))
+        return [dict(relax_sweeps=s.relax_sweeps, not_converged=s.not_converged, a_final=s.a_final,
+                     A_last=s.A_last, k_last=s.k_last) for s in st]
+
+    def simulate_noalloc(self, imgs, phi, sampled, T_hat, params, phi_sum, phi_init=None, stream=None, phi_m2=None,
+                         phi_states=None):
+        """simulate() on the library's static per-device workspace (no
+        workspace argument, nothing allocated by the call)."""
+        import torch
+        n = len(imgs)
+        ns = sites_of(imgs)
+        T = np.ascontiguousarray(T_hat, dtype=np.float64)
+        if T.size < n:
+            raise ValueError(f"T_hat: {T.size} values for {n} images")
+        st = (ChainStats * (n * params.R))()
+        f32 = torch.float32
+        self._check(self.lib.mpr_simulate_noalloc(
+            self._h, imgs, n, self._t(phi, "phi", f32, ns), self._t(sampled, "sampled", torch.uint8, ns),
+            T.ctypes.data_as(C.c_void_p), C.byref(params), self._t(phi_init, "phi_init", f32, ns, optional=True),
+            self._t(phi_sum, "phi_sum", f32, ns), self._t(phi_m2, "phi_m2", f32, ns, optional=True),
             self._t(phi_states, "phi_states", f32, max(0, params.R * params.K) * ns, optional=True), st,
             _stream(stream)))
         return [dict(relax_sweeps=s.relax_sweeps, not_converged=s.not_converged, a_final=s.a_final,

@@ -23,6 +23,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -51,6 +52,15 @@ constexpr int64_t kVarOffset = 65536;    // per-call partials
 constexpr int kCompactSites = 4 * kBlock;  // sites per block of the compacted sweep shapes
 constexpr int kRecordSegs = 32;            // blocks per chain of record_states_kernel
 constexpr int kWarmMinStates = 25;         // default of mpr_params.warm_min_states
+
+// Workspace of mpr_simulate_noalloc, for callers that cannot allocate: one
+// copy per device, held by the library's code object until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is a stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns on each device, kept per device by static_ws_addr.
+constexpr int64_t kStaticWorkspaceBytes = (int64_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char static_workspace[kStaticWorkspaceBytes];
 
 // Sites whose single-precision decision is too close to call are not written
 // by the sweep kernels: they set the site's bit in their block's mask (one
@@ -2000,6 +2010,7 @@ struct mpr_ctx {
     int device = 0;
     std::string err;
     void *scratch = nullptr;          // small device scratch (partials, counters)
+    void *static_ws = nullptr;        // this device's static_workspace (device address)
     unsigned int *done_host = nullptr;  // pinned
     // sweeps run on a context-owned stream (captured into HIP graphs),
     // ordered after and before the caller's stream with two events
@@ -2481,9 +2492,10 @@ int set_active(mpr_ctx *ctx, ChainSet &cs, const std::vector<int32_t> &active, h
 // Runs sweeps until every chain is done.  Returns 0 or an error code.
 // Sweeps run on ctx->gstream: a few direct sweeps per block shape first (to
 // tune it, unless fixed or cached), then groups of `spl` sweeps replayed as
-// a captured graph, checking the done-counter after each group.
+// a captured graph (launched directly when `graphs` is false: instantiating
+// a graph allocates), checking the done-counter after each group.
 int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stream, int64_t max_sweeps,
-               int poll_every, bool table)
+               int poll_every, bool table, bool graphs = true)
 {
     const int n = (int)cs.desc.size();
     unsigned int *d_done = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kDoneOffset);
@@ -2617,7 +2629,7 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     hipGraphExec_t &ge = cap.exec;
     auto capture = [&]() {
         cap.release();
-        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        if (graphs && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             sweeps(v, spl);
             if (hipStreamEndCapture(st, &cap.graph) != hipSuccess ||
                 hipGraphInstantiate(&cap.exec, cap.graph, nullptr, nullptr, 0) != hipSuccess)
@@ -2792,6 +2804,26 @@ double invert_table(const std::vector<double> &Tg, const std::vector<double> &op
     return std::exp(x0 + (ys - y[k]) * (x1 - x0) / (y[k + 1] - y[k]));
 }
 
+// Device address of static_workspace on `device` (the current device),
+// looked up once per device and kept for the process.
+std::mutex g_static_ws_mu;
+void *g_static_ws_addr[kMaxDevices] = {};
+
+hipError_t static_ws_addr(int device, void **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_ws_mu);
+    if (!g_static_ws_addr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(static_workspace));
+        if (e != hipSuccess) return e;
+        g_static_ws_addr[device] = ptr;
+    }
+    *out = g_static_ws_addr[device];
+    return hipSuccess;
+}
+
 std::vector<double> temperature_grid(const mpr_params *p)
 {
     std::vector<double> Tg(p->table_nT);
@@ -2816,6 +2848,11 @@ int32_t mpr_create(mpr_ctx **out, int32_t device)
     if (hipSetDevice(device) != hipSuccess) return MPR_ERR_HIP;
     mpr_ctx *ctx = new mpr_ctx();
     ctx->device = device;
+    // without it only mpr_simulate_noalloc is unavailable (it reports so)
+    if (static_ws_addr(device, &ctx->static_ws) != hipSuccess) {
+        ctx->static_ws = nullptr;
+        (void)hipGetLastError();
+    }
     if (hipMalloc(&ctx->scratch, kScratchBytes) != hipSuccess ||
         hipHostMalloc((void **)&ctx->done_host, sizeof(unsigned int), hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess ||
@@ -3066,16 +3103,21 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
     return MPR_OK;
 }
 
-int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *phi, const uint8_t *sampled,
-                     const double *T_hat, const mpr_params *p, const float *phi_init, void *ws, int64_t ws_bytes,
-                     float *phi_sum, float *phi_m2, float *phi_states, mpr_chain_stats *stats, void *stream_)
+// mpr_simulate on the workspace ws (the caller's, checked as device memory,
+// or this device's static workspace, `caller_ws` false); `graphs` false
+// launches every sweep directly.
+static int32_t simulate_call(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *phi,
+                             const uint8_t *sampled, const double *T_hat, const mpr_params *p,
+                             const float *phi_init, void *ws, int64_t ws_bytes, float *phi_sum, float *phi_m2,
+                             float *phi_states, mpr_chain_stats *stats, void *stream_, bool caller_ws, bool graphs)
 {
     if (!ctx) return MPR_ERR_ARG;
     if (!valid_images(imgs, n) || !valid_params(p) || !phi || !sampled || !T_hat || !phi_sum)
         return fail(ctx, MPR_ERR_ARG, "simulate: invalid argument");
     if (int rc = mpr_check_device(ctx, "simulate",
-                                  {{"phi", phi}, {"sampled", sampled}, {"phi_init", phi_init}, {"workspace", ws},
-                                   {"phi_sum", phi_sum}, {"phi_m2", phi_m2}, {"phi_states", phi_states}}))
+                                  {{"phi", phi}, {"sampled", sampled}, {"phi_init", phi_init},
+                                   {"workspace", caller_ws ? ws : nullptr}, {"phi_sum", phi_sum},
+                                   {"phi_m2", phi_m2}, {"phi_states", phi_states}}))
         return rc;
     if (phi_m2 && p->K > 1 && !p->spread)
         return fail(ctx, MPR_ERR_ARG, "simulate: phi_m2 with K > 1 needs params.spread = 1");
@@ -3166,7 +3208,7 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
                        (uint32_t)(p->seed >> 32), 0, cs.fp64 ? 1 : 0);
     HIP_TRY(ctx, hipGetLastError());
     const int64_t relax_cap = p->fixed_relax >= 0 ? p->fixed_relax : (int64_t)p->i_max + 1;
-    rc = run_chains(ctx, cs, p, stream, relax_cap + p->K + 1, p->n_f, false);
+    rc = run_chains(ctx, cs, p, stream, relax_cap + p->K + 1, p->n_f, false, graphs);
     if (rc) return rc;
     if (cs.fp64)
         hipLaunchKernelGGL(finalize_fp64_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, cs.d_desc,
@@ -3192,6 +3234,36 @@ int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float
     }
     return MPR_OK;
 }
+
+int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *phi, const uint8_t *sampled,
+                     const double *T_hat, const mpr_params *p, const float *phi_init, void *ws, int64_t ws_bytes,
+                     float *phi_sum, float *phi_m2, float *phi_states, mpr_chain_stats *stats, void *stream_)
+{
+    return simulate_call(ctx, imgs, n, phi, sampled, T_hat, p, phi_init, ws, ws_bytes, phi_sum, phi_m2, phi_states,
+                         stats, stream_, true, true);
+}
+
+int32_t mpr_simulate_noalloc(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *phi,
+                             const uint8_t *sampled, const double *T_hat, const mpr_params *p,
+                             const float *phi_init, float *phi_sum, float *phi_m2, float *phi_states,
+                             mpr_chain_stats *stats, void *stream_)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!valid_images(imgs, n) || !valid_params(p))
+        return fail(ctx, MPR_ERR_ARG, "simulate_noalloc: invalid argument");
+    if (!ctx->static_ws)
+        return fail(ctx, MPR_ERR_HIP, "simulate_noalloc: no static workspace on device %d", ctx->device);
+    const int64_t need = sim_bytes(imgs, n, p);
+    if (need > kStaticWorkspaceBytes)
+        return fail(ctx, MPR_ERR_WORKSPACE,
+                    "simulate_noalloc: this batch needs %lld workspace bytes, the static workspace holds %lld "
+                    "(use mpr_simulate with a workspace of mpr_workspace_size bytes)",
+                    (long long)need, (long long)kStaticWorkspaceBytes);
+    return simulate_call(ctx, imgs, n, phi, sampled, T_hat, p, phi_init, ctx->static_ws, kStaticWorkspaceBytes,
+                         phi_sum, phi_m2, phi_states, stats, stream_, false, false);
+}
+
+int64_t mpr_simulate_noalloc_max_bytes(void) { return kStaticWorkspaceBytes; }
 
 int32_t mpr_predict(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *z, const uint8_t *sampled,
                     const float *phi_sum, const double *zmin_zmax, int32_t M, float *z_hat, void *stream_)
