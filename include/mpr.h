@@ -28,7 +28,8 @@
  *    enqueued on it and every call synchronises the stream before it
  *    returns.
  *  - Sampled flags are uint8: nonzero = sampled (fixed), 0 = gap.
- *  - Every call returns MPR_OK (0) or an error code; mpr_last_error gives a
+ *  - Every call returns MPR_OK (0) or an error code (mpr_simulate also
+ *    MPR_INCOMPLETE, see mpr_params.sweep_limit); mpr_last_error gives a
  *    text for the most recent failure on the context.  No C++ exception
  *    crosses the boundary.  A context is used by one host thread at a time.
  */
@@ -46,7 +47,9 @@ enum {
     MPR_ERR_ARG = 1,         /* invalid argument (null pointer, bad size, non-finite sample) */
     MPR_ERR_DEGENERATE = 2,  /* data the method cannot handle, see each call */
     MPR_ERR_WORKSPACE = 3,   /* workspace smaller than mpr_workspace_size */
-    MPR_ERR_HIP = 4          /* a HIP runtime call failed */
+    MPR_ERR_HIP = 4,         /* a HIP runtime call failed */
+    MPR_INCOMPLETE = 5       /* not an error: mpr_simulate stopped at params.sweep_limit with
+                                chains still running (outputs not written; resume later) */
 };
 
 /* Flags of mpr_params.tile_rows (and the tile argument of
@@ -124,7 +127,18 @@ typedef struct {
                                 state right after the stopping rule fires stays correlated with
                                 it).  0 turns the check off (parity tests that start the
                                 oracle and the library from the same angles). */
-    int32_t reserved;        /* set to 0 (pads the struct to a multiple of 8 bytes) */
+    int32_t sweep_limit;     /* > 0: mpr_simulate runs at most this many sweeps in this call
+                                and returns MPR_INCOMPLETE if a chain is still running; the
+                                workspace then holds the whole state of the run (a checkpoint:
+                                its first mpr_workspace_size bytes, which may be copied to the
+                                host and later back into any workspace); 0: run to the end */
+    int32_t resume;          /* 1: mpr_simulate continues the run held in the workspace (left
+                                by a call that returned MPR_INCOMPLETE, with the same images and
+                                parameters apart from sweep_limit, resume, tile_rows and
+                                sweeps_per_launch) instead of starting its chains; phi_init is
+                                ignored.  Results equal those of an uninterrupted run bit for
+                                bit (random numbers are keyed by sweep, not by call). */
+    int32_t reserved;        /* set to 0 (pads the struct to 128 bytes) */
 } mpr_params;
 
 /* Per chain results of mpr_simulate (R per image, image-major). */

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpr.so")
 
-MPR_OK, MPR_ERR_ARG, MPR_ERR_DEGENERATE, MPR_ERR_WORKSPACE, MPR_ERR_HIP = range(5)
+MPR_OK, MPR_ERR_ARG, MPR_ERR_DEGENERATE, MPR_ERR_WORKSPACE, MPR_ERR_HIP, MPR_INCOMPLETE = range(6)
 FLAG_KEPT, FLAG_ACCEPTED, FLAG_WRAPPED, FLAG_UPDATED, FLAG_FP64 = 1, 2, 4, 8, 16
 
 # Every symbol include/mpr.h declares.
@@ -57,7 +57,8 @@ class Params(C.Structure):
         ("table_meas", C.c_int32), ("tile_rows", C.c_int32), ("table_T_lo", C.c_double),
         ("table_T_hi", C.c_double), ("seed", C.c_uint64), ("sweeps_per_launch", C.c_int32),
         ("spread", C.c_int32), ("fp64", C.c_int32), ("table_side_cap", C.c_int32),
-        ("warm_min_states", C.c_int32), ("reserved", C.c_int32),
+        ("warm_min_states", C.c_int32), ("sweep_limit", C.c_int32), ("resume", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -266,8 +267,8 @@ class Context:
             _stream(stream)))
         return e_s, T, cl
 
-    def simulate(self, imgs, phi, sampled, T_hat, params, ws, phi_sum, phi_init=None, stream=None, phi_m2=None,
-                 phi_states=None):
+    def _simulate(self, fn, ws_args, imgs, phi, sampled, T_hat, params, phi_sum, phi_init, stream, phi_m2,
+                  phi_states, allow_incomplete):
         import torch
         n = len(imgs)
         ns = sites_of(imgs)
@@ -276,36 +277,33 @@ class Context:
             raise ValueError(f"T_hat: {T.size} values for {n} images")
         st = (ChainStats * (n * params.R))()
         f32 = torch.float32
-        self._check(self.lib.mpr_simulate(
-            self._h, imgs, n, self._t(phi, "phi", f32, ns), self._t(sampled, "sampled", torch.uint8, ns),
-            T.ctypes.data_as(C.c_void_p), C.byref(params), self._t(phi_init, "phi_init", f32, ns, optional=True),
-            self._t(ws, "ws"), ws.numel() * ws.element_size(), self._t(phi_sum, "phi_sum", f32, ns),
-            self._t(phi_m2, "phi_m2", f32, ns, optional=True),
-            self._t(phi_states, "phi_states", f32, max(0, params.R * params.K) * ns, optional=True), st,
-            _stream(stream)))
-        return [dict(relax_sweeps=s.relax_sweeps, not_converged=s.not_converged, a_final=s.a_final,
-                     A_last=s.A_last, k_last=s.k_last) for s in st]
+        rc = fn(self._h, imgs, n, self._t(phi, "phi", f32, ns), self._t(sampled, "sampled", torch.uint8, ns),
+                T.ctypes.data_as(C.c_void_p), C.byref(params),
+                self._t(phi_init, "phi_init", f32, ns, optional=True), *ws_args,
+                self._t(phi_sum, "phi_sum", f32, ns), self._t(phi_m2, "phi_m2", f32, ns, optional=True),
+                self._t(phi_states, "phi_states", f32, max(0, params.R * params.K) * ns, optional=True), st,
+                _stream(stream))
+        if not (allow_incomplete and rc == MPR_INCOMPLETE):
+            self._check(rc)
+        stats = [dict(relax_sweeps=s.relax_sweeps, not_converged=s.not_converged, a_final=s.a_final,
+                      A_last=s.A_last, k_last=s.k_last) for s in st]
+        return (rc == MPR_OK, stats) if allow_incomplete else stats
+
+    def simulate(self, imgs, phi, sampled, T_hat, params, ws, phi_sum, phi_init=None, stream=None, phi_m2=None,
+                 phi_states=None, allow_incomplete=False):
+        """Per-chain statistics; with allow_incomplete, (done, statistics),
+        done False when params.sweep_limit stopped the run (resume it with
+        params.resume = 1 on the same workspace contents)."""
+        return self._simulate(self.lib.mpr_simulate, (self._t(ws, "ws"), ws.numel() * ws.element_size()), imgs,
+                              phi, sampled, T_hat, params, phi_sum, phi_init, stream, phi_m2, phi_states,
+                              allow_incomplete)
 
     def simulate_noalloc(self, imgs, phi, sampled, T_hat, params, phi_sum, phi_init=None, stream=None, phi_m2=None,
-                         phi_states=None):
+                         phi_states=None, allow_incomplete=False):
         """simulate() on the library's static per-device workspace (no
         workspace argument, nothing allocated by the call)."""
-        import torch
-        n = len(imgs)
-        ns = sites_of(imgs)
-        T = np.ascontiguousarray(T_hat, dtype=np.float64)
-        if T.size < n:
-            raise ValueError(f"T_hat: {T.size} values for {n} images")
-        st = (ChainStats * (n * params.R))()
-        f32 = torch.float32
-        self._check(self.lib.mpr_simulate_noalloc(
-            self._h, imgs, n, self._t(phi, "phi", f32, ns), self._t(sampled, "sampled", torch.uint8, ns),
-            T.ctypes.data_as(C.c_void_p), C.byref(params), self._t(phi_init, "phi_init", f32, ns, optional=True),
-            self._t(phi_sum, "phi_sum", f32, ns), self._t(phi_m2, "phi_m2", f32, ns, optional=True),
-            self._t(phi_states, "phi_states", f32, max(0, params.R * params.K) * ns, optional=True), st,
-            _stream(stream)))
-        return [dict(relax_sweeps=s.relax_sweeps, not_converged=s.not_converged, a_final=s.a_final,
-                     A_last=s.A_last, k_last=s.k_last) for s in st]
+        return self._simulate(self.lib.mpr_simulate_noalloc, (), imgs, phi, sampled, T_hat, params, phi_sum,
+                              phi_init, stream, phi_m2, phi_states, allow_incomplete)
 
     def predict(self, imgs, z, sampled, phi_sum, zmin_zmax, M, z_hat, stream=None):
         import torch

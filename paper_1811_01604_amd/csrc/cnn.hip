@@ -273,6 +273,189 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
+// A residual block of the inference forward pass in one kernel:
+//   out = h + conv2(t) + b2,  t = bf16(ReLU(conv1(h) + b1))
+// with the inner activation t kept in LDS instead of a round trip through
+// HBM.  A persistent block of 4 waves loops over 14 x 30-pixel output tiles.
+// The (14 + 4) x (30 + 4) input pixels around a tile are staged in LDS like
+// conv3x3_kernel's tile (the same 18 x 34 shape), conv1 computes t on the
+// 16 x 32 pixels around the output tile (each wave 4 rows, the MFMA scheme
+// of conv3x3_kernel), rounds it to bfloat16 as the layer-by-layer path
+// stores it, and writes it to a second staged tile, zero outside the image
+// (conv2's zero padding) and in the tile's last two rows and columns; conv2
+// then computes 16 x 32 outputs of which the first 14 x 30 are the tile's
+// (the rest read the zero border), and its epilogue adds b2 and the skip
+// input from the staged input tile.  Every product and rounding is that of
+// the two conv3x3_kernel launches, so the output is the same bits.  Both
+// layers' packed weights live in LDS (144 KB in all: one block per CU).
+// Tiles are ordered so that each XCD takes a contiguous run of them: tiles
+// in flight on one XCD are neighbours and share their halo pixels in its L2.
+constexpr int RTH = CTH - 2, RTW = CTW - 2;  // output tile of the fused block
+
+struct ResArgs {
+    const bf16 *in;    // block input h, N x H x W x 32
+    const bf16 *w1;    // packed forward weights of the two convs
+    const bf16 *w2;
+    const float *b1;
+    const float *b2;
+    bf16 *out;
+    int N, H, W;
+};
+
+__device__ __forceinline__ void res_tile_origin(int tile, int tiles_x, int tiles_y, int &n, int &y0, int &x0)
+{
+    const int tx = tile % tiles_x;
+    const int rest = tile / tiles_x;
+    const int ty = rest % tiles_y;
+    n = rest / tiles_y;
+    y0 = ty * RTH;
+    x0 = tx * RTW;
+}
+
+// conv3x3_kernel's products of one staged tile: wave w's output rows
+// 4w .. 4w + 3, pixel column m = lane & 31, weights from LDS rows of 80 B.
+__device__ __forceinline__ void res_products(const bf16 *tile, const bf16 *wl, int wave, int m, int kq,
+                                             f32x16 (&acc)[4])
+{
+#pragma unroll
+    for (int o = 0; o < 4; ++o)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[o][i] = 0.0f;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int kh = 0; kh < 2; ++kh) {
+            bf16x8 wa[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                wa[d] = *reinterpret_cast<const bf16x8 *>(wl + ((d * 3 + dx) * CH + m) * PIXS + kh * 16 + kq * 8);
+#pragma unroll
+            for (int ir = 0; ir < 6; ++ir) {
+                const bf16x8 pb = *reinterpret_cast<const bf16x8 *>(
+                    tile + ((4 * wave + ir) * C_IN_W + m + dx) * PIXS + kh * 16 + kq * 8);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const int o = ir - d;
+                    if (o < 0 || o > 3) continue;
+                    acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[d], pb, acc[o], 0, 0, 0);
+                }
+            }
+        }
+}
+
+__global__ __launch_bounds__(256) void resblock_kernel(ResArgs a)
+{
+    __shared__ __attribute__((aligned(16))) bf16 itile[C_IN_T * PIXS];  // staged input, 18 x 34 pixels
+    __shared__ __attribute__((aligned(16))) bf16 ttile[C_IN_T * PIXS];  // inner activation, 18 x 34 pixels
+    __shared__ __attribute__((aligned(16))) bf16 wl1[C_W_ROWS * PIXS];  // packed weights, 288 rows each
+    __shared__ __attribute__((aligned(16))) bf16 wl2[C_W_ROWS * PIXS];
+    __shared__ float bl[2 * CH];                                        // b1, b2
+    const int tiles_x = (a.W + RTW - 1) / RTW, tiles_y = (a.H + RTH - 1) / RTH;
+    const int n_tiles = tiles_x * tiles_y * a.N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 31, kq = lane >> 5;
+    for (int k = threadIdx.x; k < C_W_ROWS * 4; k += blockDim.x) {
+        *reinterpret_cast<uint4 *>(wl1 + (k >> 2) * PIXS + (k & 3) * 8) =
+            *reinterpret_cast<const uint4 *>(a.w1 + (k >> 2) * CH + (k & 3) * 8);
+        *reinterpret_cast<uint4 *>(wl2 + (k >> 2) * PIXS + (k & 3) * 8) =
+            *reinterpret_cast<const uint4 *>(a.w2 + (k >> 2) * CH + (k & 3) * 8);
+    }
+    if (threadIdx.x < CH) {
+        bl[threadIdx.x] = a.b1[threadIdx.x];
+        bl[CH + threadIdx.x] = a.b2[threadIdx.x];
+    }
+    // the inner tile's border (rows 16, 17 and columns 32, 33) stays zero
+    for (int k = threadIdx.x; k < C_IN_T * 4; k += blockDim.x) {
+        const int pix = k >> 2, r = pix / C_IN_W, c = pix - r * C_IN_W;
+        if (r >= CTH || c >= CTW)
+            *reinterpret_cast<uint4 *>(ttile + pix * PIXS + (k & 3) * 8) = make_uint4(0u, 0u, 0u, 0u);
+    }
+    // this block's tiles: the blocks of XCD x = blockIdx % 8 (there are
+    // ceil((G - x) / 8) of them) take a contiguous run of the tile sequence
+    // in proportion to their number, in turn
+    const int G = (int)gridDim.x, xcd = (int)blockIdx.x & 7;
+    int before = 0;  // blocks on the XCDs below this one
+    for (int x = 0; x < xcd; ++x) before += (G - x + 7) >> 3;
+    const int nx8 = (G - xcd + 7) >> 3;  // blocks on this XCD (>= 1: this one)
+    const int t_lo = (int)((int64_t)n_tiles * before / G), t_hi = (int)((int64_t)n_tiles * (before + nx8) / G);
+    const int step = nx8;
+    int tile_id = t_lo + ((int)blockIdx.x >> 3);
+    uint4 pre[C_PER_THREAD];
+    uint32_t pre_valid = 0u;
+    if (tile_id < t_hi) {
+        int n, y0, x0;
+        res_tile_origin(tile_id, tiles_x, tiles_y, n, y0, x0);
+        conv_load_tile(a.in, n, a.H, a.W, y0 - 1, x0 - 1, pre, pre_valid);
+        conv_store_tile(itile, pre, pre_valid);
+    }
+    __syncthreads();
+    for (; tile_id < t_hi; tile_id += step) {
+        int n, y0, x0;
+        res_tile_origin(tile_id, tiles_x, tiles_y, n, y0, x0);
+        {
+            const int next = tile_id + step < t_hi ? tile_id + step : tile_id;
+            int n2, y2, x2;
+            res_tile_origin(next, tiles_x, tiles_y, n2, y2, x2);
+            conv_load_tile(a.in, n2, a.H, a.W, y2 - 1, x2 - 1, pre, pre_valid);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        f32x16 acc[4];
+        // conv1: t at rows y0 - 1 + 4 wave + o, columns x0 - 1 + m
+        res_products(itile, wl1, wave, m, kq, acc);
+        {
+            const int gx = x0 - 1 + m;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const int tr = 4 * wave + o, gy = y0 - 1 + tr;
+                const bool inside = gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int c0 = 8 * j + 4 * kq;
+                    uint2 tv = make_uint2(0u, 0u);
+                    if (inside) {
+                        bf16 *tp = reinterpret_cast<bf16 *>(&tv);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) tp[r] = (bf16)fmaxf(acc[o][4 * j + r] + bl[c0 + r], 0.0f);
+                    }
+                    *reinterpret_cast<uint2 *>(ttile + (tr * C_IN_W + m) * PIXS + c0) = tv;
+                }
+            }
+        }
+        __syncthreads();  // t complete
+        // conv2: outputs at rows y0 + 4 wave + o, columns x0 + m
+        res_products(ttile, wl2, wave, m, kq, acc);
+        {
+            const int gx = x0 + m;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const int orow = 4 * wave + o, gy = y0 + orow;
+                if (orow >= RTH || m >= RTW || gy >= a.H || gx >= a.W) continue;
+                const int64_t pix = ((int64_t)n * a.H + gy) * a.W + gx;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int c0 = 8 * j + 4 * kq;
+                    const uint2 w2 = *reinterpret_cast<const uint2 *>(itile + ((orow + 2) * C_IN_W + m + 2) * PIXS + c0);
+                    float v[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] = acc[o][4 * j + r] + bl[CH + c0 + r];
+                    v[0] += __uint_as_float(w2.x << 16);
+                    v[1] += __uint_as_float(w2.x & 0xFFFF0000u);
+                    v[2] += __uint_as_float(w2.y << 16);
+                    v[3] += __uint_as_float(w2.y & 0xFFFF0000u);
+                    uint2 ov;
+                    bf16 *op = reinterpret_cast<bf16 *>(&ov);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) op[r] = (bf16)v[r];
+                    *reinterpret_cast<uint2 *>(a.out + pix * CH + c0) = ov;
+                }
+            }
+        }
+        __syncthreads();  // every wave is done with both tiles
+        if (tile_id + step < t_hi) conv_store_tile(itile, pre, pre_valid);
+        __syncthreads();
+    }
+}
+
 struct WgradArgs {
     const bf16 *in;     // layer input, N x H x W x 32
     const bf16 *gout;   // output gradient, N x H x W x 32
@@ -526,6 +709,24 @@ void launch_conv(hipStream_t st, const bf16 *in, const bf16 *wpack, const float 
     }
 }
 
+void launch_resblock(hipStream_t st, const bf16 *in, const bf16 *w1, const float *b1, const bf16 *w2,
+                     const float *b2, bf16 *out, int n, int h, int w)
+{
+    ResArgs a;
+    a.in = in;
+    a.w1 = w1;
+    a.w2 = w2;
+    a.b1 = b1;
+    a.b2 = b2;
+    a.out = out;
+    a.N = n;
+    a.H = h;
+    a.W = w;
+    // persistent: one block per compute unit (144 KB of LDS each)
+    const int64_t tiles = (int64_t)n * ((h + RTH - 1) / RTH) * ((w + RTW - 1) / RTW);
+    hipLaunchKernelGGL(resblock_kernel, dim3((unsigned)std::min<int64_t>(tiles, 256)), dim3(256), 0, st, a);
+}
+
 void launch_wgrad(hipStream_t st, const bf16 *in, const bf16 *gout, const bf16 *gref, float *partial, float *grads,
                   int n, int h, int w)
 {
@@ -644,10 +845,15 @@ int32_t mpr_cnn_forward(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const flo
     hipStream_t st = (hipStream_t)stream;
     launch_conv(st, (const bf16 *)x, fwd_pack(packed, 0), bias_of(params, 0), nullptr, nullptr, 1, A.h[0], n, h, w);
     for (int b = 0; b < NBLK; ++b) {
-        launch_conv(st, A.h[b], fwd_pack(packed, 1 + 2 * b), bias_of(params, 1 + 2 * b), nullptr, nullptr, 1, A.t[b],
-                    n, h, w);
-        launch_conv(st, A.t[b], fwd_pack(packed, 2 + 2 * b), bias_of(params, 2 + 2 * b), A.h[b], nullptr, 0,
-                    A.h[b + 1], n, h, w);
+        if (training) {  // the inner activations are kept for the backward pass
+            launch_conv(st, A.h[b], fwd_pack(packed, 1 + 2 * b), bias_of(params, 1 + 2 * b), nullptr, nullptr, 1,
+                        A.t[b], n, h, w);
+            launch_conv(st, A.t[b], fwd_pack(packed, 2 + 2 * b), bias_of(params, 2 + 2 * b), A.h[b], nullptr, 0,
+                        A.h[b + 1], n, h, w);
+        } else {  // the same bits with the inner activation in LDS
+            launch_resblock(st, A.h[b], fwd_pack(packed, 1 + 2 * b), bias_of(params, 1 + 2 * b),
+                            fwd_pack(packed, 2 + 2 * b), bias_of(params, 2 + 2 * b), A.h[b + 1], n, h, w);
+        }
     }
     launch_conv(st, A.h[NBLK], fwd_pack(packed, NLAYER - 1), bias_of(params, NLAYER - 1), nullptr, nullptr, 0,
                 (bf16 *)y, n, h, w);

@@ -32,6 +32,8 @@
 #include "../../include/mpr.h"
 #include "mpr_device.h"
 
+static_assert(sizeof(mpr_params) == 128, "mpr_params layout");
+
 using namespace mpr;
 
 namespace {
@@ -823,8 +825,9 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
 // the block after each colour, before anything reads them.  The gap sites
 // of the tile are then written to the chain's second half-grids (h2):
 // reading h and writing h2 keeps every tile's halo at the state before the
-// sweep while other tiles store theirs.  The last block to finish swaps h
-// and h2 of every chain it swept, and runs the per-sweep control.
+// sweep while other tiles store theirs.  control_kernel then swaps h and h2
+// of every chain swept (one thread per chain: no block of the sweep waits
+// for the others) before it runs the per-sweep control.
 //
 // Within a colour the gap sites are listed in LDS first (wave ballots; each
 // wave lists the candidates it read, interleaved with the other waves at 64
@@ -872,8 +875,10 @@ __device__ __noinline__ SiteOutD tile_redo_site(const float *a, int rows, int c,
 
 template <int TH>
 struct TileShared {
-    static constexpr int NA = (TH + 2) * (kTileH + 2);      // candidates of the colour-0 pass with its ring
-    static constexpr int CAP = (NA + kBlock - 1) / kBlock * 64;  // list entries per wave
+    // list entries per wave: its rows of the colour-0 pass with the ring
+    // (TH + 2 rows of kTileH columns, a row per wave in turn) and its share
+    // of the ring's two side columns (at most 64 per wave)
+    static constexpr int CAP = (TH + 2 + kTileNW - 1) / kTileNW * 64 + 64;
     static constexpr int RW = ((TH + 4) * kTileLS + 31) / 32;     // redo bitmap words
     alignas(16) float a[2][TH + 4][kTileLS];  // angle words (sign bit: sampled), colour, row, half-column
     // per wave: gap entries from the front, sampled entries from the back;
@@ -882,7 +887,6 @@ struct TileShared {
     uint32_t redo[RW];
     uint32_t red[3][kTileNW];
     int any_redo[2];
-    int last;
 };
 
 template <bool DIAG, int TH, bool EDGE>
@@ -932,25 +936,21 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
     }
     __syncthreads();
 
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int npass = mode == 0 ? 2 : 1;
     for (int pass = 0; pass < npass; ++pass) {
         const int c = mode == 0 ? pass : mode - 1;
         const bool ring = mode == 0 && c == 0;       // colour 0 of a full sweep: tile and ring
         const bool energy = c == 1 && !eq;           // the sweep's energy comes from colour 1
-        const int ncols = ring ? kTileH + 2 : kTileH;
-        const int ncand = ring ? (TH + 2) * (kTileH + 2) : TH * kTileH;
-        const int r_lo = ring ? 1 : 2, j_lo = ring ? 3 : 4;
+        const int r_lo = ring ? 1 : 2, r_hi = TH + (ring ? 3 : 2);
         uint16_t *lst = L.list[wid];
-        // list the gap sites (and, for the energy, the sampled sites)
+        // list the gap sites (and, for the energy, the sampled sites): a
+        // wave takes one row at a time, lane l its tile column j = 4 + l;
+        // with the ring, then the ring's side columns j = 3 and kTileH + 4,
+        // two lanes per row
         int ng = 0, ns = 0;
-        for (int base = 0; base < ncand; base += kBlock) {
-            const int i = base + wid * 64 + lane;
+        auto add = [&](bool cand, int r, int j) {
             bool gap = false, smp = false;
-            uint32_t ent = 0u;
-            if (i < ncand) {
-                const int rr = ring ? i / (kTileH + 2) : i / kTileH;
-                const int r = r_lo + rr, j = j_lo + (i - rr * ncols);
+            if (cand) {
                 const float v = L.a[c][r][j];
                 bool in = true;
                 if (EDGE) {
@@ -959,13 +959,21 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
                 }
                 gap = in && !is_fixed(v);
                 smp = energy && in && is_fixed(v);
-                ent = ((uint32_t)r << 7) | (uint32_t)j;
             }
-            const uint64_t bg = __ballot(gap), bs = __ballot(smp);
-            if (gap) lst[ng + __popcll(bg & below)] = (uint16_t)ent;
-            if (smp) lst[TileShared<TH>::CAP - 1 - (ns + __popcll(bs & below))] = (uint16_t)ent;
+            const uint16_t ent = (uint16_t)((r << 7) | j);
+            const uint64_t bg = __ballot(gap);
+            if (gap) lst[ng + rank_below(bg)] = ent;
             ng += __popcll(bg);
-            ns += __popcll(bs);
+            if (energy) {
+                const uint64_t bs = __ballot(smp);
+                if (smp) lst[TileShared<TH>::CAP - 1 - (ns + rank_below(bs))] = ent;
+                ns += __popcll(bs);
+            }
+        };
+        for (int r = r_lo + wid; r < r_hi; r += kTileNW) add(true, r, 4 + lane);
+        if (ring) {
+            const int k = wid * 64 + lane;
+            add(k < 2 * (TH + 2), 1 + (k >> 1), (k & 1) ? kTileH + 4 : 3);
         }
         __syncthreads();
         // the listed gap sites
@@ -1074,29 +1082,34 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
                 const uint32_t idx = (uint32_t)(y * d.S + h);
                 gsti4(dst, idx, v);
                 if (ap) {
+                    // the group's gap sites into the equilibrium sums (and the
+                    // squared deviations), the arithmetic of accumulate_state,
+                    // with 16-byte loads and stores; the other elements keep
+                    // their values
                     const int W = (d.nx - ((y + cc) & 1) + 1) >> 1;
-                    const float vv[4] = {v.x, v.y, v.z, v.w};
                     const bool gg[4] = {g0, g1, g2, g3};
+                    const v4f s0 = gldi4(ap, idx);
+                    v4f s1 = s0;
+                    v4f m = mp ? gldi4(mp, idx) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        if (gg[e] && h + e < W) accumulate_state_i(ap, mp, idx + (uint32_t)e, vv[e], ik, ikm1);
+                        if (gg[e] && h + e < W) {
+                            s1[e] = s0[e] + v[e];
+                            m[e] = fmaf(v[e] - s0[e] * ikm1, v[e] - s1[e] * ik, m[e]);
+                        }
+                    gsti4(ap, idx, s1);
+                    if (mp) gsti4(mp, idx, m);
                 }
             }
         }
     }
 }
 
-struct TileControl {
-    FusedControl f;   // f.on: run the per-sweep control in the last block
-    int32_t swap;     // full sweeps: swap h and h2 of the swept chains in the last block
-    int32_t pad;
-};
-
 template <bool DIAG, int TH>
-__global__ __launch_bounds__(kBlock) void sweep_tile_kernel(ChainDesc *__restrict__ descs,
+__global__ __launch_bounds__(kBlock) void sweep_tile_kernel(const ChainDesc *__restrict__ descs,
                                                             ChainState *__restrict__ states, BlockMap bm,
                                                             int mode, SweepConsts sc, int or_only,
-                                                            uint8_t *__restrict__ flags, TileControl tc)
+                                                            uint8_t *__restrict__ flags)
 {
     __shared__ TileShared<TH> L;
     const int tid = (int)threadIdx.x;
@@ -1151,33 +1164,6 @@ __global__ __launch_bounds__(kBlock) void sweep_tile_kernel(ChainDesc *__restric
             }
         }
     }
-    if (!tc.swap && !tc.f.on) return;
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        L.last = atomicAdd(tc.f.ticket, 1u) == gridDim.x - 1u;
-    }
-    __syncthreads();
-    if (!L.last) return;
-    __threadfence();  // the other blocks' sums and stores are visible
-    if (tc.swap) {
-        for (int k = tid; k < bm.n; k += kBlock) {
-            const int c = bm.id[k];
-            if (states[c].phase == PH_DONE) continue;
-            ChainDesc &dd = descs[c];
-            float *t0 = dd.h[0], *t1 = dd.h[1];
-            dd.h[0] = dd.h2[0];
-            dd.h[1] = dd.h2[1];
-            dd.h2[0] = t0;
-            dd.h2[1] = t1;
-        }
-        __threadfence();
-        __syncthreads();
-    }
-    if (tc.f.on)
-        for (int c = tid; c < tc.f.n_all; c += kBlock)
-            control_chain(descs, states, c, tc.f.cp, tc.f.done_count, tc.f.work);
-    if (tid == 0) *tc.f.ticket = 0u;
 }
 
 // The double-precision sweep: the layout of half_sweep_body (a thread per
@@ -1493,12 +1479,26 @@ __global__ __launch_bounds__(kBlock) void half_sweep_fp64_compact_kernel(const C
     }
 }
 
-// control_chain for every chain, one thread per chain.
-__global__ void control_kernel(const ChainDesc *__restrict__ descs, ChainState *__restrict__ states, int n,
-                               CtlParams cp, unsigned int *done_count, unsigned long long *work)
+// control_chain for every chain, one thread per chain.  With `swap` (after
+// a fused tile sweep, which read h and wrote h2) it first exchanges h and h2
+// of every chain that sweep updated (those not done), toggling the chain's
+// `swapped` flag; with `control` 0 it does only that.
+__global__ void control_kernel(ChainDesc *__restrict__ descs, ChainState *__restrict__ states, int n,
+                               CtlParams cp, unsigned int *done_count, unsigned long long *work, int swap,
+                               int control)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < n) control_chain(descs, states, c, cp, done_count, work);
+    if (c >= n) return;
+    if (swap && states[c].phase != PH_DONE) {
+        ChainDesc &d = descs[c];
+        float *t0 = d.h[0], *t1 = d.h[1];
+        d.h[0] = d.h2[0];
+        d.h[1] = d.h2[1];
+        d.h2[0] = t0;
+        d.h2[1] = t1;
+        states[c].swapped ^= 1;
+    }
+    if (control) control_chain(descs, states, c, cp, done_count, work);
 }
 
 // 1 for every chain that is done, else 0 (for rebuilding the launch list).
@@ -2171,7 +2171,8 @@ bool valid_params(const mpr_params *p)
            (p->tile_rows == 0 || shape_of(p->tile_rows) >= 0) &&
            p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096 && (p->spread == 0 || p->spread == 1) &&
            (p->fp64 == 0 || p->fp64 == 1) &&
-           (p->table_side_cap == 0 || p->table_side_cap >= 2) && p->warm_min_states >= 0;
+           (p->table_side_cap == 0 || p->table_side_cap >= 2) && p->warm_min_states >= 0 && p->sweep_limit >= 0 &&
+           (p->resume == 0 || p->resume == 1);
 }
 
 bool valid_images(const mpr_image *imgs, int n)
@@ -2187,9 +2188,21 @@ bool valid_images(const mpr_image *imgs, int n)
     return true;
 }
 
+// Head of a simulate workspace: what a resumed call checks before it
+// continues the run the workspace holds.
+struct RunHeader {
+    uint64_t magic;     // kRunMagic
+    uint64_t key;       // run_key of the images and parameters
+    int64_t bytes;      // sim_bytes of the run
+    int32_t n_chains;
+    int32_t state;      // 1: stopped at sweep_limit with chains running (resumable)
+};
+constexpr uint64_t kRunMagic = 0x4D50522D52554E31ull;  // "MPR-RUN1"
+constexpr int64_t kRunHeaderBytes = 256;
+
 int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
 {
-    int64_t b = 0;
+    int64_t b = kRunHeaderBytes;
     for (int i = 0; i < n; ++i) {
         const int64_t hg = round_up(half_grid_bytes(imgs[i].nx, imgs[i].ny, p->fp64 ? 8 : 4), 256);
         // angles (twice for single precision: the fused sweep's second buffer),
@@ -2202,6 +2215,34 @@ int64_t sim_bytes(const mpr_image *imgs, int n, const mpr_params *p)
     b += round_up(kNumShapes * (chains + 1) * 8, 256) + round_up(chains * 4 + 4, 256);
     for (int i = 0; i < n; ++i) b += redo_bytes(imgs[i].nx, imgs[i].ny, p->R);
     return b;
+}
+
+// FNV-1a over the images (size, offset, id), the parameters that shape a
+// run's chains (all but sweep_limit, resume, tile_rows and
+// sweeps_per_launch, which do not change its results) and the temperatures.
+uint64_t run_key(const mpr_image *imgs, int n, const mpr_params *p, const double *T_hat)
+{
+    uint64_t h = 0xCBF29CE484222325ull;
+    auto mix = [&h](const void *v, size_t len) {
+        const unsigned char *b = (const unsigned char *)v;
+        for (size_t i = 0; i < len; ++i) h = (h ^ b[i]) * 0x100000001B3ull;
+    };
+    mix(&n, sizeof n);
+    for (int i = 0; i < n; ++i) {
+        mix(&imgs[i].nx, 4);
+        mix(&imgs[i].ny, 4);
+        mix(&imgs[i].offset, 8);
+        mix(&imgs[i].id, 4);
+    }
+    mpr_params q = *p;
+    q.sweep_limit = 0;
+    q.resume = 0;
+    q.tile_rows = 0;
+    q.sweeps_per_launch = 0;
+    q.reserved = 0;
+    mix(&q, sizeof q);
+    mix(T_hat, sizeof(double) * (size_t)n);
+    return h;
 }
 
 // Table chains run in double precision when q != 1/2 (the single-precision
@@ -2446,21 +2487,21 @@ void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colo
 // of it in place (mode 1, 2: diagnostics).
 template <bool DIAG>
 void launch_tile(hipStream_t st, const ChainSet &cs, int v, int mode, const SweepConsts &sc, int or_only,
-                 uint8_t *flags, const TileControl &tc)
+                 uint8_t *flags)
 {
     const dim3 grid((unsigned)cs.total_blocks[v]), blk(kBlock);
     switch (kShapes[v].rows) {
         case 16:
             hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 16>), grid, blk, 0, st, cs.d_desc, cs.d_state,
-                               block_map(cs, v), mode, sc, or_only, flags, tc);
+                               block_map(cs, v), mode, sc, or_only, flags);
             break;
         case 24:
             hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 24>), grid, blk, 0, st, cs.d_desc, cs.d_state,
-                               block_map(cs, v), mode, sc, or_only, flags, tc);
+                               block_map(cs, v), mode, sc, or_only, flags);
             break;
         default:
             hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 32>), grid, blk, 0, st, cs.d_desc, cs.d_state,
-                               block_map(cs, v), mode, sc, or_only, flags, tc);
+                               block_map(cs, v), mode, sc, or_only, flags);
             break;
     }
 }
@@ -2493,9 +2534,11 @@ int set_active(mpr_ctx *ctx, ChainSet &cs, const std::vector<int32_t> &active, h
 // Sweeps run on ctx->gstream: a few direct sweeps per block shape first (to
 // tune it, unless fixed or cached), then groups of `spl` sweeps replayed as
 // a captured graph (launched directly when `graphs` is false: instantiating
-// a graph allocates), checking the done-counter after each group.
+// a graph allocates), checking the done-counter after each group.  At most
+// max_sweeps sweeps run; chains still running then are an error, or with
+// `stop_ok` the result MPR_INCOMPLETE.
 int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stream, int64_t max_sweeps,
-               int poll_every, bool table, bool graphs = true)
+               int poll_every, bool table, bool graphs = true, bool stop_ok = false)
 {
     const int n = (int)cs.desc.size();
     unsigned int *d_done = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kDoneOffset);
@@ -2530,15 +2573,20 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     fc.work = d_work;
     fc.n_all = n;
     fc.on = 1;
-    TileControl tcl;
-    tcl.f = fc;
-    tcl.f.on = fuse ? 1 : 0;
-    tcl.swap = 1;
-    tcl.pad = 0;
+    auto control = [&](int swap, int ctl) {
+        hipLaunchKernelGGL(control_kernel, dim3(cblocks), dim3(64), 0, st, cs.d_desc, cs.d_state, n, cp, d_done,
+                           d_work, swap, ctl);
+    };
+    // A sweep: the fused tile sweep, then control_kernel with the swap of
+    // h and h2 (and the control, unless the states are recorded in between);
+    // or two half-sweeps, the colour-1 redo kernel running the control
+    // unless the states are recorded (or the chains are double precision).
     auto sweeps = [&](int v, int count) {
         for (int i = 0; i < count; ++i) {
-            if (kShapes[v].fused) {
-                launch_tile<false>(st, cs, v, 0, sc, 0, nullptr, tcl);
+            const bool fused = kShapes[v].fused;
+            if (fused) {
+                launch_tile<false>(st, cs, v, 0, sc, 0, nullptr);
+                control(1, cs.states_out ? 0 : 1);
             } else {
                 launch_half(st, cs, v, table, 0, sc);
                 launch_half(st, cs, v, table, 1, sc, fuse ? &fc : nullptr);
@@ -2547,9 +2595,7 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
                 hipLaunchKernelGGL(record_states_kernel, dim3((unsigned)(cs.n_active * kRecordSegs)), dim3(kBlock), 0,
                                    st, cs.d_desc, cs.d_state, cs.d_offset, cs.d_ids, kRecordSegs, cs.K,
                                    cs.fp64 ? 1 : 0, cs.states_n_total, cs.states_out);
-            if (!fuse)
-                hipLaunchKernelGGL(control_kernel, dim3(cblocks), dim3(64), 0, st, cs.d_desc, cs.d_state, n, cp,
-                                   d_done, d_work);
+            if (fused ? cs.states_out != nullptr : !fuse) control(0, 1);
         }
     };
     int64_t done_sweeps = 0;
@@ -2649,7 +2695,9 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     const bool can_shrink = (int64_t)n <= (int64_t)kScratchBytes - kVarOffset;
     int rc = MPR_OK;
     while (!finished && done_sweeps < max_sweeps) {
-        rc = block(v, spl, ge, nullptr);
+        // the last group may be shorter: exactly max_sweeps sweeps run
+        const int cnt = (int)std::min<int64_t>(spl, max_sweeps - done_sweeps);
+        rc = block(v, cnt, cnt == spl ? ge : nullptr, nullptr);
         if (rc) break;
         const unsigned int done_now = *ctx->done_host + already;
         if (finished || !can_shrink || done_now - done_listed < std::max(1u, (unsigned int)cs.n_active / 8u))
@@ -2675,7 +2723,9 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     if (rc) return rc;
     HIP_TRY(ctx, hipEventRecord(ctx->ev_out, st));
     HIP_TRY(ctx, hipStreamWaitEvent(stream, ctx->ev_out, 0));
-    if (!finished) return fail(ctx, MPR_ERR_HIP, "chains did not finish within %lld sweeps", (long long)max_sweeps);
+    if (!finished)
+        return stop_ok ? MPR_INCOMPLETE
+                       : fail(ctx, MPR_ERR_HIP, "chains did not finish within %lld sweeps", (long long)max_sweeps);
     return MPR_OK;
 }
 
@@ -2725,19 +2775,34 @@ ChainState fresh_state(double T, int phase)
     return s;
 }
 
-int upload_chains(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream, double q)
+// With `resume` the states are not uploaded but read back from the
+// workspace (the run it holds), and each chain whose fused sweeps left h and
+// h2 exchanged gets them exchanged in its descriptor too.
+int upload_chains(mpr_ctx *ctx, ChainSet &cs, Carver &cv, hipStream_t stream, double q, bool resume = false)
 {
     const int n = (int)cs.desc.size();
     cs.d_desc = (ChainDesc *)cv.take(n * (int64_t)sizeof(ChainDesc));
     cs.d_state = (ChainState *)cv.take(n * (int64_t)sizeof(ChainState));
     cs.d_offset = (int64_t *)cv.take(n * 8);
     if (!cs.d_desc || !cs.d_state || !cs.d_offset) return fail(ctx, MPR_ERR_WORKSPACE, "workspace too small");
-    for (auto &s : cs.state) {
-        s.inv_T = (float)(1.0 / s.T);
-        s.dscale = (float)(kTwoPi * q / s.a_cur);
+    if (resume) {
+        HIP_TRY(ctx, hipMemcpyAsync(cs.state.data(), cs.d_state, n * sizeof(ChainState), hipMemcpyDeviceToHost,
+                                    stream));
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        for (int c = 0; c < n; ++c)
+            if (cs.state[c].swapped) {
+                std::swap(cs.desc[c].h[0], cs.desc[c].h2[0]);
+                std::swap(cs.desc[c].h[1], cs.desc[c].h2[1]);
+            }
+    } else {
+        for (auto &s : cs.state) {
+            s.inv_T = (float)(1.0 / s.T);
+            s.dscale = (float)(kTwoPi * q / s.a_cur);
+        }
+        HIP_TRY(ctx, hipMemcpyAsync(cs.d_state, cs.state.data(), n * sizeof(ChainState), hipMemcpyHostToDevice,
+                                    stream));
     }
     HIP_TRY(ctx, hipMemcpyAsync(cs.d_desc, cs.desc.data(), n * sizeof(ChainDesc), hipMemcpyHostToDevice, stream));
-    HIP_TRY(ctx, hipMemcpyAsync(cs.d_state, cs.state.data(), n * sizeof(ChainState), hipMemcpyHostToDevice, stream));
     HIP_TRY(ctx, hipMemcpyAsync(cs.d_offset, cs.offset.data(), n * 8, hipMemcpyHostToDevice, stream));
     return upload_starts(ctx, cs, cv, stream);
 }
@@ -3135,6 +3200,24 @@ static int32_t simulate_call(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, con
     // via a device reduction would need scratch; count with the e_s-style
     // partials instead, reusing the map kernel's layout.
     Carver cv{(char *)ws, ws_bytes};
+    // the run header: checked before a resumed run continues; a fresh run
+    // marks the workspace as not resumable until it stops at sweep_limit
+    RunHeader *d_hdr = (RunHeader *)cv.take(kRunHeaderBytes);
+    const uint64_t key = run_key(imgs, n, p, T_hat);
+    const bool resume = p->resume != 0;
+    RunHeader hdr{kRunMagic, key, sim_bytes(imgs, n, p), n * p->R, 0};
+    if (resume) {
+        RunHeader old;
+        HIP_TRY(ctx, hipMemcpyAsync(&old, d_hdr, sizeof old, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        if (old.magic != hdr.magic || old.key != hdr.key || old.bytes != hdr.bytes || old.n_chains != hdr.n_chains ||
+            old.state != 1)
+            return fail(ctx, MPR_ERR_ARG,
+                        "simulate: resume needs a workspace holding a run stopped at sweep_limit with the same "
+                        "images, parameters and temperatures");
+    } else {
+        HIP_TRY(ctx, hipMemcpyAsync(d_hdr, &hdr, sizeof hdr, hipMemcpyHostToDevice, stream));
+    }
     ImgDev *d_img = (ImgDev *)cv.take(n * (int64_t)sizeof(ImgDev));
     std::vector<ImgDev> hi(n);
     for (int b = 0; b < n; ++b) hi[b] = {imgs[b].offset, imgs[b].nx, imgs[b].ny};
@@ -3194,29 +3277,45 @@ static int32_t simulate_call(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, con
             cs.states_n_total = std::max(cs.states_n_total, imgs[b].offset + (int64_t)imgs[b].nx * imgs[b].ny);
     }
     const int eb = cs.fp64 ? 8 : 4;
-    int rc = upload_chains(ctx, cs, cv, stream, p->q);
+    int rc = upload_chains(ctx, cs, cv, stream, p->q, resume);
     if (rc) return rc;
     int64_t maxn = 0;
     for (int b = 0; b < n; ++b) maxn = std::max(maxn, (int64_t)imgs[b].nx * imgs[b].ny);
-    for (auto &d : cs.desc)
-        for (int c = 0; c < 2; ++c) {
-            HIP_TRY(ctx, hipMemsetAsync(d.h[c], 0, half_grid_bytes(d.nx, d.ny, eb), stream));
-            if (d.h2[c]) HIP_TRY(ctx, hipMemsetAsync(d.h2[c], 0, half_grid_bytes(d.nx, d.ny, eb), stream));
-        }
-    hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), (unsigned)cs.desc.size()), dim3(kBlock), 0,
-                       stream, cs.d_desc, cs.d_offset, phi, sampled, phi_init, (uint32_t)p->seed,
-                       (uint32_t)(p->seed >> 32), 0, cs.fp64 ? 1 : 0);
-    HIP_TRY(ctx, hipGetLastError());
+    if (!resume) {
+        for (auto &d : cs.desc)
+            for (int c = 0; c < 2; ++c) {
+                HIP_TRY(ctx, hipMemsetAsync(d.h[c], 0, half_grid_bytes(d.nx, d.ny, eb), stream));
+                if (d.h2[c]) HIP_TRY(ctx, hipMemsetAsync(d.h2[c], 0, half_grid_bytes(d.nx, d.ny, eb), stream));
+            }
+        hipLaunchKernelGGL(init_chains_kernel, dim3(blocks_for(maxn, 2048), (unsigned)cs.desc.size()), dim3(kBlock),
+                           0, stream, cs.d_desc, cs.d_offset, phi, sampled, phi_init, (uint32_t)p->seed,
+                           (uint32_t)(p->seed >> 32), 0, cs.fp64 ? 1 : 0);
+        HIP_TRY(ctx, hipGetLastError());
+    }
+    // sweeps left to the run's cap (a resumed run has done `swept` of them),
+    // and to this call's sweep_limit
     const int64_t relax_cap = p->fixed_relax >= 0 ? p->fixed_relax : (int64_t)p->i_max + 1;
-    rc = run_chains(ctx, cs, p, stream, relax_cap + p->K + 1, p->n_f, false, graphs);
-    if (rc) return rc;
-    if (cs.fp64)
-        hipLaunchKernelGGL(finalize_fp64_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, cs.d_desc,
-                           d_img, p->R, p->K, sampled, phi_sum, phi_m2);
-    else
-        hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream, cs.d_desc,
-                           d_img, p->R, p->K, sampled, phi_sum, phi_m2);
-    HIP_TRY(ctx, hipGetLastError());
+    int64_t swept = 0;
+    for (const auto &st : cs.state) swept = std::max<int64_t>(swept, (int64_t)st.sweep);
+    int64_t limit = std::max<int64_t>(1, relax_cap + p->K + 1 - swept);
+    if (p->sweep_limit > 0) limit = std::min<int64_t>(limit, p->sweep_limit);
+    rc = run_chains(ctx, cs, p, stream, limit, p->n_f, false, graphs, p->sweep_limit > 0);
+    const bool incomplete = rc == MPR_INCOMPLETE;
+    if (rc && !incomplete) return rc;
+    if (incomplete || resume) {
+        // resumable while chains are running, not once the run is finished
+        hdr.state = incomplete ? 1 : 0;
+        HIP_TRY(ctx, hipMemcpyAsync(d_hdr, &hdr, sizeof hdr, hipMemcpyHostToDevice, stream));
+    }
+    if (!incomplete) {  // an incomplete run writes no outputs, only its statistics so far
+        if (cs.fp64)
+            hipLaunchKernelGGL(finalize_fp64_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream,
+                               cs.d_desc, d_img, p->R, p->K, sampled, phi_sum, phi_m2);
+        else
+            hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(maxn, 4096), n), dim3(kBlock), 0, stream,
+                               cs.d_desc, d_img, p->R, p->K, sampled, phi_sum, phi_m2);
+        HIP_TRY(ctx, hipGetLastError());
+    }
     if (stats) {
         HIP_TRY(ctx, hipMemcpyAsync(cs.state.data(), cs.d_state, cs.state.size() * sizeof(ChainState),
                                     hipMemcpyDeviceToHost, stream));
@@ -3232,7 +3331,7 @@ static int32_t simulate_call(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, con
             stats[c].k_last = s.k;
         }
     }
-    return MPR_OK;
+    return incomplete ? MPR_INCOMPLETE : MPR_OK;
 }
 
 int32_t mpr_simulate(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const float *phi, const uint8_t *sampled,
@@ -3578,9 +3677,7 @@ int32_t mpr_diag_half_sweep(mpr_ctx *ctx, int32_t nx, int32_t ny, float *phi, co
     const Shape sh = kShapes[v];
     const Redo rd = cs.redo;
     if (sh.fused) {
-        TileControl tc;
-        std::memset(&tc, 0, sizeof tc);
-        launch_tile<true>(stream, cs, v, colour + 1, sc, mode, flags, tc);
+        launch_tile<true>(stream, cs, v, colour + 1, sc, mode, flags);
     } else if (sh.compact) {
         if (sh.rows == 2)
             hipLaunchKernelGGL((half_sweep_compact_kernel<true, 2>), grid, dim3(kBlock), 0, stream, cs.d_desc,

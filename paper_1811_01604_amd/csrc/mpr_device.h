@@ -63,7 +63,8 @@ struct ChainState {
     int32_t eq_left;
     float inv_k;           // 1 / k and 1 / (k - 1) for the k-th equilibrium state
     float inv_km1;         // of the next sweep (k = 1: 1 and 0)
-    int32_t pad;
+    int32_t swapped;       // 1 while the chain's h and h2 are exchanged (fused sweeps
+                           // toggle it), so that a resumed run can rebuild its descriptor
     double inv_k_d;        // the same in double (double-precision chains)
     double inv_km1_d;
     double ring[kMaxFit];  // last n_fit values of 1 + e
@@ -113,6 +114,13 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 __device__ __forceinline__ float unit24(uint32_t w)
 {
     return (float)(w >> 8) * 5.9604644775390625e-08f;
+}
+
+// Set bits of the wave mask m in the lanes below this one (a lane's rank
+// among the lanes whose bit is set).
+__device__ __forceinline__ int rank_below(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // ------------------------------------------------------------- sign bit

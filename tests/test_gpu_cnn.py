@@ -184,6 +184,34 @@ def test_network_forward_loss_backward(ctx):
     assert np.all(g[-1, WSZ + 2:] == 0)
 
 
+@pytest.mark.parametrize("shape", [(1, 8, 32), (2, 37, 61), (1, 14, 30), (1, 15, 31), (3, 71, 100)])
+def test_fused_residual_blocks_equal_the_layer_by_layer_forward(ctx, shape):
+    """Inference runs each residual block as one kernel (the inner
+    activation in LDS, rounded to bfloat16 as the layer-by-layer path stores
+    it); the training forward runs the convs one by one.  Their outputs must
+    be the same bits, on shapes smaller than, equal to, one more than and
+    several times the 14 x 30 output tile, and the inference output meets
+    the oracle's bar."""
+    n, h, w = shape
+    params = layer_params(7 + h, scale=0.15)
+    p, packed = packs(ctx, params)
+    rng = np.random.default_rng(w)
+    xo = cnn.bf16_round(rng.normal(0, 1, size=(n, h, w, 32)))
+    x = to_bf16(xo)
+    y_inf, y_train = torch.empty_like(x), torch.empty_like(x)
+    ws_i = torch.empty(ctx.cnn_workspace_size(n, h, w, False), dtype=torch.uint8, device="cuda")
+    ws_t = torch.empty(ctx.cnn_workspace_size(n, h, w, True), dtype=torch.uint8, device="cuda")
+    ctx.cnn_forward(p, packed, x, ws_i, y_inf, training=False)
+    ctx.cnn_forward(p, packed, x, ws_t, y_train, training=True)
+    torch.cuda.synchronize()
+    a = y_inf.view(torch.int16).cpu().numpy()
+    b = y_train.view(torch.int16).cpu().numpy()
+    assert np.array_equal(a, b), int((a != b).sum())
+    yo, _ = forward_bf16(rounded(params), xo)
+    err, c = close(from_dev(y_inf), yo)
+    say(f"  {shape}: bit-equal; against the oracle max rel err {err:.2e}, cosine {c:.6f}")
+
+
 def test_decode_matches_oracle(ctx):
     rng = np.random.default_rng(4)
     n, h, w = 1, 9, 40

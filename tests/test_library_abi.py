@@ -35,7 +35,8 @@ def test_library_is_gfx950_code_object():
 def test_struct_layouts_match_header():
     # sizes implied by the header's field order (natural alignment)
     assert C.sizeof(mpr.Image) == 24
-    assert C.sizeof(mpr.Params) == 120
+    assert C.sizeof(mpr.Params) == 128
+    assert mpr.Params.sweep_limit.offset == 116 and mpr.Params.resume.offset == 120
     assert C.sizeof(mpr.ChainStats) == 32
 
 
