@@ -244,10 +244,11 @@ def combine_scaling(gpu_path: str, cpu_path: str) -> dict:
 
 def cnn_inference(ctx, model, size: int = 2048, reps: int = 5) -> dict:
     """Event-timed warm-start network inference on one size x size image.
-    Algorithmic HBM bytes per pixel: each of the 18 convolutions reads its
-    32-channel bf16 input and writes its output (2 x 64 B), and the 8
-    residual convolutions also read the skip tensor (64 B): 2816 B; flops per
-    pixel: 18 x 2 x 9 x 32 x 32."""
+    Algorithmic HBM bytes per pixel: the stem and head convolutions and the
+    8 residual blocks (each one kernel, its inner activation kept on chip)
+    each read their 32-channel bf16 input and write their output (2 x 64 B):
+    10 x 128 = 1280 B (a layer-by-layer pass would move 2816 B: 18 x 128 plus
+    the 8 skip reads); flops per pixel: 18 x 2 x 9 x 32 x 32."""
     import numpy as np
     import torch
     rng = np.random.default_rng(5)
@@ -268,10 +269,11 @@ def cnn_inference(ctx, model, size: int = 2048, reps: int = 5) -> dict:
             ms.append(e0.elapsed_time(e1))
     t = float(np.median(ms)) * 1e-3
     px = size * size
-    nbytes, flops = 2816.0 * px, 18 * 2 * 9 * 32 * 32 * float(px)
+    nbytes, flops = 1280.0 * px, 18 * 2 * 9 * 32 * 32 * float(px)
     return {"image": f"{size}x{size}", "forward_ms": t * 1e3, "bound": "hbm", "achieved": nbytes / t / 1e9,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
-            "bytes_per_forward": nbytes, "tflops": flops / t / 1e12, "bf16_mfma_peak_tflops": 2500.0}
+            "bytes_per_forward": nbytes, "tflops": flops / t / 1e12, "bf16_mfma_peak_tflops": 2500.0,
+            "mfma_frac": flops / t / 1e12 / 2500.0}
 
 
 def cloud_leg(ctx, mpr, prm, steps: int) -> dict:
@@ -338,6 +340,9 @@ def main():
     ap.add_argument("--cpu-p-sweep", default="",
                     help="with --cpu-scaling: also the gap-fraction sweep, as L:p1,p2,... "
                          "(e.g. 2048:0.05,0.2,0.35,0.5,0.65,0.8,0.95)")
+    ap.add_argument("--cnn-only", action="store_true",
+                    help="only the warm-start network's 2048^2 inference timing (one JSON line), e.g. for a "
+                         "kernel trace of the network alone")
     ap.add_argument("--combine", nargs=2, metavar=("GPU_JSONL", "CPU_JSONL"),
                     help="join the GPU scaling study's lines with the oracle's lines of the same (L, p) into "
                          "one JSON document with the oracle's time to fill and the speed-up, and exit")
@@ -375,6 +380,13 @@ def main():
 
     import paper_1811_01604_amd as mpr
     from paper_1811_01604_amd import warmstart
+
+    if args.cnn_only:
+        ctx = mpr.Context(0)
+        params, _ = warmstart.load()
+        print(json.dumps(cnn_inference(ctx, warmstart.WarmStart(ctx, params))), flush=True)
+        ctx.close()
+        return
 
     # CPU-side inputs first, before anything touches the GPU (the evaluation
     # images are made in worker processes)
