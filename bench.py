@@ -350,7 +350,7 @@ def main():
                     help="run one 1 GiB plain copy first (calibrates HBM byte counters)")
     ap.add_argument("--tile", default="auto",
                     help="sweep block shape: auto (tuned), or rows 1/2/4/8, with a 'c' suffix for the compacted "
-                         "shapes 2c/4c/8c, or 16f/24f/32f for the fused tile sweep (for profiling runs that must "
+                         "shapes 2c/4c/8c, or 16f/24f/32f/48f for the fused tile sweep (for profiling runs that must "
                          "see one kernel)")
     ap.add_argument("--fp64", action="store_true",
                     help="run the chains in double precision (the paper's DP variant)")

@@ -2111,12 +2111,13 @@ struct Shape {
     bool compact;
     bool fused;
 };
-constexpr int kNumShapes = 10;
+constexpr int kNumShapes = 11;
 constexpr int kNumPlainShapes = 4;
 constexpr int kNumUnfusedShapes = 7;   // the shapes of double-precision chains
 constexpr Shape kShapes[kNumShapes] = {{1, false, false}, {2, false, false}, {4, false, false}, {8, false, false},
                                        {2, true, false},  {4, true, false},  {8, true, false},
-                                       {16, false, true}, {24, false, true}, {32, false, true}};
+                                       {16, false, true}, {24, false, true}, {32, false, true},
+                                       {48, false, true}};
 constexpr int kDefaultShape = 2;  // plain, 4 half-rows
 
 int tile_code(const Shape &sh)
@@ -2497,6 +2498,10 @@ void launch_tile(hipStream_t st, const ChainSet &cs, int v, int mode, const Swee
             break;
         case 24:
             hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 24>), grid, blk, 0, st, cs.d_desc, cs.d_state,
+                               block_map(cs, v), mode, sc, or_only, flags);
+            break;
+        case 48:
+            hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 48>), grid, blk, 0, st, cs.d_desc, cs.d_state,
                                block_map(cs, v), mode, sc, or_only, flags);
             break;
         default:

@@ -21,7 +21,7 @@ torch = pytest.importorskip("torch")
 import paper_1811_01604_amd as mpr  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-FUSED_TILES = [16 | mpr.TILE_FUSED, 24 | mpr.TILE_FUSED, 32 | mpr.TILE_FUSED]
+FUSED_TILES = [16 | mpr.TILE_FUSED, 24 | mpr.TILE_FUSED, 32 | mpr.TILE_FUSED, 48 | mpr.TILE_FUSED]
 
 
 def say(*a):
@@ -82,7 +82,8 @@ def test_fused_sweep_equals_half_sweeps_on_a_ragged_batch(ctx, T):
     Ts = np.full(len(SHAPES), T)
     ref = run(ctx, imgs, phi, mk, Ts, 4, 5, R=3, K=5, spread=1)
     say(f"  T={T}: relax sweeps {[s[0] for s in ref['stats']]}")
-    for tile, spl in [(FUSED_TILES[0], 5), (FUSED_TILES[1], 1), (FUSED_TILES[2], 64), (FUSED_TILES[2], 3)]:
+    for tile, spl in [(FUSED_TILES[0], 5), (FUSED_TILES[1], 1), (FUSED_TILES[2], 64), (FUSED_TILES[2], 3),
+                      (FUSED_TILES[3], 4)]:
         got = run(ctx, imgs, phi, mk, Ts, tile, spl, R=3, K=5, spread=1)
         for key in ref:
             assert got[key] == ref[key], (tile, spl, key)
