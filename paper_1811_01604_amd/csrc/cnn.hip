@@ -275,22 +275,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
 // A residual block of the inference forward pass in one kernel:
 //   out = h + conv2(t) + b2,  t = bf16(ReLU(conv1(h) + b1))
-// with the inner activation t kept in LDS instead of a round trip through
-// HBM.  A persistent block of 4 waves loops over 14 x 30-pixel output tiles.
-// The (14 + 4) x (30 + 4) input pixels around a tile are staged in LDS like
-// conv3x3_kernel's tile (the same 18 x 34 shape), conv1 computes t on the
-// 16 x 32 pixels around the output tile (each wave 4 rows, the MFMA scheme
-// of conv3x3_kernel), rounds it to bfloat16 as the layer-by-layer path
-// stores it, and writes it to a second staged tile, zero outside the image
-// (conv2's zero padding) and in the tile's last two rows and columns; conv2
-// then computes 16 x 32 outputs of which the first 14 x 30 are the tile's
-// (the rest read the zero border), and its epilogue adds b2 and the skip
-// input from the staged input tile.  Every product and rounding is that of
-// the two conv3x3_kernel launches, so the output is the same bits.  Both
-// layers' packed weights live in LDS (144 KB in all: one block per CU).
-// Tiles are ordered so that each XCD takes a contiguous run of them: tiles
-// in flight on one XCD are neighbours and share their halo pixels in its L2.
-constexpr int RTH = CTH - 2, RTW = CTW - 2;  // output tile of the fused block
+// with the inner activation t kept on chip instead of a round trip through
+// HBM.  Persistent blocks of 4 waves, two per CU (72 KB of LDS and at most
+// 256 registers each, like conv3x3_kernel), loop over 14 x 30-pixel output
+// tiles.  The (14 + 4) x (30 + 4) input pixels around a tile are staged in
+// LDS like conv3x3_kernel's tile (the same 18 x 34 shape) and conv1
+// computes t on the 16 x 32 pixels around the output tile (each wave 4
+// rows, the MFMA scheme of conv3x3_kernel).  Each lane then keeps the skip
+// inputs of its conv2 outputs in registers, and t, rounded to bfloat16 as
+// the layer-by-layer path stores it, overwrites the staged tile (zero
+// outside the image, conv2's zero padding, and in the tile's last two rows
+// and columns).  conv2 computes 16 x 32 outputs of which the first 14 x 30
+// are the tile's (the rest read the zero border); its epilogue adds b2 and
+// the skip input.  Every product and rounding is that of the two
+// conv3x3_kernel launches, so the output is the same bits.  One layer's
+// packed weights are in LDS at a time: the other layer's are loaded into
+// registers while a conv runs and stored after it (an L2 read of 18 KB per
+// conv and tile).  Tiles are ordered so that each XCD takes a contiguous run
+// of them: tiles in flight on one XCD are neighbours and share their halo
+// pixels in its L2.
+constexpr int RTH = CTH - 2, RTW = CTW - 2;             // output tile of the fused block
+constexpr int W_CHUNKS = C_W_ROWS * 4;                  // 16-byte chunks of one layer's packed weights
 
 struct ResArgs {
     const bf16 *in;    // block input h, N x H x W x 32
@@ -310,6 +315,14 @@ __device__ __forceinline__ void res_tile_origin(int tile, int tiles_x, int tiles
     n = rest / tiles_y;
     y0 = ty * RTH;
     x0 = tx * RTW;
+}
+
+// One layer's packed weights into LDS rows of 80 B.
+__device__ __forceinline__ void res_copy_w(const bf16 *__restrict__ w, bf16 *wl)
+{
+    for (int k = (int)threadIdx.x; k < W_CHUNKS; k += 256)
+        *reinterpret_cast<uint4 *>(wl + (k >> 2) * PIXS + (k & 3) * 8) =
+            *reinterpret_cast<const uint4 *>(w + (k >> 2) * CH + (k & 3) * 8);
 }
 
 // conv3x3_kernel's products of one staged tile: wave w's output rows
@@ -343,32 +356,18 @@ __device__ __forceinline__ void res_products(const bf16 *tile, const bf16 *wl, i
         }
 }
 
-__global__ __launch_bounds__(256) void resblock_kernel(ResArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void resblock_kernel(ResArgs a)
 {
-    __shared__ __attribute__((aligned(16))) bf16 itile[C_IN_T * PIXS];  // staged input, 18 x 34 pixels
-    __shared__ __attribute__((aligned(16))) bf16 ttile[C_IN_T * PIXS];  // inner activation, 18 x 34 pixels
-    __shared__ __attribute__((aligned(16))) bf16 wl1[C_W_ROWS * PIXS];  // packed weights, 288 rows each
-    __shared__ __attribute__((aligned(16))) bf16 wl2[C_W_ROWS * PIXS];
-    __shared__ float bl[2 * CH];                                        // b1, b2
+    __shared__ __attribute__((aligned(16))) bf16 tile[C_IN_T * PIXS];  // staged input, then t: 18 x 34 pixels
+    __shared__ __attribute__((aligned(16))) bf16 wl[C_W_ROWS * PIXS];  // one layer's packed weights
+    __shared__ float bl[2 * CH];                                       // b1, b2
     const int tiles_x = (a.W + RTW - 1) / RTW, tiles_y = (a.H + RTH - 1) / RTH;
     const int n_tiles = tiles_x * tiles_y * a.N;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 31, kq = lane >> 5;
-    for (int k = threadIdx.x; k < C_W_ROWS * 4; k += blockDim.x) {
-        *reinterpret_cast<uint4 *>(wl1 + (k >> 2) * PIXS + (k & 3) * 8) =
-            *reinterpret_cast<const uint4 *>(a.w1 + (k >> 2) * CH + (k & 3) * 8);
-        *reinterpret_cast<uint4 *>(wl2 + (k >> 2) * PIXS + (k & 3) * 8) =
-            *reinterpret_cast<const uint4 *>(a.w2 + (k >> 2) * CH + (k & 3) * 8);
-    }
     if (threadIdx.x < CH) {
         bl[threadIdx.x] = a.b1[threadIdx.x];
         bl[CH + threadIdx.x] = a.b2[threadIdx.x];
-    }
-    // the inner tile's border (rows 16, 17 and columns 32, 33) stays zero
-    for (int k = threadIdx.x; k < C_IN_T * 4; k += blockDim.x) {
-        const int pix = k >> 2, r = pix / C_IN_W, c = pix - r * C_IN_W;
-        if (r >= CTH || c >= CTW)
-            *reinterpret_cast<uint4 *>(ttile + pix * PIXS + (k & 3) * 8) = make_uint4(0u, 0u, 0u, 0u);
     }
     // this block's tiles: the blocks of XCD x = blockIdx % 8 (there are
     // ceil((G - x) / 8) of them) take a contiguous run of the tile sequence
@@ -382,26 +381,30 @@ __global__ __launch_bounds__(256) void resblock_kernel(ResArgs a)
     int tile_id = t_lo + ((int)blockIdx.x >> 3);
     uint4 pre[C_PER_THREAD];
     uint32_t pre_valid = 0u;
+    res_copy_w(a.w1, wl);
     if (tile_id < t_hi) {
         int n, y0, x0;
         res_tile_origin(tile_id, tiles_x, tiles_y, n, y0, x0);
         conv_load_tile(a.in, n, a.H, a.W, y0 - 1, x0 - 1, pre, pre_valid);
-        conv_store_tile(itile, pre, pre_valid);
+        conv_store_tile(tile, pre, pre_valid);
     }
     __syncthreads();
     for (; tile_id < t_hi; tile_id += step) {
         int n, y0, x0;
         res_tile_origin(tile_id, tiles_x, tiles_y, n, y0, x0);
-        {
-            const int next = tile_id + step < t_hi ? tile_id + step : tile_id;
-            int n2, y2, x2;
-            res_tile_origin(next, tiles_x, tiles_y, n2, y2, x2);
-            conv_load_tile(a.in, n2, a.H, a.W, y2 - 1, x2 - 1, pre, pre_valid);
-        }
-        __builtin_amdgcn_sched_barrier(0);
         f32x16 acc[4];
         // conv1: t at rows y0 - 1 + 4 wave + o, columns x0 - 1 + m
-        res_products(itile, wl1, wave, m, kq, acc);
+        res_products(tile, wl, wave, m, kq, acc);
+        // the skip inputs of this lane's conv2 outputs (staged pixel
+        // (4 wave + o + 2, m + 2)), read before t overwrites the tile
+        uint2 skip[4][4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                skip[o][j] = *reinterpret_cast<const uint2 *>(
+                    tile + (min(4 * wave + o + 2, CTH + 1) * C_IN_W + m + 2) * PIXS + 8 * j + 4 * kq);
+        __syncthreads();  // every wave is done with the input tile and conv1's weights
         {
             const int gx = x0 - 1 + m;
 #pragma unroll
@@ -417,13 +420,29 @@ __global__ __launch_bounds__(256) void resblock_kernel(ResArgs a)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) tp[r] = (bf16)fmaxf(acc[o][4 * j + r] + bl[c0 + r], 0.0f);
                     }
-                    *reinterpret_cast<uint2 *>(ttile + (tr * C_IN_W + m) * PIXS + c0) = tv;
+                    *reinterpret_cast<uint2 *>(tile + (tr * C_IN_W + m) * PIXS + c0) = tv;
                 }
             }
+            // the tile's last two rows and columns: zero
+            for (int k = threadIdx.x; k < (2 * C_IN_W + 2 * CTH) * 4; k += blockDim.x) {
+                const int q = k >> 2, chunk = k & 3;
+                const int pix = q < 2 * C_IN_W ? (CTH + q / C_IN_W) * C_IN_W + q % C_IN_W
+                                               : ((q - 2 * C_IN_W) >> 1) * C_IN_W + CTW + ((q - 2 * C_IN_W) & 1);
+                *reinterpret_cast<uint4 *>(tile + pix * PIXS + chunk * 8) = make_uint4(0u, 0u, 0u, 0u);
+            }
         }
-        __syncthreads();  // t complete
+        res_copy_w(a.w2, wl);
+        __syncthreads();  // t and conv2's weights are in LDS
         // conv2: outputs at rows y0 + 4 wave + o, columns x0 + m
-        res_products(ttile, wl2, wave, m, kq, acc);
+        res_products(tile, wl, wave, m, kq, acc);
+        __syncthreads();  // every wave is done with t and conv2's weights
+        if (tile_id + step < t_hi) {  // the next tile's pixels (the CU's other block computes meanwhile)
+            int n2, y2, x2;
+            res_tile_origin(tile_id + step, tiles_x, tiles_y, n2, y2, x2);
+            conv_load_tile(a.in, n2, a.H, a.W, y2 - 1, x2 - 1, pre, pre_valid);
+            conv_store_tile(tile, pre, pre_valid);
+            res_copy_w(a.w1, wl);
+        }
         {
             const int gx = x0 + m;
 #pragma unroll
@@ -434,7 +453,7 @@ __global__ __launch_bounds__(256) void resblock_kernel(ResArgs a)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int c0 = 8 * j + 4 * kq;
-                    const uint2 w2 = *reinterpret_cast<const uint2 *>(itile + ((orow + 2) * C_IN_W + m + 2) * PIXS + c0);
+                    const uint2 w2 = skip[o][j];
                     float v[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) v[r] = acc[o][4 * j + r] + bl[CH + c0 + r];
@@ -450,9 +469,7 @@ __global__ __launch_bounds__(256) void resblock_kernel(ResArgs a)
                 }
             }
         }
-        __syncthreads();  // every wave is done with both tiles
-        if (tile_id + step < t_hi) conv_store_tile(itile, pre, pre_valid);
-        __syncthreads();
+        __syncthreads();  // the next tile and conv1's weights are in LDS
     }
 }
 
@@ -722,9 +739,9 @@ void launch_resblock(hipStream_t st, const bf16 *in, const bf16 *w1, const float
     a.N = n;
     a.H = h;
     a.W = w;
-    // persistent: one block per compute unit (144 KB of LDS each)
+    // persistent: two blocks per compute unit (72 KB of LDS each)
     const int64_t tiles = (int64_t)n * ((h + RTH - 1) / RTH) * ((w + RTW - 1) / RTW);
-    hipLaunchKernelGGL(resblock_kernel, dim3((unsigned)std::min<int64_t>(tiles, 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(resblock_kernel, dim3((unsigned)std::min<int64_t>(tiles, 512)), dim3(256), 0, st, a);
 }
 
 void launch_wgrad(hipStream_t st, const bf16 *in, const bf16 *gout, const bf16 *gref, float *partial, float *grads,
