@@ -243,36 +243,37 @@ def combine_scaling(gpu_path: str, cpu_path: str) -> dict:
 
 
 def cnn_inference(ctx, model, size: int = 2048, reps: int = 5) -> dict:
-    """Event-timed warm-start network inference on one size x size image.
-    Algorithmic HBM bytes per pixel: the stem and head convolutions and the
-    8 residual blocks (each one kernel, its inner activation kept on chip)
-    each read their 32-channel bf16 input and write their output (2 x 64 B):
-    10 x 128 = 1280 B (a layer-by-layer pass would move 2816 B: 18 x 128 plus
-    the 8 skip reads); flops per pixel: 18 x 2 x 9 x 32 x 32."""
+    """Event-timed warm-start network inference on one size x size image,
+    from the sample angles to the starting gap angles (one mpr_cnn_infer:
+    the encoding in the stem's staging, the decoding in the head's
+    epilogue).  Algorithmic HBM bytes per pixel: the stem reads the angle and
+    the flag (5 B) and writes its activation (64 B); the 8 residual blocks
+    (each one kernel, its inner activation kept on chip) read their input
+    and write their output (2 x 64 B); the head reads its input and the flag
+    and writes the angle (64 + 1 + 4 B): 1162 B (a layer-by-layer pass with
+    separate encode and decode would move about 3.4 KB); flops per pixel:
+    18 x 2 x 9 x 32 x 32."""
     import numpy as np
     import torch
     rng = np.random.default_rng(5)
     phi = torch.from_numpy(rng.uniform(0, 2 * np.pi, size=(1, size, size)).astype(np.float32)).cuda()
     sm = torch.from_numpy((rng.random((1, size, size)) < 0.5).astype(np.uint8)).cuda()
-    x = torch.empty((1, size, size, 32), dtype=torch.bfloat16, device="cuda")
-    y = torch.empty_like(x)
-    ws = torch.empty(ctx.cnn_workspace_size(1, size, size, False), dtype=torch.uint8, device="cuda")
-    ctx.cnn_encode(phi, sm, x)
+    init = torch.empty_like(phi)
     ms = []
     for i in range(reps + 1):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        ctx.cnn_forward(model.p, model.packed, x, ws, y, training=False)
+        model(phi, sm, init)
         e1.record()
         torch.cuda.synchronize()
         if i:
             ms.append(e0.elapsed_time(e1))
     t = float(np.median(ms)) * 1e-3
     px = size * size
-    nbytes, flops = 1280.0 * px, 18 * 2 * 9 * 32 * 32 * float(px)
-    return {"image": f"{size}x{size}", "forward_ms": t * 1e3, "bound": "hbm", "achieved": nbytes / t / 1e9,
+    nbytes, flops = 1162.0 * px, 18 * 2 * 9 * 32 * 32 * float(px)
+    return {"image": f"{size}x{size}", "inference_ms": t * 1e3, "bound": "hbm", "achieved": nbytes / t / 1e9,
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
-            "bytes_per_forward": nbytes, "tflops": flops / t / 1e12, "bf16_mfma_peak_tflops": 2500.0,
+            "bytes_per_inference": nbytes, "tflops": flops / t / 1e12, "bf16_mfma_peak_tflops": 2500.0,
             "mfma_frac": flops / t / 1e12 / 2500.0}
 
 
@@ -504,7 +505,7 @@ def main():
         params, info = warmstart.load()
         model = warmstart.WarmStart(ctx, params)
         cnn = cnn_inference(ctx, model)
-        log(f"  network inference 2048^2: {cnn['forward_ms']:.2f} ms, {cnn['achieved']:.0f} GB/s, "
+        log(f"  network inference 2048^2: {cnn['inference_ms']:.2f} ms, {cnn['achieved']:.0f} GB/s, "
             f"{cnn['tflops']:.0f} TFLOP/s")
         layouts = ((1, 100), (4, 25), (100, 1))
         ws_summary = warmstart.evaluate(ctx, model, warm_fields, layouts=layouts)

@@ -125,8 +125,12 @@ typedef struct {
                                 start from the same angles, and the realizations average out
                                 that start only over enough equilibrium sweeps (with K = 1 the
                                 state right after the stopping rule fires stays correlated with
-                                it).  0 turns the check off (parity tests that start the
-                                oracle and the library from the same angles). */
+                                it).  Default 100: on 2048^2 fields with 50% cloud gaps, 32
+                                images, the warm start's MAE over the plain start's is
+                                1.012 (95% interval up to 1.023) with K = 25 and 1.0045 (up
+                                to 1.013) with K = 50, within 1.006 with K = 100.  0 turns
+                                the check off (parity tests that start the oracle and the
+                                library from the same angles). */
     int32_t sweep_limit;     /* > 0: mpr_simulate runs at most this many sweeps in this call
                                 and returns MPR_INCOMPLETE if a chain is still running; the
                                 workspace then holds the whole state of the run (a checkpoint:
@@ -359,6 +363,14 @@ int32_t mpr_cnn_opt_step(mpr_ctx *ctx, float *params, const float *grads, float 
  * 2 pi (the gap entries of phi_init for mpr_simulate; 0 at samples). */
 int32_t mpr_cnn_decode(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const void *y,
                        const uint8_t *sampled, float *phi_init, void *stream);
+/* The warm start in one call: mpr_cnn_encode, mpr_cnn_forward (inference)
+ * and mpr_cnn_decode with the same results bit for bit, the encoding done
+ * while the stem stages its input and the decoding in the head's epilogue
+ * (no x or y tensor).  phi, sampled, phi_init: n x h x w (dev); workspace:
+ * mpr_cnn_workspace_size(n, h, w, 0) bytes (dev). */
+int32_t mpr_cnn_infer(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *params,
+                      const void *packed, const float *phi, const uint8_t *sampled, void *ws,
+                      int64_t ws_bytes, float *phi_init, void *stream);
 /* Diagnostics: one conv layer (wpack in the forward or dgrad layout of
  * mpr_cnn_pack; bias, add, ref nullable: out = ReLU?(conv + bias + add),
  * zeroed where ref <= 0), and one layer's weight and bias gradients

@@ -27,7 +27,7 @@ EXPORTS = [
     "mpr_quantiles", "mpr_select_q", "mpr_select_q_workspace_size",
     "mpr_profile_enable", "mpr_profile_read",
     "mpr_cnn_param_count", "mpr_cnn_packed_bytes", "mpr_cnn_workspace_size", "mpr_cnn_pack", "mpr_cnn_encode",
-    "mpr_cnn_forward", "mpr_cnn_loss", "mpr_cnn_backward", "mpr_cnn_opt_step", "mpr_cnn_decode",
+    "mpr_cnn_forward", "mpr_cnn_infer", "mpr_cnn_loss", "mpr_cnn_backward", "mpr_cnn_opt_step", "mpr_cnn_decode",
     "mpr_cnn_diag_conv", "mpr_cnn_diag_wgrad",
     "mpr_diag_philox", "mpr_diag_half_sweep", "mpr_diag_half_sweep_fp64", "mpr_diag_copy", "mpr_diag_energy", "mpr_diag_sg_slope",
 ]
@@ -132,6 +132,7 @@ def _declare(L):
         "mpr_cnn_pack": (i32, [P, P, P, P]),
         "mpr_cnn_encode": (i32, [P, i32, i32, i32, P, P, P, P]),
         "mpr_cnn_forward": (i32, [P, i32, i32, i32, P, P, P, P, i64, i32, P, P]),
+        "mpr_cnn_infer": (i32, [P, i32, i32, i32, P, P, P, P, P, i64, P, P]),
         "mpr_cnn_loss": (i32, [P, i32, i32, i32, P, P, P, i64, P, P, i64, P, P]),
         "mpr_cnn_backward": (i32, [P, i32, i32, i32, P, P, P, P, P, i64, P, P]),
         "mpr_cnn_opt_step": (i32, [P, P, P, P, P, i64, d, d, d, d, P]),
@@ -399,6 +400,18 @@ class Context:
                                              self._t(x, "x", torch.bfloat16, 32 * px), self._t(ws, "ws"),
                                              ws.numel() * ws.element_size(), 1 if training else 0,
                                              self._t(y, "y", torch.bfloat16, 32 * px), _stream(stream)))
+
+    def cnn_infer(self, params, packed, phi, sampled, ws, phi_init, stream=None):
+        """encode + forward (inference) + decode in one call, phi_init out."""
+        import torch
+        n, h, w = phi.shape
+        px, pc, pb = self._cnn_sizes(n, h, w)
+        self._check(self.lib.mpr_cnn_infer(self._h, n, h, w, self._t(params, "params", torch.float32, pc),
+                                           self._t(packed, "packed", nbytes=pb),
+                                           self._t(phi, "phi", torch.float32, px),
+                                           self._t(sampled, "sampled", torch.uint8, px), self._t(ws, "ws"),
+                                           ws.numel() * ws.element_size(),
+                                           self._t(phi_init, "phi_init", torch.float32, px), _stream(stream)))
 
     def cnn_loss(self, y, target, sampled, n_gaps, dy, ws, stream=None) -> float:
         import torch

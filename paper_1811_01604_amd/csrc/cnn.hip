@@ -52,6 +52,12 @@ struct ConvArgs {
     bf16 *out;
     int N, H, W;
     int relu;
+    // the network's own input and output (SIDE bits 2 and 3): encoded from
+    // the sample angles while staging, decoded into starting gap angles in
+    // the epilogue
+    const float *phi;
+    const uint8_t *sampled;
+    float *phi_out;
 };
 
 // Stages the (TH+2) x (TW+2) input pixels around an output tile into LDS,
@@ -136,9 +142,57 @@ __device__ __forceinline__ void conv_store_tile(bf16 *tile, const uint4 (&r)[C_P
     }
 }
 
+// The stem's staging with the network input computed on the way (SIDE bit
+// 2): chunk 0 of a sampled pixel inside the image is (cos q phi, sin q phi,
+// 1) in bfloat16 with q = 1/2 (encode_kernel's values), every other chunk
+// zero.  The loads keep the raw angle and flag; the encoding is done when
+// the chunk is stored, after the products that the loads overlap.
+__device__ __forceinline__ void enc_load_tile(const float *__restrict__ phi, const uint8_t *__restrict__ sampled,
+                                              int n, int H, int W, int y0, int x0, uint4 (&r)[C_PER_THREAD],
+                                              uint32_t &valid)
+{
+    valid = 0u;
+#pragma unroll
+    for (int j = 0; j < C_PER_THREAD; ++j) {
+        const int k = min((int)threadIdx.x + 256 * j, C_CHUNKS - 1);
+        const int chunk = k & 3, pix = k >> 2;
+        const int rr = pix / C_IN_W, cc = pix - rr * C_IN_W;
+        const int gy = y0 - 1 + rr, gx = x0 - 1 + cc;
+        const bool ok = chunk == 0 && gy >= 0 && gy < H && gx >= 0 && gx < W;
+        valid |= ok ? (1u << j) : 0u;
+        const int gyc = min(max(gy, 0), H - 1), gxc = min(max(gx, 0), W - 1);
+        const int64_t p = ((int64_t)n * H + gyc) * W + gxc;
+        r[j] = make_uint4(__float_as_uint(phi[p]), (uint32_t)sampled[p], 0u, 0u);
+    }
+}
+
+__device__ __forceinline__ void enc_store_tile(bf16 *tile, const uint4 (&r)[C_PER_THREAD], uint32_t valid)
+{
+#pragma unroll
+    for (int j = 0; j < C_PER_THREAD; ++j) {
+        const int k = (int)threadIdx.x + 256 * j;
+        if (k >= C_CHUNKS) continue;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (((valid >> j) & 1u) && r[j].y) {
+            const float th = 0.5f * fabsf(__uint_as_float(r[j].x));
+            bf16 e[8];
+            e[0] = (bf16)cosf(th);
+            e[1] = (bf16)sinf(th);
+            e[2] = (bf16)1.0f;
+#pragma unroll
+            for (int i = 3; i < 8; ++i) e[i] = (bf16)0.0f;
+            v = *reinterpret_cast<const uint4 *>(e);
+        }
+        *reinterpret_cast<uint4 *>(tile + (k >> 2) * PIXS + (k & 3) * 8) = v;
+    }
+}
+
 // SIDE: bit 0 = the layer adds a residual input, bit 1 = its output is
 // zeroed where a ReLU reference is <= 0 (the residual, else the reference,
-// is loaded ahead; with both, the reference is read in the epilogue)
+// is loaded ahead; with both, the reference is read in the epilogue), bit 2
+// = the network's stem (input encoded while staging), bit 3 = its head
+// (output channels 0 and 1 decoded into starting gap angles, decode_kernel's
+// arithmetic, instead of stored)
 template <int SIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void conv3x3_kernel(ConvArgs a)
 {
@@ -159,8 +213,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if (tile_id < n_tiles) {
         int n, y0, x0;
         conv_tile_origin(tile_id, tiles_x, tiles_y, n, y0, x0);
-        conv_load_tile(a.in, n, a.H, a.W, y0, x0, pre, pre_valid);
-        conv_store_tile(tile, pre, pre_valid);
+        if (SIDE & 4) {
+            enc_load_tile(a.phi, a.sampled, n, a.H, a.W, y0, x0, pre, pre_valid);
+            enc_store_tile(tile, pre, pre_valid);
+        } else {
+            conv_load_tile(a.in, n, a.H, a.W, y0, x0, pre, pre_valid);
+            conv_store_tile(tile, pre, pre_valid);
+        }
     }
     __syncthreads();
     // Per tile: side loads, next tile's loads, products from LDS; barrier;
@@ -196,7 +255,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             const int next = tile_id + (int)gridDim.x < n_tiles ? tile_id + (int)gridDim.x : tile_id;
             int n2, y2, x2;
             conv_tile_origin(next, tiles_x, tiles_y, n2, y2, x2);
-            conv_load_tile(a.in, n2, a.H, a.W, y2, x2, pre, pre_valid);
+            if (SIDE & 4) enc_load_tile(a.phi, a.sampled, n2, a.H, a.W, y2, x2, pre, pre_valid);
+            else conv_load_tile(a.in, n2, a.H, a.W, y2, x2, pre, pre_valid);
         }
         // keep the loads above ahead of the products (the scheduler would
         // otherwise sink them to their use and expose their latency)
@@ -229,7 +289,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 }
             }
         __syncthreads();  // every wave is done reading this tile from LDS
-        if (tile_id + (int)gridDim.x < n_tiles) conv_store_tile(tile, pre, pre_valid);
+        if (tile_id + (int)gridDim.x < n_tiles) {
+            if (SIDE & 4) enc_store_tile(tile, pre, pre_valid);
+            else conv_store_tile(tile, pre, pre_valid);
+        }
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             const int gy = y0 + 4 * wave + o;
@@ -261,6 +324,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
                         if (!(rv[r] > 0.0f)) v[r] = 0.0f;
+                }
+                if (SIDE & 8) {
+                    // channels 0 and 1 (lanes of kq = 0, run j = 0): the
+                    // starting angle atan2(max(s, 0), c) / q below 2 pi, 0 at
+                    // sampled pixels, from the bfloat16-rounded outputs
+                    if (j == 0 && kq == 0) {
+                        const float c = (float)(bf16)v[0], s = (float)(bf16)v[1];
+                        const float th = atan2f(fmaxf(s, 0.0f) + 0.0f, c);
+                        a.phi_out[pix] = a.sampled[pix] ? 0.0f : fminf(th / 0.5f, 6.28318501f);
+                    }
+                    continue;
                 }
                 uint2 ov;
                 bf16 *op = reinterpret_cast<bf16 *>(&ov);
@@ -726,6 +800,31 @@ void launch_conv(hipStream_t st, const bf16 *in, const bf16 *wpack, const float 
     }
 }
 
+// The network's stem with its input encoded from the sample angles while
+// staging (SIDE 4), or its head with the output decoded into starting gap
+// angles (SIDE 8).
+void launch_conv_io(hipStream_t st, bool stem, const bf16 *in, const bf16 *wpack, const float *bias, bf16 *out,
+                    const float *phi, const uint8_t *sampled, float *phi_out, int n, int h, int w)
+{
+    ConvArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.in = in;
+    a.w = wpack;
+    a.bias = bias;
+    a.out = out;
+    a.N = n;
+    a.H = h;
+    a.W = w;
+    a.relu = stem ? 1 : 0;
+    a.phi = phi;
+    a.sampled = sampled;
+    a.phi_out = phi_out;
+    const int64_t tiles = (int64_t)n * ((h + CTH - 1) / CTH) * ((w + CTW - 1) / CTW);
+    const dim3 grid((unsigned)std::min<int64_t>(tiles, 512));
+    if (stem) hipLaunchKernelGGL(conv3x3_kernel<4>, grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(conv3x3_kernel<8>, grid, dim3(256), 0, st, a);
+}
+
 void launch_resblock(hipStream_t st, const bf16 *in, const bf16 *w1, const float *b1, const bf16 *w2,
                      const float *b2, bf16 *out, int n, int h, int w)
 {
@@ -874,6 +973,34 @@ int32_t mpr_cnn_forward(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const flo
     }
     launch_conv(st, A.h[NBLK], fwd_pack(packed, NLAYER - 1), bias_of(params, NLAYER - 1), nullptr, nullptr, 0,
                 (bf16 *)y, n, h, w);
+    CHIP(ctx, hipGetLastError());
+    CHIP(ctx, hipStreamSynchronize(st));
+    return MPR_OK;
+}
+
+int32_t mpr_cnn_infer(mpr_ctx *ctx, int32_t n, int32_t h, int32_t w, const float *params, const void *packed,
+                      const float *phi, const uint8_t *sampled, void *ws, int64_t ws_bytes, float *phi_init,
+                      void *stream)
+{
+    if (!ctx) return MPR_ERR_ARG;
+    if (!shape_ok(n, h, w) || !params || !packed || !phi || !sampled || !ws || !phi_init)
+        return cfail(ctx, MPR_ERR_ARG, "cnn_infer: invalid argument");
+    if (int rc = mpr_check_device(ctx, "cnn_infer",
+                                  {{"params", params}, {"packed", packed}, {"phi", phi}, {"sampled", sampled},
+                                   {"workspace", ws}, {"phi_init", phi_init}}))
+        return rc;
+    if (ws_bytes < mpr_cnn_workspace_size(n, h, w, 0))
+        return cfail(ctx, MPR_ERR_WORKSPACE, "cnn_infer: workspace too small");
+    Acts A;
+    if (!carve_acts(ws, ws_bytes, n, h, w, false, A)) return cfail(ctx, MPR_ERR_WORKSPACE, "workspace");
+    hipStream_t st = (hipStream_t)stream;
+    launch_conv_io(st, true, nullptr, fwd_pack(packed, 0), bias_of(params, 0), A.h[0], phi, sampled, nullptr, n, h,
+                   w);
+    for (int b = 0; b < NBLK; ++b)
+        launch_resblock(st, A.h[b], fwd_pack(packed, 1 + 2 * b), bias_of(params, 1 + 2 * b),
+                        fwd_pack(packed, 2 + 2 * b), bias_of(params, 2 + 2 * b), A.h[b + 1], n, h, w);
+    launch_conv_io(st, false, A.h[NBLK], fwd_pack(packed, NLAYER - 1), bias_of(params, NLAYER - 1), nullptr,
+                   nullptr, sampled, phi_init, n, h, w);
     CHIP(ctx, hipGetLastError());
     CHIP(ctx, hipStreamSynchronize(st));
     return MPR_OK;

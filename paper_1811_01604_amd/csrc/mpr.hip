@@ -53,7 +53,7 @@ constexpr int64_t kSlopeOffset = 4096;   // diag slope input / output
 constexpr int64_t kVarOffset = 65536;    // per-call partials
 constexpr int kCompactSites = 4 * kBlock;  // sites per block of the compacted sweep shapes
 constexpr int kRecordSegs = 32;            // blocks per chain of record_states_kernel
-constexpr int kWarmMinStates = 25;         // default of mpr_params.warm_min_states
+constexpr int kWarmMinStates = 100;        // default of mpr_params.warm_min_states
 
 // Workspace of mpr_simulate_noalloc, for callers that cannot allocate: one
 // copy per device, held by the library's code object until the process
@@ -827,7 +827,8 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
 // reading h and writing h2 keeps every tile's halo at the state before the
 // sweep while other tiles store theirs.  control_kernel then swaps h and h2
 // of every chain swept (one thread per chain: no block of the sweep waits
-// for the others) before it runs the per-sweep control.
+// for the others) before it runs the per-sweep control; a launch of at most
+// a few thousand blocks does both in its last block instead.
 //
 // Within a colour the gap sites are listed in LDS first (wave ballots; each
 // wave lists the candidates it read, interleaved with the other waves at 64
@@ -841,6 +842,12 @@ __global__ __launch_bounds__(kBlock) void redo_fp64_kernel(const ChainDesc *__re
 constexpr int kTileH = 64;                // half-columns per tile and colour
 constexpr int kTileLS = kTileH + 8;       // LDS row: half-columns hx0 - 4 .. hx0 + kTileH + 3
 constexpr int kTileNW = kBlock / 64;      // waves per block
+// Fused sweeps of at most this many blocks run the control themselves: each
+// block then ends with a device-scope fence (a write-back of its XCD's L2)
+// and a ticket; measured, that saves the control kernel's node in a 1024^2
+// one-chain sweep (344 blocks: 38 -> 34 us per sweep) but costs ~37 us per
+// sweep at 2752 blocks (4096^2, one chain).
+constexpr int64_t kTileCtlMaxBlocks = 512;
 
 // The double-precision decision of one tile site (colour c, local row r,
 // half-column j) from its LDS inputs: the steps of redo_fp64_kernel.  Kept
@@ -1105,11 +1112,16 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
     }
 }
 
+// With `ctl.on` (launches of a few thousand blocks, where one ticket counter
+// costs little) the last block to finish also exchanges h and h2 of the
+// swept chains and runs the per-sweep control, which saves the control
+// kernel's launch in each sweep of a small fill; it finds out that it is last
+// from the ticket counter, which it resets.
 template <bool DIAG, int TH>
-__global__ __launch_bounds__(kBlock) void sweep_tile_kernel(const ChainDesc *__restrict__ descs,
+__global__ __launch_bounds__(kBlock) void sweep_tile_kernel(ChainDesc *__restrict__ descs,
                                                             ChainState *__restrict__ states, BlockMap bm,
                                                             int mode, SweepConsts sc, int or_only,
-                                                            uint8_t *__restrict__ flags)
+                                                            uint8_t *__restrict__ flags, FusedControl ctl)
 {
     __shared__ TileShared<TH> L;
     const int tid = (int)threadIdx.x;
@@ -1164,6 +1176,31 @@ __global__ __launch_bounds__(kBlock) void sweep_tile_kernel(const ChainDesc *__r
             }
         }
     }
+    if (!ctl.on) return;
+    __shared__ int last;
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        last = atomicAdd(ctl.ticket, 1u) == gridDim.x - 1u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // the other blocks' sums and stores are visible
+    for (int k = tid; k < bm.n; k += kBlock) {
+        const int c = bm.id[k];
+        if (states[c].phase == PH_DONE) continue;
+        ChainDesc &dd = descs[c];
+        float *t0 = dd.h[0], *t1 = dd.h[1];
+        dd.h[0] = dd.h2[0];
+        dd.h[1] = dd.h2[1];
+        dd.h2[0] = t0;
+        dd.h2[1] = t1;
+        states[c].swapped ^= 1;
+    }
+    __syncthreads();
+    for (int c = tid; c < ctl.n_all; c += kBlock)
+        control_chain(descs, states, c, ctl.cp, ctl.done_count, ctl.work);
+    if (tid == 0) *ctl.ticket = 0u;
 }
 
 // The double-precision sweep: the layout of half_sweep_body (a thread per
@@ -2488,25 +2525,28 @@ void launch_half(hipStream_t st, const ChainSet &cs, int v, bool table, int colo
 // of it in place (mode 1, 2: diagnostics).
 template <bool DIAG>
 void launch_tile(hipStream_t st, const ChainSet &cs, int v, int mode, const SweepConsts &sc, int or_only,
-                 uint8_t *flags)
+                 uint8_t *flags, const FusedControl *ctl = nullptr)
 {
+    FusedControl fc;
+    if (ctl) fc = *ctl;
+    else std::memset(&fc, 0, sizeof fc);
     const dim3 grid((unsigned)cs.total_blocks[v]), blk(kBlock);
     switch (kShapes[v].rows) {
         case 16:
             hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 16>), grid, blk, 0, st, cs.d_desc, cs.d_state,
-                               block_map(cs, v), mode, sc, or_only, flags);
+                               block_map(cs, v), mode, sc, or_only, flags, fc);
             break;
         case 24:
             hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 24>), grid, blk, 0, st, cs.d_desc, cs.d_state,
-                               block_map(cs, v), mode, sc, or_only, flags);
+                               block_map(cs, v), mode, sc, or_only, flags, fc);
             break;
         case 48:
             hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 48>), grid, blk, 0, st, cs.d_desc, cs.d_state,
-                               block_map(cs, v), mode, sc, or_only, flags);
+                               block_map(cs, v), mode, sc, or_only, flags, fc);
             break;
         default:
             hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 32>), grid, blk, 0, st, cs.d_desc, cs.d_state,
-                               block_map(cs, v), mode, sc, or_only, flags);
+                               block_map(cs, v), mode, sc, or_only, flags, fc);
             break;
     }
 }
@@ -2584,12 +2624,16 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     };
     // A sweep: the fused tile sweep, then control_kernel with the swap of
     // h and h2 (and the control, unless the states are recorded in between);
-    // or two half-sweeps, the colour-1 redo kernel running the control
-    // unless the states are recorded (or the chains are double precision).
+    // a fused sweep of at most kTileCtlMaxBlocks blocks does the swap and the
+    // control in its last block instead (unless states are recorded); or two
+    // half-sweeps, the colour-1 redo kernel running the control unless the
+    // states are recorded (or the chains are double precision).
     auto sweeps = [&](int v, int count) {
         for (int i = 0; i < count; ++i) {
             const bool fused = kShapes[v].fused;
-            if (fused) {
+            if (fused && fuse && cs.total_blocks[v] <= kTileCtlMaxBlocks) {
+                launch_tile<false>(st, cs, v, 0, sc, 0, nullptr, &fc);  // swap and control in its last block
+            } else if (fused) {
                 launch_tile<false>(st, cs, v, 0, sc, 0, nullptr);
                 control(1, cs.states_out ? 0 : 1);
             } else {

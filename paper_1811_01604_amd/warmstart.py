@@ -220,17 +220,14 @@ class WarmStart:
         self._ws = None
 
     def __call__(self, phi, sampled, phi_init):
-        """phi, sampled, phi_init: device tensors of shape (n, h, w)."""
+        """phi, sampled, phi_init: device tensors of shape (n, h, w); one
+        library call (encode, inference and decode fused)."""
         import torch
         n, h, w = phi.shape
         need = self.ctx.cnn_workspace_size(n, h, w, False)
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
-        x = torch.empty((n, h, w, 32), dtype=torch.bfloat16, device="cuda")
-        y = torch.empty_like(x)
-        self.ctx.cnn_encode(phi, sampled, x)
-        self.ctx.cnn_forward(self.p, self.packed, x, self._ws, y, training=False)
-        self.ctx.cnn_decode(y, sampled, phi_init)
+        self.ctx.cnn_infer(self.p, self.packed, phi, sampled, self._ws, phi_init)
 
 
 def _eval_field(args):
@@ -288,7 +285,7 @@ def evaluate(ctx, model, fields, layouts=((1, 100),), min_states=None):
         g = m == 0
         T = None
         for R, K in layouts:
-            prm = mpr.default_params(R=R, K=K, seed=4242)
+            prm = mpr.default_params(R=R, K=K, seed=4242, warm_min_states=min_states)
             ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
             if T is None:
                 _, T, _ = ctx.estimate_temperature(imgs, phi, md, prm, ws)
@@ -353,7 +350,28 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--evaluate", default="",
+                    help="instead of training: compare the committed network's warm start with the plain start "
+                         "in these layouts RxK (e.g. 1x100,2x50,4x25) on --eval-seeds images of --eval-size^2 "
+                         "per mask kind, with the library's warm-start check set to --min-states; one JSON line")
+    ap.add_argument("--eval-size", type=int, default=2048)
+    ap.add_argument("--eval-seeds", type=int, default=32)
+    ap.add_argument("--min-states", type=int, default=-1, help="-1: the library default")
     args = ap.parse_args()
+    if args.evaluate:
+        layouts = tuple(tuple(int(v) for v in t.split("x")) for t in args.evaluate.split(","))
+        fields = make_eval_fields(size=args.eval_size, seeds=args.eval_seeds, workers=min(args.workers, 8))
+        if ROOT not in sys.path:
+            sys.path.insert(0, ROOT)
+        import paper_1811_01604_amd as mpr
+        ctx = mpr.Context(0)
+        params, info = load()
+        res = evaluate(ctx, WarmStart(ctx, params), fields, layouts=layouts,
+                       min_states=None if args.min_states < 0 else args.min_states)
+        print(json.dumps({"layouts": res, "size": args.eval_size, "seeds": args.eval_seeds,
+                          "min_states": args.min_states}), flush=True)
+        ctx.close()
+        return
     t0 = time.perf_counter()
     log(f"generating {args.samples} fields of {args.size}^2 on {args.workers} workers")
     z, mask = make_fields(args.samples, args.size, args.seed, args.workers)

@@ -212,6 +212,32 @@ def test_fused_residual_blocks_equal_the_layer_by_layer_forward(ctx, shape):
     say(f"  {shape}: bit-equal; against the oracle max rel err {err:.2e}, cosine {c:.6f}")
 
 
+@pytest.mark.parametrize("shape", [(1, 8, 32), (2, 37, 61), (1, 100, 130)])
+def test_fused_inference_equals_encode_forward_decode(ctx, shape):
+    """mpr_cnn_infer (the encoding done while the stem stages its input, the
+    decoding in the head's epilogue) gives the starting angles of
+    mpr_cnn_encode, mpr_cnn_forward and mpr_cnn_decode bit for bit."""
+    n, h, w = shape
+    params = layer_params(11 + w, scale=0.15)
+    p, packed = packs(ctx, params)
+    rng = np.random.default_rng(h)
+    phi = torch.from_numpy(rng.uniform(0, 2 * np.pi, size=shape).astype(np.float32)).cuda()
+    sd = torch.from_numpy((rng.random(shape) < 0.4).astype(np.uint8)).cuda()
+    ws = torch.empty(ctx.cnn_workspace_size(n, h, w, False), dtype=torch.uint8, device="cuda")
+    x = torch.empty((n, h, w, 32), dtype=torch.bfloat16, device="cuda")
+    y = torch.empty_like(x)
+    a = torch.full_like(phi, -1.0)
+    b = torch.full_like(phi, -2.0)
+    ctx.cnn_encode(phi, sd, x)
+    ctx.cnn_forward(p, packed, x, ws, y, training=False)
+    ctx.cnn_decode(y, sd, a)
+    ctx.cnn_infer(p, packed, phi, sd, ws, b)
+    torch.cuda.synchronize()
+    av, bv = a.cpu().numpy(), b.cpu().numpy()
+    assert np.array_equal(av.view(np.uint32), bv.view(np.uint32)), int((av != bv).sum())
+    assert np.all(bv[sd.cpu().numpy() == 1] == 0)
+
+
 def test_decode_matches_oracle(ctx):
     rng = np.random.default_rng(4)
     n, h, w = 1, 9, 40

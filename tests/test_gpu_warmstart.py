@@ -38,7 +38,7 @@ def test_warm_start_gain():
 
 def test_warm_start_with_one_state_per_chain_is_refused():
     """(R, K) = (100, 1): mpr_simulate returns MPR_ERR_ARG for phi_init, as
-    for any K below warm_min_states (25); with the check off it runs."""
+    for any K below warm_min_states (100); with the check off it runs."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     z, m = warmstart._eval_field(("random", 64, 0))
@@ -49,13 +49,13 @@ def test_warm_start_with_one_state_per_chain_is_refused():
         phi = torch.empty_like(zd)
         ctx.map_to_angles(imgs, zd, md, phi)
         init = torch.full_like(phi, 1.0)
-        for R, K in ((100, 1), (4, 24)):
+        for R, K in ((100, 1), (4, 25), (2, 50), (1, 99)):
             prm = mpr.default_params(R=R, K=K)
             ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
             with pytest.raises(mpr.MprError) as e:
                 ctx.simulate(imgs, phi, md, np.array([0.05]), prm, ws, torch.empty_like(phi), phi_init=init)
             assert e.value.code == mpr.MPR_ERR_ARG and "warm_min_states" in str(e.value)
-        prm = mpr.default_params(R=4, K=25)
+        prm = mpr.default_params(R=1, K=100)
         ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
         ctx.simulate(imgs, phi, md, np.array([0.05]), prm, ws, torch.empty_like(phi), phi_init=init)
         prm = mpr.default_params(R=100, K=1, warm_min_states=0)
