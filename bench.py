@@ -351,8 +351,8 @@ def main():
                     help="run one 1 GiB plain copy first (calibrates HBM byte counters)")
     ap.add_argument("--tile", default="auto",
                     help="sweep block shape: auto (tuned), or rows 1/2/4/8, with a 'c' suffix for the compacted "
-                         "shapes 2c/4c/8c, or 16f/24f/32f/48f for the fused tile sweep (for profiling runs that must "
-                         "see one kernel)")
+                         "shapes 2c/4c/8c, or 8f/12f/16f/24f/32f/48f for the fused tile sweep, or 8p/12p/16p/24p/32p "
+                         "for fused sweeps many per cooperative launch (for profiling runs that must see one kernel)")
     ap.add_argument("--fp64", action="store_true",
                     help="run the chains in double precision (the paper's DP variant)")
     ap.add_argument("--warm-seeds", type=int, default=32,
@@ -409,8 +409,9 @@ def main():
     zh = torch.zeros_like(z)
     tile = 0
     if args.tile != "auto":
-        tile = int(args.tile.rstrip("cf")) | (mpr.TILE_COMPACT if args.tile.endswith("c") else 0) | \
-            (mpr.TILE_FUSED if args.tile.endswith("f") else 0)
+        tile = int(args.tile.rstrip("cfp")) | (mpr.TILE_COMPACT if args.tile.endswith("c") else 0) | \
+            (mpr.TILE_FUSED if args.tile.endswith("f") else 0) | \
+            (mpr.TILE_FUSED | mpr.TILE_PERSIST if args.tile.endswith("p") else 0)
     prm = mpr.default_params(R=args.chains, K=args.K, fixed_relax=args.fixed_sweeps, tile_rows=tile,
                              fp64=1 if args.fp64 else 0)
     ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
@@ -486,10 +487,13 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(args.workload, prm.R,
                                         ("fp64-" if args.fp64 else "") + str(prof["last_tile"])),
-            "kernel": ("sweep_tile_kernel" if prof["last_tile"] & mpr.TILE_FUSED else
+            "kernel": ("sweep_tile_persist_kernel" if prof["last_tile"] & mpr.TILE_PERSIST else
+                       "sweep_tile_kernel" if prof["last_tile"] & mpr.TILE_FUSED else
                        "half_sweep_" + ("fp64_" if args.fp64 else "") +
                        ("compact_kernel" if prof["last_tile"] & mpr.TILE_COMPACT else "kernel")),
-            "launch": ("one fused sweep (both colours) of every running chain" if prof["last_tile"] & mpr.TILE_FUSED
+            "launch": ("one fused sweep (both colours) of every running chain, many per cooperative launch"
+                       if prof["last_tile"] & mpr.TILE_PERSIST else
+                       "one fused sweep (both colours) of every running chain" if prof["last_tile"] & mpr.TILE_FUSED
                        else "one half-sweep (one colour) of every running chain"),
             "tile_rows": prof["last_tile"] & 0xFF,
             "launch_ms": launch_ms, "useful_bytes_per_launch": bytes_per_launch,

@@ -54,10 +54,15 @@ enum {
 
 /* Flags of mpr_params.tile_rows (and the tile argument of
  * mpr_diag_half_sweep): the compacted sweep shape, and the fused tile sweep
- * (a whole sweep per launch on tiles of 16, 24, 32 or 48 rows x 128 columns
+ * (a whole sweep per launch on tiles of 8, 12, 16, 24, 32 or 48 rows x 128 columns
  * staged in LDS with a two-site halo; single precision only). */
 #define MPR_TILE_COMPACT 0x100
 #define MPR_TILE_FUSED 0x200
+/* With MPR_TILE_FUSED (8, 12, 16, 24 or 32 rows): the fused sweeps of a chain
+ * set whose tiles the GPU holds at once run many per cooperative launch, with
+ * a grid barrier between sweeps (small fills; a set too large for that, or a
+ * call that records states, runs the same rows one launch per sweep). */
+#define MPR_TILE_PERSIST 0x400
 
 typedef struct mpr_ctx mpr_ctx;
 
@@ -98,7 +103,7 @@ typedef struct {
     int32_t tile_rows;    /* sweep block shape: 1, 2, 4 or 8 half-rows x (256 / rows)
                              site pairs, or 2, 4 or 8 half-rows | MPR_TILE_COMPACT for
                              (1024 / rows) sites with the gap sites compacted onto
-                             lanes, or 16, 24, 32 or 48 rows | MPR_TILE_FUSED for the fused
+                             lanes, or 8, 12, 16, 24, 32 or 48 rows | MPR_TILE_FUSED for the fused
                              tile sweep (single precision; a double-precision run
                              takes the default shape instead); 0 = autotune
                              (results do not depend on it) */

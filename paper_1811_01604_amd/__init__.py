@@ -104,7 +104,8 @@ def load(path: str = LIB_PATH):
 
 
 TILE_COMPACT = 0x100  # Params.tile_rows flag: the compacted sweep shape
-TILE_FUSED = 0x200  # Params.tile_rows flag: the fused tile sweep (rows 16, 24 or 32)
+TILE_FUSED = 0x200  # Params.tile_rows flag: the fused tile sweep (rows 8, 12, 16, 24, 32 or 48)
+TILE_PERSIST = 0x400  # with TILE_FUSED (rows 8 to 32): many fused sweeps per cooperative launch
 
 
 def _declare(L):

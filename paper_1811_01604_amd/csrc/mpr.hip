@@ -47,6 +47,8 @@ constexpr uint32_t kInitSweep = 0xFFFFFFFFu;
 // per-call partial results.
 constexpr int64_t kDoneOffset = 0;       // done-chain counter
 constexpr int64_t kTicketOffset = 256;   // last-block ticket of the redo kernel with the control fused
+constexpr int64_t kGenOffset = 512;      // barrier generation of the persistent sweep
+constexpr int64_t kAbortOffset = 768;    // barrier time-out word of the persistent sweep
 constexpr int64_t kWorkOffset = 1024;    // three work counters (profiling)
 constexpr int64_t kEnergyOffset = 2048;  // diag energy accumulator
 constexpr int64_t kSlopeOffset = 4096;   // diag slope input / output
@@ -880,6 +882,29 @@ __device__ __noinline__ SiteOutD tile_redo_site(const float *a, int rows, int c,
                          (double)rr, a_cur, T, sc.q64, or_only != 0);
 }
 
+// The parameters one sweep of a chain reads (written by the control between
+// sweeps).
+struct SweepState {
+    int32_t phase;
+    uint32_t sweep;
+    float inv_T, dscale, inv_k, inv_km1;
+    double T, a_cur;
+};
+
+__device__ __forceinline__ SweepState sweep_state_of(const ChainState *stp)
+{
+    SweepState s;
+    s.phase = stp->phase;
+    s.sweep = stp->sweep;
+    s.inv_T = stp->inv_T;
+    s.dscale = stp->dscale;
+    s.inv_k = stp->inv_k;
+    s.inv_km1 = stp->inv_km1;
+    s.T = stp->T;
+    s.a_cur = stp->a_cur;
+    return s;
+}
+
 template <int TH>
 struct TileShared {
     // list entries per wave: its rows of the colour-0 pass with the ring
@@ -897,15 +922,15 @@ struct TileShared {
 };
 
 template <bool DIAG, int TH, bool EDGE>
-__device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDesc &d, ChainState *stp, int y0,
+__device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDesc &d, const SweepState &ss, int y0,
                                                 int hx0, int mode, const SweepConsts &sc, int or_only,
                                                 uint8_t *__restrict__ flags, uint64_t &e_thread,
                                                 uint32_t &acc_thread)
 {
     const int tid = (int)threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int phase = stp->phase;
-    const uint32_t sweep = stp->sweep;
-    const float inv_T = stp->inv_T, dscale = stp->dscale;
+    const int phase = ss.phase;
+    const uint32_t sweep = ss.sweep;
+    const float inv_T = ss.inv_T, dscale = ss.dscale;
     const bool eq = phase == PH_EQ;
     float *const dst0 = mode == 0 ? d.h2[0] : d.h[0];
     float *const dst1 = mode == 0 ? d.h2[1] : d.h[1];
@@ -1053,7 +1078,7 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
                     m &= m - 1u;
                     const int r = wi / kTileLS, j = wi - r * kTileLS;
                     const SiteOutD o = tile_redo_site(&L.a[0][0][0], TH + 4, c, r, j, y0, hx0, d.nx, d.ny, sweep, d.chain,
-                                                      d.image_id, sc, or_only, stp->a_cur, stp->T);
+                                                      d.image_id, sc, or_only, ss.a_cur, ss.T);
                     const int y = y0 - 2 + r, h = hx0 - 4 + j, s = (r + c) & 1;
                     L.a[c][r][j] = (float)o.phi;
                     const bool own = !ring || (r >= 2 && r < TH + 2 && j >= 4 && j < kTileH + 4);
@@ -1072,7 +1097,7 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
     // holding at least one gap site), and the equilibrium sums
     {
         constexpr int NQ = kTileH / 4;
-        const float ik = stp->inv_k, ikm1 = stp->inv_km1;
+        const float ik = ss.inv_k, ikm1 = ss.inv_km1;
         for (int cc = 0; cc < 2; ++cc) {
             if ((mode == 1 && cc == 1) || (mode == 2 && cc == 0)) continue;
             float *const dst = cc ? dst1 : dst0;
@@ -1112,6 +1137,62 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
     }
 }
 
+// The block's bond energy and accepted count added to its chain (energy in
+// 16-bit halves, so that the 32-bit lane sums cannot carry out).  Called by
+// every thread of the block.
+template <int TH>
+__device__ __forceinline__ void tile_block_sums(TileShared<TH> &L, uint64_t e_thread, uint32_t acc_thread,
+                                                ChainState *stp)
+{
+    const int tid = (int)threadIdx.x;
+    uint32_t lo = (uint32_t)(e_thread & 0xFFFFu), hi = (uint32_t)(e_thread >> 16), ac = acc_thread;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo += __shfl_xor(lo, off);
+        hi += __shfl_xor(hi, off);
+        ac += __shfl_xor(ac, off);
+    }
+    const int wid = tid >> 6;
+    if ((tid & 63) == 0) {
+        L.red[0][wid] = lo;
+        L.red[1][wid] = hi;
+        L.red[2][wid] = ac;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long e = 0ull, a = 0ull;
+        for (int i = 0; i < kTileNW; ++i) {
+            e += ((unsigned long long)L.red[1][i] << 16) + L.red[0][i];
+            a += L.red[2][i];
+        }
+        if (e) atomicAdd(&stp->e_fx, e);
+        if (a) atomicAdd(&stp->acc, a);
+    }
+}
+
+// The work of the last block of a sweep: h and h2 of every swept chain
+// exchanged (the chain's `swapped` flag toggled), then the per-sweep control
+// of all chains.  Called by every thread of that block.
+__device__ __forceinline__ void swap_and_control(ChainDesc *descs, ChainState *states, const BlockMap &bm,
+                                                 const FusedControl &ctl)
+{
+    const int tid = (int)threadIdx.x;
+    for (int k = tid; k < bm.n; k += kBlock) {
+        const int c = bm.id[k];
+        if (states[c].phase == PH_DONE) continue;
+        ChainDesc &dd = descs[c];
+        float *t0 = dd.h[0], *t1 = dd.h[1];
+        dd.h[0] = dd.h2[0];
+        dd.h[1] = dd.h2[1];
+        dd.h2[0] = t0;
+        dd.h2[1] = t1;
+        states[c].swapped ^= 1;
+    }
+    __syncthreads();
+    for (int c = tid; c < ctl.n_all; c += kBlock)
+        control_chain(descs, states, c, ctl.cp, ctl.done_count, ctl.work);
+}
+
 // With `ctl.on` (launches of a few thousand blocks, where one ticket counter
 // costs little) the last block to finish also exchanges h and h2 of the
 // swept chains and runs the per-sweep control, which saves the control
@@ -1145,36 +1226,12 @@ __global__ __launch_bounds__(kBlock) void sweep_tile_kernel(ChainDesc *__restric
         const int y0 = ty * TH, hx0 = tx * kTileH;
         const bool edge = !(ty >= 1 && y0 + TH + 2 <= d.ny && tx >= 1 && hx0 + kTileH + 2 <= (d.nx >> 1));
         __syncthreads();
+        const SweepState ss = sweep_state_of(stp);
         if (edge)
-            tile_sweep_body<DIAG, TH, true>(L, d, stp, y0, hx0, mode, sc, or_only, flags, e_thread, acc_thread);
+            tile_sweep_body<DIAG, TH, true>(L, d, ss, y0, hx0, mode, sc, or_only, flags, e_thread, acc_thread);
         else
-            tile_sweep_body<DIAG, TH, false>(L, d, stp, y0, hx0, mode, sc, or_only, flags, e_thread, acc_thread);
-        if (phase != PH_EQ) {
-            // block sums: energy in 16-bit halves (no carries in 32-bit lane sums)
-            uint32_t lo = (uint32_t)(e_thread & 0xFFFFu), hi = (uint32_t)(e_thread >> 16), ac = acc_thread;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                lo += __shfl_xor(lo, off);
-                hi += __shfl_xor(hi, off);
-                ac += __shfl_xor(ac, off);
-            }
-            const int wid = tid >> 6;
-            if ((tid & 63) == 0) {
-                L.red[0][wid] = lo;
-                L.red[1][wid] = hi;
-                L.red[2][wid] = ac;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                unsigned long long e = 0ull, a = 0ull;
-                for (int i = 0; i < kTileNW; ++i) {
-                    e += ((unsigned long long)L.red[1][i] << 16) + L.red[0][i];
-                    a += L.red[2][i];
-                }
-                if (e) atomicAdd(&stp->e_fx, e);
-                if (a) atomicAdd(&stp->acc, a);
-            }
-        }
+            tile_sweep_body<DIAG, TH, false>(L, d, ss, y0, hx0, mode, sc, or_only, flags, e_thread, acc_thread);
+        if (phase != PH_EQ) tile_block_sums(L, e_thread, acc_thread, stp);
     }
     if (!ctl.on) return;
     __shared__ int last;
@@ -1186,21 +1243,143 @@ __global__ __launch_bounds__(kBlock) void sweep_tile_kernel(ChainDesc *__restric
     __syncthreads();
     if (!last) return;
     __threadfence();  // the other blocks' sums and stores are visible
-    for (int k = tid; k < bm.n; k += kBlock) {
-        const int c = bm.id[k];
-        if (states[c].phase == PH_DONE) continue;
-        ChainDesc &dd = descs[c];
-        float *t0 = dd.h[0], *t1 = dd.h[1];
-        dd.h[0] = dd.h2[0];
-        dd.h[1] = dd.h2[1];
-        dd.h2[0] = t0;
-        dd.h2[1] = t1;
-        states[c].swapped ^= 1;
-    }
-    __syncthreads();
-    for (int c = tid; c < ctl.n_all; c += kBlock)
-        control_chain(descs, states, c, ctl.cp, ctl.done_count, ctl.work);
+    swap_and_control(descs, states, bm, ctl);
     if (tid == 0) *ctl.ticket = 0u;
+}
+
+// Persistent fused sweeps, for chain sets whose tiles all fit on the GPU at
+// once (small fills: a 1024 x 1024 chain is a few hundred tiles).  One
+// cooperative launch (which guarantees that every block is resident) runs up
+// to `count` sweeps; between two sweeps the blocks meet at a grid barrier
+// whose last arrival exchanges h and h2 and runs the per-sweep control, the
+// work of sweep_tile_kernel's last block, so that a sweep costs a barrier
+// instead of a kernel launch and its gap.  The arithmetic is that of
+// sweep_tile_kernel, so the results are the same bit for bit.
+//
+// Barrier: every wave waits for its own stores (they then sit in its XCD's
+// L2), one thread per block writes that L2 back (release) and takes a
+// ticket; the last ticket-holder runs the control, releases it, resets the
+// ticket and publishes the sweep count (bit 31: stop) in `gen`; the others
+// poll `gen` and then invalidate their caches (acquire).  A block that waits
+// longer than kPersistWaitTicks sets `abort` and every block leaves at its
+// next barrier; the host then reports an error.
+struct PersistCtl {
+    unsigned int *gen;    // sweeps completed in this launch, | 1 << 31 to stop; zero at launch
+    unsigned int *abort;  // nonzero: a block timed out at a barrier
+    int32_t count;        // sweeps to run at most
+    uint32_t need;        // done-counter value at which every chain has finished
+};
+constexpr uint64_t kPersistWaitTicks = 200000000ull;  // 2 s of the 100 MHz constant clock
+
+__device__ __forceinline__ uint32_t ld_agent(const unsigned int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int TH>
+__global__ __launch_bounds__(kBlock) void sweep_tile_persist_kernel(ChainDesc *descs, ChainState *states,
+                                                                    BlockMap bm, SweepConsts sc, FusedControl ctl,
+                                                                    PersistCtl pc)
+{
+    __shared__ TileShared<TH> L;
+    __shared__ SweepState sh_ss;
+    __shared__ int sh_last, sh_stop;
+    const int tid = (int)threadIdx.x;
+    for (int w = tid; w < TileShared<TH>::RW; w += kBlock) L.redo[w] = 0u;
+    // the tile of this block (the XCD-aware order of sweep_tile_kernel)
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    const uint32_t per = G >> 3, rem = G & 7u, xcd = b & 7u;
+    const int64_t lbk = (int64_t)xcd * per + (int64_t)min(xcd, rem) + (int64_t)(b >> 3);
+    int lb;
+    const int cid = chain_of_block(bm, lbk, &lb);
+    ChainState *stp = states + cid;
+    // the descriptor as of the launch; the block exchanges its own copy's
+    // h and h2 after each sweep of its chain, as the last block does in memory
+    ChainDesc d = descs[cid];
+    const int nbx = d.S / kTileH;
+    const int ty = lb / nbx, tx = lb - ty * nbx;
+    const int y0 = ty * TH, hx0 = tx * kTileH;
+    const bool edge = !(ty >= 1 && y0 + TH + 2 <= d.ny && tx >= 1 && hx0 + kTileH + 2 <= (d.nx >> 1));
+    for (int i = 0; i < pc.count; ++i) {
+        if (tid == 0) {
+            // coherent loads: the control of the last sweep wrote these
+            SweepState s;
+            s.phase = (int32_t)ld_agent((const unsigned int *)&stp->phase);
+            s.sweep = ld_agent(&stp->sweep);
+            s.inv_T = __uint_as_float(ld_agent((const unsigned int *)&stp->inv_T));
+            s.dscale = __uint_as_float(ld_agent((const unsigned int *)&stp->dscale));
+            s.inv_k = __uint_as_float(ld_agent((const unsigned int *)&stp->inv_k));
+            s.inv_km1 = __uint_as_float(ld_agent((const unsigned int *)&stp->inv_km1));
+            s.T = __longlong_as_double((long long)__hip_atomic_load((const unsigned long long *)&stp->T,
+                                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            s.a_cur = __longlong_as_double((long long)__hip_atomic_load(
+                (const unsigned long long *)&stp->a_cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            sh_ss = s;
+        }
+        if (tid < 2) L.any_redo[tid] = 0;
+        __syncthreads();
+        const SweepState ss = sh_ss;
+        if (ss.phase != PH_DONE) {
+            uint64_t e_thread = 0u;
+            uint32_t acc_thread = 0u;
+            if (edge)
+                tile_sweep_body<false, TH, true>(L, d, ss, y0, hx0, 0, sc, 0, nullptr, e_thread, acc_thread);
+            else
+                tile_sweep_body<false, TH, false>(L, d, ss, y0, hx0, 0, sc, 0, nullptr, e_thread, acc_thread);
+            if (ss.phase != PH_EQ) tile_block_sums(L, e_thread, acc_thread, stp);
+            float *t0 = d.h[0], *t1 = d.h[1];
+            d.h[0] = d.h2[0];
+            d.h[1] = d.h2[1];
+            d.h2[0] = t0;
+            d.h2[1] = t1;
+        }
+        // arrive: this wave's stores are in L2, then one write-back per block
+        __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            sh_last = atomicAdd(ctl.ticket, 1u) == G - 1u;
+        }
+        __syncthreads();
+        if (sh_last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            swap_and_control(descs, states, bm, ctl);
+            __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (tid == 0) {
+                const bool stop = i + 1 >= pc.count || ld_agent(ctl.done_count) >= pc.need || ld_agent(pc.abort) != 0u;
+                __hip_atomic_store(ctl.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(pc.gen, (uint32_t)(i + 1) | (stop ? 0x80000000u : 0u), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                sh_stop = stop ? 1 : 0;
+            }
+        } else if (tid == 0) {
+            const uint64_t t0 = wall_clock64();
+            int stop = 0;
+            for (;;) {
+                const uint32_t g = ld_agent(pc.gen);
+                if ((g & 0x7FFFFFFFu) >= (uint32_t)(i + 1)) {
+                    stop = (g >> 31) ? 1 : 0;
+                    break;
+                }
+                if (ld_agent(pc.abort) != 0u) {
+                    stop = 1;
+                    break;
+                }
+                if (wall_clock64() - t0 > kPersistWaitTicks) {
+                    __hip_atomic_store(pc.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    stop = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            sh_stop = stop;
+        }
+        __syncthreads();
+        if (sh_stop) break;
+    }
 }
 
 // The double-precision sweep: the layout of half_sweep_body (a thread per
@@ -2048,7 +2227,10 @@ struct mpr_ctx {
     std::string err;
     void *scratch = nullptr;          // small device scratch (partials, counters)
     void *static_ws = nullptr;        // this device's static_workspace (device address)
-    unsigned int *done_host = nullptr;  // pinned
+    unsigned int *done_host = nullptr;  // pinned: done counter, abort word, barrier generation
+    // resident blocks of the persistent sweep kernel by tile rows (0: no
+    // cooperative launch on this device)
+    std::map<int, int64_t> persist_cap;
     // sweeps run on a context-owned stream (captured into HIP graphs),
     // ordered after and before the caller's stream with two events
     hipStream_t gstream = nullptr;
@@ -2147,22 +2329,27 @@ struct Shape {
     int rows;
     bool compact;
     bool fused;
+    bool persist;  // fused sweeps, many per cooperative launch (sweep_tile_persist_kernel)
 };
-constexpr int kNumShapes = 11;
+constexpr int kNumShapes = 18;
 constexpr int kNumPlainShapes = 4;
 constexpr int kNumUnfusedShapes = 7;   // the shapes of double-precision chains
 constexpr Shape kShapes[kNumShapes] = {{1, false, false}, {2, false, false}, {4, false, false}, {8, false, false},
                                        {2, true, false},  {4, true, false},  {8, true, false},
                                        {16, false, true}, {24, false, true}, {32, false, true},
-                                       {48, false, true}};
+                                       {48, false, true}, {8, false, true},  {12, false, true},
+                                       {8, false, true, true},  {12, false, true, true}, {16, false, true, true},
+                                       {24, false, true, true}, {32, false, true, true}};
 constexpr int kDefaultShape = 2;  // plain, 4 half-rows
 
 int tile_code(const Shape &sh)
 {
-    return sh.rows | (sh.compact ? MPR_TILE_COMPACT : 0) | (sh.fused ? MPR_TILE_FUSED : 0);
+    return sh.rows | (sh.compact ? MPR_TILE_COMPACT : 0) | (sh.fused ? MPR_TILE_FUSED : 0) |
+           (sh.persist ? MPR_TILE_PERSIST : 0);
 }
 
-// Shape index of a tile_rows value (rows | MPR_TILE_COMPACT or MPR_TILE_FUSED), or -1.
+// Shape index of a tile_rows value (rows | MPR_TILE_COMPACT, MPR_TILE_FUSED or
+// MPR_TILE_FUSED | MPR_TILE_PERSIST), or -1.
 int shape_of(int tile)
 {
     for (int k = 0; k < kNumShapes; ++k)
@@ -2544,11 +2731,72 @@ void launch_tile(hipStream_t st, const ChainSet &cs, int v, int mode, const Swee
             hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 48>), grid, blk, 0, st, cs.d_desc, cs.d_state,
                                block_map(cs, v), mode, sc, or_only, flags, fc);
             break;
+        case 8:
+            hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 8>), grid, blk, 0, st, cs.d_desc, cs.d_state,
+                               block_map(cs, v), mode, sc, or_only, flags, fc);
+            break;
+        case 12:
+            hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 12>), grid, blk, 0, st, cs.d_desc, cs.d_state,
+                               block_map(cs, v), mode, sc, or_only, flags, fc);
+            break;
         default:
             hipLaunchKernelGGL((sweep_tile_kernel<DIAG, 32>), grid, blk, 0, st, cs.d_desc, cs.d_state,
                                block_map(cs, v), mode, sc, or_only, flags, fc);
             break;
     }
+}
+
+template <int TH>
+const void *persist_kernel() { return reinterpret_cast<const void *>(&sweep_tile_persist_kernel<TH>); }
+
+const void *persist_kernel_of(int rows)
+{
+    switch (rows) {
+        case 8: return persist_kernel<8>();
+        case 12: return persist_kernel<12>();
+        case 16: return persist_kernel<16>();
+        case 24: return persist_kernel<24>();
+        default: return persist_kernel<32>();
+    }
+}
+
+// Blocks of the persistent sweep kernel (tile rows `rows`) that the device
+// holds at once, 0 without cooperative launches; cached on the context.
+int64_t persist_capacity(mpr_ctx *ctx, int rows)
+{
+    auto it = ctx->persist_cap.find(rows);
+    if (it != ctx->persist_cap.end()) return it->second;
+    int coop = 0, cus = 0, per_cu = 0;
+    int64_t cap = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, ctx->device) == hipSuccess && coop &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel_of(rows), kBlock, 0) == hipSuccess)
+        cap = (int64_t)per_cu * cus;
+    (void)hipGetLastError();
+    ctx->persist_cap[rows] = cap;
+    return cap;
+}
+
+// Up to `count` fused sweeps of every listed chain in persistent shape v,
+// in one cooperative launch (the barrier generation cleared first).
+hipError_t launch_persist(hipStream_t st, const ChainSet &cs, int v, const SweepConsts &sc, const FusedControl &ctl,
+                          unsigned int *gen, unsigned int *abort_word, int count, uint32_t need)
+{
+    hipError_t e = hipMemsetAsync(gen, 0, sizeof(unsigned int), st);
+    if (e != hipSuccess) return e;
+    ChainDesc *descs = cs.d_desc;
+    ChainState *states = cs.d_state;
+    BlockMap bm = block_map(cs, v);
+    SweepConsts scc = sc;
+    FusedControl fc = ctl;
+    PersistCtl pc;
+    pc.gen = gen;
+    pc.abort = abort_word;
+    pc.count = count;
+    pc.need = need;
+    void *args[] = {&descs, &states, &bm, &scc, &fc, &pc};
+    return hipLaunchCooperativeKernel(persist_kernel_of(kShapes[v].rows), dim3((unsigned)cs.total_blocks[v]),
+                                      dim3(kBlock), args, 0, st);
 }
 
 // Builds the launch list of a chain set from the chains in `active`: block
@@ -2589,7 +2837,10 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     unsigned int *d_done = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kDoneOffset);
     unsigned int *d_ticket = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kTicketOffset);
     unsigned long long *d_work = reinterpret_cast<unsigned long long *>((char *)ctx->scratch + kWorkOffset);
+    unsigned int *d_gen = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kGenOffset);
+    unsigned int *d_abort = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kAbortOffset);
     HIP_TRY(ctx, hipMemsetAsync(d_done, 0, sizeof(unsigned int), stream));
+    HIP_TRY(ctx, hipMemsetAsync(d_abort, 0, sizeof(unsigned int), stream));
     HIP_TRY(ctx, hipMemsetAsync(d_ticket, 0, sizeof(unsigned int), stream));
     unsigned int already = 0;
     for (const auto &s : cs.state)
@@ -2628,7 +2879,20 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     // control in its last block instead (unless states are recorded); or two
     // half-sweeps, the colour-1 redo kernel running the control unless the
     // states are recorded (or the chains are double precision).
+    // The persistent shapes: single-precision chains whose tiles the device
+    // holds at once, states not recorded (nothing runs between the sweep and
+    // the control).
+    auto persist_ok = [&](int v) {
+        return kShapes[v].persist && fuse && !table && cs.total_blocks[v] > 0 &&
+               cs.total_blocks[v] <= persist_capacity(ctx, kShapes[v].rows);
+    };
+    const uint32_t need = (uint32_t)(n - (int)already);
+    hipError_t perr = hipSuccess;
     auto sweeps = [&](int v, int count) {
+        if (kShapes[v].persist) {
+            perr = launch_persist(st, cs, v, sc, fc, d_gen, d_abort, count, need);
+            return;
+        }
         for (int i = 0; i < count; ++i) {
             const bool fused = kShapes[v].fused;
             if (fused && fuse && cs.total_blocks[v] <= kTileCtlMaxBlocks) {
@@ -2654,10 +2918,21 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
         HIP_TRY(ctx, hipEventRecord(ctx->ev_t0, st));
         if (ge) HIP_TRY(ctx, hipGraphLaunch(ge, st));
         else sweeps(v, count);
+        if (perr != hipSuccess) return fail(ctx, MPR_ERR_HIP, "persistent sweep launch: %s", hipGetErrorString(perr));
         HIP_TRY(ctx, hipGetLastError());
         HIP_TRY(ctx, hipEventRecord(ctx->ev_t1, st));
         HIP_TRY(ctx, hipMemcpyAsync(ctx->done_host, d_done, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+        if (kShapes[v].persist) {
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->done_host + 1, d_abort, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->done_host + 2, d_gen, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+        }
         HIP_TRY(ctx, hipStreamSynchronize(st));
+        if (kShapes[v].persist) {
+            if (ctx->done_host[1] != 0u)
+                return fail(ctx, MPR_ERR_HIP, "persistent sweep: a block timed out at the grid barrier");
+            // the launch stops early once every chain is done
+            count = (int)(ctx->done_host[2] & 0x7FFFFFFFu);
+        }
         float ms = 0.0f;
         HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
         if (ms_out) *ms_out = ms;
@@ -2675,6 +2950,9 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     const int n_shapes = table ? kNumPlainShapes : (cs.fp64 ? kNumUnfusedShapes : kNumShapes);
     int v = p->tile_rows ? shape_of(p->tile_rows) : -1;
     if (v >= n_shapes) v = kDefaultShape;
+    // a persistent shape that does not apply here: its rows, one launch per sweep
+    auto usable = [&](int k) { return k < 0 || !kShapes[k].persist || persist_ok(k); };
+    if (!usable(v)) v = shape_of(kShapes[v].rows | MPR_TILE_FUSED);
     int maxnx = 0, maxny = 0;
     for (const auto &d : cs.desc) {
         maxnx = std::max(maxnx, d.nx);
@@ -2684,23 +2962,30 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     float sweep_ms = -1.0f;
     if (v < 0) {
         auto it = ctx->tuned_rows.find(key);
-        if (it != ctx->tuned_rows.end()) v = it->second;
+        if (it != ctx->tuned_rows.end()) v = usable(it->second) ? it->second
+                                                                 : shape_of(kShapes[it->second].rows | MPR_TILE_FUSED);
     }
     if (v < 0) {
         const int ts = std::max(1, std::min(poll_every, 3));
         float best = 0.0f;
         int tried = 0;
         for (int k = 0; k < n_shapes && !finished && done_sweeps + ts <= max_sweeps; ++k, ++tried) {
+            if (!usable(k)) continue;
+            // time per sweep; a persistent launch over more sweeps, so that
+            // its one launch does not weigh on the comparison
+            const int tk = kShapes[k].persist ? (int)std::min<int64_t>(4 * ts, max_sweeps - done_sweeps) : ts;
             float ms = 0.0f;
-            int rc = block(k, ts, nullptr, &ms);
+            const int64_t before = done_sweeps;
+            int rc = block(k, tk, nullptr, &ms);
             if (rc) return rc;
+            ms /= (float)std::max<int64_t>(1, done_sweeps - before);
             if (v < 0 || ms < best) {
                 best = ms;
                 v = k;
             }
         }
         if (v < 0) v = kDefaultShape;
-        else sweep_ms = best / (float)ts;
+        else sweep_ms = best;
         if (tried == n_shapes) ctx->tuned_rows[key] = v;
     }
     if (!table) ctx->last_tile = tile_code(kShapes[v]);
@@ -2708,6 +2993,8 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     int spl = p->sweeps_per_launch > 0 ? p->sweeps_per_launch : poll_every;
     if (p->sweeps_per_launch <= 0 && sweep_ms > 0.0f && (float)spl * sweep_ms < 1.0f)
         spl = std::min(64, poll_every * (int)std::ceil(1.0f / ((float)poll_every * sweep_ms)));
+    // a persistent launch ends by itself when every chain is done
+    if (p->sweeps_per_launch <= 0 && kShapes[v].persist) spl = 64;
     // the captured sweep group, released on every return path
     struct Captured {
         hipGraph_t graph = nullptr;
@@ -2724,7 +3011,8 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     hipGraphExec_t &ge = cap.exec;
     auto capture = [&]() {
         cap.release();
-        if (graphs && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        // (a persistent launch runs a whole group itself and is not captured)
+        if (graphs && !kShapes[v].persist && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             sweeps(v, spl);
             if (hipStreamEndCapture(st, &cap.graph) != hipSuccess ||
                 hipGraphInstantiate(&cap.exec, cap.graph, nullptr, nullptr, 0) != hipSuccess)
@@ -2968,7 +3256,7 @@ int32_t mpr_create(mpr_ctx **out, int32_t device)
         (void)hipGetLastError();
     }
     if (hipMalloc(&ctx->scratch, kScratchBytes) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->done_host, sizeof(unsigned int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->done_host, 4 * sizeof(unsigned int), hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess ||

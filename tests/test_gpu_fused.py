@@ -21,7 +21,9 @@ torch = pytest.importorskip("torch")
 import paper_1811_01604_amd as mpr  # noqa: E402
 
 pytestmark = pytest.mark.gpu
-FUSED_TILES = [16 | mpr.TILE_FUSED, 24 | mpr.TILE_FUSED, 32 | mpr.TILE_FUSED, 48 | mpr.TILE_FUSED]
+FUSED_TILES = [16 | mpr.TILE_FUSED, 24 | mpr.TILE_FUSED, 32 | mpr.TILE_FUSED, 48 | mpr.TILE_FUSED,
+               8 | mpr.TILE_FUSED, 12 | mpr.TILE_FUSED]
+PERSIST_TILES = [r | mpr.TILE_FUSED | mpr.TILE_PERSIST for r in (8, 12, 16, 24, 32)]
 
 
 def say(*a):
@@ -83,7 +85,9 @@ def test_fused_sweep_equals_half_sweeps_on_a_ragged_batch(ctx, T):
     ref = run(ctx, imgs, phi, mk, Ts, 4, 5, R=3, K=5, spread=1)
     say(f"  T={T}: relax sweeps {[s[0] for s in ref['stats']]}")
     for tile, spl in [(FUSED_TILES[0], 5), (FUSED_TILES[1], 1), (FUSED_TILES[2], 64), (FUSED_TILES[2], 3),
-                      (FUSED_TILES[3], 4)]:
+                      (FUSED_TILES[3], 4), (FUSED_TILES[4], 2), (FUSED_TILES[5], 7),
+                      (PERSIST_TILES[0], 3), (PERSIST_TILES[1], 64), (PERSIST_TILES[2], 1), (PERSIST_TILES[3], 0),
+                      (PERSIST_TILES[4], 9)]:
         got = run(ctx, imgs, phi, mk, Ts, tile, spl, R=3, K=5, spread=1)
         for key in ref:
             assert got[key] == ref[key], (tile, spl, key)
@@ -101,7 +105,7 @@ def test_fused_sweep_with_recorded_states_and_one_state_chains(ctx):
     for kw in (dict(R=2, K=4, fixed_relax=7), dict(R=5, K=1)):
         rec = kw["K"] > 1
         ref = run(ctx, imgs, phi, mk, Ts, 2 | mpr.TILE_COMPACT, 5, record=rec, **kw)
-        for tile in FUSED_TILES:
+        for tile in FUSED_TILES + PERSIST_TILES:
             got = run(ctx, imgs, phi, mk, Ts, tile, 5, record=rec, **kw)
             for key in ref:
                 assert got[key] == ref[key], (kw, tile, key)
@@ -118,3 +122,38 @@ def test_tuner_may_pick_any_shape_with_identical_results(ctx):
     b = run(ctx, imgs, phi, mk, Ts, 32 | mpr.TILE_FUSED, 0, R=4, K=3)
     assert a == b
     say(f"  tuned shape {ctx.profile_read()['last_tile']:#x}")
+
+
+def test_persistent_sweeps_of_a_1024_fill(ctx):
+    """A 1024 x 1024 fill in the paper's layout (one chain, 100 states, the
+    stopping rule): the persistent launches (many sweeps each, a grid
+    barrier between sweeps) give the one-launch-per-sweep results bit for
+    bit, whatever the launch length; so do runs cut by the sweep limit and
+    resumed."""
+    im = synth.workload_l1024()
+    imgs = mpr.images([im.z.shape])
+    z = dev(im.z.astype(np.float32))
+    mk = dev(im.mask, torch.uint8)
+    phi = torch.zeros_like(z)
+    ctx.map_to_angles(imgs, z, mk, phi)
+    Ts = np.array([0.09])
+    ref = run(ctx, imgs, phi, mk, Ts, 24 | mpr.TILE_FUSED, 8, R=1, K=100)
+    say(f"  relax sweeps {ref['stats'][0][0]}")
+    for tile in PERSIST_TILES:
+        for spl in (0, 37):
+            got = run(ctx, imgs, phi, mk, Ts, tile, spl, R=1, K=100)
+            for key in ref:
+                assert got[key] == ref[key], (tile, spl, key)
+    # cut after 50 and 40 more sweeps (of about 140), resumed with the same workspace
+    tile = 16 | mpr.TILE_FUSED | mpr.TILE_PERSIST
+    prm = mpr.default_params(R=1, K=100, tile_rows=tile, sweeps_per_launch=0)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    ps = torch.zeros_like(phi)
+    done, st = False, None
+    for limit, resume in ((50, 0), (40, 1), (100000, 1)):
+        prm = mpr.default_params(R=1, K=100, tile_rows=tile, sweeps_per_launch=0, sweep_limit=limit, resume=resume)
+        done, st = ctx.simulate(imgs, phi, mk, Ts, prm, ws, ps, allow_incomplete=True)
+        say(f"  limit {limit}: done {done}")
+        assert done == (limit > 1000)
+    assert ps.cpu().numpy().tobytes() == ref["sum"]
+    assert [(s["relax_sweeps"], s["not_converged"], s["k_last"], s["a_final"], s["A_last"]) for s in st] == ref["stats"]

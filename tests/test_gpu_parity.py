@@ -177,7 +177,8 @@ def smooth_state(ny, nx, nu, kappa, p_removed, noise, seed):
 PLAIN, COMPACT = 0, 4 | mpr.TILE_COMPACT  # default plain shape; compacted 4-row shape
 FUSED = 32 | mpr.TILE_FUSED  # fused tile sweep, 32-row tiles (one colour in the diagnostics)
 ALL_TILES = [1, 2, 4, 8, 2 | mpr.TILE_COMPACT, 4 | mpr.TILE_COMPACT, 8 | mpr.TILE_COMPACT,
-             16 | mpr.TILE_FUSED, 24 | mpr.TILE_FUSED, 32 | mpr.TILE_FUSED, 48 | mpr.TILE_FUSED]
+             16 | mpr.TILE_FUSED, 24 | mpr.TILE_FUSED, 32 | mpr.TILE_FUSED, 48 | mpr.TILE_FUSED,
+             8 | mpr.TILE_FUSED, 12 | mpr.TILE_FUSED]
 
 
 def run_pair(ctx, phi32, m, colour, T, a, sweep, mode=0, chain=0, stream_id=0, seed=3000, tile=PLAIN):
