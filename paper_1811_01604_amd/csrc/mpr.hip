@@ -49,6 +49,7 @@ constexpr int64_t kDoneOffset = 0;       // done-chain counter
 constexpr int64_t kTicketOffset = 256;   // last-block ticket of the redo kernel with the control fused
 constexpr int64_t kGenOffset = 512;      // barrier generation of the persistent sweep
 constexpr int64_t kAbortOffset = 768;    // barrier time-out word of the persistent sweep
+constexpr int64_t kSlotsOffset = 16384;  // per-chain sweep sums of the persistent sweep (32 bytes a chain)
 constexpr int64_t kWorkOffset = 1024;    // three work counters (profiling)
 constexpr int64_t kEnergyOffset = 2048;  // diag energy accumulator
 constexpr int64_t kSlopeOffset = 4096;   // diag slope input / output
@@ -630,19 +631,18 @@ __device__ void set_derived(ChainState &st, double q)
 }
 
 // Algorithm 2 steps 5.2-5.5 (relaxation), 6 (equilibrium states) and the
-// e(T, L) runs for chain c, after both half-sweeps of a sweep.
-__device__ __forceinline__ void control_chain(const ChainDesc *__restrict__ descs, ChainState *__restrict__ states,
-                                              int c, const CtlParams &cp, unsigned int *done_count,
-                                              unsigned long long *work)
+// e(T, L) runs for a chain not done, after both colours of a sweep, on its
+// state `st` (in place) with its sums e_fx and acc of that sweep.  The done
+// counter (and the work counters) are skipped where null.
+__device__ __forceinline__ void control_core(ChainState &st, const ChainDesc &d, const CtlParams &cp,
+                                             unsigned int *done_count, unsigned long long *work)
 {
-    // in place: a copy would put the ring buffer in scratch memory
-    ChainState &st = states[c];
-    if (st.phase == PH_DONE) return;
-    const ChainDesc d = descs[c];
-    // work counters: chain-sweeps, gap-site updates, useful bytes
-    atomicAdd(&work[0], 1ull);
-    atomicAdd(&work[1], (unsigned long long)d.P);
-    atomicAdd(&work[2], (unsigned long long)(cp.angle_bytes * ((int64_t)d.nx * d.ny + d.P)));
+    if (work) {
+        // work counters: chain-sweeps, gap-site updates, useful bytes
+        atomicAdd(&work[0], 1ull);
+        atomicAdd(&work[1], (unsigned long long)d.P);
+        atomicAdd(&work[2], (unsigned long long)(cp.angle_bytes * ((int64_t)d.nx * d.ny + d.P)));
+    }
     const uint32_t t = st.sweep;
     const unsigned long long acc = st.acc, efx = st.e_fx;
     st.acc = 0ull;
@@ -692,7 +692,19 @@ __device__ __forceinline__ void control_chain(const ChainDesc *__restrict__ desc
         if ((int64_t)t + 1 >= (int64_t)cp.burn + cp.meas) st.phase = PH_DONE;
     }
     set_derived(st, cp.q);
-    if (st.phase == PH_DONE) atomicAdd(done_count, 1u);
+    if (st.phase == PH_DONE && done_count) atomicAdd(done_count, 1u);
+}
+
+// The control of chain c of a chain set (control_core on its state in place:
+// a copy would put the ring buffer in scratch memory).
+__device__ __forceinline__ void control_chain(const ChainDesc *__restrict__ descs, ChainState *__restrict__ states,
+                                              int c, const CtlParams &cp, unsigned int *done_count,
+                                              unsigned long long *work)
+{
+    ChainState &st = states[c];
+    if (st.phase == PH_DONE) return;
+    const ChainDesc d = descs[c];
+    control_core(st, d, cp, done_count, work);
 }
 
 // The deferred double-precision updates of one half-sweep (block shape
@@ -905,28 +917,102 @@ __device__ __forceinline__ SweepState sweep_state_of(const ChainState *stp)
     return s;
 }
 
-template <int TH>
+template <int TH, int NW = kTileNW>
 struct TileShared {
+    static constexpr int NT = NW * 64;  // threads per block
     // list entries per wave: its rows of the colour-0 pass with the ring
     // (TH + 2 rows of kTileH columns, a row per wave in turn) and its share
     // of the ring's two side columns (at most 64 per wave)
-    static constexpr int CAP = (TH + 2 + kTileNW - 1) / kTileNW * 64 + 64;
+    static constexpr int CAP = (TH + 2 + NW - 1) / NW * 64 + 64;
     static constexpr int RW = ((TH + 4) * kTileLS + 31) / 32;     // redo bitmap words
     alignas(16) float a[2][TH + 4][kTileLS];  // angle words (sign bit: sampled), colour, row, half-column
     // per wave: gap entries from the front, sampled entries from the back;
     // entry = local row << 7 | local half-column
-    uint16_t list[kTileNW][CAP];
+    uint16_t list[NW][CAP];
     uint32_t redo[RW];
-    uint32_t red[3][kTileNW];
+    uint32_t red[3][NW];
     int any_redo[2];
 };
 
-template <bool DIAG, int TH, bool EDGE>
-__device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDesc &d, const SweepState &ss, int y0,
-                                                int hx0, int mode, const SweepConsts &sc, int or_only,
-                                                uint8_t *__restrict__ flags, uint64_t &e_thread,
-                                                uint32_t &acc_thread)
+// Equilibrium sums and squared deviations of a tile's own sites (both
+// colours), staged with the angles when the sweep is known to need them.
+template <int TH>
+struct TilePre {
+    alignas(16) float acc[2][TH][kTileH];
+    alignas(16) float m2[2][TH][kTileH];
+};
+
+// Stages the tile and its halo (both colours, 18 float4 per row and colour;
+// the colour loop outside, so that the base pointer of every load is
+// uniform) from h into LDS, and with `P` the tile's own equilibrium sums
+// (and squared deviations, where kept).  No barrier at the end.
+template <int TH, int NW>
+__device__ __forceinline__ void tile_stage(TileShared<TH, NW> &L, TilePre<TH> *P, const ChainDesc &d, int y0, int hx0)
 {
+    constexpr int NT = TileShared<TH, NW>::NT;
+    const int tid = (int)threadIdx.x;
+    constexpr int NQ = kTileLS / 4;
+    constexpr int NLOAD = (TH + 4) * NQ;
+    constexpr int IT = (NLOAD + NT - 1) / NT;
+    v4f v[2][IT];
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+        const float *src = cc ? d.h[1] : d.h[0];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int k = tid + it * NT;
+            const int r = k / NQ, q = k - r * NQ;
+            const int y = y0 - 2 + r, h = hx0 - 4 + 4 * q;
+            const bool in = k < NLOAD && y >= 0 && y < d.ny && h >= 0 && h < d.S;
+            // outside the grid: zeros, never a candidate (EDGE bounds)
+            // nor a valid neighbour
+            v[cc][it] = gldi4(src, in ? (uint32_t)(y * d.S + h) : 0u);
+            if (!in) v[cc][it] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    }
+    if (P) {
+        // the tile's rows y0 .. y0 + TH - 1, half-columns hx0 .. hx0 + kTileH - 1
+        constexpr int PQ = kTileH / 4;
+        constexpr int PLOAD = TH * PQ;
+        constexpr int PIT = (PLOAD + NT - 1) / NT;
+        const bool with_m2 = d.m2[0] != nullptr;
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const float *ap = cc ? d.acc[1] : d.acc[0];
+            const float *mp = cc ? d.m2[1] : d.m2[0];
+#pragma unroll
+            for (int it = 0; it < PIT; ++it) {
+                const int k = tid + it * NT;
+                const int r = k / PQ, q = k - r * PQ;
+                const int y = y0 + r;
+                if (k < PLOAD && y < d.ny) {
+                    const uint32_t idx = (uint32_t)(y * d.S + hx0 + 4 * q);
+                    *(v4f *)&P->acc[cc][r][4 * q] = gldi4(ap, idx);
+                    if (with_m2) *(v4f *)&P->m2[cc][r][4 * q] = gldi4(mp, idx);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int k = tid + it * NT;
+            const int r = k / NQ, q = k - r * NQ;
+            if (k < NLOAD) *(v4f *)&L.a[cc][r][4 * q] = v[cc][it];
+        }
+}
+
+// The sweep (mode 0) or one colour (modes 1, 2) of a staged tile, and the
+// write-back of its gap sites and equilibrium sums (those from `P` when
+// given: staged by tile_stage for this sweep).
+template <bool DIAG, int TH, bool EDGE, int NW>
+__device__ __forceinline__ void tile_update(TileShared<TH, NW> &L, const TilePre<TH> *P, const ChainDesc &d,
+                                            const SweepState &ss, int y0, int hx0, int mode, const SweepConsts &sc,
+                                            int or_only, uint8_t *__restrict__ flags, uint64_t &e_thread,
+                                            uint32_t &acc_thread)
+{
+    constexpr int NT = TileShared<TH, NW>::NT;
     const int tid = (int)threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int phase = ss.phase;
     const uint32_t sweep = ss.sweep;
@@ -934,39 +1020,6 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
     const bool eq = phase == PH_EQ;
     float *const dst0 = mode == 0 ? d.h2[0] : d.h[0];
     float *const dst1 = mode == 0 ? d.h2[1] : d.h[1];
-
-    // stage the tile and its halo: 18 float4 per row and colour (the colour
-    // loop outside, so that the base pointer of every load is uniform)
-    {
-        constexpr int NQ = kTileLS / 4;
-        constexpr int NLOAD = (TH + 4) * NQ;
-        constexpr int IT = (NLOAD + kBlock - 1) / kBlock;
-        v4f v[2][IT];
-#pragma unroll
-        for (int cc = 0; cc < 2; ++cc) {
-            const float *src = cc ? d.h[1] : d.h[0];
-#pragma unroll
-            for (int it = 0; it < IT; ++it) {
-                const int k = tid + it * kBlock;
-                const int r = k / NQ, q = k - r * NQ;
-                const int y = y0 - 2 + r, h = hx0 - 4 + 4 * q;
-                const bool in = k < NLOAD && y >= 0 && y < d.ny && h >= 0 && h < d.S;
-                // outside the grid: zeros, never a candidate (EDGE bounds)
-                // nor a valid neighbour
-                v[cc][it] = gldi4(src, in ? (uint32_t)(y * d.S + h) : 0u);
-                if (!in) v[cc][it] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-            }
-        }
-#pragma unroll
-        for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-            for (int it = 0; it < IT; ++it) {
-                const int k = tid + it * kBlock;
-                const int r = k / NQ, q = k - r * NQ;
-                if (k < NLOAD) *(v4f *)&L.a[cc][r][4 * q] = v[cc][it];
-            }
-    }
-    __syncthreads();
 
     const int npass = mode == 0 ? 2 : 1;
     for (int pass = 0; pass < npass; ++pass) {
@@ -998,11 +1051,11 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
             ng += __popcll(bg);
             if (energy) {
                 const uint64_t bs = __ballot(smp);
-                if (smp) lst[TileShared<TH>::CAP - 1 - (ns + rank_below(bs))] = ent;
+                if (smp) lst[TileShared<TH, NW>::CAP - 1 - (ns + rank_below(bs))] = ent;
                 ns += __popcll(bs);
             }
         };
-        for (int r = r_lo + wid; r < r_hi; r += kTileNW) add(true, r, 4 + lane);
+        for (int r = r_lo + wid; r < r_hi; r += NW) add(true, r, 4 + lane);
         if (ring) {
             const int k = wid * 64 + lane;
             add(k < 2 * (TH + 2), 1 + (k >> 1), (k & 1) ? kTileH + 4 : 3);
@@ -1051,7 +1104,7 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
         }
         // bond energies of the tile's sampled colour-1 sites
         for (int e = lane; e < ns; e += 64) {
-            const uint32_t ent = lst[TileShared<TH>::CAP - 1 - e];
+            const uint32_t ent = lst[TileShared<TH, NW>::CAP - 1 - e];
             const int r = (int)(ent >> 7), j = (int)(ent & 127u);
             const int s = (r + c) & 1;
             const float *oth = &L.a[c ^ 1][r][j];
@@ -1069,7 +1122,7 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
         __syncthreads();
         // the deferred decisions, in double precision from the same inputs
         if (L.any_redo[pass]) {
-            for (int wd = tid; wd < TileShared<TH>::RW; wd += kBlock) {
+            for (int wd = tid; wd < TileShared<TH, NW>::RW; wd += NT) {
                 uint32_t m = L.redo[wd];
                 if (!m) continue;
                 L.redo[wd] = 0u;
@@ -1103,7 +1156,7 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
             float *const dst = cc ? dst1 : dst0;
             float *const ap = eq ? (cc ? d.acc[1] : d.acc[0]) : nullptr;
             float *const mp = cc ? d.m2[1] : d.m2[0];
-            for (int k = tid; k < TH * NQ; k += kBlock) {
+            for (int k = tid; k < TH * NQ; k += NT) {
                 const int rr = k / NQ, q = k - rr * NQ;
                 const int y = y0 + rr;
                 if (y >= d.ny) continue;
@@ -1120,9 +1173,10 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
                     // their values
                     const int W = (d.nx - ((y + cc) & 1) + 1) >> 1;
                     const bool gg[4] = {g0, g1, g2, g3};
-                    const v4f s0 = gldi4(ap, idx);
+                    const v4f s0 = P ? *(const v4f *)&P->acc[cc][rr][4 * q] : gldi4(ap, idx);
                     v4f s1 = s0;
-                    v4f m = mp ? gldi4(mp, idx) : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                    v4f m = mp ? (P ? *(const v4f *)&P->m2[cc][rr][4 * q] : gldi4(mp, idx))
+                               : v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         if (gg[e] && h + e < W) {
@@ -1137,12 +1191,24 @@ __device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDe
     }
 }
 
+// Stage, then sweep, the tile of a one-launch-per-sweep kernel.
+template <bool DIAG, int TH, bool EDGE>
+__device__ __forceinline__ void tile_sweep_body(TileShared<TH> &L, const ChainDesc &d, const SweepState &ss, int y0,
+                                                int hx0, int mode, const SweepConsts &sc, int or_only,
+                                                uint8_t *__restrict__ flags, uint64_t &e_thread,
+                                                uint32_t &acc_thread)
+{
+    tile_stage<TH, kTileNW>(L, nullptr, d, y0, hx0);
+    __syncthreads();
+    tile_update<DIAG, TH, EDGE, kTileNW>(L, nullptr, d, ss, y0, hx0, mode, sc, or_only, flags, e_thread, acc_thread);
+}
+
 // The block's bond energy and accepted count added to its chain (energy in
 // 16-bit halves, so that the 32-bit lane sums cannot carry out).  Called by
 // every thread of the block.
-template <int TH>
-__device__ __forceinline__ void tile_block_sums(TileShared<TH> &L, uint64_t e_thread, uint32_t acc_thread,
-                                                ChainState *stp)
+template <int TH, int NW>
+__device__ __forceinline__ void tile_block_sums(TileShared<TH, NW> &L, uint64_t e_thread, uint32_t acc_thread,
+                                                unsigned long long *e_sum, unsigned long long *acc_sum)
 {
     const int tid = (int)threadIdx.x;
     uint32_t lo = (uint32_t)(e_thread & 0xFFFFu), hi = (uint32_t)(e_thread >> 16), ac = acc_thread;
@@ -1161,12 +1227,12 @@ __device__ __forceinline__ void tile_block_sums(TileShared<TH> &L, uint64_t e_th
     __syncthreads();
     if (tid == 0) {
         unsigned long long e = 0ull, a = 0ull;
-        for (int i = 0; i < kTileNW; ++i) {
+        for (int i = 0; i < NW; ++i) {
             e += ((unsigned long long)L.red[1][i] << 16) + L.red[0][i];
             a += L.red[2][i];
         }
-        if (e) atomicAdd(&stp->e_fx, e);
-        if (a) atomicAdd(&stp->acc, a);
+        if (e) atomicAdd(e_sum, e);
+        if (a) atomicAdd(acc_sum, a);
     }
 }
 
@@ -1231,7 +1297,7 @@ __global__ __launch_bounds__(kBlock) void sweep_tile_kernel(ChainDesc *__restric
             tile_sweep_body<DIAG, TH, true>(L, d, ss, y0, hx0, mode, sc, or_only, flags, e_thread, acc_thread);
         else
             tile_sweep_body<DIAG, TH, false>(L, d, ss, y0, hx0, mode, sc, or_only, flags, e_thread, acc_thread);
-        if (phase != PH_EQ) tile_block_sums(L, e_thread, acc_thread, stp);
+        if (phase != PH_EQ) tile_block_sums(L, e_thread, acc_thread, &stp->e_fx, &stp->acc);
     }
     if (!ctl.on) return;
     __shared__ int last;
@@ -1248,93 +1314,124 @@ __global__ __launch_bounds__(kBlock) void sweep_tile_kernel(ChainDesc *__restric
 }
 
 // Persistent fused sweeps, for chain sets whose tiles all fit on the GPU at
-// once (small fills: a 1024 x 1024 chain is a few hundred tiles).  One
+// once (small fills: a 1024 x 1024 chain is 256 tiles of 32 rows).  One
 // cooperative launch (which guarantees that every block is resident) runs up
-// to `count` sweeps; between two sweeps the blocks meet at a grid barrier
-// whose last arrival exchanges h and h2 and runs the per-sweep control, the
-// work of sweep_tile_kernel's last block, so that a sweep costs a barrier
-// instead of a kernel launch and its gap.  The arithmetic is that of
+// to `count` sweeps of 512-thread blocks, with a grid barrier between two
+// sweeps in place of a kernel launch and its gap.  Every block keeps its
+// chain's descriptor and state and runs the chain's per-sweep control itself
+// (the same inputs give every block of a chain the same result), from the
+// sweep's bond energy and accepted count, which the blocks add into one of
+// two per-chain slots (alternating sweeps), so that nothing waits for one
+// block's control; the chain's first block counts it done and writes its
+// state and descriptor back at the end.  The arithmetic is that of
 // sweep_tile_kernel, so the results are the same bit for bit.
 //
 // Barrier: every wave waits for its own stores (they then sit in its XCD's
 // L2), one thread per block writes that L2 back (release) and takes a
-// ticket; the last ticket-holder runs the control, releases it, resets the
-// ticket and publishes the sweep count (bit 31: stop) in `gen`; the others
-// poll `gen` and then invalidate their caches (acquire).  A block that waits
-// longer than kPersistWaitTicks sets `abort` and every block leaves at its
-// next barrier; the host then reports an error.
+// ticket; the last ticket-holder clears the slots read in this sweep, resets
+// the ticket and publishes the sweep count (bit 31: stop) in `gen`; the
+// others poll `gen` and then invalidate their caches (acquire).  A block
+// that waits longer than kPersistWaitTicks sets `abort` and every block
+// leaves at its next barrier; the host then reports an error.
 struct PersistCtl {
     unsigned int *gen;    // sweeps completed in this launch, | 1 << 31 to stop; zero at launch
     unsigned int *abort;  // nonzero: a block timed out at a barrier
+    unsigned long long *slots;  // per chain: [sweep parity][energy, accepted]; zero at launch
     int32_t count;        // sweeps to run at most
     uint32_t need;        // done-counter value at which every chain has finished
 };
 constexpr uint64_t kPersistWaitTicks = 200000000ull;  // 2 s of the 100 MHz constant clock
+constexpr int kPersistThreads = 512;
+constexpr int64_t kPersistMaxChains = 1024;  // chains of a set that can take the persistent shapes
+static_assert(kSlotsOffset + 32 * kPersistMaxChains <= kVarOffset, "persistent sweep slots overlap the partials");
 
 __device__ __forceinline__ uint32_t ld_agent(const unsigned int *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int TH>
-__global__ __launch_bounds__(kBlock) void sweep_tile_persist_kernel(ChainDesc *descs, ChainState *states,
-                                                                    BlockMap bm, SweepConsts sc, FusedControl ctl,
-                                                                    PersistCtl pc)
+__device__ __forceinline__ unsigned long long ld_agent64(const unsigned long long *p)
 {
-    __shared__ TileShared<TH> L;
-    __shared__ SweepState sh_ss;
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int TH>
+__global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu(4))) void sweep_tile_persist_kernel(ChainDesc *descs, ChainState *states,
+                                                                             BlockMap bm, SweepConsts sc,
+                                                                             FusedControl ctl, PersistCtl pc)
+{
+    constexpr int NW = kPersistThreads / 64;
+    __shared__ TileShared<TH, NW> L;
+    __shared__ TilePre<TH> P;
+    __shared__ ChainState sst;  // this block's copy of its chain's state
     __shared__ int sh_last, sh_stop;
     const int tid = (int)threadIdx.x;
-    for (int w = tid; w < TileShared<TH>::RW; w += kBlock) L.redo[w] = 0u;
+    for (int w = tid; w < TileShared<TH, NW>::RW; w += kPersistThreads) L.redo[w] = 0u;
     // the tile of this block (the XCD-aware order of sweep_tile_kernel)
     const uint32_t G = gridDim.x, b = blockIdx.x;
     const uint32_t per = G >> 3, rem = G & 7u, xcd = b & 7u;
     const int64_t lbk = (int64_t)xcd * per + (int64_t)min(xcd, rem) + (int64_t)(b >> 3);
     int lb;
     const int cid = chain_of_block(bm, lbk, &lb);
-    ChainState *stp = states + cid;
-    // the descriptor as of the launch; the block exchanges its own copy's
-    // h and h2 after each sweep of its chain, as the last block does in memory
+    const bool lead = lb == 0;  // the chain's first block
+    unsigned long long *const slot = pc.slots + 4 * cid;
+    // descriptor and state as of the launch (earlier kernels wrote them)
     ChainDesc d = descs[cid];
+    {
+        const unsigned long long *src = reinterpret_cast<const unsigned long long *>(states + cid);
+        unsigned long long *dst = reinterpret_cast<unsigned long long *>(&sst);
+        for (int k = tid; k < (int)(sizeof(ChainState) / 8); k += kPersistThreads) dst[k] = src[k];
+    }
     const int nbx = d.S / kTileH;
     const int ty = lb / nbx, tx = lb - ty * nbx;
     const int y0 = ty * TH, hx0 = tx * kTileH;
     const bool edge = !(ty >= 1 && y0 + TH + 2 <= d.ny && tx >= 1 && hx0 + kTileH + 2 <= (d.nx >> 1));
+    const bool sums = d.acc[0] != nullptr;
+    __syncthreads();
+    int phase = sst.phase;  // the chain's phase as of the last control
+    bool swept = false;     // the previous loop pass swept the chain (its control is due)
     for (int i = 0; i < pc.count; ++i) {
-        if (tid == 0) {
-            // coherent loads: the control of the last sweep wrote these
-            SweepState s;
-            s.phase = (int32_t)ld_agent((const unsigned int *)&stp->phase);
-            s.sweep = ld_agent(&stp->sweep);
-            s.inv_T = __uint_as_float(ld_agent((const unsigned int *)&stp->inv_T));
-            s.dscale = __uint_as_float(ld_agent((const unsigned int *)&stp->dscale));
-            s.inv_k = __uint_as_float(ld_agent((const unsigned int *)&stp->inv_k));
-            s.inv_km1 = __uint_as_float(ld_agent((const unsigned int *)&stp->inv_km1));
-            s.T = __longlong_as_double((long long)__hip_atomic_load((const unsigned long long *)&stp->T,
-                                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            s.a_cur = __longlong_as_double((long long)__hip_atomic_load(
-                (const unsigned long long *)&stp->a_cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            sh_ss = s;
+        // the control of the previous sweep: its sums (coherent loads) are
+        // read while the tile is staged
+        unsigned long long te = 0ull, ta = 0ull;
+        const bool due = swept;
+        if (tid == 0 && due) {
+            te = ld_agent64(slot + 2 * ((i - 1) & 1));
+            ta = ld_agent64(slot + 2 * ((i - 1) & 1) + 1);
+        }
+        // the equilibrium sums are staged too when the last sweep was an
+        // equilibrium one (the next is then one as well, or none)
+        const bool pre = sums && phase == PH_EQ;
+        if (phase != PH_DONE) tile_stage<TH, NW>(L, pre ? &P : nullptr, d, y0, hx0);
+        if (tid == 0 && due) {
+            sst.e_fx = te;
+            sst.acc = ta;
+            control_core(sst, d, ctl.cp, lead ? ctl.done_count : nullptr, lead ? ctl.work : nullptr);
         }
         if (tid < 2) L.any_redo[tid] = 0;
         __syncthreads();
-        const SweepState ss = sh_ss;
-        if (ss.phase != PH_DONE) {
+        const SweepState ss = sweep_state_of(&sst);
+        phase = ss.phase;
+        swept = phase != PH_DONE;
+        if (swept) {
             uint64_t e_thread = 0u;
             uint32_t acc_thread = 0u;
+            const TilePre<TH> *pp = pre ? &P : nullptr;
             if (edge)
-                tile_sweep_body<false, TH, true>(L, d, ss, y0, hx0, 0, sc, 0, nullptr, e_thread, acc_thread);
+                tile_update<false, TH, true, NW>(L, pp, d, ss, y0, hx0, 0, sc, 0, nullptr, e_thread, acc_thread);
             else
-                tile_sweep_body<false, TH, false>(L, d, ss, y0, hx0, 0, sc, 0, nullptr, e_thread, acc_thread);
-            if (ss.phase != PH_EQ) tile_block_sums(L, e_thread, acc_thread, stp);
+                tile_update<false, TH, false, NW>(L, pp, d, ss, y0, hx0, 0, sc, 0, nullptr, e_thread, acc_thread);
+            if (ss.phase != PH_EQ) tile_block_sums(L, e_thread, acc_thread, slot + 2 * (i & 1), slot + 2 * (i & 1) + 1);
+            // the sweep wrote h2: exchange the buffers (as sweep_tile_kernel's last block does in memory)
             float *t0 = d.h[0], *t1 = d.h[1];
             d.h[0] = d.h2[0];
             d.h[1] = d.h2[1];
             d.h2[0] = t0;
             d.h2[1] = t1;
+            if (tid == 0) sst.swapped ^= 1;
         }
         // arrive: this wave's stores are in L2, then one write-back per block
-        __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
         __syncthreads();
         if (tid == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1342,11 +1439,17 @@ __global__ __launch_bounds__(kBlock) void sweep_tile_persist_kernel(ChainDesc *d
         }
         __syncthreads();
         if (sh_last) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            swap_and_control(descs, states, bm, ctl);
-            __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            // every block has read the sums of the previous sweep: clear
+            // their slots for the sweep after next
+            for (int k = tid; k < bm.n; k += kPersistThreads) {
+                unsigned long long *sk = pc.slots + 4 * bm.id[k] + 2 * ((i + 1) & 1);
+                __hip_atomic_store(sk, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(sk + 1, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
             __syncthreads();
             if (tid == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 const bool stop = i + 1 >= pc.count || ld_agent(ctl.done_count) >= pc.need || ld_agent(pc.abort) != 0u;
                 __hip_atomic_store(ctl.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1378,7 +1481,28 @@ __global__ __launch_bounds__(kBlock) void sweep_tile_persist_kernel(ChainDesc *d
             sh_stop = stop;
         }
         __syncthreads();
-        if (sh_stop) break;
+        if (sh_stop) {
+            // the control of the last sweep updated
+            if (tid == 0 && swept) {
+                sst.e_fx = ld_agent64(slot + 2 * (i & 1));
+                sst.acc = ld_agent64(slot + 2 * (i & 1) + 1);
+                control_core(sst, d, ctl.cp, lead ? ctl.done_count : nullptr, lead ? ctl.work : nullptr);
+            }
+            break;
+        }
+    }
+    // the chain's first block writes its state and descriptor back
+    __syncthreads();
+    if (lead) {
+        const unsigned long long *src = reinterpret_cast<const unsigned long long *>(&sst);
+        unsigned long long *dst = reinterpret_cast<unsigned long long *>(states + cid);
+        for (int k = tid; k < (int)(sizeof(ChainState) / 8); k += kPersistThreads) dst[k] = src[k];
+        if (tid == 0) {
+            descs[cid].h[0] = d.h[0];
+            descs[cid].h[1] = d.h[1];
+            descs[cid].h2[0] = d.h2[0];
+            descs[cid].h2[1] = d.h2[1];
+        }
     }
 }
 
@@ -2770,7 +2894,8 @@ int64_t persist_capacity(mpr_ctx *ctx, int rows)
     int64_t cap = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, ctx->device) == hipSuccess && coop &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel_of(rows), kBlock, 0) == hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel_of(rows), kPersistThreads, 0) ==
+            hipSuccess)
         cap = (int64_t)per_cu * cus;
     (void)hipGetLastError();
     ctx->persist_cap[rows] = cap;
@@ -2780,9 +2905,11 @@ int64_t persist_capacity(mpr_ctx *ctx, int rows)
 // Up to `count` fused sweeps of every listed chain in persistent shape v,
 // in one cooperative launch (the barrier generation cleared first).
 hipError_t launch_persist(hipStream_t st, const ChainSet &cs, int v, const SweepConsts &sc, const FusedControl &ctl,
-                          unsigned int *gen, unsigned int *abort_word, int count, uint32_t need)
+                          unsigned int *gen, unsigned int *abort_word, unsigned long long *slots, int count,
+                          uint32_t need)
 {
     hipError_t e = hipMemsetAsync(gen, 0, sizeof(unsigned int), st);
+    if (e == hipSuccess) e = hipMemsetAsync(slots, 0, cs.desc.size() * 32, st);
     if (e != hipSuccess) return e;
     ChainDesc *descs = cs.d_desc;
     ChainState *states = cs.d_state;
@@ -2792,11 +2919,12 @@ hipError_t launch_persist(hipStream_t st, const ChainSet &cs, int v, const Sweep
     PersistCtl pc;
     pc.gen = gen;
     pc.abort = abort_word;
+    pc.slots = slots;
     pc.count = count;
     pc.need = need;
     void *args[] = {&descs, &states, &bm, &scc, &fc, &pc};
     return hipLaunchCooperativeKernel(persist_kernel_of(kShapes[v].rows), dim3((unsigned)cs.total_blocks[v]),
-                                      dim3(kBlock), args, 0, st);
+                                      dim3(kPersistThreads), args, 0, st);
 }
 
 // Builds the launch list of a chain set from the chains in `active`: block
@@ -2839,6 +2967,7 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     unsigned long long *d_work = reinterpret_cast<unsigned long long *>((char *)ctx->scratch + kWorkOffset);
     unsigned int *d_gen = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kGenOffset);
     unsigned int *d_abort = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kAbortOffset);
+    unsigned long long *d_slots = reinterpret_cast<unsigned long long *>((char *)ctx->scratch + kSlotsOffset);
     HIP_TRY(ctx, hipMemsetAsync(d_done, 0, sizeof(unsigned int), stream));
     HIP_TRY(ctx, hipMemsetAsync(d_abort, 0, sizeof(unsigned int), stream));
     HIP_TRY(ctx, hipMemsetAsync(d_ticket, 0, sizeof(unsigned int), stream));
@@ -2883,14 +3012,14 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     // holds at once, states not recorded (nothing runs between the sweep and
     // the control).
     auto persist_ok = [&](int v) {
-        return kShapes[v].persist && fuse && !table && cs.total_blocks[v] > 0 &&
+        return kShapes[v].persist && fuse && !table && n <= kPersistMaxChains && cs.total_blocks[v] > 0 &&
                cs.total_blocks[v] <= persist_capacity(ctx, kShapes[v].rows);
     };
     const uint32_t need = (uint32_t)(n - (int)already);
     hipError_t perr = hipSuccess;
     auto sweeps = [&](int v, int count) {
         if (kShapes[v].persist) {
-            perr = launch_persist(st, cs, v, sc, fc, d_gen, d_abort, count, need);
+            perr = launch_persist(st, cs, v, sc, fc, d_gen, d_abort, d_slots, count, need);
             return;
         }
         for (int i = 0; i < count; ++i) {
@@ -2973,6 +3102,12 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
             if (!usable(k)) continue;
             // time per sweep; a persistent launch over more sweeps, so that
             // its one launch does not weigh on the comparison
+            if (kShapes[k].persist) {
+                // an untimed first launch (the first of a kernel costs more)
+                int rc = block(k, 1, nullptr, nullptr);
+                if (rc) return rc;
+                if (finished || done_sweeps + ts > max_sweeps) break;
+            }
             const int tk = kShapes[k].persist ? (int)std::min<int64_t>(4 * ts, max_sweeps - done_sweeps) : ts;
             float ms = 0.0f;
             const int64_t before = done_sweeps;
