@@ -1021,6 +1021,47 @@ __device__ __forceinline__ void tile_update(TileShared<TH, NW> &L, const TilePre
     float *const dst0 = mode == 0 ? d.h2[0] : d.h[0];
     float *const dst1 = mode == 0 ? d.h2[1] : d.h[1];
 
+    // the tile's gap sites of colour cc to the destination half-grid
+    // (16-byte groups holding at least one gap site), and the equilibrium sums
+    auto write_back = [&](int cc) {
+        constexpr int NQ = kTileH / 4;
+        const float ik = ss.inv_k, ikm1 = ss.inv_km1;
+        float *const dst = cc ? dst1 : dst0;
+        float *const ap = eq ? (cc ? d.acc[1] : d.acc[0]) : nullptr;
+        float *const mp = cc ? d.m2[1] : d.m2[0];
+        for (int k = tid; k < TH * NQ; k += NT) {
+            const int rr = k / NQ, q = k - rr * NQ;
+            const int y = y0 + rr;
+            if (y >= d.ny) continue;
+            const int h = hx0 + 4 * q;
+            const v4f v = *(const v4f *)&L.a[cc][rr + 2][4 + 4 * q];
+            const bool g0 = !is_fixed(v.x), g1 = !is_fixed(v.y), g2 = !is_fixed(v.z), g3 = !is_fixed(v.w);
+            if (!(g0 || g1 || g2 || g3)) continue;
+            const uint32_t idx = (uint32_t)(y * d.S + h);
+            gsti4(dst, idx, v);
+            if (ap) {
+                // the group's gap sites into the equilibrium sums (and the
+                // squared deviations), the arithmetic of accumulate_state,
+                // with 16-byte loads and stores; the other elements keep
+                // their values
+                const int W = (d.nx - ((y + cc) & 1) + 1) >> 1;
+                const bool gg[4] = {g0, g1, g2, g3};
+                const v4f s0 = P ? *(const v4f *)&P->acc[cc][rr][4 * q] : gldi4(ap, idx);
+                v4f s1 = s0;
+                v4f m = mp ? (P ? *(const v4f *)&P->m2[cc][rr][4 * q] : gldi4(mp, idx))
+                           : v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (gg[e] && h + e < W) {
+                        s1[e] = s0[e] + v[e];
+                        m[e] = fmaf(v[e] - s0[e] * ikm1, v[e] - s1[e] * ik, m[e]);
+                    }
+                gsti4(ap, idx, s1);
+                if (mp) gsti4(mp, idx, m);
+            }
+        }
+    };
+
     const int npass = mode == 0 ? 2 : 1;
     for (int pass = 0; pass < npass; ++pass) {
         const int c = mode == 0 ? pass : mode - 1;
@@ -1144,51 +1185,12 @@ __device__ __forceinline__ void tile_update(TileShared<TH, NW> &L, const TilePre
             }
             __syncthreads();
         }
+        if (mode == 0 && pass == 0) write_back(0);
     }
 
-    // the tile's gap sites to the destination half-grids (16-byte groups
-    // holding at least one gap site), and the equilibrium sums
-    {
-        constexpr int NQ = kTileH / 4;
-        const float ik = ss.inv_k, ikm1 = ss.inv_km1;
-        for (int cc = 0; cc < 2; ++cc) {
-            if ((mode == 1 && cc == 1) || (mode == 2 && cc == 0)) continue;
-            float *const dst = cc ? dst1 : dst0;
-            float *const ap = eq ? (cc ? d.acc[1] : d.acc[0]) : nullptr;
-            float *const mp = cc ? d.m2[1] : d.m2[0];
-            for (int k = tid; k < TH * NQ; k += NT) {
-                const int rr = k / NQ, q = k - rr * NQ;
-                const int y = y0 + rr;
-                if (y >= d.ny) continue;
-                const int h = hx0 + 4 * q;
-                const v4f v = *(const v4f *)&L.a[cc][rr + 2][4 + 4 * q];
-                const bool g0 = !is_fixed(v.x), g1 = !is_fixed(v.y), g2 = !is_fixed(v.z), g3 = !is_fixed(v.w);
-                if (!(g0 || g1 || g2 || g3)) continue;
-                const uint32_t idx = (uint32_t)(y * d.S + h);
-                gsti4(dst, idx, v);
-                if (ap) {
-                    // the group's gap sites into the equilibrium sums (and the
-                    // squared deviations), the arithmetic of accumulate_state,
-                    // with 16-byte loads and stores; the other elements keep
-                    // their values
-                    const int W = (d.nx - ((y + cc) & 1) + 1) >> 1;
-                    const bool gg[4] = {g0, g1, g2, g3};
-                    const v4f s0 = P ? *(const v4f *)&P->acc[cc][rr][4 * q] : gldi4(ap, idx);
-                    v4f s1 = s0;
-                    v4f m = mp ? (P ? *(const v4f *)&P->m2[cc][rr][4 * q] : gldi4(mp, idx))
-                               : v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (gg[e] && h + e < W) {
-                            s1[e] = s0[e] + v[e];
-                            m[e] = fmaf(v[e] - s0[e] * ikm1, v[e] - s1[e] * ik, m[e]);
-                        }
-                    gsti4(ap, idx, s1);
-                    if (mp) gsti4(mp, idx, m);
-                }
-            }
-        }
-    }
+    // the colour not written back after its own pass (colour 0 of a full
+    // sweep is final once its pass is done: colour 1 only reads it)
+    write_back(mode == 1 ? 0 : 1);
 }
 
 // Stage, then sweep, the tile of a one-launch-per-sweep kernel.
