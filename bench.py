@@ -319,6 +319,52 @@ def cloud_leg(ctx, mpr, prm, steps: int) -> dict:
             "mean_sweeps_per_chain": float(np.mean(sweeps)), "T_hat": T, "MAE": mae}
 
 
+def small_fill_leg(ctx, mpr, steps: int) -> dict:
+    """A small fill in the paper's layout: the L=1024 workload, one chain of
+    K = 100 states with the stopping rule, `steps` timed fills after one
+    untimed fill (which builds the e(T, L) table of the size and tunes the
+    sweep shape, both cached).  Reports site-updates/s over whole fills (map,
+    temperature, simulate, predict) and the fill's own sweep time per sweep
+    (event-timed sweep groups)."""
+    import numpy as np
+    import torch
+    im, desc = make_workload("l1024")
+    imgs = mpr.images([(im.ny, im.nx)])
+    z = torch.from_numpy(im.z.astype(np.float32)).cuda()
+    mk = torch.from_numpy(im.mask).cuda()
+    phi, ps, zh = torch.zeros_like(z), torch.zeros_like(z), torch.zeros_like(z)
+    prm = mpr.default_params(R=1, K=100)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    P = int((im.mask == 0).sum())
+
+    def fill():
+        zz = ctx.map_to_angles(imgs, z, mk, phi)
+        _, T, _ = ctx.estimate_temperature(imgs, phi, mk, prm, ws)
+        st = ctx.simulate(imgs, phi, mk, T, prm, ws, ps)
+        ctx.predict(imgs, z, mk, ps, zz, prm.R * prm.K, zh)
+        return st
+
+    fill()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    sweeps = 0
+    for _ in range(steps):
+        st = fill()
+        sweeps += sum(x["relax_sweeps"] + prm.K for x in st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pr = ctx.profile_read()
+    ctx.profile_enable(False)
+    del ws
+    sweep_us = pr["sweep_kernel_ms"] * 1e3 / max(1, pr["chain_sweeps"])
+    log(f"small fill l1024 (1,100): {sweeps * P / dt:.3e} site-updates/s, {dt / steps * 1e3:.2f} ms per fill, "
+        f"{sweep_us:.1f} us per sweep")
+    return {"workload": desc, "value": sweeps * P / dt, "unit": "site-updates/s", "steps": steps,
+            "ms_per_step": dt / steps * 1e3, "chains_R": prm.R, "states_per_chain_K": prm.K, "gap_sites": P,
+            "sweeps_per_fill": sweeps / steps, "sweep_us": sweep_us, "tile_rows": pr["last_tile"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,6 +405,9 @@ def main():
                     help="images per mask type for the warm-start comparison at L=2048 (0 = skip)")
     ap.add_argument("--cloud-steps", type=int, default=1,
                     help="timed steps of the same fill with the 40%% cloud mask, reported as l4096_cloud "
+                         "(0 = skip; only with the default workload)")
+    ap.add_argument("--small-steps", type=int, default=5,
+                    help="timed fills of the L=1024 workload in the (1, 100) layout, reported as small_fill "
                          "(0 = skip; only with the default workload)")
     args = ap.parse_args()
     if args.combine:
@@ -504,6 +553,8 @@ def main():
     }
     if args.cloud_steps > 0 and args.workload == "l4096-random" and not args.fp64:
         out["l4096_cloud"] = cloud_leg(ctx, mpr, prm, args.cloud_steps)
+    if args.small_steps > 0 and args.workload == "l4096-random" and not args.fp64:
+        out["small_fill"] = small_fill_leg(ctx, mpr, args.small_steps)
     if warm_fields is not None:
         log("warm start vs plain start at L=2048")
         params, info = warmstart.load()

@@ -268,8 +268,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             for (int i = 0; i < 16; ++i) acc[o][i] = 0.0f;
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx)
+            // the stem's encoded input has three nonzero channels: input
+            // channels 16 .. 31 are zero, and their products (exact zeros
+            // added to sums that start at +0) change nothing
 #pragma unroll
-            for (int kh = 0; kh < 2; ++kh) {
+            for (int kh = 0; kh < ((SIDE & 4) ? 1 : 2); ++kh) {
                 // weights of taps (dy, dx - 1), dy = -1, 0, 1: out-channel m, in-channels kh*16 + kq*8 .. +7
                 bf16x8 wa[3];
 #pragma unroll
