@@ -147,7 +147,11 @@ typedef struct {
                                 sweeps_per_launch) instead of starting its chains; phi_init is
                                 ignored.  Results equal those of an uninterrupted run bit for
                                 bit (random numbers are keyed by sweep, not by call). */
-    int32_t reserved;        /* set to 0 (pads the struct to 128 bytes) */
+    int32_t barrier_timeout_us; /* > 0: the longest a block of the persistent sweep
+                                (MPR_TILE_PERSIST) waits at its grid barrier, in microseconds,
+                                before the call gives up with MPR_ERR_HIP (every block then
+                                leaves at its next barrier; the workspace contents are lost);
+                                0: 2 seconds.  Results do not depend on it. */
 } mpr_params;
 
 /* Per chain results of mpr_simulate (R per image, image-major). */

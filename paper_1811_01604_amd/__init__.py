@@ -58,7 +58,7 @@ class Params(C.Structure):
         ("table_T_hi", C.c_double), ("seed", C.c_uint64), ("sweeps_per_launch", C.c_int32),
         ("spread", C.c_int32), ("fp64", C.c_int32), ("table_side_cap", C.c_int32),
         ("warm_min_states", C.c_int32), ("sweep_limit", C.c_int32), ("resume", C.c_int32),
-        ("reserved", C.c_int32),
+        ("barrier_timeout_us", C.c_int32),
     ]
 
 

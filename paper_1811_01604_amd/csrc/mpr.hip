@@ -39,7 +39,8 @@ using namespace mpr;
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kMapBlocks = 64;           // partial-result blocks per image (map, e_s)
+constexpr int kMapBlocks = 512;          // partial-result blocks per image at most (map, e_s)
+constexpr int kHoldoutBlocks = 64;       // partial-result blocks of the hold-out error
 constexpr size_t kScratchBytes = 8u << 20;
 constexpr uint32_t kTableStream = 0x80000000u;
 constexpr uint32_t kInitSweep = 0xFFFFFFFFu;
@@ -1333,16 +1334,18 @@ __global__ __launch_bounds__(kBlock) void sweep_tile_kernel(ChainDesc *__restric
 // ticket; the last ticket-holder clears the slots read in this sweep, resets
 // the ticket and publishes the sweep count (bit 31: stop) in `gen`; the
 // others poll `gen` and then invalidate their caches (acquire).  A block
-// that waits longer than kPersistWaitTicks sets `abort` and every block
-// leaves at its next barrier; the host then reports an error.
+// that waits longer than its bound (2 s unless the call sets another) sets
+// `abort` and every block leaves at its next barrier; the host then reports
+// an error.
 struct PersistCtl {
     unsigned int *gen;    // sweeps completed in this launch, | 1 << 31 to stop; zero at launch
     unsigned int *abort;  // nonzero: a block timed out at a barrier
     unsigned long long *slots;  // per chain: [sweep parity][energy, accepted]; zero at launch
+    uint64_t wait_ticks;  // the longest wait at a barrier, in ticks of the 100 MHz constant clock
     int32_t count;        // sweeps to run at most
     uint32_t need;        // done-counter value at which every chain has finished
 };
-constexpr uint64_t kPersistWaitTicks = 200000000ull;  // 2 s of the 100 MHz constant clock
+constexpr uint64_t kPersistWaitTicks = 200000000ull;  // default wait bound: 2 s
 constexpr int kPersistThreads = 512;
 constexpr int64_t kPersistMaxChains = 1024;  // chains of a set that can take the persistent shapes
 static_assert(kSlotsOffset + 32 * kPersistMaxChains <= kVarOffset, "persistent sweep slots overlap the partials");
@@ -1472,7 +1475,7 @@ __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu
                     stop = 1;
                     break;
                 }
-                if (wall_clock64() - t0 > kPersistWaitTicks) {
+                if ((uint64_t)(wall_clock64() - t0) > pc.wait_ticks) {
                     __hip_atomic_store(pc.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     stop = 1;
                     break;
@@ -2272,15 +2275,26 @@ __global__ void predict_kernel(const ImgDev *__restrict__ imgs, const double *__
 }
 
 // Per-block sums of -cos(q (phi_i - phi_j)) over sample-sample bonds.
+// Partial-result blocks of an image of n sites: one per 4096 sites, at most
+// kMapBlocks.  A function of the image alone, so that an image's e_s (a sum
+// of doubles) does not depend on the batch it is in.
+__host__ __device__ inline int image_blocks(int64_t n)
+{
+    const int64_t b = (n + 4095) / 4096;
+    return (int)(b < 1 ? 1 : (b > kMapBlocks ? kMapBlocks : b));
+}
+
 __global__ void sample_energy_kernel(const ImgDev *__restrict__ imgs, const float *__restrict__ phi,
                                      const uint8_t *__restrict__ sampled, double q, double *__restrict__ psum,
                                      unsigned long long *__restrict__ pcount)
 {
     const ImgDev im = imgs[blockIdx.y];
     const int64_t n = (int64_t)im.nx * im.ny;
+    const int nbk = image_blocks(n);  // this image's blocks (the grid covers the largest image)
+    if ((int)blockIdx.x >= nbk) return;
     double s = 0.0;
     unsigned long long cnt = 0ull;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)nbk * blockDim.x) {
         const int64_t j = im.offset + i;
         if (!sampled[j]) continue;
         const int y = (int)(i / im.nx);
@@ -2523,7 +2537,7 @@ bool valid_params(const mpr_params *p)
            p->sweeps_per_launch >= 0 && p->sweeps_per_launch <= 4096 && (p->spread == 0 || p->spread == 1) &&
            (p->fp64 == 0 || p->fp64 == 1) &&
            (p->table_side_cap == 0 || p->table_side_cap >= 2) && p->warm_min_states >= 0 && p->sweep_limit >= 0 &&
-           (p->resume == 0 || p->resume == 1);
+           (p->resume == 0 || p->resume == 1) && p->barrier_timeout_us >= 0;
 }
 
 bool valid_images(const mpr_image *imgs, int n)
@@ -2590,7 +2604,7 @@ uint64_t run_key(const mpr_image *imgs, int n, const mpr_params *p, const double
     q.resume = 0;
     q.tile_rows = 0;
     q.sweeps_per_launch = 0;
-    q.reserved = 0;
+    q.barrier_timeout_us = 0;
     mix(&q, sizeof q);
     mix(T_hat, sizeof(double) * (size_t)n);
     return h;
@@ -2908,7 +2922,7 @@ int64_t persist_capacity(mpr_ctx *ctx, int rows)
 // in one cooperative launch (the barrier generation cleared first).
 hipError_t launch_persist(hipStream_t st, const ChainSet &cs, int v, const SweepConsts &sc, const FusedControl &ctl,
                           unsigned int *gen, unsigned int *abort_word, unsigned long long *slots, int count,
-                          uint32_t need)
+                          uint32_t need, uint64_t wait_ticks)
 {
     hipError_t e = hipMemsetAsync(gen, 0, sizeof(unsigned int), st);
     if (e == hipSuccess) e = hipMemsetAsync(slots, 0, cs.desc.size() * 32, st);
@@ -2922,6 +2936,7 @@ hipError_t launch_persist(hipStream_t st, const ChainSet &cs, int v, const Sweep
     pc.gen = gen;
     pc.abort = abort_word;
     pc.slots = slots;
+    pc.wait_ticks = wait_ticks;
     pc.count = count;
     pc.need = need;
     void *args[] = {&descs, &states, &bm, &scc, &fc, &pc};
@@ -3018,10 +3033,11 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
                cs.total_blocks[v] <= persist_capacity(ctx, kShapes[v].rows);
     };
     const uint32_t need = (uint32_t)(n - (int)already);
+    const uint64_t wait_ticks = p->barrier_timeout_us > 0 ? (uint64_t)p->barrier_timeout_us * 100u : kPersistWaitTicks;
     hipError_t perr = hipSuccess;
     auto sweeps = [&](int v, int count) {
         if (kShapes[v].persist) {
-            perr = launch_persist(st, cs, v, sc, fc, d_gen, d_abort, d_slots, count, need);
+            perr = launch_persist(st, cs, v, sc, fc, d_gen, d_abort, d_slots, count, need, wait_ticks);
             return;
         }
         for (int i = 0; i < count; ++i) {
@@ -3478,12 +3494,14 @@ int32_t mpr_map_to_angles(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const 
         std::vector<ImgDev> hi(nb);
         for (int b = 0; b < nb; ++b) hi[b] = {imgs[b0 + b].offset, imgs[b0 + b].nx, imgs[b0 + b].ny};
         HIP_TRY(ctx, hipMemcpyAsync(d_img, hi.data(), nb * sizeof(ImgDev), hipMemcpyHostToDevice, stream));
-        hipLaunchKernelGGL(map_minmax_kernel, dim3(kMapBlocks, nb), dim3(kBlock), 0, stream, d_img, z, sampled, pmin,
+        int mb = 1;  // partial blocks per image: the largest image's count (min, max and counts are exact)
+        for (int b = 0; b < nb; ++b) mb = std::max(mb, image_blocks((int64_t)hi[b].nx * hi[b].ny));
+        hipLaunchKernelGGL(map_minmax_kernel, dim3(mb, nb), dim3(kBlock), 0, stream, d_img, z, sampled, pmin,
                            pmax, pcnt, pbad);
         HIP_TRY(ctx, hipGetLastError());
-        std::vector<float> hmin(nb * kMapBlocks), hmax(nb * kMapBlocks);
-        std::vector<unsigned long long> hcnt(nb * kMapBlocks);
-        std::vector<unsigned int> hbad(nb * kMapBlocks);
+        std::vector<float> hmin(nb * mb), hmax(nb * mb);
+        std::vector<unsigned long long> hcnt(nb * mb);
+        std::vector<unsigned int> hbad(nb * mb);
         HIP_TRY(ctx, hipMemcpyAsync(hmin.data(), pmin, hmin.size() * 4, hipMemcpyDeviceToHost, stream));
         HIP_TRY(ctx, hipMemcpyAsync(hmax.data(), pmax, hmax.size() * 4, hipMemcpyDeviceToHost, stream));
         HIP_TRY(ctx, hipMemcpyAsync(hcnt.data(), pcnt, hcnt.size() * 8, hipMemcpyDeviceToHost, stream));
@@ -3494,11 +3512,11 @@ int32_t mpr_map_to_angles(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const 
             float lo = INFINITY, hi2 = -INFINITY;
             unsigned long long cnt = 0;
             unsigned int bad = 0;
-            for (int k = 0; k < kMapBlocks; ++k) {
-                lo = std::min(lo, hmin[b * kMapBlocks + k]);
-                hi2 = std::max(hi2, hmax[b * kMapBlocks + k]);
-                cnt += hcnt[b * kMapBlocks + k];
-                bad |= hbad[b * kMapBlocks + k];
+            for (int k = 0; k < mb; ++k) {
+                lo = std::min(lo, hmin[b * mb + k]);
+                hi2 = std::max(hi2, hmax[b * mb + k]);
+                cnt += hcnt[b * mb + k];
+                bad |= hbad[b * mb + k];
             }
             if (bad) return fail(ctx, MPR_ERR_ARG, "image %d: non-finite sampled value", b0 + b);
             if (cnt < 2 || !(hi2 > lo))
@@ -3541,20 +3559,23 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
         std::vector<ImgDev> hi(n);
         for (int b = 0; b < n; ++b) hi[b] = {imgs[b].offset, imgs[b].nx, imgs[b].ny};
         HIP_TRY(ctx, hipMemcpyAsync(d_img, hi.data(), n * sizeof(ImgDev), hipMemcpyHostToDevice, stream));
-        hipLaunchKernelGGL(sample_energy_kernel, dim3(kMapBlocks, n), dim3(kBlock), 0, stream, d_img, phi, sampled,
+        int mb = 1;  // the grid covers the largest image; each image uses image_blocks of its own size
+        for (int b = 0; b < n; ++b) mb = std::max(mb, image_blocks((int64_t)hi[b].nx * hi[b].ny));
+        hipLaunchKernelGGL(sample_energy_kernel, dim3(mb, n), dim3(kBlock), 0, stream, d_img, phi, sampled,
                            p->q, psum, pcnt);
         HIP_TRY(ctx, hipGetLastError());
-        std::vector<double> hs((size_t)n * kMapBlocks);
-        std::vector<unsigned long long> hc((size_t)n * kMapBlocks);
+        std::vector<double> hs((size_t)n * mb);
+        std::vector<unsigned long long> hc((size_t)n * mb);
         HIP_TRY(ctx, hipMemcpyAsync(hs.data(), psum, hs.size() * 8, hipMemcpyDeviceToHost, stream));
         HIP_TRY(ctx, hipMemcpyAsync(hc.data(), pcnt, hc.size() * 8, hipMemcpyDeviceToHost, stream));
         HIP_TRY(ctx, hipStreamSynchronize(stream));
         for (int b = 0; b < n; ++b) {
             double s = 0.0;
             unsigned long long c = 0;
-            for (int k = 0; k < kMapBlocks; ++k) {
-                s += hs[(size_t)b * kMapBlocks + k];
-                c += hc[(size_t)b * kMapBlocks + k];
+            const int nbk = image_blocks((int64_t)hi[b].nx * hi[b].ny);
+            for (int k = 0; k < nbk; ++k) {
+                s += hs[(size_t)b * mb + k];
+                c += hc[(size_t)b * mb + k];
             }
             if (c == 0) return fail(ctx, MPR_ERR_DEGENERATE, "image %d: no sample-sample pair", b);
             e_s[b] = s / (double)c;
@@ -3701,21 +3722,24 @@ static int32_t simulate_call(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, con
         // count gaps with the map reduction on a constant z
         char *sp = (char *)ctx->scratch + kVarOffset;
         float *pmin = (float *)sp;
-        float *pmax = pmin + (int64_t)n * kMapBlocks;
-        unsigned long long *pcnt = (unsigned long long *)(pmax + (int64_t)n * kMapBlocks);
-        unsigned int *pbad = (unsigned int *)(pcnt + (int64_t)n * kMapBlocks);
-        if ((int64_t)n * kMapBlocks * 24 + 512 > (int64_t)kScratchBytes - kVarOffset)
+        int mb = 1;  // partial blocks per image (the counts are exact for any number)
+        for (int b = 0; b < n; ++b) mb = std::max(mb, image_blocks((int64_t)hi[b].nx * hi[b].ny));
+        mb = (int)std::max<int64_t>(1, std::min<int64_t>(mb, ((int64_t)kScratchBytes - kVarOffset - 512) / (24 * (int64_t)n)));
+        float *pmax = pmin + (int64_t)n * mb;
+        unsigned long long *pcnt = (unsigned long long *)(pmax + (int64_t)n * mb);
+        unsigned int *pbad = (unsigned int *)(pcnt + (int64_t)n * mb);
+        if ((int64_t)n * mb * 24 + 512 > (int64_t)kScratchBytes - kVarOffset)
             return fail(ctx, MPR_ERR_ARG, "too many images in one call");
         // map_minmax counts sampled sites of finite value; phi is finite
-        hipLaunchKernelGGL(map_minmax_kernel, dim3(kMapBlocks, n), dim3(kBlock), 0, stream, d_img, phi, sampled, pmin,
+        hipLaunchKernelGGL(map_minmax_kernel, dim3(mb, n), dim3(kBlock), 0, stream, d_img, phi, sampled, pmin,
                            pmax, pcnt, pbad);
         HIP_TRY(ctx, hipGetLastError());
-        std::vector<unsigned long long> hc((size_t)n * kMapBlocks);
+        std::vector<unsigned long long> hc((size_t)n * mb);
         HIP_TRY(ctx, hipMemcpyAsync(hc.data(), pcnt, hc.size() * 8, hipMemcpyDeviceToHost, stream));
         HIP_TRY(ctx, hipStreamSynchronize(stream));
         for (int b = 0; b < n; ++b) {
             unsigned long long c = 0;
-            for (int k = 0; k < kMapBlocks; ++k) c += hc[(size_t)b * kMapBlocks + k];
+            for (int k = 0; k < mb; ++k) c += hc[(size_t)b * mb + k];
             gaps[b] = (int64_t)imgs[b].nx * imgs[b].ny - (int64_t)c;
         }
     }
@@ -4017,7 +4041,7 @@ int32_t mpr_select_q(mpr_ctx *ctx, const mpr_image *img, const float *z, const u
     int rc = mpr_map_to_angles(ctx, &im0, 1, zi, fit, phi, zmm, stream);
     if (rc) return rc;
     double *d_ps = (double *)((char *)ctx->scratch + kVarOffset);
-    unsigned long long *d_pc = (unsigned long long *)(d_ps + kMapBlocks);
+    unsigned long long *d_pc = (unsigned long long *)(d_ps + kHoldoutBlocks);
     int best = -1;
     for (int k = 0; k < nq; ++k) {
         mpr_params pk = *p;
@@ -4031,17 +4055,17 @@ int32_t mpr_select_q(mpr_ctx *ctx, const mpr_image *img, const float *z, const u
         if (rc) return rc;
         rc = mpr_predict(ctx, &im0, 1, zi, fit, psum, zmm, pk.R * pk.K, zhat, stream);
         if (rc) return rc;
-        hipLaunchKernelGGL(holdout_error_kernel, dim3(kMapBlocks), dim3(kBlock), 0, stream, n, zi, si, fit, zhat,
-                           d_ps, d_pc);
+        hipLaunchKernelGGL(holdout_error_kernel, dim3(kHoldoutBlocks), dim3(kBlock), 0, stream, n, zi, si, fit,
+                           zhat, d_ps, d_pc);
         HIP_TRY(ctx, hipGetLastError());
-        double hs[kMapBlocks];
-        unsigned long long hc[kMapBlocks];
+        double hs[kHoldoutBlocks];
+        unsigned long long hc[kHoldoutBlocks];
         HIP_TRY(ctx, hipMemcpyAsync(hs, d_ps, sizeof hs, hipMemcpyDeviceToHost, stream));
         HIP_TRY(ctx, hipMemcpyAsync(hc, d_pc, sizeof hc, hipMemcpyDeviceToHost, stream));
         HIP_TRY(ctx, hipStreamSynchronize(stream));
         double sum = 0.0;
         unsigned long long cnt = 0;
-        for (int b = 0; b < kMapBlocks; ++b) {
+        for (int b = 0; b < kHoldoutBlocks; ++b) {
             sum += hs[b];
             cnt += hc[b];
         }

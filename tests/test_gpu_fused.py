@@ -157,3 +157,28 @@ def test_persistent_sweeps_of_a_1024_fill(ctx):
         assert done == (limit > 1000)
     assert ps.cpu().numpy().tobytes() == ref["sum"]
     assert [(s["relax_sweeps"], s["not_converged"], s["k_last"], s["a_final"], s["A_last"]) for s in st] == ref["stats"]
+
+
+def test_persistent_barrier_timeout_is_an_error_and_the_context_recovers(ctx):
+    """A barrier wait bound of 1 us (params.barrier_timeout_us), which the
+    early blocks of a 256-block persistent launch exceed at the first
+    barrier: every block leaves at its next barrier and the call returns
+    MPR_ERR_HIP (no hang); the next call on the same context, with the
+    default bound, gives the results of one launch per sweep."""
+    im = synth.workload_l1024()
+    imgs = mpr.images([im.z.shape])
+    z = dev(im.z.astype(np.float32))
+    mk = dev(im.mask, torch.uint8)
+    phi = torch.zeros_like(z)
+    ctx.map_to_angles(imgs, z, mk, phi)
+    Ts = np.array([0.09])
+    tile = 32 | mpr.TILE_FUSED | mpr.TILE_PERSIST
+    prm = mpr.default_params(R=1, K=5, fixed_relax=20, tile_rows=tile, barrier_timeout_us=1)
+    ws = torch.empty(ctx.workspace_size(imgs, prm), dtype=torch.uint8, device="cuda")
+    with pytest.raises(mpr.MprError) as e:
+        ctx.simulate(imgs, phi, mk, Ts, prm, ws, torch.zeros_like(phi))
+    assert e.value.code == mpr.MPR_ERR_HIP and "barrier" in str(e.value)
+    say(f"  refused: {e.value}")
+    ref = run(ctx, imgs, phi, mk, Ts, 32 | mpr.TILE_FUSED, 4, R=1, K=5, fixed_relax=20)
+    got = run(ctx, imgs, phi, mk, Ts, tile, 0, R=1, K=5, fixed_relax=20)
+    assert got == ref

@@ -37,6 +37,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(mpr.Image) == 24
     assert C.sizeof(mpr.Params) == 128
     assert mpr.Params.sweep_limit.offset == 116 and mpr.Params.resume.offset == 120
+    assert mpr.Params.barrier_timeout_us.offset == 124
     assert C.sizeof(mpr.ChainStats) == 32
 
 
