@@ -162,7 +162,9 @@ __device__ __forceinline__ void enc_load_tile(const float *__restrict__ phi, con
         valid |= ok ? (1u << j) : 0u;
         const int gyc = min(max(gy, 0), H - 1), gxc = min(max(gx, 0), W - 1);
         const int64_t p = ((int64_t)n * H + gyc) * W + gxc;
-        r[j] = make_uint4(__float_as_uint(phi[p]), (uint32_t)sampled[p], 0u, 0u);
+        // only chunk 0 carries data: the other three lanes of a pixel load nothing
+        r[j] = chunk == 0 ? make_uint4(__float_as_uint(phi[p]), (uint32_t)sampled[p], 0u, 0u)
+                          : make_uint4(0u, 0u, 0u, 0u);
     }
 }
 
@@ -353,26 +355,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // A residual block of the inference forward pass in one kernel:
 //   out = h + conv2(t) + b2,  t = bf16(ReLU(conv1(h) + b1))
 // with the inner activation t kept on chip instead of a round trip through
-// HBM.  Persistent blocks of 4 waves, two per CU (72 KB of LDS and at most
-// 256 registers each, like conv3x3_kernel), loop over 14 x 30-pixel output
-// tiles.  The (14 + 4) x (30 + 4) input pixels around a tile are staged in
-// LDS like conv3x3_kernel's tile (the same 18 x 34 shape) and conv1
-// computes t on the 16 x 32 pixels around the output tile (each wave 4
-// rows, the MFMA scheme of conv3x3_kernel).  Each lane then keeps the skip
-// inputs of its conv2 outputs in registers, and t, rounded to bfloat16 as
-// the layer-by-layer path stores it, overwrites the staged tile (zero
-// outside the image, conv2's zero padding, and in the tile's last two rows
-// and columns).  conv2 computes 16 x 32 outputs of which the first 14 x 30
-// are the tile's (the rest read the zero border); its epilogue adds b2 and
-// the skip input.  Every product and rounding is that of the two
-// conv3x3_kernel launches, so the output is the same bits.  One layer's
-// packed weights are in LDS at a time: the other layer's are loaded into
-// registers while a conv runs and stored after it (an L2 read of 18 KB per
-// conv and tile).  Tiles are ordered so that each XCD takes a contiguous run
-// of them: tiles in flight on one XCD are neighbours and share their halo
+// HBM.  Persistent blocks of 8 waves, one per CU, loop over 14 x 30-pixel
+// output tiles; both layers' packed weights stay in LDS for the whole
+// kernel.  The (14 + 4) x (30 + 4) input pixels around a tile are staged in
+// LDS like conv3x3_kernel's tile (the same 18 x 34 shape), and conv1
+// computes t on the 16 x 32 pixels around the output tile, each wave two
+// rows (the MFMA scheme of conv3x3_kernel, whose products for one output
+// row come in the same order), so two waves per SIMD hide each other's LDS
+// latency.  Each lane then keeps the skip inputs of its conv2 outputs in
+// registers, and t, rounded to bfloat16 as the layer-by-layer path stores
+// it, overwrites the staged tile (zero outside the image, conv2's zero
+// padding, and in the tile's last two rows and columns).  conv2 computes
+// 16 x 32 outputs of which the first 14 x 30 are the tile's (the rest read
+// the zero border); the next tile's pixels are loaded into registers while
+// it runs, and its epilogue adds b2 and the skip input.  Every product and
+// rounding is that of the two conv3x3_kernel launches, so the output is the
+// same bits.  Tiles are ordered so that each XCD takes a contiguous run of
+// them: tiles in flight on one XCD are neighbours and share their halo
 // pixels in its L2.
 constexpr int RTH = CTH - 2, RTW = CTW - 2;             // output tile of the fused block
-constexpr int W_CHUNKS = C_W_ROWS * 4;                  // 16-byte chunks of one layer's packed weights
 
 struct ResArgs {
     const bf16 *in;    // block input h, N x H x W x 32
@@ -394,21 +395,56 @@ __device__ __forceinline__ void res_tile_origin(int tile, int tiles_x, int tiles
     x0 = tx * RTW;
 }
 
+constexpr int RES_NT = 512;                                          // threads of a residual-block block
+constexpr int RES_PT = (C_CHUNKS + RES_NT - 1) / RES_NT;             // staged chunks per thread
+constexpr int W_CHUNKS = C_W_ROWS * 4;                               // 16-byte chunks of one layer's weights
+
 // One layer's packed weights into LDS rows of 80 B.
 __device__ __forceinline__ void res_copy_w(const bf16 *__restrict__ w, bf16 *wl)
 {
-    for (int k = (int)threadIdx.x; k < W_CHUNKS; k += 256)
+    for (int k = (int)threadIdx.x; k < W_CHUNKS; k += RES_NT)
         *reinterpret_cast<uint4 *>(wl + (k >> 2) * PIXS + (k & 3) * 8) =
             *reinterpret_cast<const uint4 *>(w + (k >> 2) * CH + (k & 3) * 8);
 }
 
-// conv3x3_kernel's products of one staged tile: wave w's output rows
-// 4w .. 4w + 3, pixel column m = lane & 31, weights from LDS rows of 80 B.
-__device__ __forceinline__ void res_products(const bf16 *tile, const bf16 *wl, int wave, int m, int kq,
-                                             f32x16 (&acc)[4])
+// conv_load_tile / conv_store_tile for 512-thread blocks.
+__device__ __forceinline__ void res_load_tile(const bf16 *__restrict__ src, int n, int H, int W, int y0, int x0,
+                                              uint4 (&r)[RES_PT], uint32_t &valid)
+{
+    valid = 0u;
+#pragma unroll
+    for (int j = 0; j < RES_PT; ++j) {
+        const int k = min((int)threadIdx.x + RES_NT * j, C_CHUNKS - 1);
+        const int chunk = k & 3, pix = k >> 2;
+        const int rr = pix / C_IN_W, cc = pix - rr * C_IN_W;
+        const int gy = y0 - 1 + rr, gx = x0 - 1 + cc;
+        const bool ok = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        valid |= ok ? (1u << j) : 0u;
+        const int gyc = min(max(gy, 0), H - 1), gxc = min(max(gx, 0), W - 1);
+        r[j] = *reinterpret_cast<const uint4 *>(src + (((int64_t)n * H + gyc) * W + gxc) * CH + chunk * 8);
+    }
+}
+
+__device__ __forceinline__ void res_store_tile(bf16 *tile, const uint4 (&r)[RES_PT], uint32_t valid)
 {
 #pragma unroll
-    for (int o = 0; o < 4; ++o)
+    for (int j = 0; j < RES_PT; ++j) {
+        const int k = (int)threadIdx.x + RES_NT * j;
+        if (k < C_CHUNKS)
+            *reinterpret_cast<uint4 *>(tile + (k >> 2) * PIXS + (k & 3) * 8) =
+                ((valid >> j) & 1u) ? r[j] : make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+// One convolution's products over a staged tile for wave w's output rows
+// 2w and 2w + 1 (pixel column m = lane & 31, weights from LDS rows of
+// 80 B): per output row the products of conv3x3_kernel in its order (column
+// shift dx, channel chunk kh, row tap d).
+__device__ __forceinline__ void res_products(const bf16 *tile, const bf16 *wl, int wave, int m, int kq,
+                                             f32x16 (&acc)[2])
+{
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[o][i] = 0.0f;
 #pragma unroll
@@ -420,24 +456,51 @@ __device__ __forceinline__ void res_products(const bf16 *tile, const bf16 *wl, i
             for (int d = 0; d < 3; ++d)
                 wa[d] = *reinterpret_cast<const bf16x8 *>(wl + ((d * 3 + dx) * CH + m) * PIXS + kh * 16 + kq * 8);
 #pragma unroll
-            for (int ir = 0; ir < 6; ++ir) {
+            for (int ir = 0; ir < 4; ++ir) {
                 const bf16x8 pb = *reinterpret_cast<const bf16x8 *>(
-                    tile + ((4 * wave + ir) * C_IN_W + m + dx) * PIXS + kh * 16 + kq * 8);
+                    tile + ((2 * wave + ir) * C_IN_W + m + dx) * PIXS + kh * 16 + kq * 8);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     const int o = ir - d;
-                    if (o < 0 || o > 3) continue;
+                    if (o < 0 || o > 1) continue;
                     acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[d], pb, acc[o], 0, 0, 0);
                 }
             }
         }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void resblock_kernel(ResArgs a)
+// res_products with the weight operands in registers: this lane's output
+// channel m and input-channel half kq, per column shift dx, channel chunk
+// kh and row tap d.
+__device__ __forceinline__ void res_products_reg(const bf16 *tile, const bf16x8 (&wr)[3][2][3], int wave, int m,
+                                                 int kq, f32x16 (&acc)[2])
+{
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[o][i] = 0.0f;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+            for (int ir = 0; ir < 4; ++ir) {
+                const bf16x8 pb = *reinterpret_cast<const bf16x8 *>(
+                    tile + ((2 * wave + ir) * C_IN_W + m + dx) * PIXS + kh * 16 + kq * 8);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const int o = ir - d;
+                    if (o < 0 || o > 1) continue;
+                    acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wr[dx][kh][d], pb, acc[o], 0, 0, 0);
+                }
+            }
+}
+
+__global__ __launch_bounds__(RES_NT) __attribute__((amdgpu_waves_per_eu(2, 2))) void resblock_kernel(ResArgs a)
 {
     __shared__ __attribute__((aligned(16))) bf16 tile[C_IN_T * PIXS];  // staged input, then t: 18 x 34 pixels
-    __shared__ __attribute__((aligned(16))) bf16 wl[C_W_ROWS * PIXS];  // one layer's packed weights
-    __shared__ float bl[2 * CH];                                       // b1, b2
+    __shared__ __attribute__((aligned(16))) bf16 wl1[C_W_ROWS * PIXS];  // conv1's packed weights
+    __shared__ float bl[2 * CH];                                        // b1, b2
     const int tiles_x = (a.W + RTW - 1) / RTW, tiles_y = (a.H + RTH - 1) / RTH;
     const int n_tiles = tiles_x * tiles_y * a.N;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -446,6 +509,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         bl[threadIdx.x] = a.b1[threadIdx.x];
         bl[CH + threadIdx.x] = a.b2[threadIdx.x];
     }
+    // conv1's weights in LDS, conv2's weight operands in registers, for the whole kernel
+    res_copy_w(a.w1, wl1);
+    bf16x8 w2r[3][2][3];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                w2r[dx][kh][d] =
+                    *reinterpret_cast<const bf16x8 *>(a.w2 + ((d * 3 + dx) * CH + m) * CH + kh * 16 + kq * 8);
     // this block's tiles: the blocks of XCD x = blockIdx % 8 (there are
     // ceil((G - x) / 8) of them) take a contiguous run of the tile sequence
     // in proportion to their number, in turn
@@ -456,37 +530,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int t_lo = (int)((int64_t)n_tiles * before / G), t_hi = (int)((int64_t)n_tiles * (before + nx8) / G);
     const int step = nx8;
     int tile_id = t_lo + ((int)blockIdx.x >> 3);
-    uint4 pre[C_PER_THREAD];
+    uint4 pre[RES_PT];
     uint32_t pre_valid = 0u;
-    res_copy_w(a.w1, wl);
     if (tile_id < t_hi) {
         int n, y0, x0;
         res_tile_origin(tile_id, tiles_x, tiles_y, n, y0, x0);
-        conv_load_tile(a.in, n, a.H, a.W, y0 - 1, x0 - 1, pre, pre_valid);
-        conv_store_tile(tile, pre, pre_valid);
+        res_load_tile(a.in, n, a.H, a.W, y0 - 1, x0 - 1, pre, pre_valid);
+        res_store_tile(tile, pre, pre_valid);
     }
     __syncthreads();
     for (; tile_id < t_hi; tile_id += step) {
         int n, y0, x0;
         res_tile_origin(tile_id, tiles_x, tiles_y, n, y0, x0);
-        f32x16 acc[4];
-        // conv1: t at rows y0 - 1 + 4 wave + o, columns x0 - 1 + m
-        res_products(tile, wl, wave, m, kq, acc);
+        f32x16 acc[2];
+        // conv1: t at rows y0 - 1 + 2 wave + o, columns x0 - 1 + m
+        res_products(tile, wl1, wave, m, kq, acc);
         // the skip inputs of this lane's conv2 outputs (staged pixel
-        // (4 wave + o + 2, m + 2)), read before t overwrites the tile
-        uint2 skip[4][4];
+        // (2 wave + o + 2, m + 2)), read before t overwrites the tile
+        uint2 skip[2][4];
 #pragma unroll
-        for (int o = 0; o < 4; ++o)
+        for (int o = 0; o < 2; ++o)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 skip[o][j] = *reinterpret_cast<const uint2 *>(
-                    tile + (min(4 * wave + o + 2, CTH + 1) * C_IN_W + m + 2) * PIXS + 8 * j + 4 * kq);
-        __syncthreads();  // every wave is done with the input tile and conv1's weights
+                    tile + (min(2 * wave + o + 2, CTH + 1) * C_IN_W + m + 2) * PIXS + 8 * j + 4 * kq);
+        __syncthreads();  // every wave is done with the input tile
         {
             const int gx = x0 - 1 + m;
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                const int tr = 4 * wave + o, gy = y0 - 1 + tr;
+            for (int o = 0; o < 2; ++o) {
+                const int tr = 2 * wave + o, gy = y0 - 1 + tr;
                 const bool inside = gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -501,30 +574,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 }
             }
             // the tile's last two rows and columns: zero
-            for (int k = threadIdx.x; k < (2 * C_IN_W + 2 * CTH) * 4; k += blockDim.x) {
+            for (int k = threadIdx.x; k < (2 * C_IN_W + 2 * CTH) * 4; k += RES_NT) {
                 const int q = k >> 2, chunk = k & 3;
                 const int pix = q < 2 * C_IN_W ? (CTH + q / C_IN_W) * C_IN_W + q % C_IN_W
                                                : ((q - 2 * C_IN_W) >> 1) * C_IN_W + CTW + ((q - 2 * C_IN_W) & 1);
                 *reinterpret_cast<uint4 *>(tile + pix * PIXS + chunk * 8) = make_uint4(0u, 0u, 0u, 0u);
             }
         }
-        res_copy_w(a.w2, wl);
-        __syncthreads();  // t and conv2's weights are in LDS
-        // conv2: outputs at rows y0 + 4 wave + o, columns x0 + m
-        res_products(tile, wl, wave, m, kq, acc);
-        __syncthreads();  // every wave is done with t and conv2's weights
-        if (tile_id + step < t_hi) {  // the next tile's pixels (the CU's other block computes meanwhile)
+        __syncthreads();  // t is in LDS
+        // the next tile's pixels, in flight during conv2 and the epilogue
+        const bool more = tile_id + step < t_hi;
+        if (more) {
             int n2, y2, x2;
             res_tile_origin(tile_id + step, tiles_x, tiles_y, n2, y2, x2);
-            conv_load_tile(a.in, n2, a.H, a.W, y2 - 1, x2 - 1, pre, pre_valid);
-            conv_store_tile(tile, pre, pre_valid);
-            res_copy_w(a.w1, wl);
+            res_load_tile(a.in, n2, a.H, a.W, y2 - 1, x2 - 1, pre, pre_valid);
         }
+        // conv2: outputs at rows y0 + 2 wave + o, columns x0 + m
+        res_products_reg(tile, w2r, wave, m, kq, acc);
         {
             const int gx = x0 + m;
 #pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                const int orow = 4 * wave + o, gy = y0 + orow;
+            for (int o = 0; o < 2; ++o) {
+                const int orow = 2 * wave + o, gy = y0 + orow;
                 if (orow >= RTH || m >= RTW || gy >= a.H || gx >= a.W) continue;
                 const int64_t pix = ((int64_t)n * a.H + gy) * a.W + gx;
 #pragma unroll
@@ -546,7 +617,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 }
             }
         }
-        __syncthreads();  // the next tile and conv1's weights are in LDS
+        __syncthreads();  // every wave is done with t
+        if (more) res_store_tile(tile, pre, pre_valid);
+        __syncthreads();  // the next tile is in LDS
     }
 }
 
@@ -841,9 +914,9 @@ void launch_resblock(hipStream_t st, const bf16 *in, const bf16 *w1, const float
     a.N = n;
     a.H = h;
     a.W = w;
-    // persistent: two blocks per compute unit (72 KB of LDS each)
+    // persistent: one 512-thread block per compute unit (95 KB of LDS)
     const int64_t tiles = (int64_t)n * ((h + RTH - 1) / RTH) * ((w + RTW - 1) / RTW);
-    hipLaunchKernelGGL(resblock_kernel, dim3((unsigned)std::min<int64_t>(tiles, 512)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(resblock_kernel, dim3((unsigned)std::min<int64_t>(tiles, 256)), dim3(RES_NT), 0, st, a);
 }
 
 void launch_wgrad(hipStream_t st, const bf16 *in, const bf16 *gout, const bf16 *gref, float *partial, float *grads,
