@@ -2,8 +2,9 @@
 per-device workspace) against mpr_simulate with a caller's workspace, called
 through the C ABI: the same kernels, random numbers and stopping rule, so
 the outputs must be equal bit for bit.  Two calls in a row, the second on a
-smaller batch (the static workspace keeps the first call's contents), then a
-batch too large for the static workspace, which is refused before any work.
+smaller batch (the static workspace keeps the first call's contents), a third
+in the persistent sweep shape, then a batch too large for the static
+workspace, which is refused before any work.
 """
 import sys
 
@@ -84,7 +85,11 @@ def test_noalloc_equals_simulate_on_two_calls_the_second_smaller(ctx):
     say(f"  call 1 equal ({need} workspace bytes); call 2: 1 image (40x50), R=2, K=3")
     _, _, (a, b) = both(ctx, [(40, 50)], 901, 0.02, False, R=2, K=3, spread=1)
     assert a == b
-    say("  call 2 equal")
+    say("  call 2 equal; call 3: the same image in the persistent sweep shape (no graph either way)")
+    tile = 32 | mpr.TILE_FUSED | mpr.TILE_PERSIST
+    _, _, (a, b) = both(ctx, [(40, 50)], 901, 0.02, False, R=2, K=3, spread=1, tile_rows=tile)
+    assert a == b
+    say("  call 3 equal")
 
 
 def test_noalloc_refuses_a_batch_beyond_its_static_workspace(ctx):
