@@ -1,5 +1,6 @@
 """CPU checks of the benchmark script's host paths (no GPU work):
   - more than one GPU is refused with a message, before anything touches a GPU;
+  - the help lists the extra legs and the sweep shapes;
   - the oracle leg of the scaling study prints one JSON line per case, with a
     whole fill up to the full-fill size and one timed sweep beyond it.
 """
@@ -80,3 +81,13 @@ def test_cpu_baseline_all_cores_runs_independent_chains():
     out = bench.cpu_baseline_all_cores(im, 0.09, 2, 5, 2)
     assert out["cores"] == 2 and out["kind"] == "oracle" and out["value"] > 0
     assert "2 independent chains" in out["sample"]
+
+
+def test_help_lists_the_extra_legs_and_shapes():
+    """The benchmark's extra legs (cloud mask, small fill) can be switched off
+    and the sweep shapes named, the persistent ones included."""
+    r = run("--help", timeout=120)
+    assert r.returncode == 0
+    for opt in ("--cloud-steps", "--small-steps", "--tile", "--cnn-only", "--copy-probe"):
+        assert opt in r.stdout, opt
+    assert "32p" in r.stdout and "48f" in r.stdout
