@@ -25,6 +25,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -1014,7 +1015,10 @@ __device__ __forceinline__ void tile_update(TileShared<TH, NW> &L, const TilePre
                                             uint32_t &acc_thread)
 {
     constexpr int NT = TileShared<TH, NW>::NT;
-    const int tid = (int)threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // the wave index through readfirstlane: the compiler then knows it is
+    // uniform, and keeps the row loops of the list building and their
+    // counters on the scalar unit
+    const int tid = (int)threadIdx.x, lane = tid & 63, wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int phase = ss.phase;
     const uint32_t sweep = ss.sweep;
     const float inv_T = ss.inv_T, dscale = ss.dscale;
@@ -1074,33 +1078,40 @@ __device__ __forceinline__ void tile_update(TileShared<TH, NW> &L, const TilePre
         // wave takes one row at a time, lane l its tile column j = 4 + l;
         // with the ring, then the ring's side columns j = 3 and kTileH + 4,
         // two lanes per row
+        // A site in the tile is either a gap or a sample, so a lane's rank
+        // among the sampled lanes is its rank among the lanes holding a
+        // site less its rank among the gap lanes: one ballot per row.  FULL:
+        // every lane of the wave holds a site (the interior rows of an
+        // interior tile), so that rank among them is the lane index.
         int ng = 0, ns = 0;
-        auto add = [&](bool cand, int r, int j) {
-            bool gap = false, smp = false;
+        auto add = [&](auto FULL, bool cand, int r, int j) {
+            constexpr bool full = decltype(FULL)::value;
+            bool in = cand, gap = false;
             if (cand) {
                 const float v = L.a[c][r][j];
-                bool in = true;
                 if (EDGE) {
                     const int y = y0 - 2 + r, h = hx0 - 4 + j, s = (r + c) & 1;
                     in = y < d.ny && y >= 0 && h >= 0 && h < ((d.nx - s + 1) >> 1);
                 }
                 gap = in && !is_fixed(v);
-                smp = energy && in && is_fixed(v);
             }
             const uint16_t ent = (uint16_t)((r << 7) | j);
             const uint64_t bg = __ballot(gap);
-            if (gap) lst[ng + rank_below(bg)] = ent;
-            ng += __popcll(bg);
+            const int rg = rank_below(bg);
+            if (gap) lst[ng + rg] = ent;
+            const int cg = __popcll(bg);
+            ng += cg;
             if (energy) {
-                const uint64_t bs = __ballot(smp);
-                if (smp) lst[TileShared<TH, NW>::CAP - 1 - (ns + rank_below(bs))] = ent;
-                ns += __popcll(bs);
+                const uint64_t bi = full ? ~0ull : __ballot(in);
+                const int rs = (full ? lane : rank_below(bi)) - rg;
+                if (in && !gap) lst[TileShared<TH, NW>::CAP - 1 - (ns + rs)] = ent;
+                ns += (full ? 64 : __popcll(bi)) - cg;
             }
         };
-        for (int r = r_lo + wid; r < r_hi; r += NW) add(true, r, 4 + lane);
+        for (int r = r_lo + wid; r < r_hi; r += NW) add(std::integral_constant<bool, !EDGE>{}, true, r, 4 + lane);
         if (ring) {
             const int k = wid * 64 + lane;
-            add(k < 2 * (TH + 2), 1 + (k >> 1), (k & 1) ? kTileH + 4 : 3);
+            add(std::false_type{}, k < 2 * (TH + 2), 1 + (k >> 1), (k & 1) ? kTileH + 4 : 3);
         }
         __syncthreads();
         // the listed gap sites
