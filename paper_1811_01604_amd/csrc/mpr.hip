@@ -1857,6 +1857,21 @@ __global__ void control_kernel(ChainDesc *__restrict__ descs, ChainState *__rest
     if (control) control_chain(descs, states, c, cp, done_count, work);
 }
 
+// Zeroes the control words given (null: skipped) and n64 64-bit words at
+// `wide`, in one launch of one block: the counters and barrier words a run of
+// sweeps starts from (one small kernel in place of a memset per word).
+__global__ void clear_words_kernel(unsigned int *w0, unsigned int *w1, unsigned int *w2,
+                                   unsigned long long *wide, int n64)
+{
+    const int t = (int)threadIdx.x;
+    if (t == 0) {
+        if (w0) *w0 = 0u;
+        if (w1) *w1 = 0u;
+        if (w2) *w2 = 0u;
+    }
+    for (int k = t; k < n64; k += (int)blockDim.x) wide[k] = 0ull;
+}
+
 // 1 for every chain that is done, else 0 (for rebuilding the launch list).
 __global__ void done_flags_kernel(const ChainState *__restrict__ states, int n, uint8_t *__restrict__ out)
 {
@@ -2935,8 +2950,9 @@ hipError_t launch_persist(hipStream_t st, const ChainSet &cs, int v, const Sweep
                           unsigned int *gen, unsigned int *abort_word, unsigned long long *slots, int count,
                           uint32_t need, uint64_t wait_ticks)
 {
-    hipError_t e = hipMemsetAsync(gen, 0, sizeof(unsigned int), st);
-    if (e == hipSuccess) e = hipMemsetAsync(slots, 0, cs.desc.size() * 32, st);
+    hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(kBlock), 0, st, gen, nullptr, nullptr, slots,
+                       (int)cs.desc.size() * 4);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     ChainDesc *descs = cs.d_desc;
     ChainState *states = cs.d_state;
@@ -2996,9 +3012,8 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     unsigned int *d_gen = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kGenOffset);
     unsigned int *d_abort = reinterpret_cast<unsigned int *>((char *)ctx->scratch + kAbortOffset);
     unsigned long long *d_slots = reinterpret_cast<unsigned long long *>((char *)ctx->scratch + kSlotsOffset);
-    HIP_TRY(ctx, hipMemsetAsync(d_done, 0, sizeof(unsigned int), stream));
-    HIP_TRY(ctx, hipMemsetAsync(d_abort, 0, sizeof(unsigned int), stream));
-    HIP_TRY(ctx, hipMemsetAsync(d_ticket, 0, sizeof(unsigned int), stream));
+    hipLaunchKernelGGL(clear_words_kernel, dim3(1), dim3(kBlock), 0, stream, d_done, d_abort, d_ticket, nullptr, 0);
+    HIP_TRY(ctx, hipGetLastError());
     unsigned int already = 0;
     for (const auto &s : cs.state)
         if (s.phase == PH_DONE) ++already;
@@ -3157,8 +3172,9 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
     int spl = p->sweeps_per_launch > 0 ? p->sweeps_per_launch : poll_every;
     if (p->sweeps_per_launch <= 0 && sweep_ms > 0.0f && (float)spl * sweep_ms < 1.0f)
         spl = std::min(64, poll_every * (int)std::ceil(1.0f / ((float)poll_every * sweep_ms)));
-    // a persistent launch ends by itself when every chain is done
-    if (p->sweeps_per_launch <= 0 && kShapes[v].persist) spl = 64;
+    // a persistent launch ends by itself when every chain is done: a group
+    // of 256 sweeps covers a whole small fill in one launch and one poll
+    if (p->sweeps_per_launch <= 0 && kShapes[v].persist) spl = 256;
     // the captured sweep group, released on every return path
     struct Captured {
         hipGraph_t graph = nullptr;
