@@ -56,6 +56,10 @@ constexpr int64_t kWorkOffset = 1024;    // three work counters (profiling)
 constexpr int64_t kEnergyOffset = 2048;  // diag energy accumulator
 constexpr int64_t kSlopeOffset = 4096;   // diag slope input / output
 constexpr int64_t kVarOffset = 65536;    // per-call partials
+constexpr int64_t kHostWordsBytes = 1024;      // pinned mirror of the control words
+constexpr int64_t kHostStageBytes = 64 << 10;  // pinned host block (control words + staging)
+static_assert(kAbortOffset + 4 <= kHostWordsBytes && kGenOffset + 4 <= kHostWordsBytes,
+              "the control words are read back in one copy");
 constexpr int kCompactSites = 4 * kBlock;  // sites per block of the compacted sweep shapes
 constexpr int kRecordSegs = 32;            // blocks per chain of record_states_kernel
 constexpr int kWarmMinStates = 100;        // default of mpr_params.warm_min_states
@@ -1074,15 +1078,15 @@ __device__ __forceinline__ void tile_update(TileShared<TH, NW> &L, const TilePre
         const bool energy = c == 1 && !eq;           // the sweep's energy comes from colour 1
         const int r_lo = ring ? 1 : 2, r_hi = TH + (ring ? 3 : 2);
         uint16_t *lst = L.list[wid];
-        // list the gap sites (and, for the energy, the sampled sites): a
+        // List the gap sites (and, for the energy, the sampled sites): a
         // wave takes one row at a time, lane l its tile column j = 4 + l;
         // with the ring, then the ring's side columns j = 3 and kTileH + 4,
-        // two lanes per row
-        // A site in the tile is either a gap or a sample, so a lane's rank
-        // among the sampled lanes is its rank among the lanes holding a
-        // site less its rank among the gap lanes: one ballot per row.  FULL:
-        // every lane of the wave holds a site (the interior rows of an
-        // interior tile), so that rank among them is the lane index.
+        // two lanes per row.  A site in the tile is either a gap or a
+        // sample, so a lane's rank among the sampled lanes is its rank among
+        // the lanes holding a site less its rank among the gap lanes: one
+        // ballot per row.  FULL: every lane of the wave holds a site (the
+        // interior rows of an interior tile), so that rank among them is the
+        // lane index.
         int ng = 0, ns = 0;
         auto add = [&](auto FULL, bool cand, int r, int j) {
             constexpr bool full = decltype(FULL)::value;
@@ -2393,7 +2397,11 @@ struct mpr_ctx {
     std::string err;
     void *scratch = nullptr;          // small device scratch (partials, counters)
     void *static_ws = nullptr;        // this device's static_workspace (device address)
-    unsigned int *done_host = nullptr;  // pinned: done counter, abort word, barrier generation
+    // pinned host memory: the first kHostWordsBytes mirror the scratch's
+    // control words (done counter, barrier generation, abort word); the
+    // rest stages small read-backs (the per-block partials of the map and
+    // of the sample energies) in one copy each
+    unsigned int *done_host = nullptr;
     // resident blocks of the persistent sweep kernel by tile rows (0: no
     // cooperative launch on this device)
     std::map<int, int64_t> persist_cap;
@@ -2474,6 +2482,15 @@ int half_stride(int nx) { return (int)round_up((nx + 1) / 2, 64); }
 int64_t half_grid_bytes(int nx, int ny, int eb = 4) { return (int64_t)ny * half_stride(nx) * eb; }
 
 // Simple bump allocator over the caller's workspace.
+// Host memory for a read-back of `bytes`: the context's pinned staging
+// area when it fits, else `spill` (pageable), resized.
+char *stage_for(mpr_ctx *ctx, int64_t bytes, std::vector<char> &spill)
+{
+    if (bytes <= kHostStageBytes - kHostWordsBytes) return (char *)ctx->done_host + kHostWordsBytes;
+    spill.resize((size_t)bytes);
+    return spill.data();
+}
+
 struct Carver {
     char *base;
     int64_t cap, used = 0;
@@ -3094,17 +3111,17 @@ int run_chains(mpr_ctx *ctx, ChainSet &cs, const mpr_params *p, hipStream_t stre
         if (perr != hipSuccess) return fail(ctx, MPR_ERR_HIP, "persistent sweep launch: %s", hipGetErrorString(perr));
         HIP_TRY(ctx, hipGetLastError());
         HIP_TRY(ctx, hipEventRecord(ctx->ev_t1, st));
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->done_host, d_done, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
-        if (kShapes[v].persist) {
-            HIP_TRY(ctx, hipMemcpyAsync(ctx->done_host + 1, d_abort, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
-            HIP_TRY(ctx, hipMemcpyAsync(ctx->done_host + 2, d_gen, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
-        }
+        // the done counter; after a persistent launch the words up to the
+        // abort word, in one copy (done counter, generation, abort word)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->done_host, d_done,
+                                    kShapes[v].persist ? (size_t)(kAbortOffset + 4) : sizeof(unsigned int),
+                                    hipMemcpyDeviceToHost, st));
         HIP_TRY(ctx, hipStreamSynchronize(st));
         if (kShapes[v].persist) {
-            if (ctx->done_host[1] != 0u)
+            if (ctx->done_host[kAbortOffset / 4] != 0u)
                 return fail(ctx, MPR_ERR_HIP, "persistent sweep: a block timed out at the grid barrier");
             // the launch stops early once every chain is done
-            count = (int)(ctx->done_host[2] & 0x7FFFFFFFu);
+            count = (int)(ctx->done_host[kGenOffset / 4] & 0x7FFFFFFFu);
         }
         float ms = 0.0f;
         HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev_t0, ctx->ev_t1));
@@ -3436,7 +3453,7 @@ int32_t mpr_create(mpr_ctx **out, int32_t device)
         (void)hipGetLastError();
     }
     if (hipMalloc(&ctx->scratch, kScratchBytes) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->done_host, 4 * sizeof(unsigned int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->done_host, kHostStageBytes, hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming) != hipSuccess ||
@@ -3529,11 +3546,19 @@ int32_t mpr_map_to_angles(mpr_ctx *ctx, const mpr_image *imgs, int32_t n, const 
         std::vector<float> hmin(nb * mb), hmax(nb * mb);
         std::vector<unsigned long long> hcnt(nb * mb);
         std::vector<unsigned int> hbad(nb * mb);
-        HIP_TRY(ctx, hipMemcpyAsync(hmin.data(), pmin, hmin.size() * 4, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(ctx, hipMemcpyAsync(hmax.data(), pmax, hmax.size() * 4, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(ctx, hipMemcpyAsync(hcnt.data(), pcnt, hcnt.size() * 8, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(ctx, hipMemcpyAsync(hbad.data(), pbad, hbad.size() * 4, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        // the four partial arrays lie one after the other: one copy
+        {
+            const char *src = (const char *)pmin;
+            const int64_t span = (const char *)(pbad + (int64_t)nb * mb) - src;
+            std::vector<char> big;
+            char *h = stage_for(ctx, span, big);
+            HIP_TRY(ctx, hipMemcpyAsync(h, src, (size_t)span, hipMemcpyDeviceToHost, stream));
+            HIP_TRY(ctx, hipStreamSynchronize(stream));
+            std::memcpy(hmin.data(), h + ((const char *)pmin - src), hmin.size() * 4);
+            std::memcpy(hmax.data(), h + ((const char *)pmax - src), hmax.size() * 4);
+            std::memcpy(hcnt.data(), h + ((const char *)pcnt - src), hcnt.size() * 8);
+            std::memcpy(hbad.data(), h + ((const char *)pbad - src), hbad.size() * 4);
+        }
         std::vector<double> zmm(2 * nb);
         for (int b = 0; b < nb; ++b) {
             float lo = INFINITY, hi2 = -INFINITY;
@@ -3593,9 +3618,17 @@ int32_t mpr_estimate_temperature(mpr_ctx *ctx, const mpr_image *imgs, int32_t n,
         HIP_TRY(ctx, hipGetLastError());
         std::vector<double> hs((size_t)n * mb);
         std::vector<unsigned long long> hc((size_t)n * mb);
-        HIP_TRY(ctx, hipMemcpyAsync(hs.data(), psum, hs.size() * 8, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(ctx, hipMemcpyAsync(hc.data(), pcnt, hc.size() * 8, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        // the sums, then the counts (carved after them): one copy
+        {
+            const char *src = (const char *)psum;
+            const int64_t span = (const char *)(pcnt + (int64_t)n * mb) - src;
+            std::vector<char> big;
+            char *h = stage_for(ctx, span, big);
+            HIP_TRY(ctx, hipMemcpyAsync(h, src, (size_t)span, hipMemcpyDeviceToHost, stream));
+            HIP_TRY(ctx, hipStreamSynchronize(stream));
+            std::memcpy(hs.data(), h, hs.size() * 8);
+            std::memcpy(hc.data(), h + ((const char *)pcnt - src), hc.size() * 8);
+        }
         for (int b = 0; b < n; ++b) {
             double s = 0.0;
             unsigned long long c = 0;
