@@ -159,6 +159,24 @@ def test_persistent_sweeps_of_a_1024_fill(ctx):
     assert [(s["relax_sweeps"], s["not_converged"], s["k_last"], s["a_final"], s["A_last"]) for s in st] == ref["stats"]
 
 
+def test_persistent_fill_longer_than_one_launch(ctx):
+    """The same 1024 x 1024 chain with 300 equilibrium states: with the
+    default launch groups (256 sweeps) the fill takes two persistent
+    launches, whose results equal one fused launch per sweep bit for bit."""
+    im = synth.workload_l1024()
+    imgs = mpr.images([im.z.shape])
+    z = dev(im.z.astype(np.float32))
+    mk = dev(im.mask, torch.uint8)
+    phi = torch.zeros_like(z)
+    ctx.map_to_angles(imgs, z, mk, phi)
+    Ts = np.array([0.09])
+    ref = run(ctx, imgs, phi, mk, Ts, 32 | mpr.TILE_FUSED, 8, R=1, K=300)
+    assert ref["stats"][0][0] + 300 > 256  # more sweeps than one launch group
+    got = run(ctx, imgs, phi, mk, Ts, 32 | mpr.TILE_FUSED | mpr.TILE_PERSIST, 0, R=1, K=300)
+    for key in ref:
+        assert got[key] == ref[key], key
+
+
 def test_persistent_barrier_timeout_is_an_error_and_the_context_recovers(ctx):
     """A barrier wait bound of 1 us (params.barrier_timeout_us), which the
     early blocks of a 256-block persistent launch exceed at the first
